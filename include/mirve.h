@@ -1,0 +1,213 @@
+/*
+ * mirve.h -- C ABI of the MI355X FFT phase-field-fracture toughness solver.
+ *
+ * The library computes the effective fracture toughness of a periodic voxel
+ * RVE following Aranda & Segurado, "Effective toughness estimation by FFT
+ * based phase field fracture" (arXiv 2508.07424):
+ *   - degraded elastic law sigma = g(phi) C^r : eps with g = (1-phi)^2 + k
+ *     (Sec. 2.1 Eq. 2, Sec. 2.2 Eq. 12-13),
+ *   - Fourier-Galerkin equilibrium with the compatible-strain projection
+ *     (Sec. 4.1 Eq. 24 R1, Eq. 26),
+ *   - AT2 damage balance with history (Eq. 10b, 11, 16b, 38),
+ *   - dissipation control: the macroscopic strain E_M = f E (Eq. 9) is the
+ *     unknown that makes D(phi) = tau (Eq. 10c / 16c),
+ *   - crack-tip enrichment of the initial notch (Sec. 4.3 Eq. 35, 37a, 38),
+ *   - G_eff = V (T^f - 1/2 Sigma^f E^f) / A_g (Sec. 4.2 Eq. 32-33).
+ *
+ * Conventions
+ *   - Every function returns RVE_OK (0) or a negative RVE_E* code; the text
+ *     of the last error of a handle is available from rve_last_error().
+ *   - Grids: n[0] = n_x, n[1] = n_y, n[2] = n_z (n_z = 1 in 2D).  Host
+ *     arrays of voxel data are C-ordered with x fastest:
+ *     index = (z * n_y + y) * n_x + x.  Multi-component fields put the
+ *     component slowest: [c][z][y][x].
+ *   - Symmetric tensors are Mandel vectors: 2D plane strain
+ *     [xx, yy, sqrt2 xy] (s = 3); 3D [xx, yy, zz, sqrt2 yz, sqrt2 xz,
+ *     sqrt2 xy] (s = 6).
+ *   - The library never allocates device memory.  The caller passes a
+ *     device workspace of at least rve_query_workspace() bytes and a HIP
+ *     stream (hipStream_t, or NULL for the default stream); both must
+ *     outlive the handle.  Host input arrays are copied during the call.
+ *   - A handle is not thread-safe.  Distinct handles may run concurrently
+ *     on distinct streams.
+ *   - Steps are transactional: a step that fails leaves the committed state
+ *     (phi, history, E, curve) unchanged.
+ */
+#ifndef MIRVE_H
+#define MIRVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define RVE_OK        0
+#define RVE_EINVAL   -1   /* invalid argument or configuration            */
+#define RVE_ENOSPC   -2   /* workspace smaller than rve_query_workspace() */
+#define RVE_EDEVICE  -3   /* HIP runtime error                            */
+#define RVE_ENOCONV  -4   /* an iteration hit its limit (state unchanged) */
+#define RVE_ENUMERIC -5   /* NaN / Inf met in a reduction                 */
+#define RVE_ESTATE   -6   /* call out of order (e.g. step before set_microstructure) */
+#define RVE_ENOTDONE -7   /* no fracture point reached yet                */
+
+/* precision modes */
+#define RVE_PREC_FP64  0  /* every field and transform in FP64                        */
+#define RVE_PREC_MIXED 1  /* fields, FFTs, constitutive and Krylov updates in FP32;
+                             reductions, the arc-length solve and curve in FP64       */
+
+/* tension / compression split of the elastic energy */
+#define RVE_SPLIT_NONE   0 /* the paper's model: sigma = g C:eps, psi = 1/2 eps:C:eps  */
+#define RVE_SPLIT_VOLDEV 1 /* volumetric split: only K<tr eps>_+^2 and the deviatoric
+                              energy are degraded and drive damage                  */
+
+/* phase kinds */
+#define RVE_PHASE_ISO   0  /* isotropic: E, nu                                */
+#define RVE_PHASE_CUBIC 1  /* cubic: C11, C12, C44 in lattice axes; rotated by
+                              the per-voxel in-plane angle theta (Eq. 13)     */
+
+/* fields for rve_get_field / rve_set_field (host arrays of doubles) */
+#define RVE_FIELD_PHI     0  /* damage phi (committed)                 N values   */
+#define RVE_FIELD_HIST    1  /* history H^n (committed)                N          */
+#define RVE_FIELD_PSI_INI 2  /* initial-crack energy psi_ini (Eq. 37a)  N          */
+#define RVE_FIELD_EPS1    3  /* unit-load strain f + eps~_1             s * N      */
+#define RVE_FIELD_SIG1    4  /* unit-load stress g C:eps_1              s * N      */
+#define RVE_FIELD_PSI1    5  /* unit-load energy density psi_o1         N          */
+#define RVE_FIELD_PHI_INI 6  /* enriched initial damage (Eq. 35)        N          */
+
+typedef struct rve_handle_s* rve_handle;
+
+typedef struct {
+    int    dim;            /* 2 (plane strain) or 3                                  */
+    int    n[3];           /* grid; each n_i in [2, 1024]; n[2] = 1 when dim = 2     */
+    double h;              /* voxel size (> 0)                                       */
+    double ell;            /* phase-field length l (> 0)                             */
+    double k_res;          /* residual stiffness k in g = (1-phi)^2 + k (> 0)        */
+    double f[6];           /* Mandel load direction f of E_M = f E (first s used)    */
+    int    split;          /* RVE_SPLIT_*                                            */
+    int    history;        /* 1: H = max(psi_o + psi_ini, H^n) (Eq. 38); 0: no max   */
+    int    precision;      /* RVE_PREC_*                                             */
+    double tol;            /* stagger tolerance on the relative change of phi and E  */
+    double tol_cg;         /* mechanics CG: ||r|| <= tol_cg ||b||                    */
+    double tol_pcg;        /* damage PCG: ||r|| <= tol_pcg ||rhs||                   */
+    double tol_al;         /* dissipation constraint: |D - tau| <= tol_al tau        */
+    int    max_stagger;    /* stagger iteration limit per step                       */
+    int    max_cg;         /* CG iteration limit per mechanics solve                 */
+    int    max_pcg;        /* PCG iteration limit per damage solve                   */
+    int    anderson_depth; /* Anderson acceleration depth of the stagger (0 = off)   */
+    double frac_threshold; /* phi at which a voxel counts as broken (0.95)           */
+    double A_g;            /* reference crack area; 0 = lines along the load axis
+                              without a notch voxel, times h^(dim-1) (Eq. 32)        */
+    int    max_materials;  /* capacity of the per-material table: distinct
+                              (phase, theta, notch) combinations, <= 65536          */
+} rve_config;
+
+typedef struct {
+    int    kind;           /* RVE_PHASE_ISO or RVE_PHASE_CUBIC */
+    double E, nu;          /* isotropic constants              */
+    double C11, C12, C44;  /* cubic constants (lattice axes)   */
+    double Gc;             /* critical energy release rate     */
+} rve_phase;
+
+typedef struct {
+    double E;              /* macroscopic strain scalar of the step (Eq. 9)          */
+    double Sigma;          /* <sigma>:f                                              */
+    double D;              /* dissipation functional D(phi) (Eq. 3)                  */
+    double Gamma;          /* crack surface Gamma(phi) (Eq. 4)                       */
+    double tau;            /* imposed dissipation tau^{n+1}                          */
+    double T;              /* trapezoid of Sigma dE up to this step (Eq. 33)         */
+    int    n_stagger;      /* stagger iterations                                     */
+    int    n_cg;           /* mechanics CG iterations                                */
+    int    n_pcg;          /* damage PCG iterations                                  */
+    int    n_greenop;      /* Green-operator applications                            */
+    double res_R1;         /* ||P[sigma]|| / ||sigma|| at the committed state        */
+    double res_R2;         /* ||damage residual|| / ||2H|| at the committed state    */
+    double res_R3;         /* |D - tau| / tau                                        */
+    int    fractured;      /* 1 once every line along the load axis is broken        */
+    int    step;           /* index of the committed step (1, 2, ...)                */
+} rve_step_info;
+
+/* Fill cfg with defaults (tolerances, limits, FP64, no split, history on). */
+int rve_default_config(rve_config* cfg);
+
+/* Bytes of device workspace a handle of this configuration needs (its HBM
+ * footprint; used for admission by a serving loop). */
+int rve_query_workspace(const rve_config* cfg, size_t* bytes);
+
+/* Create a handle bound to a caller-owned device workspace and stream.
+ * Computes the plan (FFT factors, twiddles, launch shapes).  No compute. */
+int rve_create(const rve_config* cfg, void* dev_workspace, size_t workspace_bytes,
+               void* hip_stream, rve_handle* out);
+
+int rve_destroy(rve_handle h);
+
+/* Microstructure and initial crack (Sec. 2, 4.3).
+ *   phase_id  N uint16, index into phases[0 .. nphases-1]
+ *   phases    nphases phase descriptions (copied)
+ *   theta     N doubles, in-plane lattice angle per voxel, or NULL (= 0);
+ *             cubic stiffness is rotated by it about z (Eq. 13)
+ *   void_mask N uint8 or NULL: notch voxels (stiffness k C, no driving force)
+ *   phi_disc  N uint8 or NULL: sharp enrichment points of Eq. 35
+ *   phi_M     maximum of the enriched initial damage (Eq. 35), in (0, 1)
+ * Computes phi_ini, psi_ini, H^0 = psi_ini and tau^0 = D(phi_ini) on the
+ * device and resets the loading curve.  Synchronises the stream. */
+int rve_set_microstructure(rve_handle h, const uint16_t* phase_id, const rve_phase* phases,
+                           int nphases, const double* theta, const uint8_t* void_mask,
+                           const uint8_t* phi_disc, double phi_M);
+
+/* One dissipation-controlled step tau^{n+1} = tau^n + dtau (Eq. 16): the
+ * staggered fixed point of equilibrium, damage and the constraint, then
+ * commit and the fracture test.  out may be NULL. */
+int rve_step_dissipation(rve_handle h, double dtau, rve_step_info* out);
+
+/* Advance several independent handles by one step each, overlapping their
+ * device work (each handle must have its own stream). info may be NULL;
+ * status[i] receives each handle's return code. Returns RVE_OK if all did. */
+int rve_step_dissipation_batch(rve_handle* hs, int count, const double* dtau,
+                               rve_step_info* info, int* status);
+
+/* G_eff = V (T^F - 1/2 Sigma^F E^F) / A_g at the fracture point F
+ * (Eq. 32-33).  RVE_ENOTDONE before F. */
+int rve_effective_toughness(rve_handle h, double* G_eff);
+
+/* Copy a field (RVE_FIELD_*) to / from a host array of doubles in the host
+ * layout above.  count must equal the field's size.  Setting PHI or HIST
+ * replaces the committed state (used for checkpoints and tests). */
+int rve_get_field(rve_handle h, int which, double* host, size_t count);
+int rve_set_field(rve_handle h, int which, const double* host, size_t count);
+
+/* Scalars of the committed state: out[0..5] = {E, Sigma, T, tau, tau0, step}. */
+int rve_get_scalars(rve_handle h, double* out6);
+int rve_set_scalars(rve_handle h, const double* in6);
+
+/* Green operator (Eq. 24 R1): out = F^-1{ P : F[ g(phi) C : eps ] } at the
+ * committed phi, for eps given as s*N host doubles.  Used for parity. */
+int rve_apply_green_op(rve_handle h, const double* eps_host, double* out_host);
+
+/* Device-resident variant for benchmarking: eps and out are device arrays
+ * of s*N elements of the handle's bulk type (double, or float in MIXED
+ * mode); `repeat` applications are enqueued on the handle's stream
+ * (asynchronous). */
+int rve_apply_green_op_device(rve_handle h, const void* eps_dev, void* out_dev, int repeat);
+
+/* Equilibrium for the unit load at the committed phi (Eq. 16a): updates
+ * EPS1/SIG1/PSI1 and returns the CG iteration count and Sigma_1. */
+int rve_solve_mechanics(rve_handle h, int* iterations, double* Sigma1);
+
+/* Damage balance at load E with the current unit energy PSI1 and the
+ * committed history (Eq. 16b, 38): returns D(phi(E)) and the PCG count;
+ * phi(E) is left in the field returned by RVE_FIELD_PHI only if commit_phi. */
+int rve_solve_damage(rve_handle h, double E, double* D, int* iterations, int commit_phi);
+
+/* Dissipation D(phi) and crack surface Gamma(phi) of the committed phi. */
+int rve_dissipation(rve_handle h, double* D, double* Gamma);
+
+const char* rve_last_error(rve_handle h);
+const char* rve_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MIRVE_H */

@@ -1,0 +1,64 @@
+// Internal declarations shared by the HIP kernels and the host driver.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace mirve {
+
+constexpr int kMaxStages = 12;     // radix stages per axis (N <= 1024)
+constexpr int kMaxMat = 65536;     // material table entries
+constexpr int kRedBlocks = 1024;   // max blocks of a reduction kernel
+
+template <typename T>
+struct cplx {
+    T x, y;
+};
+
+template <typename T>
+__host__ __device__ inline cplx<T> cmul(cplx<T> a, cplx<T> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__host__ __device__ inline cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__host__ __device__ inline cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__host__ __device__ inline cplx<T> cconj(cplx<T> a) { return {a.x, -a.y}; }
+template <typename T>
+__host__ __device__ inline cplx<T> cscale(cplx<T> a, T s) { return {a.x * s, a.y * s}; }
+
+// Mixed-radix Stockham plan of one axis.  Twiddles w_N^m = exp(-2 pi i m/N),
+// m = 0..N-1, live at tw_off (in elements of cplx<T>) of the twiddle table.
+struct AxisPlan {
+    int N;
+    int nst;
+    int rad[kMaxStages];
+    int tw_off;
+    int min_rad;
+};
+
+// Per-material constants, indexed by the per-voxel material id.  The
+// stiffness is the Mandel matrix of the (rotated) phase stiffness, already
+// multiplied by k for notch voxels.
+template <typename T>
+struct MatEntry {
+    T C[36];         // s x s Mandel stiffness, row-major, s = 3 or 6
+    T K;             // bulk modulus (C:I = 3K I)
+    T Gc;            // critical energy release rate
+    T drive;         // 1, or 0 on notch voxels (no elastic driving force)
+    T pad;
+};
+
+// Geometry shared by all kernels of a handle.
+struct Geom {
+    int dim, s;
+    int nx, ny, nz;
+    int nxh;                  // nx / 2 + 1
+    long long N;              // voxels
+    long long Nspec;          // nxh * ny * nz (complex per component)
+    double h, ell, k_res;
+    double inv_N;             // 1 / N (inverse DFT normalisation)
+};
+
+}  // namespace mirve

@@ -1,0 +1,407 @@
+// Green-operator pipeline: F^-1{ P(xi) : F[ g(phi) C : eps ] } (Eq. 24 R1,
+// Eq. 26) as three kinds of LDS-staged passes over the field.
+//
+//  x-forward : per block, a few rows along x of all s components.  The
+//              prologue evaluates the degraded stress voxel by voxel (Eq. 2,
+//              12) -- or the conjugate-gradient direction update fused with
+//              it -- and two real rows are packed into one complex line
+//              (row 2i in the real part, row 2i+1 in the imaginary part),
+//              transformed, and split into their half spectra.
+//  axis pass : per block, TX consecutive kx columns of all s components
+//              along y (or z).  Forward, projection P(n) applied per
+//              frequency, inverse, in one visit when it is the last axis.
+//  x-inverse : the reverse of the x-forward pass; the epilogue stores the
+//              result or applies the conjugate-gradient update in place.
+//
+// Spectrum layout: [c][z][y][kx], kx in [0, n_x/2], pitch n_x/2 + 1.
+#include "kernels.h"
+#include "fft_device.h"
+#include "reduce.h"
+
+namespace mirve {
+
+// ---------------------------------------------------------------------------
+// pointwise helpers
+// ---------------------------------------------------------------------------
+
+template <typename T, int S>
+__device__ inline void mat_apply(const MatEntry<T>& m, const T (&e)[S], T (&o)[S]) {
+#pragma unroll
+    for (int a = 0; a < S; ++a) {
+        T acc = T(0);
+#pragma unroll
+        for (int b = 0; b < S; ++b) acc += m.C[a * S + b] * e[b];
+        o[a] = acc;
+    }
+}
+
+template <typename T>
+__device__ inline T degr(T phi, T k) {
+    const T u = T(1) - phi;
+    return u * u + k;
+}
+
+// Compatible-strain projection P(n) (Eq. 26, symmetric reading) on one
+// Mandel vector of complex spectra, n real and unit (or zero).
+template <typename T>
+__device__ inline void project2(cplx<T> (&v)[3], T n1, T n2) {
+    const T is2 = T(0.70710678118654752440084436210485);
+    const T s2 = T(1.4142135623730950488016887242097);
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+        const T a = part ? v[0].y : v[0].x;
+        const T b = part ? v[1].y : v[1].x;
+        const T c = (part ? v[2].y : v[2].x) * is2;
+        const T u1 = a * n1 + c * n2, u2 = c * n1 + b * n2;
+        const T w = n1 * u1 + n2 * u2;
+        const T p0 = T(2) * n1 * u1 - w * n1 * n1;
+        const T p1 = T(2) * n2 * u2 - w * n2 * n2;
+        const T p2 = s2 * (n1 * u2 + n2 * u1 - w * n1 * n2);
+        if (part) { v[0].y = p0; v[1].y = p1; v[2].y = p2; }
+        else { v[0].x = p0; v[1].x = p1; v[2].x = p2; }
+    }
+}
+
+template <typename T>
+__device__ inline void project3(cplx<T> (&v)[6], T n1, T n2, T n3) {
+    const T is2 = T(0.70710678118654752440084436210485);
+    const T s2 = T(1.4142135623730950488016887242097);
+    const T n[3] = {n1, n2, n3};
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+        T q[6];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) q[a] = part ? v[a].y : v[a].x;
+        const T t[3][3] = {{q[0], q[5] * is2, q[4] * is2},
+                           {q[5] * is2, q[1], q[3] * is2},
+                           {q[4] * is2, q[3] * is2, q[2]}};
+        T u[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) u[i] = t[i][0] * n[0] + t[i][1] * n[1] + t[i][2] * n[2];
+        const T w = n[0] * u[0] + n[1] * u[1] + n[2] * u[2];
+        auto P = [&](int i, int j) { return n[i] * u[j] + u[i] * n[j] - w * n[i] * n[j]; };
+        const T o[6] = {P(0, 0), P(1, 1), P(2, 2), s2 * P(1, 2), s2 * P(0, 2), s2 * P(0, 1)};
+#pragma unroll
+        for (int a = 0; a < 6; ++a) {
+            if (part) v[a].y = o[a];
+            else v[a].x = o[a];
+        }
+    }
+}
+
+__device__ inline int signed_k(int k, int N) { return (2 * k < N) ? k : k - N; }
+
+// Frequency direction with the Nyquist rule: on an even axis the index
+// k = -N/2 keeps its frequency only if every other index is zero.
+template <typename T>
+__device__ inline void freq_dir(const Geom& g, int kx, int ky, int kz, T& n1, T& n2, T& n3) {
+    int sx = (g.nx % 2 == 0 && 2 * kx == g.nx) ? -g.nx / 2 : kx;
+    int sy = signed_k(ky, g.ny);
+    int sz = g.dim == 3 ? signed_k(kz, g.nz) : 0;
+    // the tests use the original indices (a corner with several Nyquist
+    // indices loses all of them)
+    const int ox = sx, oy = sy, oz = sz;
+    const bool nyx = (g.nx % 2 == 0) && (ox == -g.nx / 2);
+    const bool nyy = (g.ny % 2 == 0) && (oy == -g.ny / 2);
+    const bool nyz = g.dim == 3 && (g.nz % 2 == 0) && (oz == -g.nz / 2);
+    if (nyx && (oy != 0 || oz != 0)) sx = 0;
+    if (nyy && (ox != 0 || oz != 0)) sy = 0;
+    if (nyz && (ox != 0 || oy != 0)) sz = 0;
+    // same h on every axis: xi_j is proportional to k_j / N_j
+    const double x1 = double(sx) / g.nx, x2 = double(sy) / g.ny, x3 = double(sz) / g.nz;
+    const double nr = sqrt(x1 * x1 + x2 * x2 + x3 * x3);
+    if (nr == 0.0) { n1 = n2 = n3 = T(0); return; }
+    n1 = T(x1 / nr);
+    n2 = T(x2 / nr);
+    n3 = T(x3 / nr);
+}
+
+// ---------------------------------------------------------------------------
+// x-forward pass
+// ---------------------------------------------------------------------------
+
+template <typename T, int S, int MODE, int MAXB>
+__global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    const Geom& g = a.g;
+    if (MODE == XF_CG && a.cg->done) return;
+    const int nx = g.nx;
+    const int nrows = g.ny * g.nz;
+    const int RB = a.rows_per_block;
+    const int npairs = RB / 2;
+    const int r0 = blockIdx.x * RB;
+
+    T beta = T(0);
+    bool first = false;
+    if (MODE == XF_CG) {
+        beta = T(a.cg->beta);
+        first = a.cg->first != 0;
+    }
+    double part = 0.0;
+    for (int v = threadIdx.x; v < RB * nx; v += blockDim.x) {
+        const int rl = v / nx, x = v - rl * nx;
+        const int row = r0 + rl;
+        T sig[S];
+        if (row < nrows) {
+            const long long idx = (long long)row * nx + x;
+            const MatEntry<T>& m = a.mat[a.mat_id[idx]];
+            const T gg = degr(a.phi[idx], T(g.k_res));
+            T e[S];
+            if (MODE == XF_CG) {
+#pragma unroll
+                for (int c = 0; c < S; ++c) {
+                    const T rv = a.r[c * g.N + idx];
+                    const T pv = first ? rv : rv + beta * a.p[c * g.N + idx];
+                    a.p[c * g.N + idx] = pv;
+                    e[c] = pv;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < S; ++c)
+                    e[c] = (a.eps ? a.eps[c * g.N + idx] : T(0)) + a.fcoef * a.f[c];
+            }
+            T o[S];
+            mat_apply<T, S>(m, e, o);
+#pragma unroll
+            for (int c = 0; c < S; ++c) {
+                sig[c] = gg * o[c];
+                if (MODE == XF_CG) part += double(e[c]) * double(sig[c]);
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < S; ++c) sig[c] = T(0);
+        }
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+            cplx<T>& dst = buf[(c * npairs + (rl >> 1)) * nx + x];
+            if (rl & 1) dst.y = sig[c];
+            else dst.x = sig[c];
+        }
+    }
+    __syncthreads();
+    lds_fft<T, MAXB>(buf, S * npairs, nx, 1, a.pl, a.tw, false);
+
+    const int nxh = g.nxh;
+    for (int e = threadIdx.x; e < S * npairs * nxh; e += blockDim.x) {
+        const int line = e / nxh, k = e - line * nxh;
+        const int c = line / npairs, pair = line - c * npairs;
+        const cplx<T> z = buf[line * nx + k];
+        const cplx<T> zm = buf[line * nx + (k == 0 ? 0 : nx - k)];
+        // A = (Z_k + conj Z_{-k}) / 2 ;  B = (Z_k - conj Z_{-k}) / (2i)
+        const cplx<T> A = {T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)};
+        const cplx<T> B = {T(0.5) * (z.y + zm.y), T(-0.5) * (z.x - zm.x)};
+        const int rowA = r0 + 2 * pair;
+        cplx<T>* sp = a.spec + (long long)c * g.Nspec;
+        if (rowA < nrows) sp[(long long)rowA * nxh + k] = A;
+        if (rowA + 1 < nrows) sp[(long long)(rowA + 1) * nxh + k] = B;
+    }
+    if (MODE == XF_CG) {
+        double pv[1] = {part};
+        block_sum_store<1>(pv, a.partials, 0, blockIdx.x);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// axis pass (y or z): forward, [projection], inverse
+// ---------------------------------------------------------------------------
+
+template <typename T, int S, int MODE, int MAXB>
+__global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    const Geom& g = a.g;
+    if (a.cg && a.cg->done) return;
+    const int TX = a.tx;
+    const int kx0 = blockIdx.x * TX;
+    const int other = blockIdx.y;            // z for the y pass, y for the z pass
+    const int Na = a.pl.N;
+    const long long astride = a.axis == 1 ? g.nxh : (long long)g.ny * g.nxh;
+    const long long base = a.axis == 1 ? (long long)other * g.ny * g.nxh : (long long)other * g.nxh;
+    const int W = S * TX;
+
+    for (int e = threadIdx.x; e < W * Na; e += blockDim.x) {
+        const int t = e % TX, c = (e / TX) % S, j = e / W;
+        const int kx = kx0 + t;
+        cplx<T> v = {T(0), T(0)};
+        if (kx < g.nxh) v = a.spec[(long long)c * g.Nspec + base + j * astride + kx];
+        buf[e] = v;
+    }
+    __syncthreads();
+    const bool inv_only = MODE == AX_INV;
+    lds_fft<T, MAXB>(buf, W, 1, W, a.pl, a.tw, inv_only);
+
+    if (MODE == AX_FWD_P_INV) {
+        for (int e = threadIdx.x; e < TX * Na; e += blockDim.x) {
+            const int t = e % TX, j = e / TX;
+            const int kx = kx0 + t;
+            int ky, kz;
+            if (a.axis == 1) { ky = j; kz = other; }
+            else { ky = other; kz = j; }
+            T n1, n2, n3;
+            freq_dir<T>(g, kx, ky, kz, n1, n2, n3);
+            cplx<T> v[S];
+#pragma unroll
+            for (int c = 0; c < S; ++c) v[c] = buf[j * W + c * TX + t];
+            if constexpr (S == 3) project2<T>(v, n1, n2);
+            else project3<T>(v, n1, n2, n3);
+#pragma unroll
+            for (int c = 0; c < S; ++c) buf[j * W + c * TX + t] = v[c];
+        }
+        __syncthreads();
+        lds_fft<T, MAXB>(buf, W, 1, W, a.pl, a.tw, true);
+    }
+
+    for (int e = threadIdx.x; e < W * Na; e += blockDim.x) {
+        const int t = e % TX, c = (e / TX) % S, j = e / W;
+        const int kx = kx0 + t;
+        if (kx < g.nxh) a.spec[(long long)c * g.Nspec + base + j * astride + kx] = buf[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// x-inverse pass
+// ---------------------------------------------------------------------------
+
+template <typename T, int S, int MODE, int MAXB>
+__global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    const Geom& g = a.g;
+    if (a.cg && a.cg->done) return;
+    const int nx = g.nx, nxh = g.nxh;
+    const int nrows = g.ny * g.nz;
+    const int RB = a.rows_per_block;
+    const int npairs = RB / 2;
+    const int r0 = blockIdx.x * RB;
+
+    for (int e = threadIdx.x; e < S * npairs * nx; e += blockDim.x) {
+        const int line = e / nx, k = e - line * nx;
+        const int c = line / npairs, pair = line - c * npairs;
+        const int rowA = r0 + 2 * pair;
+        const cplx<T>* sp = a.spec + (long long)c * g.Nspec;
+        const bool lo = k < nxh;
+        const int kk = lo ? k : nx - k;
+        cplx<T> A = {T(0), T(0)}, B = {T(0), T(0)};
+        if (rowA < nrows) A = sp[(long long)rowA * nxh + kk];
+        if (rowA + 1 < nrows) B = sp[(long long)(rowA + 1) * nxh + kk];
+        if (!lo) { A.y = -A.y; B.y = -B.y; }
+        buf[e] = {A.x - B.y, A.y + B.x};     // Z = A + i B
+    }
+    __syncthreads();
+    lds_fft<T, MAXB>(buf, S * npairs, nx, 1, a.pl, a.tw, true);
+
+    const T scale = T(g.inv_N) * a.scale;
+    T alpha = T(0);
+    if (MODE == XI_CG) alpha = T(a.cg->alpha);
+    double part = 0.0;
+    for (int v = threadIdx.x; v < RB * nx; v += blockDim.x) {
+        const int rl = v / nx, x = v - rl * nx;
+        const int row = r0 + rl;
+        if (row >= nrows) continue;
+        const long long idx = (long long)row * nx + x;
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+            const cplx<T> z = buf[(c * npairs + (rl >> 1)) * nx + x];
+            const T q = ((rl & 1) ? z.y : z.x) * scale;
+            if (MODE == XI_STORE) {
+                if (a.out) a.out[c * g.N + idx] = q;
+                part += double(q) * double(q);
+            } else {  // XI_CG
+                const long long o = c * g.N + idx;
+                a.x[o] += alpha * a.p[o];
+                const T rn = a.r[o] - alpha * q;
+                a.r[o] = rn;
+                part += double(rn) * double(rn);
+            }
+        }
+    }
+    double pv[1] = {part};
+    block_sum_store<1>(pv, a.partials, 0, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+// ---------------------------------------------------------------------------
+
+template <typename T, int S, int MODE>
+static hipError_t launch_xfwd_s(const XfwdArgs<T>& a, int maxb, int nblocks, size_t lds,
+                                hipStream_t st) {
+    switch (maxb) {
+        case 1: hipLaunchKernelGGL((k_xfwd<T, S, MODE, 1>), dim3(nblocks), dim3(256), lds, st, a); break;
+        case 2: hipLaunchKernelGGL((k_xfwd<T, S, MODE, 2>), dim3(nblocks), dim3(256), lds, st, a); break;
+        case 4: hipLaunchKernelGGL((k_xfwd<T, S, MODE, 4>), dim3(nblocks), dim3(256), lds, st, a); break;
+        default: hipLaunchKernelGGL((k_xfwd<T, S, MODE, 8>), dim3(nblocks), dim3(256), lds, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xfwd(const XfwdArgs<T>& a, int mode, int maxb, int nblocks, size_t lds,
+                       hipStream_t st) {
+    if (a.g.s == 3)
+        return mode == XF_CG ? launch_xfwd_s<T, 3, XF_CG>(a, maxb, nblocks, lds, st)
+                             : launch_xfwd_s<T, 3, XF_GREEN>(a, maxb, nblocks, lds, st);
+    return mode == XF_CG ? launch_xfwd_s<T, 6, XF_CG>(a, maxb, nblocks, lds, st)
+                         : launch_xfwd_s<T, 6, XF_GREEN>(a, maxb, nblocks, lds, st);
+}
+
+template <typename T, int S, int MODE>
+static hipError_t launch_axis_s(const AxisArgs<T>& a, int maxb, dim3 grid, size_t lds,
+                                hipStream_t st) {
+    switch (maxb) {
+        case 1: hipLaunchKernelGGL((k_axis<T, S, MODE, 1>), grid, dim3(256), lds, st, a); break;
+        case 2: hipLaunchKernelGGL((k_axis<T, S, MODE, 2>), grid, dim3(256), lds, st, a); break;
+        case 4: hipLaunchKernelGGL((k_axis<T, S, MODE, 4>), grid, dim3(256), lds, st, a); break;
+        default: hipLaunchKernelGGL((k_axis<T, S, MODE, 8>), grid, dim3(256), lds, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_axis(const AxisArgs<T>& a, int mode, int maxb, dim3 grid, size_t lds,
+                       hipStream_t st) {
+    if (a.g.s == 3) {
+        switch (mode) {
+            case AX_FWD: return launch_axis_s<T, 3, AX_FWD>(a, maxb, grid, lds, st);
+            case AX_INV: return launch_axis_s<T, 3, AX_INV>(a, maxb, grid, lds, st);
+            default: return launch_axis_s<T, 3, AX_FWD_P_INV>(a, maxb, grid, lds, st);
+        }
+    }
+    switch (mode) {
+        case AX_FWD: return launch_axis_s<T, 6, AX_FWD>(a, maxb, grid, lds, st);
+        case AX_INV: return launch_axis_s<T, 6, AX_INV>(a, maxb, grid, lds, st);
+        default: return launch_axis_s<T, 6, AX_FWD_P_INV>(a, maxb, grid, lds, st);
+    }
+}
+
+template <typename T, int S, int MODE>
+static hipError_t launch_xinv_s(const XinvArgs<T>& a, int maxb, int nblocks, size_t lds,
+                                hipStream_t st) {
+    switch (maxb) {
+        case 1: hipLaunchKernelGGL((k_xinv<T, S, MODE, 1>), dim3(nblocks), dim3(256), lds, st, a); break;
+        case 2: hipLaunchKernelGGL((k_xinv<T, S, MODE, 2>), dim3(nblocks), dim3(256), lds, st, a); break;
+        case 4: hipLaunchKernelGGL((k_xinv<T, S, MODE, 4>), dim3(nblocks), dim3(256), lds, st, a); break;
+        default: hipLaunchKernelGGL((k_xinv<T, S, MODE, 8>), dim3(nblocks), dim3(256), lds, st, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xinv(const XinvArgs<T>& a, int mode, int maxb, int nblocks, size_t lds,
+                       hipStream_t st) {
+    if (a.g.s == 3)
+        return mode == XI_CG ? launch_xinv_s<T, 3, XI_CG>(a, maxb, nblocks, lds, st)
+                             : launch_xinv_s<T, 3, XI_STORE>(a, maxb, nblocks, lds, st);
+    return mode == XI_CG ? launch_xinv_s<T, 6, XI_CG>(a, maxb, nblocks, lds, st)
+                         : launch_xinv_s<T, 6, XI_STORE>(a, maxb, nblocks, lds, st);
+}
+
+template hipError_t launch_xfwd<double>(const XfwdArgs<double>&, int, int, int, size_t, hipStream_t);
+template hipError_t launch_xfwd<float>(const XfwdArgs<float>&, int, int, int, size_t, hipStream_t);
+template hipError_t launch_axis<double>(const AxisArgs<double>&, int, int, dim3, size_t, hipStream_t);
+template hipError_t launch_axis<float>(const AxisArgs<float>&, int, int, dim3, size_t, hipStream_t);
+template hipError_t launch_xinv<double>(const XinvArgs<double>&, int, int, int, size_t, hipStream_t);
+template hipError_t launch_xinv<float>(const XinvArgs<float>&, int, int, int, size_t, hipStream_t);
+
+}  // namespace mirve

@@ -1,0 +1,59 @@
+// Deterministic block reductions (wave64 butterflies, then a fixed-order sum
+// over the waves of the block).  Each block writes its partial sums to
+// partials[v * stride + block]; a finalize kernel adds the blocks in index
+// order, so results are bitwise reproducible for a fixed launch shape.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mirve {
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Sum NV per-thread values over the block; thread 0 stores them.
+template <int NV>
+__device__ inline void block_sum_store(double (&v)[NV], double* partials, int stride, int bid) {
+    __shared__ double sh[NV][16];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sh[i][wid] = v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += sh[i][w];
+            partials[i * stride + bid] = s;
+        }
+    }
+}
+
+__device__ inline void block_max_store(double v, double* partials, int bid) {
+    __shared__ double sh[16];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    v = wave_max(v);
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        double m = sh[0];
+        for (int w = 1; w < nw; ++w) m = fmax(m, sh[w]);
+        partials[bid] = m;
+    }
+}
+
+}  // namespace mirve

@@ -1,0 +1,290 @@
+"""Seeded synthetic RVE workloads (microstructure geometry and load cases).
+
+This module only draws geometry (which voxel belongs to which phase, where
+the notch and its tips are) and lists the material constants and load of a
+workload.  It holds none of the solver's arithmetic, so the test oracle and
+the GPU library can both consume its output.
+
+All arrays use the public layout: shape (n_y, n_x) in 2D or (n_z, n_y, n_x)
+in 3D, C order, so x is the fastest index in memory.  Voxel centres sit at
+(i + 1/2) h.  Distances are periodic.
+
+The paper ships no RVE files (its composites, laminates and polycrystals are
+described only in prose, Sec. 5), so the generators follow its prose:
+random sequential adsorption of circular fibres (Sec. 5.2.2), periodic
+Voronoi grains with in-plane orientations (Sec. 5.3), orthogonal laminates
+(Sec. 5.1.2), and a one-voxel-thick notch row with crack-tip enrichment
+points at its two ends (Sec. 4.3).
+"""
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+
+@dataclass
+class Workload:
+    """One RVE toughness problem in the public layout."""
+    n: tuple                      # (n_x, n_y[, n_z])
+    h: float
+    ell: float
+    phases: List[dict]            # {"kind": "iso", E, nu, Gc} or {"kind": "cubic", C11, C12, C44, Gc}
+    phase_id: np.ndarray          # uint16, shape reversed(n)
+    f: np.ndarray                 # Mandel load direction (s,)
+    dtau: float
+    theta: Optional[np.ndarray] = None     # per-voxel in-plane angle (rad) or None
+    void: Optional[np.ndarray] = None      # uint8 notch mask
+    phi_disc: Optional[np.ndarray] = None  # uint8 enrichment points
+    phi_M: float = 0.8
+    k: float = 1e-6
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def dim(self):
+        return len(self.n)
+
+    @property
+    def shape(self):
+        return tuple(reversed(self.n))
+
+
+def _centres(n, h):
+    """Voxel-centre coordinates, one array per axis, in public layout."""
+    axes = [(np.arange(N) + 0.5) * h for N in n]
+    grids = np.meshgrid(*axes, indexing="ij")          # [x, y, z] indexing
+    return [np.ascontiguousarray(g.T) for g in grids]  # public layout
+
+
+def _periodic_delta(a, b, L):
+    d = np.abs(a - b) % L
+    return np.minimum(d, L - d)
+
+
+def rsa_disks(n, h, rng, radius_sampler, *, count=None, vf=None, min_gap=1.0,
+              forbidden=None, max_tries=200000):
+    """Random sequential adsorption of non-overlapping periodic disks/spheres.
+
+    Disks are added until ``count`` are placed or the voxel volume fraction
+    reaches ``vf``.  ``forbidden(centre, r)`` may veto a candidate.  Returns
+    (list of (centre, r), mask of inclusion voxels in public layout).
+    """
+    d = len(n)
+    L = np.array(n, dtype=float) * h
+    coords = _centres(n, h)
+    mask = np.zeros(tuple(reversed(n)), dtype=bool)
+    placed = []
+    tries = 0
+    while True:
+        if count is not None and len(placed) >= count:
+            break
+        if vf is not None and mask.mean() >= vf:
+            break
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("RSA could not place more inclusions")
+        r = float(radius_sampler(rng))
+        c = rng.uniform(0.0, 1.0, size=d) * L
+        ok = True
+        for (c2, r2) in placed:
+            dist = math.sqrt(sum(_periodic_delta(c[j], c2[j], L[j]) ** 2 for j in range(d)))
+            if dist < r + r2 + min_gap:
+                ok = False
+                break
+        if ok and forbidden is not None and forbidden(c, r):
+            ok = False
+        if not ok:
+            continue
+        dist2 = sum(_periodic_delta(coords[j], c[j], L[j]) ** 2 for j in range(d))
+        mask |= dist2 <= r * r
+        placed.append((c, r))
+    return placed, mask
+
+
+def notch_2d(n, h, row, x0, x1):
+    """A notch row y = row, x in [x0, x1): void mask and tip points."""
+    nx, ny = n
+    void = np.zeros((ny, nx), dtype=np.uint8)
+    void[row, x0:x1] = 1
+    tips = np.zeros((ny, nx), dtype=np.uint8)
+    tips[row, x0] = 1
+    tips[row, x1 - 1] = 1
+    return void, tips
+
+
+def notch_3d_square(n, h, zrow, x0, x1, y0, y1):
+    """A square notch in plane z = zrow: void mask and its boundary voxels
+    (the crack front, used as enrichment points)."""
+    nx, ny, nz = n
+    void = np.zeros((nz, ny, nx), dtype=np.uint8)
+    void[zrow, y0:y1, x0:x1] = 1
+    tips = np.zeros_like(void)
+    tips[zrow, y0:y1, x0] = 1
+    tips[zrow, y0:y1, x1 - 1] = 1
+    tips[zrow, y0, x0:x1] = 1
+    tips[zrow, y1 - 1, x0:x1] = 1
+    return void, tips
+
+
+def load_yy(dim):
+    """f = e_y (x) e_y in Mandel form (Eq. 39)."""
+    f = np.zeros(3 if dim == 2 else 6)
+    f[1] = 1.0
+    return f
+
+
+def load_zz():
+    f = np.zeros(6)
+    f[2] = 1.0
+    return f
+
+
+def iso(E, nu, Gc):
+    return {"kind": "iso", "E": float(E), "nu": float(nu), "Gc": float(Gc)}
+
+
+def cubic(C11, C12, C44, Gc):
+    return {"kind": "cubic", "C11": float(C11), "C12": float(C12), "C44": float(C44), "Gc": float(Gc)}
+
+
+# --------------------------------------------------------------------------
+# named workloads
+# --------------------------------------------------------------------------
+
+def composite_2d_small(seed=1):
+    """64 x 64 two-phase composite, 10 disks of radius 6 (plain FP64 case).
+
+    Matrix E=1, nu=0.3, Gc=1; inclusions E=5, nu=0.25, Gc=2; l = 1.5 h;
+    16-voxel notch along x at mid-height with enrichment at both tips;
+    uniaxial y load; dtau = 0.01 Gc L_x.
+    """
+    n = (64, 64)
+    h = 1.0
+    r = 6.0
+    row = 32
+    yc = (row + 0.5) * h
+
+    def forbidden(c, rad):
+        return _periodic_delta(c[1], yc, n[1] * h) < rad + 2.0
+
+    rng = np.random.default_rng(seed)
+    _, mask = rsa_disks(n, h, rng, lambda g: r, count=10, forbidden=forbidden)
+    void, tips = notch_2d(n, h, row, 24, 40)
+    pid = mask.astype(np.uint16)
+    return Workload(n=n, h=h, ell=1.5, phases=[iso(1, 0.3, 1), iso(5, 0.25, 2)],
+                    phase_id=pid, f=load_yy(2), dtau=0.01 * 1.0 * n[0] * h,
+                    void=void, phi_disc=tips, phi_M=0.8, k=1e-6,
+                    meta={"name": "composite_2d_64", "vf": float(mask.mean()), "seed": seed})
+
+
+def composite_2d(n=256, seed=1, E_ratio=5.0, Gc_ratio=2.0, vf=0.3, ell=2.0, crack=40,
+                 rmin=5.0, rmax=9.0):
+    """n x n fibre composite: disks with r ~ U[rmin, rmax] up to volume
+    fraction vf, elastic and toughness contrasts, a crack-voxel notch."""
+    nn = (n, n)
+    h = 1.0
+    row = n // 2
+    yc = (row + 0.5) * h
+
+    def forbidden(c, rad):
+        return _periodic_delta(c[1], yc, n * h) < rad + 2.0 and \
+            _periodic_delta(c[0], (n // 2) * h, n * h) < crack / 2 + rad + 2.0
+
+    rng = np.random.default_rng(seed)
+    placed, mask = rsa_disks(nn, h, rng, lambda g: g.uniform(rmin, rmax), vf=vf,
+                             forbidden=forbidden)
+    x0 = n // 2 - crack // 2
+    void, tips = notch_2d(nn, h, row, x0, x0 + crack)
+    return Workload(n=nn, h=h, ell=ell,
+                    phases=[iso(1, 0.3, 1), iso(E_ratio, 0.25, Gc_ratio)],
+                    phase_id=mask.astype(np.uint16), f=load_yy(2), dtau=0.01 * n * h,
+                    void=void, phi_disc=tips, phi_M=0.8, k=1e-6,
+                    meta={"name": "composite_2d_%d" % n, "fibres": len(placed),
+                          "vf": float(mask.mean()), "seed": seed})
+
+
+def homogeneous_2d(nx=32, ny=32, ell=1.5, crack=8, E=1.0, nu=0.3, Gc=1.0, phi_M=0.8,
+                   dtau_frac=0.01):
+    """Homogeneous plate with a centred notch (the 'broken in two' check)."""
+    n = (nx, ny)
+    h = 1.0
+    row = ny // 2
+    x0 = nx // 2 - crack // 2
+    void, tips = notch_2d(n, h, row, x0, x0 + crack)
+    return Workload(n=n, h=h, ell=ell, phases=[iso(E, nu, Gc)],
+                    phase_id=np.zeros((ny, nx), dtype=np.uint16), f=load_yy(2),
+                    dtau=dtau_frac * Gc * nx * h, void=void, phi_disc=tips, phi_M=phi_M,
+                    k=1e-6, meta={"name": "homogeneous_2d_%dx%d" % (nx, ny)})
+
+
+def laminate_2d(nx=64, ny=32, widths=(0.5, 0.5), Gcs=(1.0, 3.0), Es=(1.0, 1.0), nus=(0.3, 0.3),
+                ell=1.5, crack_frac=0.1):
+    """Orthogonal laminate: layers normal to x (the crack, along x, crosses
+    them), notch of crack_frac L_x starting at x = 0 at mid-height."""
+    n = (nx, ny)
+    h = 1.0
+    pid = np.zeros((ny, nx), dtype=np.uint16)
+    edges = np.round(np.cumsum((0.0,) + tuple(widths)) * nx).astype(int)
+    for p in range(len(widths)):
+        pid[:, edges[p]:edges[p + 1]] = p
+    row = ny // 2
+    a = max(2, int(round(crack_frac * nx)))
+    void, tips = notch_2d(n, h, row, 0, a)
+    tips[row, 0] = 0          # the notch starts at the periodic boundary: one tip
+    phases = [iso(Es[p], nus[p], Gcs[p]) for p in range(len(widths))]
+    return Workload(n=n, h=h, ell=ell, phases=phases, phase_id=pid, f=load_yy(2),
+                    dtau=0.01 * min(Gcs) * nx * h, void=void, phi_disc=tips, phi_M=0.8,
+                    k=1e-6, meta={"name": "laminate_2d", "edges": edges.tolist()})
+
+
+def polycrystal_2d(n=512, grains=200, seed=1000, zener=2.0, a_cleave=1.0, ell=2.0,
+                   crack_frac=0.1):
+    """Periodic Voronoi polycrystal with uniform in-plane orientations.
+
+    Cubic C11 = 1, C12 = 0.5, C44 = z/4 (so 2 C44 / (C11 - C12) = z);
+    per-grain Gc = 1 + a cos^2(4 theta).  Each grain is its own phase.
+    """
+    nn = (n, n)
+    h = 1.0
+    rng = np.random.default_rng(seed)
+    seeds = rng.uniform(0.0, n * h, size=(grains, 2))
+    theta_g = rng.uniform(0.0, 2.0 * np.pi, size=grains)
+    X, Y = _centres(nn, h)
+    best = np.full(X.shape, np.inf)
+    gid = np.zeros(X.shape, dtype=np.uint16)
+    for g in range(grains):
+        d2 = _periodic_delta(X, seeds[g, 0], n * h) ** 2 + _periodic_delta(Y, seeds[g, 1], n * h) ** 2
+        closer = d2 < best
+        best[closer] = d2[closer]
+        gid[closer] = g
+    C44 = zener / 4.0
+    phases = [cubic(1.0, 0.5, C44, 1.0 + a_cleave * math.cos(4.0 * t) ** 2) for t in theta_g]
+    theta = theta_g[gid]
+    row = n // 2
+    a = max(2, int(round(crack_frac * n)))
+    x0 = n // 2 - a // 2
+    void, tips = notch_2d(nn, h, row, x0, x0 + a)
+    return Workload(n=nn, h=h, ell=ell, phases=phases, phase_id=gid, f=load_yy(2),
+                    dtau=0.01 * n * h, theta=theta, void=void, phi_disc=tips, phi_M=0.8,
+                    k=1e-6, meta={"name": "polycrystal_2d_%d" % n, "grains": grains,
+                                  "seed": seed, "zener": zener, "a": a_cleave})
+
+
+def composite_3d(n=128, seed=1, spheres=40, vf=0.2, E_ratio=5.0, Gc_ratio=3.0, ell=2.0):
+    """n^3 sphere composite; square notch L/2 x L/2 in the z mid-plane; z load."""
+    nn = (n, n, n)
+    h = 1.0
+    r = (vf * n ** 3 / spheres * 3.0 / (4.0 * math.pi)) ** (1.0 / 3.0)
+    zc = (n // 2 + 0.5) * h
+
+    def forbidden(c, rad):
+        return _periodic_delta(c[2], zc, n * h) < rad + 2.0
+
+    rng = np.random.default_rng(seed)
+    _, mask = rsa_disks(nn, h, rng, lambda g: r, count=spheres, forbidden=forbidden)
+    q = n // 4
+    void, tips = notch_3d_square(nn, h, n // 2, q, q + n // 2, q, q + n // 2)
+    return Workload(n=nn, h=h, ell=ell, phases=[iso(1, 0.3, 1), iso(E_ratio, 0.3, Gc_ratio)],
+                    phase_id=mask.astype(np.uint16), f=load_zz(), dtau=0.01 * n * n * h * h,
+                    void=void, phi_disc=tips, phi_M=0.8, k=1e-6,
+                    meta={"name": "composite_3d_%d" % n, "r": r, "vf": float(mask.mean())})

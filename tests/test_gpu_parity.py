@@ -1,0 +1,121 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+FP64 mode must agree with the oracle to 1e-10 relative (operators to
+1e-12); mixed mode to 1e-5 on the stress field.
+"""
+import numpy as np
+import pytest
+
+from oracle import model, solver, spectral
+from paper_2508_07424_amd import workloads as W
+from tests.helpers import oracle_problem, rel, to_oracle
+
+pytestmark = pytest.mark.gpu
+
+TIGHT = dict(tol=1e-12, tol_cg=1e-13, tol_pcg=1e-14, tol_al=1e-13)
+OTIGHT = dict(tol=1e-12, tol_cg=1e-13, tol_al=1e-13)
+
+
+def _lib():
+    from paper_2508_07424_amd import mirve
+    return mirve
+
+
+def _cases():
+    return [
+        ("composite64", lambda: W.composite_2d_small()),
+        ("homog48x40", lambda: W.homogeneous_2d(nx=48, ny=40, crack=8)),
+        ("homog30x18", lambda: W.homogeneous_2d(nx=30, ny=18, crack=6)),
+        ("poly64", lambda: W.polycrystal_2d(n=64, grains=12, seed=3, zener=3.0, a_cleave=2.0)),
+        ("laminate63x21", lambda: W.laminate_2d(nx=63, ny=21, widths=(0.4, 0.6), Gcs=(1, 3))),
+        ("comp3d16", lambda: W.composite_3d(n=16, spheres=2, vf=0.1)),
+        ("comp3d12x10x14", lambda: W.Workload(
+            n=(12, 10, 14), h=1.0, ell=1.5, phases=[W.iso(1, 0.3, 1), W.iso(3, 0.2, 2)],
+            phase_id=(np.random.default_rng(7).random((14, 10, 12)) < 0.3).astype(np.uint16),
+            f=W.load_zz(), dtau=1.0)),
+    ]
+
+
+@pytest.mark.parametrize("name,make", _cases())
+def test_green_op_fp64(name, make):
+    m = _lib()
+    w = make()
+    print("case", name, w.n, flush=True)
+    r = m.from_workload(w)
+    prob = oracle_problem(w)
+    st = solver.State(prob)
+    rng = np.random.default_rng(11)
+    s = prob.s
+    eps = rng.standard_normal((s,) + w.shape)
+    gpu = r.rve_apply_green_op(eps)
+    sig = model.stress(to_oracle(eps, prob.d), st.phi, prob.mat)
+    ref = prob.to_public(spectral.green_apply(sig, prob.P))
+    assert rel(gpu, ref) < 1e-12
+    # initial state of the enrichment (Eq. 35, 37a)
+    assert rel(r.rve_get_field("phi_ini"), prob.to_public(st.phi_ini)) < 1e-11
+    assert rel(r.rve_get_field("psi_ini"), prob.to_public(st.psi_ini)) < 1e-9
+    assert abs(r.rve_get_scalars()["tau0"] - st.tau) <= 1e-11 * max(abs(st.tau), 1e-300) + 1e-300
+
+
+@pytest.mark.parametrize("name,make", _cases()[:3] + _cases()[5:6])
+def test_green_op_mixed(name, make):
+    m = _lib()
+    w = make()
+    print("case", name, w.n, flush=True)
+    r = m.from_workload(w, precision=m.RVE_PREC_MIXED)
+    prob = oracle_problem(w)
+    st = solver.State(prob)
+    rng = np.random.default_rng(12)
+    eps = rng.standard_normal((prob.s,) + w.shape)
+    gpu = r.rve_apply_green_op(eps)
+    sig = model.stress(to_oracle(eps, prob.d), st.phi, prob.mat)
+    ref = prob.to_public(spectral.green_apply(sig, prob.P))
+    assert rel(gpu, ref) < 1e-5
+
+
+@pytest.mark.parametrize("name,make", [_cases()[0], _cases()[3], _cases()[5]])
+def test_mechanics_and_damage(name, make):
+    m = _lib()
+    w = make()
+    print("case", name, w.n, flush=True)
+    r = m.from_workload(w, **TIGHT)
+    prob = oracle_problem(w, **OTIGHT)
+    st = solver.State(prob)
+    it, S1 = r.rve_solve_mechanics()
+    x, it_o = solver.mechanics(prob, st.phi, st.x)
+    eps1_o, _, psi1_o, S1_o = solver.unit_response(prob, st.phi, x)
+    print("cg iterations gpu", it, "oracle", it_o, flush=True)
+    assert rel(r.rve_get_field("eps1"), prob.to_public(eps1_o)) < 1e-10
+    assert abs(S1 - S1_o) <= 1e-10 * abs(S1_o)
+    # damage balance at a load E from the same unit energy
+    r.rve_set_field("psi1", prob.to_public(psi1_o))
+    E = 1.5 * np.sqrt(1.0 / prob.ell / max(psi1_o.max(), 1e-300))
+    D, npcg = r.rve_solve_damage(E, commit=True)
+    H = solver.history_field(prob, E, psi1_o, st.psi_ini, st.H)
+    phi_o = model.solve_damage(H, prob.mat.Gc, prob.ell, prob.Dmats)
+    D_o = model.dissipation(phi_o, prob.mat.Gc, prob.ell, prob.h)
+    print("pcg iterations", npcg, flush=True)
+    assert abs(D - D_o) <= 1e-10 * D_o
+    assert rel(r.rve_get_field("phi"), prob.to_public(phi_o)) < 1e-10
+
+
+@pytest.mark.parametrize("name,make,nsteps", [
+    ("composite64", lambda: W.composite_2d_small(), 3),
+    ("homog48x40", lambda: W.homogeneous_2d(nx=48, ny=40, crack=8), 3),
+])
+def test_steps_fp64(name, make, nsteps):
+    m = _lib()
+    w = make()
+    print("case", name, w.n, flush=True)
+    r = m.from_workload(w, **TIGHT)
+    prob = oracle_problem(w, **OTIGHT)
+    st = solver.State(prob)
+    for k in range(nsteps):
+        info = r.rve_step_dissipation(w.dtau)
+        rec = solver.step(prob, st, w.dtau)
+        print("step", k + 1, {q: info[q] for q in ("E", "Sigma", "D", "n_stagger", "n_cg", "n_pcg",
+                                                   "res_R1", "res_R2", "res_R3")}, flush=True)
+        for key in ("E", "Sigma", "D", "T"):
+            assert abs(info[key] - rec[key]) <= 1e-9 * abs(rec[key]), (key, info[key], rec[key])
+    assert rel(r.rve_get_field("phi"), prob.to_public(st.phi)) < 1e-9
+    assert rel(r.rve_get_field("hist"), prob.to_public(st.H)) < 1e-9
