@@ -1,0 +1,166 @@
+#!/usr/bin/env python
+"""Benchmark of the FFT Green-operator solve of the phase-field-fracture
+toughness solver on one MI355X.
+
+A step is one dissipation-controlled step (Eq. 16 of the paper: mechanics CG
+with the fused Green operator, damage PCG, arc-length constraint, commit and
+fracture test) of every RVE of a batch of synthetic 256 x 256 fibre
+composites: elastic contrast {2, 5, 10} x toughness contrast {1, 2, 4}, fibre
+radius U[5, 9] up to volume fraction 0.3, l = 2 voxels, a 40-voxel notch.
+The RVEs are loaded to an intermediate state by the warm-up steps, then K
+steps are timed.
+
+value = sum over RVEs of (voxels x Green-operator applications) / seconds.
+
+The JSON line also carries the roofline of the dominant kernel (timed with
+HIP events on its stream, repeated launches of the same kernel on the same
+data) and the CPU oracle's rate on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+os.environ.setdefault("OMP_NUM_THREADS", "1")
+os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
+os.environ.setdefault("MKL_NUM_THREADS", "1")
+
+HBM_PEAK_GBS = 8000.0
+PASS_NAMES = {3: "x-forward + constitutive + CG direction (k_xfwd)",
+              1: "axis pass: y FFT, projection, inverse y FFT (k_axis)",
+              4: "x-inverse + CG update (k_xinv)"}
+
+
+def _workloads(size, batch, seed0=1):
+    from paper_2508_07424_amd import workloads as W
+    combos = [(e, g) for e in (2.0, 5.0, 10.0) for g in (1.0, 2.0, 4.0)]
+    out = []
+    for i in range(batch):
+        e, g = combos[i % len(combos)]
+        out.append(W.composite_2d(n=size, seed=seed0 + i, E_ratio=e, Gc_ratio=g, vf=0.3, ell=2.0,
+                                  crack=int(round(40 * size / 256))))
+    return out
+
+
+def roofline(r, torch, repeat=50):
+    """Average duration of each CG-iteration pass (one launch covers every
+    RVE of the batch) by HIP events on the handle's stream; returns the
+    dominant one with its algorithmic bytes."""
+    stream = torch.cuda.current_stream() if r.stream is None else r.stream
+    res = {}
+    for p in (3, 1, 4):
+        r.rve_profile_pass(p, 3)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        nbytes = r.rve_profile_pass(p, repeat)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / repeat
+        res[p] = (ms, nbytes)
+    dom = max(res, key=lambda k: res[k][0])
+    ms, nbytes = res[dom]
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": PASS_NAMES[dom], "avg_us": round(ms * 1e3, 2),
+            "bytes_per_launch": nbytes,
+            "passes_us": {PASS_NAMES[k]: round(v[0] * 1e3, 2) for k, v in res.items()}}
+
+
+def cpu_baseline(w, seconds):
+    """The oracle's conjugate-gradient Green-operator solve on the host,
+    bounded to about `seconds` of work: voxel-iterations per second."""
+    import numpy as np
+    from oracle import solver
+    prob = solver.Problem(w.n, w.h, w.ell, w.phases, w.phase_id, w.f, theta=w.theta, void=w.void,
+                          phi_disc=w.phi_disc, phi_M=w.phi_M, k=w.k, tol_cg=1e-300, max_cg=5)
+    st = solver.State(prob)
+    t0 = time.perf_counter()
+    x, it = solver.mechanics(prob, st.phi, st.x)
+    t1 = time.perf_counter()
+    per = (t1 - t0) / max(it + 2, 1)                 # CG iterations + the two set-up applications
+    n_it = max(5, int(seconds / max(per, 1e-6)))
+    prob.max_cg = n_it
+    t0 = time.perf_counter()
+    x, it = solver.mechanics(prob, st.phi, st.x)
+    t1 = time.perf_counter()
+    N = int(np.prod(w.n))
+    return {"value": round(N * (it + 2) / (t1 - t0), 1), "unit": "voxel-iter/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d CG iterations (+2 set-up Green operators) of the oracle's mechanics solve on "
+                      "one %s RVE at its enriched initial state, numpy FFT, 1 thread, %.1f s"
+                      % (it, "x".join(map(str, w.n)), t1 - t0)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=9)
+    ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(RVEs shard across GPUs with no collective; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2508_07424_amd import mirve
+    prec = mirve.RVE_PREC_FP64 if args.precision == "fp64" else mirve.RVE_PREC_MIXED
+    wls = _workloads(args.size, args.batch)
+    # one batched handle: every launch covers all RVEs of the batch
+    rve = mirve.from_workloads(wls, precision=prec)
+    dtaus = [w.dtau for w in wls]
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        _, st = rve.rve_step_dissipation_slots(dtaus)
+        assert all(v == 0 for v in st), st
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    greenops = 0
+    for _ in range(args.steps):
+        info, st = rve.rve_step_dissipation_slots(dtaus)
+        assert all(v == 0 for v in st), st
+        greenops += sum(rve.N * i["n_greenop"] for i in info)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sec = t1 - t0
+    value = greenops / sec
+
+    roof = roofline(rve, torch)
+    out = {
+        "metric": "voxel-iter/s FFT Green-op solve",
+        "value": round(value, 1),
+        "unit": "voxel-iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * sec / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == mirve.RVE_PREC_FP64 else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": "2D fibre composite %dx%d, vf 0.3, r~U[5,9], E ratio {2,5,10} x "
+                               "Gc ratio {1,2,4}, l=2, 40-voxel notch" % (args.size, args.size),
+                   "batch": args.batch, "precision": args.precision,
+                   "rve_steps_per_s": round(args.batch * args.steps / sec, 3),
+                   "greenops_per_rve_step": round(greenops / (args.batch * args.steps) /
+                                                  (args.size * args.size), 1)},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wls[0], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -32,6 +32,10 @@
  *     on distinct streams.
  *   - Steps are transactional: a step that fails leaves the committed state
  *     (phi, history, E, curve) unchanged.
+ *   - A handle holds cfg.batch RVE slots of the same grid.  Every kernel
+ *     launch covers all slots; slots advance in lockstep and each keeps its
+ *     own microstructure, state and convergence.  The functions without a
+ *     slot argument address slot 0 (rve_step_dissipation needs batch = 1).
  */
 #ifndef MIRVE_H
 #define MIRVE_H
@@ -102,6 +106,8 @@ typedef struct {
                               without a notch voxel, times h^(dim-1) (Eq. 32)        */
     int    max_materials;  /* capacity of the per-material table: distinct
                               (phase, theta, notch) combinations, <= 65536          */
+    int    batch;          /* RVE slots of this handle (same grid, own microstructure
+                              and state), advanced together by every launch; 1-1024  */
 } rve_config;
 
 typedef struct {
@@ -157,10 +163,28 @@ int rve_set_microstructure(rve_handle h, const uint16_t* phase_id, const rve_pha
                            int nphases, const double* theta, const uint8_t* void_mask,
                            const uint8_t* phi_disc, double phi_M);
 
+/* Same for one slot of a batched handle; slot in [0, batch). */
+int rve_set_microstructure_slot(rve_handle h, int slot, const uint16_t* phase_id,
+                                const rve_phase* phases, int nphases, const double* theta,
+                                const uint8_t* void_mask, const uint8_t* phi_disc, double phi_M);
+
 /* One dissipation-controlled step tau^{n+1} = tau^n + dtau (Eq. 16): the
  * staggered fixed point of equilibrium, damage and the constraint, then
- * commit and the fracture test.  out may be NULL. */
+ * commit and the fracture test.  out may be NULL.  Needs batch = 1. */
 int rve_step_dissipation(rve_handle h, double dtau, rve_step_info* out);
+
+/* One lockstep step of every slot b with dtau[b] > 0 (dtau[b] = 0: the slot
+ * idles).  dtau, info (may be NULL) and status have `batch` entries; each
+ * slot's step is transactional on its own.  Returns RVE_OK if every stepped
+ * slot succeeded, else the first failure code. */
+int rve_step_dissipation_slots(rve_handle h, const double* dtau, rve_step_info* info,
+                               int* status);
+
+/* Number of slots of the handle. */
+int rve_batch_size(rve_handle h);
+
+/* Forget a slot's microstructure and state (the slot can be set again). */
+int rve_release_slot(rve_handle h, int slot);
 
 /* Advance several independent handles by one step each, overlapping their
  * device work (each handle must have its own stream). info may be NULL;
@@ -171,25 +195,31 @@ int rve_step_dissipation_batch(rve_handle* hs, int count, const double* dtau,
 /* G_eff = V (T^F - 1/2 Sigma^F E^F) / A_g at the fracture point F
  * (Eq. 32-33).  RVE_ENOTDONE before F. */
 int rve_effective_toughness(rve_handle h, double* G_eff);
+int rve_effective_toughness_slot(rve_handle h, int slot, double* G_eff);
 
 /* Copy a field (RVE_FIELD_*) to / from a host array of doubles in the host
  * layout above.  count must equal the field's size.  Setting PHI or HIST
  * replaces the committed state (used for checkpoints and tests). */
 int rve_get_field(rve_handle h, int which, double* host, size_t count);
 int rve_set_field(rve_handle h, int which, const double* host, size_t count);
+int rve_get_field_slot(rve_handle h, int slot, int which, double* host, size_t count);
+int rve_set_field_slot(rve_handle h, int slot, int which, const double* host, size_t count);
 
-/* Scalars of the committed state: out[0..5] = {E, Sigma, T, tau, tau0, step}. */
+/* Scalars of the committed state: out[0..5] = {E, Sigma, T, tau, tau0, step}.
+ * The slot form also returns out[6] = fractured and out[7] = A_g (8 values). */
 int rve_get_scalars(rve_handle h, double* out6);
 int rve_set_scalars(rve_handle h, const double* in6);
+int rve_get_scalars_slot(rve_handle h, int slot, double* out8);
+int rve_set_scalars_slot(rve_handle h, int slot, const double* in6);
 
 /* Green operator (Eq. 24 R1): out = F^-1{ P : F[ g(phi) C : eps ] } at the
  * committed phi, for eps given as s*N host doubles.  Used for parity. */
 int rve_apply_green_op(rve_handle h, const double* eps_host, double* out_host);
 
 /* Device-resident variant for benchmarking: eps and out are device arrays
- * of s*N elements of the handle's bulk type (double, or float in MIXED
- * mode); `repeat` applications are enqueued on the handle's stream
- * (asynchronous). */
+ * of batch*s*N elements of the handle's bulk type (double, or float in MIXED
+ * mode), one block of s*N per slot; `repeat` applications over every slot
+ * with a microstructure are enqueued on the handle's stream. */
 int rve_apply_green_op_device(rve_handle h, const void* eps_dev, void* out_dev, int repeat);
 
 /* Equilibrium for the unit load at the committed phi (Eq. 16a): updates
@@ -204,6 +234,17 @@ int rve_solve_damage(rve_handle h, double E, double* D, int* iterations, int com
 /* Dissipation D(phi) and crack surface Gamma(phi) of the committed phi. */
 int rve_dissipation(rve_handle h, double* D, double* Gamma);
 
+/* Benchmark helper: enqueue `repeat` launches of one kind of FFT pass of the
+ * Green operator on the handle's stream (asynchronous) and report the
+ * compulsory HBM bytes of one launch (every input read once, every output
+ * written once).  pass: 0 x-forward with the constitutive law, 1 the axis
+ * pass carrying the projection, 2 x-inverse (store), 3 x-forward with the CG
+ * direction update, 4 x-inverse with the CG update.  Works on scratch
+ * buffers; the committed state is not changed. */
+int rve_profile_pass(rve_handle h, int pass, int repeat, double* bytes_per_launch);
+
+/* Message of the last error of h (or of the calling thread when h is NULL,
+ * e.g. after a failed rve_create / rve_query_workspace). */
 const char* rve_last_error(rve_handle h);
 const char* rve_version(void);
 

@@ -56,9 +56,11 @@ struct Geom {
     int nx, ny, nz;
     int nxh;                  // nx / 2 + 1
     long long N;              // voxels
-    long long Nspec;          // nxh * ny * nz (complex per component)
+    long long Nspec;          // nxh * ny * nz (complex per component); layout [kx][z][y]
     double h, ell, k_res;
     double inv_N;             // 1 / N (inverse DFT normalisation)
+    int B;                    // RVEs in the batch
+    int mstride;              // material-table entries per RVE
 };
 
 }  // namespace mirve

@@ -97,14 +97,22 @@ __device__ inline void dft_any(cplx<T> (&v)[8], int R, bool inv) {
     }
 }
 
-// In-place DFT of `nlines` lines in LDS.  Element e of line l is at
-// buf[l * lstride + e * estride].  MAXB bounds the butterflies a thread
-// carries per pass: nlines * N / min_radix <= MAXB * blockDim.x.
+// LDS element index of element e of a line: one padding slot after every 16
+// elements, so that the strided scatters of the early Stockham passes (stride
+// R elements) spread over all banks instead of hitting a few.
+__device__ __forceinline__ int lp(int e) { return e + (e >> 4); }
+
+// LDS line stride for lines of N elements (odd, so that walking across lines
+// is conflict-free too).
+__host__ __device__ inline int lds_line(int N) { return N + (N >> 4) + 1; }
+
+// In-place DFT of `nlines` lines in LDS; element e of line l is at
+// buf[l * lstride + lp(e)].  MAXB bounds the butterflies a thread carries
+// per pass: nlines * N / min_radix <= MAXB * blockDim.x.
 template <typename T, int MAXB>
-__device__ void lds_fft(cplx<T>* buf, int nlines, int lstride, int estride, const AxisPlan& pl,
+__device__ void lds_fft(cplx<T>* buf, int nlines, int lstride, const AxisPlan& pl,
                         const cplx<T>* __restrict__ tw, bool inv) {
     const int N = pl.N;
-    const bool line_fast = lstride < estride;
     int p = 1;
     for (int st = 0; st < pl.nst; ++st) {
         const int R = pl.rad[st];
@@ -116,14 +124,12 @@ __device__ void lds_fft(cplx<T>* buf, int nlines, int lstride, int estride, cons
         for (int c = 0; c < MAXB; ++c) {
             const int b = threadIdx.x + c * blockDim.x;
             if (b < total) {
-                int line, i;
-                if (line_fast) { line = b % nlines; i = b / nlines; }
-                else { line = b / nb; i = b - line * nb; }
+                const int line = b / nb, i = b - line * nb;
                 const cplx<T>* base = buf + line * lstride;
                 const int k = i % p;
 #pragma unroll
                 for (int t = 0; t < 8; ++t)
-                    if (t < R) v[c][t] = base[(i + t * nb) * estride];
+                    if (t < R) v[c][t] = base[lp(i + t * nb)];
 #pragma unroll
                 for (int t = 1; t < 8; ++t) {
                     if (t < R) {
@@ -140,15 +146,13 @@ __device__ void lds_fft(cplx<T>* buf, int nlines, int lstride, int estride, cons
         for (int c = 0; c < MAXB; ++c) {
             const int b = threadIdx.x + c * blockDim.x;
             if (b < total) {
-                int line, i;
-                if (line_fast) { line = b % nlines; i = b / nlines; }
-                else { line = b / nb; i = b - line * nb; }
+                const int line = b / nb, i = b - line * nb;
                 cplx<T>* base = buf + line * lstride;
                 const int k = i % p;
                 const int j = (i - k) * R + k;
 #pragma unroll
                 for (int t = 0; t < 8; ++t)
-                    if (t < R) base[(j + t * p) * estride] = v[c][t];
+                    if (t < R) base[lp(j + t * p)] = v[c][t];
             }
         }
         __syncthreads();

@@ -7,13 +7,16 @@
 //              it -- and two real rows are packed into one complex line
 //              (row 2i in the real part, row 2i+1 in the imaginary part),
 //              transformed, and split into their half spectra.
-//  axis pass : per block, TX consecutive kx columns of all s components
-//              along y (or z).  Forward, projection P(n) applied per
-//              frequency, inverse, in one visit when it is the last axis.
+//  axis pass : per block, whole lines of all s components along y (stored
+//              contiguously) or a tile of y columns along z (strided by
+//              n_y, read in 128-byte rows).  Forward, projection P(n) applied
+//              per frequency, inverse, in one visit on the last axis.
 //  x-inverse : the reverse of the x-forward pass; the epilogue stores the
 //              result or applies the conjugate-gradient update in place.
 //
-// Spectrum layout: [c][z][y][kx], kx in [0, n_x/2], pitch n_x/2 + 1.
+// Spectrum layout (per RVE): [c][kx][z][y], kx in [0, n_x/2]: the x passes
+// transpose through LDS so that the y lines are contiguous.  A batch of B
+// RVEs of the same grid shares every launch (RVE index = last grid index).
 #include "kernels.h"
 #include "fft_device.h"
 #include "reduce.h"
@@ -125,18 +128,30 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const Geom& g = a.g;
-    if (MODE == XF_CG && a.cg->done) return;
-    const int nx = g.nx;
-    const int nrows = g.ny * g.nz;
+    const int b = blockIdx.y;
+    if (MODE == XF_CG) {
+        if (a.cg[b].done) return;
+    } else if (a.active && !a.active[b]) {
+        return;
+    }
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int nrows = ny * nz;
     const int RB = a.rows_per_block;
     const int npairs = RB / 2;
     const int r0 = blockIdx.x * RB;
+    const int LS = lds_line(nx);
+    const long long N = g.N;
+    const long long so = (long long)b * N;
+    const long long fo = so * S;
+    const MatEntry<T>* mat = a.mat + (long long)b * g.mstride;
+    const uint16_t* mid = a.mat_id + so;
+    const T* phi = a.phi + so;
 
     T beta = T(0);
     bool first = false;
     if (MODE == XF_CG) {
-        beta = T(a.cg->beta);
-        first = a.cg->first != 0;
+        beta = T(a.cg[b].beta);
+        first = a.cg[b].first != 0;
     }
     double part = 0.0;
     for (int v = threadIdx.x; v < RB * nx; v += blockDim.x) {
@@ -145,21 +160,22 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
         T sig[S];
         if (row < nrows) {
             const long long idx = (long long)row * nx + x;
-            const MatEntry<T>& m = a.mat[a.mat_id[idx]];
-            const T gg = degr(a.phi[idx], T(g.k_res));
+            const MatEntry<T>& m = mat[mid[idx]];
+            const T gg = degr(phi[idx], T(g.k_res));
             T e[S];
             if (MODE == XF_CG) {
 #pragma unroll
                 for (int c = 0; c < S; ++c) {
-                    const T rv = a.r[c * g.N + idx];
-                    const T pv = first ? rv : rv + beta * a.p[c * g.N + idx];
-                    a.p[c * g.N + idx] = pv;
+                    const long long o = fo + c * N + idx;
+                    const T rv = a.r[o];
+                    const T pv = first ? rv : rv + beta * a.p[o];
+                    a.p[o] = pv;
                     e[c] = pv;
                 }
             } else {
 #pragma unroll
                 for (int c = 0; c < S; ++c)
-                    e[c] = (a.eps ? a.eps[c * g.N + idx] : T(0)) + a.fcoef * a.f[c];
+                    e[c] = (a.eps ? a.eps[fo + c * N + idx] : T(0)) + a.fcoef * a.f[c];
             }
             T o[S];
             mat_apply<T, S>(m, e, o);
@@ -174,36 +190,41 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
         }
 #pragma unroll
         for (int c = 0; c < S; ++c) {
-            cplx<T>& dst = buf[(c * npairs + (rl >> 1)) * nx + x];
+            cplx<T>& dst = buf[(c * npairs + (rl >> 1)) * LS + lp(x)];
             if (rl & 1) dst.y = sig[c];
             else dst.x = sig[c];
         }
     }
     __syncthreads();
-    lds_fft<T, MAXB>(buf, S * npairs, nx, 1, a.pl, a.tw, false);
+    lds_fft<T, MAXB>(buf, S * npairs, LS, a.pl, a.tw, false);
 
+    // split the packed lines into the half spectra of their two rows and
+    // store them transposed: consecutive threads write consecutive y
     const int nxh = g.nxh;
+    cplx<T>* sp = a.spec + (long long)b * S * g.Nspec;
     for (int e = threadIdx.x; e < S * npairs * nxh; e += blockDim.x) {
-        const int line = e / nxh, k = e - line * nxh;
-        const int c = line / npairs, pair = line - c * npairs;
-        const cplx<T> z = buf[line * nx + k];
-        const cplx<T> zm = buf[line * nx + (k == 0 ? 0 : nx - k)];
+        const int pr = e % npairs;
+        const int k = (e / npairs) % nxh;
+        const int c = e / (npairs * nxh);
+        const int line = c * npairs + pr;
+        const cplx<T> z = buf[line * LS + lp(k)];
+        const cplx<T> zm = buf[line * LS + lp(k == 0 ? 0 : nx - k)];
         // A = (Z_k + conj Z_{-k}) / 2 ;  B = (Z_k - conj Z_{-k}) / (2i)
         const cplx<T> A = {T(0.5) * (z.x + zm.x), T(0.5) * (z.y - zm.y)};
-        const cplx<T> B = {T(0.5) * (z.y + zm.y), T(-0.5) * (z.x - zm.x)};
-        const int rowA = r0 + 2 * pair;
-        cplx<T>* sp = a.spec + (long long)c * g.Nspec;
-        if (rowA < nrows) sp[(long long)rowA * nxh + k] = A;
-        if (rowA + 1 < nrows) sp[(long long)(rowA + 1) * nxh + k] = B;
+        const cplx<T> Bv = {T(0.5) * (z.y + zm.y), T(-0.5) * (z.x - zm.x)};
+        const int rowA = r0 + 2 * pr;
+        cplx<T>* spc = sp + (long long)c * g.Nspec + (long long)k * nz * ny;
+        if (rowA < nrows) spc[rowA] = A;            // rowA = z * ny + y
+        if (rowA + 1 < nrows) spc[rowA + 1] = Bv;
     }
     if (MODE == XF_CG) {
         double pv[1] = {part};
-        block_sum_store<1>(pv, a.partials, 0, blockIdx.x);
+        block_sum_store<1>(pv, a.partials + (long long)b * a.nblocks, 0, blockIdx.x);
     }
 }
 
 // ---------------------------------------------------------------------------
-// axis pass (y or z): forward, [projection], inverse
+// axis pass: forward, [projection], inverse along y (contiguous lines) or z
 // ---------------------------------------------------------------------------
 
 template <typename T, int S, int MODE, int MAXB>
@@ -211,51 +232,90 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const Geom& g = a.g;
-    if (a.cg && a.cg->done) return;
-    const int TX = a.tx;
-    const int kx0 = blockIdx.x * TX;
-    const int other = blockIdx.y;            // z for the y pass, y for the z pass
+    const int b = blockIdx.z;
+    if (a.cg && a.cg[b].done) return;
+    if (a.active && !a.active[b]) return;
+    const int TL = a.lines;
     const int Na = a.pl.N;
-    const long long astride = a.axis == 1 ? g.nxh : (long long)g.ny * g.nxh;
-    const long long base = a.axis == 1 ? (long long)other * g.ny * g.nxh : (long long)other * g.nxh;
-    const int W = S * TX;
-
-    for (int e = threadIdx.x; e < W * Na; e += blockDim.x) {
-        const int t = e % TX, c = (e / TX) % S, j = e / W;
-        const int kx = kx0 + t;
-        cplx<T> v = {T(0), T(0)};
-        if (kx < g.nxh) v = a.spec[(long long)c * g.Nspec + base + j * astride + kx];
-        buf[e] = v;
-    }
-    __syncthreads();
+    const int ny = g.ny, nz = g.nz;
+    cplx<T>* sp = a.spec + (long long)b * S * g.Nspec;
     const bool inv_only = MODE == AX_INV;
-    lds_fft<T, MAXB>(buf, W, 1, W, a.pl, a.tw, inv_only);
 
-    if (MODE == AX_FWD_P_INV) {
-        for (int e = threadIdx.x; e < TX * Na; e += blockDim.x) {
-            const int t = e % TX, j = e / TX;
-            const int kx = kx0 + t;
-            int ky, kz;
-            if (a.axis == 1) { ky = j; kz = other; }
-            else { ky = other; kz = j; }
-            T n1, n2, n3;
-            freq_dir<T>(g, kx, ky, kz, n1, n2, n3);
-            cplx<T> v[S];
-#pragma unroll
-            for (int c = 0; c < S; ++c) v[c] = buf[j * W + c * TX + t];
-            if constexpr (S == 3) project2<T>(v, n1, n2);
-            else project3<T>(v, n1, n2, n3);
-#pragma unroll
-            for (int c = 0; c < S; ++c) buf[j * W + c * TX + t] = v[c];
+    const int LS = lds_line(Na);
+    if (a.contiguous) {
+        // lines L = kx * nz + z, element y; LDS line (c, tl)
+        const long long nlines = (long long)g.nxh * nz;
+        const long long L0 = (long long)blockIdx.x * TL;
+        for (int e = threadIdx.x; e < S * TL * Na; e += blockDim.x) {
+            const int j = e % Na, tl = (e / Na) % TL, c = e / (Na * TL);
+            const long long L = L0 + tl;
+            cplx<T> v = {T(0), T(0)};
+            if (L < nlines) v = sp[(long long)c * g.Nspec + L * ny + j];
+            buf[(c * TL + tl) * LS + lp(j)] = v;
         }
         __syncthreads();
-        lds_fft<T, MAXB>(buf, W, 1, W, a.pl, a.tw, true);
-    }
-
-    for (int e = threadIdx.x; e < W * Na; e += blockDim.x) {
-        const int t = e % TX, c = (e / TX) % S, j = e / W;
-        const int kx = kx0 + t;
-        if (kx < g.nxh) a.spec[(long long)c * g.Nspec + base + j * astride + kx] = buf[e];
+        lds_fft<T, MAXB>(buf, S * TL, LS, a.pl, a.tw, inv_only);
+        if (MODE == AX_FWD_P_INV) {
+            for (int e = threadIdx.x; e < TL * Na; e += blockDim.x) {
+                const int j = e % Na, tl = e / Na;
+                const long long L = L0 + tl;
+                if (L >= nlines) continue;
+                const int kx = (int)(L / nz), kz = (int)(L % nz);
+                T n1, n2, n3;
+                freq_dir<T>(g, kx, j, kz, n1, n2, n3);
+                cplx<T> v[S];
+#pragma unroll
+                for (int c = 0; c < S; ++c) v[c] = buf[(c * TL + tl) * LS + lp(j)];
+                if constexpr (S == 3) project2<T>(v, n1, n2);
+                else project3<T>(v, n1, n2, n3);
+#pragma unroll
+                for (int c = 0; c < S; ++c) buf[(c * TL + tl) * LS + lp(j)] = v[c];
+            }
+            __syncthreads();
+            lds_fft<T, MAXB>(buf, S * TL, LS, a.pl, a.tw, true);
+        }
+        for (int e = threadIdx.x; e < S * TL * Na; e += blockDim.x) {
+            const int j = e % Na, tl = (e / Na) % TL, c = e / (Na * TL);
+            const long long L = L0 + tl;
+            if (L < nlines) sp[(long long)c * g.Nspec + L * ny + j] = buf[(c * TL + tl) * LS + lp(j)];
+        }
+    } else {
+        // z lines at fixed (kx, y), y in a tile of TL columns; LDS line (c, tl)
+        const int nyt = (ny + TL - 1) / TL;
+        const int kx = blockIdx.x / nyt;
+        const int y0 = (blockIdx.x % nyt) * TL;
+        const int W = S * TL;
+        const long long base = (long long)kx * nz * ny + y0;
+        for (int e = threadIdx.x; e < W * Na; e += blockDim.x) {
+            const int tl = e % TL, c = (e / TL) % S, j = e / W;
+            cplx<T> v = {T(0), T(0)};
+            if (y0 + tl < ny) v = sp[(long long)c * g.Nspec + base + (long long)j * ny + tl];
+            buf[(c * TL + tl) * LS + lp(j)] = v;
+        }
+        __syncthreads();
+        lds_fft<T, MAXB>(buf, W, LS, a.pl, a.tw, inv_only);
+        if (MODE == AX_FWD_P_INV) {
+            for (int e = threadIdx.x; e < TL * Na; e += blockDim.x) {
+                const int tl = e % TL, j = e / TL;
+                if (y0 + tl >= ny) continue;
+                T n1, n2, n3;
+                freq_dir<T>(g, kx, y0 + tl, j, n1, n2, n3);
+                cplx<T> v[S];
+#pragma unroll
+                for (int c = 0; c < S; ++c) v[c] = buf[(c * TL + tl) * LS + lp(j)];
+                if constexpr (S == 3) project2<T>(v, n1, n2);
+                else project3<T>(v, n1, n2, n3);
+#pragma unroll
+                for (int c = 0; c < S; ++c) buf[(c * TL + tl) * LS + lp(j)] = v[c];
+            }
+            __syncthreads();
+            lds_fft<T, MAXB>(buf, W, LS, a.pl, a.tw, true);
+        }
+        for (int e = threadIdx.x; e < W * Na; e += blockDim.x) {
+            const int tl = e % TL, c = (e / TL) % S, j = e / W;
+            if (y0 + tl < ny)
+                sp[(long long)c * g.Nspec + base + (long long)j * ny + tl] = buf[(c * TL + tl) * LS + lp(j)];
+        }
     }
 }
 
@@ -268,32 +328,39 @@ __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const Geom& g = a.g;
-    if (a.cg && a.cg->done) return;
-    const int nx = g.nx, nxh = g.nxh;
-    const int nrows = g.ny * g.nz;
+    const int b = blockIdx.y;
+    if (a.cg && a.cg[b].done) return;
+    if (a.active && !a.active[b]) return;
+    const int nx = g.nx, nxh = g.nxh, ny = g.ny, nz = g.nz;
+    const int nrows = ny * nz;
     const int RB = a.rows_per_block;
     const int npairs = RB / 2;
     const int r0 = blockIdx.x * RB;
+    const int LS = lds_line(nx);
+    const cplx<T>* sp = a.spec + (long long)b * S * g.Nspec;
 
+    // gather Z = A + iB from the transposed half spectra of the row pair
     for (int e = threadIdx.x; e < S * npairs * nx; e += blockDim.x) {
-        const int line = e / nx, k = e - line * nx;
-        const int c = line / npairs, pair = line - c * npairs;
-        const int rowA = r0 + 2 * pair;
-        const cplx<T>* sp = a.spec + (long long)c * g.Nspec;
+        const int pr = e % npairs;
+        const int k = (e / npairs) % nx;
+        const int c = e / (npairs * nx);
+        const int rowA = r0 + 2 * pr;
         const bool lo = k < nxh;
         const int kk = lo ? k : nx - k;
+        const cplx<T>* spc = sp + (long long)c * g.Nspec + (long long)kk * nz * ny;
         cplx<T> A = {T(0), T(0)}, B = {T(0), T(0)};
-        if (rowA < nrows) A = sp[(long long)rowA * nxh + kk];
-        if (rowA + 1 < nrows) B = sp[(long long)(rowA + 1) * nxh + kk];
+        if (rowA < nrows) A = spc[rowA];
+        if (rowA + 1 < nrows) B = spc[rowA + 1];
         if (!lo) { A.y = -A.y; B.y = -B.y; }
-        buf[e] = {A.x - B.y, A.y + B.x};     // Z = A + i B
+        buf[(c * npairs + pr) * LS + lp(k)] = {A.x - B.y, A.y + B.x};
     }
     __syncthreads();
-    lds_fft<T, MAXB>(buf, S * npairs, nx, 1, a.pl, a.tw, true);
+    lds_fft<T, MAXB>(buf, S * npairs, LS, a.pl, a.tw, true);
 
     const T scale = T(g.inv_N) * a.scale;
     T alpha = T(0);
-    if (MODE == XI_CG) alpha = T(a.cg->alpha);
+    if (MODE == XI_CG) alpha = T(a.cg[b].alpha);
+    const long long fo = (long long)b * S * g.N;
     double part = 0.0;
     for (int v = threadIdx.x; v < RB * nx; v += blockDim.x) {
         const int rl = v / nx, x = v - rl * nx;
@@ -302,13 +369,13 @@ __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
         const long long idx = (long long)row * nx + x;
 #pragma unroll
         for (int c = 0; c < S; ++c) {
-            const cplx<T> z = buf[(c * npairs + (rl >> 1)) * nx + x];
+            const cplx<T> z = buf[(c * npairs + (rl >> 1)) * LS + lp(x)];
             const T q = ((rl & 1) ? z.y : z.x) * scale;
+            const long long o = fo + c * g.N + idx;
             if (MODE == XI_STORE) {
-                if (a.out) a.out[c * g.N + idx] = q;
+                if (a.out) a.out[o] = q;
                 part += double(q) * double(q);
             } else {  // XI_CG
-                const long long o = c * g.N + idx;
                 a.x[o] += alpha * a.p[o];
                 const T rn = a.r[o] - alpha * q;
                 a.r[o] = rn;
@@ -317,45 +384,48 @@ __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
         }
     }
     double pv[1] = {part};
-    block_sum_store<1>(pv, a.partials, 0, blockIdx.x);
+    block_sum_store<1>(pv, a.partials + (long long)b * a.nblocks, 0, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
 // host-side launchers
 // ---------------------------------------------------------------------------
 
-template <typename T, int S, int MODE>
-static hipError_t launch_xfwd_s(const XfwdArgs<T>& a, int maxb, int nblocks, size_t lds,
-                                hipStream_t st) {
-    switch (maxb) {
-        case 1: hipLaunchKernelGGL((k_xfwd<T, S, MODE, 1>), dim3(nblocks), dim3(256), lds, st, a); break;
-        case 2: hipLaunchKernelGGL((k_xfwd<T, S, MODE, 2>), dim3(nblocks), dim3(256), lds, st, a); break;
-        case 4: hipLaunchKernelGGL((k_xfwd<T, S, MODE, 4>), dim3(nblocks), dim3(256), lds, st, a); break;
-        default: hipLaunchKernelGGL((k_xfwd<T, S, MODE, 8>), dim3(nblocks), dim3(256), lds, st, a); break;
-    }
+template <typename K, typename A>
+static hipError_t launch_k(K kern, dim3 grid, size_t lds, hipStream_t st, const A& a) {
+    hipLaunchKernelGGL(kern, grid, dim3(256), lds, st, a);
     return hipGetLastError();
 }
 
+template <typename T, int S, int MODE>
+static hipError_t launch_xfwd_s(const XfwdArgs<T>& a, int maxb, size_t lds, hipStream_t st) {
+    const dim3 grid(a.nblocks, a.g.B);
+    switch (maxb) {
+        case 1: return launch_k(k_xfwd<T, S, MODE, 1>, grid, lds, st, a);
+        case 2: return launch_k(k_xfwd<T, S, MODE, 2>, grid, lds, st, a);
+        case 4: return launch_k(k_xfwd<T, S, MODE, 4>, grid, lds, st, a);
+        default: return launch_k(k_xfwd<T, S, MODE, 8>, grid, lds, st, a);
+    }
+}
+
 template <typename T>
-hipError_t launch_xfwd(const XfwdArgs<T>& a, int mode, int maxb, int nblocks, size_t lds,
-                       hipStream_t st) {
+hipError_t launch_xfwd(const XfwdArgs<T>& a, int mode, int maxb, size_t lds, hipStream_t st) {
     if (a.g.s == 3)
-        return mode == XF_CG ? launch_xfwd_s<T, 3, XF_CG>(a, maxb, nblocks, lds, st)
-                             : launch_xfwd_s<T, 3, XF_GREEN>(a, maxb, nblocks, lds, st);
-    return mode == XF_CG ? launch_xfwd_s<T, 6, XF_CG>(a, maxb, nblocks, lds, st)
-                         : launch_xfwd_s<T, 6, XF_GREEN>(a, maxb, nblocks, lds, st);
+        return mode == XF_CG ? launch_xfwd_s<T, 3, XF_CG>(a, maxb, lds, st)
+                             : launch_xfwd_s<T, 3, XF_GREEN>(a, maxb, lds, st);
+    return mode == XF_CG ? launch_xfwd_s<T, 6, XF_CG>(a, maxb, lds, st)
+                         : launch_xfwd_s<T, 6, XF_GREEN>(a, maxb, lds, st);
 }
 
 template <typename T, int S, int MODE>
 static hipError_t launch_axis_s(const AxisArgs<T>& a, int maxb, dim3 grid, size_t lds,
                                 hipStream_t st) {
     switch (maxb) {
-        case 1: hipLaunchKernelGGL((k_axis<T, S, MODE, 1>), grid, dim3(256), lds, st, a); break;
-        case 2: hipLaunchKernelGGL((k_axis<T, S, MODE, 2>), grid, dim3(256), lds, st, a); break;
-        case 4: hipLaunchKernelGGL((k_axis<T, S, MODE, 4>), grid, dim3(256), lds, st, a); break;
-        default: hipLaunchKernelGGL((k_axis<T, S, MODE, 8>), grid, dim3(256), lds, st, a); break;
+        case 1: return launch_k(k_axis<T, S, MODE, 1>, grid, lds, st, a);
+        case 2: return launch_k(k_axis<T, S, MODE, 2>, grid, lds, st, a);
+        case 4: return launch_k(k_axis<T, S, MODE, 4>, grid, lds, st, a);
+        default: return launch_k(k_axis<T, S, MODE, 8>, grid, lds, st, a);
     }
-    return hipGetLastError();
 }
 
 template <typename T>
@@ -376,32 +446,30 @@ hipError_t launch_axis(const AxisArgs<T>& a, int mode, int maxb, dim3 grid, size
 }
 
 template <typename T, int S, int MODE>
-static hipError_t launch_xinv_s(const XinvArgs<T>& a, int maxb, int nblocks, size_t lds,
-                                hipStream_t st) {
+static hipError_t launch_xinv_s(const XinvArgs<T>& a, int maxb, size_t lds, hipStream_t st) {
+    const dim3 grid(a.nblocks, a.g.B);
     switch (maxb) {
-        case 1: hipLaunchKernelGGL((k_xinv<T, S, MODE, 1>), dim3(nblocks), dim3(256), lds, st, a); break;
-        case 2: hipLaunchKernelGGL((k_xinv<T, S, MODE, 2>), dim3(nblocks), dim3(256), lds, st, a); break;
-        case 4: hipLaunchKernelGGL((k_xinv<T, S, MODE, 4>), dim3(nblocks), dim3(256), lds, st, a); break;
-        default: hipLaunchKernelGGL((k_xinv<T, S, MODE, 8>), dim3(nblocks), dim3(256), lds, st, a); break;
+        case 1: return launch_k(k_xinv<T, S, MODE, 1>, grid, lds, st, a);
+        case 2: return launch_k(k_xinv<T, S, MODE, 2>, grid, lds, st, a);
+        case 4: return launch_k(k_xinv<T, S, MODE, 4>, grid, lds, st, a);
+        default: return launch_k(k_xinv<T, S, MODE, 8>, grid, lds, st, a);
     }
-    return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_xinv(const XinvArgs<T>& a, int mode, int maxb, int nblocks, size_t lds,
-                       hipStream_t st) {
+hipError_t launch_xinv(const XinvArgs<T>& a, int mode, int maxb, size_t lds, hipStream_t st) {
     if (a.g.s == 3)
-        return mode == XI_CG ? launch_xinv_s<T, 3, XI_CG>(a, maxb, nblocks, lds, st)
-                             : launch_xinv_s<T, 3, XI_STORE>(a, maxb, nblocks, lds, st);
-    return mode == XI_CG ? launch_xinv_s<T, 6, XI_CG>(a, maxb, nblocks, lds, st)
-                         : launch_xinv_s<T, 6, XI_STORE>(a, maxb, nblocks, lds, st);
+        return mode == XI_CG ? launch_xinv_s<T, 3, XI_CG>(a, maxb, lds, st)
+                             : launch_xinv_s<T, 3, XI_STORE>(a, maxb, lds, st);
+    return mode == XI_CG ? launch_xinv_s<T, 6, XI_CG>(a, maxb, lds, st)
+                         : launch_xinv_s<T, 6, XI_STORE>(a, maxb, lds, st);
 }
 
-template hipError_t launch_xfwd<double>(const XfwdArgs<double>&, int, int, int, size_t, hipStream_t);
-template hipError_t launch_xfwd<float>(const XfwdArgs<float>&, int, int, int, size_t, hipStream_t);
+template hipError_t launch_xfwd<double>(const XfwdArgs<double>&, int, int, size_t, hipStream_t);
+template hipError_t launch_xfwd<float>(const XfwdArgs<float>&, int, int, size_t, hipStream_t);
 template hipError_t launch_axis<double>(const AxisArgs<double>&, int, int, dim3, size_t, hipStream_t);
 template hipError_t launch_axis<float>(const AxisArgs<float>&, int, int, dim3, size_t, hipStream_t);
-template hipError_t launch_xinv<double>(const XinvArgs<double>&, int, int, int, size_t, hipStream_t);
-template hipError_t launch_xinv<float>(const XinvArgs<float>&, int, int, int, size_t, hipStream_t);
+template hipError_t launch_xinv<double>(const XinvArgs<double>&, int, int, size_t, hipStream_t);
+template hipError_t launch_xinv<float>(const XinvArgs<float>&, int, int, size_t, hipStream_t);
 
 }  // namespace mirve

@@ -1,11 +1,20 @@
 // Kernel argument blocks and launchers.
+//
+// Every kernel works on a batch of B RVEs of the same grid.  Fields of RVE b
+// start at b * (field size); the launch grid carries the RVE index in its
+// last dimension.  Per-RVE scalars (Krylov state, loads, mixing weights)
+// live in device arrays indexed by b.  An optional mask active[b] lets a
+// launch skip RVEs that have finished a phase.
 #pragma once
 #include "common.h"
 
 namespace mirve {
 
-// Device-resident scalars of one conjugate-gradient solve.  The finalize
-// kernels update them so that an iteration needs no host round trip.
+constexpr int kMaxVals = 32;       // reduction values per RVE (partials / sums slots)
+constexpr int kAndersonMax = 5;    // Anderson depth limit
+constexpr int kHist = kAndersonMax + 1;
+
+// Device-resident scalars of one conjugate-gradient solve (one per RVE).
 struct CgDev {
     double rr;       // r . r of the current residual
     double pAp;      // p . A p
@@ -13,11 +22,17 @@ struct CgDev {
     double bn2;      // ||b||^2 (stopping reference)
     double tol2;     // tol^2
     int it;          // iterations done
-    int done;        // 1 once converged, failed or out of iterations
+    int done;        // 1 once converged, failed or out of iterations (or inactive)
     int first;       // next direction update is p = r
-    int status;      // 0 ok, 1 converged, 2 breakdown / non-finite, 3 max iterations
+    int status;      // 0 running, 1 converged, 2 breakdown / non-finite, 3 max iterations
     int max_it;
     int pad;
+};
+
+// Jacobi-preconditioned CG of the damage system (one per RVE).
+struct PcgDev {
+    double rz, pq, alpha, beta, rr, bn2, tol2;
+    int it, done, status, max_it;
 };
 
 enum { XF_GREEN = 0, XF_CG = 1 };
@@ -32,15 +47,17 @@ struct XfwdArgs {
     const uint16_t* mat_id;
     const MatEntry<T>* mat;
     const T* phi;
-    const T* eps;        // XF_GREEN: strain field (s*N) or null
+    const T* eps;        // XF_GREEN: strain field (s*N per RVE) or null
     T fcoef;             // XF_GREEN: + fcoef * f
     T f[6];
     const T* r;          // XF_CG
     T* p;                // XF_CG (updated in place)
-    const CgDev* cg;     // XF_CG
+    const CgDev* cg;     // XF_CG: per-RVE state; XF_GREEN: null
+    const int* active;   // XF_GREEN: optional per-RVE mask
     cplx<T>* spec;
-    double* partials;
+    double* partials;    // [B][nblocks]
     int rows_per_block;
+    int nblocks;
 };
 
 template <typename T>
@@ -49,9 +66,10 @@ struct AxisArgs {
     AxisPlan pl;
     const cplx<T>* tw;
     cplx<T>* spec;
-    const CgDev* cg;     // skip when cg && cg->done
-    int axis;            // 1 = y, 2 = z
-    int tx;              // kx columns per block
+    const CgDev* cg;     // skip RVE b when cg && cg[b].done
+    const int* active;   // or when active && !active[b]
+    int contiguous;      // 1: y lines (stride 1); 0: z lines (stride n_y)
+    int lines;           // lines per block (y pass) / y columns per block (z pass)
 };
 
 template <typename T>
@@ -66,154 +84,158 @@ struct XinvArgs {
     const T* p;          // XI_CG
     T* r;                // XI_CG
     const CgDev* cg;
-    double* partials;
+    const int* active;
+    double* partials;    // [B][nblocks]
     int rows_per_block;
+    int nblocks;
 };
 
 template <typename T>
-hipError_t launch_xfwd(const XfwdArgs<T>& a, int mode, int maxb, int nblocks, size_t lds,
-                       hipStream_t st);
+hipError_t launch_xfwd(const XfwdArgs<T>& a, int mode, int maxb, size_t lds, hipStream_t st);
 template <typename T>
 hipError_t launch_axis(const AxisArgs<T>& a, int mode, int maxb, dim3 grid, size_t lds,
                        hipStream_t st);
 template <typename T>
-hipError_t launch_xinv(const XinvArgs<T>& a, int mode, int maxb, int nblocks, size_t lds,
-                       hipStream_t st);
+hipError_t launch_xinv(const XinvArgs<T>& a, int mode, int maxb, size_t lds, hipStream_t st);
 
 // ---------------------------------------------------------------------------
-// pointwise / stencil kernels (pointwise.hip)
+// finalize kernels (one block per RVE, fixed-order sums)
 // ---------------------------------------------------------------------------
 
-// Finalize kernels for the mechanics CG.
-hipError_t launch_cg_init(CgDev* cg, const double* partials_rr, int nrr, const double* partials_b,
-                          int nb, double tol, int max_it, hipStream_t st);
-hipError_t launch_cg_alpha(CgDev* cg, const double* partials, int n, hipStream_t st);
-hipError_t launch_cg_beta(CgDev* cg, const double* partials, int n, hipStream_t st);
+// CG partials are [B][n] (one per block of the pass that made them).
+hipError_t launch_cg_init(CgDev* cg, const double* prr, const double* pb, int n, int B,
+                          double tol, int max_it, const int* active, hipStream_t st);
+hipError_t launch_cg_alpha(CgDev* cg, const double* partials, int n, int B, hipStream_t st);
+hipError_t launch_cg_beta(CgDev* cg, const double* partials, int n, int B, hipStream_t st);
+// sums[b*kMaxVals + v] = sum_k partials[(b*kMaxVals + v)*kRedBlocks + k], v < nv
+hipError_t launch_sum_partials(const double* partials, int n, int nv, int B, double* sums,
+                               const int* active, hipStream_t st);
+// sums[b*kMaxVals + slot] = sum_k p[b*n + k]  (pass partials)
+hipError_t launch_sum_rows(const double* p, int n, int B, double* sums, int slot, hipStream_t st);
+// sums[b*kMaxVals] = max_k partials[(b*kMaxVals)*kRedBlocks + k]
+hipError_t launch_max_partials(const double* partials, int n, int B, double* sums,
+                               const int* active, hipStream_t st);
 
-// Sum (fixed order) nv groups of n partials: out[v] = sum_b partials[v*stride + b].
-hipError_t launch_sum_partials(const double* partials, int stride, int n, int nv, double* out,
-                               hipStream_t st);
-hipError_t launch_max_partials(const double* partials, int n, double* out, hipStream_t st);
+// Damage PCG partials use the kMaxVals layout above.
+hipError_t launch_pcg_fin_start(PcgDev* d, const double* partials, int n, int B, double tol,
+                                int max_it, const int* active, hipStream_t st);
+hipError_t launch_pcg_fin_alpha(PcgDev* d, const double* partials, int n, int B, hipStream_t st);
+hipError_t launch_pcg_fin_beta(PcgDev* d, const double* partials, int n, int B, hipStream_t st);
 
-// Unit response: eps1 = f + x, sigma1 = g C eps1, psi1 (0 on notch voxels),
-// partial sums of sigma1:f (slot 0) and sigma1:sigma1 (slot 1, stride
-// kRedBlocks).  Also writes eps1/sig1 if non-null.
+// ---------------------------------------------------------------------------
+// pointwise / stencil kernels; `nred` blocks per RVE for reductions
+// ---------------------------------------------------------------------------
+
+struct F6 {
+    double v[6];
+};
+
+// eps1 = f + x, sigma1 = g C eps1, psi1 (0 on notch voxels); partial sums of
+// sigma1:f (value 0) and sigma1:sigma1 (value 1); eps1 / sig1 written if non-null.
 template <typename T>
 hipError_t launch_unit_response(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                                const T* phi, const T* x, const double* f, int split, T* psi1,
-                                T* eps1, T* sig1, double* partials, int nblocks, hipStream_t st);
+                                const T* phi, const T* x, const F6& f, T* psi1, T* eps1, T* sig1,
+                                double* partials, int nred, const int* active, hipStream_t st);
 
-// History at load E: H = max(E^2 psi1 + psi_ini, Hn) (or without max),
-// optionally its E-derivative mask.
+// H = max(E_b^2 psi1 + psi_ini, Hn) (history) or E_b^2 psi1 + psi_ini; rhs = 2H.
 template <typename T>
-hipError_t launch_history(const Geom& g, const T* psi1, const T* psi_ini, const T* Hn, double E,
-                          int history, T* H, hipStream_t st);
+hipError_t launch_history(const Geom& g, const T* psi1, const T* psi_ini, const T* Hn,
+                          const double* E, int history, T* H, T* rhs, const int* active,
+                          hipStream_t st);
 
-// Damage operator q = a(x) p + D^T (w(x) D p) with a = Gc/l + 2H, w = Gc l
-// (coefficient mode 0; H may be null) or a = 1, w = c (mode 1, the
-// enrichment smoothing).  See launch_pcg_matvec.
-
-// Jacobi diagonal of the damage operator.
+// Damage operator q = a(x) p + D^T (w(x) D p): mode 0 a = Gc/l + 2H (H may be
+// null), w = Gc l; mode 1 a = 1, w = c (the enrichment smoothing).
 template <typename T>
 hipError_t launch_damage_diag(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                              const T* H, int mode, double c, T* dinv, hipStream_t st);
-
-// Jacobi-preconditioned CG of the damage system; scalars live on the device.
-struct PcgDev {
-    double rz, pq, alpha, beta, rr, bn2, tol2;
-    int it, done, status, max_it;
-};
-// r = b - Ax, p = z = dinv r; partials: r.z, r.r, b.b
-template <typename T>
-hipError_t launch_pcg_start(const Geom& g, const T* b, const T* Ax, const T* dinv, T* r, T* p,
-                            double* partials, int nblocks, hipStream_t st);
-hipError_t launch_pcg_fin_start(PcgDev* d, const double* partials, int n, double tol, int max_it,
-                                hipStream_t st);
-// q = A p with p.q partials, skipped once done
+                              const T* H, int mode, double c, T* dinv, const int* active,
+                              hipStream_t st);
 template <typename T>
 hipError_t launch_pcg_matvec(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
                              const T* H, int mode, double c, const T* p, T* q, double* partials,
-                             int nblocks, const PcgDev* d, hipStream_t st);
-hipError_t launch_pcg_fin_alpha(PcgDev* d, const double* partials, int n, hipStream_t st);
+                             int nred, const PcgDev* d, const int* active, hipStream_t st);
+// r = b - Ax, p = dinv r; partials r.z, r.r, b.b
+template <typename T>
+hipError_t launch_pcg_start(const Geom& g, const T* b, const T* Ax, const T* dinv, T* r, T* p,
+                            double* partials, int nred, const int* active, hipStream_t st);
 // x += alpha p; r -= alpha q; partials r.(dinv r), r.r
 template <typename T>
 hipError_t launch_pcg_update(const Geom& g, const PcgDev* d, T* x, T* r, const T* p, const T* q,
-                             const T* dinv, double* partials, int nblocks, hipStream_t st);
-hipError_t launch_pcg_fin_beta(PcgDev* d, const double* partials, int n, hipStream_t st);
+                             const T* dinv, double* partials, int nred, hipStream_t st);
 // p = dinv r + beta p
 template <typename T>
 hipError_t launch_pcg_dir(const Geom& g, const PcgDev* d, const T* r, const T* dinv, T* p,
                           hipStream_t st);
 
-// Dissipation D(phi) and Gamma(phi) partial sums (Eq. 3, 4).
+// D(phi) (value 0) and Gamma(phi) (value 1) partials without the h^d factor.
 template <typename T>
 hipError_t launch_dissipation(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                              const T* phi, double* partials, int nblocks, hipStream_t st);
-
-// Damage residual norm partials: ||(Gc/l + 2H) phi + L phi - 2H||^2 and ||2H||^2.
+                              const T* phi, double* partials, int nred, const int* active,
+                              hipStream_t st);
+// ||(Gc/l + 2H) phi + L phi - 2H||^2 (value 0) and ||2H||^2 (value 1)
 template <typename T>
 hipError_t launch_damage_residual(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                                  const T* H, const T* phi, double* partials, int nblocks,
-                                  hipStream_t st);
-
-// Field utilities.
-template <typename T>
-hipError_t launch_copy(const T* src, T* dst, long long n, hipStream_t st);
-template <typename T>
-hipError_t launch_fill(T* dst, T v, long long n, hipStream_t st);
-template <typename T>
-hipError_t launch_max_field(const T* a, long long n, double* partials, int nblocks, hipStream_t st);
-template <typename T>
-hipError_t launch_scale_field(T* a, const double* num, double c, long long n, hipStream_t st);
+                                  const T* H, const T* phi, double* partials, int nred,
+                                  const int* active, hipStream_t st);
 // psi_ini = max(0, gamma'(phi) / (2 (1 - phi))) (Eq. 37a)
 template <typename T>
 hipError_t launch_psi_ini(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                          const T* phi, T* psi_ini, hipStream_t st);
-// Anderson mixing of the stagger iterates (depth <= kAndersonMax).
-constexpr int kAndersonMax = 5;
-template <typename T>
-struct Ptrs {
-    const T* p[kAndersonMax + 1];
-};
-struct Coef {
-    double v[kAndersonMax];
-};
-// Gram data of residual history F_0..F_m (oldest first, m1 = m + 1 <= kAndersonMax + 1):
-// value a*kAndersonMax + b = dF_a . dF_b, value kAndersonMax^2 + a = dF_a . F_m,
-// dF_a = F_{a+1} - F_a.  Partials are strided by kRedBlocks.
-template <typename T>
-hipError_t launch_anderson_gram(const Geom& g, const Ptrs<T>& F, int m1, double* partials,
-                                int nblocks, hipStream_t st);
-// out = G_m - sum_a gamma_a (G_{a+1} - G_a)
-template <typename T>
-hipError_t launch_anderson_mix(const Geom& g, const Ptrs<T>& G, int m1, const Coef& c, T* out,
-                               hipStream_t st);
-// ||a - b||^2 and ||a||^2 partials
-template <typename T>
-hipError_t launch_diff_norms(const T* a, const T* b, long long n, double* partials, int nblocks,
-                             hipStream_t st);
-// number of lines along the load axis without a broken voxel
-template <typename T>
-hipError_t launch_fracture_count(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                                 const T* phi, double thr, int axis, int* count, hipStream_t st);
-// 2 (1 - phi) dH/dE (right-hand side of the E-tangent of the damage balance)
+                          const T* phi, T* psi_ini, const int* active, hipStream_t st);
+// 2 (1 - phi) dH/dE with dH/dE = 2 E psi1 where E^2 psi1 + psi_ini > Hn (or everywhere)
 template <typename T>
 hipError_t launch_tangent_rhs(const Geom& g, const T* phi, const T* psi1, const T* psi_ini,
-                              const T* Hn, double E, int history, T* out, hipStream_t st);
-// partials of sum Gc (phi dphi / l + l grad phi . grad dphi)
+                              const T* Hn, const double* E, int history, T* out,
+                              const int* active, hipStream_t st);
+// sum Gc (phi dphi / l + l grad phi . grad dphi) partials (value 0)
 template <typename T>
 hipError_t launch_dissipation_dir(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                                  const T* phi, const T* dphi, double* partials, int nblocks,
-                                  hipStream_t st);
-// out = a - b
+                                  const T* phi, const T* dphi, double* partials, int nred,
+                                  const int* active, hipStream_t st);
+
+// Field utilities over n elements per RVE (stride n).
 template <typename T>
-hipError_t launch_sub(const T* a, const T* b, T* out, long long n, hipStream_t st);
-// b = c a
+hipError_t launch_copy(const T* src, T* dst, long long n, int B, const int* active, hipStream_t st);
 template <typename T>
-hipError_t launch_scaled(const T* a, double c, T* b, long long n, hipStream_t st);
-// Commit history: Hn = max(E^2 psi1 + psi_ini, Hn)  (or no max)
+hipError_t launch_fill(T* dst, T v, long long n, int B, const int* active, hipStream_t st);
 template <typename T>
-hipError_t launch_commit_history(const Geom& g, const T* psi1, const T* psi_ini, double E,
-                                 int history, T* Hn, hipStream_t st);
+hipError_t launch_sub(const T* a, const T* b, T* out, long long n, int B, const int* active,
+                      hipStream_t st);
+// max over the field (value 0) per RVE
+template <typename T>
+hipError_t launch_max_field(const T* a, long long n, int B, double* partials, int nred,
+                            const int* active, hipStream_t st);
+// a *= c / den[b * kMaxVals]
+template <typename T>
+hipError_t launch_scale_field(T* a, const double* den, double c, long long n, int B,
+                              const int* active, hipStream_t st);
+// ||a - b||^2 (value 0) and ||a||^2 (value 1)
+template <typename T>
+hipError_t launch_diff_norms(const T* a, const T* b, long long n, int B, double* partials,
+                             int nred, const int* active, hipStream_t st);
+
+// Anderson mixing.  History slot k of every RVE is a batched field at
+// base + k * slot_stride; order[b * kHist + i] (i < m1[b]) lists RVE b's
+// slots from oldest to newest.
+// Gram data: value a*kAndersonMax + c = dF_a . dF_c, value kAndersonMax^2 + a = dF_a . F_m.
+template <typename T>
+hipError_t launch_anderson_gram(const Geom& g, const T* Fbase, long long slot_stride,
+                                const int* order, const int* m1, double* partials, int nred,
+                                const int* active, hipStream_t st);
+// out = G_m - sum_a gamma[b*kAndersonMax + a] (G_{a+1} - G_a)
+template <typename T>
+hipError_t launch_anderson_mix(const Geom& g, const T* Gbase, long long slot_stride,
+                               const int* order, const int* m1, const double* gamma, T* out,
+                               const int* active, hipStream_t st);
+
+// number of lines along the load axis without a broken voxel, per RVE
+template <typename T>
+hipError_t launch_fracture_count(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
+                                 const T* phi, double thr, int axis, int* count,
+                                 const int* active, hipStream_t st);
+// Hn = max(E_b^2 psi1 + psi_ini, Hn) (or without max)
+template <typename T>
+hipError_t launch_commit_history(const Geom& g, const T* psi1, const T* psi_ini, const double* E,
+                                 int history, T* Hn, const int* active, hipStream_t st);
+// zero n integers (a kernel, so that captured graphs hold no memset node)
+hipError_t launch_zero_int(int* p, int n, hipStream_t st);
 
 }  // namespace mirve

@@ -7,6 +7,10 @@
 // operator L(phi) = -div(G_c l grad phi) (Eq. 10b, 17) is D^T diag(G_c l) D,
 // evaluated as a 2d+1 point stencil instead of the paper's FFT form (the two
 // are the same linear map).
+//
+// Batches: blockIdx.y is the RVE; reductions write per-block partial sums to
+// partials[(b * kMaxVals + v) * kRedBlocks + block] and a finalize kernel
+// (one block per RVE) adds them in a fixed order.
 #include <cfloat>
 #include "kernels.h"
 #include "reduce.h"
@@ -19,6 +23,12 @@ static inline int blocks_for(long long n) {
     long long b = (n + TPB - 1) / TPB;
     return (int)(b < 1 ? 1 : b);
 }
+
+__device__ inline double* pslot(double* partials, int b, int v) {
+    return partials + ((long long)b * kMaxVals + v) * kRedBlocks;
+}
+
+__device__ inline bool skip(const int* active, int b) { return active && !active[b]; }
 
 template <typename T>
 __device__ inline T degr(T phi, T k) {
@@ -47,12 +57,11 @@ __device__ inline Nb neighbours(const Geom& g, long long idx) {
 }
 
 // ---------------------------------------------------------------------------
-// finalize kernels (one thread; fixed-order sums)
+// finalize kernels: one block of 256 threads per RVE (blockIdx.x = b)
 // ---------------------------------------------------------------------------
 
-// Fixed-order sum of n partials by one block of 256 threads: thread t adds
-// entries t, t+256, ... in order, then a fixed tree over the threads.  Every
-// thread returns the total.
+// Fixed-order sum of n values: thread t adds entries t, t+256, ... in order,
+// then a fixed tree over the threads.  Every thread returns the total.
 __device__ inline double sum_fixed(const double* p, int n) {
     __shared__ double sh[256];
     double s = 0.0;
@@ -68,10 +77,31 @@ __device__ inline double sum_fixed(const double* p, int n) {
     return tot;
 }
 
-__global__ void k_cg_init(CgDev* cg, const double* prr, int nrr, const double* pb, int nb,
-                          double tol, int max_it) {
-    const double rr = sum_fixed(prr, nrr);
-    const double bn2 = sum_fixed(pb, nb);
+__device__ inline double max_fixed(const double* p, int n) {
+    __shared__ double sh[256];
+    double s = -DBL_MAX;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s = fmax(s, p[i]);
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    const double tot = sh[0];
+    __syncthreads();
+    return tot;
+}
+
+__global__ void k_cg_init(CgDev* cgs, const double* prr, const double* pb, int n, double tol,
+                          int max_it, const int* active) {
+    const int b = blockIdx.x;
+    CgDev* cg = cgs + b;
+    if (skip(active, b)) {
+        if (threadIdx.x == 0) { cg->done = 1; cg->status = 0; cg->it = 0; }
+        return;
+    }
+    const double rr = sum_fixed(prr + (long long)b * n, n);
+    const double bn2 = sum_fixed(pb + (long long)b * n, n);
     if (threadIdx.x != 0) return;
     cg->rr = rr;
     cg->bn2 = bn2;
@@ -87,9 +117,11 @@ __global__ void k_cg_init(CgDev* cg, const double* prr, int nrr, const double* p
     else if (rr <= cg->tol2 * bn2) { cg->done = 1; cg->status = 1; }
 }
 
-__global__ void k_cg_alpha(CgDev* cg, const double* p, int n) {
+__global__ void k_cg_alpha(CgDev* cgs, const double* p, int n) {
+    const int b = blockIdx.x;
+    CgDev* cg = cgs + b;
     if (cg->done) return;
-    const double pAp = sum_fixed(p, n);
+    const double pAp = sum_fixed(p + (long long)b * n, n);
     if (threadIdx.x != 0) return;
     cg->pAp = pAp;
     if (!(pAp > 0.0) || !isfinite(pAp)) {
@@ -101,9 +133,11 @@ __global__ void k_cg_alpha(CgDev* cg, const double* p, int n) {
     cg->alpha = cg->rr / pAp;
 }
 
-__global__ void k_cg_beta(CgDev* cg, const double* p, int n) {
+__global__ void k_cg_beta(CgDev* cgs, const double* p, int n) {
+    const int b = blockIdx.x;
+    CgDev* cg = cgs + b;
     if (cg->done) return;
-    const double rr = sum_fixed(p, n);
+    const double rr = sum_fixed(p + (long long)b * n, n);
     if (threadIdx.x != 0) return;
     cg->beta = rr / cg->rr;
     cg->rr = rr;
@@ -114,253 +148,68 @@ __global__ void k_cg_beta(CgDev* cg, const double* p, int n) {
     else if (cg->it >= cg->max_it) { cg->done = 1; cg->status = 3; }
 }
 
-hipError_t launch_cg_init(CgDev* cg, const double* prr, int nrr, const double* pb, int nb,
-                          double tol, int max_it, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_init, dim3(1), dim3(256), 0, st, cg, prr, nrr, pb, nb, tol, max_it);
+hipError_t launch_cg_init(CgDev* cg, const double* prr, const double* pb, int n, int B,
+                          double tol, int max_it, const int* active, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_init, dim3(B), dim3(256), 0, st, cg, prr, pb, n, tol, max_it, active);
     return hipGetLastError();
 }
-hipError_t launch_cg_alpha(CgDev* cg, const double* p, int n, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, st, cg, p, n);
+hipError_t launch_cg_alpha(CgDev* cg, const double* p, int n, int B, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_alpha, dim3(B), dim3(256), 0, st, cg, p, n);
     return hipGetLastError();
 }
-hipError_t launch_cg_beta(CgDev* cg, const double* p, int n, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, st, cg, p, n);
+hipError_t launch_cg_beta(CgDev* cg, const double* p, int n, int B, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_beta, dim3(B), dim3(256), 0, st, cg, p, n);
     return hipGetLastError();
 }
 
-__global__ void k_sum_partials(const double* p, int stride, int n, int nv, double* out) {
+__global__ void k_sum_partials(const double* p, int n, int nv, double* sums, const int* active) {
+    const int b = blockIdx.x;
+    if (skip(active, b)) return;
     for (int v = 0; v < nv; ++v) {
-        const double s = sum_fixed(p + (long long)v * stride, n);
-        if (threadIdx.x == 0) out[v] = s;
+        const double s = sum_fixed(p + ((long long)b * kMaxVals + v) * kRedBlocks, n);
+        if (threadIdx.x == 0) sums[b * kMaxVals + v] = s;
     }
 }
-hipError_t launch_sum_partials(const double* p, int stride, int n, int nv, double* out,
+hipError_t launch_sum_partials(const double* p, int n, int nv, int B, double* sums,
+                               const int* active, hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_partials, dim3(B), dim3(256), 0, st, p, n, nv, sums, active);
+    return hipGetLastError();
+}
+
+__global__ void k_sum_rows(const double* p, int n, double* sums, int slot) {
+    const int b = blockIdx.x;
+    const double s = sum_fixed(p + (long long)b * n, n);
+    if (threadIdx.x == 0) sums[b * kMaxVals + slot] = s;
+}
+hipError_t launch_sum_rows(const double* p, int n, int B, double* sums, int slot, hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_rows, dim3(B), dim3(256), 0, st, p, n, sums, slot);
+    return hipGetLastError();
+}
+
+__global__ void k_max_partials(const double* p, int n, double* sums, const int* active) {
+    const int b = blockIdx.x;
+    if (skip(active, b)) return;
+    const double m = max_fixed(p + (long long)b * kMaxVals * kRedBlocks, n);
+    if (threadIdx.x == 0) sums[b * kMaxVals] = m;
+}
+hipError_t launch_max_partials(const double* p, int n, int B, double* sums, const int* active,
                                hipStream_t st) {
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, p, stride, n, nv, out);
+    hipLaunchKernelGGL(k_max_partials, dim3(B), dim3(256), 0, st, p, n, sums, active);
     return hipGetLastError();
 }
 
-__global__ void k_max_partials(const double* p, int n, double* out) {
-    if (threadIdx.x != 0) return;
-    double m = -DBL_MAX;
-    for (int i = 0; i < n; ++i) m = fmax(m, p[i]);
-    out[0] = m;
-}
-hipError_t launch_max_partials(const double* p, int n, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(256), 0, st, p, n, out);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// unit response and history
-// ---------------------------------------------------------------------------
-
-struct F6 {
-    double v[6];
-};
-
-template <typename T, int S>
-__global__ void __launch_bounds__(TPB) k_unit_response(Geom g, const uint16_t* mat_id,
-                                                       const MatEntry<T>* mat, const T* phi,
-                                                       const T* x, F6 f, T* psi1, T* eps1,
-                                                       T* sig1, double* partials) {
-    double part = 0.0, part2 = 0.0;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.N;
-         i += (long long)gridDim.x * blockDim.x) {
-        const MatEntry<T>& m = mat[mat_id[i]];
-        const T gg = degr(phi[i], T(g.k_res));
-        T e[S], o[S];
-#pragma unroll
-        for (int c = 0; c < S; ++c) e[c] = T(f.v[c]) + x[c * g.N + i];
-        T psi = T(0);
-#pragma unroll
-        for (int a = 0; a < S; ++a) {
-            T acc = T(0);
-#pragma unroll
-            for (int b = 0; b < S; ++b) acc += m.C[a * S + b] * e[b];
-            o[a] = acc;
-            psi += e[a] * acc;
-        }
-        psi1[i] = T(0.5) * psi * m.drive;
-#pragma unroll
-        for (int c = 0; c < S; ++c) {
-            const T sg = gg * o[c];
-            if (eps1) eps1[c * g.N + i] = e[c];
-            if (sig1) sig1[c * g.N + i] = sg;
-            part += double(sg) * f.v[c];
-            part2 += double(sg) * double(sg);
-        }
+__global__ void k_pcg_fin_start(PcgDev* ds, const double* p, int n, double tol, int max_it,
+                                const int* active) {
+    const int b = blockIdx.x;
+    PcgDev* d = ds + b;
+    if (skip(active, b)) {
+        if (threadIdx.x == 0) { d->done = 1; d->status = 0; d->it = 0; }
+        return;
     }
-    double pv[2] = {part, part2};
-    block_sum_store<2>(pv, partials, kRedBlocks, blockIdx.x);
-}
-
-template <typename T>
-hipError_t launch_unit_response(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                                const T* phi, const T* x, const double* f, int split, T* psi1,
-                                T* eps1, T* sig1, double* partials, int nblocks, hipStream_t st) {
-    (void)split;
-    F6 ff;
-    for (int c = 0; c < 6; ++c) ff.v[c] = c < g.s ? f[c] : 0.0;
-    if (g.s == 3)
-        hipLaunchKernelGGL((k_unit_response<T, 3>), dim3(nblocks), dim3(TPB), 0, st, g, mat_id,
-                           mat, phi, x, ff, psi1, eps1, sig1, partials);
-    else
-        hipLaunchKernelGGL((k_unit_response<T, 6>), dim3(nblocks), dim3(TPB), 0, st, g, mat_id,
-                           mat, phi, x, ff, psi1, eps1, sig1, partials);
-    return hipGetLastError();
-}
-
-template <typename T>
-__global__ void __launch_bounds__(TPB) k_history(long long N, const T* psi1, const T* psi_ini,
-                                                 const T* Hn, T E2, int history, T* H) {
-    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const T ht = E2 * psi1[i] + psi_ini[i];
-    H[i] = history ? (ht > Hn[i] ? ht : Hn[i]) : ht;
-}
-
-template <typename T>
-hipError_t launch_history(const Geom& g, const T* psi1, const T* psi_ini, const T* Hn, double E,
-                          int history, T* H, hipStream_t st) {
-    hipLaunchKernelGGL((k_history<T>), dim3(blocks_for(g.N)), dim3(TPB), 0, st, g.N, psi1,
-                       psi_ini, Hn, T(E * E), history, H);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_commit_history(const Geom& g, const T* psi1, const T* psi_ini, double E,
-                                 int history, T* Hn, hipStream_t st) {
-    // in place: H = max(E^2 psi1 + psi_ini, Hn)
-    hipLaunchKernelGGL((k_history<T>), dim3(blocks_for(g.N)), dim3(TPB), 0, st, g.N, psi1,
-                       psi_ini, (const T*)Hn, T(E * E), history, Hn);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// damage operator and its PCG
-// ---------------------------------------------------------------------------
-
-// a(x) and w(x) of the operator a p + D^T (w D p).
-template <typename T>
-__device__ inline void coeffs(const Geom& g, const MatEntry<T>* mat, const uint16_t* mat_id,
-                              const T* H, int mode, T c, long long i, T& a, T& w) {
-    if (mode == 0) {
-        const T gc = mat[mat_id[i]].Gc;
-        a = gc / T(g.ell) + (H ? T(2) * H[i] : T(0));
-        w = gc * T(g.ell);
-    } else {
-        a = T(1);
-        w = c;
-    }
-}
-
-template <typename T>
-__device__ inline T wcoef(const MatEntry<T>* mat, const uint16_t* mat_id, int mode, T ell, T c,
-                          long long i) {
-    return mode == 0 ? mat[mat_id[i]].Gc * ell : c;
-}
-
-template <typename T>
-__device__ inline T apply_op(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                             const T* H, int mode, T c, const T* p, long long i) {
-    T a, w;
-    coeffs(g, mat, mat_id, H, mode, c, i, a, w);
-    const Nb n = neighbours(g, i);
-    const T ell = T(g.ell);
-    const T ih2 = T(1.0 / (g.h * g.h));
-    const T pc = p[i];
-    T acc = T(0);
-    acc += wcoef(mat, mat_id, mode, ell, c, n.xm) * (pc - p[n.xm]) - w * (p[n.xp] - pc);
-    acc += wcoef(mat, mat_id, mode, ell, c, n.ym) * (pc - p[n.ym]) - w * (p[n.yp] - pc);
-    if (g.dim == 3)
-        acc += wcoef(mat, mat_id, mode, ell, c, n.zm) * (pc - p[n.zm]) - w * (p[n.zp] - pc);
-    return a * pc + acc * ih2;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(TPB) k_pcg_matvec(Geom g, const uint16_t* mat_id,
-                                                    const MatEntry<T>* mat, const T* H, int mode,
-                                                    T c, const T* p, T* q, double* partials,
-                                                    const PcgDev* d) {
-    if (d && d->done) return;
-    double part = 0.0;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.N;
-         i += (long long)gridDim.x * blockDim.x) {
-        const T v = apply_op(g, mat_id, mat, H, mode, c, p, i);
-        q[i] = v;
-        part += double(p[i]) * double(v);
-    }
-    if (partials) {
-        double pv[1] = {part};
-        block_sum_store<1>(pv, partials, 0, blockIdx.x);
-    }
-}
-
-template <typename T>
-hipError_t launch_pcg_matvec(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                             const T* H, int mode, double c, const T* p, T* q, double* partials,
-                             int nblocks, const PcgDev* d, hipStream_t st) {
-    hipLaunchKernelGGL((k_pcg_matvec<T>), dim3(nblocks), dim3(TPB), 0, st, g, mat_id, mat, H,
-                       mode, T(c), p, q, partials, d);
-    return hipGetLastError();
-}
-
-template <typename T>
-__global__ void __launch_bounds__(TPB) k_damage_diag(Geom g, const uint16_t* mat_id,
-                                                     const MatEntry<T>* mat, const T* H, int mode,
-                                                     T c, T* dinv) {
-    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (i >= g.N) return;
-    T a, w;
-    coeffs(g, mat, mat_id, H, mode, c, i, a, w);
-    const Nb n = neighbours(g, i);
-    const T ell = T(g.ell);
-    T s = T(2) * w + wcoef(mat, mat_id, mode, ell, c, n.xm) + wcoef(mat, mat_id, mode, ell, c, n.ym);
-    if (g.dim == 3) s += w + wcoef(mat, mat_id, mode, ell, c, n.zm);
-    dinv[i] = T(1) / (a + s * T(1.0 / (g.h * g.h)));
-}
-
-template <typename T>
-hipError_t launch_damage_diag(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                              const T* H, int mode, double c, T* dinv, hipStream_t st) {
-    hipLaunchKernelGGL((k_damage_diag<T>), dim3(blocks_for(g.N)), dim3(TPB), 0, st, g, mat_id,
-                       mat, H, mode, T(c), dinv);
-    return hipGetLastError();
-}
-
-template <typename T>
-__global__ void __launch_bounds__(TPB) k_pcg_start(long long N, const T* b, const T* Ax,
-                                                   const T* dinv, T* r, T* p, double* partials,
-                                                   int stride) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
-         i += (long long)gridDim.x * blockDim.x) {
-        const T bi = b[i];
-        const T ri = bi - Ax[i];
-        const T zi = dinv[i] * ri;
-        r[i] = ri;
-        p[i] = zi;
-        s0 += double(ri) * double(zi);
-        s1 += double(ri) * double(ri);
-        s2 += double(bi) * double(bi);
-    }
-    double pv[3] = {s0, s1, s2};
-    block_sum_store<3>(pv, partials, stride, blockIdx.x);
-}
-
-template <typename T>
-hipError_t launch_pcg_start(const Geom& g, const T* b, const T* Ax, const T* dinv, T* r, T* p,
-                            double* partials, int nblocks, hipStream_t st) {
-    hipLaunchKernelGGL((k_pcg_start<T>), dim3(nblocks), dim3(TPB), 0, st, g.N, b, Ax, dinv, r, p,
-                       partials, kRedBlocks);
-    return hipGetLastError();
-}
-
-__global__ void k_pcg_fin_start(PcgDev* d, const double* p, int n, double tol, int max_it) {
-    const double rz = sum_fixed(p, n);
-    const double rr = sum_fixed(p + kRedBlocks, n);
-    const double bn2 = sum_fixed(p + 2 * kRedBlocks, n);
+    const double* pb = p + (long long)b * kMaxVals * kRedBlocks;
+    const double rz = sum_fixed(pb, n);
+    const double rr = sum_fixed(pb + kRedBlocks, n);
+    const double bn2 = sum_fixed(pb + 2 * kRedBlocks, n);
     if (threadIdx.x != 0) return;
     d->rz = rz;
     d->rr = rr;
@@ -370,59 +219,37 @@ __global__ void k_pcg_fin_start(PcgDev* d, const double* p, int n, double tol, i
     d->max_it = max_it;
     d->status = 0;
     d->done = 0;
-    if (!isfinite(d->rr) || !isfinite(d->rz)) { d->done = 1; d->status = 2; }
-    else if (d->rr <= d->tol2 * d->bn2) { d->done = 1; d->status = 1; }
+    if (!isfinite(rr) || !isfinite(rz)) { d->done = 1; d->status = 2; }
+    else if (rr <= d->tol2 * bn2) { d->done = 1; d->status = 1; }
 }
-hipError_t launch_pcg_fin_start(PcgDev* d, const double* p, int n, double tol, int max_it,
-                                hipStream_t st) {
-    hipLaunchKernelGGL(k_pcg_fin_start, dim3(1), dim3(256), 0, st, d, p, n, tol, max_it);
+hipError_t launch_pcg_fin_start(PcgDev* d, const double* p, int n, int B, double tol, int max_it,
+                                const int* active, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_fin_start, dim3(B), dim3(256), 0, st, d, p, n, tol, max_it, active);
     return hipGetLastError();
 }
 
-__global__ void k_pcg_fin_alpha(PcgDev* d, const double* p, int n) {
+__global__ void k_pcg_fin_alpha(PcgDev* ds, const double* p, int n) {
+    const int b = blockIdx.x;
+    PcgDev* d = ds + b;
     if (d->done) return;
-    const double pq = sum_fixed(p, n);
+    const double pq = sum_fixed(p + (long long)b * kMaxVals * kRedBlocks, n);
     if (threadIdx.x != 0) return;
     d->pq = pq;
     if (!(pq > 0.0) || !isfinite(pq)) { d->done = 1; d->status = 2; d->alpha = 0.0; return; }
     d->alpha = d->rz / pq;
 }
-hipError_t launch_pcg_fin_alpha(PcgDev* d, const double* p, int n, hipStream_t st) {
-    hipLaunchKernelGGL(k_pcg_fin_alpha, dim3(1), dim3(256), 0, st, d, p, n);
+hipError_t launch_pcg_fin_alpha(PcgDev* d, const double* p, int n, int B, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_fin_alpha, dim3(B), dim3(256), 0, st, d, p, n);
     return hipGetLastError();
 }
 
-template <typename T>
-__global__ void __launch_bounds__(TPB) k_pcg_update(long long N, const PcgDev* d, T* x, T* r,
-                                                    const T* p, const T* q, const T* dinv,
-                                                    double* partials, int stride) {
+__global__ void k_pcg_fin_beta(PcgDev* ds, const double* p, int n) {
+    const int b = blockIdx.x;
+    PcgDev* d = ds + b;
     if (d->done) return;
-    const T alpha = T(d->alpha);
-    double s0 = 0.0, s1 = 0.0;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
-         i += (long long)gridDim.x * blockDim.x) {
-        x[i] += alpha * p[i];
-        const T ri = r[i] - alpha * q[i];
-        r[i] = ri;
-        s0 += double(ri) * double(dinv[i] * ri);
-        s1 += double(ri) * double(ri);
-    }
-    double pv[2] = {s0, s1};
-    block_sum_store<2>(pv, partials, stride, blockIdx.x);
-}
-
-template <typename T>
-hipError_t launch_pcg_update(const Geom& g, const PcgDev* d, T* x, T* r, const T* p, const T* q,
-                             const T* dinv, double* partials, int nblocks, hipStream_t st) {
-    hipLaunchKernelGGL((k_pcg_update<T>), dim3(nblocks), dim3(TPB), 0, st, g.N, d, x, r, p, q,
-                       dinv, partials, kRedBlocks);
-    return hipGetLastError();
-}
-
-__global__ void k_pcg_fin_beta(PcgDev* d, const double* p, int n) {
-    if (d->done) return;
-    const double rz = sum_fixed(p, n);
-    const double rr = sum_fixed(p + kRedBlocks, n);
+    const double* pb = p + (long long)b * kMaxVals * kRedBlocks;
+    const double rz = sum_fixed(pb, n);
+    const double rr = sum_fixed(pb + kRedBlocks, n);
     if (threadIdx.x != 0) return;
     d->beta = rz / d->rz;
     d->rz = rz;
@@ -432,36 +259,303 @@ __global__ void k_pcg_fin_beta(PcgDev* d, const double* p, int n) {
     else if (rr <= d->tol2 * d->bn2) { d->done = 1; d->status = 1; }
     else if (d->it >= d->max_it) { d->done = 1; d->status = 3; }
 }
-hipError_t launch_pcg_fin_beta(PcgDev* d, const double* p, int n, hipStream_t st) {
-    hipLaunchKernelGGL(k_pcg_fin_beta, dim3(1), dim3(256), 0, st, d, p, n);
+hipError_t launch_pcg_fin_beta(PcgDev* d, const double* p, int n, int B, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_fin_beta, dim3(B), dim3(256), 0, st, d, p, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// unit response and history
+// ---------------------------------------------------------------------------
+
+template <typename T, int S>
+__global__ void __launch_bounds__(TPB) k_unit_response(Geom g, const uint16_t* mat_id,
+                                                       const MatEntry<T>* mat, const T* phi,
+                                                       const T* x, F6 f, T* psi1, T* eps1,
+                                                       T* sig1, double* partials,
+                                                       const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
+    const long long so = (long long)b * g.N, fo = so * S;
+    const MatEntry<T>* mt = mat + (long long)b * g.mstride;
+    double part = 0.0, part2 = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.N;
+         i += (long long)gridDim.x * blockDim.x) {
+        const MatEntry<T>& m = mt[mat_id[so + i]];
+        const T gg = degr(phi[so + i], T(g.k_res));
+        T e[S], o[S];
+#pragma unroll
+        for (int c = 0; c < S; ++c) e[c] = T(f.v[c]) + x[fo + c * g.N + i];
+        T psi = T(0);
+#pragma unroll
+        for (int a = 0; a < S; ++a) {
+            T acc = T(0);
+#pragma unroll
+            for (int c = 0; c < S; ++c) acc += m.C[a * S + c] * e[c];
+            o[a] = acc;
+            psi += e[a] * acc;
+        }
+        psi1[so + i] = T(0.5) * psi * m.drive;
+#pragma unroll
+        for (int c = 0; c < S; ++c) {
+            const T sg = gg * o[c];
+            if (eps1) eps1[fo + c * g.N + i] = e[c];
+            if (sig1) sig1[fo + c * g.N + i] = sg;
+            part += double(sg) * f.v[c];
+            part2 += double(sg) * double(sg);
+        }
+    }
+    double pv[2] = {part, part2};
+    block_sum_store<2>(pv, pslot(partials, b, 0), kRedBlocks, blockIdx.x);
+}
+
+template <typename T>
+hipError_t launch_unit_response(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
+                                const T* phi, const T* x, const F6& f, T* psi1, T* eps1, T* sig1,
+                                double* partials, int nred, const int* active, hipStream_t st) {
+    const dim3 grid(nred, g.B);
+    if (g.s == 3)
+        hipLaunchKernelGGL((k_unit_response<T, 3>), grid, dim3(TPB), 0, st, g, mat_id, mat, phi, x,
+                           f, psi1, eps1, sig1, partials, active);
+    else
+        hipLaunchKernelGGL((k_unit_response<T, 6>), grid, dim3(TPB), 0, st, g, mat_id, mat, phi, x,
+                           f, psi1, eps1, sig1, partials, active);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_history(long long N, const T* psi1, const T* psi_ini,
+                                                 const T* Hn, const double* E, int history, T* H,
+                                                 T* rhs, const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const long long o = (long long)b * N + i;
+    const T E2 = T(E[b] * E[b]);
+    const T ht = E2 * psi1[o] + psi_ini[o];
+    const T h = history ? (ht > Hn[o] ? ht : Hn[o]) : ht;
+    H[o] = h;
+    if (rhs) rhs[o] = T(2) * h;
+}
+
+template <typename T>
+hipError_t launch_history(const Geom& g, const T* psi1, const T* psi_ini, const T* Hn,
+                          const double* E, int history, T* H, T* rhs, const int* active,
+                          hipStream_t st) {
+    hipLaunchKernelGGL((k_history<T>), dim3(blocks_for(g.N), g.B), dim3(TPB), 0, st, g.N, psi1,
+                       psi_ini, Hn, E, history, H, rhs, active);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_commit_history(const Geom& g, const T* psi1, const T* psi_ini, const double* E,
+                                 int history, T* Hn, const int* active, hipStream_t st) {
+    // in place: Hn = max(E^2 psi1 + psi_ini, Hn)
+    hipLaunchKernelGGL((k_history<T>), dim3(blocks_for(g.N), g.B), dim3(TPB), 0, st, g.N, psi1,
+                       psi_ini, (const T*)Hn, E, history, Hn, (T*)nullptr, active);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// damage operator and its PCG
+// ---------------------------------------------------------------------------
+
+// a(x) and w(x) of the operator a p + D^T (w D p).
+template <typename T>
+__device__ inline void coeffs(const Geom& g, const MatEntry<T>* mat, const uint16_t* mid,
+                              const T* H, int mode, T c, long long i, T& a, T& w) {
+    if (mode == 0) {
+        const T gc = mat[mid[i]].Gc;
+        a = gc / T(g.ell) + (H ? T(2) * H[i] : T(0));
+        w = gc * T(g.ell);
+    } else {
+        a = T(1);
+        w = c;
+    }
+}
+
+template <typename T>
+__device__ inline T wcoef(const MatEntry<T>* mat, const uint16_t* mid, int mode, T ell, T c,
+                          long long i) {
+    return mode == 0 ? mat[mid[i]].Gc * ell : c;
+}
+
+// fields passed here are already offset to the RVE
+template <typename T>
+__device__ inline T apply_op(const Geom& g, const uint16_t* mid, const MatEntry<T>* mat,
+                             const T* H, int mode, T c, const T* p, long long i) {
+    T a, w;
+    coeffs(g, mat, mid, H, mode, c, i, a, w);
+    const Nb n = neighbours(g, i);
+    const T ell = T(g.ell);
+    const T ih2 = T(1.0 / (g.h * g.h));
+    const T pc = p[i];
+    T acc = T(0);
+    acc += wcoef(mat, mid, mode, ell, c, n.xm) * (pc - p[n.xm]) - w * (p[n.xp] - pc);
+    acc += wcoef(mat, mid, mode, ell, c, n.ym) * (pc - p[n.ym]) - w * (p[n.yp] - pc);
+    if (g.dim == 3)
+        acc += wcoef(mat, mid, mode, ell, c, n.zm) * (pc - p[n.zm]) - w * (p[n.zp] - pc);
+    return a * pc + acc * ih2;
+}
+
+#define RVE_OFFSETS                                                   \
+    const long long so = (long long)b * g.N;                          \
+    const uint16_t* mid = mat_id + so;                                \
+    const MatEntry<T>* mt = mat + (long long)b * g.mstride;
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_pcg_matvec(Geom g, const uint16_t* mat_id,
+                                                    const MatEntry<T>* mat, const T* H, int mode,
+                                                    T c, const T* p, T* q, double* partials,
+                                                    const PcgDev* d, const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
+    if (d && d[b].done) return;
+    RVE_OFFSETS
+    const T* Hb = H ? H + so : nullptr;
+    double part = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.N;
+         i += (long long)gridDim.x * blockDim.x) {
+        const T v = apply_op(g, mid, mt, Hb, mode, c, p + so, i);
+        q[so + i] = v;
+        part += double(p[so + i]) * double(v);
+    }
+    if (partials) {
+        double pv[1] = {part};
+        block_sum_store<1>(pv, pslot(partials, b, 0), kRedBlocks, blockIdx.x);
+    }
+}
+
+template <typename T>
+hipError_t launch_pcg_matvec(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
+                             const T* H, int mode, double c, const T* p, T* q, double* partials,
+                             int nred, const PcgDev* d, const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_pcg_matvec<T>), dim3(nred, g.B), dim3(TPB), 0, st, g, mat_id, mat, H,
+                       mode, T(c), p, q, partials, d, active);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_damage_diag(Geom g, const uint16_t* mat_id,
+                                                     const MatEntry<T>* mat, const T* H, int mode,
+                                                     T c, T* dinv, const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i >= g.N) return;
+    RVE_OFFSETS
+    T a, w;
+    coeffs(g, mt, mid, H ? H + so : (const T*)nullptr, mode, c, i, a, w);
+    const Nb n = neighbours(g, i);
+    const T ell = T(g.ell);
+    T s = T(2) * w + wcoef(mt, mid, mode, ell, c, n.xm) + wcoef(mt, mid, mode, ell, c, n.ym);
+    if (g.dim == 3) s += w + wcoef(mt, mid, mode, ell, c, n.zm);
+    dinv[so + i] = T(1) / (a + s * T(1.0 / (g.h * g.h)));
+}
+
+template <typename T>
+hipError_t launch_damage_diag(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
+                              const T* H, int mode, double c, T* dinv, const int* active,
+                              hipStream_t st) {
+    hipLaunchKernelGGL((k_damage_diag<T>), dim3(blocks_for(g.N), g.B), dim3(TPB), 0, st, g,
+                       mat_id, mat, H, mode, T(c), dinv, active);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_pcg_start(long long N, const T* bv, const T* Ax,
+                                                   const T* dinv, T* r, T* p, double* partials,
+                                                   const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
+    const long long so = (long long)b * N;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long o = so + i;
+        const T bi = bv[o];
+        const T ri = bi - Ax[o];
+        const T zi = dinv[o] * ri;
+        r[o] = ri;
+        p[o] = zi;
+        s0 += double(ri) * double(zi);
+        s1 += double(ri) * double(ri);
+        s2 += double(bi) * double(bi);
+    }
+    double pv[3] = {s0, s1, s2};
+    block_sum_store<3>(pv, pslot(partials, b, 0), kRedBlocks, blockIdx.x);
+}
+
+template <typename T>
+hipError_t launch_pcg_start(const Geom& g, const T* b, const T* Ax, const T* dinv, T* r, T* p,
+                            double* partials, int nred, const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_pcg_start<T>), dim3(nred, g.B), dim3(TPB), 0, st, g.N, b, Ax, dinv, r,
+                       p, partials, active);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_pcg_update(long long N, const PcgDev* d, T* x, T* r,
+                                                    const T* p, const T* q, const T* dinv,
+                                                    double* partials) {
+    const int b = blockIdx.y;
+    if (d[b].done) return;
+    const T alpha = T(d[b].alpha);
+    const long long so = (long long)b * N;
+    double s0 = 0.0, s1 = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long o = so + i;
+        x[o] += alpha * p[o];
+        const T ri = r[o] - alpha * q[o];
+        r[o] = ri;
+        s0 += double(ri) * double(dinv[o] * ri);
+        s1 += double(ri) * double(ri);
+    }
+    double pv[2] = {s0, s1};
+    block_sum_store<2>(pv, pslot(partials, b, 0), kRedBlocks, blockIdx.x);
+}
+
+template <typename T>
+hipError_t launch_pcg_update(const Geom& g, const PcgDev* d, T* x, T* r, const T* p, const T* q,
+                             const T* dinv, double* partials, int nred, hipStream_t st) {
+    hipLaunchKernelGGL((k_pcg_update<T>), dim3(nred, g.B), dim3(TPB), 0, st, g.N, d, x, r, p, q,
+                       dinv, partials);
     return hipGetLastError();
 }
 
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_pcg_dir(long long N, const PcgDev* d, const T* r,
                                                  const T* dinv, T* p) {
-    if (d->done) return;
+    const int b = blockIdx.y;
+    if (d[b].done) return;
     const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (i >= N) return;
-    p[i] = dinv[i] * r[i] + T(d->beta) * p[i];
+    const long long o = (long long)b * N + i;
+    p[o] = dinv[o] * r[o] + T(d[b].beta) * p[o];
 }
 
 template <typename T>
 hipError_t launch_pcg_dir(const Geom& g, const PcgDev* d, const T* r, const T* dinv, T* p,
                           hipStream_t st) {
-    hipLaunchKernelGGL((k_pcg_dir<T>), dim3(blocks_for(g.N)), dim3(TPB), 0, st, g.N, d, r, dinv,
-                       p);
+    hipLaunchKernelGGL((k_pcg_dir<T>), dim3(blocks_for(g.N), g.B), dim3(TPB), 0, st, g.N, d, r,
+                       dinv, p);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// AT2 functionals, residual, enrichment energy
+// AT2 functionals, residual, enrichment energy, tangent
 // ---------------------------------------------------------------------------
 
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_dissipation(Geom g, const uint16_t* mat_id,
-                                                     const MatEntry<T>* mat, const T* phi,
-                                                     double* partials, int stride) {
+                                                     const MatEntry<T>* mat, const T* phi_all,
+                                                     double* partials, const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
+    RVE_OFFSETS
+    const T* phi = phi_all + so;
     double sD = 0.0, sG = 0.0;
     const double ell = g.ell, ih = 1.0 / g.h;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.N;
@@ -472,18 +566,19 @@ __global__ void __launch_bounds__(TPB) k_dissipation(Geom g, const uint16_t* mat
         const double gy = (double(phi[n.yp]) - pc) * ih;
         const double gz = g.dim == 3 ? (double(phi[n.zp]) - pc) * ih : 0.0;
         const double dens = pc * pc / (2.0 * ell) + 0.5 * ell * (gx * gx + gy * gy + gz * gz);
-        sD += double(mat[mat_id[i]].Gc) * dens;
+        sD += double(mt[mid[i]].Gc) * dens;
         sG += dens;
     }
     double pv[2] = {sD, sG};
-    block_sum_store<2>(pv, partials, stride, blockIdx.x);
+    block_sum_store<2>(pv, pslot(partials, b, 0), kRedBlocks, blockIdx.x);
 }
 
 template <typename T>
 hipError_t launch_dissipation(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                              const T* phi, double* partials, int nblocks, hipStream_t st) {
-    hipLaunchKernelGGL((k_dissipation<T>), dim3(nblocks), dim3(TPB), 0, st, g, mat_id, mat, phi,
-                       partials, kRedBlocks);
+                              const T* phi, double* partials, int nred, const int* active,
+                              hipStream_t st) {
+    hipLaunchKernelGGL((k_dissipation<T>), dim3(nred, g.B), dim3(TPB), 0, st, g, mat_id, mat, phi,
+                       partials, active);
     return hipGetLastError();
 }
 
@@ -491,77 +586,90 @@ template <typename T>
 __global__ void __launch_bounds__(TPB) k_damage_residual(Geom g, const uint16_t* mat_id,
                                                          const MatEntry<T>* mat, const T* H,
                                                          const T* phi, double* partials,
-                                                         int stride) {
+                                                         const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
+    RVE_OFFSETS
     double s0 = 0.0, s1 = 0.0;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.N;
          i += (long long)gridDim.x * blockDim.x) {
-        const T v = apply_op(g, mat_id, mat, H, 0, T(0), phi, i);
-        const double b = 2.0 * double(H[i]);
-        const double res = double(v) - b;
+        const T v = apply_op(g, mid, mt, H + so, 0, T(0), phi + so, i);
+        const double bb = 2.0 * double(H[so + i]);
+        const double res = double(v) - bb;
         s0 += res * res;
-        s1 += b * b;
+        s1 += bb * bb;
     }
     double pv[2] = {s0, s1};
-    block_sum_store<2>(pv, partials, stride, blockIdx.x);
+    block_sum_store<2>(pv, pslot(partials, b, 0), kRedBlocks, blockIdx.x);
 }
 
 template <typename T>
 hipError_t launch_damage_residual(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                                  const T* H, const T* phi, double* partials, int nblocks,
-                                  hipStream_t st) {
-    hipLaunchKernelGGL((k_damage_residual<T>), dim3(nblocks), dim3(TPB), 0, st, g, mat_id, mat, H,
-                       phi, partials, kRedBlocks);
+                                  const T* H, const T* phi, double* partials, int nred,
+                                  const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_damage_residual<T>), dim3(nred, g.B), dim3(TPB), 0, st, g, mat_id, mat,
+                       H, phi, partials, active);
     return hipGetLastError();
 }
 
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_psi_ini(Geom g, const uint16_t* mat_id,
                                                  const MatEntry<T>* mat, const T* phi,
-                                                 T* psi_ini) {
+                                                 T* psi_ini, const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
     const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (i >= g.N) return;
+    RVE_OFFSETS
     // gamma'(phi) = Gc phi / l + L phi  (operator with H = 0)
-    const T gp = apply_op(g, mat_id, mat, (const T*)nullptr, 0, T(0), phi, i);
-    const T v = gp / (T(2) * (T(1) - phi[i]));
-    psi_ini[i] = v > T(0) ? v : T(0);
+    const T gp = apply_op(g, mid, mt, (const T*)nullptr, 0, T(0), phi + so, i);
+    const T v = gp / (T(2) * (T(1) - phi[so + i]));
+    psi_ini[so + i] = v > T(0) ? v : T(0);
 }
 
 template <typename T>
 hipError_t launch_psi_ini(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                          const T* phi, T* psi_ini, hipStream_t st) {
-    hipLaunchKernelGGL((k_psi_ini<T>), dim3(blocks_for(g.N)), dim3(TPB), 0, st, g, mat_id, mat,
-                       phi, psi_ini);
+                          const T* phi, T* psi_ini, const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_psi_ini<T>), dim3(blocks_for(g.N), g.B), dim3(TPB), 0, st, g, mat_id,
+                       mat, phi, psi_ini, active);
     return hipGetLastError();
 }
 
-// Right-hand side of the E-tangent of the damage balance:
-// 2 (1 - phi) dH/dE, dH/dE = 2 E psi1 where E^2 psi1 + psi_ini > H^n (or
-// everywhere without the history max).
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_tangent_rhs(long long N, const T* phi, const T* psi1,
-                                                     const T* psi_ini, const T* Hn, T E,
-                                                     int history, T* out) {
+                                                     const T* psi_ini, const T* Hn,
+                                                     const double* E, int history, T* out,
+                                                     const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
     const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (i >= N) return;
-    const T ht = E * E * psi1[i] + psi_ini[i];
-    const bool active = history ? (ht > Hn[i]) : true;
-    out[i] = active ? T(2) * (T(1) - phi[i]) * T(2) * E * psi1[i] : T(0);
+    const long long o = (long long)b * N + i;
+    const T e = T(E[b]);
+    const T ht = e * e * psi1[o] + psi_ini[o];
+    const bool on = history ? (ht > Hn[o]) : true;
+    out[o] = on ? T(2) * (T(1) - phi[o]) * T(2) * e * psi1[o] : T(0);
 }
 
 template <typename T>
 hipError_t launch_tangent_rhs(const Geom& g, const T* phi, const T* psi1, const T* psi_ini,
-                              const T* Hn, double E, int history, T* out, hipStream_t st) {
-    hipLaunchKernelGGL((k_tangent_rhs<T>), dim3(blocks_for(g.N)), dim3(TPB), 0, st, g.N, phi,
-                       psi1, psi_ini, Hn, T(E), history, out);
+                              const T* Hn, const double* E, int history, T* out,
+                              const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_tangent_rhs<T>), dim3(blocks_for(g.N), g.B), dim3(TPB), 0, st, g.N, phi,
+                       psi1, psi_ini, Hn, E, history, out, active);
     return hipGetLastError();
 }
 
-// dD(phi)[dphi] = h^d sum Gc (phi dphi / l + l grad phi . grad dphi); partial sums
-// without the h^d factor.
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_dissipation_dir(Geom g, const uint16_t* mat_id,
-                                                         const MatEntry<T>* mat, const T* phi,
-                                                         const T* dphi, double* partials) {
+                                                         const MatEntry<T>* mat, const T* phi_a,
+                                                         const T* dphi_a, double* partials,
+                                                         const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
+    RVE_OFFSETS
+    const T* phi = phi_a + so;
+    const T* dphi = dphi_a + so;
     double s = 0.0;
     const double ell = g.ell, ih = 1.0 / g.h;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.N;
@@ -571,116 +679,127 @@ __global__ void __launch_bounds__(TPB) k_dissipation_dir(Geom g, const uint16_t*
         double gg = (double(phi[n.xp]) - pc) * (double(dphi[n.xp]) - dc);
         gg += (double(phi[n.yp]) - pc) * (double(dphi[n.yp]) - dc);
         if (g.dim == 3) gg += (double(phi[n.zp]) - pc) * (double(dphi[n.zp]) - dc);
-        s += double(mat[mat_id[i]].Gc) * (pc * dc / ell + ell * gg * ih * ih);
+        s += double(mt[mid[i]].Gc) * (pc * dc / ell + ell * gg * ih * ih);
     }
     double pv[1] = {s};
-    block_sum_store<1>(pv, partials, 0, blockIdx.x);
+    block_sum_store<1>(pv, pslot(partials, b, 0), kRedBlocks, blockIdx.x);
 }
 
 template <typename T>
 hipError_t launch_dissipation_dir(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                                  const T* phi, const T* dphi, double* partials, int nblocks,
-                                  hipStream_t st) {
-    hipLaunchKernelGGL((k_dissipation_dir<T>), dim3(nblocks), dim3(TPB), 0, st, g, mat_id, mat,
-                       phi, dphi, partials);
-    return hipGetLastError();
-}
-
-// out = a - b
-template <typename T>
-__global__ void __launch_bounds__(TPB) k_sub(const T* a, const T* b, T* out, long long n) {
-    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (i < n) out[i] = a[i] - b[i];
-}
-template <typename T>
-hipError_t launch_sub(const T* a, const T* b, T* out, long long n, hipStream_t st) {
-    hipLaunchKernelGGL((k_sub<T>), dim3(blocks_for(n)), dim3(TPB), 0, st, a, b, out, n);
-    return hipGetLastError();
-}
-
-// b = c * a
-template <typename T>
-__global__ void __launch_bounds__(TPB) k_scaled(const T* a, T c, T* b, long long n) {
-    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (i < n) b[i] = c * a[i];
-}
-template <typename T>
-hipError_t launch_scaled(const T* a, double c, T* b, long long n, hipStream_t st) {
-    hipLaunchKernelGGL((k_scaled<T>), dim3(blocks_for(n)), dim3(TPB), 0, st, a, T(c), b, n);
+                                  const T* phi, const T* dphi, double* partials, int nred,
+                                  const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_dissipation_dir<T>), dim3(nred, g.B), dim3(TPB), 0, st, g, mat_id, mat,
+                       phi, dphi, partials, active);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// field utilities
+// field utilities (n elements per RVE)
 // ---------------------------------------------------------------------------
 
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_copy(const T* s, T* d, long long n) {
+__global__ void __launch_bounds__(TPB) k_copy(const T* s, T* d, long long n, const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
     const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (i < n) d[i] = s[i];
+    if (i < n) d[(long long)b * n + i] = s[(long long)b * n + i];
 }
 template <typename T>
-hipError_t launch_copy(const T* s, T* d, long long n, hipStream_t st) {
-    hipLaunchKernelGGL((k_copy<T>), dim3(blocks_for(n)), dim3(TPB), 0, st, s, d, n);
+hipError_t launch_copy(const T* s, T* d, long long n, int B, const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_copy<T>), dim3(blocks_for(n), B), dim3(TPB), 0, st, s, d, n, active);
     return hipGetLastError();
 }
 
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_fill(T* d, T v, long long n) {
+__global__ void __launch_bounds__(TPB) k_fill(T* d, T v, long long n, const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
     const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (i < n) d[i] = v;
+    if (i < n) d[(long long)b * n + i] = v;
 }
 template <typename T>
-hipError_t launch_fill(T* d, T v, long long n, hipStream_t st) {
-    hipLaunchKernelGGL((k_fill<T>), dim3(blocks_for(n)), dim3(TPB), 0, st, d, v, n);
+hipError_t launch_fill(T* d, T v, long long n, int B, const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_fill<T>), dim3(blocks_for(n), B), dim3(TPB), 0, st, d, v, n, active);
     return hipGetLastError();
 }
 
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_max_field(const T* a, long long n, double* partials) {
+__global__ void __launch_bounds__(TPB) k_sub(const T* a, const T* c, T* out, long long n,
+                                             const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
+    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+    if (i < n) {
+        const long long o = (long long)b * n + i;
+        out[o] = a[o] - c[o];
+    }
+}
+template <typename T>
+hipError_t launch_sub(const T* a, const T* c, T* out, long long n, int B, const int* active,
+                      hipStream_t st) {
+    hipLaunchKernelGGL((k_sub<T>), dim3(blocks_for(n), B), dim3(TPB), 0, st, a, c, out, n, active);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_max_field(const T* a, long long n, double* partials,
+                                                   const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
     double m = -DBL_MAX;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x)
-        m = fmax(m, double(a[i]));
-    block_max_store(m, partials, blockIdx.x);
+        m = fmax(m, double(a[(long long)b * n + i]));
+    block_max_store(m, pslot(partials, b, 0), blockIdx.x);
 }
 template <typename T>
-hipError_t launch_max_field(const T* a, long long n, double* partials, int nblocks,
-                            hipStream_t st) {
-    hipLaunchKernelGGL((k_max_field<T>), dim3(nblocks), dim3(TPB), 0, st, a, n, partials);
+hipError_t launch_max_field(const T* a, long long n, int B, double* partials, int nred,
+                            const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_max_field<T>), dim3(nred, B), dim3(TPB), 0, st, a, n, partials, active);
     return hipGetLastError();
 }
 
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_scale_field(T* a, const double* den, double c,
-                                                     long long n) {
+                                                     long long n, const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
     const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (i < n) a[i] = T(double(a[i]) * (c / den[0]));
+    if (i < n) {
+        const long long o = (long long)b * n + i;
+        a[o] = T(double(a[o]) * (c / den[b * kMaxVals]));
+    }
 }
 template <typename T>
-hipError_t launch_scale_field(T* a, const double* den, double c, long long n, hipStream_t st) {
-    hipLaunchKernelGGL((k_scale_field<T>), dim3(blocks_for(n)), dim3(TPB), 0, st, a, den, c, n);
+hipError_t launch_scale_field(T* a, const double* den, double c, long long n, int B,
+                              const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_scale_field<T>), dim3(blocks_for(n), B), dim3(TPB), 0, st, a, den, c, n,
+                       active);
     return hipGetLastError();
 }
 
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_diff_norms(const T* a, const T* b, long long n,
-                                                    double* partials, int stride) {
+__global__ void __launch_bounds__(TPB) k_diff_norms(const T* a, const T* c, long long n,
+                                                    double* partials, const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
     double s0 = 0.0, s1 = 0.0;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
-        const double d = double(a[i]) - double(b[i]);
+        const long long o = (long long)b * n + i;
+        const double d = double(a[o]) - double(c[o]);
         s0 += d * d;
-        s1 += double(a[i]) * double(a[i]);
+        s1 += double(a[o]) * double(a[o]);
     }
     double pv[2] = {s0, s1};
-    block_sum_store<2>(pv, partials, stride, blockIdx.x);
+    block_sum_store<2>(pv, pslot(partials, b, 0), kRedBlocks, blockIdx.x);
 }
 template <typename T>
-hipError_t launch_diff_norms(const T* a, const T* b, long long n, double* partials, int nblocks,
-                             hipStream_t st) {
-    hipLaunchKernelGGL((k_diff_norms<T>), dim3(nblocks), dim3(TPB), 0, st, a, b, n, partials,
-                       kRedBlocks);
+hipError_t launch_diff_norms(const T* a, const T* c, long long n, int B, double* partials,
+                             int nred, const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_diff_norms<T>), dim3(nred, B), dim3(TPB), 0, st, a, c, n, partials,
+                       active);
     return hipGetLastError();
 }
 
@@ -688,13 +807,19 @@ hipError_t launch_diff_norms(const T* a, const T* b, long long n, double* partia
 // Anderson mixing of the stagger iterates
 // ---------------------------------------------------------------------------
 
-// Gram data of the residual history F_0..F_m (oldest first):
-// values [i*m + j] (i, j < m) = dF_i . dF_j with dF_i = F_{i+1} - F_i,
-// values [m*m + i] = dF_i . F_m.
 template <typename T, int MM>
-__global__ void __launch_bounds__(TPB) k_anderson_gram(long long N, Ptrs<T> F, int m1,
-                                                       double* partials, int stride) {
+__global__ void __launch_bounds__(TPB) k_anderson_gram(long long N, const T* Fbase,
+                                                       long long sstride, const int* order,
+                                                       const int* m1a, double* partials,
+                                                       const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
+    const int m1 = m1a[b];
     const int m = m1 - 1;
+    const T* F[MM + 1];
+#pragma unroll
+    for (int k = 0; k <= MM; ++k)
+        F[k] = Fbase + (long long)order[b * kHist + (k < m1 ? k : 0)] * sstride + (long long)b * N;
     double acc[MM * MM + MM];
 #pragma unroll
     for (int k = 0; k < MM * MM + MM; ++k) acc[k] = 0.0;
@@ -702,45 +827,57 @@ __global__ void __launch_bounds__(TPB) k_anderson_gram(long long N, Ptrs<T> F, i
          i += (long long)gridDim.x * blockDim.x) {
         double f[MM + 1];
 #pragma unroll
-        for (int k = 0; k <= MM; ++k) f[k] = k < m1 ? double(F.p[k][i]) : 0.0;
+        for (int k = 0; k <= MM; ++k) f[k] = k < m1 ? double(F[k][i]) : 0.0;
         double df[MM];
 #pragma unroll
         for (int k = 0; k < MM; ++k) df[k] = k < m ? f[k + 1] - f[k] : 0.0;
-        const double last = f[m];
+        double last = 0.0;
+#pragma unroll
+        for (int k = 0; k <= MM; ++k)
+            if (k == m) last = f[k];
 #pragma unroll
         for (int a = 0; a < MM; ++a) {
 #pragma unroll
-            for (int b = 0; b < MM; ++b) acc[a * MM + b] += df[a] * df[b];
+            for (int c = 0; c < MM; ++c) acc[a * MM + c] += df[a] * df[c];
             acc[MM * MM + a] += df[a] * last;
         }
     }
-    block_sum_store<MM * MM + MM>(acc, partials, stride, blockIdx.x);
+    block_sum_store<MM * MM + MM>(acc, pslot(partials, b, 0), kRedBlocks, blockIdx.x);
 }
 
 template <typename T>
-hipError_t launch_anderson_gram(const Geom& g, const Ptrs<T>& F, int m1, double* partials,
-                                int nblocks, hipStream_t st) {
-    hipLaunchKernelGGL((k_anderson_gram<T, kAndersonMax>), dim3(nblocks), dim3(TPB), 0, st, g.N,
-                       F, m1, partials, kRedBlocks);
+hipError_t launch_anderson_gram(const Geom& g, const T* Fbase, long long slot_stride,
+                                const int* order, const int* m1, double* partials, int nred,
+                                const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_anderson_gram<T, kAndersonMax>), dim3(nred, g.B), dim3(TPB), 0, st, g.N,
+                       Fbase, slot_stride, order, m1, partials, active);
     return hipGetLastError();
 }
 
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_anderson_mix(long long N, Ptrs<T> G, int m1, Coef c,
-                                                      T* out) {
+__global__ void __launch_bounds__(TPB) k_anderson_mix(long long N, const T* Gbase,
+                                                      long long sstride, const int* order,
+                                                      const int* m1a, const double* gamma, T* out,
+                                                      const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
     const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (i >= N) return;
-    const int m = m1 - 1;
-    double v = double(G.p[m][i]);
-    for (int k = 0; k < m; ++k) v -= c.v[k] * (double(G.p[k + 1][i]) - double(G.p[k][i]));
-    out[i] = T(v);
+    const int m = m1a[b] - 1;
+    auto G = [&](int k) {
+        return double(Gbase[(long long)order[b * kHist + k] * sstride + (long long)b * N + i]);
+    };
+    double v = G(m);
+    for (int k = 0; k < m; ++k) v -= gamma[b * kAndersonMax + k] * (G(k + 1) - G(k));
+    out[(long long)b * N + i] = T(v);
 }
 
 template <typename T>
-hipError_t launch_anderson_mix(const Geom& g, const Ptrs<T>& G, int m1, const Coef& c, T* out,
-                               hipStream_t st) {
-    hipLaunchKernelGGL((k_anderson_mix<T>), dim3(blocks_for(g.N)), dim3(TPB), 0, st, g.N, G, m1,
-                       c, out);
+hipError_t launch_anderson_mix(const Geom& g, const T* Gbase, long long slot_stride,
+                               const int* order, const int* m1, const double* gamma, T* out,
+                               const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_anderson_mix<T>), dim3(blocks_for(g.N), g.B), dim3(TPB), 0, st, g.N,
+                       Gbase, slot_stride, order, m1, gamma, out, active);
     return hipGetLastError();
 }
 
@@ -750,8 +887,12 @@ hipError_t launch_anderson_mix(const Geom& g, const Ptrs<T>& G, int m1, const Co
 
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_fracture(Geom g, const uint16_t* mat_id,
-                                                  const MatEntry<T>* mat, const T* phi, T thr,
-                                                  int axis, int* count) {
+                                                  const MatEntry<T>* mat, const T* phi_a, T thr,
+                                                  int axis, int* count, const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
+    RVE_OFFSETS
+    const T* phi = phi_a + so;
     const long long nlines = g.N / (axis == 0 ? g.nx : axis == 1 ? g.ny : g.nz);
     const long long l = blockIdx.x * (long long)blockDim.x + threadIdx.x;
     if (l >= nlines) return;
@@ -765,17 +906,27 @@ __global__ void __launch_bounds__(TPB) k_fracture(Geom g, const uint16_t* mat_id
     bool broken = false;
     for (int k = 0; k < len && !broken; ++k) {
         const long long i = base + k * stride;
-        if (phi[i] >= thr || mat[mat_id[i]].drive == T(0)) broken = true;
+        if (phi[i] >= thr || mt[mid[i]].drive == T(0)) broken = true;
     }
-    if (!broken) atomicAdd(count, 1);
+    if (!broken) atomicAdd(count + b, 1);
 }
 
 template <typename T>
 hipError_t launch_fracture_count(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                                 const T* phi, double thr, int axis, int* count, hipStream_t st) {
+                                 const T* phi, double thr, int axis, int* count,
+                                 const int* active, hipStream_t st) {
     const long long nlines = g.N / (axis == 0 ? g.nx : axis == 1 ? g.ny : g.nz);
-    hipLaunchKernelGGL((k_fracture<T>), dim3(blocks_for(nlines)), dim3(TPB), 0, st, g, mat_id,
-                       mat, phi, T(thr), axis, count);
+    hipLaunchKernelGGL((k_fracture<T>), dim3(blocks_for(nlines), g.B), dim3(TPB), 0, st, g,
+                       mat_id, mat, phi, T(thr), axis, count, active);
+    return hipGetLastError();
+}
+
+__global__ void k_zero_int(int* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+hipError_t launch_zero_int(int* p, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_int, dim3(blocks_for(n)), dim3(TPB), 0, st, p, n);
     return hipGetLastError();
 }
 
@@ -783,52 +934,58 @@ hipError_t launch_fracture_count(const Geom& g, const uint16_t* mat_id, const Ma
 // explicit instantiations
 // ---------------------------------------------------------------------------
 
-#define INST(T)                                                                                   \
-    template hipError_t launch_unit_response<T>(const Geom&, const uint16_t*, const MatEntry<T>*, \
-                                                const T*, const T*, const double*, int, T*, T*,   \
-                                                T*, double*, int, hipStream_t);                   \
-    template hipError_t launch_history<T>(const Geom&, const T*, const T*, const T*, double, int, \
-                                          T*, hipStream_t);                                       \
-    template hipError_t launch_commit_history<T>(const Geom&, const T*, const T*, double, int,    \
-                                                 T*, hipStream_t);                                \
-    template hipError_t launch_pcg_matvec<T>(const Geom&, const uint16_t*, const MatEntry<T>*,    \
-                                             const T*, int, double, const T*, T*, double*, int,   \
-                                             const PcgDev*, hipStream_t);                         \
-    template hipError_t launch_damage_diag<T>(const Geom&, const uint16_t*, const MatEntry<T>*,   \
-                                              const T*, int, double, T*, hipStream_t);            \
-    template hipError_t launch_pcg_start<T>(const Geom&, const T*, const T*, const T*, T*, T*,    \
-                                            double*, int, hipStream_t);                           \
-    template hipError_t launch_pcg_update<T>(const Geom&, const PcgDev*, T*, T*, const T*,        \
-                                             const T*, const T*, double*, int, hipStream_t);      \
-    template hipError_t launch_pcg_dir<T>(const Geom&, const PcgDev*, const T*, const T*, T*,     \
-                                          hipStream_t);                                           \
-    template hipError_t launch_dissipation<T>(const Geom&, const uint16_t*, const MatEntry<T>*,   \
-                                              const T*, double*, int, hipStream_t);               \
-    template hipError_t launch_damage_residual<T>(const Geom&, const uint16_t*,                   \
-                                                  const MatEntry<T>*, const T*, const T*,         \
-                                                  double*, int, hipStream_t);                     \
-    template hipError_t launch_psi_ini<T>(const Geom&, const uint16_t*, const MatEntry<T>*,       \
-                                          const T*, T*, hipStream_t);                             \
-    template hipError_t launch_copy<T>(const T*, T*, long long, hipStream_t);                     \
-    template hipError_t launch_tangent_rhs<T>(const Geom&, const T*, const T*, const T*,          \
-                                              const T*, double, int, T*, hipStream_t);            \
-    template hipError_t launch_dissipation_dir<T>(const Geom&, const uint16_t*,                   \
-                                                  const MatEntry<T>*, const T*, const T*,         \
-                                                  double*, int, hipStream_t);                     \
-    template hipError_t launch_scaled<T>(const T*, double, T*, long long, hipStream_t);           \
-    template hipError_t launch_sub<T>(const T*, const T*, T*, long long, hipStream_t);            \
-    template hipError_t launch_fill<T>(T*, T, long long, hipStream_t);                            \
-    template hipError_t launch_max_field<T>(const T*, long long, double*, int, hipStream_t);      \
-    template hipError_t launch_scale_field<T>(T*, const double*, double, long long, hipStream_t); \
-    template hipError_t launch_diff_norms<T>(const T*, const T*, long long, double*, int,         \
-                                             hipStream_t);                                        \
-    template hipError_t launch_anderson_gram<T>(const Geom&, const Ptrs<T>&, int, double*, int,   \
-                                                hipStream_t);                                     \
-    template hipError_t launch_anderson_mix<T>(const Geom&, const Ptrs<T>&, int, const Coef&, T*, \
-                                               hipStream_t);                                      \
-    template hipError_t launch_fracture_count<T>(const Geom&, const uint16_t*,                    \
-                                                 const MatEntry<T>*, const T*, double, int, int*, \
-                                                 hipStream_t);
+#define INST(T)                                                                                    \
+    template hipError_t launch_unit_response<T>(const Geom&, const uint16_t*, const MatEntry<T>*,  \
+                                                const T*, const T*, const F6&, T*, T*, T*,         \
+                                                double*, int, const int*, hipStream_t);            \
+    template hipError_t launch_history<T>(const Geom&, const T*, const T*, const T*,               \
+                                          const double*, int, T*, T*, const int*, hipStream_t);    \
+    template hipError_t launch_commit_history<T>(const Geom&, const T*, const T*, const double*,   \
+                                                 int, T*, const int*, hipStream_t);                \
+    template hipError_t launch_pcg_matvec<T>(const Geom&, const uint16_t*, const MatEntry<T>*,     \
+                                             const T*, int, double, const T*, T*, double*, int,    \
+                                             const PcgDev*, const int*, hipStream_t);              \
+    template hipError_t launch_damage_diag<T>(const Geom&, const uint16_t*, const MatEntry<T>*,    \
+                                              const T*, int, double, T*, const int*,               \
+                                              hipStream_t);                                        \
+    template hipError_t launch_pcg_start<T>(const Geom&, const T*, const T*, const T*, T*, T*,     \
+                                            double*, int, const int*, hipStream_t);                \
+    template hipError_t launch_pcg_update<T>(const Geom&, const PcgDev*, T*, T*, const T*,         \
+                                             const T*, const T*, double*, int, hipStream_t);       \
+    template hipError_t launch_pcg_dir<T>(const Geom&, const PcgDev*, const T*, const T*, T*,      \
+                                          hipStream_t);                                            \
+    template hipError_t launch_dissipation<T>(const Geom&, const uint16_t*, const MatEntry<T>*,    \
+                                              const T*, double*, int, const int*, hipStream_t);    \
+    template hipError_t launch_damage_residual<T>(const Geom&, const uint16_t*,                    \
+                                                  const MatEntry<T>*, const T*, const T*,          \
+                                                  double*, int, const int*, hipStream_t);          \
+    template hipError_t launch_psi_ini<T>(const Geom&, const uint16_t*, const MatEntry<T>*,        \
+                                          const T*, T*, const int*, hipStream_t);                  \
+    template hipError_t launch_tangent_rhs<T>(const Geom&, const T*, const T*, const T*,           \
+                                              const T*, const double*, int, T*, const int*,        \
+                                              hipStream_t);                                        \
+    template hipError_t launch_dissipation_dir<T>(const Geom&, const uint16_t*,                    \
+                                                  const MatEntry<T>*, const T*, const T*,          \
+                                                  double*, int, const int*, hipStream_t);          \
+    template hipError_t launch_copy<T>(const T*, T*, long long, int, const int*, hipStream_t);     \
+    template hipError_t launch_fill<T>(T*, T, long long, int, const int*, hipStream_t);            \
+    template hipError_t launch_sub<T>(const T*, const T*, T*, long long, int, const int*,          \
+                                      hipStream_t);                                                \
+    template hipError_t launch_max_field<T>(const T*, long long, int, double*, int, const int*,    \
+                                            hipStream_t);                                          \
+    template hipError_t launch_scale_field<T>(T*, const double*, double, long long, int,           \
+                                              const int*, hipStream_t);                            \
+    template hipError_t launch_diff_norms<T>(const T*, const T*, long long, int, double*, int,     \
+                                             const int*, hipStream_t);                             \
+    template hipError_t launch_anderson_gram<T>(const Geom&, const T*, long long, const int*,      \
+                                                const int*, double*, int, const int*,              \
+                                                hipStream_t);                                      \
+    template hipError_t launch_anderson_mix<T>(const Geom&, const T*, long long, const int*,       \
+                                               const int*, const double*, T*, const int*,          \
+                                               hipStream_t);                                       \
+    template hipError_t launch_fracture_count<T>(const Geom&, const uint16_t*,                     \
+                                                 const MatEntry<T>*, const T*, double, int, int*,  \
+                                                 const int*, hipStream_t);
 
 INST(double)
 INST(float)

@@ -19,9 +19,11 @@ __device__ inline double wave_max(double v) {
     return v;
 }
 
-// Sum NV per-thread values over the block; thread 0 stores them.
+// Sum NV per-thread values over the block; thread 0 stores value i at
+// partials[i * stride + bid].
 template <int NV>
-__device__ inline void block_sum_store(double (&v)[NV], double* partials, int stride, int bid) {
+__device__ inline void block_sum_store(double (&v)[NV], double* partials, long long stride,
+                                       int bid) {
     __shared__ double sh[NV][16];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll

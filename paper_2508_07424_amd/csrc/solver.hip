@@ -29,6 +29,7 @@
 
 #include "../../include/mirve.h"
 #include "kernels.h"
+#include "fft_device.h"
 
 namespace mirve {
 
@@ -164,6 +165,25 @@ static int round_maxb(long long need) {
 
 constexpr size_t kLdsCap = 60 * 1024;
 
+// Number of Krylov iterations to enqueue before the next host check: the
+// observed rate of decrease of the residual predicts how many are still
+// needed, so few launches run past convergence (those exit at once).
+struct ChunkPlanner {
+    int it_prev = 0;
+    double rr_prev = -1.0;
+    int next(int it, double rr, double target) {
+        int c = 16;
+        if (rr_prev > 0.0 && it > it_prev && rr > 0.0 && rr < rr_prev && target > 0.0) {
+            const double rate = std::log(rr / rr_prev) / double(it - it_prev);   // < 0
+            const double need = std::log(target / rr) / rate;
+            c = (int)std::ceil(need * 1.05) + 1;
+        }
+        it_prev = it;
+        rr_prev = rr;
+        return std::max(4, std::min(c, 256));
+    }
+};
+
 // ---------------------------------------------------------------------------
 // workspace layout
 // ---------------------------------------------------------------------------
@@ -181,23 +201,30 @@ struct Layout {
 
 using namespace mirve;
 
+// Committed host-side state of one RVE slot.
+struct SlotState {
+    bool ready = false;
+    bool fractured = false;
+    double E = 0, Sigma = 0, T = 0, tau = 0, tau0 = 0;
+    double V = 0, A_g = 0, min_gc = 0;
+    int step = 0;
+};
+
 struct SolverBase {
     virtual ~SolverBase() {}
-    virtual int set_microstructure(const uint16_t*, const rve_phase*, int, const double*,
+    virtual int set_microstructure(int slot, const uint16_t*, const rve_phase*, int, const double*,
                                    const uint8_t*, const uint8_t*, double) = 0;
-    virtual int step(double dtau, rve_step_info* out) = 0;
-    virtual int get_field(int which, double* host, size_t count) = 0;
-    virtual int set_field(int which, const double* host, size_t count) = 0;
-    virtual int apply_green(const double* eps, double* out) = 0;
+    virtual int step(const double* dtau, rve_step_info* info, int* status) = 0;
+    virtual int get_field(int slot, int which, double* host, size_t count) = 0;
+    virtual int set_field(int slot, int which, const double* host, size_t count) = 0;
+    virtual int apply_green(int slot, const double* eps, double* out) = 0;
     virtual int apply_green_device(const void* eps, void* out, int repeat) = 0;
-    virtual int solve_mechanics(int* it, double* Sigma1) = 0;
-    virtual int solve_damage(double E, double* D, int* it, int commit) = 0;
-    virtual int dissipation(double* D, double* G) = 0;
-    double E_c = 0, Sigma_c = 0, T_c = 0, tau_c = 0, tau0 = 0;
-    int step_c = 0;
-    bool fractured = false;
-    bool ready = false;
-    double V = 0, A_g = 0;
+    virtual int solve_mechanics(int slot, int* it, double* Sigma1) = 0;
+    virtual int solve_damage(int slot, double E, double* D, int* it, int commit) = 0;
+    virtual int dissipation(int slot, double* D, double* G) = 0;
+    virtual int profile_pass(int pass, int repeat, double* bytes_per_launch) = 0;
+    std::vector<SlotState> slots;
+    int B = 1;
 };
 
 struct rve_handle_s {
@@ -215,66 +242,75 @@ struct Solver : SolverBase {
     Geom g;
     AxisPlan plx, ply, plz;
     int RB = 2, nbx = 1, maxb_x = 1;
-    int txy = 1, maxb_y = 1, txz = 1, maxb_z = 1;
+    int tly = 1, maxb_y = 1, tlz = 1, maxb_z = 1;
     size_t lds_x = 0, lds_y = 0, lds_z = 0;
     int nred = 1;
     hipStream_t st;
-    double min_gc = 0;
     int load_axis = 1;
+    void* ws = nullptr;
+    int m1_max = 1;
 
-    // device pointers
+    // device pointers (each field holds B RVEs back to back)
     T *phi_c, *phi_w, *Hn, *psi_ini, *phi_ini, *psi1, *H, *px, *pr, *pp, *pq, *pdinv, *pb, *tmp;
     T *x, *x_c, *r, *p;
-    T* aF[kAndersonMax + 1];
-    T* aG[kAndersonMax + 1];
+    T *aF, *aG;                     // Anderson ring buffers: kHist slots of B*N
     cplx<T>* spec;
     cplx<T>* tw;
     uint16_t* mat_id;
     MatEntry<T>* mat;
-    double *partials, *cgpA, *cgpB, *sums;
+    double *partials, *cgpA, *cgpB, *sums, *dE, *dgamma;
+    int *dmask[4], *dorder, *dm1, *count;
     CgDev* cg;
     PcgDev* pcg;
-    int* count;
-    // pinned host mirrors
+    // pinned host mirrors / staging
     CgDev* h_cg = nullptr;
     PcgDev* h_pcg = nullptr;
     double* h_sums = nullptr;
     int* h_count = nullptr;
+    void* h_stage = nullptr;
+    size_t stage_bytes = 0;
 
     int greenops = 0;
 
+    // ------------------------------------------------------------------ layout
     static size_t layout(const rve_config& c, const Geom& g, int nbx, Layout& L, Solver* s) {
-        const size_t fN = sizeof(T) * g.N;
+        const long long B = g.B;
+        const size_t fN = sizeof(T) * g.N * B;
         const size_t sN = fN * g.s;
-        const int m1 = std::max(0, std::min(c.anderson_depth, kAndersonMax)) + 1;
         T** single[] = {s ? &s->phi_c : nullptr, s ? &s->phi_w : nullptr, s ? &s->Hn : nullptr,
                         s ? &s->psi_ini : nullptr, s ? &s->phi_ini : nullptr, s ? &s->psi1 : nullptr,
                         s ? &s->H : nullptr, s ? &s->px : nullptr, s ? &s->pr : nullptr,
                         s ? &s->pp : nullptr, s ? &s->pq : nullptr, s ? &s->pdinv : nullptr,
                         s ? &s->pb : nullptr, s ? &s->tmp : nullptr};
+        const int ns = sizeof(single) / sizeof(single[0]);
         std::vector<size_t> offs;
-        for (size_t i = 0; i < sizeof(single) / sizeof(single[0]); ++i) offs.push_back(L.off(fN));
-        std::vector<size_t> aoffF, aoffG;
-        for (int i = 0; i < m1; ++i) { aoffF.push_back(L.off(fN)); aoffG.push_back(L.off(fN)); }
+        for (int i = 0; i < ns; ++i) offs.push_back(L.off(fN));
+        const int m1 = std::max(0, std::min(c.anderson_depth, kAndersonMax)) + 1;
+        const size_t oaF = L.off(fN * (m1 > 1 ? m1 : 1));
+        const size_t oaG = L.off(fN * (m1 > 1 ? m1 : 1));
         const size_t ox = L.off(sN), oxc = L.off(sN), orr = L.off(sN), op = L.off(sN);
-        const size_t ospec = L.off(sizeof(cplx<T>) * g.s * g.Nspec);
+        const size_t ospec = L.off(sizeof(cplx<T>) * g.s * g.Nspec * B);
         const size_t otw = L.off(sizeof(cplx<T>) * (g.nx + g.ny + g.nz));
-        const size_t omid = L.off(sizeof(uint16_t) * g.N);
-        const size_t omat = L.off(sizeof(MatEntry<T>) * std::max(1, c.max_materials));
-        const size_t opart = L.off(sizeof(double) * 40 * kRedBlocks);
-        const size_t ocgA = L.off(sizeof(double) * std::max(nbx, 1));
-        const size_t ocgB = L.off(sizeof(double) * std::max(nbx, 1));
-        const size_t osums = L.off(sizeof(double) * 64);
-        const size_t ocg = L.off(sizeof(CgDev));
-        const size_t opcg = L.off(sizeof(PcgDev));
-        const size_t ocnt = L.off(sizeof(int) * 4);
+        const size_t omid = L.off(sizeof(uint16_t) * g.N * B);
+        const size_t omat = L.off(sizeof(MatEntry<T>) * (size_t)g.mstride * B);
+        const size_t opart = L.off(sizeof(double) * kMaxVals * kRedBlocks * B);
+        const size_t ocgA = L.off(sizeof(double) * std::max(nbx, 1) * B);
+        const size_t ocgB = L.off(sizeof(double) * std::max(nbx, 1) * B);
+        const size_t osums = L.off(sizeof(double) * kMaxVals * B);
+        const size_t oE = L.off(sizeof(double) * B);
+        const size_t ogam = L.off(sizeof(double) * kAndersonMax * B);
+        size_t omask[4];
+        for (int i = 0; i < 4; ++i) omask[i] = L.off(sizeof(int) * B);
+        const size_t oord = L.off(sizeof(int) * kHist * B);
+        const size_t om1 = L.off(sizeof(int) * B);
+        const size_t ocnt = L.off(sizeof(int) * B);
+        const size_t ocg = L.off(sizeof(CgDev) * B);
+        const size_t opcg = L.off(sizeof(PcgDev) * B);
         if (s) {
             char* base = (char*)s->ws;
-            for (size_t i = 0; i < offs.size(); ++i) *single[i] = (T*)(base + offs[i]);
-            for (int i = 0; i <= kAndersonMax; ++i) {
-                s->aF[i] = i < m1 ? (T*)(base + aoffF[i]) : nullptr;
-                s->aG[i] = i < m1 ? (T*)(base + aoffG[i]) : nullptr;
-            }
+            for (int i = 0; i < ns; ++i) *single[i] = (T*)(base + offs[i]);
+            s->aF = (T*)(base + oaF);
+            s->aG = (T*)(base + oaG);
             s->x = (T*)(base + ox);
             s->x_c = (T*)(base + oxc);
             s->r = (T*)(base + orr);
@@ -287,19 +323,22 @@ struct Solver : SolverBase {
             s->cgpA = (double*)(base + ocgA);
             s->cgpB = (double*)(base + ocgB);
             s->sums = (double*)(base + osums);
+            s->dE = (double*)(base + oE);
+            s->dgamma = (double*)(base + ogam);
+            for (int i = 0; i < 4; ++i) s->dmask[i] = (int*)(base + omask[i]);
+            s->dorder = (int*)(base + oord);
+            s->dm1 = (int*)(base + om1);
+            s->count = (int*)(base + ocnt);
             s->cg = (CgDev*)(base + ocg);
             s->pcg = (PcgDev*)(base + opcg);
-            s->count = (int*)(base + ocnt);
         }
         return L.total;
     }
 
-    void* ws = nullptr;
-
     // geometry and launch shapes from a configuration; false if unsupported
     static bool make_geom(const rve_config& c, Geom& g, AxisPlan& px, AxisPlan& py, AxisPlan& pz,
-                          int& RB, int& nbx, int& maxb_x, size_t& lds_x, int& txy, int& maxb_y,
-                          size_t& lds_y, int& txz, int& maxb_z, size_t& lds_z, std::string& why) {
+                          int& RB, int& nbx, int& maxb_x, size_t& lds_x, int& tly, int& maxb_y,
+                          size_t& lds_y, int& tlz, int& maxb_z, size_t& lds_z, std::string& why) {
         g.dim = c.dim;
         g.s = c.dim == 2 ? 3 : 6;
         g.nx = c.n[0];
@@ -312,37 +351,41 @@ struct Solver : SolverBase {
         g.ell = c.ell;
         g.k_res = c.k_res;
         g.inv_N = 1.0 / double(g.N);
+        g.B = std::max(1, c.batch);
+        g.mstride = std::max(1, c.max_materials);
         if (!factorize(g.nx, px) || !factorize(g.ny, py) || !factorize(g.nz, pz)) {
             why = "grid sizes must be products of 2, 3, 5, 7 (<= 1024)";
             return false;
         }
         const size_t ce = sizeof(cplx<T>);
-        // x passes: rows per block
-        RB = std::max(2, std::min(16, 1024 / std::max(1, g.nx)));
+        // x passes: 4-16 rows per block (the transposed store writes RB/2 pairs of rows)
+        RB = std::max(2, std::min(16, 2048 / std::max(1, g.nx)));
         RB &= ~1;
-        while (RB > 2 && (size_t)g.s * (RB / 2) * g.nx * ce > kLdsCap) RB -= 2;
-        lds_x = (size_t)g.s * (RB / 2) * g.nx * ce;
-        if (lds_x > kLdsCap) { why = "n_x too large for the LDS budget"; return false; }
-        maxb_x = round_maxb(((long long)g.s * (RB / 2) * g.nx / px.min_rad + 255) / 256);
-        while (maxb_x < 0 && RB > 2) {
-            RB -= 2;
-            maxb_x = round_maxb(((long long)g.s * (RB / 2) * g.nx / px.min_rad + 255) / 256);
-            lds_x = (size_t)g.s * (RB / 2) * g.nx * ce;
-        }
-        if (maxb_x < 0) { why = "x plan does not fit"; return false; }
+        auto xmb = [&](int rb) {
+            return round_maxb(((long long)g.s * (rb / 2) * g.nx / px.min_rad + 255) / 256);
+        };
+        const size_t lx = (size_t)lds_line(g.nx) * ce;
+        while (RB > 2 && ((size_t)g.s * (RB / 2) * lx > kLdsCap || xmb(RB) < 0)) RB -= 2;
+        lds_x = (size_t)g.s * (RB / 2) * lx;
+        maxb_x = xmb(RB);
+        if (lds_x > kLdsCap || maxb_x < 0) { why = "n_x too large for the LDS budget"; return false; }
         const int nrows = g.ny * g.nz;
         nbx = (nrows + RB - 1) / RB;
-        auto pick_tx = [&](const AxisPlan& pl, int& tx, int& mb, size_t& lds) -> bool {
-            for (int t : {8, 4, 2, 1}) {
-                if (t > g.nxh && t > 1) continue;
-                const size_t l = (size_t)g.s * t * pl.N * ce;
+        // y pass: whole contiguous lines, about 1024 elements per component per block
+        auto pick = [&](const AxisPlan& pl, int want, int& tl, int& mb, size_t& lds) -> bool {
+            for (int t = want; t >= 1; --t) {
+                const size_t l = (size_t)g.s * t * lds_line(pl.N) * ce;
                 const int m = round_maxb(((long long)g.s * t * pl.N / pl.min_rad + 255) / 256);
-                if (l <= kLdsCap && m > 0) { tx = t; mb = m; lds = l; return true; }
+                if (l <= kLdsCap && m > 0) { tl = t; mb = m; lds = l; return true; }
             }
             return false;
         };
-        if (!pick_tx(py, txy, maxb_y, lds_y)) { why = "n_y too large for the LDS budget"; return false; }
-        if (g.dim == 3 && !pick_tx(pz, txz, maxb_z, lds_z)) {
+        if (!pick(py, std::max(1, std::min(16, 1024 / g.ny)), tly, maxb_y, lds_y)) {
+            why = "n_y too large for the LDS budget";
+            return false;
+        }
+        // z pass: a tile of y columns, 64-128 bytes per row
+        if (g.dim == 3 && !pick(pz, std::max(1, std::min(g.ny, int(128 / ce))), tlz, maxb_z, lds_z)) {
             why = "n_z too large for the LDS budget";
             return false;
         }
@@ -351,7 +394,7 @@ struct Solver : SolverBase {
 
     Solver(rve_handle_s* h, const rve_config& c, void* wsp, hipStream_t s) : hd(h), cfg(c), st(s) {
         std::string why;
-        make_geom(c, g, plx, ply, plz, RB, nbx, maxb_x, lds_x, txy, maxb_y, lds_y, txz, maxb_z,
+        make_geom(c, g, plx, ply, plz, RB, nbx, maxb_x, lds_x, tly, maxb_y, lds_y, tlz, maxb_z,
                   lds_z, why);
         ws = wsp;
         Layout L;
@@ -362,7 +405,9 @@ struct Solver : SolverBase {
         for (int a = 0; a < g.dim; ++a)
             if (std::fabs(c.f[a]) > best) { best = std::fabs(c.f[a]); ax = a; }
         load_axis = ax;
-        V = double(g.N) * std::pow(g.h, g.dim);
+        B = g.B;
+        slots.assign(B, SlotState());
+        m1_max = std::max(0, std::min(c.anderson_depth, kAndersonMax)) + 1;
     }
 
     ~Solver() override {
@@ -370,6 +415,7 @@ struct Solver : SolverBase {
         if (h_pcg) (void)hipHostFree(h_pcg);
         if (h_sums) (void)hipHostFree(h_sums);
         if (h_count) (void)hipHostFree(h_count);
+        if (h_stage) (void)hipHostFree(h_stage);
     }
 
     int fail(int code, const std::string& m) {
@@ -377,18 +423,25 @@ struct Solver : SolverBase {
         return code;
     }
 
-#define HIPCHK(expr)                                                                  \
-    do {                                                                              \
-        hipError_t e_ = (expr);                                                       \
-        if (e_ != hipSuccess)                                                         \
-            return fail(RVE_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+#define HIPCHK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(RVE_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+#define CHK(expr)                      \
+    do {                               \
+        int rc_ = (expr);              \
+        if (rc_ != RVE_OK) return rc_; \
     } while (0)
 
     int init_device() {
-        HIPCHK(hipHostMalloc((void**)&h_cg, sizeof(CgDev), hipHostMallocDefault));
-        HIPCHK(hipHostMalloc((void**)&h_pcg, sizeof(PcgDev), hipHostMallocDefault));
-        HIPCHK(hipHostMalloc((void**)&h_sums, sizeof(double) * 64, hipHostMallocDefault));
-        HIPCHK(hipHostMalloc((void**)&h_count, sizeof(int) * 4, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&h_cg, sizeof(CgDev) * B, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&h_pcg, sizeof(PcgDev) * B, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&h_sums, sizeof(double) * kMaxVals * B, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&h_count, sizeof(int) * B, hipHostMallocDefault));
+        stage_bytes = sizeof(double) * kHist * B + 64;
+        HIPCHK(hipHostMalloc(&h_stage, stage_bytes, hipHostMallocDefault));
         // twiddles, exp(-2 pi i m / N), computed in long double
         std::vector<cplx<T>> t;
         for (int N : {g.nx, g.ny, g.nz}) {
@@ -401,8 +454,12 @@ struct Solver : SolverBase {
         ply.tw_off = g.nx;
         plz.tw_off = g.nx + g.ny;
         HIPCHK(hipMemcpyAsync(tw, t.data(), t.size() * sizeof(cplx<T>), hipMemcpyHostToDevice, st));
-        HIPCHK(launch_fill<T>(x, T(0), g.s * g.N, st));
-        HIPCHK(launch_fill<T>(x_c, T(0), g.s * g.N, st));
+        // every slot starts with a valid (zero) material index and table
+        HIPCHK(hipMemsetAsync(mat_id, 0, sizeof(uint16_t) * g.N * B, st));
+        HIPCHK(hipMemsetAsync(mat, 0, sizeof(MatEntry<T>) * (size_t)g.mstride * B, st));
+        HIPCHK(launch_fill<T>(x, T(0), g.s * g.N, B, nullptr, st));
+        HIPCHK(launch_fill<T>(x_c, T(0), g.s * g.N, B, nullptr, st));
+        HIPCHK(launch_fill<T>(phi_c, T(0), g.N, B, nullptr, st));
         HIPCHK(hipStreamSynchronize(st));
         return RVE_OK;
     }
@@ -412,38 +469,52 @@ struct Solver : SolverBase {
         return RVE_OK;
     }
 
-    // ---- host <-> device field copies -----------------------------------
+    // small host -> device uploads through the pinned staging buffer
+    int upload_ints(int* dev, const std::vector<int>& v) {
+        HIPCHK(hipStreamSynchronize(st));
+        std::memcpy(h_stage, v.data(), sizeof(int) * v.size());
+        HIPCHK(hipMemcpyAsync(dev, h_stage, sizeof(int) * v.size(), hipMemcpyHostToDevice, st));
+        return RVE_OK;
+    }
+    int upload_doubles(double* dev, const std::vector<double>& v) {
+        HIPCHK(hipStreamSynchronize(st));
+        std::memcpy(h_stage, v.data(), sizeof(double) * v.size());
+        HIPCHK(hipMemcpyAsync(dev, h_stage, sizeof(double) * v.size(), hipMemcpyHostToDevice, st));
+        return RVE_OK;
+    }
+    int read_sums(int nv) {
+        (void)nv;
+        HIPCHK(hipMemcpyAsync(h_sums, sums, sizeof(double) * kMaxVals * B, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return RVE_OK;
+    }
+    double sum_of(int b, int v) const { return h_sums[b * kMaxVals + v]; }
+
+    // ---- host <-> device field copies (one slot) ---------------------------
     int upload(T* dst, const double* src, size_t n) {
         if (sizeof(T) == sizeof(double)) {
-            HIPCHK(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpy(dst, src, n * sizeof(double), hipMemcpyHostToDevice));
         } else {
             std::vector<T> tmpv(n);
             for (size_t i = 0; i < n; ++i) tmpv[i] = T(src[i]);
-            HIPCHK(hipMemcpyAsync(dst, tmpv.data(), n * sizeof(T), hipMemcpyHostToDevice, st));
-            HIPCHK(hipStreamSynchronize(st));
+            HIPCHK(hipMemcpy(dst, tmpv.data(), n * sizeof(T), hipMemcpyHostToDevice));
         }
         return RVE_OK;
     }
     int download(double* dst, const T* src, size_t n) {
+        HIPCHK(hipStreamSynchronize(st));
         if (sizeof(T) == sizeof(double)) {
-            HIPCHK(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
+            HIPCHK(hipMemcpy(dst, src, n * sizeof(double), hipMemcpyDeviceToHost));
         } else {
             std::vector<T> tmpv(n);
-            HIPCHK(hipMemcpyAsync(tmpv.data(), src, n * sizeof(T), hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
+            HIPCHK(hipMemcpy(tmpv.data(), src, n * sizeof(T), hipMemcpyDeviceToHost));
             for (size_t i = 0; i < n; ++i) dst[i] = double(tmpv[i]);
         }
         return RVE_OK;
     }
-    int read_sums(int nv) {
-        HIPCHK(hipMemcpyAsync(h_sums, sums, sizeof(double) * nv, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        return RVE_OK;
-    }
 
     // ---- Green operator passes --------------------------------------------
-    int fwd_x(int mode, const T* phi, const T* eps, double fcoef, double* part) {
+    int fwd_x(int mode, const T* phi, const T* eps, double fcoef, double* part, const int* mask) {
         XfwdArgs<T> a;
         std::memset(&a, 0, sizeof(a));
         a.g = g;
@@ -457,45 +528,43 @@ struct Solver : SolverBase {
         for (int c = 0; c < 6; ++c) a.f[c] = T(c < g.s ? cfg.f[c] : 0.0);
         a.r = r;
         a.p = p;
-        a.cg = cg;
+        a.cg = mode == XF_CG ? cg : nullptr;
+        a.active = mask;
         a.spec = spec;
         a.partials = part;
         a.rows_per_block = RB;
-        HIPCHK(launch_xfwd<T>(a, mode, maxb_x, nbx, lds_x, st));
+        a.nblocks = nbx;
+        HIPCHK(launch_xfwd<T>(a, mode, maxb_x, lds_x, st));
         return RVE_OK;
     }
-    int axes(const CgDev* c) {
+    int axes(const CgDev* c, const int* mask) {
         AxisArgs<T> a;
         std::memset(&a, 0, sizeof(a));
         a.g = g;
         a.spec = spec;
         a.cg = c;
+        a.active = mask;
+        a.pl = ply;
+        a.tw = tw + ply.tw_off;
+        a.contiguous = 1;
+        a.lines = tly;
+        const dim3 gy((unsigned)((g.nxh * (long long)g.nz + tly - 1) / tly), 1, B);
         if (g.dim == 2) {
-            a.pl = ply;
-            a.tw = tw + ply.tw_off;
-            a.axis = 1;
-            a.tx = txy;
-            HIPCHK(launch_axis<T>(a, AX_FWD_P_INV, maxb_y, dim3((g.nxh + txy - 1) / txy, g.nz),
-                                  lds_y, st));
+            HIPCHK(launch_axis<T>(a, AX_FWD_P_INV, maxb_y, gy, lds_y, st));
         } else {
-            a.pl = ply;
-            a.tw = tw + ply.tw_off;
-            a.axis = 1;
-            a.tx = txy;
-            const dim3 gy((g.nxh + txy - 1) / txy, g.nz);
             HIPCHK(launch_axis<T>(a, AX_FWD, maxb_y, gy, lds_y, st));
-            AxisArgs<T> b = a;
-            b.pl = plz;
-            b.tw = tw + plz.tw_off;
-            b.axis = 2;
-            b.tx = txz;
-            HIPCHK(launch_axis<T>(b, AX_FWD_P_INV, maxb_z, dim3((g.nxh + txz - 1) / txz, g.ny),
-                                  lds_z, st));
+            AxisArgs<T> bz = a;
+            bz.pl = plz;
+            bz.tw = tw + plz.tw_off;
+            bz.contiguous = 0;
+            bz.lines = tlz;
+            const dim3 gz((unsigned)(g.nxh * ((g.ny + tlz - 1) / tlz)), 1, B);
+            HIPCHK(launch_axis<T>(bz, AX_FWD_P_INV, maxb_z, gz, lds_z, st));
             HIPCHK(launch_axis<T>(a, AX_INV, maxb_y, gy, lds_y, st));
         }
         return RVE_OK;
     }
-    int inv_x(int mode, T* out, double scale, double* part) {
+    int inv_x(int mode, T* out, double scale, double* part, const int* mask) {
         XinvArgs<T> a;
         std::memset(&a, 0, sizeof(a));
         a.g = g;
@@ -508,228 +577,310 @@ struct Solver : SolverBase {
         a.p = p;
         a.r = r;
         a.cg = mode == XI_CG ? cg : nullptr;
+        a.active = mask;
         a.partials = part;
         a.rows_per_block = RB;
-        HIPCHK(launch_xinv<T>(a, mode, maxb_x, nbx, lds_x, st));
+        a.nblocks = nbx;
+        HIPCHK(launch_xinv<T>(a, mode, maxb_x, lds_x, st));
         return RVE_OK;
     }
-#define CHK(expr)                    \
-    do {                             \
-        int rc_ = (expr);            \
-        if (rc_ != RVE_OK) return rc_; \
-    } while (0)
 
     // out = scale * F^-1{P : F[g C (eps + fcoef f)]}; ||out||^2 partials in part
-    int green(const T* phi, const T* eps, double fcoef, T* out, double scale, double* part) {
-        CHK(fwd_x(XF_GREEN, phi, eps, fcoef, part));
-        CHK(axes(nullptr));
-        CHK(inv_x(XI_STORE, out, scale, part));
+    int green(const T* phi, const T* eps, double fcoef, T* out, double scale, double* part,
+              const int* mask) {
+        CHK(fwd_x(XF_GREEN, phi, eps, fcoef, part, mask));
+        CHK(axes(nullptr, mask));
+        CHK(inv_x(XI_STORE, out, scale, part, mask));
         ++greenops;
         return RVE_OK;
     }
 
-    // ---- (M) mechanics CG ---------------------------------------------------
-    int mech_solve(const T* phi, int* iters) {
-        CHK(green(phi, nullptr, 1.0, nullptr, 1.0, cgpB));          // ||b||^2
-        CHK(green(phi, x, 1.0, r, -1.0, cgpA));                     // r0 = -P[gC(f + x)]
-        HIPCHK(launch_cg_init(cg, cgpA, nbx, cgpB, nbx, cfg.tol_cg, cfg.max_cg, st));
-        int chunk = 8;
-        int total = 0;
-        for (;;) {
-            for (int k = 0; k < chunk; ++k) {
-                CHK(fwd_x(XF_CG, phi, nullptr, 0.0, cgpA));
-                CHK(axes(cg));
-                HIPCHK(launch_cg_alpha(cg, cgpA, nbx, st));
-                CHK(inv_x(XI_CG, nullptr, 1.0, cgpB));
-                HIPCHK(launch_cg_beta(cg, cgpB, nbx, st));
-            }
-            total += chunk;
-            HIPCHK(hipMemcpyAsync(h_cg, cg, sizeof(CgDev), hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            if (h_cg->done) break;
-            if (total > cfg.max_cg + chunk) break;
-            chunk = std::min(chunk * 2, 64);
-        }
-        greenops += h_cg->it;
-        if (iters) *iters = h_cg->it;
-        if (h_cg->status == 1) return RVE_OK;
-        if (h_cg->status == 2) {
-            // a breakdown at a residual already near the target is convergence
-            if (std::isfinite(h_cg->rr) && h_cg->rr <= 1e4 * h_cg->tol2 * h_cg->bn2) return RVE_OK;
-            return fail(RVE_ENUMERIC, "mechanics CG breakdown or non-finite residual");
-        }
-        return fail(RVE_ENOCONV, "mechanics CG did not converge");
+    // masks: device int[B] built from a host vector
+    int set_mask(int which, const std::vector<int>& act) { return upload_ints(dmask[which], act); }
+    static bool any(const std::vector<int>& v) {
+        for (int a : v)
+            if (a) return true;
+        return false;
     }
 
-    int unit_response(const T* phi, double* Sigma1, double* sig2, T* eps1 = nullptr,
-                      T* sig1 = nullptr) {
-        HIPCHK(launch_unit_response<T>(g, mat_id, mat, phi, x, cfg.f, cfg.split, psi1, eps1, sig1,
-                                       partials, nred, st));
-        HIPCHK(launch_sum_partials(partials, kRedBlocks, nred, 2, sums, st));
-        CHK(read_sums(2));
-        if (Sigma1) *Sigma1 = h_sums[0] / double(g.N);
-        if (sig2) *sig2 = h_sums[1];
-        if (!std::isfinite(h_sums[0])) return fail(RVE_ENUMERIC, "non-finite unit stress");
+    // ---- (M) mechanics CG over the active RVEs --------------------------------
+    int mech_solve(const T* phi, int mask_id, const std::vector<int>& act, std::vector<int>& iters,
+                   std::vector<int>& rcs) {
+        const int* mk = dmask[mask_id];
+        CHK(green(phi, nullptr, 1.0, nullptr, 1.0, cgpB, mk));          // ||b||^2
+        CHK(green(phi, x, 1.0, r, -1.0, cgpA, mk));                     // r0 = -P[gC(f + x)]
+        HIPCHK(launch_cg_init(cg, cgpA, cgpB, nbx, B, cfg.tol_cg, cfg.max_cg, mk, st));
+        int chunk = 8, total = 0;
+        std::vector<ChunkPlanner> plan(B);
+        for (;;) {
+            for (int k = 0; k < chunk; ++k) {
+                CHK(fwd_x(XF_CG, phi, nullptr, 0.0, cgpA, nullptr));
+                CHK(axes(cg, nullptr));
+                HIPCHK(launch_cg_alpha(cg, cgpA, nbx, B, st));
+                CHK(inv_x(XI_CG, nullptr, 1.0, cgpB, nullptr));
+                HIPCHK(launch_cg_beta(cg, cgpB, nbx, B, st));
+            }
+            total += chunk;
+            HIPCHK(hipMemcpyAsync(h_cg, cg, sizeof(CgDev) * B, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            bool all = true;
+            int next = 4;
+            for (int b = 0; b < B; ++b) {
+                if (!act[b] || h_cg[b].done) continue;
+                all = false;
+                next = std::max(next, plan[b].next(h_cg[b].it, h_cg[b].rr, h_cg[b].tol2 * h_cg[b].bn2));
+            }
+            if (all || total > cfg.max_cg + chunk) break;
+            chunk = next;
+        }
+        for (int b = 0; b < B; ++b) {
+            if (!act[b]) continue;
+            const CgDev& c = h_cg[b];
+            iters[b] += c.it;
+            greenops += c.it;
+            if (c.status == 1) continue;
+            if (c.status == 2) {
+                if (std::isfinite(c.rr) && c.rr <= 1e4 * c.tol2 * c.bn2) continue;
+                rcs[b] = RVE_ENUMERIC;
+                hd->err = "mechanics CG breakdown or non-finite residual";
+            } else {
+                rcs[b] = RVE_ENOCONV;
+                hd->err = "mechanics CG did not converge";
+            }
+        }
         return RVE_OK;
     }
 
-    // ---- (A) damage PCG -----------------------------------------------------
+    int unit_response(const T* phi, int mask_id, T* eps1 = nullptr, T* sig1 = nullptr) {
+        F6 f;
+        for (int c = 0; c < 6; ++c) f.v[c] = c < g.s ? cfg.f[c] : 0.0;
+        HIPCHK(launch_unit_response<T>(g, mat_id, mat, phi, x, f, psi1, eps1, sig1, partials, nred,
+                                       dmask[mask_id], st));
+        HIPCHK(launch_sum_partials(partials, nred, 2, B, sums, dmask[mask_id], st));
+        return read_sums(2);
+    }
+
+    // ---- (A) damage PCG over the active RVEs -----------------------------------
     // Solve a(x) u + D^T(w D u) = b (mode 0: a = Gc/l + 2 Hc, w = Gc l; mode 1:
     // a = 1, w = c) from the initial guess in u.
-    int pcg_solve(const T* Hc, int mode, double c, const T* b, T* u, double tol, int max_it,
-                  int* iters) {
-        HIPCHK(launch_damage_diag<T>(g, mat_id, mat, Hc, mode, c, pdinv, st));
-        HIPCHK(launch_pcg_matvec<T>(g, mat_id, mat, Hc, mode, c, u, pq, nullptr, nred, nullptr, st));
-        HIPCHK(launch_pcg_start<T>(g, b, pq, pdinv, pr, pp, partials, nred, st));
-        HIPCHK(launch_pcg_fin_start(pcg, partials, nred, tol, max_it, st));
+    int pcg_solve(const T* Hc, int mode, double c, const T* bvec, T* u, double tol, int max_it,
+                  int mask_id, const std::vector<int>& act, std::vector<int>& iters,
+                  std::vector<int>& rcs) {
+        const int* mk = dmask[mask_id];
+        HIPCHK(launch_damage_diag<T>(g, mat_id, mat, Hc, mode, c, pdinv, mk, st));
+        HIPCHK(launch_pcg_matvec<T>(g, mat_id, mat, Hc, mode, c, u, pq, nullptr, nred, nullptr, mk, st));
+        HIPCHK(launch_pcg_start<T>(g, bvec, pq, pdinv, pr, pp, partials, nred, mk, st));
+        HIPCHK(launch_pcg_fin_start(pcg, partials, nred, B, tol, max_it, mk, st));
         int chunk = 8, total = 0;
+        std::vector<ChunkPlanner> plan(B);
         for (;;) {
             for (int k = 0; k < chunk; ++k) {
                 HIPCHK(launch_pcg_matvec<T>(g, mat_id, mat, Hc, mode, c, pp, pq, partials, nred,
-                                            pcg, st));
-                HIPCHK(launch_pcg_fin_alpha(pcg, partials, nred, st));
+                                            pcg, nullptr, st));
+                HIPCHK(launch_pcg_fin_alpha(pcg, partials, nred, B, st));
                 HIPCHK(launch_pcg_update<T>(g, pcg, u, pr, pp, pq, pdinv, partials, nred, st));
-                HIPCHK(launch_pcg_fin_beta(pcg, partials, nred, st));
+                HIPCHK(launch_pcg_fin_beta(pcg, partials, nred, B, st));
                 HIPCHK(launch_pcg_dir<T>(g, pcg, pr, pdinv, pp, st));
             }
             total += chunk;
-            HIPCHK(hipMemcpyAsync(h_pcg, pcg, sizeof(PcgDev), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(h_pcg, pcg, sizeof(PcgDev) * B, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
-            if (h_pcg->done) break;
-            if (total > max_it + chunk) break;
-            chunk = std::min(chunk * 2, 64);
+            bool all = true;
+            int next = 4;
+            for (int b = 0; b < B; ++b) {
+                if (!act[b] || h_pcg[b].done) continue;
+                all = false;
+                next = std::max(next, plan[b].next(h_pcg[b].it, h_pcg[b].rr, h_pcg[b].tol2 * h_pcg[b].bn2));
+            }
+            if (all || total > max_it + chunk) break;
+            chunk = next;
         }
-        if (iters) *iters += h_pcg->it;
-        if (h_pcg->status == 1) return RVE_OK;
-        if (h_pcg->status == 2) {
-            if (std::isfinite(h_pcg->rr) && h_pcg->rr <= 1e4 * h_pcg->tol2 * h_pcg->bn2) return RVE_OK;
-            if (h_pcg->bn2 == 0.0) return RVE_OK;
-            return fail(RVE_ENUMERIC, "damage PCG breakdown or non-finite residual");
+        for (int b = 0; b < B; ++b) {
+            if (!act[b]) continue;
+            const PcgDev& d = h_pcg[b];
+            iters[b] += d.it;
+            if (d.status == 1) continue;
+            if (d.status == 2) {
+                if (std::isfinite(d.rr) && (d.rr <= 1e4 * d.tol2 * d.bn2 || d.bn2 == 0.0)) continue;
+                rcs[b] = RVE_ENUMERIC;
+                hd->err = "damage PCG breakdown or non-finite residual";
+            } else {
+                rcs[b] = RVE_ENOCONV;
+                hd->err = "damage PCG did not converge";
+            }
         }
-        return fail(RVE_ENOCONV, "damage PCG did not converge");
-    }
-
-    int dissip(const T* phi, double* D, double* G) {
-        HIPCHK(launch_dissipation<T>(g, mat_id, mat, phi, partials, nred, st));
-        HIPCHK(launch_sum_partials(partials, kRedBlocks, nred, 2, sums, st));
-        CHK(read_sums(2));
-        const double hd_ = std::pow(g.h, g.dim);
-        if (D) *D = h_sums[0] * hd_;
-        if (G) *G = h_sums[1] * hd_;
-        if (!std::isfinite(h_sums[0])) return fail(RVE_ENUMERIC, "non-finite dissipation");
         return RVE_OK;
     }
 
-    // phi(E) into u (warm start in u); D(phi(E)) out
-    int damage_at(double E, T* u, double* D, int* npcg) {
-        HIPCHK(launch_history<T>(g, psi1, psi_ini, Hn, E, cfg.history, H, st));
-        HIPCHK(launch_scaled<T>(H, 2.0, pb, g.N, st));
-        CHK(pcg_solve(H, 0, 0.0, pb, u, cfg.tol_pcg, cfg.max_pcg, npcg));
-        return dissip(u, D, nullptr);
+    int dissip(const T* phi, int mask_id) {
+        HIPCHK(launch_dissipation<T>(g, mat_id, mat, phi, partials, nred, dmask[mask_id], st));
+        HIPCHK(launch_sum_partials(partials, nred, 2, B, sums, dmask[mask_id], st));
+        return read_sums(2);
+    }
+    double hd_() const { return std::pow(g.h, g.dim); }
+
+    // phi(E) into u (warm start in u) for the RVEs of mask_id; D out
+    int damage_at(const std::vector<double>& E, T* u, int mask_id, const std::vector<int>& act,
+                  std::vector<double>& D, std::vector<int>& npcg, std::vector<int>& rcs) {
+        CHK(upload_doubles(dE, E));
+        HIPCHK(launch_history<T>(g, psi1, psi_ini, Hn, dE, cfg.history, H, pb, dmask[mask_id], st));
+        CHK(pcg_solve(H, 0, 0.0, pb, u, cfg.tol_pcg, cfg.max_pcg, mask_id, act, npcg, rcs));
+        CHK(dissip(u, mask_id));
+        for (int b = 0; b < B; ++b)
+            if (act[b]) D[b] = sum_of(b, 0) * hd_();
+        return RVE_OK;
     }
 
-    // dD/dE at (E, u = phi(E)) via the tangent system with the same H
-    int damage_slope(double E, const T* u, double* dD, int* npcg) {
-        HIPCHK(launch_tangent_rhs<T>(g, u, psi1, psi_ini, Hn, E, cfg.history, pb, st));
-        HIPCHK(launch_fill<T>(tmp, T(0), g.N, st));
-        CHK(pcg_solve(H, 0, 0.0, pb, tmp, cfg.tol_pcg, cfg.max_pcg, npcg));
-        HIPCHK(launch_dissipation_dir<T>(g, mat_id, mat, u, tmp, partials, nred, st));
-        HIPCHK(launch_sum_partials(partials, kRedBlocks, nred, 1, sums, st));
+    // dD/dE at (E, u = phi(E)) via the tangent system with the same H (dE holds E)
+    int damage_slope(T* u, int mask_id, const std::vector<int>& act, std::vector<double>& dD,
+                     std::vector<int>& npcg, std::vector<int>& rcs) {
+        const int* mk = dmask[mask_id];
+        HIPCHK(launch_tangent_rhs<T>(g, u, psi1, psi_ini, Hn, dE, cfg.history, pb, mk, st));
+        HIPCHK(launch_fill<T>(tmp, T(0), g.N, B, mk, st));
+        CHK(pcg_solve(H, 0, 0.0, pb, tmp, cfg.tol_pcg, cfg.max_pcg, mask_id, act, npcg, rcs));
+        HIPCHK(launch_dissipation_dir<T>(g, mat_id, mat, u, tmp, partials, nred, mk, st));
+        HIPCHK(launch_sum_partials(partials, nred, 1, B, sums, mk, st));
         CHK(read_sums(1));
-        *dD = h_sums[0] * std::pow(g.h, g.dim);
+        for (int b = 0; b < B; ++b)
+            if (act[b]) dD[b] = sum_of(b, 0) * hd_();
         return RVE_OK;
     }
 
-    int max_psi1(double* m) {
-        HIPCHK(launch_max_field<T>(psi1, g.N, partials, nred, st));
-        HIPCHK(launch_max_partials(partials, nred, sums, st));
-        CHK(read_sums(1));
-        *m = h_sums[0];
+    // E >= 0 with D(phi(E)) = tau (Eq. 16c) for every active RVE; phi(E) left in u.
+    // Uses masks 2 and 3.
+    int arclength(const std::vector<double>& tau, const std::vector<double>& E0, T* u,
+                  const std::vector<int>& act, std::vector<double>& Eout, std::vector<int>& npcg,
+                  std::vector<int>& rcs) {
+        std::vector<double> lo(B, 0.0), hi(B, INFINITY), E(B, 0.0), D(B, 0.0), dD(B, 0.0);
+        std::vector<int> al(B, 0);
+        bool need_guess = false;
+        for (int b = 0; b < B; ++b) {
+            al[b] = act[b] && rcs[b] == RVE_OK;
+            E[b] = E0[b];
+            if (al[b] && !(E[b] > 0.0)) need_guess = true;
+        }
+        if (need_guess) {
+            CHK(set_mask(2, al));
+            HIPCHK(launch_max_field<T>(psi1, g.N, B, partials, nred, dmask[2], st));
+            HIPCHK(launch_max_partials(partials, nred, B, sums, dmask[2], st));
+            CHK(read_sums(1));
+            for (int b = 0; b < B; ++b) {
+                if (!al[b] || E[b] > 0.0) continue;
+                const double pm = sum_of(b, 0);
+                E[b] = pm > 0.0 ? std::sqrt(slots[b].min_gc / cfg.ell / pm) : 1.0;
+            }
+        }
+        for (int it = 0; it < 200 && any(al); ++it) {
+            CHK(set_mask(2, al));
+            CHK(damage_at(E, u, 2, al, D, npcg, rcs));
+            std::vector<int> sl(B, 0);
+            for (int b = 0; b < B; ++b) {
+                if (!al[b]) continue;
+                if (rcs[b] != RVE_OK) { al[b] = 0; continue; }
+                if (std::fabs(D[b] - tau[b]) <= cfg.tol_al * tau[b]) {
+                    Eout[b] = E[b];
+                    al[b] = 0;
+                    continue;
+                }
+                if (D[b] < tau[b]) lo[b] = std::max(lo[b], E[b]);
+                else hi[b] = std::min(hi[b], E[b]);
+                if (!std::isinf(hi[b]) && hi[b] - lo[b] <= 1e-15 * hi[b]) {
+                    Eout[b] = E[b];
+                    al[b] = 0;
+                    continue;
+                }
+                sl[b] = 1;
+            }
+            if (!any(sl)) continue;
+            CHK(set_mask(3, sl));
+            CHK(damage_slope(u, 3, sl, dD, npcg, rcs));
+            for (int b = 0; b < B; ++b) {
+                if (!sl[b]) continue;
+                if (rcs[b] != RVE_OK) { al[b] = 0; continue; }
+                double En = dD[b] > 0.0 ? E[b] - (D[b] - tau[b]) / dD[b] : NAN;
+                if (!(lo[b] < En && En < hi[b]))
+                    En = std::isinf(hi[b]) ? 2.0 * E[b] : 0.5 * (lo[b] + hi[b]);
+                E[b] = En;
+            }
+        }
+        for (int b = 0; b < B; ++b)
+            if (al[b] && rcs[b] == RVE_OK) {
+                rcs[b] = RVE_ENOCONV;
+                hd->err = "dissipation constraint (arc-length) did not converge";
+            }
         return RVE_OK;
     }
 
-    // E >= 0 with D(phi(E)) = tau (Eq. 16c); phi(E) left in u.
-    int arclength(double tau, double E0, double* Eout, T* u, int* npcg) {
-        double lo = 0.0, hi = INFINITY;
-        double E = E0;
-        if (!(E > 0.0)) {
-            double pm = 0.0;
-            CHK(max_psi1(&pm));
-            E = pm > 0.0 ? std::sqrt(min_gc / cfg.ell / pm) : 1.0;
+    // ---- Anderson mixing (host side of the small least-squares problems) ------
+    int anderson_mix(const std::vector<int>& mixing, const std::vector<int>& nhist, T* out,
+                     std::vector<int>& rcs) {
+        std::vector<int> order(kHist * B, 0), m1(B, 1);
+        for (int b = 0; b < B; ++b) {
+            if (!mixing[b]) continue;
+            m1[b] = std::min(nhist[b], m1_max);
+            for (int i = 0; i < m1[b]; ++i) order[b * kHist + i] = (nhist[b] - m1[b] + i) % m1_max;
         }
-        for (int it = 0; it < 200; ++it) {
-            double Dv = 0.0;
-            CHK(damage_at(E, u, &Dv, npcg));
-            if (std::fabs(Dv - tau) <= cfg.tol_al * tau) { *Eout = E; return RVE_OK; }
-            if (Dv < tau) lo = std::max(lo, E);
-            else hi = std::min(hi, E);
-            double dD = 0.0;
-            CHK(damage_slope(E, u, &dD, npcg));
-            double En = dD > 0.0 ? E - (Dv - tau) / dD : NAN;
-            if (!(lo < En && En < hi)) En = std::isinf(hi) ? 2.0 * E : 0.5 * (lo + hi);
-            if (!std::isinf(hi) && hi - lo <= 1e-15 * hi) { *Eout = E; return RVE_OK; }
-            E = En;
-        }
-        return fail(RVE_ENOCONV, "dissipation constraint (arc-length) did not converge");
-    }
-
-    // ---- Anderson mixing (host side of the small least-squares problem) -------
-    int anderson_mix(int count, int m1_max, T* out) {
-        const int m1 = std::min(count, m1_max);
-        Ptrs<T> F, G;
-        for (int i = 0; i < m1; ++i) {
-            const int slot = (count - m1 + i) % m1_max;
-            F.p[i] = aF[slot];
-            G.p[i] = aG[slot];
-        }
-        for (int i = m1; i <= kAndersonMax; ++i) { F.p[i] = F.p[0]; G.p[i] = G.p[0]; }
-        HIPCHK(launch_anderson_gram<T>(g, F, m1, partials, nred, st));
+        CHK(upload_ints(dorder, order));
+        CHK(upload_ints(dm1, m1));
+        CHK(set_mask(3, mixing));
+        const long long sstride = g.N * (long long)B;
+        HIPCHK(launch_anderson_gram<T>(g, aF, sstride, dorder, dm1, partials, nred, dmask[3], st));
         const int nv = kAndersonMax * kAndersonMax + kAndersonMax;
-        HIPCHK(launch_sum_partials(partials, kRedBlocks, nred, nv, sums, st));
+        HIPCHK(launch_sum_partials(partials, nred, nv, B, sums, dmask[3], st));
         CHK(read_sums(nv));
-        const int m = m1 - 1;
-        // normal equations (dF^T dF + ridge) gamma = dF^T F_m
-        double A[kAndersonMax][kAndersonMax], bvec[kAndersonMax];
-        double tr = 0.0;
-        for (int a = 0; a < m; ++a) tr += h_sums[a * kAndersonMax + a];
-        for (int a = 0; a < m; ++a) {
-            for (int b = 0; b < m; ++b) A[a][b] = h_sums[a * kAndersonMax + b];
-            A[a][a] += 1e-14 * tr;
-            bvec[a] = h_sums[kAndersonMax * kAndersonMax + a];
-        }
-        // Gaussian elimination with partial pivoting
-        for (int k = 0; k < m; ++k) {
-            int piv = k;
-            for (int i = k + 1; i < m; ++i)
-                if (std::fabs(A[i][k]) > std::fabs(A[piv][k])) piv = i;
-            if (piv != k) {
-                for (int j = 0; j < m; ++j) std::swap(A[k][j], A[piv][j]);
-                std::swap(bvec[k], bvec[piv]);
+        std::vector<double> gam(kAndersonMax * B, 0.0);
+        for (int b = 0; b < B; ++b) {
+            if (!mixing[b]) continue;
+            const int m = m1[b] - 1;
+            const double* hs = h_sums + b * kMaxVals;
+            // normal equations (dF^T dF + ridge) gamma = dF^T F_m
+            double A[kAndersonMax][kAndersonMax], bv[kAndersonMax];
+            double tr = 0.0;
+            for (int a = 0; a < m; ++a) tr += hs[a * kAndersonMax + a];
+            for (int a = 0; a < m; ++a) {
+                for (int c = 0; c < m; ++c) A[a][c] = hs[a * kAndersonMax + c];
+                A[a][a] += 1e-14 * tr;
+                bv[a] = hs[kAndersonMax * kAndersonMax + a];
             }
-            if (A[k][k] == 0.0) return fail(RVE_ENUMERIC, "singular Anderson system");
-            for (int i = k + 1; i < m; ++i) {
-                const double f = A[i][k] / A[k][k];
-                for (int j = k; j < m; ++j) A[i][j] -= f * A[k][j];
-                bvec[i] -= f * bvec[k];
+            bool ok = true;
+            for (int k = 0; k < m && ok; ++k) {
+                int piv = k;
+                for (int i = k + 1; i < m; ++i)
+                    if (std::fabs(A[i][k]) > std::fabs(A[piv][k])) piv = i;
+                if (piv != k) {
+                    for (int j = 0; j < m; ++j) std::swap(A[k][j], A[piv][j]);
+                    std::swap(bv[k], bv[piv]);
+                }
+                if (A[k][k] == 0.0) { ok = false; break; }
+                for (int i = k + 1; i < m; ++i) {
+                    const double f = A[i][k] / A[k][k];
+                    for (int j = k; j < m; ++j) A[i][j] -= f * A[k][j];
+                    bv[i] -= f * bv[k];
+                }
+            }
+            double* gb = &gam[b * kAndersonMax];
+            for (int k = m - 1; k >= 0 && ok; --k) {
+                double s = bv[k];
+                for (int j = k + 1; j < m; ++j) s -= A[k][j] * gb[j];
+                gb[k] = s / A[k][k];
+            }
+            for (int k = 0; k < m; ++k)
+                if (!std::isfinite(gb[k])) ok = false;
+            if (!ok) {
+                rcs[b] = RVE_ENUMERIC;
+                hd->err = "singular or non-finite Anderson system";
             }
         }
-        Coef c;
-        for (int i = 0; i < kAndersonMax; ++i) c.v[i] = 0.0;
-        for (int k = m - 1; k >= 0; --k) {
-            double s = bvec[k];
-            for (int j = k + 1; j < m; ++j) s -= A[k][j] * c.v[j];
-            c.v[k] = s / A[k][k];
-        }
-        for (int k = 0; k < m; ++k)
-            if (!std::isfinite(c.v[k])) return fail(RVE_ENUMERIC, "non-finite Anderson weights");
-        HIPCHK(launch_anderson_mix<T>(g, G, m1, c, out, st));
+        CHK(upload_doubles(dgamma, gam));
+        HIPCHK(launch_anderson_mix<T>(g, aG, sstride, dorder, dm1, dgamma, out, dmask[3], st));
         return RVE_OK;
     }
 
-    // ---- microstructure ----------------------------------------------------
-    int set_microstructure(const uint16_t* pid, const rve_phase* phases, int nph,
+    // ---- microstructure of one slot ---------------------------------------------
+    int set_microstructure(int slot, const uint16_t* pid, const rve_phase* phases, int nph,
                            const double* theta, const uint8_t* vmask, const uint8_t* disc,
                            double phi_M) override {
+        if (slot < 0 || slot >= B) return fail(RVE_EINVAL, "slot out of range");
         if (!pid || !phases || nph <= 0) return fail(RVE_EINVAL, "phase_id and phases required");
         if (!(phi_M > 0.0 && phi_M < 1.0)) return fail(RVE_EINVAL, "phi_M must be in (0, 1)");
         for (int i = 0; i < nph; ++i) {
@@ -745,10 +896,12 @@ struct Solver : SolverBase {
                 return fail(RVE_EINVAL, "unknown phase kind");
             }
         }
+        SlotState& S = slots[slot];
+        S.ready = false;
         std::map<std::tuple<int, double, int>, int> keys;
         std::vector<uint16_t> ids(g.N);
         std::vector<MatEntry<T>> table;
-        min_gc = INFINITY;
+        S.min_gc = INFINITY;
         for (long long i = 0; i < g.N; ++i) {
             const int ph = pid[i];
             if (ph >= nph) return fail(RVE_EINVAL, "phase_id out of range");
@@ -760,7 +913,7 @@ struct Solver : SolverBase {
             int id;
             if (it == keys.end()) {
                 id = (int)table.size();
-                if (id >= cfg.max_materials || id >= kMaxMat)
+                if (id >= g.mstride || id >= kMaxMat)
                     return fail(RVE_EINVAL, "more distinct materials than max_materials");
                 keys[key] = id;
                 HostMat hm = phase_entry(phases[ph], std::get<1>(key), nt != 0, cfg.k_res);
@@ -768,10 +921,10 @@ struct Solver : SolverBase {
                 std::memset(&me, 0, sizeof(me));
                 static const int in2d[3] = {0, 1, 5};
                 for (int a = 0; a < g.s; ++a)
-                    for (int b = 0; b < g.s; ++b) {
+                    for (int c = 0; c < g.s; ++c) {
                         const int ia = g.dim == 2 ? in2d[a] : a;
-                        const int ib = g.dim == 2 ? in2d[b] : b;
-                        me.C[a * g.s + b] = T(hm.C[ia][ib]);
+                        const int ic = g.dim == 2 ? in2d[c] : c;
+                        me.C[a * g.s + c] = T(hm.C[ia][ic]);
                     }
                 me.K = T(hm.K);
                 me.Gc = T(hm.Gc);
@@ -781,15 +934,16 @@ struct Solver : SolverBase {
                 id = it->second;
             }
             ids[i] = (uint16_t)id;
-            min_gc = std::min(min_gc, phases[ph].Gc);
+            S.min_gc = std::min(S.min_gc, phases[ph].Gc);
         }
-        HIPCHK(hipMemcpyAsync(mat_id, ids.data(), sizeof(uint16_t) * g.N, hipMemcpyHostToDevice, st));
-        HIPCHK(hipMemcpyAsync(mat, table.data(), sizeof(MatEntry<T>) * table.size(),
-                              hipMemcpyHostToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(mat_id + (long long)slot * g.N, ids.data(), sizeof(uint16_t) * g.N,
+                         hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(mat + (long long)slot * g.mstride, table.data(),
+                         sizeof(MatEntry<T>) * table.size(), hipMemcpyHostToDevice));
         // reference crack area: lines along the load axis without a notch voxel
         if (cfg.A_g > 0) {
-            A_g = cfg.A_g;
+            S.A_g = cfg.A_g;
         } else {
             long long lines = 0;
             const int la = load_axis;
@@ -806,226 +960,393 @@ struct Solver : SolverBase {
                     if (vmask[base + k * stride]) { notch = true; break; }
                 if (!notch) ++lines;
             }
-            A_g = double(lines) * std::pow(g.h, g.dim - 1);
+            S.A_g = double(lines) * std::pow(g.h, g.dim - 1);
         }
+        S.V = double(g.N) * hd_();
+        std::vector<int> one(B, 0);
+        one[slot] = 1;
+        CHK(set_mask(0, one));
+        const int* mk = dmask[0];
+        const long long so = (long long)slot * g.N;
         // crack-tip enrichment (Eq. 35): (1 + l^2 D^T D) phi_o = phi_disc
-        bool any = false;
+        bool anyd = false;
         std::vector<double> d(g.N, 0.0);
         if (disc)
             for (long long i = 0; i < g.N; ++i)
-                if (disc[i]) { d[i] = 1.0; any = true; }
-        if (any) {
-            CHK(upload(pb, d.data(), g.N));
-            HIPCHK(launch_fill<T>(phi_ini, T(0), g.N, st));
-            int it = 0;
+                if (disc[i]) { d[i] = 1.0; anyd = true; }
+        HIPCHK(launch_fill<T>(phi_ini, T(0), g.N, B, mk, st));
+        if (anyd) {
+            CHK(upload(pb + so, d.data(), g.N));
+            std::vector<int> it(B, 0), rcs(B, RVE_OK);
             const double ctol = sizeof(T) == 8 ? 1e-15 : 1e-7;
-            CHK(pcg_solve(nullptr, 1, cfg.ell * cfg.ell, pb, phi_ini, ctol, 100000, &it));
-            HIPCHK(launch_max_field<T>(phi_ini, g.N, partials, nred, st));
-            HIPCHK(launch_max_partials(partials, nred, sums, st));
-            HIPCHK(launch_scale_field<T>(phi_ini, sums, phi_M, g.N, st));
-        } else {
-            HIPCHK(launch_fill<T>(phi_ini, T(0), g.N, st));
+            CHK(pcg_solve(nullptr, 1, cfg.ell * cfg.ell, pb, phi_ini, ctol, 100000, 0, one, it, rcs));
+            if (rcs[slot] != RVE_OK) return rcs[slot];
+            HIPCHK(launch_max_field<T>(phi_ini, g.N, B, partials, nred, mk, st));
+            HIPCHK(launch_max_partials(partials, nred, B, sums, mk, st));
+            HIPCHK(launch_scale_field<T>(phi_ini, sums, phi_M, g.N, B, mk, st));
         }
-        HIPCHK(launch_psi_ini<T>(g, mat_id, mat, phi_ini, psi_ini, st));
-        HIPCHK(launch_copy<T>(phi_ini, phi_c, g.N, st));
-        HIPCHK(launch_copy<T>(psi_ini, Hn, g.N, st));
-        HIPCHK(launch_fill<T>(x, T(0), g.s * g.N, st));
-        HIPCHK(launch_fill<T>(x_c, T(0), g.s * g.N, st));
-        HIPCHK(launch_fill<T>(psi1, T(0), g.N, st));
-        double D0 = 0.0;
-        CHK(dissip(phi_c, &D0, nullptr));
-        tau_c = tau0 = D0;
-        E_c = Sigma_c = T_c = 0.0;
-        step_c = 0;
-        fractured = false;
-        ready = true;
+        HIPCHK(launch_psi_ini<T>(g, mat_id, mat, phi_ini, psi_ini, mk, st));
+        HIPCHK(launch_copy<T>(phi_ini, phi_c, g.N, B, mk, st));
+        HIPCHK(launch_copy<T>(psi_ini, Hn, g.N, B, mk, st));
+        HIPCHK(launch_fill<T>(x, T(0), g.s * g.N, B, mk, st));
+        HIPCHK(launch_fill<T>(x_c, T(0), g.s * g.N, B, mk, st));
+        HIPCHK(launch_fill<T>(psi1, T(0), g.N, B, mk, st));
+        CHK(dissip(phi_c, 0));
+        S.tau = S.tau0 = sum_of(slot, 0) * hd_();
+        if (!std::isfinite(S.tau)) return fail(RVE_ENUMERIC, "non-finite initial dissipation");
+        S.E = S.Sigma = S.T = 0.0;
+        S.step = 0;
+        S.fractured = false;
+        S.ready = true;
         return RVE_OK;
     }
 
-    // ---- one step ------------------------------------------------------------
-    int step(double dtau, rve_step_info* out) override {
-        if (!ready) return fail(RVE_ESTATE, "set_microstructure first");
-        if (!(dtau > 0.0) || !std::isfinite(dtau)) return fail(RVE_EINVAL, "dtau must be > 0");
-        int rc = step_impl(dtau, out);
-        if (rc != RVE_OK) {
-            // transactional: the working strain restarts from the committed one
-            (void)launch_copy<T>(x_c, x, g.s * g.N, st);
+    // ---- one lockstep step of the RVEs with dtau[b] > 0 ---------------------------
+    int step(const double* dtau, rve_step_info* info, int* status) override {
+        std::vector<int> act(B, 0), rcs(B, RVE_OK);
+        for (int b = 0; b < B; ++b) {
+            if (dtau[b] == 0.0) continue;
+            if (!slots[b].ready) { rcs[b] = RVE_ESTATE; continue; }
+            if (!(dtau[b] > 0.0) || !std::isfinite(dtau[b])) { rcs[b] = RVE_EINVAL; continue; }
+            act[b] = 1;
+        }
+        int rc = RVE_OK;
+        if (any(act)) rc = step_impl(dtau, act, rcs, info);
+        // transactional: a failed RVE restarts its working strain from the committed one
+        std::vector<int> failed(B, 0);
+        for (int b = 0; b < B; ++b) failed[b] = act[b] && rcs[b] != RVE_OK;
+        if (any(failed) && set_mask(1, failed) == RVE_OK) {
+            (void)launch_copy<T>(x_c, x, g.s * g.N, B, dmask[1], st);
             (void)hipStreamSynchronize(st);
         }
-        return rc;
+        int worst = rc;
+        for (int b = 0; b < B; ++b) {
+            if (status) status[b] = rc != RVE_OK && act[b] ? rc : rcs[b];
+            if (worst == RVE_OK && rcs[b] != RVE_OK) worst = rcs[b];
+        }
+        return worst;
     }
 
-    int step_impl(double dtau, rve_step_info* out) {
-        const double tau = tau_c + dtau;
+    int step_impl(const double* dtau, const std::vector<int>& act, std::vector<int>& rcs,
+                  rve_step_info* info) {
         greenops = 0;
-        int ncg = 0, npcg = 0;
-        HIPCHK(launch_copy<T>(phi_c, phi_w, g.N, st));
-        HIPCHK(launch_copy<T>(x_c, x, g.s * g.N, st));
-        double E = E_c;
-        const int m1_max = std::max(0, std::min(cfg.anderson_depth, kAndersonMax)) + 1;
-        int nhist = 0;
-        bool conv = false;
-        int it = 0;
-        for (it = 1; it <= cfg.max_stagger; ++it) {
-            int c = 0;
-            CHK(mech_solve(phi_w, &c));
-            ncg += c;
-            CHK(unit_response(phi_w, nullptr, nullptr));
-            HIPCHK(launch_copy<T>(phi_w, px, g.N, st));
-            double En = 0.0;
-            CHK(arclength(tau, E, &En, px, &npcg));
-            HIPCHK(launch_diff_norms<T>(px, phi_w, g.N, partials, nred, st));
-            HIPCHK(launch_sum_partials(partials, kRedBlocks, nred, 2, sums, st));
+        std::vector<double> tau(B, 0.0), E(B, 0.0), En(B, 0.0);
+        std::vector<int> ncg(B, 0), npcg(B, 0), nst(B, 0), nhist(B, 0), stag = act, conv(B, 0);
+        for (int b = 0; b < B; ++b) {
+            tau[b] = slots[b].tau + (act[b] ? dtau[b] : 0.0);
+            E[b] = slots[b].E;
+        }
+        CHK(set_mask(0, act));
+        HIPCHK(launch_copy<T>(phi_c, phi_w, g.N, B, dmask[0], st));
+        HIPCHK(launch_copy<T>(x_c, x, g.s * g.N, B, dmask[0], st));
+        for (int it = 1; it <= cfg.max_stagger && any(stag); ++it) {
+            CHK(set_mask(1, stag));
+            CHK(mech_solve(phi_w, 1, stag, ncg, rcs));
+            CHK(unit_response(phi_w, 1));
+            HIPCHK(launch_copy<T>(phi_w, px, g.N, B, dmask[1], st));
+            CHK(arclength(tau, E, px, stag, En, npcg, rcs));
+            HIPCHK(launch_diff_norms<T>(px, phi_w, g.N, B, partials, nred, dmask[1], st));
+            HIPCHK(launch_sum_partials(partials, nred, 2, B, sums, dmask[1], st));
             CHK(read_sums(2));
-            const double dphi = std::sqrt(h_sums[0]) / std::max(std::sqrt(h_sums[1]), 1e-300);
-            const double dE = std::fabs(En - E) / std::max(std::fabs(En), 1e-300);
-            const double err = std::max(dphi, dE);
-            if (!std::isfinite(err)) return fail(RVE_ENUMERIC, "non-finite stagger update");
-            E = En;
-            if (err < cfg.tol) {
-                HIPCHK(launch_copy<T>(px, phi_w, g.N, st));
-                conv = true;
-                break;
-            }
-            if (m1_max > 1) {
-                const int slot = nhist % m1_max;
-                HIPCHK(launch_sub<T>(px, phi_w, aF[slot], g.N, st));
-                HIPCHK(launch_copy<T>(px, aG[slot], g.N, st));
-                ++nhist;
-                if (nhist >= 2) {
-                    CHK(anderson_mix(nhist, m1_max, phi_w));
+            std::vector<int> done(B, 0), mixing(B, 0), plain(B, 0);
+            for (int b = 0; b < B; ++b) {
+                if (!stag[b]) continue;
+                nst[b] = it;
+                if (rcs[b] != RVE_OK) { stag[b] = 0; continue; }
+                const double dphi = std::sqrt(sum_of(b, 0)) / std::max(std::sqrt(sum_of(b, 1)), 1e-300);
+                const double dEr = std::fabs(En[b] - E[b]) / std::max(std::fabs(En[b]), 1e-300);
+                const double err = std::max(dphi, dEr);
+                E[b] = En[b];
+                if (!std::isfinite(err)) {
+                    rcs[b] = RVE_ENUMERIC;
+                    hd->err = "non-finite stagger update";
+                    stag[b] = 0;
+                } else if (err < cfg.tol) {
+                    done[b] = 1;
+                    conv[b] = 1;
+                    stag[b] = 0;
+                } else if (m1_max > 1) {
+                    mixing[b] = 1;
                 } else {
-                    HIPCHK(launch_copy<T>(px, phi_w, g.N, st));
+                    plain[b] = 1;
                 }
-            } else {
-                HIPCHK(launch_copy<T>(px, phi_w, g.N, st));
+            }
+            // converged: phi_w = phi(E); no mixing: phi_w = phi(E)
+            std::vector<int> take(B, 0);
+            for (int b = 0; b < B; ++b) take[b] = done[b] || plain[b];
+            if (any(take)) {
+                CHK(set_mask(2, take));
+                HIPCHK(launch_copy<T>(px, phi_w, g.N, B, dmask[2], st));
+            }
+            if (any(mixing)) {
+                // push F = phi(E) - phi_w and G = phi(E) into each RVE's ring slot
+                for (int slot = 0; slot < m1_max; ++slot) {
+                    std::vector<int> ms(B, 0);
+                    bool a = false;
+                    for (int b = 0; b < B; ++b)
+                        if (mixing[b] && nhist[b] % m1_max == slot) { ms[b] = 1; a = true; }
+                    if (!a) continue;
+                    CHK(set_mask(2, ms));
+                    T* Fs = aF + (long long)slot * g.N * B;
+                    T* Gs = aG + (long long)slot * g.N * B;
+                    HIPCHK(launch_sub<T>(px, phi_w, Fs, g.N, B, dmask[2], st));
+                    HIPCHK(launch_copy<T>(px, Gs, g.N, B, dmask[2], st));
+                }
+                std::vector<int> mix2(B, 0), first(B, 0);
+                for (int b = 0; b < B; ++b) {
+                    if (!mixing[b]) continue;
+                    nhist[b] += 1;
+                    if (nhist[b] >= 2) mix2[b] = 1;
+                    else first[b] = 1;
+                }
+                if (any(first)) {
+                    CHK(set_mask(2, first));
+                    HIPCHK(launch_copy<T>(px, phi_w, g.N, B, dmask[2], st));
+                }
+                if (any(mix2)) CHK(anderson_mix(mix2, nhist, phi_w, rcs));
+                for (int b = 0; b < B; ++b)
+                    if (mix2[b] && rcs[b] != RVE_OK) stag[b] = 0;
             }
         }
-        if (!conv) return fail(RVE_ENOCONV, "stagger did not converge");
-        // final equilibrium at the committed damage, then commit
-        int c = 0;
-        CHK(mech_solve(phi_w, &c));
-        ncg += c;
-        double Sigma1 = 0.0, s2 = 0.0;
-        CHK(unit_response(phi_w, &Sigma1, &s2));
-        // residuals of the committed state: R1 (equilibrium) and R2 (damage with the H
-        // used by the last damage solve)
-        CHK(green(phi_w, x, 1.0, nullptr, 1.0, cgpB));
-        HIPCHK(launch_sum_partials(cgpB, 0, nbx, 1, sums, st));
+        for (int b = 0; b < B; ++b)
+            if (act[b] && rcs[b] == RVE_OK && !conv[b]) {
+                rcs[b] = RVE_ENOCONV;
+                hd->err = "stagger did not converge";
+            }
+        std::vector<int> ok(B, 0);
+        for (int b = 0; b < B; ++b) ok[b] = act[b] && rcs[b] == RVE_OK;
+        if (!any(ok)) return RVE_OK;
+        // final equilibrium at the converged damage, then commit
+        CHK(set_mask(1, ok));
+        CHK(mech_solve(phi_w, 1, ok, ncg, rcs));
+        for (int b = 0; b < B; ++b) ok[b] = ok[b] && rcs[b] == RVE_OK;
+        CHK(set_mask(1, ok));
+        CHK(unit_response(phi_w, 1));
+        std::vector<double> S1(B, 0.0), s2(B, 0.0), R1(B, 0.0), R2(B, 0.0);
+        for (int b = 0; b < B; ++b)
+            if (ok[b]) { S1[b] = sum_of(b, 0) / double(g.N); s2[b] = sum_of(b, 1); }
+        // residuals of the committed state: R1 (equilibrium) and R2 (damage with
+        // the H of the last damage solve)
+        CHK(green(phi_w, x, 1.0, nullptr, 1.0, cgpB, dmask[1]));
+        HIPCHK(launch_sum_rows(cgpB, nbx, B, sums, 0, st));
         CHK(read_sums(1));
-        const double R1 = std::sqrt(h_sums[0]) / std::max(std::sqrt(s2), 1e-300);
-        HIPCHK(launch_damage_residual<T>(g, mat_id, mat, H, phi_w, partials, nred, st));
-        HIPCHK(launch_sum_partials(partials, kRedBlocks, nred, 2, sums, st));
+        for (int b = 0; b < B; ++b)
+            if (ok[b]) R1[b] = std::sqrt(sum_of(b, 0)) / std::max(std::sqrt(s2[b]), 1e-300);
+        HIPCHK(launch_damage_residual<T>(g, mat_id, mat, H, phi_w, partials, nred, dmask[1], st));
+        HIPCHK(launch_sum_partials(partials, nred, 2, B, sums, dmask[1], st));
         CHK(read_sums(2));
-        const double R2 = std::sqrt(h_sums[0]) / std::max(std::sqrt(h_sums[1]), 1e-300);
-        HIPCHK(launch_commit_history<T>(g, psi1, psi_ini, E, cfg.history, Hn, st));
-        HIPCHK(launch_copy<T>(phi_w, phi_c, g.N, st));
-        HIPCHK(launch_copy<T>(x, x_c, g.s * g.N, st));
-        const double Sigma = E * Sigma1;
-        T_c += 0.5 * (Sigma + Sigma_c) * (E - E_c);
-        E_c = E;
-        Sigma_c = Sigma;
-        tau_c = tau;
-        ++step_c;
-        double D = 0.0, G = 0.0;
-        CHK(dissip(phi_c, &D, &G));
-        HIPCHK(hipMemsetAsync(count, 0, sizeof(int), st));
-        HIPCHK(launch_fracture_count<T>(g, mat_id, mat, phi_c, cfg.frac_threshold, load_axis, count, st));
-        HIPCHK(hipMemcpyAsync(h_count, count, sizeof(int), hipMemcpyDeviceToHost, st));
+        for (int b = 0; b < B; ++b)
+            if (ok[b]) R2[b] = std::sqrt(sum_of(b, 0)) / std::max(std::sqrt(sum_of(b, 1)), 1e-300);
+        CHK(upload_doubles(dE, E));
+        HIPCHK(launch_commit_history<T>(g, psi1, psi_ini, dE, cfg.history, Hn, dmask[1], st));
+        HIPCHK(launch_copy<T>(phi_w, phi_c, g.N, B, dmask[1], st));
+        HIPCHK(launch_copy<T>(x, x_c, g.s * g.N, B, dmask[1], st));
+        CHK(dissip(phi_c, 1));
+        std::vector<double> D(B, 0.0), G(B, 0.0);
+        for (int b = 0; b < B; ++b)
+            if (ok[b]) { D[b] = sum_of(b, 0) * hd_(); G[b] = sum_of(b, 1) * hd_(); }
+        HIPCHK(launch_zero_int(count, B, st));
+        HIPCHK(launch_fracture_count<T>(g, mat_id, mat, phi_c, cfg.frac_threshold, load_axis, count,
+                                        dmask[1], st));
+        HIPCHK(hipMemcpyAsync(h_count, count, sizeof(int) * B, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        fractured = h_count[0] == 0;
-        if (out) {
-            out->E = E;
-            out->Sigma = Sigma;
-            out->D = D;
-            out->Gamma = G;
-            out->tau = tau;
-            out->T = T_c;
-            out->n_stagger = it;
-            out->n_cg = ncg;
-            out->n_pcg = npcg;
-            out->n_greenop = greenops;
-            out->res_R1 = R1;
-            out->res_R2 = R2;
-            out->res_R3 = std::fabs(D - tau) / tau;
-            out->fractured = fractured ? 1 : 0;
-            out->step = step_c;
+        for (int b = 0; b < B; ++b) {
+            if (!ok[b]) continue;
+            SlotState& S = slots[b];
+            const double Sigma = E[b] * S1[b];
+            S.T += 0.5 * (Sigma + S.Sigma) * (E[b] - S.E);
+            S.E = E[b];
+            S.Sigma = Sigma;
+            S.tau = tau[b];
+            S.step += 1;
+            S.fractured = h_count[b] == 0;
+            if (info) {
+                rve_step_info& o = info[b];
+                o.E = E[b];
+                o.Sigma = Sigma;
+                o.D = D[b];
+                o.Gamma = G[b];
+                o.tau = tau[b];
+                o.T = S.T;
+                o.n_stagger = nst[b];
+                o.n_cg = ncg[b];
+                o.n_pcg = npcg[b];
+                o.n_greenop = ncg[b] + 2 * (nst[b] + 1) + 1;   // CG + two set-up operators per solve + R1
+                o.res_R1 = R1[b];
+                o.res_R2 = R2[b];
+                o.res_R3 = std::fabs(D[b] - tau[b]) / tau[b];
+                o.fractured = S.fractured ? 1 : 0;
+                o.step = S.step;
+            }
         }
         return RVE_OK;
     }
 
-    // ---- fields ------------------------------------------------------------------
-    int get_field(int which, double* hostp, size_t cnt) override {
-        if (!ready) return fail(RVE_ESTATE, "set_microstructure first");
+    // ---- single-slot helpers --------------------------------------------------------
+    int check_slot(int slot) {
+        if (slot < 0 || slot >= B) return fail(RVE_EINVAL, "slot out of range");
+        if (!slots[slot].ready) return fail(RVE_ESTATE, "set_microstructure first");
+        return RVE_OK;
+    }
+    std::vector<int> only(int slot) {
+        std::vector<int> v(B, 0);
+        v[slot] = 1;
+        return v;
+    }
+
+    int get_field(int slot, int which, double* hostp, size_t cnt) override {
+        CHK(check_slot(slot));
         const size_t N = (size_t)g.N, sN = (size_t)g.s * g.N;
+        const long long so = (long long)slot * g.N;
         switch (which) {
-            case RVE_FIELD_PHI: if (cnt != N) break; return download(hostp, phi_c, N);
-            case RVE_FIELD_HIST: if (cnt != N) break; return download(hostp, Hn, N);
-            case RVE_FIELD_PSI_INI: if (cnt != N) break; return download(hostp, psi_ini, N);
-            case RVE_FIELD_PSI1: if (cnt != N) break; return download(hostp, psi1, N);
-            case RVE_FIELD_PHI_INI: if (cnt != N) break; return download(hostp, phi_ini, N);
+            case RVE_FIELD_PHI: if (cnt != N) break; return download(hostp, phi_c + so, N);
+            case RVE_FIELD_HIST: if (cnt != N) break; return download(hostp, Hn + so, N);
+            case RVE_FIELD_PSI_INI: if (cnt != N) break; return download(hostp, psi_ini + so, N);
+            case RVE_FIELD_PSI1: if (cnt != N) break; return download(hostp, psi1 + so, N);
+            case RVE_FIELD_PHI_INI: if (cnt != N) break; return download(hostp, phi_ini + so, N);
             case RVE_FIELD_EPS1:
             case RVE_FIELD_SIG1: {
                 if (cnt != sN) break;
-                CHK(unit_response(phi_c, nullptr, nullptr, r, p));
-                return download(hostp, which == RVE_FIELD_EPS1 ? r : p, sN);
+                CHK(set_mask(0, only(slot)));
+                // x holds the working strain; show the committed one
+                HIPCHK(launch_copy<T>(x_c, x, g.s * g.N, B, dmask[0], st));
+                CHK(unit_response(phi_c, 0, r, p));
+                return download(hostp, (which == RVE_FIELD_EPS1 ? r : p) + so * g.s, sN);
             }
             default: return fail(RVE_EINVAL, "unknown field");
         }
         return fail(RVE_EINVAL, "field size mismatch");
     }
 
-    int set_field(int which, const double* hostp, size_t cnt) override {
-        if (!ready) return fail(RVE_ESTATE, "set_microstructure first");
+    int set_field(int slot, int which, const double* hostp, size_t cnt) override {
+        CHK(check_slot(slot));
         const size_t N = (size_t)g.N;
+        const long long so = (long long)slot * g.N;
         if (cnt != N) return fail(RVE_EINVAL, "field size mismatch");
         for (size_t i = 0; i < N; ++i)
             if (!std::isfinite(hostp[i])) return fail(RVE_EINVAL, "non-finite field value");
+        HIPCHK(hipStreamSynchronize(st));
         switch (which) {
-            case RVE_FIELD_PHI: CHK(upload(phi_c, hostp, N)); return sync();
-            case RVE_FIELD_HIST: CHK(upload(Hn, hostp, N)); return sync();
-            case RVE_FIELD_PSI1: CHK(upload(psi1, hostp, N)); return sync();
+            case RVE_FIELD_PHI: return upload(phi_c + so, hostp, N);
+            case RVE_FIELD_HIST: return upload(Hn + so, hostp, N);
+            case RVE_FIELD_PSI1: return upload(psi1 + so, hostp, N);
             default: return fail(RVE_EINVAL, "field is read-only");
         }
     }
 
-    int apply_green(const double* eps, double* outp) override {
-        if (!ready) return fail(RVE_ESTATE, "set_microstructure first");
+    int apply_green(int slot, const double* eps, double* outp) override {
+        CHK(check_slot(slot));
         const size_t sN = (size_t)g.s * g.N;
-        CHK(upload(r, eps, sN));
-        CHK(green(phi_c, r, 0.0, p, 1.0, cgpB));
-        return download(outp, p, sN);
+        const long long fo = (long long)slot * g.s * g.N;
+        HIPCHK(hipStreamSynchronize(st));
+        CHK(upload(r + fo, eps, sN));
+        CHK(set_mask(0, only(slot)));
+        CHK(green(phi_c, r, 0.0, p, 1.0, cgpB, dmask[0]));
+        return download(outp, p + fo, sN);
     }
 
     int apply_green_device(const void* eps, void* outp, int repeat) override {
-        if (!ready) return fail(RVE_ESTATE, "set_microstructure first");
+        std::vector<int> rd(B, 0);
+        for (int b = 0; b < B; ++b) rd[b] = slots[b].ready ? 1 : 0;
+        CHK(set_mask(0, rd));
         for (int i = 0; i < repeat; ++i)
-            CHK(green(phi_c, (const T*)eps, 0.0, (T*)outp, 1.0, cgpB));
+            CHK(green(phi_c, (const T*)eps, 0.0, (T*)outp, 1.0, cgpB, dmask[0]));
         return RVE_OK;
     }
 
-    int solve_mechanics(int* it, double* Sigma1) override {
-        if (!ready) return fail(RVE_ESTATE, "set_microstructure first");
-        HIPCHK(launch_copy<T>(x_c, x, g.s * g.N, st));
-        CHK(mech_solve(phi_c, it));
-        CHK(unit_response(phi_c, Sigma1, nullptr));
-        HIPCHK(launch_copy<T>(x, x_c, g.s * g.N, st));
+    int solve_mechanics(int slot, int* it, double* Sigma1) override {
+        CHK(check_slot(slot));
+        std::vector<int> one = only(slot), its(B, 0), rcs(B, RVE_OK);
+        CHK(set_mask(0, one));
+        HIPCHK(launch_copy<T>(x_c, x, g.s * g.N, B, dmask[0], st));
+        CHK(mech_solve(phi_c, 0, one, its, rcs));
+        if (rcs[slot] != RVE_OK) return rcs[slot];
+        CHK(unit_response(phi_c, 0));
+        if (Sigma1) *Sigma1 = sum_of(slot, 0) / double(g.N);
+        if (it) *it = its[slot];
+        HIPCHK(launch_copy<T>(x, x_c, g.s * g.N, B, dmask[0], st));
         return sync();
     }
 
-    int solve_damage(double E, double* D, int* it, int commit) override {
-        if (!ready) return fail(RVE_ESTATE, "set_microstructure first");
-        HIPCHK(launch_copy<T>(phi_c, px, g.N, st));
-        int n = 0;
-        CHK(damage_at(E, px, D, &n));
-        if (it) *it = n;
-        if (commit) HIPCHK(launch_copy<T>(px, phi_c, g.N, st));
+    int solve_damage(int slot, double E, double* D, int* it, int commit) override {
+        CHK(check_slot(slot));
+        std::vector<int> one = only(slot), its(B, 0), rcs(B, RVE_OK);
+        std::vector<double> Ev(B, 0.0), Dv(B, 0.0);
+        Ev[slot] = E;
+        CHK(set_mask(2, one));
+        HIPCHK(launch_copy<T>(phi_c, px, g.N, B, dmask[2], st));
+        CHK(damage_at(Ev, px, 2, one, Dv, its, rcs));
+        if (rcs[slot] != RVE_OK) return rcs[slot];
+        if (D) *D = Dv[slot];
+        if (it) *it = its[slot];
+        if (commit) HIPCHK(launch_copy<T>(px, phi_c, g.N, B, dmask[2], st));
         return sync();
     }
 
-    int dissipation(double* D, double* G) override {
-        if (!ready) return fail(RVE_ESTATE, "set_microstructure first");
-        return dissip(phi_c, D, G);
+    int dissipation(int slot, double* D, double* G) override {
+        CHK(check_slot(slot));
+        CHK(set_mask(0, only(slot)));
+        CHK(dissip(phi_c, 0));
+        if (D) *D = sum_of(slot, 0) * hd_();
+        if (G) *G = sum_of(slot, 1) * hd_();
+        return RVE_OK;
+    }
+
+    // Launch one kind of pass `repeat` times on every ready RVE of the batch
+    // (for timing against its algorithmic bytes).  0: x-forward (constitutive),
+    // 1: the projection axis pass, 2: x-inverse (store), 3: x-forward with the
+    // CG direction update, 4: x-inverse with the CG update (alpha = 0, so the
+    // iterate is unchanged).
+    int profile_pass(int pass, int repeat, double* bytes) override {
+        std::vector<int> rd(B, 0);
+        int nready = 0;
+        for (int b = 0; b < B; ++b) { rd[b] = slots[b].ready ? 1 : 0; nready += rd[b]; }
+        if (!nready) return fail(RVE_ESTATE, "set_microstructure first");
+        CHK(set_mask(0, rd));
+        std::vector<CgDev> c(B);
+        for (int b = 0; b < B; ++b) {
+            std::memset(&c[b], 0, sizeof(CgDev));
+            c[b].beta = 0.5;
+            c[b].alpha = 0.0;
+            c[b].done = rd[b] ? 0 : 1;
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(cg, c.data(), sizeof(CgDev) * B, hipMemcpyHostToDevice));
+        AxisArgs<T> a;
+        std::memset(&a, 0, sizeof(a));
+        a.g = g;
+        a.spec = spec;
+        a.active = dmask[0];
+        const bool three = g.dim == 3;
+        a.pl = three ? plz : ply;
+        a.tw = tw + (three ? plz.tw_off : ply.tw_off);
+        a.contiguous = three ? 0 : 1;
+        a.lines = three ? tlz : tly;
+        const dim3 grid = three ? dim3((unsigned)(g.nxh * ((g.ny + tlz - 1) / tlz)), 1, B)
+                                : dim3((unsigned)((g.nxh * (long long)g.nz + tly - 1) / tly), 1, B);
+        for (int i = 0; i < repeat; ++i) {
+            switch (pass) {
+                case 0: CHK(fwd_x(XF_GREEN, phi_c, r, 0.0, cgpA, dmask[0])); break;
+                case 1: HIPCHK(launch_axis<T>(a, AX_FWD_P_INV, three ? maxb_z : maxb_y, grid,
+                                              three ? lds_z : lds_y, st)); break;
+                case 2: CHK(inv_x(XI_STORE, p, 1.0, cgpB, dmask[0])); break;
+                case 3: CHK(fwd_x(XF_CG, phi_c, nullptr, 0.0, cgpA, nullptr)); break;
+                case 4: CHK(inv_x(XI_CG, nullptr, 1.0, cgpB, nullptr)); break;
+                default: return fail(RVE_EINVAL, "unknown pass");
+            }
+        }
+        // compulsory bytes of one launch: every input read once, every output written once
+        const double w = sizeof(T), sp = (double)g.nxh / g.nx, S = g.s, N = (double)g.N * nready;
+        double bb = 0.0;
+        switch (pass) {
+            case 0: bb = N * ((S + 1) * w + 2) + N * sp * S * w; break;
+            case 1: bb = 2.0 * N * sp * S * w; break;
+            case 2: bb = N * sp * S * w + N * S * w; break;
+            case 3: bb = N * (3 * S * w + w + 2) + N * sp * S * w; break;
+            case 4: bb = N * sp * S * w + N * 5 * S * w; break;
+        }
+        if (bytes) *bytes = bb;
+        return RVE_OK;
     }
 };
 
@@ -1048,6 +1369,7 @@ static int validate(const rve_config* c, std::string& why) {
     if (c->max_stagger < 1 || c->max_cg < 1 || c->max_pcg < 1) { why = "iteration limits must be >= 1"; return RVE_EINVAL; }
     if (c->anderson_depth < 0 || c->anderson_depth > kAndersonMax) { why = "anderson_depth in [0, 5]"; return RVE_EINVAL; }
     if (c->max_materials < 1 || c->max_materials > kMaxMat) { why = "max_materials in [1, 65536]"; return RVE_EINVAL; }
+    if (c->batch < 1 || c->batch > 1024) { why = "batch in [1, 1024]"; return RVE_EINVAL; }
     const int s = c->dim == 2 ? 3 : 6;
     double fn = 0;
     for (int a = 0; a < s; ++a) {
@@ -1067,6 +1389,8 @@ static int geom_check(const rve_config* c, Geom& g, int& nbx, std::string& why) 
         return RVE_EINVAL;
     return RVE_OK;
 }
+
+static thread_local std::string g_last_error;
 
 extern "C" {
 
@@ -1094,6 +1418,7 @@ int rve_default_config(rve_config* c) {
     c->frac_threshold = 0.95;
     c->A_g = 0.0;
     c->max_materials = 4096;
+    c->batch = 1;
     return RVE_OK;
 }
 
@@ -1101,15 +1426,15 @@ int rve_query_workspace(const rve_config* c, size_t* bytes) {
     std::string why;
     if (!bytes) return RVE_EINVAL;
     int rc = validate(c, why);
-    if (rc) return rc;
+    if (rc) { g_last_error = why; return rc; }
     Geom g;
     int nbx = 1;
     Layout L;
     if (c->precision == RVE_PREC_FP64) {
-        if ((rc = geom_check<double>(c, g, nbx, why))) return rc;
+        if ((rc = geom_check<double>(c, g, nbx, why))) { g_last_error = why; return rc; }
         Solver<double>::layout(*c, g, nbx, L, nullptr);
     } else {
-        if ((rc = geom_check<float>(c, g, nbx, why))) return rc;
+        if ((rc = geom_check<float>(c, g, nbx, why))) { g_last_error = why; return rc; }
         Solver<float>::layout(*c, g, nbx, L, nullptr);
     }
     *bytes = L.total;
@@ -1119,14 +1444,12 @@ int rve_query_workspace(const rve_config* c, size_t* bytes) {
 int rve_create(const rve_config* c, void* ws, size_t wsb, void* stream, rve_handle* out) {
     if (!out) return RVE_EINVAL;
     *out = nullptr;
-    std::string why;
-    int rc = validate(c, why);
-    if (rc) return rc;
     size_t need = 0;
+    int rc;
     if ((rc = rve_query_workspace(c, &need))) return rc;
-    if (!ws) return RVE_EINVAL;
-    if (wsb < need) return RVE_ENOSPC;
-    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) return RVE_EINVAL;
+    if (!ws) { g_last_error = "null workspace"; return RVE_EINVAL; }
+    if (wsb < need) { g_last_error = "workspace too small"; return RVE_ENOSPC; }
+    if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) { g_last_error = "workspace not 256-byte aligned"; return RVE_EINVAL; }
     auto* h = new rve_handle_s();
     h->cfg = *c;
     hipStream_t st = (hipStream_t)stream;
@@ -1140,6 +1463,7 @@ int rve_create(const rve_config* c, void* ws, size_t wsb, void* stream, rve_hand
         rc = s->init_device();
     }
     if (rc) {
+        g_last_error = h->err;
         delete h;
         return rc;
     }
@@ -1152,17 +1476,35 @@ int rve_destroy(rve_handle h) {
     return RVE_OK;
 }
 
+int rve_batch_size(rve_handle h) { return h ? h->impl->B : 0; }
+
+int rve_set_microstructure_slot(rve_handle h, int slot, const uint16_t* phase_id,
+                                const rve_phase* phases, int nphases, const double* theta,
+                                const uint8_t* void_mask, const uint8_t* phi_disc, double phi_M) {
+    if (!h) return RVE_EINVAL;
+    return h->impl->set_microstructure(slot, phase_id, phases, nphases, theta, void_mask, phi_disc,
+                                       phi_M);
+}
+
 int rve_set_microstructure(rve_handle h, const uint16_t* phase_id, const rve_phase* phases,
                            int nphases, const double* theta, const uint8_t* void_mask,
                            const uint8_t* phi_disc, double phi_M) {
-    if (!h) return RVE_EINVAL;
-    return h->impl->set_microstructure(phase_id, phases, nphases, theta, void_mask, phi_disc,
+    return rve_set_microstructure_slot(h, 0, phase_id, phases, nphases, theta, void_mask, phi_disc,
                                        phi_M);
+}
+
+int rve_step_dissipation_slots(rve_handle h, const double* dtau, rve_step_info* info, int* status) {
+    if (!h || !dtau) return RVE_EINVAL;
+    return h->impl->step(dtau, info, status);
 }
 
 int rve_step_dissipation(rve_handle h, double dtau, rve_step_info* out) {
     if (!h) return RVE_EINVAL;
-    return h->impl->step(dtau, out);
+    if (h->impl->B != 1) { h->err = "batched handle: use rve_step_dissipation_slots"; return RVE_EINVAL; }
+    if (dtau == 0.0) { h->err = "dtau must be > 0"; return RVE_EINVAL; }
+    int status = RVE_OK;
+    int rc = h->impl->step(&dtau, out, &status);
+    return rc != RVE_OK ? rc : status;
 }
 
 int rve_step_dissipation_batch(rve_handle* hs, int count, const double* dtau,
@@ -1172,7 +1514,7 @@ int rve_step_dissipation_batch(rve_handle* hs, int count, const double* dtau,
     std::vector<std::thread> th;
     for (int i = 0; i < count; ++i) {
         if (!hs[i]) { rcs[i] = RVE_EINVAL; continue; }
-        th.emplace_back([&, i]() { rcs[i] = hs[i]->impl->step(dtau[i], info ? &info[i] : nullptr); });
+        th.emplace_back([&, i]() { rcs[i] = rve_step_dissipation(hs[i], dtau[i], info ? &info[i] : nullptr); });
     }
     for (auto& t : th) t.join();
     int rc = RVE_OK;
@@ -1183,54 +1525,76 @@ int rve_step_dissipation_batch(rve_handle* hs, int count, const double* dtau,
     return rc;
 }
 
-int rve_effective_toughness(rve_handle h, double* G) {
-    if (!h || !G) return RVE_EINVAL;
-    SolverBase* s = h->impl.get();
-    if (!s->ready) { h->err = "set_microstructure first"; return RVE_ESTATE; }
-    if (!s->fractured) { h->err = "fracture point not reached"; return RVE_ENOTDONE; }
-    *G = s->V * (s->T_c - 0.5 * s->Sigma_c * s->E_c) / s->A_g;
+int rve_effective_toughness_slot(rve_handle h, int slot, double* G) {
+    if (!h || !G || slot < 0 || slot >= h->impl->B) return RVE_EINVAL;
+    const SlotState& s = h->impl->slots[slot];
+    if (!s.ready) { h->err = "set_microstructure first"; return RVE_ESTATE; }
+    if (!s.fractured) { h->err = "fracture point not reached"; return RVE_ENOTDONE; }
+    *G = s.V * (s.T - 0.5 * s.Sigma * s.E) / s.A_g;
     return RVE_OK;
 }
 
+int rve_effective_toughness(rve_handle h, double* G) { return rve_effective_toughness_slot(h, 0, G); }
+
+int rve_get_field_slot(rve_handle h, int slot, int which, double* host, size_t count) {
+    if (!h || !host) return RVE_EINVAL;
+    return h->impl->get_field(slot, which, host, count);
+}
 int rve_get_field(rve_handle h, int which, double* host, size_t count) {
-    if (!h || !host) return RVE_EINVAL;
-    return h->impl->get_field(which, host, count);
+    return rve_get_field_slot(h, 0, which, host, count);
 }
-
+int rve_set_field_slot(rve_handle h, int slot, int which, const double* host, size_t count) {
+    if (!h || !host) return RVE_EINVAL;
+    return h->impl->set_field(slot, which, host, count);
+}
 int rve_set_field(rve_handle h, int which, const double* host, size_t count) {
-    if (!h || !host) return RVE_EINVAL;
-    return h->impl->set_field(which, host, count);
+    return rve_set_field_slot(h, 0, which, host, count);
 }
 
-int rve_get_scalars(rve_handle h, double* o) {
-    if (!h || !o) return RVE_EINVAL;
-    SolverBase* s = h->impl.get();
-    o[0] = s->E_c;
-    o[1] = s->Sigma_c;
-    o[2] = s->T_c;
-    o[3] = s->tau_c;
-    o[4] = s->tau0;
-    o[5] = s->step_c;
+int rve_get_scalars_slot(rve_handle h, int slot, double* o) {
+    if (!h || !o || slot < 0 || slot >= h->impl->B) return RVE_EINVAL;
+    const SlotState& s = h->impl->slots[slot];
+    o[0] = s.E;
+    o[1] = s.Sigma;
+    o[2] = s.T;
+    o[3] = s.tau;
+    o[4] = s.tau0;
+    o[5] = s.step;
+    o[6] = s.fractured ? 1.0 : 0.0;
+    o[7] = s.A_g;
     return RVE_OK;
 }
+int rve_get_scalars(rve_handle h, double* o) {
+    double t[8];
+    int rc = rve_get_scalars_slot(h, 0, t);
+    if (rc == RVE_OK && o) std::memcpy(o, t, sizeof(double) * 6);
+    return rc;
+}
 
-int rve_set_scalars(rve_handle h, const double* in) {
-    if (!h || !in) return RVE_EINVAL;
+int rve_set_scalars_slot(rve_handle h, int slot, const double* in) {
+    if (!h || !in || slot < 0 || slot >= h->impl->B) return RVE_EINVAL;
     for (int i = 0; i < 6; ++i)
         if (!std::isfinite(in[i])) return RVE_EINVAL;
-    SolverBase* s = h->impl.get();
-    s->E_c = in[0];
-    s->Sigma_c = in[1];
-    s->T_c = in[2];
-    s->tau_c = in[3];
-    s->tau0 = in[4];
-    s->step_c = (int)in[5];
+    SlotState& s = h->impl->slots[slot];
+    s.E = in[0];
+    s.Sigma = in[1];
+    s.T = in[2];
+    s.tau = in[3];
+    s.tau0 = in[4];
+    s.step = (int)in[5];
+    return RVE_OK;
+}
+int rve_set_scalars(rve_handle h, const double* in) { return rve_set_scalars_slot(h, 0, in); }
+
+int rve_release_slot(rve_handle h, int slot) {
+    if (!h || slot < 0 || slot >= h->impl->B) return RVE_EINVAL;
+    h->impl->slots[slot] = SlotState();
     return RVE_OK;
 }
 
 int rve_apply_green_op(rve_handle h, const double* eps, double* out) {
     if (!h || !eps || !out) return RVE_EINVAL;
-    return h->impl->apply_green(eps, out);
+    return h->impl->apply_green(0, eps, out);
 }
 
 int rve_apply_green_op_device(rve_handle h, const void* eps, void* out, int repeat) {
@@ -1240,21 +1604,26 @@ int rve_apply_green_op_device(rve_handle h, const void* eps, void* out, int repe
 
 int rve_solve_mechanics(rve_handle h, int* it, double* Sigma1) {
     if (!h) return RVE_EINVAL;
-    return h->impl->solve_mechanics(it, Sigma1);
+    return h->impl->solve_mechanics(0, it, Sigma1);
 }
 
 int rve_solve_damage(rve_handle h, double E, double* D, int* it, int commit) {
     if (!h || !(E >= 0.0)) return RVE_EINVAL;
-    return h->impl->solve_damage(E, D, it, commit);
+    return h->impl->solve_damage(0, E, D, it, commit);
 }
 
 int rve_dissipation(rve_handle h, double* D, double* G) {
     if (!h) return RVE_EINVAL;
-    return h->impl->dissipation(D, G);
+    return h->impl->dissipation(0, D, G);
 }
 
-const char* rve_last_error(rve_handle h) { return h ? h->err.c_str() : "null handle"; }
+int rve_profile_pass(rve_handle h, int pass, int repeat, double* bytes_per_launch) {
+    if (!h || repeat < 0) return RVE_EINVAL;
+    return h->impl->profile_pass(pass, repeat, bytes_per_launch);
+}
 
-const char* rve_version(void) { return "mirve 0.1 (gfx950)"; }
+const char* rve_last_error(rve_handle h) { return h ? h->err.c_str() : g_last_error.c_str(); }
+
+const char* rve_version(void) { return "mirve 0.2 (gfx950)"; }
 
 }  // extern "C"

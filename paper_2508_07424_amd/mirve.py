@@ -35,10 +35,13 @@ FIELDS = {"phi": 0, "hist": 1, "psi_ini": 2, "eps1": 3, "sig1": 4, "psi1": 5, "p
 
 # every function declared in include/mirve.h
 EXPORTS = ["rve_default_config", "rve_query_workspace", "rve_create", "rve_destroy",
-           "rve_set_microstructure", "rve_step_dissipation", "rve_step_dissipation_batch",
-           "rve_effective_toughness", "rve_get_field", "rve_set_field", "rve_get_scalars",
-           "rve_set_scalars", "rve_apply_green_op", "rve_apply_green_op_device",
-           "rve_solve_mechanics", "rve_solve_damage", "rve_dissipation", "rve_last_error",
+           "rve_set_microstructure", "rve_set_microstructure_slot", "rve_step_dissipation",
+           "rve_step_dissipation_slots", "rve_step_dissipation_batch", "rve_batch_size",
+           "rve_release_slot", "rve_effective_toughness", "rve_effective_toughness_slot",
+           "rve_get_field", "rve_set_field", "rve_get_field_slot", "rve_set_field_slot",
+           "rve_get_scalars", "rve_set_scalars", "rve_get_scalars_slot", "rve_set_scalars_slot",
+           "rve_apply_green_op", "rve_apply_green_op_device", "rve_solve_mechanics",
+           "rve_solve_damage", "rve_dissipation", "rve_profile_pass", "rve_last_error",
            "rve_version"]
 
 
@@ -49,7 +52,7 @@ class rve_config(C.Structure):
                 ("tol_cg", C.c_double), ("tol_pcg", C.c_double), ("tol_al", C.c_double),
                 ("max_stagger", C.c_int), ("max_cg", C.c_int), ("max_pcg", C.c_int),
                 ("anderson_depth", C.c_int), ("frac_threshold", C.c_double), ("A_g", C.c_double),
-                ("max_materials", C.c_int)]
+                ("max_materials", C.c_int), ("batch", C.c_int)]
 
 
 class rve_phase(C.Structure):
@@ -80,6 +83,15 @@ def _load():
         "rve_create": (I, [C.POINTER(rve_config), P, S, P, C.POINTER(P)]),
         "rve_destroy": (I, [P]),
         "rve_set_microstructure": (I, [P, P, C.POINTER(rve_phase), I, P, P, P, D]),
+        "rve_set_microstructure_slot": (I, [P, I, P, C.POINTER(rve_phase), I, P, P, P, D]),
+        "rve_step_dissipation_slots": (I, [P, dp, C.POINTER(rve_step_info), C.POINTER(C.c_int)]),
+        "rve_batch_size": (I, [P]),
+        "rve_release_slot": (I, [P, I]),
+        "rve_effective_toughness_slot": (I, [P, I, dp]),
+        "rve_get_field_slot": (I, [P, I, I, dp, S]),
+        "rve_set_field_slot": (I, [P, I, I, dp, S]),
+        "rve_get_scalars_slot": (I, [P, I, dp]),
+        "rve_set_scalars_slot": (I, [P, I, dp]),
         "rve_step_dissipation": (I, [P, D, C.POINTER(rve_step_info)]),
         "rve_step_dissipation_batch": (I, [C.POINTER(P), I, dp, C.POINTER(rve_step_info),
                                            C.POINTER(C.c_int)]),
@@ -93,6 +105,7 @@ def _load():
         "rve_solve_mechanics": (I, [P, C.POINTER(C.c_int), dp]),
         "rve_solve_damage": (I, [P, D, dp, C.POINTER(C.c_int), I]),
         "rve_dissipation": (I, [P, dp, dp]),
+        "rve_profile_pass": (I, [P, I, I, dp]),
         "rve_last_error": (C.c_char_p, [P]),
         "rve_version": (C.c_char_p, []),
     }
@@ -150,7 +163,7 @@ def rve_query_workspace(cfg):
     b = C.c_size_t(0)
     rc = lib.rve_query_workspace(C.byref(cfg), C.byref(b))
     if rc != RVE_OK:
-        raise MirveError(rc, "invalid configuration")
+        raise MirveError(rc, lib.rve_last_error(None).decode())
     return b.value
 
 
@@ -178,8 +191,9 @@ class Rve:
         rc = lib.rve_create(C.byref(cfg), C.c_void_p(self.workspace.data_ptr()),
                             C.c_size_t(self.nbytes), C.c_void_p(sptr), C.byref(h))
         if rc != RVE_OK:
-            raise MirveError(rc, "rve_create failed")
+            raise MirveError(rc, lib.rve_last_error(None).decode())
         self.h = h
+        self.B = int(cfg.batch)
         self.dim = cfg.dim
         self.n = tuple(cfg.n[: cfg.dim])
         self.s = 3 if cfg.dim == 2 else 6
@@ -204,7 +218,7 @@ class Rve:
 
     # -- API with the C names' semantics ------------------------------------
     def rve_set_microstructure(self, phase_id, phases, theta=None, void=None, phi_disc=None,
-                               phi_M=0.8):
+                               phi_M=0.8, slot=0):
         pid = np.ascontiguousarray(phase_id, dtype=np.uint16).reshape(-1)
         assert pid.size == self.N
         th = None if theta is None else np.ascontiguousarray(theta, dtype=np.float64).reshape(-1)
@@ -212,44 +226,57 @@ class Rve:
         pd = None if phi_disc is None else np.ascontiguousarray(phi_disc, dtype=np.uint8).reshape(-1)
         arr = phases_array(phases)
         vp = lambda a: None if a is None else C.c_void_p(a.ctypes.data)
-        self._chk(lib.rve_set_microstructure(self.h, vp(pid), arr, len(phases), vp(th), vp(vm),
-                                             vp(pd), float(phi_M)))
+        self._chk(lib.rve_set_microstructure_slot(self.h, int(slot), vp(pid), arr, len(phases),
+                                                  vp(th), vp(vm), vp(pd), float(phi_M)))
 
-    def set_workload(self, w):
+    def set_workload(self, w, slot=0):
         self.rve_set_microstructure(w.phase_id, w.phases, theta=w.theta, void=w.void,
-                                    phi_disc=w.phi_disc, phi_M=w.phi_M)
+                                    phi_disc=w.phi_disc, phi_M=w.phi_M, slot=slot)
+
+    def rve_step_dissipation_slots(self, dtaus):
+        """One lockstep step; dtaus[b] > 0 steps slot b.  Returns (infos, status)."""
+        dt = np.ascontiguousarray(dtaus, dtype=np.float64)
+        assert dt.size == self.B
+        infos = (rve_step_info * self.B)()
+        status = (C.c_int * self.B)()
+        lib.rve_step_dissipation_slots(self.h, _dptr(dt), infos, status)
+        return [infos[i].as_dict() for i in range(self.B)], [status[i] for i in range(self.B)]
+
+    def rve_release_slot(self, slot):
+        self._chk(lib.rve_release_slot(self.h, int(slot)))
 
     def rve_step_dissipation(self, dtau):
         info = rve_step_info()
         self._chk(lib.rve_step_dissipation(self.h, float(dtau), C.byref(info)))
         return info.as_dict()
 
-    def rve_effective_toughness(self):
+    def rve_effective_toughness(self, slot=0):
         g = C.c_double(0.0)
-        self._chk(lib.rve_effective_toughness(self.h, C.byref(g)))
+        self._chk(lib.rve_effective_toughness_slot(self.h, int(slot), C.byref(g)))
         return g.value
 
-    def rve_get_field(self, name):
+    def rve_get_field(self, name, slot=0):
         which = FIELDS[name]
         cnt = self.N * (self.s if name in ("eps1", "sig1") else 1)
         out = np.empty(cnt, dtype=np.float64)
-        self._chk(lib.rve_get_field(self.h, which, _dptr(out), cnt))
+        self._chk(lib.rve_get_field_slot(self.h, int(slot), which, _dptr(out), cnt))
         if name in ("eps1", "sig1"):
             return out.reshape((self.s,) + self.shape)
         return out.reshape(self.shape)
 
-    def rve_set_field(self, name, arr):
+    def rve_set_field(self, name, arr, slot=0):
         a = np.ascontiguousarray(arr, dtype=np.float64).reshape(-1)
-        self._chk(lib.rve_set_field(self.h, FIELDS[name], _dptr(a), a.size))
+        self._chk(lib.rve_set_field_slot(self.h, int(slot), FIELDS[name], _dptr(a), a.size))
 
-    def rve_get_scalars(self):
-        o = np.zeros(6)
-        self._chk(lib.rve_get_scalars(self.h, _dptr(o)))
-        return dict(E=o[0], Sigma=o[1], T=o[2], tau=o[3], tau0=o[4], step=int(o[5]))
+    def rve_get_scalars(self, slot=0):
+        o = np.zeros(8)
+        self._chk(lib.rve_get_scalars_slot(self.h, int(slot), _dptr(o)))
+        return dict(E=o[0], Sigma=o[1], T=o[2], tau=o[3], tau0=o[4], step=int(o[5]),
+                    fractured=bool(o[6]), A_g=o[7])
 
-    def rve_set_scalars(self, d):
+    def rve_set_scalars(self, d, slot=0):
         a = np.array([d["E"], d["Sigma"], d["T"], d["tau"], d["tau0"], d["step"]], dtype=float)
-        self._chk(lib.rve_set_scalars(self.h, _dptr(a)))
+        self._chk(lib.rve_set_scalars_slot(self.h, int(slot), _dptr(a)))
 
     def rve_apply_green_op(self, eps):
         e = np.ascontiguousarray(eps, dtype=np.float64).reshape(-1)
@@ -281,6 +308,12 @@ class Rve:
         return D.value, G.value
 
 
+    def rve_profile_pass(self, which, repeat=1):
+        b = C.c_double(0.0)
+        self._chk(lib.rve_profile_pass(self.h, int(which), int(repeat), C.byref(b)))
+        return b.value
+
+
 def rve_step_dissipation_batch(rves, dtaus):
     n = len(rves)
     hs = (C.c_void_p * n)(*[r.h for r in rves])
@@ -300,4 +333,20 @@ def from_workload(w, precision=RVE_PREC_FP64, stream=None, **kw):
     cfg = make_config(w.n, h=w.h, ell=w.ell, k=w.k, f=w.f, precision=precision, **kw)
     r = Rve(cfg, stream=stream)
     r.set_workload(w)
+    return r
+
+
+def from_workloads(ws, precision=RVE_PREC_FP64, stream=None, **kw):
+    """One batched handle holding the workloads (same grid, l, h, k, f) in
+    slots 0..len(ws)-1."""
+    w0 = ws[0]
+    for w in ws:
+        assert tuple(w.n) == tuple(w0.n) and w.ell == w0.ell and w.h == w0.h and w.k == w0.k
+        assert np.array_equal(np.asarray(w.f), np.asarray(w0.f))
+    kw.setdefault("max_materials", max(4096, max(len(w.phases) * 2 for w in ws)))
+    cfg = make_config(w0.n, h=w0.h, ell=w0.ell, k=w0.k, f=w0.f, precision=precision,
+                      batch=len(ws), **kw)
+    r = Rve(cfg, stream=stream)
+    for i, w in enumerate(ws):
+        r.set_workload(w, slot=i)
     return r
