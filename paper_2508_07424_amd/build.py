@@ -17,7 +17,11 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmirve.so")
-SOURCES = ["greenop.hip", "pointwise.hip", "solver.hip"]
+# (source, object, extra flags)
+SOURCES = [("greenop.hip", "greenop_f64.o", ["-DMIRVE_REAL=double"]),
+           ("greenop.hip", "greenop_f32.o", ["-DMIRVE_REAL=float"]),
+           ("pointwise.hip", "pointwise.o", []),
+           ("solver.hip", "solver.o", [])]
 ARCH = "gfx950"
 
 # Packed-FP32 instructions are kept out of the device code.
@@ -33,9 +37,10 @@ def hipcc():
     return path
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc()] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(item):
+    src, objname, extra = item
+    obj = os.path.join(BUILD, objname)
+    cmd = [hipcc()] + FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     msgs = [l for l in (res.stdout + res.stderr).splitlines() if "packed-fp32-ops" not in l]
     if res.returncode != 0:

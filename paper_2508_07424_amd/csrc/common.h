@@ -36,6 +36,7 @@ struct AxisPlan {
     int rad[kMaxStages];
     int tw_off;
     int min_rad;
+    int fastN;       // N when the fixed-size two-level FFT is used, else 0
 };
 
 // Per-material constants, indexed by the per-voxel material id.  The

@@ -110,7 +110,7 @@ __host__ __device__ inline int lds_line(int N) { return N + (N >> 4) + 1; }
 // buf[l * lstride + lp(e)].  MAXB bounds the butterflies a thread carries
 // per pass: nlines * N / min_radix <= MAXB * blockDim.x.
 template <typename T, int MAXB>
-__device__ void lds_fft(cplx<T>* buf, int nlines, int lstride, const AxisPlan& pl,
+__device__ __forceinline__ void lds_fft(cplx<T>* buf, int nlines, int lstride, const AxisPlan& pl,
                         const cplx<T>* __restrict__ tw, bool inv) {
     const int N = pl.N;
     int p = 1;

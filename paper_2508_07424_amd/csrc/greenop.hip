@@ -18,7 +18,7 @@
 // transpose through LDS so that the y lines are contiguous.  A batch of B
 // RVEs of the same grid shares every launch (RVE index = last grid index).
 #include "kernels.h"
-#include "fft_device.h"
+#include "fft2l.h"
 #include "reduce.h"
 
 namespace mirve {
@@ -47,7 +47,7 @@ __device__ inline T degr(T phi, T k) {
 // Compatible-strain projection P(n) (Eq. 26, symmetric reading) on one
 // Mandel vector of complex spectra, n real and unit (or zero).
 template <typename T>
-__device__ inline void project2(cplx<T> (&v)[3], T n1, T n2) {
+__device__ __forceinline__ void project2(cplx<T> (&v)[3], T n1, T n2) {
     const T is2 = T(0.70710678118654752440084436210485);
     const T s2 = T(1.4142135623730950488016887242097);
 #pragma unroll
@@ -66,7 +66,7 @@ __device__ inline void project2(cplx<T> (&v)[3], T n1, T n2) {
 }
 
 template <typename T>
-__device__ inline void project3(cplx<T> (&v)[6], T n1, T n2, T n3) {
+__device__ __forceinline__ void project3(cplx<T> (&v)[6], T n1, T n2, T n3) {
     const T is2 = T(0.70710678118654752440084436210485);
     const T s2 = T(1.4142135623730950488016887242097);
     const T n[3] = {n1, n2, n3};
@@ -92,12 +92,12 @@ __device__ inline void project3(cplx<T> (&v)[6], T n1, T n2, T n3) {
     }
 }
 
-__device__ inline int signed_k(int k, int N) { return (2 * k < N) ? k : k - N; }
+__device__ __forceinline__ int signed_k(int k, int N) { return (2 * k < N) ? k : k - N; }
 
 // Frequency direction with the Nyquist rule: on an even axis the index
 // k = -N/2 keeps its frequency only if every other index is zero.
 template <typename T>
-__device__ inline void freq_dir(const Geom& g, int kx, int ky, int kz, T& n1, T& n2, T& n3) {
+__device__ __forceinline__ void freq_dir(const Geom& g, int kx, int ky, int kz, T& n1, T& n2, T& n3) {
     int sx = (g.nx % 2 == 0 && 2 * kx == g.nx) ? -g.nx / 2 : kx;
     int sy = signed_k(ky, g.ny);
     int sz = g.dim == 3 ? signed_k(kz, g.nz) : 0;
@@ -123,7 +123,7 @@ __device__ inline void freq_dir(const Geom& g, int kx, int ky, int kz, T& n1, T&
 // x-forward pass
 // ---------------------------------------------------------------------------
 
-template <typename T, int S, int MODE, int MAXB>
+template <typename T, int S, int MODE, typename F>
 __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
         }
     }
     __syncthreads();
-    lds_fft<T, MAXB>(buf, S * npairs, LS, a.pl, a.tw, false);
+    line_fft<T, F>(buf, S * npairs, LS, a.pl, a.tw, false);
 
     // split the packed lines into the half spectra of their two rows and
     // store them transposed: consecutive threads write consecutive y
@@ -227,7 +227,7 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
 // axis pass: forward, [projection], inverse along y (contiguous lines) or z
 // ---------------------------------------------------------------------------
 
-template <typename T, int S, int MODE, int MAXB>
+template <typename T, int S, int MODE, typename F>
 __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -254,7 +254,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
             buf[(c * TL + tl) * LS + lp(j)] = v;
         }
         __syncthreads();
-        lds_fft<T, MAXB>(buf, S * TL, LS, a.pl, a.tw, inv_only);
+        line_fft<T, F>(buf, S * TL, LS, a.pl, a.tw, inv_only);
         if (MODE == AX_FWD_P_INV) {
             for (int e = threadIdx.x; e < TL * Na; e += blockDim.x) {
                 const int j = e % Na, tl = e / Na;
@@ -272,7 +272,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
                 for (int c = 0; c < S; ++c) buf[(c * TL + tl) * LS + lp(j)] = v[c];
             }
             __syncthreads();
-            lds_fft<T, MAXB>(buf, S * TL, LS, a.pl, a.tw, true);
+            line_fft<T, F>(buf, S * TL, LS, a.pl, a.tw, true);
         }
         for (int e = threadIdx.x; e < S * TL * Na; e += blockDim.x) {
             const int j = e % Na, tl = (e / Na) % TL, c = e / (Na * TL);
@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
             buf[(c * TL + tl) * LS + lp(j)] = v;
         }
         __syncthreads();
-        lds_fft<T, MAXB>(buf, W, LS, a.pl, a.tw, inv_only);
+        line_fft<T, F>(buf, W, LS, a.pl, a.tw, inv_only);
         if (MODE == AX_FWD_P_INV) {
             for (int e = threadIdx.x; e < TL * Na; e += blockDim.x) {
                 const int tl = e % TL, j = e / TL;
@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
                 for (int c = 0; c < S; ++c) buf[(c * TL + tl) * LS + lp(j)] = v[c];
             }
             __syncthreads();
-            lds_fft<T, MAXB>(buf, W, LS, a.pl, a.tw, true);
+            line_fft<T, F>(buf, W, LS, a.pl, a.tw, true);
         }
         for (int e = threadIdx.x; e < W * Na; e += blockDim.x) {
             const int tl = e % TL, c = (e / TL) % S, j = e / W;
@@ -323,7 +323,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
 // x-inverse pass
 // ---------------------------------------------------------------------------
 
-template <typename T, int S, int MODE, int MAXB>
+template <typename T, int S, int MODE, typename F>
 __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -355,7 +355,7 @@ __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
         buf[(c * npairs + pr) * LS + lp(k)] = {A.x - B.y, A.y + B.x};
     }
     __syncthreads();
-    lds_fft<T, MAXB>(buf, S * npairs, LS, a.pl, a.tw, true);
+    line_fft<T, F>(buf, S * npairs, LS, a.pl, a.tw, true);
 
     const T scale = T(g.inv_N) * a.scale;
     T alpha = T(0);
@@ -393,19 +393,36 @@ __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
 
 template <typename K, typename A>
 static hipError_t launch_k(K kern, dim3 grid, size_t lds, hipStream_t st, const A& a) {
-    hipLaunchKernelGGL(kern, grid, dim3(256), lds, st, a);
+    hipLaunchKernelGGL(kern, grid, dim3(a.threads), lds, st, a);
     return hipGetLastError();
 }
+
+// Instantiate kernel template KT<T, S, MODE, F> for the FFT policy of the
+// plan: fixed power-of-two length, else the runtime plan with maxb.
+#define MIRVE_DISPATCH(KT, T, S, MODE, pl, maxb, grid, lds, st, a)                         \
+    do {                                                                                    \
+        switch ((pl).fastN) {                                                               \
+            case 16: return launch_k(KT<T, S, MODE, FastFFT<16>>, grid, lds, st, a);        \
+            case 32: return launch_k(KT<T, S, MODE, FastFFT<32>>, grid, lds, st, a);        \
+            case 64: return launch_k(KT<T, S, MODE, FastFFT<64>>, grid, lds, st, a);        \
+            case 128: return launch_k(KT<T, S, MODE, FastFFT<128>>, grid, lds, st, a);      \
+            case 256: return launch_k(KT<T, S, MODE, FastFFT<256>>, grid, lds, st, a);      \
+            case 512: return launch_k(KT<T, S, MODE, FastFFT<512>>, grid, lds, st, a);      \
+            case 1024: return launch_k(KT<T, S, MODE, FastFFT<1024>>, grid, lds, st, a);    \
+            default: break;                                                                 \
+        }                                                                                   \
+        switch (maxb) {                                                                     \
+            case 1: return launch_k(KT<T, S, MODE, GenericFFT<1>>, grid, lds, st, a);       \
+            case 2: return launch_k(KT<T, S, MODE, GenericFFT<2>>, grid, lds, st, a);       \
+            case 4: return launch_k(KT<T, S, MODE, GenericFFT<4>>, grid, lds, st, a);       \
+            default: return launch_k(KT<T, S, MODE, GenericFFT<8>>, grid, lds, st, a);      \
+        }                                                                                   \
+    } while (0)
 
 template <typename T, int S, int MODE>
 static hipError_t launch_xfwd_s(const XfwdArgs<T>& a, int maxb, size_t lds, hipStream_t st) {
     const dim3 grid(a.nblocks, a.g.B);
-    switch (maxb) {
-        case 1: return launch_k(k_xfwd<T, S, MODE, 1>, grid, lds, st, a);
-        case 2: return launch_k(k_xfwd<T, S, MODE, 2>, grid, lds, st, a);
-        case 4: return launch_k(k_xfwd<T, S, MODE, 4>, grid, lds, st, a);
-        default: return launch_k(k_xfwd<T, S, MODE, 8>, grid, lds, st, a);
-    }
+    MIRVE_DISPATCH(k_xfwd, T, S, MODE, a.pl, maxb, grid, lds, st, a);
 }
 
 template <typename T>
@@ -420,12 +437,7 @@ hipError_t launch_xfwd(const XfwdArgs<T>& a, int mode, int maxb, size_t lds, hip
 template <typename T, int S, int MODE>
 static hipError_t launch_axis_s(const AxisArgs<T>& a, int maxb, dim3 grid, size_t lds,
                                 hipStream_t st) {
-    switch (maxb) {
-        case 1: return launch_k(k_axis<T, S, MODE, 1>, grid, lds, st, a);
-        case 2: return launch_k(k_axis<T, S, MODE, 2>, grid, lds, st, a);
-        case 4: return launch_k(k_axis<T, S, MODE, 4>, grid, lds, st, a);
-        default: return launch_k(k_axis<T, S, MODE, 8>, grid, lds, st, a);
-    }
+    MIRVE_DISPATCH(k_axis, T, S, MODE, a.pl, maxb, grid, lds, st, a);
 }
 
 template <typename T>
@@ -448,12 +460,7 @@ hipError_t launch_axis(const AxisArgs<T>& a, int mode, int maxb, dim3 grid, size
 template <typename T, int S, int MODE>
 static hipError_t launch_xinv_s(const XinvArgs<T>& a, int maxb, size_t lds, hipStream_t st) {
     const dim3 grid(a.nblocks, a.g.B);
-    switch (maxb) {
-        case 1: return launch_k(k_xinv<T, S, MODE, 1>, grid, lds, st, a);
-        case 2: return launch_k(k_xinv<T, S, MODE, 2>, grid, lds, st, a);
-        case 4: return launch_k(k_xinv<T, S, MODE, 4>, grid, lds, st, a);
-        default: return launch_k(k_xinv<T, S, MODE, 8>, grid, lds, st, a);
-    }
+    MIRVE_DISPATCH(k_xinv, T, S, MODE, a.pl, maxb, grid, lds, st, a);
 }
 
 template <typename T>
@@ -465,11 +472,10 @@ hipError_t launch_xinv(const XinvArgs<T>& a, int mode, int maxb, size_t lds, hip
                          : launch_xinv_s<T, 6, XI_STORE>(a, maxb, lds, st);
 }
 
-template hipError_t launch_xfwd<double>(const XfwdArgs<double>&, int, int, size_t, hipStream_t);
-template hipError_t launch_xfwd<float>(const XfwdArgs<float>&, int, int, size_t, hipStream_t);
-template hipError_t launch_axis<double>(const AxisArgs<double>&, int, int, dim3, size_t, hipStream_t);
-template hipError_t launch_axis<float>(const AxisArgs<float>&, int, int, dim3, size_t, hipStream_t);
-template hipError_t launch_xinv<double>(const XinvArgs<double>&, int, int, size_t, hipStream_t);
-template hipError_t launch_xinv<float>(const XinvArgs<float>&, int, int, size_t, hipStream_t);
+// One object per precision (MIRVE_REAL = double or float) keeps the build parallel.
+template hipError_t launch_xfwd<MIRVE_REAL>(const XfwdArgs<MIRVE_REAL>&, int, int, size_t, hipStream_t);
+template hipError_t launch_axis<MIRVE_REAL>(const AxisArgs<MIRVE_REAL>&, int, int, dim3, size_t,
+                                            hipStream_t);
+template hipError_t launch_xinv<MIRVE_REAL>(const XinvArgs<MIRVE_REAL>&, int, int, size_t, hipStream_t);
 
 }  // namespace mirve

@@ -58,6 +58,7 @@ struct XfwdArgs {
     double* partials;    // [B][nblocks]
     int rows_per_block;
     int nblocks;
+    int threads;         // block size (multiple of 64, <= 256)
 };
 
 template <typename T>
@@ -70,6 +71,7 @@ struct AxisArgs {
     const int* active;   // or when active && !active[b]
     int contiguous;      // 1: y lines (stride 1); 0: z lines (stride n_y)
     int lines;           // lines per block (y pass) / y columns per block (z pass)
+    int threads;         // block size (multiple of 64, <= 256)
 };
 
 template <typename T>
@@ -88,6 +90,7 @@ struct XinvArgs {
     double* partials;    // [B][nblocks]
     int rows_per_block;
     int nblocks;
+    int threads;         // block size (multiple of 64, <= 256)
 };
 
 template <typename T>
@@ -157,14 +160,18 @@ hipError_t launch_pcg_matvec(const Geom& g, const uint16_t* mat_id, const MatEnt
 template <typename T>
 hipError_t launch_pcg_start(const Geom& g, const T* b, const T* Ax, const T* dinv, T* r, T* p,
                             double* partials, int nred, const int* active, hipStream_t st);
-// x += alpha p; r -= alpha q; partials r.(dinv r), r.r
+// One PCG iteration: (1) direction and operator: p_new = dinv r + beta p_old
+// evaluated at the voxel and its stencil neighbours, q = A p_new, partials
+// p.q; (2) alpha; (3) update: x += alpha p, r -= alpha q, partials r.z, r.r;
+// (4) beta and convergence.
+template <typename T>
+hipError_t launch_pcg_matvec_dir(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
+                                 const T* H, int mode, double c, const T* r, const T* dinv,
+                                 const T* p_old, T* p_new, T* q, double* partials, int nred,
+                                 const PcgDev* d, hipStream_t st);
 template <typename T>
 hipError_t launch_pcg_update(const Geom& g, const PcgDev* d, T* x, T* r, const T* p, const T* q,
                              const T* dinv, double* partials, int nred, hipStream_t st);
-// p = dinv r + beta p
-template <typename T>
-hipError_t launch_pcg_dir(const Geom& g, const PcgDev* d, const T* r, const T* dinv, T* p,
-                          hipStream_t st);
 
 // D(phi) (value 0) and Gamma(phi) (value 1) partials without the h^d factor.
 template <typename T>

@@ -117,51 +117,11 @@ __global__ void k_cg_init(CgDev* cgs, const double* prr, const double* pb, int n
     else if (rr <= cg->tol2 * bn2) { cg->done = 1; cg->status = 1; }
 }
 
-__global__ void k_cg_alpha(CgDev* cgs, const double* p, int n) {
-    const int b = blockIdx.x;
-    CgDev* cg = cgs + b;
-    if (cg->done) return;
-    const double pAp = sum_fixed(p + (long long)b * n, n);
-    if (threadIdx.x != 0) return;
-    cg->pAp = pAp;
-    if (!(pAp > 0.0) || !isfinite(pAp)) {
-        cg->done = 1;
-        cg->status = 2;
-        cg->alpha = 0.0;
-        return;
-    }
-    cg->alpha = cg->rr / pAp;
-}
-
-__global__ void k_cg_beta(CgDev* cgs, const double* p, int n) {
-    const int b = blockIdx.x;
-    CgDev* cg = cgs + b;
-    if (cg->done) return;
-    const double rr = sum_fixed(p + (long long)b * n, n);
-    if (threadIdx.x != 0) return;
-    cg->beta = rr / cg->rr;
-    cg->rr = rr;
-    cg->first = 0;
-    cg->it += 1;
-    if (!isfinite(rr)) { cg->done = 1; cg->status = 2; }
-    else if (rr <= cg->tol2 * cg->bn2) { cg->done = 1; cg->status = 1; }
-    else if (cg->it >= cg->max_it) { cg->done = 1; cg->status = 3; }
-}
-
 hipError_t launch_cg_init(CgDev* cg, const double* prr, const double* pb, int n, int B,
                           double tol, int max_it, const int* active, hipStream_t st) {
     hipLaunchKernelGGL(k_cg_init, dim3(B), dim3(256), 0, st, cg, prr, pb, n, tol, max_it, active);
     return hipGetLastError();
 }
-hipError_t launch_cg_alpha(CgDev* cg, const double* p, int n, int B, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_alpha, dim3(B), dim3(256), 0, st, cg, p, n);
-    return hipGetLastError();
-}
-hipError_t launch_cg_beta(CgDev* cg, const double* p, int n, int B, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_beta, dim3(B), dim3(256), 0, st, cg, p, n);
-    return hipGetLastError();
-}
-
 __global__ void k_sum_partials(const double* p, int n, int nv, double* sums, const int* active) {
     const int b = blockIdx.x;
     if (skip(active, b)) return;
@@ -215,6 +175,7 @@ __global__ void k_pcg_fin_start(PcgDev* ds, const double* p, int n, double tol, 
     d->rr = rr;
     d->bn2 = bn2;
     d->tol2 = tol * tol;
+    d->beta = 0.0;
     d->it = 0;
     d->max_it = max_it;
     d->status = 0;
@@ -261,6 +222,45 @@ __global__ void k_pcg_fin_beta(PcgDev* ds, const double* p, int n) {
 }
 hipError_t launch_pcg_fin_beta(PcgDev* d, const double* p, int n, int B, hipStream_t st) {
     hipLaunchKernelGGL(k_pcg_fin_beta, dim3(B), dim3(256), 0, st, d, p, n);
+    return hipGetLastError();
+}
+
+__global__ void k_cg_alpha(CgDev* cgs, const double* p, int n) {
+    const int b = blockIdx.x;
+    CgDev* cg = cgs + b;
+    if (cg->done) return;
+    const double pAp = sum_fixed(p + (long long)b * n, n);
+    if (threadIdx.x != 0 || cg->max_it < 0) return;      // max_it < 0: timing run
+    cg->pAp = pAp;
+    if (!(pAp > 0.0) || !isfinite(pAp)) {
+        cg->done = 1;
+        cg->status = 2;
+        cg->alpha = 0.0;
+        return;
+    }
+    cg->alpha = cg->rr / pAp;
+}
+hipError_t launch_cg_alpha(CgDev* cg, const double* p, int n, int B, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_alpha, dim3(B), dim3(256), 0, st, cg, p, n);
+    return hipGetLastError();
+}
+
+__global__ void k_cg_beta(CgDev* cgs, const double* p, int n) {
+    const int b = blockIdx.x;
+    CgDev* cg = cgs + b;
+    if (cg->done) return;
+    const double rr = sum_fixed(p + (long long)b * n, n);
+    if (threadIdx.x != 0 || cg->max_it < 0) return;
+    cg->beta = rr / cg->rr;
+    cg->rr = rr;
+    cg->first = 0;
+    cg->it += 1;
+    if (!isfinite(rr)) { cg->done = 1; cg->status = 2; }
+    else if (rr <= cg->tol2 * cg->bn2) { cg->done = 1; cg->status = 1; }
+    else if (cg->it >= cg->max_it) { cg->done = 1; cg->status = 3; }
+}
+hipError_t launch_cg_beta(CgDev* cg, const double* p, int n, int B, hipStream_t st) {
+    hipLaunchKernelGGL(k_cg_beta, dim3(B), dim3(256), 0, st, cg, p, n);
     return hipGetLastError();
 }
 
@@ -495,6 +495,62 @@ hipError_t launch_pcg_start(const Geom& g, const T* b, const T* Ax, const T* din
     return hipGetLastError();
 }
 
+// p_new = dinv r + beta p_old evaluated at any voxel
+template <typename T>
+__device__ __forceinline__ T pdir(const T* r, const T* dinv, const T* p_old, T beta, long long j) {
+    return dinv[j] * r[j] + beta * p_old[j];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_pcg_matvec_dir(Geom g, const uint16_t* mat_id,
+                                                        const MatEntry<T>* mat, const T* H,
+                                                        int mode, T c, const T* r_a,
+                                                        const T* dinv_a, const T* po_a, T* pn_a,
+                                                        T* q_a, double* partials,
+                                                        const PcgDev* d) {
+    const int b = blockIdx.y;
+    if (d[b].done) return;
+    RVE_OFFSETS
+    const T* r = r_a + so;
+    const T* dinv = dinv_a + so;
+    const T* po = po_a + so;
+    const T* Hb = H ? H + so : nullptr;
+    const T beta = T(d[b].beta);
+    const T ell = T(g.ell);
+    const T ih2 = T(1.0 / (g.h * g.h));
+    double part = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.N;
+         i += (long long)gridDim.x * blockDim.x) {
+        T a, w;
+        coeffs(g, mt, mid, Hb, mode, c, i, a, w);
+        const Nb n = neighbours(g, i);
+        const T pc = pdir(r, dinv, po, beta, i);
+        T acc = wcoef(mt, mid, mode, ell, c, n.xm) * (pc - pdir(r, dinv, po, beta, n.xm)) -
+                w * (pdir(r, dinv, po, beta, n.xp) - pc);
+        acc += wcoef(mt, mid, mode, ell, c, n.ym) * (pc - pdir(r, dinv, po, beta, n.ym)) -
+               w * (pdir(r, dinv, po, beta, n.yp) - pc);
+        if (g.dim == 3)
+            acc += wcoef(mt, mid, mode, ell, c, n.zm) * (pc - pdir(r, dinv, po, beta, n.zm)) -
+                   w * (pdir(r, dinv, po, beta, n.zp) - pc);
+        const T v = a * pc + acc * ih2;
+        pn_a[so + i] = pc;
+        q_a[so + i] = v;
+        part += double(pc) * double(v);
+    }
+    double pv[1] = {part};
+    block_sum_store<1>(pv, pslot(partials, b, 0), kRedBlocks, blockIdx.x);
+}
+
+template <typename T>
+hipError_t launch_pcg_matvec_dir(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
+                                 const T* H, int mode, double c, const T* r, const T* dinv,
+                                 const T* p_old, T* p_new, T* q, double* partials, int nred,
+                                 const PcgDev* d, hipStream_t st) {
+    hipLaunchKernelGGL((k_pcg_matvec_dir<T>), dim3(nred, g.B), dim3(TPB), 0, st, g, mat_id, mat, H,
+                       mode, T(c), r, dinv, p_old, p_new, q, partials, d);
+    return hipGetLastError();
+}
+
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_pcg_update(long long N, const PcgDev* d, T* x, T* r,
                                                     const T* p, const T* q, const T* dinv,
@@ -522,25 +578,6 @@ hipError_t launch_pcg_update(const Geom& g, const PcgDev* d, T* x, T* r, const T
                              const T* dinv, double* partials, int nred, hipStream_t st) {
     hipLaunchKernelGGL((k_pcg_update<T>), dim3(nred, g.B), dim3(TPB), 0, st, g.N, d, x, r, p, q,
                        dinv, partials);
-    return hipGetLastError();
-}
-
-template <typename T>
-__global__ void __launch_bounds__(TPB) k_pcg_dir(long long N, const PcgDev* d, const T* r,
-                                                 const T* dinv, T* p) {
-    const int b = blockIdx.y;
-    if (d[b].done) return;
-    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const long long o = (long long)b * N + i;
-    p[o] = dinv[o] * r[o] + T(d[b].beta) * p[o];
-}
-
-template <typename T>
-hipError_t launch_pcg_dir(const Geom& g, const PcgDev* d, const T* r, const T* dinv, T* p,
-                          hipStream_t st) {
-    hipLaunchKernelGGL((k_pcg_dir<T>), dim3(blocks_for(g.N), g.B), dim3(TPB), 0, st, g.N, d, r,
-                       dinv, p);
     return hipGetLastError();
 }
 
@@ -952,8 +989,10 @@ hipError_t launch_zero_int(int* p, int n, hipStream_t st) {
                                             double*, int, const int*, hipStream_t);                \
     template hipError_t launch_pcg_update<T>(const Geom&, const PcgDev*, T*, T*, const T*,         \
                                              const T*, const T*, double*, int, hipStream_t);       \
-    template hipError_t launch_pcg_dir<T>(const Geom&, const PcgDev*, const T*, const T*, T*,      \
-                                          hipStream_t);                                            \
+    template hipError_t launch_pcg_matvec_dir<T>(const Geom&, const uint16_t*, const MatEntry<T>*, \
+                                                 const T*, int, double, const T*, const T*,        \
+                                                 const T*, T*, T*, double*, int, const PcgDev*,    \
+                                                 hipStream_t);                                     \
     template hipError_t launch_dissipation<T>(const Geom&, const uint16_t*, const MatEntry<T>*,    \
                                               const T*, double*, int, const int*, hipStream_t);    \
     template hipError_t launch_damage_residual<T>(const Geom&, const uint16_t*,                    \

@@ -29,7 +29,7 @@
 
 #include "../../include/mirve.h"
 #include "kernels.h"
-#include "fft_device.h"
+#include "fft2l.h"
 
 namespace mirve {
 
@@ -138,11 +138,17 @@ static HostMat phase_entry(const rve_phase& ph, double theta, bool notch, double
 static bool factorize(int N, AxisPlan& pl) {
     pl.N = N;
     pl.nst = 0;
-    int n = N;
+    pl.fastN = 0;
+    int n = N, k = 0;
+    while (n % 2 == 0) { n /= 2; ++k; }
+    // powers of two as radix 8 and 4 (a radix 2 only for N = 2): the smallest
+    // radix sets the butterflies a thread carries
     std::vector<int> r;
-    while (n % 8 == 0) { r.push_back(8); n /= 8; }
-    while (n % 4 == 0) { r.push_back(4); n /= 4; }
-    while (n % 2 == 0) { r.push_back(2); n /= 2; }
+    int n8 = k / 3, rem = k % 3;
+    if (rem == 1 && n8 > 0) { --n8; r.push_back(4); r.push_back(4); }
+    else if (rem == 2) r.push_back(4);
+    else if (rem == 1) r.push_back(2);
+    for (int i = 0; i < n8; ++i) r.insert(r.begin(), 8);
     for (int p : {3, 5, 7}) while (n % p == 0) { r.push_back(p); n /= p; }
     if (n != 1 || (int)r.size() > kMaxStages) return false;
     pl.min_rad = 8;
@@ -154,6 +160,9 @@ static bool factorize(int N, AxisPlan& pl) {
     if (pl.nst == 0) { pl.min_rad = 1; }
     return true;
 }
+
+// lengths served by the fixed-size two-level FFT
+static bool fast_len(int N) { return N >= 16 && N <= 1024 && (N & (N - 1)) == 0; }
 
 static int round_maxb(long long need) {
     if (need <= 1) return 1;
@@ -243,6 +252,7 @@ struct Solver : SolverBase {
     AxisPlan plx, ply, plz;
     int RB = 2, nbx = 1, maxb_x = 1;
     int tly = 1, maxb_y = 1, tlz = 1, maxb_z = 1;
+    int thr_x = 256, thr_y = 256, thr_z = 256;
     size_t lds_x = 0, lds_y = 0, lds_z = 0;
     int nred = 1;
     hipStream_t st;
@@ -251,7 +261,7 @@ struct Solver : SolverBase {
     int m1_max = 1;
 
     // device pointers (each field holds B RVEs back to back)
-    T *phi_c, *phi_w, *Hn, *psi_ini, *phi_ini, *psi1, *H, *px, *pr, *pp, *pq, *pdinv, *pb, *tmp;
+    T *phi_c, *phi_w, *Hn, *psi_ini, *phi_ini, *psi1, *H, *px, *pr, *pp, *pp2, *pq, *pdinv, *pb, *tmp;
     T *x, *x_c, *r, *p;
     T *aF, *aG;                     // Anderson ring buffers: kHist slots of B*N
     cplx<T>* spec;
@@ -280,7 +290,8 @@ struct Solver : SolverBase {
         T** single[] = {s ? &s->phi_c : nullptr, s ? &s->phi_w : nullptr, s ? &s->Hn : nullptr,
                         s ? &s->psi_ini : nullptr, s ? &s->phi_ini : nullptr, s ? &s->psi1 : nullptr,
                         s ? &s->H : nullptr, s ? &s->px : nullptr, s ? &s->pr : nullptr,
-                        s ? &s->pp : nullptr, s ? &s->pq : nullptr, s ? &s->pdinv : nullptr,
+                        s ? &s->pp : nullptr, s ? &s->pp2 : nullptr, s ? &s->pq : nullptr,
+                        s ? &s->pdinv : nullptr,
                         s ? &s->pb : nullptr, s ? &s->tmp : nullptr};
         const int ns = sizeof(single) / sizeof(single[0]);
         std::vector<size_t> offs;
@@ -336,9 +347,12 @@ struct Solver : SolverBase {
     }
 
     // geometry and launch shapes from a configuration; false if unsupported
+    static int threads_for(int n) { return std::min(256, ((n + 63) / 64) * 64); }
+
     static bool make_geom(const rve_config& c, Geom& g, AxisPlan& px, AxisPlan& py, AxisPlan& pz,
                           int& RB, int& nbx, int& maxb_x, size_t& lds_x, int& tly, int& maxb_y,
-                          size_t& lds_y, int& tlz, int& maxb_z, size_t& lds_z, std::string& why) {
+                          size_t& lds_y, int& tlz, int& maxb_z, size_t& lds_z, int& thr_x,
+                          int& thr_y, int& thr_z, std::string& why) {
         g.dim = c.dim;
         g.s = c.dim == 2 ? 3 : 6;
         g.nx = c.n[0];
@@ -358,36 +372,64 @@ struct Solver : SolverBase {
             return false;
         }
         const size_t ce = sizeof(cplx<T>);
-        // x passes: 4-16 rows per block (the transposed store writes RB/2 pairs of rows)
-        RB = std::max(2, std::min(16, 2048 / std::max(1, g.nx)));
+        // x passes: RB rows per block (RB/2 packed pairs); enough blocks to fill
+        // the chip (>= ~1024 over the batch), at most 16 rows
+        const size_t lx = (size_t)lds_line(g.nx) * ce;
+        const long long rows_total = (long long)g.ny * g.nz * g.B;
+        RB = (int)std::max<long long>(2, std::min<long long>(16, rows_total / 1024));
         RB &= ~1;
+        if (fast_len(g.nx)) {
+            while (RB > 2 && ((size_t)g.s * (RB / 2) * lx > kLdsCap ||
+                              g.s * (RB / 2) * split_max(g.nx) > 256))
+                RB -= 2;
+            if ((size_t)g.s * (RB / 2) * lx <= kLdsCap && g.s * (RB / 2) * split_max(g.nx) <= 256)
+                px.fastN = g.nx;
+        }
         auto xmb = [&](int rb) {
             return round_maxb(((long long)g.s * (rb / 2) * g.nx / px.min_rad + 255) / 256);
         };
-        const size_t lx = (size_t)lds_line(g.nx) * ce;
-        while (RB > 2 && ((size_t)g.s * (RB / 2) * lx > kLdsCap || xmb(RB) < 0)) RB -= 2;
+        if (!px.fastN)
+            while (RB > 2 && ((size_t)g.s * (RB / 2) * lx > kLdsCap || xmb(RB) < 0)) RB -= 2;
         lds_x = (size_t)g.s * (RB / 2) * lx;
-        maxb_x = xmb(RB);
+        maxb_x = px.fastN ? 1 : xmb(RB);
         if (lds_x > kLdsCap || maxb_x < 0) { why = "n_x too large for the LDS budget"; return false; }
+        thr_x = px.fastN ? threads_for(g.s * (RB / 2) * split_max(g.nx)) : 256;
         const int nrows = g.ny * g.nz;
         nbx = (nrows + RB - 1) / RB;
         // y pass: whole contiguous lines, about 1024 elements per component per block
-        auto pick = [&](const AxisPlan& pl, int want, int& tl, int& mb, size_t& lds) -> bool {
-            for (int t = want; t >= 1; --t) {
+        auto pick = [&](AxisPlan& pl, int want, int& tl, int& mb, size_t& lds, int& thr) -> bool {
+            const bool fast = fast_len(pl.N);
+            for (int t = std::max(1, want); t >= 1; --t) {
                 const size_t l = (size_t)g.s * t * lds_line(pl.N) * ce;
+                if (fast) {
+                    if (l <= kLdsCap && g.s * t * split_max(pl.N) <= 256) {
+                        tl = t; mb = 1; lds = l; pl.fastN = pl.N;
+                        thr = threads_for(g.s * t * split_max(pl.N));
+                        return true;
+                    }
+                    continue;
+                }
                 const int m = round_maxb(((long long)g.s * t * pl.N / pl.min_rad + 255) / 256);
-                if (l <= kLdsCap && m > 0) { tl = t; mb = m; lds = l; return true; }
+                if (l <= kLdsCap && m > 0) { tl = t; mb = m; lds = l; thr = 256; return true; }
             }
             return false;
         };
-        if (!pick(py, std::max(1, std::min(16, 1024 / g.ny)), tly, maxb_y, lds_y)) {
+        // y pass: whole lines; lines per block so that the batch gives >= ~1024 blocks
+        const long long ylines = (long long)g.nxh * g.nz * g.B;
+        const int want_y = (int)std::max<long long>(1, std::min<long long>(16, ylines / 1024));
+        if (!pick(py, want_y, tly, maxb_y, lds_y, thr_y)) {
             why = "n_y too large for the LDS budget";
             return false;
         }
-        // z pass: a tile of y columns, 64-128 bytes per row
-        if (g.dim == 3 && !pick(pz, std::max(1, std::min(g.ny, int(128 / ce))), tlz, maxb_z, lds_z)) {
-            why = "n_z too large for the LDS budget";
-            return false;
+        // z pass: a tile of y columns (up to 128 bytes per row)
+        if (g.dim == 3) {
+            const long long zcols = (long long)g.nxh * g.ny * g.B;
+            const int want_z = (int)std::max<long long>(
+                1, std::min<long long>(std::min<long long>(g.ny, 128 / ce), zcols / 1024));
+            if (!pick(pz, want_z, tlz, maxb_z, lds_z, thr_z)) {
+                why = "n_z too large for the LDS budget";
+                return false;
+            }
         }
         return true;
     }
@@ -395,7 +437,7 @@ struct Solver : SolverBase {
     Solver(rve_handle_s* h, const rve_config& c, void* wsp, hipStream_t s) : hd(h), cfg(c), st(s) {
         std::string why;
         make_geom(c, g, plx, ply, plz, RB, nbx, maxb_x, lds_x, tly, maxb_y, lds_y, tlz, maxb_z,
-                  lds_z, why);
+                  lds_z, thr_x, thr_y, thr_z, why);
         ws = wsp;
         Layout L;
         layout(c, g, nbx, L, this);
@@ -534,6 +576,7 @@ struct Solver : SolverBase {
         a.partials = part;
         a.rows_per_block = RB;
         a.nblocks = nbx;
+        a.threads = thr_x;
         HIPCHK(launch_xfwd<T>(a, mode, maxb_x, lds_x, st));
         return RVE_OK;
     }
@@ -548,6 +591,7 @@ struct Solver : SolverBase {
         a.tw = tw + ply.tw_off;
         a.contiguous = 1;
         a.lines = tly;
+        a.threads = thr_y;
         const dim3 gy((unsigned)((g.nxh * (long long)g.nz + tly - 1) / tly), 1, B);
         if (g.dim == 2) {
             HIPCHK(launch_axis<T>(a, AX_FWD_P_INV, maxb_y, gy, lds_y, st));
@@ -558,6 +602,7 @@ struct Solver : SolverBase {
             bz.tw = tw + plz.tw_off;
             bz.contiguous = 0;
             bz.lines = tlz;
+            bz.threads = thr_z;
             const dim3 gz((unsigned)(g.nxh * ((g.ny + tlz - 1) / tlz)), 1, B);
             HIPCHK(launch_axis<T>(bz, AX_FWD_P_INV, maxb_z, gz, lds_z, st));
             HIPCHK(launch_axis<T>(a, AX_INV, maxb_y, gy, lds_y, st));
@@ -581,6 +626,7 @@ struct Solver : SolverBase {
         a.partials = part;
         a.rows_per_block = RB;
         a.nblocks = nbx;
+        a.threads = thr_x;
         HIPCHK(launch_xinv<T>(a, mode, maxb_x, lds_x, st));
         return RVE_OK;
     }
@@ -671,16 +717,18 @@ struct Solver : SolverBase {
         HIPCHK(launch_pcg_matvec<T>(g, mat_id, mat, Hc, mode, c, u, pq, nullptr, nred, nullptr, mk, st));
         HIPCHK(launch_pcg_start<T>(g, bvec, pq, pdinv, pr, pp, partials, nred, mk, st));
         HIPCHK(launch_pcg_fin_start(pcg, partials, nred, B, tol, max_it, mk, st));
+        T* pcur = pp;   // directions alternate between pp and pp2
         int chunk = 8, total = 0;
         std::vector<ChunkPlanner> plan(B);
         for (;;) {
             for (int k = 0; k < chunk; ++k) {
-                HIPCHK(launch_pcg_matvec<T>(g, mat_id, mat, Hc, mode, c, pp, pq, partials, nred,
-                                            pcg, nullptr, st));
+                T* pn = pcur == pp ? pp2 : pp;
+                HIPCHK(launch_pcg_matvec_dir<T>(g, mat_id, mat, Hc, mode, c, pr, pdinv, pcur, pn, pq,
+                                                partials, nred, pcg, st));
                 HIPCHK(launch_pcg_fin_alpha(pcg, partials, nred, B, st));
-                HIPCHK(launch_pcg_update<T>(g, pcg, u, pr, pp, pq, pdinv, partials, nred, st));
+                HIPCHK(launch_pcg_update<T>(g, pcg, u, pr, pn, pq, pdinv, partials, nred, st));
                 HIPCHK(launch_pcg_fin_beta(pcg, partials, nred, B, st));
-                HIPCHK(launch_pcg_dir<T>(g, pcg, pr, pdinv, pp, st));
+                pcur = pn;
             }
             total += chunk;
             HIPCHK(hipMemcpyAsync(h_pcg, pcg, sizeof(PcgDev) * B, hipMemcpyDeviceToHost, st));
@@ -1308,6 +1356,7 @@ struct Solver : SolverBase {
             std::memset(&c[b], 0, sizeof(CgDev));
             c[b].beta = 0.5;
             c[b].alpha = 0.0;
+            c[b].max_it = -1;           // the passes keep these scalars fixed
             c[b].done = rd[b] ? 0 : 1;
         }
         HIPCHK(hipStreamSynchronize(st));
@@ -1322,6 +1371,7 @@ struct Solver : SolverBase {
         a.tw = tw + (three ? plz.tw_off : ply.tw_off);
         a.contiguous = three ? 0 : 1;
         a.lines = three ? tlz : tly;
+        a.threads = three ? thr_z : thr_y;
         const dim3 grid = three ? dim3((unsigned)(g.nxh * ((g.ny + tlz - 1) / tlz)), 1, B)
                                 : dim3((unsigned)((g.nxh * (long long)g.nz + tly - 1) / tly), 1, B);
         for (int i = 0; i < repeat; ++i) {
@@ -1383,9 +1433,9 @@ static int validate(const rve_config* c, std::string& why) {
 template <typename T>
 static int geom_check(const rve_config* c, Geom& g, int& nbx, std::string& why) {
     AxisPlan a, b, d;
-    int RB, mx, ty, my, tz, mz;
+    int RB, mx, ty, my, tz, mz, t1, t2, t3;
     size_t lx, ly, lz;
-    if (!Solver<T>::make_geom(*c, g, a, b, d, RB, nbx, mx, lx, ty, my, ly, tz, mz, lz, why))
+    if (!Solver<T>::make_geom(*c, g, a, b, d, RB, nbx, mx, lx, ty, my, ly, tz, mz, lz, t1, t2, t3, why))
         return RVE_EINVAL;
     return RVE_OK;
 }
