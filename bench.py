@@ -30,6 +30,7 @@ HBM_PEAK_GBS = 8000.0
 PASS_NAMES = {3: "x-forward + constitutive + CG direction (k_xfwd)",
               1: "axis pass: y FFT, projection, inverse y FFT (k_axis)",
               4: "x-inverse + CG update (k_xinv)"}
+PASS_SYMBOLS = {3: "k_xfwd", 1: "k_axis", 4: "k_xinv"}
 
 
 def _workloads(size, batch, seed0=1):
@@ -65,9 +66,57 @@ def roofline(r, torch, repeat=50):
     gbs = nbytes / (ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": PASS_NAMES[dom], "avg_us": round(ms * 1e3, 2),
+            "kernel": PASS_NAMES[dom], "kernel_symbol": PASS_SYMBOLS[dom],
+            "avg_us": round(ms * 1e3, 2),
             "bytes_per_launch": nbytes,
             "passes_us": {PASS_NAMES[k]: round(v[0] * 1e3, 2) for k, v in res.items()}}
+
+
+def copy_bandwidth(torch, mib=1024, repeat=10):
+    """Plain device-to-device copy of `mib` MiB (beyond the 256 MB last-level
+    cache): the measured HBM bandwidth the roofline is also quoted against."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(repeat):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / repeat
+    del src, dst
+    return round(2 * n * 8 / (ms * 1e-3) / 1e9, 1)
+
+
+def stored_traffic(kernel_file):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if it was taken on the current
+    kernel sources (else None)."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", kernel_file)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(os.path.join(here, "paper_2508_07424_amd", "csrc"))):
+        with open(os.path.join(here, "paper_2508_07424_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    if vals.get("csrc_sha256") != h.hexdigest():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(w, seconds):
@@ -105,6 +154,8 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="set up the batch and time the Green-operator passes only (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -119,6 +170,11 @@ def main():
     rve = mirve.from_workloads(wls, precision=prec)
     dtaus = [w.dtau for w in wls]
     torch.cuda.synchronize()
+    if args.roofline_only:
+        roof = roofline(rve, torch)
+        roof["copy_gbs"] = copy_bandwidth(torch)
+        print(json.dumps({"roofline": roof}), flush=True)
+        return
 
     for _ in range(args.warmup):
         _, st = rve.rve_step_dissipation_slots(dtaus)
@@ -136,6 +192,12 @@ def main():
     value = greenops / sec
 
     roof = roofline(rve, torch)
+    roof["copy_gbs"] = copy_bandwidth(torch)
+    roof["frac_of_copy"] = round(roof["achieved"] / roof["copy_gbs"], 4)
+    tag = "f64" if prec == mirve.RVE_PREC_FP64 else "mixed"
+    roof["traffic"] = stored_traffic("traffic_%s_%dx%d_b%d_%s.txt" % (
+        roof["kernel_symbol"], args.size, args.size, args.batch, tag))
+    op_s = sum(v for v in roof["passes_us"].values()) * 1e-6
     out = {
         "metric": "voxel-iter/s FFT Green-op solve",
         "value": round(value, 1),
@@ -154,7 +216,8 @@ def main():
                    "batch": args.batch, "precision": args.precision,
                    "rve_steps_per_s": round(args.batch * args.steps / sec, 3),
                    "greenops_per_rve_step": round(greenops / (args.batch * args.steps) /
-                                                  (args.size * args.size), 1)},
+                                                  (args.size * args.size), 1),
+                   "operator_voxel_iter_per_s": round(rve.N * args.batch / op_s, 1)},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

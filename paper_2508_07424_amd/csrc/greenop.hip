@@ -119,6 +119,16 @@ __device__ __forceinline__ void freq_dir(const Geom& g, int kx, int ky, int kz, 
     n3 = T(x3 / nr);
 }
 
+// Consecutive workgroups of a launch go to the eight XCDs in turn, and each
+// XCD has its own L2.  Renumbering the x index so that the workgroups one XCD
+// receives cover consecutive row groups lets neighbouring groups, which share
+// the cache lines of the transposed spectrum, meet in the same L2.  A
+// bijection of [0, n) when n is a multiple of 8, else the identity.
+__device__ __forceinline__ int xcd_group(int bx, int n) {
+    if (n & 7) return bx;
+    return (bx & 7) * (n >> 3) + (bx >> 3);
+}
+
 // ---------------------------------------------------------------------------
 // x-forward pass
 // ---------------------------------------------------------------------------
@@ -138,7 +148,8 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
     const int nrows = ny * nz;
     const int RB = a.rows_per_block;
     const int npairs = RB / 2;
-    const int r0 = blockIdx.x * RB;
+    const int grp = xcd_group(blockIdx.x, gridDim.x);
+    const int r0 = grp * RB;
     const int LS = lds_line(nx);
     const long long N = g.N;
     const long long so = (long long)b * N;
@@ -219,7 +230,7 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
     }
     if (MODE == XF_CG) {
         double pv[1] = {part};
-        block_sum_store<1>(pv, a.partials + (long long)b * a.nblocks, 0, blockIdx.x);
+        block_sum_store<1>(pv, a.partials + (long long)b * a.nblocks, 0, grp);
     }
 }
 
@@ -282,8 +293,9 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
     } else {
         // z lines at fixed (kx, y), y in a tile of TL columns; LDS line (c, tl)
         const int nyt = (ny + TL - 1) / TL;
-        const int kx = blockIdx.x / nyt;
-        const int y0 = (blockIdx.x % nyt) * TL;
+        const int tile = xcd_group(blockIdx.x, gridDim.x);
+        const int kx = tile / nyt;
+        const int y0 = (tile % nyt) * TL;
         const int W = S * TL;
         const long long base = (long long)kx * nz * ny + y0;
         for (int e = threadIdx.x; e < W * Na; e += blockDim.x) {
@@ -335,7 +347,8 @@ __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
     const int nrows = ny * nz;
     const int RB = a.rows_per_block;
     const int npairs = RB / 2;
-    const int r0 = blockIdx.x * RB;
+    const int grp = xcd_group(blockIdx.x, gridDim.x);
+    const int r0 = grp * RB;
     const int LS = lds_line(nx);
     const cplx<T>* sp = a.spec + (long long)b * S * g.Nspec;
 
@@ -384,7 +397,7 @@ __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
         }
     }
     double pv[1] = {part};
-    block_sum_store<1>(pv, a.partials + (long long)b * a.nblocks, 0, blockIdx.x);
+    block_sum_store<1>(pv, a.partials + (long long)b * a.nblocks, 0, grp);
 }
 
 // ---------------------------------------------------------------------------
