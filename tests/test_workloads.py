@@ -1,0 +1,91 @@
+"""Host logic of the seeded workload generators: geometry only, no solver
+arithmetic.  The recipes follow the paper's prose on its microstructures
+(Sec. 5.1.2 laminates, Sec. 5.2.2 random fibres, Sec. 5.3 polycrystals) and
+the notch with crack-tip enrichment points of Sec. 4.3."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2508_07424_amd import workloads as W
+
+
+def _min_periodic_gap(placed, L):
+    gaps = []
+    for i in range(len(placed)):
+        for j in range(i):
+            (c1, r1), (c2, r2) = placed[i], placed[j]
+            d = math.sqrt(sum(W._periodic_delta(c1[k], c2[k], L[k]) ** 2 for k in range(len(L))))
+            gaps.append(d - r1 - r2)
+    return min(gaps)
+
+
+def test_small_composite_recipe():
+    w = W.composite_2d_small(seed=1)
+    assert w.n == (64, 64) and w.phase_id.shape == (64, 64) and w.phase_id.dtype == np.uint16
+    assert set(np.unique(w.phase_id)) == {0, 1}
+    assert 0.2 < w.meta["vf"] < 0.32           # 10 disks of radius 6 on 64^2
+    # 16-voxel notch on row 32, tips at its two ends, notch voxels in the matrix
+    assert w.void.sum() == 16 and w.void[32, 24:40].all()
+    assert w.phi_disc.sum() == 2 and w.phi_disc[32, 24] and w.phi_disc[32, 39]
+    assert (w.phase_id[w.void.astype(bool)] == 0).all()
+    assert w.dtau == pytest.approx(0.64)
+    # same seed, same geometry; another seed, another one
+    assert np.array_equal(W.composite_2d_small(seed=1).phase_id, w.phase_id)
+    assert not np.array_equal(W.composite_2d_small(seed=2).phase_id, w.phase_id)
+
+
+def test_rsa_disks_do_not_overlap():
+    rng = np.random.default_rng(3)
+    placed, mask = W.rsa_disks((96, 96), 1.0, rng, lambda g: g.uniform(5, 9), vf=0.3)
+    assert mask.mean() >= 0.3
+    assert _min_periodic_gap(placed, (96.0, 96.0)) >= 1.0 - 1e-12
+    # every disk's centre voxel is inside the mask, across the periodic seam too
+    for c, r in placed:
+        ix, iy = int(c[0]) % 96, int(c[1]) % 96
+        assert mask[iy, ix]
+
+
+@pytest.mark.parametrize("seed", [1, 5])
+def test_fibre_composite_256(seed):
+    w = W.composite_2d(n=256, seed=seed, E_ratio=10.0, Gc_ratio=4.0)
+    assert 0.3 <= w.meta["vf"] < 0.32
+    # r ~ U[5, 9] at vf 0.3 needs about 120 fibres on 256^2
+    assert 90 < w.meta["fibres"] < 160
+    assert w.void.sum() == 40 and w.void[128].sum() == 40
+    assert w.phases[1]["E"] == 10.0 and w.phases[1]["Gc"] == 4.0
+    assert (w.phase_id[w.void.astype(bool)] == 0).all()
+
+
+def test_laminate_layers():
+    w = W.laminate_2d(nx=64, ny=32, widths=(0.25, 0.5, 0.25), Gcs=(1, 2, 3), Es=(1, 1, 1),
+                      nus=(0.3, 0.3, 0.3))
+    assert w.meta["edges"] == [0, 16, 48, 64]
+    assert (w.phase_id[:, :16] == 0).all() and (w.phase_id[:, 16:48] == 1).all()
+    assert (w.phase_id[:, 48:] == 2).all()
+    # a notch starting at the periodic boundary has one tip
+    assert w.phi_disc.sum() == 1
+
+
+def test_polycrystal_voronoi():
+    w = W.polycrystal_2d(n=128, grains=30, seed=1000, zener=3.0, a_cleave=2.0)
+    gid = w.phase_id
+    assert len(w.phases) == 30 and gid.max() < 30
+    assert len(np.unique(gid)) >= 25            # nearly every seed owns voxels
+    for p in w.phases:
+        assert p["kind"] == "cubic" and p["C44"] == pytest.approx(0.75)
+        assert 1.0 <= p["Gc"] <= 3.0
+    # theta is constant per grain and Gc follows 1 + a cos^2(4 theta)
+    for g in np.unique(gid)[:10]:
+        t = np.unique(w.theta[gid == g])
+        assert t.size == 1
+        assert w.phases[g]["Gc"] == pytest.approx(1 + 2.0 * math.cos(4 * t[0]) ** 2)
+
+
+def test_composite_3d_small():
+    w = W.composite_3d(n=32, seed=1, spheres=6, vf=0.2)
+    assert w.phase_id.shape == (32, 32, 32)
+    assert w.void[16].sum() == 16 * 16 and w.void.sum() == 256
+    # crack front: the boundary ring of the square notch
+    assert w.phi_disc.sum() == 4 * 16 - 4
+    assert list(w.f) == [0, 0, 1, 0, 0, 0]
