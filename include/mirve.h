@@ -67,6 +67,12 @@ extern "C" {
 #define RVE_SPLIT_VOLDEV 1 /* volumetric split: only K<tr eps>_+^2 and the deviatoric
                               energy are degraded and drive damage                  */
 
+/* preconditioner of the damage solve (Eq. 16b) */
+#define RVE_PRECOND_FFT    0 /* diag^-1/2 F^-1 [1 / (abar + bbar |d(xi)|^2)] F diag^-1/2, with
+                                abar = mean(Gc/l + 2H), bbar = mean(Gc) l and d the
+                                forward-difference symbols (the default)                */
+#define RVE_PRECOND_JACOBI 1 /* the inverse diagonal of the damage operator          */
+
 /* phase kinds */
 #define RVE_PHASE_ISO   0  /* isotropic: E, nu                                */
 #define RVE_PHASE_CUBIC 1  /* cubic: C11, C12, C44 in lattice axes; rotated by
@@ -108,6 +114,7 @@ typedef struct {
                               (phase, theta, notch) combinations, <= 65536          */
     int    batch;          /* RVE slots of this handle (same grid, own microstructure
                               and state), advanced together by every launch; 1-1024  */
+    int    damage_precond; /* RVE_PRECOND_* of the damage solve                      */
 } rve_config;
 
 typedef struct {

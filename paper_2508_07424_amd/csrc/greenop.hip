@@ -119,6 +119,26 @@ __device__ __forceinline__ void freq_dir(const Geom& g, int kx, int ky, int kz, 
     n3 = T(x3 / nr);
 }
 
+// Symbol of the damage preconditioner at frequency (kx, ky, kz):
+// 1 / (abar + bbar |d|^2), |d_j|^2 = 4 sin^2(pi k_j / N_j) / h^2 for the
+// forward differences of the damage operator (Sec. 4.1, Eq. 24 R2).
+template <typename T>
+__device__ __forceinline__ T sinpi_t(T v);
+template <>
+__device__ __forceinline__ double sinpi_t<double>(double v) { return sinpi(v); }
+template <>
+__device__ __forceinline__ float sinpi_t<float>(float v) { return sinpif(v); }
+
+template <typename T>
+__device__ __forceinline__ T precond_symbol(const Geom& g, int kx, int ky, int kz, double abar,
+                                            double bbar) {
+    const T sx = sinpi_t<T>(T(kx) / T(g.nx));
+    const T sy = sinpi_t<T>(T(ky) / T(g.ny));
+    const T sz = g.dim == 3 ? sinpi_t<T>(T(kz) / T(g.nz)) : T(0);
+    const T d2 = T(4.0 / (g.h * g.h)) * (sx * sx + sy * sy + sz * sz);
+    return T(1) / (T(abar) + T(bbar) * d2);
+}
+
 // Consecutive workgroups of a launch go to the eight XCDs in turn, and each
 // XCD has its own L2.  Renumbering the x index so that the workgroups one XCD
 // receives cover consecutive row groups lets neighbouring groups, which share
@@ -139,8 +159,12 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const Geom& g = a.g;
     const int b = blockIdx.y;
+    const int k = a.iter;
+    constexpr bool PCG = MODE == XF_PCG || MODE == XF_PCG0;
     if (MODE == XF_CG) {
-        if (a.cg[b].done) return;
+        if (a.cg[b].conv <= k) return;
+    } else if (PCG) {
+        if (a.pcg[b].conv <= k) return;
     } else if (a.active && !a.active[b]) {
         return;
     }
@@ -158,18 +182,65 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
     const uint16_t* mid = a.mat_id + so;
     const T* phi = a.phi + so;
 
-    T beta = T(0);
+    // CG: beta = rr_k / rr_{k-1} and the stopping test, from the r.r
+    // partials of the previous x-inverse pass.  PCG: alpha = rz_k / p.q.
+    T beta = T(0), alpha = T(0);
     bool first = false;
     if (MODE == XF_CG) {
-        beta = T(a.cg[b].beta);
-        first = a.cg[b].first != 0;
+        const CgDev& cg = a.cg[b];
+        if (cg.max_it < 0) {
+            beta = T(0.5);                       // timing run
+        } else if (k == 0) {
+            first = true;
+        } else {
+            double rr[1];
+            block_sum_all<1>(a.rr_part + (long long)b * a.nblocks, 0, a.nblocks, rr);
+            int stop = 0;
+            if (!isfinite(rr[0])) stop = 2;
+            else if (rr[0] <= cg.tol2 * cg.bn2) stop = 1;
+            else if (k >= cg.max_it) stop = 3;
+            const double prev = cg.rr_hist[(k - 1) & 1];
+            if (threadIdx.x == 0) {
+                CgDev* w = const_cast<CgDev*>(a.cg) + b;
+                w->rr_hist[k & 1] = rr[0];
+                w->rr = rr[0];
+                if (stop) {
+                    w->status = stop;
+                    w->conv = k;
+                }
+            }
+            if (stop) return;
+            beta = T(rr[0] / prev);
+        }
+    } else if (MODE == XF_PCG) {
+        double pq[1];
+        block_sum_all<1>(a.pq_part + (long long)b * a.pq_stride, 0, a.pq_n, pq);
+        if (!(pq[0] > 0.0) || !isfinite(pq[0])) {
+            if (threadIdx.x == 0) {
+                a.pcg[b].status = 2;
+                a.pcg[b].conv = k;
+            }
+            return;
+        }
+        alpha = T(a.pcg[b].rz_hist[k & 1] / pq[0]);
     }
     double part = 0.0;
     for (int v = threadIdx.x; v < RB * nx; v += blockDim.x) {
         const int rl = v / nx, x = v - rl * nx;
         const int row = r0 + rl;
         T sig[S];
-        if (row < nrows) {
+        if (row < nrows && PCG) {
+            // damage PCG: x += alpha p, r -= alpha q; transform sc * r
+            const long long o = so + (long long)row * nx + x;
+            T rv = a.r[o];
+            if (MODE == XF_PCG) {
+                a.x[o] += alpha * a.pd[o];
+                rv -= alpha * a.q[o];
+                a.r[o] = rv;
+            }
+            part += double(rv) * double(rv);
+            sig[0] = a.sc[o] * rv;
+        } else if (row < nrows) {
             const long long idx = (long long)row * nx + x;
             const MatEntry<T>& m = mat[mid[idx]];
             const T gg = degr(phi[idx], T(g.k_res));
@@ -228,7 +299,7 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
         if (rowA < nrows) spc[rowA] = A;            // rowA = z * ny + y
         if (rowA + 1 < nrows) spc[rowA + 1] = Bv;
     }
-    if (MODE == XF_CG) {
+    if (MODE != XF_GREEN) {
         double pv[1] = {part};
         block_sum_store<1>(pv, a.partials + (long long)b * a.nblocks, 0, grp);
     }
@@ -244,7 +315,8 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const Geom& g = a.g;
     const int b = blockIdx.z;
-    if (a.cg && a.cg[b].done) return;
+    if (a.cg && a.cg[b].conv <= a.iter) return;
+    if (a.pcg && a.pcg[b].conv <= a.iter) return;
     if (a.active && !a.active[b]) return;
     const int TL = a.lines;
     const int Na = a.pl.N;
@@ -266,7 +338,21 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
         }
         __syncthreads();
         line_fft<T, F>(buf, S * TL, LS, a.pl, a.tw, inv_only);
-        if (MODE == AX_FWD_P_INV) {
+        if constexpr (MODE == AX_FWD_M_INV) {
+            const double abar = a.pcg[b].abar, bbar = a.pcg[b].bbar;
+            for (int e = threadIdx.x; e < S * TL * Na; e += blockDim.x) {
+                const int j = e % Na, tl = (e / Na) % TL, c = e / (Na * TL);
+                const long long L = L0 + tl;
+                if (L >= nlines) continue;
+                const T m = precond_symbol<T>(g, (int)(L / nz), j, (int)(L % nz), abar, bbar);
+                cplx<T>& v = buf[(c * TL + tl) * LS + lp(j)];
+                v.x *= m;
+                v.y *= m;
+            }
+            __syncthreads();
+            line_fft<T, F>(buf, S * TL, LS, a.pl, a.tw, true);
+        }
+        if constexpr (MODE == AX_FWD_P_INV) {
             for (int e = threadIdx.x; e < TL * Na; e += blockDim.x) {
                 const int j = e % Na, tl = e / Na;
                 const long long L = L0 + tl;
@@ -278,7 +364,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
 #pragma unroll
                 for (int c = 0; c < S; ++c) v[c] = buf[(c * TL + tl) * LS + lp(j)];
                 if constexpr (S == 3) project2<T>(v, n1, n2);
-                else project3<T>(v, n1, n2, n3);
+                else if constexpr (S == 6) project3<T>(v, n1, n2, n3);
 #pragma unroll
                 for (int c = 0; c < S; ++c) buf[(c * TL + tl) * LS + lp(j)] = v[c];
             }
@@ -306,7 +392,20 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
         }
         __syncthreads();
         line_fft<T, F>(buf, W, LS, a.pl, a.tw, inv_only);
-        if (MODE == AX_FWD_P_INV) {
+        if constexpr (MODE == AX_FWD_M_INV) {
+            const double abar = a.pcg[b].abar, bbar = a.pcg[b].bbar;
+            for (int e = threadIdx.x; e < W * Na; e += blockDim.x) {
+                const int tl = e % TL, c = (e / TL) % S, j = e / W;
+                if (y0 + tl >= ny) continue;
+                const T m = precond_symbol<T>(g, kx, y0 + tl, j, abar, bbar);
+                cplx<T>& v = buf[(c * TL + tl) * LS + lp(j)];
+                v.x *= m;
+                v.y *= m;
+            }
+            __syncthreads();
+            line_fft<T, F>(buf, W, LS, a.pl, a.tw, true);
+        }
+        if constexpr (MODE == AX_FWD_P_INV) {
             for (int e = threadIdx.x; e < TL * Na; e += blockDim.x) {
                 const int tl = e % TL, j = e / TL;
                 if (y0 + tl >= ny) continue;
@@ -316,7 +415,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
 #pragma unroll
                 for (int c = 0; c < S; ++c) v[c] = buf[(c * TL + tl) * LS + lp(j)];
                 if constexpr (S == 3) project2<T>(v, n1, n2);
-                else project3<T>(v, n1, n2, n3);
+                else if constexpr (S == 6) project3<T>(v, n1, n2, n3);
 #pragma unroll
                 for (int c = 0; c < S; ++c) buf[(c * TL + tl) * LS + lp(j)] = v[c];
             }
@@ -341,8 +440,27 @@ __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
     cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
     const Geom& g = a.g;
     const int b = blockIdx.y;
-    if (a.cg && a.cg[b].done) return;
-    if (a.active && !a.active[b]) return;
+    if (MODE == XI_CG) {
+        if (a.cg[b].conv <= a.iter) return;
+    } else if (MODE == XI_PCG) {
+        if (a.pcg[b].conv <= a.iter) return;
+    } else if (a.active && !a.active[b]) {
+        return;
+    }
+    // CG: alpha = rr_k / p.Ap from the partials of the x-forward pass
+    T alpha = T(0);
+    if (MODE == XI_CG && a.cg[b].max_it >= 0) {
+        double pap[1];
+        block_sum_all<1>(a.pAp_part + (long long)b * a.nblocks, 0, a.nblocks, pap);
+        if (!(pap[0] > 0.0) || !isfinite(pap[0])) {
+            if (threadIdx.x == 0) {
+                a.cg[b].status = 2;
+                a.cg[b].conv = a.iter;
+            }
+            return;
+        }
+        alpha = T(a.cg[b].rr_hist[a.iter & 1] / pap[0]);
+    }
     const int nx = g.nx, nxh = g.nxh, ny = g.ny, nz = g.nz;
     const int nrows = ny * nz;
     const int RB = a.rows_per_block;
@@ -371,8 +489,6 @@ __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
     line_fft<T, F>(buf, S * npairs, LS, a.pl, a.tw, true);
 
     const T scale = T(g.inv_N) * a.scale;
-    T alpha = T(0);
-    if (MODE == XI_CG) alpha = T(a.cg[b].alpha);
     const long long fo = (long long)b * S * g.N;
     double part = 0.0;
     for (int v = threadIdx.x; v < RB * nx; v += blockDim.x) {
@@ -388,6 +504,10 @@ __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
             if (MODE == XI_STORE) {
                 if (a.out) a.out[o] = q;
                 part += double(q) * double(q);
+            } else if (MODE == XI_PCG) {   // z = sc F^-1[...]; r.z
+                const T z = a.sc[o] * q;
+                a.out[o] = z;
+                part += double(a.r[o]) * double(z);
             } else {  // XI_CG
                 a.x[o] += alpha * a.p[o];
                 const T rn = a.r[o] - alpha * q;
@@ -440,6 +560,8 @@ static hipError_t launch_xfwd_s(const XfwdArgs<T>& a, int maxb, size_t lds, hipS
 
 template <typename T>
 hipError_t launch_xfwd(const XfwdArgs<T>& a, int mode, int maxb, size_t lds, hipStream_t st) {
+    if (mode == XF_PCG) return launch_xfwd_s<T, 1, XF_PCG>(a, maxb, lds, st);
+    if (mode == XF_PCG0) return launch_xfwd_s<T, 1, XF_PCG0>(a, maxb, lds, st);
     if (a.g.s == 3)
         return mode == XF_CG ? launch_xfwd_s<T, 3, XF_CG>(a, maxb, lds, st)
                              : launch_xfwd_s<T, 3, XF_GREEN>(a, maxb, lds, st);
@@ -453,20 +575,31 @@ static hipError_t launch_axis_s(const AxisArgs<T>& a, int maxb, dim3 grid, size_
     MIRVE_DISPATCH(k_axis, T, S, MODE, a.pl, maxb, grid, lds, st, a);
 }
 
+// The damage preconditioner (a.pcg set) transforms one scalar field.
 template <typename T>
 hipError_t launch_axis(const AxisArgs<T>& a, int mode, int maxb, dim3 grid, size_t lds,
                        hipStream_t st) {
+    if (a.pcg) {
+        switch (mode) {
+            case AX_FWD: return launch_axis_s<T, 1, AX_FWD>(a, maxb, grid, lds, st);
+            case AX_INV: return launch_axis_s<T, 1, AX_INV>(a, maxb, grid, lds, st);
+            case AX_FWD_M_INV: return launch_axis_s<T, 1, AX_FWD_M_INV>(a, maxb, grid, lds, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
     if (a.g.s == 3) {
         switch (mode) {
             case AX_FWD: return launch_axis_s<T, 3, AX_FWD>(a, maxb, grid, lds, st);
             case AX_INV: return launch_axis_s<T, 3, AX_INV>(a, maxb, grid, lds, st);
-            default: return launch_axis_s<T, 3, AX_FWD_P_INV>(a, maxb, grid, lds, st);
+            case AX_FWD_P_INV: return launch_axis_s<T, 3, AX_FWD_P_INV>(a, maxb, grid, lds, st);
+            default: return hipErrorInvalidValue;
         }
     }
     switch (mode) {
         case AX_FWD: return launch_axis_s<T, 6, AX_FWD>(a, maxb, grid, lds, st);
         case AX_INV: return launch_axis_s<T, 6, AX_INV>(a, maxb, grid, lds, st);
-        default: return launch_axis_s<T, 6, AX_FWD_P_INV>(a, maxb, grid, lds, st);
+        case AX_FWD_P_INV: return launch_axis_s<T, 6, AX_FWD_P_INV>(a, maxb, grid, lds, st);
+        default: return hipErrorInvalidValue;
     }
 }
 
@@ -478,6 +611,7 @@ static hipError_t launch_xinv_s(const XinvArgs<T>& a, int maxb, size_t lds, hipS
 
 template <typename T>
 hipError_t launch_xinv(const XinvArgs<T>& a, int mode, int maxb, size_t lds, hipStream_t st) {
+    if (mode == XI_PCG) return launch_xinv_s<T, 1, XI_PCG>(a, maxb, lds, st);
     if (a.g.s == 3)
         return mode == XI_CG ? launch_xinv_s<T, 3, XI_CG>(a, maxb, lds, st)
                              : launch_xinv_s<T, 3, XI_STORE>(a, maxb, lds, st);

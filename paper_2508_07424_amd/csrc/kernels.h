@@ -14,30 +14,47 @@ constexpr int kMaxVals = 32;       // reduction values per RVE (partials / sums 
 constexpr int kAndersonMax = 5;    // Anderson depth limit
 constexpr int kHist = kAndersonMax + 1;
 
-// Device-resident scalars of one conjugate-gradient solve (one per RVE).
+constexpr int kNotDone = 0x7fffffff;
+
+// Device-resident scalars of one Krylov solve (one per RVE).
+//
+// The kernels of iteration k receive k.  A kernel that needs a dot product
+// adds the per-block partials of the launch that produced them itself, in a
+// fixed order (every block gets the same bits), so no finalize launch sits
+// between the passes.  `conv` is the iteration at which the solve stopped
+// (kNotDone while it runs, -1 for an RVE outside the solve).  It is written
+// by block 0 of the launch that decides to stop, and read as `conv <= k`:
+// every block of that launch reaches the same decision from the same sums,
+// whether it sees the old or the new value.  Values a launch writes for
+// iteration k sit in slot k & 1, while that launch reads slot (k - 1) & 1.
 struct CgDev {
-    double rr;       // r . r of the current residual
-    double pAp;      // p . A p
-    double alpha, beta;
-    double bn2;      // ||b||^2 (stopping reference)
-    double tol2;     // tol^2
-    int it;          // iterations done
-    int done;        // 1 once converged, failed or out of iterations (or inactive)
-    int first;       // next direction update is p = r
-    int status;      // 0 running, 1 converged, 2 breakdown / non-finite, 3 max iterations
-    int max_it;
+    double rr_hist[2];   // r.r at iteration k in slot k & 1
+    double rr;           // latest r.r (progress reports)
+    double rr0;          // r.r at iteration 0
+    double bn2;          // ||b||^2 (stopping reference)
+    double tol2;         // tol^2
+    int conv;            // iteration at which the solve stopped, kNotDone, or -1
+    int status;          // 0 running, 1 converged, 2 breakdown / non-finite, 3 max iterations
+    int max_it;          // < 0: timing run (alpha = 0, beta = 1/2, never stops)
     int pad;
 };
 
-// Jacobi-preconditioned CG of the damage system (one per RVE).
+// Preconditioned CG of the damage system (one per RVE).  The FFT
+// preconditioner is 1 / (abar + bbar |d(xi)|^2) between two diagonal
+// scalings.
 struct PcgDev {
-    double rz, pq, alpha, beta, rr, bn2, tol2;
-    int it, done, status, max_it;
+    double rz_hist[2];   // r.z at iteration k in slot k & 1
+    double rr;           // latest r.r
+    double rr0;          // r.r at iteration 0
+    double bn2, tol2;
+    double abar, bbar;
+    int conv, status, max_it, pad;
 };
 
-enum { XF_GREEN = 0, XF_CG = 1 };
-enum { AX_FWD = 0, AX_INV = 1, AX_FWD_P_INV = 2 };
-enum { XI_STORE = 0, XI_CG = 1 };
+enum { XF_GREEN = 0, XF_CG = 1, XF_PCG = 2, XF_PCG0 = 3 };
+enum { AX_FWD = 0, AX_INV = 1, AX_FWD_P_INV = 2, AX_FWD_M_INV = 3 };
+enum { XI_STORE = 0, XI_CG = 1, XI_PCG = 2 };
+enum { PRE_JACOBI = 0, PRE_FFT = 1 };
 
 template <typename T>
 struct XfwdArgs {
@@ -50,9 +67,19 @@ struct XfwdArgs {
     const T* eps;        // XF_GREEN: strain field (s*N per RVE) or null
     T fcoef;             // XF_GREEN: + fcoef * f
     T f[6];
-    const T* r;          // XF_CG
-    T* p;                // XF_CG (updated in place)
-    const CgDev* cg;     // XF_CG: per-RVE state; XF_GREEN: null
+    T* r;                // XF_CG: residual; XF_PCG*: damage residual (updated in place)
+    T* p;                // XF_CG: direction (updated in place)
+    T* x;                // XF_PCG: damage iterate (updated in place)
+    const T* pd;         // XF_PCG: damage direction
+    const T* q;          // XF_PCG: A pd
+    const T* sc;         // XF_PCG*: diagonal scaling of the preconditioner
+    const CgDev* cg;     // XF_CG
+    PcgDev* pcg;         // XF_PCG*
+    const double* rr_part;   // XF_CG: r.r partials of the previous x-inverse ([B][nblocks])
+    const double* pq_part;   // XF_PCG: p.q partials, RVE b at pq_part + b * pq_stride
+    long long pq_stride;
+    int pq_n;
+    int iter;
     const int* active;   // XF_GREEN: optional per-RVE mask
     cplx<T>* spec;
     double* partials;    // [B][nblocks]
@@ -67,7 +94,9 @@ struct AxisArgs {
     AxisPlan pl;
     const cplx<T>* tw;
     cplx<T>* spec;
-    const CgDev* cg;     // skip RVE b when cg && cg[b].done
+    const CgDev* cg;     // skip RVE b when cg[b].conv <= iter
+    const PcgDev* pcg;   // or pcg[b].conv <= iter; AX_FWD_M_INV takes abar, bbar here
+    int iter;
     const int* active;   // or when active && !active[b]
     int contiguous;      // 1: y lines (stride 1); 0: z lines (stride n_y)
     int lines;           // lines per block (y pass) / y columns per block (z pass)
@@ -81,11 +110,15 @@ struct XinvArgs {
     const cplx<T>* tw;
     const cplx<T>* spec;
     T scale;             // multiplies the (normalised) inverse
-    T* out;              // XI_STORE (may be null: norm only)
+    T* out;              // XI_STORE (may be null: norm only); XI_PCG: z
     T* x;                // XI_CG
     const T* p;          // XI_CG
-    T* r;                // XI_CG
-    const CgDev* cg;
+    T* r;                // XI_CG (updated); XI_PCG: read for r.z
+    const T* sc;         // XI_PCG: diagonal scaling
+    CgDev* cg;           // XI_CG
+    const PcgDev* pcg;   // XI_PCG
+    const double* pAp_part;  // XI_CG: p.Ap partials of the x-forward pass ([B][nblocks])
+    int iter;
     const int* active;
     double* partials;    // [B][nblocks]
     int rows_per_block;
@@ -106,10 +139,9 @@ hipError_t launch_xinv(const XinvArgs<T>& a, int mode, int maxb, size_t lds, hip
 // ---------------------------------------------------------------------------
 
 // CG partials are [B][n] (one per block of the pass that made them).
+// rr_hist[0] = r.r, conv = 0 if already converged (else kNotDone, -1 when inactive)
 hipError_t launch_cg_init(CgDev* cg, const double* prr, const double* pb, int n, int B,
                           double tol, int max_it, const int* active, hipStream_t st);
-hipError_t launch_cg_alpha(CgDev* cg, const double* partials, int n, int B, hipStream_t st);
-hipError_t launch_cg_beta(CgDev* cg, const double* partials, int n, int B, hipStream_t st);
 // sums[b*kMaxVals + v] = sum_k partials[(b*kMaxVals + v)*kRedBlocks + k], v < nv
 hipError_t launch_sum_partials(const double* partials, int n, int nv, int B, double* sums,
                                const int* active, hipStream_t st);
@@ -119,11 +151,12 @@ hipError_t launch_sum_rows(const double* p, int n, int B, double* sums, int slot
 hipError_t launch_max_partials(const double* partials, int n, int B, double* sums,
                                const int* active, hipStream_t st);
 
-// Damage PCG partials use the kMaxVals layout above.
+// Damage PCG partials use the kMaxVals layout above: value 0 p.q, 1 r.z,
+// 2 r.r, 3 b.b, 4 the diagonal term a(x), 5 the gradient weight w(x).
+// Sets bn2, tol2, conv, status, max_it and the FFT preconditioner constants
+// abar = mean a(x), bbar = mean w(x).
 hipError_t launch_pcg_fin_start(PcgDev* d, const double* partials, int n, int B, double tol,
-                                int max_it, const int* active, hipStream_t st);
-hipError_t launch_pcg_fin_alpha(PcgDev* d, const double* partials, int n, int B, hipStream_t st);
-hipError_t launch_pcg_fin_beta(PcgDev* d, const double* partials, int n, int B, hipStream_t st);
+                                int max_it, double inv_N, const int* active, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // pointwise / stencil kernels; `nred` blocks per RVE for reductions
@@ -148,30 +181,38 @@ hipError_t launch_history(const Geom& g, const T* psi1, const T* psi_ini, const 
 
 // Damage operator q = a(x) p + D^T (w(x) D p): mode 0 a = Gc/l + 2H (H may be
 // null), w = Gc l; mode 1 a = 1, w = c (the enrichment smoothing).
+// damage_diag: dinv = 1 / diag (Jacobi) or its square root (FFT scaling);
+// partials of a(x) (value 4) and w(x) (value 5).
 template <typename T>
 hipError_t launch_damage_diag(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                              const T* H, int mode, double c, T* dinv, const int* active,
-                              hipStream_t st);
+                              const T* H, int mode, double c, int sqrt_out, T* dinv,
+                              double* partials, int nred, const int* active, hipStream_t st);
 template <typename T>
 hipError_t launch_pcg_matvec(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
                              const T* H, int mode, double c, const T* p, T* q, double* partials,
                              int nred, const PcgDev* d, const int* active, hipStream_t st);
-// r = b - Ax, p = dinv r; partials r.z, r.r, b.b
+// r = b - Ax; partials r.(dinv r), r.r, b.b
 template <typename T>
-hipError_t launch_pcg_start(const Geom& g, const T* b, const T* Ax, const T* dinv, T* r, T* p,
+hipError_t launch_pcg_start(const Geom& g, const T* b, const T* Ax, const T* dinv, T* r,
                             double* partials, int nred, const int* active, hipStream_t st);
-// One PCG iteration: (1) direction and operator: p_new = dinv r + beta p_old
-// evaluated at the voxel and its stencil neighbours, q = A p_new, partials
-// p.q; (2) alpha; (3) update: x += alpha p, r -= alpha q, partials r.z, r.r;
-// (4) beta and convergence.
+// Iteration k, step 1: r.z and r.r from the partials the previous step left
+// (RVE b at rz_part + b * rz_stride, rz_n values; likewise r.r), the stopping
+// test, beta = rz_k / rz_{k-1}; then the direction p_new = z + beta p_old
+// evaluated at the voxel and its stencil neighbours (z = dinv r for Jacobi,
+// the stored field zf for the FFT preconditioner), q = A p_new, partials p.q
+// (value 0).
 template <typename T>
 hipError_t launch_pcg_matvec_dir(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                                 const T* H, int mode, double c, const T* r, const T* dinv,
-                                 const T* p_old, T* p_new, T* q, double* partials, int nred,
-                                 const PcgDev* d, hipStream_t st);
+                                 const T* H, int mode, double c, int pre, const T* r,
+                                 const T* dinv, const T* zf, const T* p_old, T* p_new, T* q,
+                                 const double* rz_part, long long rz_stride, int rz_n,
+                                 const double* rr_part, long long rr_stride, int rr_n,
+                                 double* partials, int nred, PcgDev* d, int iter, hipStream_t st);
+// Iteration k, step 2 (Jacobi): alpha = rz_k / p.q, x += alpha p,
+// r -= alpha q, partials r.(dinv r) (value 1) and r.r (value 2).
 template <typename T>
-hipError_t launch_pcg_update(const Geom& g, const PcgDev* d, T* x, T* r, const T* p, const T* q,
-                             const T* dinv, double* partials, int nred, hipStream_t st);
+hipError_t launch_pcg_update(const Geom& g, PcgDev* d, T* x, T* r, const T* p, const T* q,
+                             const T* dinv, double* partials, int nred, int iter, hipStream_t st);
 
 // D(phi) (value 0) and Gamma(phi) (value 1) partials without the h^d factor.
 template <typename T>

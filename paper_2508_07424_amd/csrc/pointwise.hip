@@ -1,7 +1,7 @@
 // Pointwise and stencil kernels: unit response, history, the damage
-// operator and its Jacobi-preconditioned CG, the AT2 functionals, the
-// crack-tip enrichment energy, Anderson mixing, fracture test and the
-// finalize kernels of the device-side Krylov scalars.
+// operator and the stencil steps of its preconditioned CG, the AT2
+// functionals, the crack-tip enrichment energy, Anderson mixing, fracture
+// test and the start-up kernels of the device-side Krylov scalars.
 //
 // Damage derivatives are forward differences with periodic wrap; the
 // operator L(phi) = -div(G_c l grad phi) (Eq. 10b, 17) is D^T diag(G_c l) D,
@@ -9,8 +9,8 @@
 // are the same linear map).
 //
 // Batches: blockIdx.y is the RVE; reductions write per-block partial sums to
-// partials[(b * kMaxVals + v) * kRedBlocks + block] and a finalize kernel
-// (one block per RVE) adds them in a fixed order.
+// partials[(b * kMaxVals + v) * kRedBlocks + block], which a one-block-per-RVE
+// kernel, or the next iteration's kernel itself, adds in a fixed order.
 #include <cfloat>
 #include "kernels.h"
 #include "reduce.h"
@@ -97,24 +97,23 @@ __global__ void k_cg_init(CgDev* cgs, const double* prr, const double* pb, int n
     const int b = blockIdx.x;
     CgDev* cg = cgs + b;
     if (skip(active, b)) {
-        if (threadIdx.x == 0) { cg->done = 1; cg->status = 0; cg->it = 0; }
+        if (threadIdx.x == 0) { cg->conv = -1; cg->status = 0; }
         return;
     }
     const double rr = sum_fixed(prr + (long long)b * n, n);
     const double bn2 = sum_fixed(pb + (long long)b * n, n);
     if (threadIdx.x != 0) return;
+    cg->rr_hist[0] = rr;
+    cg->rr_hist[1] = rr;
     cg->rr = rr;
+    cg->rr0 = rr;
     cg->bn2 = bn2;
     cg->tol2 = tol * tol;
-    cg->it = 0;
-    cg->first = 1;
-    cg->beta = 0.0;
-    cg->alpha = 0.0;
     cg->max_it = max_it;
     cg->status = 0;
-    cg->done = 0;
-    if (!isfinite(rr) || !isfinite(bn2)) { cg->done = 1; cg->status = 2; }
-    else if (rr <= cg->tol2 * bn2) { cg->done = 1; cg->status = 1; }
+    cg->conv = kNotDone;
+    if (!isfinite(rr) || !isfinite(bn2)) { cg->conv = 0; cg->status = 2; }
+    else if (rr <= cg->tol2 * bn2) { cg->conv = 0; cg->status = 1; }
 }
 
 hipError_t launch_cg_init(CgDev* cg, const double* prr, const double* pb, int n, int B,
@@ -159,108 +158,30 @@ hipError_t launch_max_partials(const double* p, int n, int B, double* sums, cons
 }
 
 __global__ void k_pcg_fin_start(PcgDev* ds, const double* p, int n, double tol, int max_it,
-                                const int* active) {
+                                double inv_N, const int* active) {
     const int b = blockIdx.x;
     PcgDev* d = ds + b;
     if (skip(active, b)) {
-        if (threadIdx.x == 0) { d->done = 1; d->status = 0; d->it = 0; }
+        if (threadIdx.x == 0) { d->conv = -1; d->status = 0; }
         return;
     }
     const double* pb = p + (long long)b * kMaxVals * kRedBlocks;
-    const double rz = sum_fixed(pb, n);
-    const double rr = sum_fixed(pb + kRedBlocks, n);
-    const double bn2 = sum_fixed(pb + 2 * kRedBlocks, n);
+    const double bn2 = sum_fixed(pb + 3 * kRedBlocks, n);
+    const double asum = sum_fixed(pb + 4 * kRedBlocks, n);
+    const double wsum = sum_fixed(pb + 5 * kRedBlocks, n);
     if (threadIdx.x != 0) return;
-    d->rz = rz;
-    d->rr = rr;
     d->bn2 = bn2;
     d->tol2 = tol * tol;
-    d->beta = 0.0;
-    d->it = 0;
+    d->abar = asum * inv_N;
+    d->bbar = wsum * inv_N;
     d->max_it = max_it;
     d->status = 0;
-    d->done = 0;
-    if (!isfinite(rr) || !isfinite(rz)) { d->done = 1; d->status = 2; }
-    else if (rr <= d->tol2 * bn2) { d->done = 1; d->status = 1; }
+    d->conv = kNotDone;
 }
 hipError_t launch_pcg_fin_start(PcgDev* d, const double* p, int n, int B, double tol, int max_it,
-                                const int* active, hipStream_t st) {
-    hipLaunchKernelGGL(k_pcg_fin_start, dim3(B), dim3(256), 0, st, d, p, n, tol, max_it, active);
-    return hipGetLastError();
-}
-
-__global__ void k_pcg_fin_alpha(PcgDev* ds, const double* p, int n) {
-    const int b = blockIdx.x;
-    PcgDev* d = ds + b;
-    if (d->done) return;
-    const double pq = sum_fixed(p + (long long)b * kMaxVals * kRedBlocks, n);
-    if (threadIdx.x != 0) return;
-    d->pq = pq;
-    if (!(pq > 0.0) || !isfinite(pq)) { d->done = 1; d->status = 2; d->alpha = 0.0; return; }
-    d->alpha = d->rz / pq;
-}
-hipError_t launch_pcg_fin_alpha(PcgDev* d, const double* p, int n, int B, hipStream_t st) {
-    hipLaunchKernelGGL(k_pcg_fin_alpha, dim3(B), dim3(256), 0, st, d, p, n);
-    return hipGetLastError();
-}
-
-__global__ void k_pcg_fin_beta(PcgDev* ds, const double* p, int n) {
-    const int b = blockIdx.x;
-    PcgDev* d = ds + b;
-    if (d->done) return;
-    const double* pb = p + (long long)b * kMaxVals * kRedBlocks;
-    const double rz = sum_fixed(pb, n);
-    const double rr = sum_fixed(pb + kRedBlocks, n);
-    if (threadIdx.x != 0) return;
-    d->beta = rz / d->rz;
-    d->rz = rz;
-    d->rr = rr;
-    d->it += 1;
-    if (!isfinite(rr) || !isfinite(rz)) { d->done = 1; d->status = 2; }
-    else if (rr <= d->tol2 * d->bn2) { d->done = 1; d->status = 1; }
-    else if (d->it >= d->max_it) { d->done = 1; d->status = 3; }
-}
-hipError_t launch_pcg_fin_beta(PcgDev* d, const double* p, int n, int B, hipStream_t st) {
-    hipLaunchKernelGGL(k_pcg_fin_beta, dim3(B), dim3(256), 0, st, d, p, n);
-    return hipGetLastError();
-}
-
-__global__ void k_cg_alpha(CgDev* cgs, const double* p, int n) {
-    const int b = blockIdx.x;
-    CgDev* cg = cgs + b;
-    if (cg->done) return;
-    const double pAp = sum_fixed(p + (long long)b * n, n);
-    if (threadIdx.x != 0 || cg->max_it < 0) return;      // max_it < 0: timing run
-    cg->pAp = pAp;
-    if (!(pAp > 0.0) || !isfinite(pAp)) {
-        cg->done = 1;
-        cg->status = 2;
-        cg->alpha = 0.0;
-        return;
-    }
-    cg->alpha = cg->rr / pAp;
-}
-hipError_t launch_cg_alpha(CgDev* cg, const double* p, int n, int B, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_alpha, dim3(B), dim3(256), 0, st, cg, p, n);
-    return hipGetLastError();
-}
-
-__global__ void k_cg_beta(CgDev* cgs, const double* p, int n) {
-    const int b = blockIdx.x;
-    CgDev* cg = cgs + b;
-    if (cg->done) return;
-    const double rr = sum_fixed(p + (long long)b * n, n);
-    if (threadIdx.x != 0 || cg->max_it < 0) return;
-    cg->beta = rr / cg->rr;
-    cg->rr = rr;
-    cg->first = 0;
-    cg->it += 1;
-    if (!isfinite(rr)) { cg->done = 1; cg->status = 2; }
-    else if (rr <= cg->tol2 * cg->bn2) { cg->done = 1; cg->status = 1; }
-    else if (cg->it >= cg->max_it) { cg->done = 1; cg->status = 3; }
-}
-hipError_t launch_cg_beta(CgDev* cg, const double* p, int n, int B, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_beta, dim3(B), dim3(256), 0, st, cg, p, n);
+                                double inv_N, const int* active, hipStream_t st) {
+    hipLaunchKernelGGL(k_pcg_fin_start, dim3(B), dim3(256), 0, st, d, p, n, tol, max_it, inv_N,
+                       active);
     return hipGetLastError();
 }
 
@@ -411,7 +332,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_matvec(Geom g, const uint16_t* mat_
                                                     const PcgDev* d, const int* active) {
     const int b = blockIdx.y;
     if (skip(active, b)) return;
-    if (d && d[b].done) return;
+    if (d && d[b].conv != kNotDone) return;
     RVE_OFFSETS
     const T* Hb = H ? H + so : nullptr;
     double part = 0.0;
@@ -439,33 +360,42 @@ hipError_t launch_pcg_matvec(const Geom& g, const uint16_t* mat_id, const MatEnt
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_damage_diag(Geom g, const uint16_t* mat_id,
                                                      const MatEntry<T>* mat, const T* H, int mode,
-                                                     T c, T* dinv, const int* active) {
+                                                     T c, int sqrt_out, T* dinv, double* partials,
+                                                     const int* active) {
     const int b = blockIdx.y;
     if (skip(active, b)) return;
-    const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (i >= g.N) return;
     RVE_OFFSETS
-    T a, w;
-    coeffs(g, mt, mid, H ? H + so : (const T*)nullptr, mode, c, i, a, w);
-    const Nb n = neighbours(g, i);
+    const T* Hb = H ? H + so : (const T*)nullptr;
     const T ell = T(g.ell);
-    T s = T(2) * w + wcoef(mt, mid, mode, ell, c, n.xm) + wcoef(mt, mid, mode, ell, c, n.ym);
-    if (g.dim == 3) s += w + wcoef(mt, mid, mode, ell, c, n.zm);
-    dinv[so + i] = T(1) / (a + s * T(1.0 / (g.h * g.h)));
+    double sa = 0.0, sw = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.N;
+         i += (long long)gridDim.x * blockDim.x) {
+        T a, w;
+        coeffs(g, mt, mid, Hb, mode, c, i, a, w);
+        const Nb n = neighbours(g, i);
+        T s = T(2) * w + wcoef(mt, mid, mode, ell, c, n.xm) + wcoef(mt, mid, mode, ell, c, n.ym);
+        if (g.dim == 3) s += w + wcoef(mt, mid, mode, ell, c, n.zm);
+        const T di = T(1) / (a + s * T(1.0 / (g.h * g.h)));
+        dinv[so + i] = sqrt_out ? sqrt(di) : di;
+        sa += double(a);
+        sw += double(w);
+    }
+    double pv[2] = {sa, sw};
+    block_sum_store<2>(pv, pslot(partials, b, 4), kRedBlocks, blockIdx.x);
 }
 
 template <typename T>
 hipError_t launch_damage_diag(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                              const T* H, int mode, double c, T* dinv, const int* active,
-                              hipStream_t st) {
-    hipLaunchKernelGGL((k_damage_diag<T>), dim3(blocks_for(g.N), g.B), dim3(TPB), 0, st, g,
-                       mat_id, mat, H, mode, T(c), dinv, active);
+                              const T* H, int mode, double c, int sqrt_out, T* dinv,
+                              double* partials, int nred, const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_damage_diag<T>), dim3(nred, g.B), dim3(TPB), 0, st, g, mat_id, mat, H,
+                       mode, T(c), sqrt_out, dinv, partials, active);
     return hipGetLastError();
 }
 
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_pcg_start(long long N, const T* bv, const T* Ax,
-                                                   const T* dinv, T* r, T* p, double* partials,
+                                                   const T* dinv, T* r, double* partials,
                                                    const int* active) {
     const int b = blockIdx.y;
     if (skip(active, b)) return;
@@ -476,62 +406,82 @@ __global__ void __launch_bounds__(TPB) k_pcg_start(long long N, const T* bv, con
         const long long o = so + i;
         const T bi = bv[o];
         const T ri = bi - Ax[o];
-        const T zi = dinv[o] * ri;
         r[o] = ri;
-        p[o] = zi;
-        s0 += double(ri) * double(zi);
+        s0 += double(ri) * double(dinv[o] * ri);
         s1 += double(ri) * double(ri);
         s2 += double(bi) * double(bi);
     }
     double pv[3] = {s0, s1, s2};
-    block_sum_store<3>(pv, pslot(partials, b, 0), kRedBlocks, blockIdx.x);
+    block_sum_store<3>(pv, pslot(partials, b, 1), kRedBlocks, blockIdx.x);
 }
 
 template <typename T>
-hipError_t launch_pcg_start(const Geom& g, const T* b, const T* Ax, const T* dinv, T* r, T* p,
+hipError_t launch_pcg_start(const Geom& g, const T* b, const T* Ax, const T* dinv, T* r,
                             double* partials, int nred, const int* active, hipStream_t st) {
     hipLaunchKernelGGL((k_pcg_start<T>), dim3(nred, g.B), dim3(TPB), 0, st, g.N, b, Ax, dinv, r,
-                       p, partials, active);
+                       partials, active);
     return hipGetLastError();
 }
 
-// p_new = dinv r + beta p_old evaluated at any voxel
-template <typename T>
-__device__ __forceinline__ T pdir(const T* r, const T* dinv, const T* p_old, T beta, long long j) {
-    return dinv[j] * r[j] + beta * p_old[j];
+// z at any voxel: dinv r (Jacobi) or the stored preconditioned residual
+template <typename T, int PRE>
+__device__ __forceinline__ T zval(const T* r, const T* dinv, const T* zf, long long j) {
+    if constexpr (PRE == PRE_JACOBI) return dinv[j] * r[j];
+    else return zf[j];
 }
 
-template <typename T>
-__global__ void __launch_bounds__(TPB) k_pcg_matvec_dir(Geom g, const uint16_t* mat_id,
-                                                        const MatEntry<T>* mat, const T* H,
-                                                        int mode, T c, const T* r_a,
-                                                        const T* dinv_a, const T* po_a, T* pn_a,
-                                                        T* q_a, double* partials,
-                                                        const PcgDev* d) {
+template <typename T, int PRE>
+__global__ void __launch_bounds__(TPB) k_pcg_matvec_dir(
+    Geom g, const uint16_t* mat_id, const MatEntry<T>* mat, const T* H, int mode, T c,
+    const T* r_a, const T* dinv_a, const T* zf_a, const T* po_a, T* pn_a, T* q_a,
+    const double* rz_part, long long rz_stride, int rz_n, const double* rr_part,
+    long long rr_stride, int rr_n, double* partials, PcgDev* d, int k) {
     const int b = blockIdx.y;
-    if (d[b].done) return;
+    if (d[b].conv <= k) return;
+    // r.z and r.r of the residual left by the previous step; stopping test
+    double rz[1], rr[1];
+    block_sum_all<1>(rz_part + (long long)b * rz_stride, 0, rz_n, rz);
+    block_sum_all<1>(rr_part + (long long)b * rr_stride, 0, rr_n, rr);
+    int stop = 0;
+    if (!isfinite(rr[0]) || !isfinite(rz[0])) stop = 2;
+    else if (rr[0] <= d[b].tol2 * d[b].bn2) stop = 1;
+    else if (k >= d[b].max_it) stop = 3;
+    const double prev = k > 0 ? d[b].rz_hist[(k - 1) & 1] : 1.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        d[b].rz_hist[k & 1] = rz[0];
+        d[b].rr = rr[0];
+        if (k == 0) d[b].rr0 = rr[0];
+        if (stop) {
+            d[b].status = stop;
+            d[b].conv = k;
+        }
+    }
+    if (stop) return;
+    const T beta = k > 0 ? T(rz[0] / prev) : T(0);
     RVE_OFFSETS
     const T* r = r_a + so;
     const T* dinv = dinv_a + so;
+    const T* zf = zf_a ? zf_a + so : nullptr;
     const T* po = po_a + so;
     const T* Hb = H ? H + so : nullptr;
-    const T beta = T(d[b].beta);
     const T ell = T(g.ell);
     const T ih2 = T(1.0 / (g.h * g.h));
+    // the first direction is z itself (p_old is not read: it may hold anything)
+    auto pdir = [&](long long j) {
+        const T z = zval<T, PRE>(r, dinv, zf, j);
+        return k > 0 ? z + beta * po[j] : z;
+    };
     double part = 0.0;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.N;
          i += (long long)gridDim.x * blockDim.x) {
         T a, w;
         coeffs(g, mt, mid, Hb, mode, c, i, a, w);
         const Nb n = neighbours(g, i);
-        const T pc = pdir(r, dinv, po, beta, i);
-        T acc = wcoef(mt, mid, mode, ell, c, n.xm) * (pc - pdir(r, dinv, po, beta, n.xm)) -
-                w * (pdir(r, dinv, po, beta, n.xp) - pc);
-        acc += wcoef(mt, mid, mode, ell, c, n.ym) * (pc - pdir(r, dinv, po, beta, n.ym)) -
-               w * (pdir(r, dinv, po, beta, n.yp) - pc);
+        const T pc = pdir(i);
+        T acc = wcoef(mt, mid, mode, ell, c, n.xm) * (pc - pdir(n.xm)) - w * (pdir(n.xp) - pc);
+        acc += wcoef(mt, mid, mode, ell, c, n.ym) * (pc - pdir(n.ym)) - w * (pdir(n.yp) - pc);
         if (g.dim == 3)
-            acc += wcoef(mt, mid, mode, ell, c, n.zm) * (pc - pdir(r, dinv, po, beta, n.zm)) -
-                   w * (pdir(r, dinv, po, beta, n.zp) - pc);
+            acc += wcoef(mt, mid, mode, ell, c, n.zm) * (pc - pdir(n.zm)) - w * (pdir(n.zp) - pc);
         const T v = a * pc + acc * ih2;
         pn_a[so + i] = pc;
         q_a[so + i] = v;
@@ -543,21 +493,38 @@ __global__ void __launch_bounds__(TPB) k_pcg_matvec_dir(Geom g, const uint16_t* 
 
 template <typename T>
 hipError_t launch_pcg_matvec_dir(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                                 const T* H, int mode, double c, const T* r, const T* dinv,
-                                 const T* p_old, T* p_new, T* q, double* partials, int nred,
-                                 const PcgDev* d, hipStream_t st) {
-    hipLaunchKernelGGL((k_pcg_matvec_dir<T>), dim3(nred, g.B), dim3(TPB), 0, st, g, mat_id, mat, H,
-                       mode, T(c), r, dinv, p_old, p_new, q, partials, d);
+                                 const T* H, int mode, double c, int pre, const T* r,
+                                 const T* dinv, const T* zf, const T* p_old, T* p_new, T* q,
+                                 const double* rz_part, long long rz_stride, int rz_n,
+                                 const double* rr_part, long long rr_stride, int rr_n,
+                                 double* partials, int nred, PcgDev* d, int iter, hipStream_t st) {
+    if (pre == PRE_JACOBI)
+        hipLaunchKernelGGL((k_pcg_matvec_dir<T, PRE_JACOBI>), dim3(nred, g.B), dim3(TPB), 0, st, g,
+                           mat_id, mat, H, mode, T(c), r, dinv, zf, p_old, p_new, q, rz_part,
+                           rz_stride, rz_n, rr_part, rr_stride, rr_n, partials, d, iter);
+    else
+        hipLaunchKernelGGL((k_pcg_matvec_dir<T, PRE_FFT>), dim3(nred, g.B), dim3(TPB), 0, st, g,
+                           mat_id, mat, H, mode, T(c), r, dinv, zf, p_old, p_new, q, rz_part,
+                           rz_stride, rz_n, rr_part, rr_stride, rr_n, partials, d, iter);
     return hipGetLastError();
 }
 
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_pcg_update(long long N, const PcgDev* d, T* x, T* r,
+__global__ void __launch_bounds__(TPB) k_pcg_update(long long N, PcgDev* d, T* x, T* r,
                                                     const T* p, const T* q, const T* dinv,
-                                                    double* partials) {
+                                                    double* partials, int k) {
     const int b = blockIdx.y;
-    if (d[b].done) return;
-    const T alpha = T(d[b].alpha);
+    if (d[b].conv <= k) return;
+    double pq[1];
+    block_sum_all<1>(pslot(partials, b, 0), 0, gridDim.x, pq);
+    if (!(pq[0] > 0.0) || !isfinite(pq[0])) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            d[b].status = 2;
+            d[b].conv = k;
+        }
+        return;
+    }
+    const T alpha = T(d[b].rz_hist[k & 1] / pq[0]);
     const long long so = (long long)b * N;
     double s0 = 0.0, s1 = 0.0;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
@@ -570,14 +537,14 @@ __global__ void __launch_bounds__(TPB) k_pcg_update(long long N, const PcgDev* d
         s1 += double(ri) * double(ri);
     }
     double pv[2] = {s0, s1};
-    block_sum_store<2>(pv, pslot(partials, b, 0), kRedBlocks, blockIdx.x);
+    block_sum_store<2>(pv, pslot(partials, b, 1), kRedBlocks, blockIdx.x);
 }
 
 template <typename T>
-hipError_t launch_pcg_update(const Geom& g, const PcgDev* d, T* x, T* r, const T* p, const T* q,
-                             const T* dinv, double* partials, int nred, hipStream_t st) {
+hipError_t launch_pcg_update(const Geom& g, PcgDev* d, T* x, T* r, const T* p, const T* q,
+                             const T* dinv, double* partials, int nred, int iter, hipStream_t st) {
     hipLaunchKernelGGL((k_pcg_update<T>), dim3(nred, g.B), dim3(TPB), 0, st, g.N, d, x, r, p, q,
-                       dinv, partials);
+                       dinv, partials, iter);
     return hipGetLastError();
 }
 
@@ -983,16 +950,17 @@ hipError_t launch_zero_int(int* p, int n, hipStream_t st) {
                                              const T*, int, double, const T*, T*, double*, int,    \
                                              const PcgDev*, const int*, hipStream_t);              \
     template hipError_t launch_damage_diag<T>(const Geom&, const uint16_t*, const MatEntry<T>*,    \
-                                              const T*, int, double, T*, const int*,               \
-                                              hipStream_t);                                        \
-    template hipError_t launch_pcg_start<T>(const Geom&, const T*, const T*, const T*, T*, T*,     \
+                                              const T*, int, double, int, T*, double*, int,        \
+                                              const int*, hipStream_t);                            \
+    template hipError_t launch_pcg_start<T>(const Geom&, const T*, const T*, const T*, T*,         \
                                             double*, int, const int*, hipStream_t);                \
-    template hipError_t launch_pcg_update<T>(const Geom&, const PcgDev*, T*, T*, const T*,         \
-                                             const T*, const T*, double*, int, hipStream_t);       \
+    template hipError_t launch_pcg_update<T>(const Geom&, PcgDev*, T*, T*, const T*, const T*,     \
+                                             const T*, double*, int, int, hipStream_t);            \
     template hipError_t launch_pcg_matvec_dir<T>(const Geom&, const uint16_t*, const MatEntry<T>*, \
-                                                 const T*, int, double, const T*, const T*,        \
-                                                 const T*, T*, T*, double*, int, const PcgDev*,    \
-                                                 hipStream_t);                                     \
+                                                 const T*, int, double, int, const T*, const T*,   \
+                                                 const T*, const T*, T*, T*, const double*,        \
+                                                 long long, int, const double*, long long, int,    \
+                                                 double*, int, PcgDev*, int, hipStream_t);         \
     template hipError_t launch_dissipation<T>(const Geom&, const uint16_t*, const MatEntry<T>*,    \
                                               const T*, double*, int, const int*, hipStream_t);    \
     template hipError_t launch_damage_residual<T>(const Geom&, const uint16_t*,                    \

@@ -1,7 +1,8 @@
 // Deterministic block reductions (wave64 butterflies, then a fixed-order sum
 // over the waves of the block).  Each block writes its partial sums to
-// partials[v * stride + block]; a finalize kernel adds the blocks in index
-// order, so results are bitwise reproducible for a fixed launch shape.
+// partials[v * stride + block]; the consumer adds the blocks with
+// block_sum_all, in a fixed order, so results are bitwise reproducible for a
+// fixed launch shape.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -56,6 +57,33 @@ __device__ inline void block_max_store(double v, double* partials, int bid) {
         for (int w = 1; w < nw; ++w) m = fmax(m, sh[w]);
         partials[bid] = m;
     }
+}
+
+// Fixed-order sum of NV arrays of n partials (array i at p[i * stride]) by
+// the whole block; every thread of every block of a launch gets the same
+// bits (the xor butterfly gives all lanes the same value, since IEEE
+// addition is commutative).  Contains barriers: call from uniform control
+// flow.
+template <int NV>
+__device__ inline void block_sum_all(const double* p, long long stride, int n, double (&out)[NV]) {
+    __shared__ double sh[NV][16];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double s = 0.0;
+        for (int k = threadIdx.x; k < n; k += blockDim.x) s += p[i * stride + k];
+        s = wave_sum(s);
+        if (lane == 0) sh[i][wid] = s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += sh[i][w];
+        out[i] = s;
+    }
+    __syncthreads();
 }
 
 }  // namespace mirve

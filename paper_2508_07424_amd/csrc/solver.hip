@@ -180,7 +180,13 @@ constexpr size_t kLdsCap = 60 * 1024;
 struct ChunkPlanner {
     int it_prev = 0;
     double rr_prev = -1.0;
-    int next(int it, double rr, double target) {
+    // it: iterations done, rr: current r.r, target: r.r to reach, rr0: r.r at
+    // iteration 0 (gives a rate at the first check)
+    int next(int it, double rr, double target, double rr0) {
+        if (rr_prev < 0.0 && rr0 > 0.0) {
+            it_prev = 0;
+            rr_prev = rr0;
+        }
         int c = 16;
         if (rr_prev > 0.0 && it > it_prev && rr > 0.0 && rr < rr_prev && target > 0.0) {
             const double rate = std::log(rr / rr_prev) / double(it - it_prev);   // < 0
@@ -189,7 +195,7 @@ struct ChunkPlanner {
         }
         it_prev = it;
         rr_prev = rr;
-        return std::max(4, std::min(c, 256));
+        return std::max(2, std::min(c, 256));
     }
 };
 
@@ -252,6 +258,8 @@ struct Solver : SolverBase {
     AxisPlan plx, ply, plz;
     int RB = 2, nbx = 1, maxb_x = 1;
     int tly = 1, maxb_y = 1, tlz = 1, maxb_z = 1;
+    // launch shape of the one-component passes of the damage preconditioner
+    int RB1 = 2, nbx1 = 1, tly1 = 1, tlz1 = 1;
     int thr_x = 256, thr_y = 256, thr_z = 256;
     size_t lds_x = 0, lds_y = 0, lds_z = 0;
     int nred = 1;
@@ -261,14 +269,15 @@ struct Solver : SolverBase {
     int m1_max = 1;
 
     // device pointers (each field holds B RVEs back to back)
-    T *phi_c, *phi_w, *Hn, *psi_ini, *phi_ini, *psi1, *H, *px, *pr, *pp, *pp2, *pq, *pdinv, *pb, *tmp;
+    T *phi_c, *phi_w, *Hn, *psi_ini, *phi_ini, *psi1, *H, *px, *pr, *pp, *pp2, *pq, *pdinv, *pb, *tmp,
+        *pz;
     T *x, *x_c, *r, *p;
     T *aF, *aG;                     // Anderson ring buffers: kHist slots of B*N
     cplx<T>* spec;
     cplx<T>* tw;
     uint16_t* mat_id;
     MatEntry<T>* mat;
-    double *partials, *cgpA, *cgpB, *sums, *dE, *dgamma;
+    double *partials, *cgpA, *cgpB, *ppA, *ppB, *sums, *dE, *dgamma;
     int *dmask[4], *dorder, *dm1, *count;
     CgDev* cg;
     PcgDev* pcg;
@@ -292,7 +301,7 @@ struct Solver : SolverBase {
                         s ? &s->H : nullptr, s ? &s->px : nullptr, s ? &s->pr : nullptr,
                         s ? &s->pp : nullptr, s ? &s->pp2 : nullptr, s ? &s->pq : nullptr,
                         s ? &s->pdinv : nullptr,
-                        s ? &s->pb : nullptr, s ? &s->tmp : nullptr};
+                        s ? &s->pb : nullptr, s ? &s->tmp : nullptr, s ? &s->pz : nullptr};
         const int ns = sizeof(single) / sizeof(single[0]);
         std::vector<size_t> offs;
         for (int i = 0; i < ns; ++i) offs.push_back(L.off(fN));
@@ -307,6 +316,8 @@ struct Solver : SolverBase {
         const size_t opart = L.off(sizeof(double) * kMaxVals * kRedBlocks * B);
         const size_t ocgA = L.off(sizeof(double) * std::max(nbx, 1) * B);
         const size_t ocgB = L.off(sizeof(double) * std::max(nbx, 1) * B);
+        const size_t oppA = L.off(sizeof(double) * std::max(nbx, 1) * B);
+        const size_t oppB = L.off(sizeof(double) * std::max(nbx, 1) * B);
         const size_t osums = L.off(sizeof(double) * kMaxVals * B);
         const size_t oE = L.off(sizeof(double) * B);
         const size_t ogam = L.off(sizeof(double) * kAndersonMax * B);
@@ -333,6 +344,8 @@ struct Solver : SolverBase {
             s->partials = (double*)(base + opart);
             s->cgpA = (double*)(base + ocgA);
             s->cgpB = (double*)(base + ocgB);
+            s->ppA = (double*)(base + oppA);
+            s->ppB = (double*)(base + oppB);
             s->sums = (double*)(base + osums);
             s->dE = (double*)(base + oE);
             s->dgamma = (double*)(base + ogam);
@@ -442,6 +455,12 @@ struct Solver : SolverBase {
         Layout L;
         layout(c, g, nbx, L, this);
         nred = (int)std::min<long long>((g.N + 255) / 256, kRedBlocks);
+        // one-component passes keep the rows / lines per block of the s-component
+        // ones: the grid stays as large, and the LDS and threads fit a fortiori
+        RB1 = RB;
+        nbx1 = (int)((g.ny * (long long)g.nz + RB1 - 1) / RB1);
+        tly1 = tly;
+        tlz1 = tlz;
         int ax = 0;
         double best = -1;
         for (int a = 0; a < g.dim; ++a)
@@ -556,7 +575,11 @@ struct Solver : SolverBase {
     }
 
     // ---- Green operator passes --------------------------------------------
-    int fwd_x(int mode, const T* phi, const T* eps, double fcoef, double* part, const int* mask) {
+    // Mechanics CG partials: the x-forward pass writes p.Ap into cgpA, the
+    // x-inverse pass r.r into cgpB; each pass of iteration k reads what the
+    // other left.
+    int fwd_x(int mode, const T* phi, const T* eps, double fcoef, double* part, const int* mask,
+              int iter = 0) {
         XfwdArgs<T> a;
         std::memset(&a, 0, sizeof(a));
         a.g = g;
@@ -571,6 +594,8 @@ struct Solver : SolverBase {
         a.r = r;
         a.p = p;
         a.cg = mode == XF_CG ? cg : nullptr;
+        a.rr_part = cgpB;
+        a.iter = iter;
         a.active = mask;
         a.spec = spec;
         a.partials = part;
@@ -580,36 +605,39 @@ struct Solver : SolverBase {
         HIPCHK(launch_xfwd<T>(a, mode, maxb_x, lds_x, st));
         return RVE_OK;
     }
-    int axes(const CgDev* c, const int* mask) {
+    dim3 grid_y(int lines) const {
+        return dim3((unsigned)((g.nxh * (long long)g.nz + lines - 1) / lines), 1, B);
+    }
+    dim3 grid_z(int cols) const { return dim3((unsigned)(g.nxh * ((g.ny + cols - 1) / cols)), 1, B); }
+    int axes(CgDev* c, const int* mask, int iter = 0) {
         AxisArgs<T> a;
         std::memset(&a, 0, sizeof(a));
         a.g = g;
         a.spec = spec;
         a.cg = c;
+        a.iter = iter;
         a.active = mask;
         a.pl = ply;
         a.tw = tw + ply.tw_off;
         a.contiguous = 1;
         a.lines = tly;
         a.threads = thr_y;
-        const dim3 gy((unsigned)((g.nxh * (long long)g.nz + tly - 1) / tly), 1, B);
         if (g.dim == 2) {
-            HIPCHK(launch_axis<T>(a, AX_FWD_P_INV, maxb_y, gy, lds_y, st));
+            HIPCHK(launch_axis<T>(a, AX_FWD_P_INV, maxb_y, grid_y(tly), lds_y, st));
         } else {
-            HIPCHK(launch_axis<T>(a, AX_FWD, maxb_y, gy, lds_y, st));
+            HIPCHK(launch_axis<T>(a, AX_FWD, maxb_y, grid_y(tly), lds_y, st));
             AxisArgs<T> bz = a;
             bz.pl = plz;
             bz.tw = tw + plz.tw_off;
             bz.contiguous = 0;
             bz.lines = tlz;
             bz.threads = thr_z;
-            const dim3 gz((unsigned)(g.nxh * ((g.ny + tlz - 1) / tlz)), 1, B);
-            HIPCHK(launch_axis<T>(bz, AX_FWD_P_INV, maxb_z, gz, lds_z, st));
-            HIPCHK(launch_axis<T>(a, AX_INV, maxb_y, gy, lds_y, st));
+            HIPCHK(launch_axis<T>(bz, AX_FWD_P_INV, maxb_z, grid_z(tlz), lds_z, st));
+            HIPCHK(launch_axis<T>(a, AX_INV, maxb_y, grid_y(tly), lds_y, st));
         }
         return RVE_OK;
     }
-    int inv_x(int mode, T* out, double scale, double* part, const int* mask) {
+    int inv_x(int mode, T* out, double scale, double* part, const int* mask, int iter = 0) {
         XinvArgs<T> a;
         std::memset(&a, 0, sizeof(a));
         a.g = g;
@@ -622,12 +650,84 @@ struct Solver : SolverBase {
         a.p = p;
         a.r = r;
         a.cg = mode == XI_CG ? cg : nullptr;
+        a.pAp_part = cgpA;
+        a.iter = iter;
         a.active = mask;
         a.partials = part;
         a.rows_per_block = RB;
         a.nblocks = nbx;
         a.threads = thr_x;
         HIPCHK(launch_xinv<T>(a, mode, maxb_x, lds_x, st));
+        return RVE_OK;
+    }
+
+    // Damage preconditioner of PCG iteration k (Sec. 4.1 Eq. 24 R2 symbols):
+    // after the x-forward pass applies x += alpha p, r -= alpha q (xmode
+    // XF_PCG; XF_PCG0 at the start), z = S F^-1[F[S r] / (abar + bbar |d|^2)]
+    // with S = sqrt(dinv).  r.r partials go to ppA, r.z partials to ppB.
+    int precond_fft(int xmode, int k, T* u, const T* pdir) {
+        XfwdArgs<T> a;
+        std::memset(&a, 0, sizeof(a));
+        a.g = g;
+        a.pl = plx;
+        a.tw = tw + plx.tw_off;
+        a.r = pr;
+        a.x = u;
+        a.pd = pdir;
+        a.q = pq;
+        a.sc = pdinv;
+        a.pcg = pcg;
+        a.pq_part = partials;
+        a.pq_stride = (long long)kMaxVals * kRedBlocks;
+        a.pq_n = nred;
+        a.iter = k;
+        a.spec = spec;
+        a.partials = ppA;
+        a.rows_per_block = RB1;
+        a.nblocks = nbx1;
+        a.threads = thr_x;
+        HIPCHK(launch_xfwd<T>(a, xmode, maxb_x, lds_x, st));
+        AxisArgs<T> y;
+        std::memset(&y, 0, sizeof(y));
+        y.g = g;
+        y.spec = spec;
+        y.pcg = pcg;
+        y.iter = k;
+        y.pl = ply;
+        y.tw = tw + ply.tw_off;
+        y.contiguous = 1;
+        y.lines = tly1;
+        y.threads = thr_y;
+        if (g.dim == 2) {
+            HIPCHK(launch_axis<T>(y, AX_FWD_M_INV, maxb_y, grid_y(tly1), lds_y, st));
+        } else {
+            HIPCHK(launch_axis<T>(y, AX_FWD, maxb_y, grid_y(tly1), lds_y, st));
+            AxisArgs<T> z = y;
+            z.pl = plz;
+            z.tw = tw + plz.tw_off;
+            z.contiguous = 0;
+            z.lines = tlz1;
+            z.threads = thr_z;
+            HIPCHK(launch_axis<T>(z, AX_FWD_M_INV, maxb_z, grid_z(tlz1), lds_z, st));
+            HIPCHK(launch_axis<T>(y, AX_INV, maxb_y, grid_y(tly1), lds_y, st));
+        }
+        XinvArgs<T> v;
+        std::memset(&v, 0, sizeof(v));
+        v.g = g;
+        v.pl = plx;
+        v.tw = tw + plx.tw_off;
+        v.spec = spec;
+        v.scale = T(1);
+        v.out = pz;
+        v.r = pr;
+        v.sc = pdinv;
+        v.pcg = pcg;
+        v.iter = k;
+        v.partials = ppB;
+        v.rows_per_block = RB1;
+        v.nblocks = nbx1;
+        v.threads = thr_x;
+        HIPCHK(launch_xinv<T>(v, XI_PCG, maxb_x, lds_x, st));
         return RVE_OK;
     }
 
@@ -656,34 +756,32 @@ struct Solver : SolverBase {
         CHK(green(phi, nullptr, 1.0, nullptr, 1.0, cgpB, mk));          // ||b||^2
         CHK(green(phi, x, 1.0, r, -1.0, cgpA, mk));                     // r0 = -P[gC(f + x)]
         HIPCHK(launch_cg_init(cg, cgpA, cgpB, nbx, B, cfg.tol_cg, cfg.max_cg, mk, st));
-        int chunk = 8, total = 0;
+        int chunk = 8, k = 0;
         std::vector<ChunkPlanner> plan(B);
         for (;;) {
-            for (int k = 0; k < chunk; ++k) {
-                CHK(fwd_x(XF_CG, phi, nullptr, 0.0, cgpA, nullptr));
-                CHK(axes(cg, nullptr));
-                HIPCHK(launch_cg_alpha(cg, cgpA, nbx, B, st));
-                CHK(inv_x(XI_CG, nullptr, 1.0, cgpB, nullptr));
-                HIPCHK(launch_cg_beta(cg, cgpB, nbx, B, st));
+            for (int i = 0; i < chunk; ++i, ++k) {
+                CHK(fwd_x(XF_CG, phi, nullptr, 0.0, cgpA, nullptr, k));
+                CHK(axes(cg, nullptr, k));
+                CHK(inv_x(XI_CG, nullptr, 1.0, cgpB, nullptr, k));
             }
-            total += chunk;
             HIPCHK(hipMemcpyAsync(h_cg, cg, sizeof(CgDev) * B, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             bool all = true;
             int next = 4;
             for (int b = 0; b < B; ++b) {
-                if (!act[b] || h_cg[b].done) continue;
+                if (!act[b] || h_cg[b].conv != kNotDone) continue;
                 all = false;
-                next = std::max(next, plan[b].next(h_cg[b].it, h_cg[b].rr, h_cg[b].tol2 * h_cg[b].bn2));
+                next = std::max(next, plan[b].next(k, h_cg[b].rr, h_cg[b].tol2 * h_cg[b].bn2, h_cg[b].rr0));
             }
-            if (all || total > cfg.max_cg + chunk) break;
+            if (all || k > cfg.max_cg + chunk) break;
             chunk = next;
         }
         for (int b = 0; b < B; ++b) {
             if (!act[b]) continue;
             const CgDev& c = h_cg[b];
-            iters[b] += c.it;
-            greenops += c.it;
+            const int it = c.conv == kNotDone ? k : c.conv;
+            iters[b] += it;
+            greenops += it;
             if (c.status == 1) continue;
             if (c.status == 2) {
                 if (std::isfinite(c.rr) && c.rr <= 1e4 * c.tol2 * c.bn2) continue;
@@ -713,40 +811,54 @@ struct Solver : SolverBase {
                   int mask_id, const std::vector<int>& act, std::vector<int>& iters,
                   std::vector<int>& rcs) {
         const int* mk = dmask[mask_id];
-        HIPCHK(launch_damage_diag<T>(g, mat_id, mat, Hc, mode, c, pdinv, mk, st));
+        const bool fft = cfg.damage_precond == RVE_PRECOND_FFT;
+        HIPCHK(launch_damage_diag<T>(g, mat_id, mat, Hc, mode, c, fft ? 1 : 0, pdinv, partials, nred,
+                                     mk, st));
         HIPCHK(launch_pcg_matvec<T>(g, mat_id, mat, Hc, mode, c, u, pq, nullptr, nred, nullptr, mk, st));
-        HIPCHK(launch_pcg_start<T>(g, bvec, pq, pdinv, pr, pp, partials, nred, mk, st));
-        HIPCHK(launch_pcg_fin_start(pcg, partials, nred, B, tol, max_it, mk, st));
+        HIPCHK(launch_pcg_start<T>(g, bvec, pq, pdinv, pr, partials, nred, mk, st));
+        HIPCHK(launch_pcg_fin_start(pcg, partials, nred, B, tol, max_it, g.inv_N, mk, st));
+        // where step 1 of each iteration finds r.z and r.r
+        const double *rzp, *rrp;
+        long long rzs, rrs;
+        int rzn, rrn;
+        if (fft) {
+            CHK(precond_fft(XF_PCG0, -1, u, nullptr));
+            rzp = ppB; rrp = ppA; rzs = rrs = nbx1; rzn = rrn = nbx1;
+        } else {
+            rzp = partials + kRedBlocks;
+            rrp = partials + 2 * kRedBlocks;
+            rzs = rrs = (long long)kMaxVals * kRedBlocks;
+            rzn = rrn = nred;
+        }
         T* pcur = pp;   // directions alternate between pp and pp2
-        int chunk = 8, total = 0;
+        int chunk = fft ? 4 : 8, k = 0;
         std::vector<ChunkPlanner> plan(B);
         for (;;) {
-            for (int k = 0; k < chunk; ++k) {
+            for (int i = 0; i < chunk; ++i, ++k) {
                 T* pn = pcur == pp ? pp2 : pp;
-                HIPCHK(launch_pcg_matvec_dir<T>(g, mat_id, mat, Hc, mode, c, pr, pdinv, pcur, pn, pq,
-                                                partials, nred, pcg, st));
-                HIPCHK(launch_pcg_fin_alpha(pcg, partials, nred, B, st));
-                HIPCHK(launch_pcg_update<T>(g, pcg, u, pr, pn, pq, pdinv, partials, nred, st));
-                HIPCHK(launch_pcg_fin_beta(pcg, partials, nred, B, st));
+                HIPCHK(launch_pcg_matvec_dir<T>(g, mat_id, mat, Hc, mode, c, fft ? PRE_FFT : PRE_JACOBI,
+                                                pr, pdinv, pz, pcur, pn, pq, rzp, rzs, rzn, rrp, rrs,
+                                                rrn, partials, nred, pcg, k, st));
+                if (fft) CHK(precond_fft(XF_PCG, k, u, pn));
+                else HIPCHK(launch_pcg_update<T>(g, pcg, u, pr, pn, pq, pdinv, partials, nred, k, st));
                 pcur = pn;
             }
-            total += chunk;
             HIPCHK(hipMemcpyAsync(h_pcg, pcg, sizeof(PcgDev) * B, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             bool all = true;
-            int next = 4;
+            int next = 2;
             for (int b = 0; b < B; ++b) {
-                if (!act[b] || h_pcg[b].done) continue;
+                if (!act[b] || h_pcg[b].conv != kNotDone) continue;
                 all = false;
-                next = std::max(next, plan[b].next(h_pcg[b].it, h_pcg[b].rr, h_pcg[b].tol2 * h_pcg[b].bn2));
+                next = std::max(next, plan[b].next(k, h_pcg[b].rr, h_pcg[b].tol2 * h_pcg[b].bn2, h_pcg[b].rr0));
             }
-            if (all || total > max_it + chunk) break;
+            if (all || k > max_it + chunk) break;
             chunk = next;
         }
         for (int b = 0; b < B; ++b) {
             if (!act[b]) continue;
             const PcgDev& d = h_pcg[b];
-            iters[b] += d.it;
+            iters[b] += d.conv == kNotDone ? k : d.conv;
             if (d.status == 1) continue;
             if (d.status == 2) {
                 if (std::isfinite(d.rr) && (d.rr <= 1e4 * d.tol2 * d.bn2 || d.bn2 == 0.0)) continue;
@@ -1354,10 +1466,9 @@ struct Solver : SolverBase {
         std::vector<CgDev> c(B);
         for (int b = 0; b < B; ++b) {
             std::memset(&c[b], 0, sizeof(CgDev));
-            c[b].beta = 0.5;
-            c[b].alpha = 0.0;
-            c[b].max_it = -1;           // the passes keep these scalars fixed
-            c[b].done = rd[b] ? 0 : 1;
+            c[b].rr_hist[0] = c[b].rr_hist[1] = c[b].rr = c[b].bn2 = 1.0;
+            c[b].max_it = -1;           // timing: alpha = 0, beta = 1/2, no stopping test
+            c[b].conv = rd[b] ? kNotDone : -1;
         }
         HIPCHK(hipStreamSynchronize(st));
         HIPCHK(hipMemcpy(cg, c.data(), sizeof(CgDev) * B, hipMemcpyHostToDevice));
@@ -1380,13 +1491,14 @@ struct Solver : SolverBase {
                 case 1: HIPCHK(launch_axis<T>(a, AX_FWD_P_INV, three ? maxb_z : maxb_y, grid,
                                               three ? lds_z : lds_y, st)); break;
                 case 2: CHK(inv_x(XI_STORE, p, 1.0, cgpB, dmask[0])); break;
-                case 3: CHK(fwd_x(XF_CG, phi_c, nullptr, 0.0, cgpA, nullptr)); break;
-                case 4: CHK(inv_x(XI_CG, nullptr, 1.0, cgpB, nullptr)); break;
+                case 3: CHK(fwd_x(XF_CG, phi_c, nullptr, 0.0, cgpA, nullptr, 1)); break;
+                case 4: CHK(inv_x(XI_CG, nullptr, 1.0, cgpB, nullptr, 1)); break;
                 default: return fail(RVE_EINVAL, "unknown pass");
             }
         }
-        // compulsory bytes of one launch: every input read once, every output written once
-        const double w = sizeof(T), sp = (double)g.nxh / g.nx, S = g.s, N = (double)g.N * nready;
+        // compulsory bytes of one launch: every input read once, every output
+        // written once; a half spectrum holds n_x/2 + 1 complex values per row
+        const double w = sizeof(T), sp = 2.0 * g.nxh / g.nx, S = g.s, N = (double)g.N * nready;
         double bb = 0.0;
         switch (pass) {
             case 0: bb = N * ((S + 1) * w + 2) + N * sp * S * w; break;
@@ -1420,6 +1532,10 @@ static int validate(const rve_config* c, std::string& why) {
     if (c->anderson_depth < 0 || c->anderson_depth > kAndersonMax) { why = "anderson_depth in [0, 5]"; return RVE_EINVAL; }
     if (c->max_materials < 1 || c->max_materials > kMaxMat) { why = "max_materials in [1, 65536]"; return RVE_EINVAL; }
     if (c->batch < 1 || c->batch > 1024) { why = "batch in [1, 1024]"; return RVE_EINVAL; }
+    if (c->damage_precond != RVE_PRECOND_FFT && c->damage_precond != RVE_PRECOND_JACOBI) {
+        why = "damage_precond must be RVE_PRECOND_FFT or RVE_PRECOND_JACOBI";
+        return RVE_EINVAL;
+    }
     const int s = c->dim == 2 ? 3 : 6;
     double fn = 0;
     for (int a = 0; a < s; ++a) {
@@ -1469,6 +1585,7 @@ int rve_default_config(rve_config* c) {
     c->A_g = 0.0;
     c->max_materials = 4096;
     c->batch = 1;
+    c->damage_precond = RVE_PRECOND_FFT;
     return RVE_OK;
 }
 

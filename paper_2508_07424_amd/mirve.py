@@ -28,6 +28,8 @@ RVE_PREC_FP64 = 0
 RVE_PREC_MIXED = 1
 RVE_SPLIT_NONE = 0
 RVE_SPLIT_VOLDEV = 1
+RVE_PRECOND_FFT = 0
+RVE_PRECOND_JACOBI = 1
 RVE_PHASE_ISO = 0
 RVE_PHASE_CUBIC = 1
 
@@ -52,7 +54,7 @@ class rve_config(C.Structure):
                 ("tol_cg", C.c_double), ("tol_pcg", C.c_double), ("tol_al", C.c_double),
                 ("max_stagger", C.c_int), ("max_cg", C.c_int), ("max_pcg", C.c_int),
                 ("anderson_depth", C.c_int), ("frac_threshold", C.c_double), ("A_g", C.c_double),
-                ("max_materials", C.c_int), ("batch", C.c_int)]
+                ("max_materials", C.c_int), ("batch", C.c_int), ("damage_precond", C.c_int)]
 
 
 class rve_phase(C.Structure):

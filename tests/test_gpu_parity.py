@@ -73,12 +73,13 @@ def test_green_op_mixed(name, make):
     assert rel(gpu, ref) < 1e-5
 
 
+@pytest.mark.parametrize("pre", [0, 1], ids=["fft", "jacobi"])
 @pytest.mark.parametrize("name,make", [_cases()[0], _cases()[3], _cases()[5]])
-def test_mechanics_and_damage(name, make):
+def test_mechanics_and_damage(name, make, pre):
     m = _lib()
     w = make()
-    print("case", name, w.n, flush=True)
-    r = m.from_workload(w, **TIGHT)
+    print("case", name, w.n, "damage_precond", pre, flush=True)
+    r = m.from_workload(w, damage_precond=pre, **TIGHT)
     prob = oracle_problem(w, **OTIGHT)
     st = solver.State(prob)
     it, S1 = r.rve_solve_mechanics()
@@ -99,15 +100,16 @@ def test_mechanics_and_damage(name, make):
     assert rel(r.rve_get_field("phi"), prob.to_public(phi_o)) < 1e-10
 
 
-@pytest.mark.parametrize("name,make,nsteps", [
-    ("composite64", lambda: W.composite_2d_small(), 3),
-    ("homog48x40", lambda: W.homogeneous_2d(nx=48, ny=40, crack=8), 3),
+@pytest.mark.parametrize("name,make,nsteps,pre", [
+    ("composite64", lambda: W.composite_2d_small(), 3, 0),
+    ("composite64-jacobi", lambda: W.composite_2d_small(), 2, 1),
+    ("homog48x40", lambda: W.homogeneous_2d(nx=48, ny=40, crack=8), 3, 0),
 ])
-def test_steps_fp64(name, make, nsteps):
+def test_steps_fp64(name, make, nsteps, pre):
     m = _lib()
     w = make()
     print("case", name, w.n, flush=True)
-    r = m.from_workload(w, **TIGHT)
+    r = m.from_workload(w, damage_precond=pre, **TIGHT)
     prob = oracle_problem(w, **OTIGHT)
     st = solver.State(prob)
     for k in range(nsteps):
