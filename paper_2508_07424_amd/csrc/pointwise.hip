@@ -444,7 +444,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_matvec_dir(
     block_sum_all<1>(rr_part + (long long)b * rr_stride, 0, rr_n, rr);
     int stop = 0;
     if (!isfinite(rr[0]) || !isfinite(rz[0])) stop = 2;
-    else if (rr[0] <= d[b].tol2 * d[b].bn2) stop = 1;
+    else if (rr[0] <= d[b].tol2 * d[b].bn2 || d[b].bn2 == 0.0) stop = 1;   // b = 0: x = 0 (host)
     else if (k >= d[b].max_it) stop = 3;
     const double prev = k > 0 ? d[b].rz_hist[(k - 1) & 1] : 1.0;
     if (blockIdx.x == 0 && threadIdx.x == 0) {

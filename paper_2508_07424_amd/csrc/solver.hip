@@ -278,7 +278,7 @@ struct Solver : SolverBase {
     uint16_t* mat_id;
     MatEntry<T>* mat;
     double *partials, *cgpA, *cgpB, *ppA, *ppB, *sums, *dE, *dgamma;
-    int *dmask[4], *dorder, *dm1, *count;
+    int *dmask[5], *dorder, *dm1, *count;
     CgDev* cg;
     PcgDev* pcg;
     // pinned host mirrors / staging
@@ -290,6 +290,8 @@ struct Solver : SolverBase {
     size_t stage_bytes = 0;
 
     int greenops = 0;
+    std::vector<int> slope_warm;     // tmp holds a usable tangent of this slot
+    static constexpr double kSlopeTol = 1e-8;
 
     // ------------------------------------------------------------------ layout
     static size_t layout(const rve_config& c, const Geom& g, int nbx, Layout& L, Solver* s) {
@@ -321,8 +323,8 @@ struct Solver : SolverBase {
         const size_t osums = L.off(sizeof(double) * kMaxVals * B);
         const size_t oE = L.off(sizeof(double) * B);
         const size_t ogam = L.off(sizeof(double) * kAndersonMax * B);
-        size_t omask[4];
-        for (int i = 0; i < 4; ++i) omask[i] = L.off(sizeof(int) * B);
+        size_t omask[5];
+        for (int i = 0; i < 5; ++i) omask[i] = L.off(sizeof(int) * B);
         const size_t oord = L.off(sizeof(int) * kHist * B);
         const size_t om1 = L.off(sizeof(int) * B);
         const size_t ocnt = L.off(sizeof(int) * B);
@@ -349,7 +351,7 @@ struct Solver : SolverBase {
             s->sums = (double*)(base + osums);
             s->dE = (double*)(base + oE);
             s->dgamma = (double*)(base + ogam);
-            for (int i = 0; i < 4; ++i) s->dmask[i] = (int*)(base + omask[i]);
+            for (int i = 0; i < 5; ++i) s->dmask[i] = (int*)(base + omask[i]);
             s->dorder = (int*)(base + oord);
             s->dm1 = (int*)(base + om1);
             s->count = (int*)(base + ocnt);
@@ -468,6 +470,7 @@ struct Solver : SolverBase {
         load_axis = ax;
         B = g.B;
         slots.assign(B, SlotState());
+        slope_warm.assign(B, 0);
         m1_max = std::max(0, std::min(c.anderson_depth, kAndersonMax)) + 1;
     }
 
@@ -855,6 +858,16 @@ struct Solver : SolverBase {
             if (all || k > max_it + chunk) break;
             chunk = next;
         }
+        // a zero right-hand side has the solution 0 (A is positive definite);
+        // the iteration stops at once for it and the warm start is cleared here
+        std::vector<int> zero(B, 0);
+        bool any_zero = false;
+        for (int b = 0; b < B; ++b)
+            if (act[b] && h_pcg[b].bn2 == 0.0) { zero[b] = 1; any_zero = true; }
+        if (any_zero) {
+            CHK(set_mask(4, zero));
+            HIPCHK(launch_fill<T>(u, T(0), g.N, B, dmask[4], st));
+        }
         for (int b = 0; b < B; ++b) {
             if (!act[b]) continue;
             const PcgDev& d = h_pcg[b];
@@ -896,8 +909,21 @@ struct Solver : SolverBase {
                      std::vector<int>& npcg, std::vector<int>& rcs) {
         const int* mk = dmask[mask_id];
         HIPCHK(launch_tangent_rhs<T>(g, u, psi1, psi_ini, Hn, dE, cfg.history, pb, mk, st));
-        HIPCHK(launch_fill<T>(tmp, T(0), g.N, B, mk, st));
-        CHK(pcg_solve(H, 0, 0.0, pb, tmp, cfg.tol_pcg, cfg.max_pcg, mask_id, act, npcg, rcs));
+        // warm start from the slot's previous tangent (zero when it has none)
+        std::vector<int> reset(B, 0);
+        bool any_reset = false;
+        for (int b = 0; b < B; ++b)
+            if (act[b] && !slope_warm[b]) { reset[b] = 1; any_reset = true; }
+        if (any_reset) {
+            CHK(set_mask(4, reset));
+            HIPCHK(launch_fill<T>(tmp, T(0), g.N, B, dmask[4], st));
+        }
+        // the tangent only steers Newton on E (the constraint is tested on D
+        // itself), so it is solved to a looser tolerance
+        const double tol = std::max(cfg.tol_pcg, kSlopeTol);
+        CHK(pcg_solve(H, 0, 0.0, pb, tmp, tol, cfg.max_pcg, mask_id, act, npcg, rcs));
+        for (int b = 0; b < B; ++b)
+            if (act[b]) slope_warm[b] = rcs[b] == RVE_OK ? 1 : 0;
         HIPCHK(launch_dissipation_dir<T>(g, mat_id, mat, u, tmp, partials, nred, mk, st));
         HIPCHK(launch_sum_partials(partials, nred, 1, B, sums, mk, st));
         CHK(read_sums(1));
@@ -1043,6 +1069,7 @@ struct Solver : SolverBase {
         if (slot < 0 || slot >= B) return fail(RVE_EINVAL, "slot out of range");
         if (!pid || !phases || nph <= 0) return fail(RVE_EINVAL, "phase_id and phases required");
         if (!(phi_M > 0.0 && phi_M < 1.0)) return fail(RVE_EINVAL, "phi_M must be in (0, 1)");
+        slope_warm[slot] = 0;
         for (int i = 0; i < nph; ++i) {
             const rve_phase& ph = phases[i];
             if (!(ph.Gc > 0.0) || !std::isfinite(ph.Gc)) return fail(RVE_EINVAL, "Gc must be > 0");
