@@ -5,10 +5,11 @@ toughness solver on one MI355X.
 A step is one dissipation-controlled step (Eq. 16 of the paper: mechanics CG
 with the fused Green operator, damage PCG, arc-length constraint, commit and
 fracture test) of every RVE of a batch of synthetic 256 x 256 fibre
-composites: elastic contrast {2, 5, 10} x toughness contrast {1, 2, 4}, fibre
-radius U[5, 9] up to volume fraction 0.3, l = 2 voxels, a 40-voxel notch.
-The RVEs are loaded to an intermediate state by the warm-up steps, then K
-steps are timed.
+composites: elastic contrast {2, 5, 10} x toughness contrast {1, 2, 4}, seven
+random realizations of each (the paper's sample size for random fibres,
+Sec. 5.2.2), fibre radius U[5, 9] up to volume fraction 0.3, l = 2 voxels, a
+40-voxel notch.  The RVEs are loaded to an intermediate state by the warm-up
+steps, then K steps are timed.
 
 value = sum over RVEs of (voxels x Green-operator applications) / seconds.
 
@@ -149,7 +150,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=9)
+    ap.add_argument("--batch", type=int, default=63, help="RVEs (9 contrast cases x 7 realizations)")
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -212,7 +213,8 @@ def main():
         "dtype": "f64" if prec == mirve.RVE_PREC_FP64 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": "2D fibre composite %dx%d, vf 0.3, r~U[5,9], E ratio {2,5,10} x "
-                               "Gc ratio {1,2,4}, l=2, 40-voxel notch" % (args.size, args.size),
+                               "Gc ratio {1,2,4} x %d realizations, l=2, 40-voxel notch"
+                               % (args.size, args.size, (args.batch + 8) // 9),
                    "batch": args.batch, "precision": args.precision,
                    "rve_steps_per_s": round(args.batch * args.steps / sec, 3),
                    "greenops_per_rve_step": round(greenops / (args.batch * args.steps) /
