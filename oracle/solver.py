@@ -103,19 +103,25 @@ def mechanics(prob, phi, x0):
     compatible subspace: A x = P[sigma(x)] is self-adjoint and positive on
     range(P) for the linear law.  With the volumetric split the law is
     piecewise linear and Newton iterations with the tangent stiffness are
-    wrapped around the same CG.
+    wrapped around the same CG.  The paper gives no solver for the split;
+    here each tangent solve stops at ||r|| <= tol_cg ||P[sigma(f)]||, the
+    load scale that ||b|| is for the linear law (a tolerance relative to the
+    shrinking Newton residual would ask for accuracy below the rounding of
+    the Green operator in the last Newton steps).
     """
     fU = _uniform(prob.f, prob.n)
     if prob.split == "none":
         x, it = _cg_linear(prob, phi, fU, x0, tangent=None)
         return x, it
+    sf = spectral.green_apply(model.stress(fU, phi, prob.mat, prob.split), prob.P)
+    r_abs = prob.tol_cg * math.sqrt(_dot(sf, sf))
     x = x0.copy()
     total = 0
     for _ in range(100):
         eps = fU + x
         R = -spectral.green_apply(model.stress(eps, phi, prob.mat, prob.split), prob.P)
         tr = eps[0] + eps[1] + (eps[2] if prob.d == 3 else 0.0)
-        dx, it = _cg_tangent(prob, phi, tr, R, prob.tol_cg)
+        dx, it = _cg_tangent(prob, phi, tr, R, r_abs)
         total += it
         x = x + dx
         if math.sqrt(_dot(dx, dx)) <= prob.tol_cg * max(math.sqrt(_dot(x + fU, x + fU)), 1e-300):
@@ -147,8 +153,9 @@ def _cg_linear(prob, phi, fU, x0, tangent=None):
     return x, it
 
 
-def _cg_tangent(prob, phi, tr, R, tol):
-    """CG for P[C_t : dx] = R with the split's tangent stiffness."""
+def _cg_tangent(prob, phi, tr, R, r_abs):
+    """CG for P[C_t : dx] = R with the split's tangent stiffness, from
+    dx = 0 until ||r|| <= r_abs."""
     g = model.degradation(phi, prob.k)
     I = model._identity(prob.d)
     Kb = prob.mat.K
@@ -165,13 +172,10 @@ def _cg_tangent(prob, phi, tr, R, tol):
     A = lambda v: spectral.green_apply(Ct(v), prob.P)
     x = np.zeros_like(R)
     r = R.copy()
-    bn = math.sqrt(_dot(R, R))
-    if bn == 0.0:
-        return x, 0
     p = r.copy()
     rr = _dot(r, r)
     it = 0
-    while math.sqrt(rr) > tol * bn and it < prob.max_cg:
+    while math.sqrt(rr) > r_abs and it < prob.max_cg:
         q = A(p)
         alpha = rr / _dot(p, q)
         x += alpha * p

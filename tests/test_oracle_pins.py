@@ -203,6 +203,65 @@ def test_homogeneous_rve_exact_uniform_stress():
     assert abs(S1 - ref @ w.f) < 1e-14
 
 
+# --------------------------------------------------------------------------
+# volumetric tension / compression split of the degraded law
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_split_stress_is_the_derivative_of_its_energy(d):
+    """sigma = dW/deps for W = g psi+ + 1/2 K <tr eps>-^2, where psi+ is the
+    oracle's driving energy (1/2 e:C:e - 1/2 K tr^2 + 1/2 K <tr>+^2): the
+    split stress and its energy must belong together (central differences)."""
+    s = mandel.nsym(d)
+    n = (3,) * d
+    rng = np.random.default_rng(5)
+    phases = [W.iso(2.0, 0.3, 1.0), W.cubic(1.0, 0.5, 0.7, 1.0)]
+    pid = rng.integers(0, 2, size=n).astype(np.uint16)
+    mat = model.MaterialField(n, phases, pid, theta=rng.uniform(0, 6.28, size=n), k=1e-6)
+    phi = rng.uniform(0.0, 0.9, size=n)
+    g = model.degradation(phi, mat.k)
+    eps = rng.standard_normal((s,) + n)              # traces of both signs
+    tr = eps[0] + eps[1] + (eps[2] if d == 3 else 0.0)
+    assert (tr > 0).any() and (tr < 0).any()
+
+    def W_of(e):
+        t = e[0] + e[1] + (e[2] if d == 3 else 0.0)
+        return g * model.energy_density(e, mat, "voldev") + 0.5 * mat.K * np.minimum(t, 0.0) ** 2
+
+    sig = model.stress(eps, phi, mat, "voldev")
+    h = 1e-6
+    for a in range(s):
+        de = np.zeros_like(eps)
+        de[a] = h
+        num = (W_of(eps + de) - W_of(eps - de)) / (2 * h)
+        assert np.max(np.abs(num - sig[a])) < 1e-7
+    # in tension the split law is the paper's law g C : eps
+    pos = tr > 0
+    lin = model.stress(eps, phi, mat, "none")
+    assert np.max(np.abs((sig - lin)[:, pos])) < 1e-14
+
+
+def test_split_homogeneous_rve_is_exact_under_compression():
+    """A homogeneous RVE under a uniform load stays uniform with the split law
+    as well (the Newton iteration must return eps~ = 0), and its stress is the
+    closed form g (C:f - K tr f I) + K tr f I for a compressive trace."""
+    w = W.Workload(n=(10, 8), h=1.0, ell=1.5, phases=[W.iso(2.0, 0.3, 1.0)],
+                   phase_id=np.zeros((8, 10), np.uint16), f=np.array([-1.0, 0.4, 0.3]), dtau=1)
+    prob = oracle_problem(w, split="voldev", tol_cg=1e-12)
+    phi = np.full(prob.n, 0.3)
+    x, _ = solver.mechanics(prob, phi, np.zeros((3,) + prob.n))
+    assert np.max(np.abs(x)) < 1e-13
+    _, sig, psi, _ = solver.unit_response(prob, phi, x)
+    C = mandel.c4_to_mandel(mandel.isotropic_c4(2.0, 0.3), 2)
+    K = 2.0 / (3 * (1 - 2 * 0.3))
+    gg = model.degradation(0.3, prob.k)
+    trf = -0.6
+    ref = gg * (C @ w.f - K * trf * np.array([1, 1, 0])) + K * trf * np.array([1, 1, 0])
+    assert np.max(np.abs(sig - ref[:, None, None])) < 1e-13
+    # only the deviatoric-type energy drives damage under compression
+    assert np.max(np.abs(psi - (0.5 * w.f @ C @ w.f - 0.5 * K * trf ** 2))) < 1e-13
+
+
 def _laminate_reference(phases, w_frac, normal_axis):
     lam = np.array([p["E"] * p["nu"] / ((1 + p["nu"]) * (1 - 2 * p["nu"])) for p in phases])
     mu = np.array([p["E"] / (2 * (1 + p["nu"])) for p in phases])
