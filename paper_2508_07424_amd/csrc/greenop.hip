@@ -161,7 +161,8 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
     const int b = blockIdx.y;
     const int k = a.iter;
     constexpr bool PCG = MODE == XF_PCG || MODE == XF_PCG0;
-    if (MODE == XF_CG) {
+    constexpr bool CGM = MODE == XF_CG || MODE == XF_CG_T;
+    if (CGM) {
         if (a.cg[b].conv <= k) return;
     } else if (PCG) {
         if (a.pcg[b].conv <= k) return;
@@ -186,7 +187,7 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
     // partials of the previous x-inverse pass.  PCG: alpha = rz_k / p.q.
     T beta = T(0), alpha = T(0);
     bool first = false;
-    if (MODE == XF_CG) {
+    if (CGM) {
         const CgDev& cg = a.cg[b];
         if (cg.max_it < 0) {
             beta = T(0.5);                       // timing run
@@ -245,7 +246,7 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
             const MatEntry<T>& m = mat[mid[idx]];
             const T gg = degr(phi[idx], T(g.k_res));
             T e[S];
-            if (MODE == XF_CG) {
+            if (CGM) {
 #pragma unroll
                 for (int c = 0; c < S; ++c) {
                     const long long o = fo + c * N + idx;
@@ -262,9 +263,29 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
             T o[S];
             mat_apply<T, S>(m, e, o);
 #pragma unroll
-            for (int c = 0; c < S; ++c) {
-                sig[c] = gg * o[c];
-                if (MODE == XF_CG) part += double(e[c]) * double(sig[c]);
+            for (int c = 0; c < S; ++c) sig[c] = gg * o[c];
+            if constexpr (MODE == XF_SPLIT || MODE == XF_CG_T) {
+                // sigma = g (C:e - K tr e I) + w K tr e I with w = g where the
+                // (Newton-point) trace is tensile, 1 where it is not: the split
+                // law itself for XF_SPLIT, its tangent for XF_CG_T
+                constexpr int NI = S == 3 ? 2 : 3;
+                T tr = T(0);
+#pragma unroll
+                for (int c = 0; c < NI; ++c) tr += e[c];
+                bool ten;
+                if constexpr (MODE == XF_SPLIT) {
+                    ten = tr > T(0);
+                    a.tmask[so + idx] = ten ? 1 : 0;
+                } else {
+                    ten = a.tmask[so + idx] != 0;
+                }
+                const T add = ((ten ? gg : T(1)) - gg) * m.K * tr;
+#pragma unroll
+                for (int c = 0; c < NI; ++c) sig[c] += add;
+            }
+            if constexpr (CGM) {
+#pragma unroll
+                for (int c = 0; c < S; ++c) part += double(e[c]) * double(sig[c]);
             }
         } else {
 #pragma unroll
@@ -299,7 +320,7 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
         if (rowA < nrows) spc[rowA] = A;            // rowA = z * ny + y
         if (rowA + 1 < nrows) spc[rowA + 1] = Bv;
     }
-    if (MODE != XF_GREEN) {
+    if (MODE != XF_GREEN && MODE != XF_SPLIT) {
         double pv[1] = {part};
         block_sum_store<1>(pv, a.partials + (long long)b * a.nblocks, 0, grp);
     }
@@ -562,11 +583,22 @@ template <typename T>
 hipError_t launch_xfwd(const XfwdArgs<T>& a, int mode, int maxb, size_t lds, hipStream_t st) {
     if (mode == XF_PCG) return launch_xfwd_s<T, 1, XF_PCG>(a, maxb, lds, st);
     if (mode == XF_PCG0) return launch_xfwd_s<T, 1, XF_PCG0>(a, maxb, lds, st);
-    if (a.g.s == 3)
-        return mode == XF_CG ? launch_xfwd_s<T, 3, XF_CG>(a, maxb, lds, st)
-                             : launch_xfwd_s<T, 3, XF_GREEN>(a, maxb, lds, st);
-    return mode == XF_CG ? launch_xfwd_s<T, 6, XF_CG>(a, maxb, lds, st)
-                         : launch_xfwd_s<T, 6, XF_GREEN>(a, maxb, lds, st);
+    if (a.g.s == 3) {
+        switch (mode) {
+            case XF_GREEN: return launch_xfwd_s<T, 3, XF_GREEN>(a, maxb, lds, st);
+            case XF_CG: return launch_xfwd_s<T, 3, XF_CG>(a, maxb, lds, st);
+            case XF_SPLIT: return launch_xfwd_s<T, 3, XF_SPLIT>(a, maxb, lds, st);
+            case XF_CG_T: return launch_xfwd_s<T, 3, XF_CG_T>(a, maxb, lds, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (mode) {
+        case XF_GREEN: return launch_xfwd_s<T, 6, XF_GREEN>(a, maxb, lds, st);
+        case XF_CG: return launch_xfwd_s<T, 6, XF_CG>(a, maxb, lds, st);
+        case XF_SPLIT: return launch_xfwd_s<T, 6, XF_SPLIT>(a, maxb, lds, st);
+        case XF_CG_T: return launch_xfwd_s<T, 6, XF_CG_T>(a, maxb, lds, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <typename T, int S, int MODE>

@@ -51,7 +51,12 @@ struct PcgDev {
     int conv, status, max_it, pad;
 };
 
-enum { XF_GREEN = 0, XF_CG = 1, XF_PCG = 2, XF_PCG0 = 3 };
+// x-forward modes: XF_GREEN the linear law; XF_CG the CG direction update
+// with the linear law; XF_PCG / XF_PCG0 the damage preconditioner;
+// XF_SPLIT the volumetric tension / compression split (nonlinear), which
+// also records whether tr(eps) > 0 per voxel; XF_CG_T the CG direction
+// update with the split's tangent at the recorded flags.
+enum { XF_GREEN = 0, XF_CG = 1, XF_PCG = 2, XF_PCG0 = 3, XF_SPLIT = 4, XF_CG_T = 5 };
 enum { AX_FWD = 0, AX_INV = 1, AX_FWD_P_INV = 2, AX_FWD_M_INV = 3 };
 enum { XI_STORE = 0, XI_CG = 1, XI_PCG = 2 };
 enum { PRE_JACOBI = 0, PRE_FFT = 1 };
@@ -73,8 +78,9 @@ struct XfwdArgs {
     const T* pd;         // XF_PCG: damage direction
     const T* q;          // XF_PCG: A pd
     const T* sc;         // XF_PCG*: diagonal scaling of the preconditioner
-    const CgDev* cg;     // XF_CG
+    const CgDev* cg;     // XF_CG, XF_CG_T
     PcgDev* pcg;         // XF_PCG*
+    uint8_t* tmask;      // XF_SPLIT: written; XF_CG_T: read (1 where tr eps > 0)
     const double* rr_part;   // XF_CG: r.r partials of the previous x-inverse ([B][nblocks])
     const double* pq_part;   // XF_PCG: p.q partials, RVE b at pq_part + b * pq_stride
     long long pq_stride;
@@ -167,11 +173,18 @@ struct F6 {
 };
 
 // eps1 = f + x, sigma1 = g C eps1, psi1 (0 on notch voxels); partial sums of
-// sigma1:f (value 0) and sigma1:sigma1 (value 1); eps1 / sig1 written if non-null.
+// sigma1:f (value 0) and sigma1:sigma1 (value 1); eps1 / sig1 written if
+// non-null.  split = 1: the volumetric split law and its tensile energy.
 template <typename T>
 hipError_t launch_unit_response(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                                const T* phi, const T* x, const F6& f, T* psi1, T* eps1, T* sig1,
-                                double* partials, int nred, const int* active, hipStream_t st);
+                                const T* phi, const T* x, const F6& f, int split, T* psi1,
+                                T* eps1, T* sig1, double* partials, int nred, const int* active,
+                                hipStream_t st);
+// Newton update of the split mechanics: x += dx; partials ||dx||^2 (value 0)
+// and ||f + x||^2 (value 1) over the s components.
+template <typename T>
+hipError_t launch_newton_update(const Geom& g, T* x, const T* dx, const F6& f, double* partials,
+                                int nred, const int* active, hipStream_t st);
 
 // H = max(E_b^2 psi1 + psi_ini, Hn) (history) or E_b^2 psi1 + psi_ini; rhs = 2H.
 template <typename T>

@@ -189,7 +189,7 @@ hipError_t launch_pcg_fin_start(PcgDev* d, const double* p, int n, int B, double
 // unit response and history
 // ---------------------------------------------------------------------------
 
-template <typename T, int S>
+template <typename T, int S, bool SPLIT>
 __global__ void __launch_bounds__(TPB) k_unit_response(Geom g, const uint16_t* mat_id,
                                                        const MatEntry<T>* mat, const T* phi,
                                                        const T* x, F6 f, T* psi1, T* eps1,
@@ -199,6 +199,7 @@ __global__ void __launch_bounds__(TPB) k_unit_response(Geom g, const uint16_t* m
     if (skip(active, b)) return;
     const long long so = (long long)b * g.N, fo = so * S;
     const MatEntry<T>* mt = mat + (long long)b * g.mstride;
+    constexpr int NI = S == 3 ? 2 : 3;      // normal components (Mandel identity)
     double part = 0.0, part2 = 0.0;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.N;
          i += (long long)gridDim.x * blockDim.x) {
@@ -216,14 +217,27 @@ __global__ void __launch_bounds__(TPB) k_unit_response(Geom g, const uint16_t* m
             o[a] = acc;
             psi += e[a] * acc;
         }
+        T sg[S];
+#pragma unroll
+        for (int c = 0; c < S; ++c) sg[c] = gg * o[c];
+        if constexpr (SPLIT) {
+            // sigma = g (C:e - K tr I + K <tr>+ I) + K <tr>- I; only the
+            // tensile energy 1/2 e:C:e - 1/2 K tr^2 + 1/2 K <tr>+^2 drives damage
+            T tr = T(0);
+#pragma unroll
+            for (int c = 0; c < NI; ++c) tr += e[c];
+            const T add = tr > T(0) ? T(0) : (T(1) - gg) * m.K * tr;
+#pragma unroll
+            for (int c = 0; c < NI; ++c) sg[c] += add;
+            psi -= tr > T(0) ? T(0) : m.K * tr * tr;
+        }
         psi1[so + i] = T(0.5) * psi * m.drive;
 #pragma unroll
         for (int c = 0; c < S; ++c) {
-            const T sg = gg * o[c];
             if (eps1) eps1[fo + c * g.N + i] = e[c];
-            if (sig1) sig1[fo + c * g.N + i] = sg;
-            part += double(sg) * f.v[c];
-            part2 += double(sg) * double(sg);
+            if (sig1) sig1[fo + c * g.N + i] = sg[c];
+            part += double(sg[c]) * f.v[c];
+            part2 += double(sg[c]) * double(sg[c]);
         }
     }
     double pv[2] = {part, part2};
@@ -232,15 +246,53 @@ __global__ void __launch_bounds__(TPB) k_unit_response(Geom g, const uint16_t* m
 
 template <typename T>
 hipError_t launch_unit_response(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
-                                const T* phi, const T* x, const F6& f, T* psi1, T* eps1, T* sig1,
-                                double* partials, int nred, const int* active, hipStream_t st) {
+                                const T* phi, const T* x, const F6& f, int split, T* psi1,
+                                T* eps1, T* sig1, double* partials, int nred, const int* active,
+                                hipStream_t st) {
     const dim3 grid(nred, g.B);
-    if (g.s == 3)
-        hipLaunchKernelGGL((k_unit_response<T, 3>), grid, dim3(TPB), 0, st, g, mat_id, mat, phi, x,
-                           f, psi1, eps1, sig1, partials, active);
+    if (g.s == 3 && !split)
+        hipLaunchKernelGGL((k_unit_response<T, 3, false>), grid, dim3(TPB), 0, st, g, mat_id, mat,
+                           phi, x, f, psi1, eps1, sig1, partials, active);
+    else if (g.s == 3)
+        hipLaunchKernelGGL((k_unit_response<T, 3, true>), grid, dim3(TPB), 0, st, g, mat_id, mat,
+                           phi, x, f, psi1, eps1, sig1, partials, active);
+    else if (!split)
+        hipLaunchKernelGGL((k_unit_response<T, 6, false>), grid, dim3(TPB), 0, st, g, mat_id, mat,
+                           phi, x, f, psi1, eps1, sig1, partials, active);
     else
-        hipLaunchKernelGGL((k_unit_response<T, 6>), grid, dim3(TPB), 0, st, g, mat_id, mat, phi, x,
-                           f, psi1, eps1, sig1, partials, active);
+        hipLaunchKernelGGL((k_unit_response<T, 6, true>), grid, dim3(TPB), 0, st, g, mat_id, mat,
+                           phi, x, f, psi1, eps1, sig1, partials, active);
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_newton_update(Geom g, T* x, const T* dx, F6 f,
+                                                       double* partials, const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
+    const long long fo = (long long)b * g.s * g.N;
+    double s0 = 0.0, s1 = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.N;
+         i += (long long)gridDim.x * blockDim.x) {
+        for (int c = 0; c < g.s; ++c) {
+            const long long o = fo + c * g.N + i;
+            const T d = dx[o];
+            const T xn = x[o] + d;
+            x[o] = xn;
+            const double e = double(xn) + f.v[c];
+            s0 += double(d) * double(d);
+            s1 += e * e;
+        }
+    }
+    double pv[2] = {s0, s1};
+    block_sum_store<2>(pv, pslot(partials, b, 0), kRedBlocks, blockIdx.x);
+}
+
+template <typename T>
+hipError_t launch_newton_update(const Geom& g, T* x, const T* dx, const F6& f, double* partials,
+                                int nred, const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_newton_update<T>), dim3(nred, g.B), dim3(TPB), 0, st, g, x, dx, f,
+                       partials, active);
     return hipGetLastError();
 }
 
@@ -940,8 +992,10 @@ hipError_t launch_zero_int(int* p, int n, hipStream_t st) {
 
 #define INST(T)                                                                                    \
     template hipError_t launch_unit_response<T>(const Geom&, const uint16_t*, const MatEntry<T>*,  \
-                                                const T*, const T*, const F6&, T*, T*, T*,         \
+                                                const T*, const T*, const F6&, int, T*, T*, T*,    \
                                                 double*, int, const int*, hipStream_t);            \
+    template hipError_t launch_newton_update<T>(const Geom&, T*, const T*, const F6&, double*,     \
+                                                int, const int*, hipStream_t);                     \
     template hipError_t launch_history<T>(const Geom&, const T*, const T*, const T*,               \
                                           const double*, int, T*, T*, const int*, hipStream_t);    \
     template hipError_t launch_commit_history<T>(const Geom&, const T*, const T*, const double*,   \

@@ -278,7 +278,9 @@ struct Solver : SolverBase {
     uint16_t* mat_id;
     MatEntry<T>* mat;
     double *partials, *cgpA, *cgpB, *ppA, *ppB, *sums, *dE, *dgamma;
-    int *dmask[5], *dorder, *dm1, *count;
+    int *dmask[6], *dorder, *dm1, *count;
+    uint8_t* tmask = nullptr;       // split: tension flags of the Newton point
+    T* dxs = nullptr;               // split: Newton correction (s fields)
     CgDev* cg;
     PcgDev* pcg;
     // pinned host mirrors / staging
@@ -290,6 +292,8 @@ struct Solver : SolverBase {
     size_t stage_bytes = 0;
 
     int greenops = 0;
+    std::vector<int> step_greens;    // Green-operator applications per slot in this step
+    static constexpr int kMaxNewton = 100;
     std::vector<int> slope_warm;     // tmp holds a usable tangent of this slot
     static constexpr double kSlopeTol = 1e-8;
 
@@ -323,8 +327,11 @@ struct Solver : SolverBase {
         const size_t osums = L.off(sizeof(double) * kMaxVals * B);
         const size_t oE = L.off(sizeof(double) * B);
         const size_t ogam = L.off(sizeof(double) * kAndersonMax * B);
-        size_t omask[5];
-        for (int i = 0; i < 5; ++i) omask[i] = L.off(sizeof(int) * B);
+        size_t omask[6];
+        for (int i = 0; i < 6; ++i) omask[i] = L.off(sizeof(int) * B);
+        const bool split = c.split != RVE_SPLIT_NONE;
+        const size_t otm = split ? L.off(sizeof(uint8_t) * g.N * B) : 0;
+        const size_t odx = split ? L.off(sN) : 0;
         const size_t oord = L.off(sizeof(int) * kHist * B);
         const size_t om1 = L.off(sizeof(int) * B);
         const size_t ocnt = L.off(sizeof(int) * B);
@@ -351,7 +358,9 @@ struct Solver : SolverBase {
             s->sums = (double*)(base + osums);
             s->dE = (double*)(base + oE);
             s->dgamma = (double*)(base + ogam);
-            for (int i = 0; i < 5; ++i) s->dmask[i] = (int*)(base + omask[i]);
+            for (int i = 0; i < 6; ++i) s->dmask[i] = (int*)(base + omask[i]);
+            s->tmask = split ? (uint8_t*)(base + otm) : nullptr;
+            s->dxs = split ? (T*)(base + odx) : nullptr;
             s->dorder = (int*)(base + oord);
             s->dm1 = (int*)(base + om1);
             s->count = (int*)(base + ocnt);
@@ -471,6 +480,7 @@ struct Solver : SolverBase {
         B = g.B;
         slots.assign(B, SlotState());
         slope_warm.assign(B, 0);
+        step_greens.assign(B, 0);
         m1_max = std::max(0, std::min(c.anderson_depth, kAndersonMax)) + 1;
     }
 
@@ -596,7 +606,8 @@ struct Solver : SolverBase {
         for (int c = 0; c < 6; ++c) a.f[c] = T(c < g.s ? cfg.f[c] : 0.0);
         a.r = r;
         a.p = p;
-        a.cg = mode == XF_CG ? cg : nullptr;
+        a.cg = (mode == XF_CG || mode == XF_CG_T) ? cg : nullptr;
+        a.tmask = tmask;
         a.rr_part = cgpB;
         a.iter = iter;
         a.active = mask;
@@ -640,7 +651,8 @@ struct Solver : SolverBase {
         }
         return RVE_OK;
     }
-    int inv_x(int mode, T* out, double scale, double* part, const int* mask, int iter = 0) {
+    int inv_x(int mode, T* out, double scale, double* part, const int* mask, int iter = 0,
+              T* xsol = nullptr) {
         XinvArgs<T> a;
         std::memset(&a, 0, sizeof(a));
         a.g = g;
@@ -649,7 +661,7 @@ struct Solver : SolverBase {
         a.spec = spec;
         a.scale = T(scale);
         a.out = out;
-        a.x = x;
+        a.x = xsol ? xsol : x;
         a.p = p;
         a.r = r;
         a.cg = mode == XI_CG ? cg : nullptr;
@@ -734,10 +746,12 @@ struct Solver : SolverBase {
         return RVE_OK;
     }
 
-    // out = scale * F^-1{P : F[g C (eps + fcoef f)]}; ||out||^2 partials in part
+    // out = scale * F^-1{P : F[sigma(eps + fcoef f)]} with the handle's law
+    // (g C : eps, or the volumetric split, which also records the tension
+    // flags); ||out||^2 partials in part
     int green(const T* phi, const T* eps, double fcoef, T* out, double scale, double* part,
               const int* mask) {
-        CHK(fwd_x(XF_GREEN, phi, eps, fcoef, part, mask));
+        CHK(fwd_x(cfg.split == RVE_SPLIT_NONE ? XF_GREEN : XF_SPLIT, phi, eps, fcoef, part, mask));
         CHK(axes(nullptr, mask));
         CHK(inv_x(XI_STORE, out, scale, part, mask));
         ++greenops;
@@ -752,20 +766,19 @@ struct Solver : SolverBase {
         return false;
     }
 
-    // ---- (M) mechanics CG over the active RVEs --------------------------------
-    int mech_solve(const T* phi, int mask_id, const std::vector<int>& act, std::vector<int>& iters,
-                   std::vector<int>& rcs) {
-        const int* mk = dmask[mask_id];
-        CHK(green(phi, nullptr, 1.0, nullptr, 1.0, cgpB, mk));          // ||b||^2
-        CHK(green(phi, x, 1.0, r, -1.0, cgpA, mk));                     // r0 = -P[gC(f + x)]
-        HIPCHK(launch_cg_init(cg, cgpA, cgpB, nbx, B, cfg.tol_cg, cfg.max_cg, mk, st));
+    // ---- (M) mechanics over the active RVEs ------------------------------------
+    // CG iterations of P[C : u] = b after launch_cg_init, with the solution
+    // accumulated in xsol; mode XF_CG (the law g C) or XF_CG_T (the split's
+    // tangent).  Adds the iterations to iters and greens.
+    int cg_loop(const T* phi, int mode, T* xsol, const std::vector<int>& act,
+                std::vector<int>& iters, std::vector<int>& rcs) {
         int chunk = 8, k = 0;
         std::vector<ChunkPlanner> plan(B);
         for (;;) {
             for (int i = 0; i < chunk; ++i, ++k) {
-                CHK(fwd_x(XF_CG, phi, nullptr, 0.0, cgpA, nullptr, k));
+                CHK(fwd_x(mode, phi, nullptr, 0.0, cgpA, nullptr, k));
                 CHK(axes(cg, nullptr, k));
-                CHK(inv_x(XI_CG, nullptr, 1.0, cgpB, nullptr, k));
+                CHK(inv_x(XI_CG, nullptr, 1.0, cgpB, nullptr, k, xsol));
             }
             HIPCHK(hipMemcpyAsync(h_cg, cg, sizeof(CgDev) * B, hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
@@ -784,6 +797,7 @@ struct Solver : SolverBase {
             const CgDev& c = h_cg[b];
             const int it = c.conv == kNotDone ? k : c.conv;
             iters[b] += it;
+            step_greens[b] += it;
             greenops += it;
             if (c.status == 1) continue;
             if (c.status == 2) {
@@ -798,11 +812,70 @@ struct Solver : SolverBase {
         return RVE_OK;
     }
 
+    // Equilibrium for the unit load f at damage phi (Eq. 16a, Eq. 24 R1),
+    // warm-started from x.
+    int mech_solve(const T* phi, int mask_id, const std::vector<int>& act, std::vector<int>& iters,
+                   std::vector<int>& rcs) {
+        if (cfg.split != RVE_SPLIT_NONE) return mech_solve_split(phi, act, iters, rcs);
+        const int* mk = dmask[mask_id];
+        CHK(green(phi, nullptr, 1.0, nullptr, 1.0, cgpB, mk));          // ||b||^2
+        CHK(green(phi, x, 1.0, r, -1.0, cgpA, mk));                     // r0 = -P[gC(f + x)]
+        for (int b = 0; b < B; ++b)
+            if (act[b]) step_greens[b] += 2;
+        HIPCHK(launch_cg_init(cg, cgpA, cgpB, nbx, B, cfg.tol_cg, cfg.max_cg, mk, st));
+        return cg_loop(phi, XF_CG, x, act, iters, rcs);
+    }
+
+    // With the volumetric split the law is piecewise linear: Newton steps
+    // P[C_t : dx] = -P[sigma(f + x)], each by CG from dx = 0 with the tangent
+    // at the tension flags of f + x, then x += dx, until
+    // ||dx|| <= tol_cg ||f + x||.  Each tangent solve stops at
+    // ||r|| <= tol_cg ||P[sigma(f)]|| (the load scale, as ||b|| for the
+    // linear law; a tolerance relative to the shrinking Newton residual would
+    // ask for accuracy below the rounding of the Green operator).
+    int mech_solve_split(const T* phi, const std::vector<int>& act, std::vector<int>& iters,
+                         std::vector<int>& rcs) {
+        F6 f;
+        for (int c = 0; c < 6; ++c) f.v[c] = c < g.s ? cfg.f[c] : 0.0;
+        std::vector<int> nw(B, 0);
+        for (int b = 0; b < B; ++b) nw[b] = act[b] && rcs[b] == RVE_OK;
+        if (!any(nw)) return RVE_OK;
+        CHK(set_mask(5, nw));
+        CHK(green(phi, nullptr, 1.0, nullptr, 1.0, ppA, dmask[5]));   // ||P sigma(f)||^2 partials
+        for (int b = 0; b < B; ++b)
+            if (nw[b]) step_greens[b] += 1;
+        for (int nt = 0; nt < kMaxNewton && any(nw); ++nt) {
+            CHK(set_mask(5, nw));
+            const int* mk = dmask[5];
+            CHK(green(phi, x, 1.0, r, -1.0, cgpA, mk));                 // R and the flags
+            for (int b = 0; b < B; ++b)
+                if (nw[b]) step_greens[b] += 1;
+            HIPCHK(launch_fill<T>(dxs, T(0), g.s * g.N, B, mk, st));
+            HIPCHK(launch_cg_init(cg, cgpA, ppA, nbx, B, cfg.tol_cg, cfg.max_cg, mk, st));
+            CHK(cg_loop(phi, XF_CG_T, dxs, nw, iters, rcs));
+            HIPCHK(launch_newton_update<T>(g, x, dxs, f, partials, nred, mk, st));
+            HIPCHK(launch_sum_partials(partials, nred, 2, B, sums, mk, st));
+            CHK(read_sums(2));
+            for (int b = 0; b < B; ++b) {
+                if (!nw[b]) continue;
+                if (rcs[b] != RVE_OK) { nw[b] = 0; continue; }
+                if (std::sqrt(sum_of(b, 0)) <= cfg.tol_cg * std::max(std::sqrt(sum_of(b, 1)), 1e-300))
+                    nw[b] = 0;
+            }
+        }
+        for (int b = 0; b < B; ++b)
+            if (nw[b]) {
+                rcs[b] = RVE_ENOCONV;
+                hd->err = "split mechanics: Newton did not converge";
+            }
+        return RVE_OK;
+    }
+
     int unit_response(const T* phi, int mask_id, T* eps1 = nullptr, T* sig1 = nullptr) {
         F6 f;
         for (int c = 0; c < 6; ++c) f.v[c] = c < g.s ? cfg.f[c] : 0.0;
-        HIPCHK(launch_unit_response<T>(g, mat_id, mat, phi, x, f, psi1, eps1, sig1, partials, nred,
-                                       dmask[mask_id], st));
+        HIPCHK(launch_unit_response<T>(g, mat_id, mat, phi, x, f, cfg.split != RVE_SPLIT_NONE ? 1 : 0,
+                                       psi1, eps1, sig1, partials, nred, dmask[mask_id], st));
         HIPCHK(launch_sum_partials(partials, nred, 2, B, sums, dmask[mask_id], st));
         return read_sums(2);
     }
@@ -1198,6 +1271,7 @@ struct Solver : SolverBase {
             act[b] = 1;
         }
         int rc = RVE_OK;
+        step_greens.assign(B, 0);
         if (any(act)) rc = step_impl(dtau, act, rcs, info);
         // transactional: a failed RVE restarts its working strain from the committed one
         std::vector<int> failed(B, 0);
@@ -1358,7 +1432,7 @@ struct Solver : SolverBase {
                 o.n_stagger = nst[b];
                 o.n_cg = ncg[b];
                 o.n_pcg = npcg[b];
-                o.n_greenop = ncg[b] + 2 * (nst[b] + 1) + 1;   // CG + two set-up operators per solve + R1
+                o.n_greenop = step_greens[b] + 1;   // mechanics solves + the R1 check
                 o.res_R1 = R1[b];
                 o.res_R2 = R2[b];
                 o.res_R3 = std::fabs(D[b] - tau[b]) / tau[b];
@@ -1552,7 +1626,7 @@ static int validate(const rve_config* c, std::string& why) {
         if (c->n[i] < 2 || c->n[i] > 1024) { why = "n out of range [2, 1024]"; return RVE_EINVAL; }
     if (c->dim == 2 && c->n[2] != 1) { why = "n[2] must be 1 in 2D"; return RVE_EINVAL; }
     if (!(c->h > 0) || !(c->ell > 0) || !(c->k_res > 0)) { why = "h, ell, k_res must be > 0"; return RVE_EINVAL; }
-    if (c->split != RVE_SPLIT_NONE) { why = "only RVE_SPLIT_NONE is available"; return RVE_EINVAL; }
+    if (c->split != RVE_SPLIT_NONE && c->split != RVE_SPLIT_VOLDEV) { why = "bad split"; return RVE_EINVAL; }
     if (c->precision != RVE_PREC_FP64 && c->precision != RVE_PREC_MIXED) { why = "bad precision"; return RVE_EINVAL; }
     if (!(c->tol > 0) || !(c->tol_cg > 0) || !(c->tol_pcg > 0) || !(c->tol_al > 0)) { why = "tolerances must be > 0"; return RVE_EINVAL; }
     if (c->max_stagger < 1 || c->max_cg < 1 || c->max_pcg < 1) { why = "iteration limits must be >= 1"; return RVE_EINVAL; }
