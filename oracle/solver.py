@@ -47,8 +47,8 @@ class Problem:
 
     def __init__(self, n, h, ell, phases, phase_id, f, *, theta=None, void=None,
                  phi_disc=None, phi_M=0.8, k=1e-6, split="none", history=True,
-                 A_g=None, tol=1e-10, tol_cg=1e-12, tol_al=1e-12, max_stagger=200,
-                 max_cg=20000, frac_threshold=0.95, anderson_depth=5):
+                 A_g=None, tol=1e-10, tol_cg=1e-12, tol_al=1e-12, max_stagger=100,
+                 max_cg=20000, frac_threshold=0.95, anderson_depth=5, max_halvings=4):
         self.n = tuple(int(v) for v in n)
         self.d = len(self.n)
         self.s = mandel.nsym(self.d)
@@ -58,6 +58,7 @@ class Problem:
         self.max_stagger, self.max_cg = max_stagger, max_cg
         self.frac_threshold = frac_threshold
         self.anderson_depth = int(anderson_depth)
+        self.max_halvings = int(max_halvings)
         tr = lambda a: None if a is None else np.ascontiguousarray(np.asarray(a).T)
         pid = tr(phase_id)
         void_x = tr(void) if void is not None else np.zeros(self.n, dtype=bool)
@@ -283,13 +284,37 @@ def fractured(prob, phi):
     return bool(np.all(np.any(broken, axis=prob.load_axis)))
 
 
-def step(prob, st, dtau):
+class StaggerNotConverged(RuntimeError):
+    pass
+
+
+def step(prob, st, dtau, _depth=0):
     """One dissipation-controlled step tau^{n+1} = tau^n + dtau (Eq. 16).
 
-    The stagger map phi -> phi_new (one (M) then one (A)) is iterated to
-    its fixed point; the iterates are combined by Anderson mixing of depth
-    prob.anderson_depth (least squares on the last residual differences),
-    which leaves the fixed point unchanged and only shortens the way there.
+    At an unstable crack advance the staggered map can stall (its fixed
+    point is approached no further, Sec. 4.1 has the paper relax its Newton
+    steps for the same reason); dissipation control allows any subdivision
+    of the increment, so a step whose stagger has not converged within
+    max_stagger iterations leaves the state unchanged and is redone as two
+    steps of dtau / 2, down to dtau / 2^max_halvings.  Returns the record of
+    the last (sub)step.
+    """
+    try:
+        return _step_once(prob, st, dtau)
+    except StaggerNotConverged:
+        if _depth >= prob.max_halvings:
+            raise
+        step(prob, st, 0.5 * dtau, _depth + 1)
+        return step(prob, st, 0.5 * dtau, _depth + 1)
+
+
+def _step_once(prob, st, dtau):
+    """One step without subdivision.  The stagger map phi -> phi_new (one
+    (M) then one (A)) is iterated to its fixed point; the iterates are
+    combined by Anderson mixing of depth prob.anderson_depth (least squares
+    on the last residual differences), which leaves the fixed point
+    unchanged and only shortens the way there.  The state is changed only
+    once the stagger has converged.
     """
     tau = st.tau + dtau
     phi, E, x = st.phi.copy(), st.E, st.x.copy()
@@ -325,7 +350,7 @@ def step(prob, st, dtau):
         else:
             phi = phi_new
     else:
-        raise RuntimeError("stagger did not converge (err=%g)" % err)
+        raise StaggerNotConverged("stagger did not converge (err=%g)" % err)
     x, ncg = mechanics(prob, phi, x)
     n_cg += ncg
     _, sig1, psi1, Sigma1 = unit_response(prob, phi, x)
