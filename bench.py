@@ -120,6 +120,43 @@ def stored_traffic(kernel_file):
         return None
 
 
+def serving(n_requests, seed, rate):
+    """The serving form against the plain form on one seeded request stream
+    (2D 32^2-64^2 composites and polycrystals, 3D 16^3-24^3 composites,
+    Poisson arrivals): continuous batching in mixed precision versus one RVE
+    at a time in FP64, same arrivals.  Reports solves/s, p50/p99 latency and
+    the largest relative G_eff difference between the two."""
+    import torch
+    from paper_2508_07424_amd import mirve, serve
+    from paper_2508_07424_amd import workloads as W
+    stream = W.serving_stream(n_requests, seed=seed, sizes_2d=(32, 48, 64), sizes_3d=(16, 24),
+                              frac_3d=0.25, rate=rate, dtau_frac=0.02)
+    reqs = [serve.Request(i, w, arrival=a, max_steps=300) for i, (a, w) in enumerate(stream)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    srv = serve.Server(precision=mirve.RVE_PREC_MIXED, slots_per_pool=16)
+    try:
+        res_s = srv.run(reqs, realtime=True)
+    finally:
+        srv.close()
+    wall_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    res_p = serve.serve_sequential(reqs, precision=mirve.RVE_PREC_FP64)
+    wall_p = time.perf_counter() - t0
+    both = [(a, b) for a, b in zip(res_s, res_p) if a.G_eff is not None and b.G_eff is not None]
+    dev = max((abs(a.G_eff - b.G_eff) / abs(b.G_eff) for a, b in both), default=None)
+    out = {"requests": n_requests, "arrival_rate_per_s": rate,
+           "served_mixed_batched": serve.summarize(res_s, wall_s),
+           "plain_fp64_one_at_a_time": serve.summarize(res_p, wall_p),
+           "max_rel_G_eff_diff": None if dev is None else float("%.3g" % dev),
+           "compared": len(both), "admission_stalls": srv.stalls,
+           "peak_workspace_bytes": srv.peak_bytes}
+    ps = out["plain_fp64_one_at_a_time"]["solves_per_s"]
+    if ps:
+        out["solves_speedup"] = round(out["served_mixed_batched"]["solves_per_s"] / ps, 2)
+    return out
+
+
 def cpu_baseline(w, seconds):
     """The oracle's conjugate-gradient Green-operator solve on the host,
     bounded to about `seconds` of work: voxel-iterations per second."""
@@ -155,6 +192,9 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=8,
+                    help="requests of the serving comparison (0: skip it)")
+    ap.add_argument("--serve-rate", type=float, default=2.0, help="Poisson arrivals per second")
     ap.add_argument("--roofline-only", action="store_true",
                     help="set up the batch and time the Green-operator passes only (for counter runs)")
     args = ap.parse_args()
@@ -222,6 +262,10 @@ def main():
                    "operator_voxel_iter_per_s": round(rve.N * args.batch / op_s, 1)},
         "roofline": roof,
     }
+    if args.serve_requests > 0:
+        del rve
+        torch.cuda.empty_cache()
+        out["serving"] = serving(args.serve_requests, seed=5, rate=args.serve_rate)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wls[0], args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -103,7 +103,8 @@ typedef struct {
     double tol_cg;         /* mechanics CG: ||r|| <= tol_cg ||b||                    */
     double tol_pcg;        /* damage PCG: ||r|| <= tol_pcg ||rhs||                   */
     double tol_al;         /* dissipation constraint: |D - tau| <= tol_al tau        */
-    int    max_stagger;    /* stagger iteration limit per step                       */
+    int    max_stagger;    /* stagger iteration limit per step; a step that reaches
+                              it is redone as two half steps, down to dtau / 16     */
     int    max_cg;         /* CG iteration limit per mechanics solve                 */
     int    max_pcg;        /* PCG iteration limit per damage solve                   */
     int    anderson_depth; /* Anderson acceleration depth of the stagger (0 = off)   */

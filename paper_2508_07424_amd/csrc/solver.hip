@@ -293,6 +293,8 @@ struct Solver : SolverBase {
 
     int greenops = 0;
     std::vector<int> step_greens;    // Green-operator applications per slot in this step
+    std::vector<int> stag_fail;      // the slot's last step stopped on the stagger limit
+    static constexpr int kMaxHalvings = 4;
     static constexpr int kMaxNewton = 100;
     std::vector<int> slope_warm;     // tmp holds a usable tangent of this slot
     static constexpr double kSlopeTol = 1e-8;
@@ -1272,20 +1274,56 @@ struct Solver : SolverBase {
         }
         int rc = RVE_OK;
         step_greens.assign(B, 0);
-        if (any(act)) rc = step_impl(dtau, act, rcs, info);
-        // transactional: a failed RVE restarts its working strain from the committed one
-        std::vector<int> failed(B, 0);
-        for (int b = 0; b < B; ++b) failed[b] = act[b] && rcs[b] != RVE_OK;
-        if (any(failed) && set_mask(1, failed) == RVE_OK) {
-            (void)launch_copy<T>(x_c, x, g.s * g.N, B, dmask[1], st);
-            (void)hipStreamSynchronize(st);
-        }
+        std::vector<double> dt(dtau, dtau + B);
+        if (any(act)) rc = step_split(dt, act, rcs, info, 0);
         int worst = rc;
         for (int b = 0; b < B; ++b) {
             if (status) status[b] = rc != RVE_OK && act[b] ? rc : rcs[b];
             if (worst == RVE_OK && rcs[b] != RVE_OK) worst = rcs[b];
         }
         return worst;
+    }
+
+    // One step of dt[b] for the slots in act.  At an unstable crack advance
+    // the staggered map can stall; dissipation control allows any
+    // subdivision of the increment, so a slot whose stagger has not
+    // converged within max_stagger iterations (its state left unchanged) is
+    // redone as two steps of dt / 2, down to dt / 2^kMaxHalvings.
+    int step_split(const std::vector<double>& dt, const std::vector<int>& act,
+                   std::vector<int>& rcs, rve_step_info* info, int depth) {
+        std::vector<int> r(rcs);
+        for (int b = 0; b < B; ++b)
+            if (act[b]) r[b] = RVE_OK;
+        stag_fail.assign(B, 0);
+        CHK(step_impl(dt.data(), act, r, info));
+        // transactional: a failed slot restarts its working strain from the committed one
+        std::vector<int> failed(B, 0);
+        for (int b = 0; b < B; ++b) failed[b] = act[b] && r[b] != RVE_OK;
+        if (any(failed)) {
+            CHK(set_mask(1, failed));
+            HIPCHK(launch_copy<T>(x_c, x, g.s * g.N, B, dmask[1], st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
+        std::vector<int> redo(B, 0);
+        std::vector<double> half(B, 0.0);
+        for (int b = 0; b < B; ++b) {
+            if (!act[b]) continue;
+            if (r[b] == RVE_ENOCONV && stag_fail[b] && depth < kMaxHalvings) {
+                redo[b] = 1;
+                half[b] = 0.5 * dt[b];
+            } else {
+                rcs[b] = r[b];
+            }
+        }
+        if (!any(redo)) return RVE_OK;
+        std::vector<int> r2(rcs);
+        CHK(step_split(half, redo, r2, info, depth + 1));
+        std::vector<int> again(B, 0);
+        for (int b = 0; b < B; ++b) again[b] = redo[b] && r2[b] == RVE_OK;
+        if (any(again)) CHK(step_split(half, again, r2, info, depth + 1));
+        for (int b = 0; b < B; ++b)
+            if (redo[b]) rcs[b] = r2[b];
+        return RVE_OK;
     }
 
     int step_impl(const double* dtau, const std::vector<int>& act, std::vector<int>& rcs,
@@ -1372,6 +1410,7 @@ struct Solver : SolverBase {
         for (int b = 0; b < B; ++b)
             if (act[b] && rcs[b] == RVE_OK && !conv[b]) {
                 rcs[b] = RVE_ENOCONV;
+                stag_fail[b] = 1;
                 hd->err = "stagger did not converge";
             }
         std::vector<int> ok(B, 0);
@@ -1678,7 +1717,7 @@ int rve_default_config(rve_config* c) {
     c->tol_cg = 1e-10;
     c->tol_pcg = 1e-12;
     c->tol_al = 1e-10;
-    c->max_stagger = 300;
+    c->max_stagger = 100;
     c->max_cg = 20000;
     c->max_pcg = 20000;
     c->anderson_depth = 5;

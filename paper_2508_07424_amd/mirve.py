@@ -76,6 +76,9 @@ class rve_step_info(C.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libmirve.so is not built; run `python -m paper_2508_07424_amd.build`")
+    # torch first: the library then binds to the HIP runtime torch has
+    # loaded, so that its workspaces and streams belong to the same runtime
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     P, I, D, S = C.c_void_p, C.c_int, C.c_double, C.c_size_t
     dp = C.POINTER(C.c_double)

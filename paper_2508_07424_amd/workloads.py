@@ -288,3 +288,65 @@ def composite_3d(n=128, seed=1, spheres=40, vf=0.2, E_ratio=5.0, Gc_ratio=3.0, e
                     phase_id=mask.astype(np.uint16), f=load_zz(), dtau=0.01 * n * n * h * h,
                     void=void, phi_disc=tips, phi_M=0.8, k=1e-6,
                     meta={"name": "composite_3d_%d" % n, "r": r, "vf": float(mask.mean())})
+
+
+def smooth_sizes(lo, hi):
+    """Grid sizes in [lo, hi] whose prime factors are 2, 3, 5, 7, even."""
+    out = []
+    for n in range(lo, hi + 1):
+        if n % 2:
+            continue
+        m = n
+        for p in (2, 3, 5, 7):
+            while m % p == 0:
+                m //= p
+        if m == 1:
+            out.append(n)
+    return out
+
+
+def serving_stream(count, seed=1, sizes_2d=(32, 48, 64, 96, 128), sizes_3d=(16, 24, 32),
+                   frac_3d=0.25, rate=1.0, dtau_frac=0.02):
+    """Requests of a serving run: list of (arrival seconds, Workload).
+
+    Per request, from a seeded generator: the dimension (3D with probability
+    frac_3d), the side log-uniform over the given 7-smooth sizes (a few
+    sizes, so that requests of one size can share a batched pool),
+    the microstructure (fibre/sphere composite or Voronoi polycrystal with
+    probability 1/2 each; polycrystals in 2D only), elastic contrast
+    U[1, 10] and toughness contrast U[1, 4].  Arrivals are a Poisson process
+    of the given rate (requests per second).  dtau = dtau_frac Gc L (larger
+    than the paper's 0.01 so that a request needs tens of steps).
+    """
+    rng = np.random.default_rng(seed)
+    s2, s3 = sorted(sizes_2d), sorted(sizes_3d)
+    t = 0.0
+    out = []
+    for i in range(count):
+        t += rng.exponential(1.0 / rate)
+        three = rng.random() < frac_3d
+        sizes = s3 if three else s2
+        lw = np.log(sizes)
+        pick = np.exp(rng.uniform(lw[0], lw[-1]))
+        n = min(sizes, key=lambda v: abs(np.log(v) - np.log(pick)))
+        e_c = float(rng.uniform(1.0, 10.0))
+        g_c = float(rng.uniform(1.0, 4.0))
+        s = int(rng.integers(1, 2 ** 31 - 1))
+        if three:
+            vol = n ** 3
+            spheres = max(1, int(round(0.15 * vol / (4.0 / 3.0 * math.pi * (n / 6.0) ** 3))))
+            w = composite_3d(n=n, seed=s, spheres=spheres, vf=0.15, E_ratio=e_c, Gc_ratio=g_c)
+            w.dtau = dtau_frac * n * n
+        elif rng.random() < 0.5:
+            vf = float(rng.uniform(0.1, 0.3))
+            w = composite_2d(n=n, seed=s, E_ratio=e_c, Gc_ratio=g_c, vf=vf, ell=2.0,
+                             crack=max(2, n // 6), rmin=max(2.0, n / 40.0), rmax=max(3.0, n / 24.0))
+            w.dtau = dtau_frac * n
+        else:
+            grains = max(4, int(round((n / 40.0) ** 2 * 4)))
+            w = polycrystal_2d(n=n, grains=grains, seed=s, zener=float(rng.uniform(1.0, 4.0)),
+                               a_cleave=float(rng.uniform(0.0, 3.0)), ell=2.0)
+            w.dtau = dtau_frac * n
+        w.meta.update({"request": i, "contrast_E": e_c, "contrast_Gc": g_c})
+        out.append((t, w))
+    return out
