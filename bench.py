@@ -28,6 +28,12 @@ os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
 os.environ.setdefault("MKL_NUM_THREADS", "1")
 
 HBM_PEAK_GBS = 8000.0
+T_START = time.perf_counter()
+
+
+def progress(msg):
+    """Progress on stderr (the JSON result is the only line on stdout)."""
+    print("[bench %6.1fs] %s" % (time.perf_counter() - T_START, msg), file=sys.stderr, flush=True)
 PASS_NAMES = {3: "x-forward + constitutive + CG direction (k_xfwd)",
               1: "axis pass: y FFT, projection, inverse y FFT (k_axis)",
               4: "x-inverse + CG update (k_xinv)"}
@@ -133,15 +139,21 @@ def serving(n_requests, seed, rate):
                               frac_3d=0.25, rate=rate, dtau_frac=0.02)
     reqs = [serve.Request(i, w, arrival=a, max_steps=300) for i, (a, w) in enumerate(stream)]
     torch.cuda.synchronize()
+    progress("serving %d requests, mixed precision, continuous batching" % n_requests)
     t0 = time.perf_counter()
     srv = serve.Server(precision=mirve.RVE_PREC_MIXED, slots_per_pool=16)
     try:
-        res_s = srv.run(reqs, realtime=True)
+        res_s = srv.run(reqs, realtime=True,
+                        on_result=lambda r: progress("  served %d: G_eff %s after %d steps"
+                                                     % (r.rid, r.G_eff, r.steps)))
     finally:
         srv.close()
     wall_s = time.perf_counter() - t0
+    progress("same requests, plain FP64, one at a time")
     t0 = time.perf_counter()
-    res_p = serve.serve_sequential(reqs, precision=mirve.RVE_PREC_FP64)
+    res_p = serve.serve_sequential(reqs, precision=mirve.RVE_PREC_FP64,
+                                   on_result=lambda r: progress("  solved %d: G_eff %s after %d steps"
+                                                                % (r.rid, r.G_eff, r.steps)))
     wall_p = time.perf_counter() - t0
     both = [(a, b) for a, b in zip(res_s, res_p) if a.G_eff is not None and b.G_eff is not None]
     dev = max((abs(a.G_eff - b.G_eff) / abs(b.G_eff) for a, b in both), default=None)
@@ -208,18 +220,21 @@ def main():
     prec = mirve.RVE_PREC_FP64 if args.precision == "fp64" else mirve.RVE_PREC_MIXED
     wls = _workloads(args.size, args.batch)
     # one batched handle: every launch covers all RVEs of the batch
+    progress("setting up %d RVEs" % len(wls))
     rve = mirve.from_workloads(wls, precision=prec)
     dtaus = [w.dtau for w in wls]
     torch.cuda.synchronize()
+    progress("set up")
     if args.roofline_only:
         roof = roofline(rve, torch)
         roof["copy_gbs"] = copy_bandwidth(torch)
         print(json.dumps({"roofline": roof}), flush=True)
         return
 
-    for _ in range(args.warmup):
+    for k in range(args.warmup):
         _, st = rve.rve_step_dissipation_slots(dtaus)
         assert all(v == 0 for v in st), st
+        progress("warm-up step %d" % (k + 1))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     greenops = 0
@@ -227,6 +242,7 @@ def main():
         info, st = rve.rve_step_dissipation_slots(dtaus)
         assert all(v == 0 for v in st), st
         greenops += sum(rve.N * i["n_greenop"] for i in info)
+        progress("timed step")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sec = t1 - t0
@@ -267,6 +283,7 @@ def main():
         torch.cuda.empty_cache()
         out["serving"] = serving(args.serve_requests, seed=5, rate=args.serve_rate)
     if not args.no_cpu_baseline:
+        progress("oracle on the host")
         out["cpu_baseline"] = cpu_baseline(wls[0], args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

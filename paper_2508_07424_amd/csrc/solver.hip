@@ -20,6 +20,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <map>
 #include <memory>
 #include <string>
@@ -288,13 +289,16 @@ struct Solver : SolverBase {
     PcgDev* h_pcg = nullptr;
     double* h_sums = nullptr;
     int* h_count = nullptr;
-    void* h_stage = nullptr;
+    void* h_stage = nullptr;       // ring of pinned upload slots
     size_t stage_bytes = 0;
+    size_t stage_off = 0;          // next free byte; reset when the stream is drained
 
     int greenops = 0;
     std::vector<int> step_greens;    // Green-operator applications per slot in this step
     std::vector<int> stag_fail;      // the slot's last step stopped on the stagger limit
+    bool trace = false;              // MIRVE_TRACE set: stagger progress on stderr
     static constexpr int kMaxHalvings = 4;
+    static constexpr double kGammaMax = 10.0;
     static constexpr int kMaxNewton = 100;
     std::vector<int> slope_warm;     // tmp holds a usable tangent of this slot
     static constexpr double kSlopeTol = 1e-8;
@@ -483,6 +487,8 @@ struct Solver : SolverBase {
         slots.assign(B, SlotState());
         slope_warm.assign(B, 0);
         step_greens.assign(B, 0);
+        const char* tr = std::getenv("MIRVE_TRACE");
+        trace = tr && *tr && *tr != '0';
         m1_max = std::max(0, std::min(c.anderson_depth, kAndersonMax)) + 1;
     }
 
@@ -516,7 +522,7 @@ struct Solver : SolverBase {
         HIPCHK(hipHostMalloc((void**)&h_pcg, sizeof(PcgDev) * B, hipHostMallocDefault));
         HIPCHK(hipHostMalloc((void**)&h_sums, sizeof(double) * kMaxVals * B, hipHostMallocDefault));
         HIPCHK(hipHostMalloc((void**)&h_count, sizeof(int) * B, hipHostMallocDefault));
-        stage_bytes = sizeof(double) * kHist * B + 64;
+        stage_bytes = std::max<size_t>(64 * 1024, 64 * (sizeof(double) * kHist * B + 256));
         HIPCHK(hipHostMalloc(&h_stage, stage_bytes, hipHostMallocDefault));
         // twiddles, exp(-2 pi i m / N), computed in long double
         std::vector<cplx<T>> t;
@@ -536,32 +542,43 @@ struct Solver : SolverBase {
         HIPCHK(launch_fill<T>(x, T(0), g.s * g.N, B, nullptr, st));
         HIPCHK(launch_fill<T>(x_c, T(0), g.s * g.N, B, nullptr, st));
         HIPCHK(launch_fill<T>(phi_c, T(0), g.N, B, nullptr, st));
-        HIPCHK(hipStreamSynchronize(st));
+        CHK(drain());
         return RVE_OK;
     }
 
     int sync() {
-        HIPCHK(hipStreamSynchronize(st));
+        CHK(drain());
         return RVE_OK;
     }
 
     // small host -> device uploads through the pinned staging buffer
-    int upload_ints(int* dev, const std::vector<int>& v) {
-        HIPCHK(hipStreamSynchronize(st));
-        std::memcpy(h_stage, v.data(), sizeof(int) * v.size());
-        HIPCHK(hipMemcpyAsync(dev, h_stage, sizeof(int) * v.size(), hipMemcpyHostToDevice, st));
+    // The copies are queued on the stream without waiting: each upload takes
+    // its own slot of the pinned ring, which is only reused after the stream
+    // has been drained (every drain resets the ring).
+    int upload_bytes(void* dev, const void* src, size_t n) {
+        const size_t need = (n + 255) & ~size_t(255);
+        if (stage_off + need > stage_bytes) CHK(drain());
+        char* slot = (char*)h_stage + stage_off;
+        std::memcpy(slot, src, n);
+        HIPCHK(hipMemcpyAsync(dev, slot, n, hipMemcpyHostToDevice, st));
+        stage_off += need;
         return RVE_OK;
     }
+    int upload_ints(int* dev, const std::vector<int>& v) {
+        return upload_bytes(dev, v.data(), sizeof(int) * v.size());
+    }
     int upload_doubles(double* dev, const std::vector<double>& v) {
+        return upload_bytes(dev, v.data(), sizeof(double) * v.size());
+    }
+    int drain() {
         HIPCHK(hipStreamSynchronize(st));
-        std::memcpy(h_stage, v.data(), sizeof(double) * v.size());
-        HIPCHK(hipMemcpyAsync(dev, h_stage, sizeof(double) * v.size(), hipMemcpyHostToDevice, st));
+        stage_off = 0;
         return RVE_OK;
     }
     int read_sums(int nv) {
         (void)nv;
         HIPCHK(hipMemcpyAsync(h_sums, sums, sizeof(double) * kMaxVals * B, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        CHK(drain());
         return RVE_OK;
     }
     double sum_of(int b, int v) const { return h_sums[b * kMaxVals + v]; }
@@ -578,7 +595,7 @@ struct Solver : SolverBase {
         return RVE_OK;
     }
     int download(double* dst, const T* src, size_t n) {
-        HIPCHK(hipStreamSynchronize(st));
+        CHK(drain());
         if (sizeof(T) == sizeof(double)) {
             HIPCHK(hipMemcpy(dst, src, n * sizeof(double), hipMemcpyDeviceToHost));
         } else {
@@ -783,7 +800,7 @@ struct Solver : SolverBase {
                 CHK(inv_x(XI_CG, nullptr, 1.0, cgpB, nullptr, k, xsol));
             }
             HIPCHK(hipMemcpyAsync(h_cg, cg, sizeof(CgDev) * B, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
+            CHK(drain());
             bool all = true;
             int next = 4;
             for (int b = 0; b < B; ++b) {
@@ -922,7 +939,7 @@ struct Solver : SolverBase {
                 pcur = pn;
             }
             HIPCHK(hipMemcpyAsync(h_pcg, pcg, sizeof(PcgDev) * B, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
+            CHK(drain());
             bool all = true;
             int next = 2;
             for (int b = 0; b < B; ++b) {
@@ -1045,7 +1062,9 @@ struct Solver : SolverBase {
                 }
                 if (D[b] < tau[b]) lo[b] = std::max(lo[b], E[b]);
                 else hi[b] = std::min(hi[b], E[b]);
-                if (!std::isinf(hi[b]) && hi[b] - lo[b] <= 1e-15 * hi[b]) {
+                // a bracket narrower than the resolution of D(E) ends the search
+                const double res = sizeof(T) == sizeof(double) ? 1e-15 : 1e-9;
+                if (!std::isinf(hi[b]) && hi[b] - lo[b] <= res * hi[b]) {
                     Eout[b] = E[b];
                     al[b] = 0;
                     continue;
@@ -1098,9 +1117,12 @@ struct Solver : SolverBase {
             double A[kAndersonMax][kAndersonMax], bv[kAndersonMax];
             double tr = 0.0;
             for (int a = 0; a < m; ++a) tr += hs[a * kAndersonMax + a];
+            // FP32 fields carry noise of about 1e-7 in the residual differences:
+            // the ridge keeps the small least-squares problem above it
+            const double ridge = sizeof(T) == sizeof(double) ? 1e-14 : 1e-6;
             for (int a = 0; a < m; ++a) {
                 for (int c = 0; c < m; ++c) A[a][c] = hs[a * kAndersonMax + c];
-                A[a][a] += 1e-14 * tr;
+                A[a][a] += ridge * tr;
                 bv[a] = hs[kAndersonMax * kAndersonMax + a];
             }
             bool ok = true;
@@ -1125,8 +1147,15 @@ struct Solver : SolverBase {
                 for (int j = k + 1; j < m; ++j) s -= A[k][j] * gb[j];
                 gb[k] = s / A[k][k];
             }
-            for (int k = 0; k < m; ++k)
+            double gsum = 0.0;
+            for (int k = 0; k < m; ++k) {
                 if (!std::isfinite(gb[k])) ok = false;
+                gsum += std::fabs(gb[k]);
+            }
+            // FP32: an extrapolation far outside the history is noise; take the
+            // plain fixed-point step instead (gamma = 0 gives phi(E))
+            if (ok && sizeof(T) != sizeof(double) && gsum > kGammaMax)
+                for (int k = 0; k < m; ++k) gb[k] = 0.0;
             if (!ok) {
                 rcs[b] = RVE_ENUMERIC;
                 hd->err = "singular or non-finite Anderson system";
@@ -1198,7 +1227,7 @@ struct Solver : SolverBase {
             ids[i] = (uint16_t)id;
             S.min_gc = std::min(S.min_gc, phases[ph].Gc);
         }
-        HIPCHK(hipStreamSynchronize(st));
+        CHK(drain());
         HIPCHK(hipMemcpy(mat_id + (long long)slot * g.N, ids.data(), sizeof(uint16_t) * g.N,
                          hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(mat + (long long)slot * g.mstride, table.data(),
@@ -1302,7 +1331,7 @@ struct Solver : SolverBase {
         if (any(failed)) {
             CHK(set_mask(1, failed));
             HIPCHK(launch_copy<T>(x_c, x, g.s * g.N, B, dmask[1], st));
-            HIPCHK(hipStreamSynchronize(st));
+            CHK(drain());
         }
         std::vector<int> redo(B, 0);
         std::vector<double> half(B, 0.0);
@@ -1355,6 +1384,9 @@ struct Solver : SolverBase {
                 const double dphi = std::sqrt(sum_of(b, 0)) / std::max(std::sqrt(sum_of(b, 1)), 1e-300);
                 const double dEr = std::fabs(En[b] - E[b]) / std::max(std::fabs(En[b]), 1e-300);
                 const double err = std::max(dphi, dEr);
+                if (trace)
+                    std::fprintf(stderr, "[mirve] slot %d step %d stagger %d dphi %.3e dE %.3e E %.9g\n",
+                                 b, slots[b].step + 1, it, dphi, dEr, En[b]);
                 E[b] = En[b];
                 if (!std::isfinite(err)) {
                     rcs[b] = RVE_ENUMERIC;
@@ -1449,7 +1481,7 @@ struct Solver : SolverBase {
         HIPCHK(launch_fracture_count<T>(g, mat_id, mat, phi_c, cfg.frac_threshold, load_axis, count,
                                         dmask[1], st));
         HIPCHK(hipMemcpyAsync(h_count, count, sizeof(int) * B, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        CHK(drain());
         for (int b = 0; b < B; ++b) {
             if (!ok[b]) continue;
             SlotState& S = slots[b];
@@ -1525,7 +1557,7 @@ struct Solver : SolverBase {
         if (cnt != N) return fail(RVE_EINVAL, "field size mismatch");
         for (size_t i = 0; i < N; ++i)
             if (!std::isfinite(hostp[i])) return fail(RVE_EINVAL, "non-finite field value");
-        HIPCHK(hipStreamSynchronize(st));
+        CHK(drain());
         switch (which) {
             case RVE_FIELD_PHI: return upload(phi_c + so, hostp, N);
             case RVE_FIELD_HIST: return upload(Hn + so, hostp, N);
@@ -1538,7 +1570,7 @@ struct Solver : SolverBase {
         CHK(check_slot(slot));
         const size_t sN = (size_t)g.s * g.N;
         const long long fo = (long long)slot * g.s * g.N;
-        HIPCHK(hipStreamSynchronize(st));
+        CHK(drain());
         CHK(upload(r + fo, eps, sN));
         CHK(set_mask(0, only(slot)));
         CHK(green(phi_c, r, 0.0, p, 1.0, cgpB, dmask[0]));
@@ -1610,7 +1642,7 @@ struct Solver : SolverBase {
             c[b].max_it = -1;           // timing: alpha = 0, beta = 1/2, no stopping test
             c[b].conv = rd[b] ? kNotDone : -1;
         }
-        HIPCHK(hipStreamSynchronize(st));
+        CHK(drain());
         HIPCHK(hipMemcpy(cg, c.data(), sizeof(CgDev) * B, hipMemcpyHostToDevice));
         AxisArgs<T> a;
         std::memset(&a, 0, sizeof(a));

@@ -158,7 +158,9 @@ def make_config(n, h=1.0, ell=1.5, k=1e-6, f=None, precision=RVE_PREC_FP64, **kw
         c.f[i] = ff[i]
     c.precision = precision
     if precision == RVE_PREC_MIXED:
-        c.tol, c.tol_cg, c.tol_pcg, c.tol_al = 1e-5, 1e-6, 1e-6, 1e-7
+        # FP32 fields resolve D(E) to about 1e-7: the constraint is held to
+        # 1e-6, the damage solves that evaluate it to 1e-7
+        c.tol, c.tol_cg, c.tol_pcg, c.tol_al = 1e-5, 1e-6, 1e-7, 1e-6
     for key, v in kw.items():
         setattr(c, key, v)
     return c

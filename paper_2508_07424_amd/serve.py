@@ -256,10 +256,10 @@ class Server:
                 p.rve.rve_release_slot(i)
         return done
 
-    def run(self, requests, realtime=True):
+    def run(self, requests, realtime=True, on_result=None):
         """Serve requests (sorted by arrival).  With realtime, a request is
         submitted once the clock passes its arrival time; otherwise all are
-        submitted at once."""
+        submitted at once.  on_result(result) is called as results come."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         k = 0
         self.t0 = self.clock()
@@ -271,7 +271,9 @@ class Server:
             if not self.pending():
                 time.sleep(max(0.0, min(0.01, reqs[k].arrival - now)))
                 continue
-            self.tick()
+            for res in self.tick():
+                if on_result:
+                    on_result(res)
         return [self.results[r.rid] for r in requests]
 
     def close(self):
@@ -292,7 +294,7 @@ def summarize(results, wall):
 
 
 def serve_sequential(requests, precision=mirve.RVE_PREC_FP64, split=mirve.RVE_SPLIT_NONE,
-                     tol=None, clock=time.perf_counter):
+                     tol=None, clock=time.perf_counter, on_result=None):
     """The plain form: one RVE at a time, first come first served, each in a
     handle of its own (batch 1).  Latency includes the wait behind earlier
     requests; arrivals are honoured (the GPU idles until the next one)."""
@@ -330,4 +332,6 @@ def serve_sequential(requests, precision=mirve.RVE_PREC_FP64, split=mirve.RVE_SP
         r.close()
         torch.cuda.synchronize()
         out[req.rid] = Result(req.rid, G, steps, st, req.arrival, start, clock() - t0, greens)
+        if on_result:
+            on_result(out[req.rid])
     return [out[r.rid] for r in requests]
