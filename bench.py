@@ -35,7 +35,7 @@ def progress(msg):
     """Progress on stderr (the JSON result is the only line on stdout)."""
     print("[bench %6.1fs] %s" % (time.perf_counter() - T_START, msg), file=sys.stderr, flush=True)
 PASS_NAMES = {3: "x-forward + constitutive + CG direction (k_xfwd)",
-              1: "axis pass: y FFT, projection, inverse y FFT (k_axis)",
+              1: "axis pass: last-axis FFT, projection, inverse FFT (k_axis)",
               4: "x-inverse + CG update (k_xinv)"}
 PASS_SYMBOLS = {3: "k_xfwd", 1: "k_axis", 4: "k_xinv"}
 
@@ -49,6 +49,42 @@ def _workloads(size, batch, seed0=1):
         out.append(W.composite_2d(n=size, seed=seed0 + i, E_ratio=e, Gc_ratio=g, vf=0.3, ell=2.0,
                                   crack=int(round(40 * size / 256))))
     return out
+
+
+def _polycrystals(size, batch):
+    """Elastic polycrystals: 200 periodic Voronoi grains per realization
+    (seed 1000 + r), in-plane orientations U[0, 2 pi), cubic C11 = 1,
+    C12 = 0.5, C44 = z / 4 with the Zener ratio z ~ U[1, 4] and cleavage
+    toughness Gc = 1 + a cos^2(4 theta), a ~ U[0, 3], per realization;
+    l = 2, a notch of 0.1 L_x (Sec. 5.3)."""
+    import numpy as np
+    from paper_2508_07424_amd import workloads as W
+    rng = np.random.default_rng(77)
+    return [W.polycrystal_2d(n=size, grains=200, seed=1000 + r, zener=float(rng.uniform(1, 4)),
+                             a_cleave=float(rng.uniform(0, 3)), ell=2.0) for r in range(batch)]
+
+
+def _spheres(size, batch):
+    """3D composites: 40 spheres by RSA at volume fraction 0.2, E contrast 5,
+    Gc contrast 3, nu = 0.3, l = 2, a square notch L/2 x L/2 in the z
+    mid-plane, load e_z (x) e_z."""
+    from paper_2508_07424_amd import workloads as W
+    return [W.composite_3d(n=size, seed=1 + r, spheres=40, vf=0.2, E_ratio=5.0, Gc_ratio=3.0)
+            for r in range(batch)]
+
+
+WORKLOADS = {
+    # name: (builder, default size, default batch, default precision, description)
+    "composite256": (_workloads, 256, 63, "fp64",
+                     "2D fibre composite {n}x{n}, vf 0.3, r~U[5,9], E ratio {{2,5,10}} x Gc ratio "
+                     "{{1,2,4}} x {r} realizations, l=2, 40-voxel notch"),
+    "polycrystal512": (_polycrystals, 512, 64, "mixed",
+                       "2D cubic polycrystal {n}x{n}, 200 Voronoi grains, Zener U[1,4], "
+                       "Gc = 1 + a cos^2(4 theta) with a U[0,3], l=2, notch 0.1 L, {b} realizations"),
+    "spheres128": (_spheres, 128, 1, "mixed",
+                   "3D sphere composite {n}^3, 40 spheres vf 0.2, E ratio 5, Gc ratio 3, l=2, "
+                   "square notch L/2 x L/2, load zz, {b} realization(s)"),
+}
 
 
 def roofline(r, torch, repeat=50):
@@ -199,9 +235,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=63, help="RVEs (9 contrast cases x 7 realizations)")
-    ap.add_argument("--size", type=int, default=256)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="composite256")
+    ap.add_argument("--batch", type=int, default=None,
+                    help="RVEs (default: 63 = 9 contrast cases x 7 realizations for composite256)")
+    ap.add_argument("--size", type=int, default=None)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default=None)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=8,
@@ -217,15 +255,23 @@ def main():
 
     import torch
     from paper_2508_07424_amd import mirve
+    build, size0, batch0, prec0, desc = WORKLOADS[args.workload]
+    args.size = args.size or size0
+    args.batch = args.batch or batch0
+    args.precision = args.precision or prec0
     prec = mirve.RVE_PREC_FP64 if args.precision == "fp64" else mirve.RVE_PREC_MIXED
-    wls = _workloads(args.size, args.batch)
+    progress("generating %d %s inputs" % (args.batch, args.workload))
+    wls = build(args.size, args.batch)
     # one batched handle: every launch covers all RVEs of the batch
     progress("setting up %d RVEs" % len(wls))
     rve = mirve.from_workloads(wls, precision=prec)
     dtaus = [w.dtau for w in wls]
     torch.cuda.synchronize()
     progress("set up")
+    shape = rve.rve_autotune(10)
+    progress("autotuned launch shape (x rows, y lines, z columns) = %s" % (shape,))
     if args.roofline_only:
+        shape = rve.rve_autotune(10)
         roof = roofline(rve, torch)
         roof["copy_gbs"] = copy_bandwidth(torch)
         print(json.dumps({"roofline": roof}), flush=True)
@@ -252,9 +298,14 @@ def main():
     roof["copy_gbs"] = copy_bandwidth(torch)
     roof["frac_of_copy"] = round(roof["achieved"] / roof["copy_gbs"], 4)
     tag = "f64" if prec == mirve.RVE_PREC_FP64 else "mixed"
-    roof["traffic"] = stored_traffic("traffic_%s_%dx%d_b%d_%s.txt" % (
-        roof["kernel_symbol"], args.size, args.size, args.batch, tag))
+    roof["traffic"] = stored_traffic("traffic_%s_%s_b%d_%s.txt" % (
+        roof["kernel_symbol"], "x".join([str(args.size)] * len(wls[0].n)), args.batch, tag))
+    # one Green operator: the x passes once each, the axis passes (2D: one;
+    # 3D: y forward, z with the projection, y inverse; the two y passes are
+    # priced as the z pass)
     op_s = sum(v for v in roof["passes_us"].values()) * 1e-6
+    if len(wls[0].n) == 3:
+        op_s += 2e-6 * roof["passes_us"][PASS_NAMES[1]]
     out = {
         "metric": "voxel-iter/s FFT Green-op solve",
         "value": round(value, 1),
@@ -268,13 +319,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if prec == mirve.RVE_PREC_FP64 else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "2D fibre composite %dx%d, vf 0.3, r~U[5,9], E ratio {2,5,10} x "
-                               "Gc ratio {1,2,4} x %d realizations, l=2, 40-voxel notch"
-                               % (args.size, args.size, (args.batch + 8) // 9),
+        "config": {"workload": desc.format(n=args.size, r=(args.batch + 8) // 9, b=args.batch),
                    "batch": args.batch, "precision": args.precision,
                    "rve_steps_per_s": round(args.batch * args.steps / sec, 3),
-                   "greenops_per_rve_step": round(greenops / (args.batch * args.steps) /
-                                                  (args.size * args.size), 1),
+                   "greenops_per_rve_step": round(greenops / (args.batch * args.steps) / rve.N, 1),
+                   "launch_shape": {"x_rows_per_block": shape[0], "y_lines_per_block": shape[1],
+                                    "z_columns_per_tile": shape[2]},
                    "operator_voxel_iter_per_s": round(rve.N * args.batch / op_s, 1)},
         "roofline": roof,
     }

@@ -247,9 +247,21 @@ int rve_dissipation(rve_handle h, double* D, double* Gamma);
  * compulsory HBM bytes of one launch (every input read once, every output
  * written once).  pass: 0 x-forward with the constitutive law, 1 the axis
  * pass carrying the projection, 2 x-inverse (store), 3 x-forward with the CG
- * direction update, 4 x-inverse with the CG update.  Works on scratch
- * buffers; the committed state is not changed. */
+ * direction update, 4 x-inverse with the CG update, 5 the forward y pass of
+ * a 3D operator (2D: as 1).  Works on scratch buffers; the committed state is
+ * not changed. */
 int rve_profile_pass(rve_handle h, int pass, int repeat, double* bytes_per_launch);
+
+/* Autotuner of the launch shapes of the Green operator's passes (rows per
+ * block of the x passes, lines per block of the y pass, y columns per tile
+ * of the 3D z pass): times every feasible shape's CG-mode passes `repeat`
+ * times on the handle's own slots (at least one slot must be set) and keeps
+ * the fastest for the handle.  The choice is cached for the process per
+ * (grid, batch, precision): later handles of the same kind take it without
+ * timing.  shape_out (may be NULL) receives the three values.  Results of
+ * the solver do not depend on the shape beyond the summation order of the
+ * per-block partial sums. */
+int rve_autotune(rve_handle h, int repeat, int* shape_out);
 
 /* Message of the last error of h (or of the calling thread when h is NULL,
  * e.g. after a failed rve_create / rve_query_workspace). */

@@ -23,6 +23,7 @@
 #include <cstdlib>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <tuple>
@@ -239,6 +240,7 @@ struct SolverBase {
     virtual int solve_damage(int slot, double E, double* D, int* it, int commit) = 0;
     virtual int dissipation(int slot, double* D, double* G) = 0;
     virtual int profile_pass(int pass, int repeat, double* bytes_per_launch) = 0;
+    virtual int autotune(int repeat, int* shape_out) = 0;
     std::vector<SlotState> slots;
     int B = 1;
 };
@@ -326,10 +328,13 @@ struct Solver : SolverBase {
         const size_t omid = L.off(sizeof(uint16_t) * g.N * B);
         const size_t omat = L.off(sizeof(MatEntry<T>) * (size_t)g.mstride * B);
         const size_t opart = L.off(sizeof(double) * kMaxVals * kRedBlocks * B);
-        const size_t ocgA = L.off(sizeof(double) * std::max(nbx, 1) * B);
-        const size_t ocgB = L.off(sizeof(double) * std::max(nbx, 1) * B);
-        const size_t oppA = L.off(sizeof(double) * std::max(nbx, 1) * B);
-        const size_t oppB = L.off(sizeof(double) * std::max(nbx, 1) * B);
+        // pass partials: one per block, sized for the smallest rows per block
+        // (2), so that any launch shape the tuner picks fits
+        const long long maxblk = std::max<long long>(nbx, (g.ny * (long long)g.nz + 1) / 2);
+        const size_t ocgA = L.off(sizeof(double) * maxblk * B);
+        const size_t ocgB = L.off(sizeof(double) * maxblk * B);
+        const size_t oppA = L.off(sizeof(double) * maxblk * B);
+        const size_t oppB = L.off(sizeof(double) * maxblk * B);
         const size_t osums = L.off(sizeof(double) * kMaxVals * B);
         const size_t oE = L.off(sizeof(double) * B);
         const size_t ogam = L.off(sizeof(double) * kAndersonMax * B);
@@ -379,10 +384,16 @@ struct Solver : SolverBase {
     // geometry and launch shapes from a configuration; false if unsupported
     static int threads_for(int n) { return std::min(256, ((n + 63) / 64) * 64); }
 
+    // Launch shape: rows per block of the x passes, lines per block of the y
+    // pass, y columns per tile of the z pass (0: the default heuristic).
+    struct Shape {
+        int rb = 0, tly = 0, tlz = 0;
+    };
+
     static bool make_geom(const rve_config& c, Geom& g, AxisPlan& px, AxisPlan& py, AxisPlan& pz,
                           int& RB, int& nbx, int& maxb_x, size_t& lds_x, int& tly, int& maxb_y,
                           size_t& lds_y, int& tlz, int& maxb_z, size_t& lds_z, int& thr_x,
-                          int& thr_y, int& thr_z, std::string& why) {
+                          int& thr_y, int& thr_z, std::string& why, const Shape* force = nullptr) {
         g.dim = c.dim;
         g.s = c.dim == 2 ? 3 : 6;
         g.nx = c.n[0];
@@ -408,9 +419,12 @@ struct Solver : SolverBase {
         const long long rows_total = (long long)g.ny * g.nz * g.B;
         RB = (int)std::max<long long>(2, std::min<long long>(16, rows_total / 1024));
         RB &= ~1;
+        const bool fixed = force && force->rb > 0;
+        if (fixed) RB = force->rb;
+        if (RB < 2 || (RB & 1)) { why = "rows per block must be even"; return false; }
         if (fast_len(g.nx)) {
-            while (RB > 2 && ((size_t)g.s * (RB / 2) * lx > kLdsCap ||
-                              g.s * (RB / 2) * split_max(g.nx) > 256))
+            while (!fixed && RB > 2 && ((size_t)g.s * (RB / 2) * lx > kLdsCap ||
+                                        g.s * (RB / 2) * split_max(g.nx) > 256))
                 RB -= 2;
             if ((size_t)g.s * (RB / 2) * lx <= kLdsCap && g.s * (RB / 2) * split_max(g.nx) <= 256)
                 px.fastN = g.nx;
@@ -418,8 +432,9 @@ struct Solver : SolverBase {
         auto xmb = [&](int rb) {
             return round_maxb(((long long)g.s * (rb / 2) * g.nx / px.min_rad + 255) / 256);
         };
+        if (fixed && fast_len(g.nx) && !px.fastN) { why = "shape exceeds the block budget"; return false; }
         if (!px.fastN)
-            while (RB > 2 && ((size_t)g.s * (RB / 2) * lx > kLdsCap || xmb(RB) < 0)) RB -= 2;
+            while (!fixed && RB > 2 && ((size_t)g.s * (RB / 2) * lx > kLdsCap || xmb(RB) < 0)) RB -= 2;
         lds_x = (size_t)g.s * (RB / 2) * lx;
         maxb_x = px.fastN ? 1 : xmb(RB);
         if (lds_x > kLdsCap || maxb_x < 0) { why = "n_x too large for the LDS budget"; return false; }
@@ -446,20 +461,27 @@ struct Solver : SolverBase {
         };
         // y pass: whole lines; lines per block so that the batch gives >= ~1024 blocks
         const long long ylines = (long long)g.nxh * g.nz * g.B;
-        const int want_y = (int)std::max<long long>(1, std::min<long long>(16, ylines / 1024));
+        const int want_y = force && force->tly > 0
+                               ? force->tly
+                               : (int)std::max<long long>(1, std::min<long long>(16, ylines / 1024));
         if (!pick(py, want_y, tly, maxb_y, lds_y, thr_y)) {
             why = "n_y too large for the LDS budget";
             return false;
         }
+        if (force && force->tly > 0 && tly != force->tly) { why = "y lines exceed the budget"; return false; }
         // z pass: a tile of y columns (up to 128 bytes per row)
         if (g.dim == 3) {
             const long long zcols = (long long)g.nxh * g.ny * g.B;
-            const int want_z = (int)std::max<long long>(
-                1, std::min<long long>(std::min<long long>(g.ny, 128 / ce), zcols / 1024));
+            const int want_z = force && force->tlz > 0
+                                   ? force->tlz
+                                   : (int)std::max<long long>(
+                                         1, std::min<long long>(std::min<long long>(g.ny, 128 / ce),
+                                                                zcols / 1024));
             if (!pick(pz, want_z, tlz, maxb_z, lds_z, thr_z)) {
                 why = "n_z too large for the LDS budget";
                 return false;
             }
+            if (force && force->tlz > 0 && tlz != force->tlz) { why = "z tile exceeds the budget"; return false; }
         }
         return true;
     }
@@ -1624,6 +1646,121 @@ struct Solver : SolverBase {
         return RVE_OK;
     }
 
+    // ---- launch shape -----------------------------------------------------------
+    int set_shape(const Shape& sh) {
+        Geom g2;
+        AxisPlan a = plx, b = ply, d = plz;
+        int rb = RB, nb = nbx, mx = maxb_x, ty = tly, my = maxb_y, tz = tlz, mz = maxb_z;
+        int t1 = thr_x, t2 = thr_y, t3 = thr_z;
+        size_t lx = lds_x, ly = lds_y, lz = lds_z;
+        std::string why;
+        if (!make_geom(cfg, g2, a, b, d, rb, nb, mx, lx, ty, my, ly, tz, mz, lz, t1, t2, t3, why, &sh))
+            return fail(RVE_EINVAL, why);
+        a.tw_off = plx.tw_off;
+        b.tw_off = ply.tw_off;
+        d.tw_off = plz.tw_off;
+        plx = a; ply = b; plz = d;
+        RB = rb; nbx = nb; maxb_x = mx; lds_x = lx;
+        tly = ty; maxb_y = my; lds_y = ly;
+        tlz = tz; maxb_z = mz; lds_z = lz;
+        thr_x = t1; thr_y = t2; thr_z = t3;
+        RB1 = RB;
+        nbx1 = (int)((g.ny * (long long)g.nz + RB1 - 1) / RB1);
+        tly1 = tly;
+        tlz1 = tlz;
+        return RVE_OK;
+    }
+
+    // Autotuner: time the CG-mode passes of every feasible launch shape on the
+    // slots' own data and keep the fastest: rows per block of the x passes
+    // (one value for x-forward and x-inverse, which share their partials),
+    // lines per block of the y pass, y columns per tile of the z pass.  The
+    // choice is cached per (grid, batch, precision) for the process.
+    int autotune(int repeat, int* out) override {
+        bool ready = false;
+        for (int b = 0; b < B; ++b) ready = ready || slots[b].ready;
+        if (!ready) return fail(RVE_ESTATE, "set_microstructure first");
+        repeat = std::max(1, repeat);
+        char key[128];
+        std::snprintf(key, sizeof(key), "%d:%dx%dx%d:B%d:w%d", g.dim, g.nx, g.ny, g.nz, B, (int)sizeof(T));
+        {
+            std::lock_guard<std::mutex> lk(tune_mutex());
+            auto it = tune_cache().find(key);
+            if (it != tune_cache().end()) {
+                CHK(set_shape(it->second));
+                if (out) { out[0] = RB; out[1] = tly; out[2] = tlz; }
+                return RVE_OK;
+            }
+        }
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        auto timed = [&](int pass, double& us) -> int {
+            CHK(profile_pass(pass, 2, nullptr));
+            HIPCHK(hipEventRecord(e0, st));
+            CHK(profile_pass(pass, repeat, nullptr));
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            us = 1e3 * ms / repeat;
+            return RVE_OK;
+        };
+        Shape best;
+        best.rb = RB;
+        best.tly = tly;
+        best.tlz = g.dim == 3 ? tlz : 0;
+        double tb = INFINITY;
+        for (int rb : {2, 4, 8, 16, 32}) {
+            Shape sh = best;
+            sh.rb = rb;
+            if (set_shape(sh) != RVE_OK) continue;
+            double a = 0, c = 0;
+            CHK(timed(3, a));
+            CHK(timed(4, c));
+            if (a + c < tb) { tb = a + c; best.rb = rb; }
+        }
+        CHK(set_shape(best));
+        tb = INFINITY;
+        for (int t : {1, 2, 4, 8, 16}) {
+            Shape sh = best;
+            sh.tly = t;
+            if (set_shape(sh) != RVE_OK) continue;
+            double a = 0;
+            CHK(timed(g.dim == 3 ? 5 : 1, a));
+            if (a < tb) { tb = a; best.tly = t; }
+        }
+        if (g.dim == 3) {
+            CHK(set_shape(best));
+            tb = INFINITY;
+            for (int t : {1, 2, 4, 8, 16}) {
+                Shape sh = best;
+                sh.tlz = t;
+                if (set_shape(sh) != RVE_OK) continue;
+                double a = 0;
+                CHK(timed(1, a));
+                if (a < tb) { tb = a; best.tlz = t; }
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        CHK(set_shape(best));
+        {
+            std::lock_guard<std::mutex> lk(tune_mutex());
+            tune_cache()[key] = best;
+        }
+        if (out) { out[0] = RB; out[1] = tly; out[2] = tlz; }
+        return RVE_OK;
+    }
+    static std::map<std::string, Shape>& tune_cache() {
+        static std::map<std::string, Shape> m;
+        return m;
+    }
+    static std::mutex& tune_mutex() {
+        static std::mutex m;
+        return m;
+    }
+
     // Launch one kind of pass `repeat` times on every ready RVE of the batch
     // (for timing against its algorithmic bytes).  0: x-forward (constitutive),
     // 1: the projection axis pass, 2: x-inverse (store), 3: x-forward with the
@@ -1665,6 +1802,16 @@ struct Solver : SolverBase {
                 case 2: CHK(inv_x(XI_STORE, p, 1.0, cgpB, dmask[0])); break;
                 case 3: CHK(fwd_x(XF_CG, phi_c, nullptr, 0.0, cgpA, nullptr, 1)); break;
                 case 4: CHK(inv_x(XI_CG, nullptr, 1.0, cgpB, nullptr, 1)); break;
+                case 5: {   // the forward y pass of a 3D operator (2D: as pass 1)
+                    AxisArgs<T> y = a;
+                    y.pl = ply;
+                    y.tw = tw + ply.tw_off;
+                    y.contiguous = 1;
+                    y.lines = tly;
+                    y.threads = thr_y;
+                    HIPCHK(launch_axis<T>(y, three ? AX_FWD : AX_FWD_P_INV, maxb_y, grid_y(tly), lds_y, st));
+                    break;
+                }
                 default: return fail(RVE_EINVAL, "unknown pass");
             }
         }
@@ -1678,6 +1825,7 @@ struct Solver : SolverBase {
             case 2: bb = N * sp * S * w + N * S * w; break;
             case 3: bb = N * (3 * S * w + w + 2) + N * sp * S * w; break;
             case 4: bb = N * sp * S * w + N * 5 * S * w; break;
+            case 5: bb = 2.0 * N * sp * S * w; break;
         }
         if (bytes) *bytes = bb;
         return RVE_OK;
@@ -1954,6 +2102,11 @@ int rve_solve_damage(rve_handle h, double E, double* D, int* it, int commit) {
 int rve_dissipation(rve_handle h, double* D, double* G) {
     if (!h) return RVE_EINVAL;
     return h->impl->dissipation(0, D, G);
+}
+
+int rve_autotune(rve_handle h, int repeat, int* shape_out) {
+    if (!h) return RVE_EINVAL;
+    return h->impl->autotune(repeat, shape_out);
 }
 
 int rve_profile_pass(rve_handle h, int pass, int repeat, double* bytes_per_launch) {

@@ -43,8 +43,8 @@ EXPORTS = ["rve_default_config", "rve_query_workspace", "rve_create", "rve_destr
            "rve_get_field", "rve_set_field", "rve_get_field_slot", "rve_set_field_slot",
            "rve_get_scalars", "rve_set_scalars", "rve_get_scalars_slot", "rve_set_scalars_slot",
            "rve_apply_green_op", "rve_apply_green_op_device", "rve_solve_mechanics",
-           "rve_solve_damage", "rve_dissipation", "rve_profile_pass", "rve_last_error",
-           "rve_version"]
+           "rve_solve_damage", "rve_dissipation", "rve_profile_pass", "rve_autotune",
+           "rve_last_error", "rve_version"]
 
 
 class rve_config(C.Structure):
@@ -111,6 +111,7 @@ def _load():
         "rve_solve_damage": (I, [P, D, dp, C.POINTER(C.c_int), I]),
         "rve_dissipation": (I, [P, dp, dp]),
         "rve_profile_pass": (I, [P, I, I, dp]),
+        "rve_autotune": (I, [P, I, C.POINTER(C.c_int)]),
         "rve_last_error": (C.c_char_p, [P]),
         "rve_version": (C.c_char_p, []),
     }
@@ -314,6 +315,13 @@ class Rve:
         self._chk(lib.rve_dissipation(self.h, C.byref(D), C.byref(G)))
         return D.value, G.value
 
+
+    def rve_autotune(self, repeat=20):
+        """Pick the fastest launch shapes for this handle; returns
+        (rows per x block, y lines per block, z columns per tile)."""
+        out = (C.c_int * 3)()
+        self._chk(lib.rve_autotune(self.h, int(repeat), out))
+        return tuple(out)
 
     def rve_profile_pass(self, which, repeat=1):
         b = C.c_double(0.0)

@@ -237,6 +237,31 @@ def laminate_2d(nx=64, ny=32, widths=(0.5, 0.5), Gcs=(1.0, 3.0), Es=(1.0, 1.0), 
                     k=1e-6, meta={"name": "laminate_2d", "edges": edges.tolist()})
 
 
+def _voronoi_ids(X, Y, seeds, L):
+    """Index of the nearest seed (periodic distance) of every voxel centre;
+    ties go to the lower index."""
+    try:
+        from scipy.spatial import cKDTree
+    except ImportError:
+        cKDTree = None
+    if cKDTree is not None and len(seeds) > 8:
+        tree = cKDTree(np.mod(seeds, L), boxsize=L)
+        pts = np.stack([np.mod(X.ravel(), L), np.mod(Y.ravel(), L)], axis=1)
+        d, idx = tree.query(pts, k=2)
+        # resolve exact ties like the brute-force scan (lowest index)
+        tie = d[:, 0] == d[:, 1]
+        best = np.where(tie, np.minimum(idx[:, 0], idx[:, 1]), idx[:, 0])
+        return best.reshape(X.shape).astype(np.uint16)
+    best = np.full(X.shape, np.inf)
+    gid = np.zeros(X.shape, dtype=np.uint16)
+    for g in range(len(seeds)):
+        d2 = _periodic_delta(X, seeds[g, 0], L) ** 2 + _periodic_delta(Y, seeds[g, 1], L) ** 2
+        closer = d2 < best
+        best[closer] = d2[closer]
+        gid[closer] = g
+    return gid
+
+
 def polycrystal_2d(n=512, grains=200, seed=1000, zener=2.0, a_cleave=1.0, ell=2.0,
                    crack_frac=0.1):
     """Periodic Voronoi polycrystal with uniform in-plane orientations.
@@ -250,13 +275,7 @@ def polycrystal_2d(n=512, grains=200, seed=1000, zener=2.0, a_cleave=1.0, ell=2.
     seeds = rng.uniform(0.0, n * h, size=(grains, 2))
     theta_g = rng.uniform(0.0, 2.0 * np.pi, size=grains)
     X, Y = _centres(nn, h)
-    best = np.full(X.shape, np.inf)
-    gid = np.zeros(X.shape, dtype=np.uint16)
-    for g in range(grains):
-        d2 = _periodic_delta(X, seeds[g, 0], n * h) ** 2 + _periodic_delta(Y, seeds[g, 1], n * h) ** 2
-        closer = d2 < best
-        best[closer] = d2[closer]
-        gid[closer] = g
+    gid = _voronoi_ids(X, Y, seeds, n * h)
     C44 = zener / 4.0
     phases = [cubic(1.0, 0.5, C44, 1.0 + a_cleave * math.cos(4.0 * t) ** 2) for t in theta_g]
     theta = theta_g[gid]

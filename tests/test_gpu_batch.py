@@ -48,3 +48,22 @@ def test_idle_slot_and_release():
     batch.rve_release_slot(1)
     info, st = batch.rve_step_dissipation_slots([ws[0].dtau, 1.0, 0.0])
     assert st[0] == 0 and st[1] == mirve.RVE_ESTATE
+
+
+def test_autotune_keeps_results():
+    """The tuner only changes launch shapes: a tuned handle gives the same
+    steps as an untuned one up to the summation order of the partials."""
+    from paper_2508_07424_amd import mirve
+    w = W.composite_2d_small()
+    tight = dict(tol=1e-12, tol_cg=1e-13, tol_pcg=1e-14, tol_al=1e-13)
+    a = mirve.from_workload(w, **tight)
+    b = mirve.from_workload(w, **tight)
+    shape = b.rve_autotune(5)
+    print("tuned shape", shape, flush=True)
+    assert shape[0] >= 2 and shape[0] % 2 == 0 and shape[1] >= 1
+    assert b.rve_autotune(5) == shape            # cached
+    for _ in range(2):
+        ia = a.rve_step_dissipation(w.dtau)
+        ib = b.rve_step_dissipation(w.dtau)
+        for key in ("E", "Sigma", "D", "T"):
+            assert abs(ia[key] - ib[key]) <= 1e-9 * abs(ia[key]), (key, ia[key], ib[key])
