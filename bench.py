@@ -264,7 +264,7 @@ def main():
     wls = build(args.size, args.batch)
     # one batched handle: every launch covers all RVEs of the batch
     progress("setting up %d RVEs" % len(wls))
-    rve = mirve.from_workloads(wls, precision=prec)
+    rve = mirve.from_workloads(wls, precision=prec, stream=torch.cuda.Stream())
     dtaus = [w.dtau for w in wls]
     torch.cuda.synchronize()
     progress("set up")

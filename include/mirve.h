@@ -116,6 +116,9 @@ typedef struct {
     int    batch;          /* RVE slots of this handle (same grid, own microstructure
                               and state), advanced together by every launch; 1-1024  */
     int    damage_precond; /* RVE_PRECOND_* of the damage solve                      */
+    int    graphs;         /* 1 (default): run the Krylov iterations as replays of
+                              captured HIP graphs (chunks of 8 iterations) when the
+                              handle has a stream of its own; 0: launch them       */
 } rve_config;
 
 typedef struct {

@@ -299,6 +299,9 @@ struct Solver : SolverBase {
     std::vector<int> step_greens;    // Green-operator applications per slot in this step
     std::vector<int> stag_fail;      // the slot's last step stopped on the stagger limit
     bool trace = false;              // MIRVE_TRACE set: stagger progress on stderr
+    // captured Krylov chunks: key -> executable graph of kGraphChunk iterations
+    std::map<std::string, hipGraphExec_t> graphs;
+    static constexpr int kGraphChunk = 8;
     static constexpr int kMaxHalvings = 4;
     static constexpr double kGammaMax = 10.0;
     static constexpr int kMaxNewton = 100;
@@ -515,6 +518,7 @@ struct Solver : SolverBase {
     }
 
     ~Solver() override {
+        clear_graphs();
         if (h_cg) (void)hipHostFree(h_cg);
         if (h_pcg) (void)hipHostFree(h_pcg);
         if (h_sums) (void)hipHostFree(h_sums);
@@ -811,16 +815,58 @@ struct Solver : SolverBase {
     // CG iterations of P[C : u] = b after launch_cg_init, with the solution
     // accumulated in xsol; mode XF_CG (the law g C) or XF_CG_T (the split's
     // tangent).  Adds the iterations to iters and greens.
+    void clear_graphs() {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
+    }
+
+    // Run `enqueue(k)` for k in [k0, k0 + n): directly, or (cfg.graphs) as
+    // replays of captured chunks of kGraphChunk iterations (n is rounded up;
+    // iterations past a solve's end leave it unchanged).  A chunk is captured
+    // once per key (the launch arguments of its iterations) and replayed.
+    template <typename F>
+    int run_iterations(const std::string& key, int k0, int n, F enqueue) {
+        if (!cfg.graphs || st == nullptr) {     // no capture on the legacy default stream
+            for (int k = k0; k < k0 + n; ++k) CHK(enqueue(k));
+            return RVE_OK;
+        }
+        for (int c0 = k0; c0 < k0 + n; c0 += kGraphChunk) {
+            const std::string gk = key + "|" + std::to_string(c0);
+            auto it = graphs.find(gk);
+            if (it == graphs.end()) {
+                hipGraph_t gr;
+                HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                int rc = RVE_OK;
+                for (int k = c0; k < c0 + kGraphChunk && rc == RVE_OK; ++k) rc = enqueue(k);
+                hipError_t e = hipStreamEndCapture(st, &gr);
+                CHK(rc);
+                HIPCHK(e);
+                hipGraphExec_t ex;
+                e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                HIPCHK(e);
+                it = graphs.emplace(gk, ex).first;
+            }
+            HIPCHK(hipGraphLaunch(it->second, st));
+        }
+        return RVE_OK;
+    }
+
     int cg_loop(const T* phi, int mode, T* xsol, const std::vector<int>& act,
                 std::vector<int>& iters, std::vector<int>& rcs) {
         int chunk = 8, k = 0;
         std::vector<ChunkPlanner> plan(B);
+        char key[160];
+        std::snprintf(key, sizeof(key), "cg:%d:%p:%p", mode, (const void*)phi, (void*)xsol);
         for (;;) {
-            for (int i = 0; i < chunk; ++i, ++k) {
-                CHK(fwd_x(mode, phi, nullptr, 0.0, cgpA, nullptr, k));
-                CHK(axes(cg, nullptr, k));
-                CHK(inv_x(XI_CG, nullptr, 1.0, cgpB, nullptr, k, xsol));
-            }
+            if (cfg.graphs && st) chunk = (chunk + kGraphChunk - 1) / kGraphChunk * kGraphChunk;
+            CHK(run_iterations(key, k, chunk, [&](int kk) -> int {
+                CHK(fwd_x(mode, phi, nullptr, 0.0, cgpA, nullptr, kk));
+                CHK(axes(cg, nullptr, kk));
+                CHK(inv_x(XI_CG, nullptr, 1.0, cgpB, nullptr, kk, xsol));
+                return RVE_OK;
+            }));
+            k += chunk;
             HIPCHK(hipMemcpyAsync(h_cg, cg, sizeof(CgDev) * B, hipMemcpyDeviceToHost, st));
             CHK(drain());
             bool all = true;
@@ -947,19 +993,25 @@ struct Solver : SolverBase {
             rzs = rrs = (long long)kMaxVals * kRedBlocks;
             rzn = rrn = nred;
         }
-        T* pcur = pp;   // directions alternate between pp and pp2
+        // directions alternate between pp (even iterations) and pp2 (odd)
         int chunk = fft ? 4 : 8, k = 0;
         std::vector<ChunkPlanner> plan(B);
+        char key[200];
+        std::snprintf(key, sizeof(key), "pcg:%d:%.17g:%d:%p:%p", mode, c, fft ? 1 : 0, (const void*)Hc,
+                      (void*)u);
         for (;;) {
-            for (int i = 0; i < chunk; ++i, ++k) {
-                T* pn = pcur == pp ? pp2 : pp;
+            if (cfg.graphs && st) chunk = (chunk + kGraphChunk - 1) / kGraphChunk * kGraphChunk;
+            CHK(run_iterations(key, k, chunk, [&](int kk) -> int {
+                T* pcur = (kk & 1) ? pp2 : pp;
+                T* pn = (kk & 1) ? pp : pp2;
                 HIPCHK(launch_pcg_matvec_dir<T>(g, mat_id, mat, Hc, mode, c, fft ? PRE_FFT : PRE_JACOBI,
                                                 pr, pdinv, pz, pcur, pn, pq, rzp, rzs, rzn, rrp, rrs,
-                                                rrn, partials, nred, pcg, k, st));
-                if (fft) CHK(precond_fft(XF_PCG, k, u, pn));
-                else HIPCHK(launch_pcg_update<T>(g, pcg, u, pr, pn, pq, pdinv, partials, nred, k, st));
-                pcur = pn;
-            }
+                                                rrn, partials, nred, pcg, kk, st));
+                if (fft) CHK(precond_fft(XF_PCG, kk, u, pn));
+                else HIPCHK(launch_pcg_update<T>(g, pcg, u, pr, pn, pq, pdinv, partials, nred, kk, st));
+                return RVE_OK;
+            }));
+            k += chunk;
             HIPCHK(hipMemcpyAsync(h_pcg, pcg, sizeof(PcgDev) * B, hipMemcpyDeviceToHost, st));
             CHK(drain());
             bool all = true;
@@ -1668,6 +1720,7 @@ struct Solver : SolverBase {
         nbx1 = (int)((g.ny * (long long)g.nz + RB1 - 1) / RB1);
         tly1 = tly;
         tlz1 = tlz;
+        clear_graphs();            // captured launches carry the old shape
         return RVE_OK;
     }
 
@@ -1852,6 +1905,7 @@ static int validate(const rve_config* c, std::string& why) {
     if (c->anderson_depth < 0 || c->anderson_depth > kAndersonMax) { why = "anderson_depth in [0, 5]"; return RVE_EINVAL; }
     if (c->max_materials < 1 || c->max_materials > kMaxMat) { why = "max_materials in [1, 65536]"; return RVE_EINVAL; }
     if (c->batch < 1 || c->batch > 1024) { why = "batch in [1, 1024]"; return RVE_EINVAL; }
+    if (c->graphs != 0 && c->graphs != 1) { why = "graphs must be 0 or 1"; return RVE_EINVAL; }
     if (c->damage_precond != RVE_PRECOND_FFT && c->damage_precond != RVE_PRECOND_JACOBI) {
         why = "damage_precond must be RVE_PRECOND_FFT or RVE_PRECOND_JACOBI";
         return RVE_EINVAL;
@@ -1906,6 +1960,7 @@ int rve_default_config(rve_config* c) {
     c->max_materials = 4096;
     c->batch = 1;
     c->damage_precond = RVE_PRECOND_FFT;
+    c->graphs = 1;
     return RVE_OK;
 }
 

@@ -54,7 +54,8 @@ class rve_config(C.Structure):
                 ("tol_cg", C.c_double), ("tol_pcg", C.c_double), ("tol_al", C.c_double),
                 ("max_stagger", C.c_int), ("max_cg", C.c_int), ("max_pcg", C.c_int),
                 ("anderson_depth", C.c_int), ("frac_threshold", C.c_double), ("A_g", C.c_double),
-                ("max_materials", C.c_int), ("batch", C.c_int), ("damage_precond", C.c_int)]
+                ("max_materials", C.c_int), ("batch", C.c_int), ("damage_precond", C.c_int),
+                ("graphs", C.c_int)]
 
 
 class rve_phase(C.Structure):
