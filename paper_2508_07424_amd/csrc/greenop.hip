@@ -139,6 +139,14 @@ __device__ __forceinline__ T precond_symbol(const Geom& g, int kx, int ky, int k
     return T(1) / (T(abar) + T(bbar) * d2);
 }
 
+// Line length of a pass: a compile-time constant for the fixed-size FFTs, so
+// that index arithmetic on it folds into shifts; the runtime plan otherwise.
+template <typename F>
+__device__ __forceinline__ int line_len(const AxisPlan& pl) {
+    if constexpr (F::fast) return F::N;
+    else return pl.N;
+}
+
 // Consecutive workgroups of a launch go to the eight XCDs in turn, and each
 // XCD has its own L2.  Renumbering the x index so that the workgroups one XCD
 // receives cover consecutive row groups lets neighbouring groups, which share
@@ -169,10 +177,11 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
     } else if (a.active && !a.active[b]) {
         return;
     }
-    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int nx = line_len<F>(a.pl), ny = g.ny, nz = g.nz;
     const int nrows = ny * nz;
-    const int RB = a.rows_per_block;
+    const int RB = a.rows_per_block;          // a power of two
     const int npairs = RB / 2;
+    const int lgp = __builtin_ctz(npairs);
     const int grp = xcd_group(blockIdx.x, gridDim.x);
     const int r0 = grp * RB;
     const int LS = lds_line(nx);
@@ -303,12 +312,13 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
 
     // split the packed lines into the half spectra of their two rows and
     // store them transposed: consecutive threads write consecutive y
-    const int nxh = g.nxh;
+    const int nxh = nx / 2 + 1;
     cplx<T>* sp = a.spec + (long long)b * S * g.Nspec;
     for (int e = threadIdx.x; e < S * npairs * nxh; e += blockDim.x) {
-        const int pr = e % npairs;
-        const int k = (e / npairs) % nxh;
-        const int c = e / (npairs * nxh);
+        const int pr = e & (npairs - 1);
+        const int q = e >> lgp;               // q = c * nxh + k
+        const int c = q / nxh;
+        const int k = q - c * nxh;
         const int line = c * npairs + pr;
         const cplx<T> z = buf[line * LS + lp(k)];
         const cplx<T> zm = buf[line * LS + lp(k == 0 ? 0 : nx - k)];
@@ -339,8 +349,9 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
     if (a.cg && a.cg[b].conv <= a.iter) return;
     if (a.pcg && a.pcg[b].conv <= a.iter) return;
     if (a.active && !a.active[b]) return;
-    const int TL = a.lines;
-    const int Na = a.pl.N;
+    const int TL = a.lines;                   // a power of two
+    const int lgt = __builtin_ctz(TL);
+    const int Na = line_len<F>(a.pl);
     const int ny = g.ny, nz = g.nz;
     cplx<T>* sp = a.spec + (long long)b * S * g.Nspec;
     const bool inv_only = MODE == AX_INV;
@@ -351,7 +362,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
         const long long nlines = (long long)g.nxh * nz;
         const long long L0 = (long long)blockIdx.x * TL;
         for (int e = threadIdx.x; e < S * TL * Na; e += blockDim.x) {
-            const int j = e % Na, tl = (e / Na) % TL, c = e / (Na * TL);
+            const int q = e / Na, j = e - q * Na, tl = q & (TL - 1), c = q >> lgt;
             const long long L = L0 + tl;
             cplx<T> v = {T(0), T(0)};
             if (L < nlines) v = sp[(long long)c * g.Nspec + L * ny + j];
@@ -362,7 +373,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
         if constexpr (MODE == AX_FWD_M_INV) {
             const double abar = a.pcg[b].abar, bbar = a.pcg[b].bbar;
             for (int e = threadIdx.x; e < S * TL * Na; e += blockDim.x) {
-                const int j = e % Na, tl = (e / Na) % TL, c = e / (Na * TL);
+                const int q = e / Na, j = e - q * Na, tl = q & (TL - 1), c = q >> lgt;
                 const long long L = L0 + tl;
                 if (L >= nlines) continue;
                 const T m = precond_symbol<T>(g, (int)(L / nz), j, (int)(L % nz), abar, bbar);
@@ -375,7 +386,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
         }
         if constexpr (MODE == AX_FWD_P_INV) {
             for (int e = threadIdx.x; e < TL * Na; e += blockDim.x) {
-                const int j = e % Na, tl = e / Na;
+                const int tl = e / Na, j = e - tl * Na;
                 const long long L = L0 + tl;
                 if (L >= nlines) continue;
                 const int kx = (int)(L / nz), kz = (int)(L % nz);
@@ -393,7 +404,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
             line_fft<T, F>(buf, S * TL, LS, a.pl, a.tw, true);
         }
         for (int e = threadIdx.x; e < S * TL * Na; e += blockDim.x) {
-            const int j = e % Na, tl = (e / Na) % TL, c = e / (Na * TL);
+            const int q = e / Na, j = e - q * Na, tl = q & (TL - 1), c = q >> lgt;
             const long long L = L0 + tl;
             if (L < nlines) sp[(long long)c * g.Nspec + L * ny + j] = buf[(c * TL + tl) * LS + lp(j)];
         }
@@ -406,7 +417,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
         const int W = S * TL;
         const long long base = (long long)kx * nz * ny + y0;
         for (int e = threadIdx.x; e < W * Na; e += blockDim.x) {
-            const int tl = e % TL, c = (e / TL) % S, j = e / W;
+            const int tl = e & (TL - 1), q = e >> lgt, j = q / S, c = q - j * S;
             cplx<T> v = {T(0), T(0)};
             if (y0 + tl < ny) v = sp[(long long)c * g.Nspec + base + (long long)j * ny + tl];
             buf[(c * TL + tl) * LS + lp(j)] = v;
@@ -416,7 +427,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
         if constexpr (MODE == AX_FWD_M_INV) {
             const double abar = a.pcg[b].abar, bbar = a.pcg[b].bbar;
             for (int e = threadIdx.x; e < W * Na; e += blockDim.x) {
-                const int tl = e % TL, c = (e / TL) % S, j = e / W;
+                const int tl = e & (TL - 1), q = e >> lgt, j = q / S, c = q - j * S;
                 if (y0 + tl >= ny) continue;
                 const T m = precond_symbol<T>(g, kx, y0 + tl, j, abar, bbar);
                 cplx<T>& v = buf[(c * TL + tl) * LS + lp(j)];
@@ -428,7 +439,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
         }
         if constexpr (MODE == AX_FWD_P_INV) {
             for (int e = threadIdx.x; e < TL * Na; e += blockDim.x) {
-                const int tl = e % TL, j = e / TL;
+                const int tl = e & (TL - 1), j = e >> lgt;
                 if (y0 + tl >= ny) continue;
                 T n1, n2, n3;
                 freq_dir<T>(g, kx, y0 + tl, j, n1, n2, n3);
@@ -444,7 +455,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
             line_fft<T, F>(buf, W, LS, a.pl, a.tw, true);
         }
         for (int e = threadIdx.x; e < W * Na; e += blockDim.x) {
-            const int tl = e % TL, c = (e / TL) % S, j = e / W;
+            const int tl = e & (TL - 1), q = e >> lgt, j = q / S, c = q - j * S;
             if (y0 + tl < ny)
                 sp[(long long)c * g.Nspec + base + (long long)j * ny + tl] = buf[(c * TL + tl) * LS + lp(j)];
         }
@@ -482,10 +493,11 @@ __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
         }
         alpha = T(a.cg[b].rr_hist[a.iter & 1] / pap[0]);
     }
-    const int nx = g.nx, nxh = g.nxh, ny = g.ny, nz = g.nz;
+    const int nx = line_len<F>(a.pl), nxh = nx / 2 + 1, ny = g.ny, nz = g.nz;
     const int nrows = ny * nz;
-    const int RB = a.rows_per_block;
+    const int RB = a.rows_per_block;          // a power of two
     const int npairs = RB / 2;
+    const int lgp = __builtin_ctz(npairs);
     const int grp = xcd_group(blockIdx.x, gridDim.x);
     const int r0 = grp * RB;
     const int LS = lds_line(nx);
@@ -493,9 +505,10 @@ __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
 
     // gather Z = A + iB from the transposed half spectra of the row pair
     for (int e = threadIdx.x; e < S * npairs * nx; e += blockDim.x) {
-        const int pr = e % npairs;
-        const int k = (e / npairs) % nx;
-        const int c = e / (npairs * nx);
+        const int pr = e & (npairs - 1);
+        const int q = e >> lgp;               // q = c * nx + k
+        const int c = q / nx;
+        const int k = q - c * nx;
         const int rowA = r0 + 2 * pr;
         const bool lo = k < nxh;
         const int kk = lo ? k : nx - k;

@@ -179,6 +179,12 @@ constexpr size_t kLdsCap = 60 * 1024;
 // Number of Krylov iterations to enqueue before the next host check: the
 // observed rate of decrease of the residual predicts how many are still
 // needed, so few launches run past convergence (those exit at once).
+static inline int pow2_floor(int v) {
+    int p = 1;
+    while (p * 2 <= v) p *= 2;
+    return p;
+}
+
 struct ChunkPlanner {
     int it_prev = 0;
     double rr_prev = -1.0;
@@ -420,15 +426,16 @@ struct Solver : SolverBase {
         // the chip (>= ~1024 over the batch), at most 16 rows
         const size_t lx = (size_t)lds_line(g.nx) * ce;
         const long long rows_total = (long long)g.ny * g.nz * g.B;
-        RB = (int)std::max<long long>(2, std::min<long long>(16, rows_total / 1024));
-        RB &= ~1;
+        // rows per block and lines per block are powers of two (the kernels
+        // split their flat indices with shifts)
+        RB = pow2_floor((int)std::max<long long>(2, std::min<long long>(16, rows_total / 1024)));
         const bool fixed = force && force->rb > 0;
         if (fixed) RB = force->rb;
-        if (RB < 2 || (RB & 1)) { why = "rows per block must be even"; return false; }
+        if (RB < 2 || (RB & (RB - 1))) { why = "rows per block must be a power of two >= 2"; return false; }
         if (fast_len(g.nx)) {
             while (!fixed && RB > 2 && ((size_t)g.s * (RB / 2) * lx > kLdsCap ||
                                         g.s * (RB / 2) * split_max(g.nx) > 256))
-                RB -= 2;
+                RB /= 2;
             if ((size_t)g.s * (RB / 2) * lx <= kLdsCap && g.s * (RB / 2) * split_max(g.nx) <= 256)
                 px.fastN = g.nx;
         }
@@ -437,7 +444,7 @@ struct Solver : SolverBase {
         };
         if (fixed && fast_len(g.nx) && !px.fastN) { why = "shape exceeds the block budget"; return false; }
         if (!px.fastN)
-            while (!fixed && RB > 2 && ((size_t)g.s * (RB / 2) * lx > kLdsCap || xmb(RB) < 0)) RB -= 2;
+            while (!fixed && RB > 2 && ((size_t)g.s * (RB / 2) * lx > kLdsCap || xmb(RB) < 0)) RB /= 2;
         lds_x = (size_t)g.s * (RB / 2) * lx;
         maxb_x = px.fastN ? 1 : xmb(RB);
         if (lds_x > kLdsCap || maxb_x < 0) { why = "n_x too large for the LDS budget"; return false; }
@@ -447,7 +454,7 @@ struct Solver : SolverBase {
         // y pass: whole contiguous lines, about 1024 elements per component per block
         auto pick = [&](AxisPlan& pl, int want, int& tl, int& mb, size_t& lds, int& thr) -> bool {
             const bool fast = fast_len(pl.N);
-            for (int t = std::max(1, want); t >= 1; --t) {
+            for (int t = pow2_floor(std::max(1, want)); t >= 1; t /= 2) {
                 const size_t l = (size_t)g.s * t * lds_line(pl.N) * ce;
                 if (fast) {
                     if (l <= kLdsCap && g.s * t * split_max(pl.N) <= 256) {
@@ -471,7 +478,7 @@ struct Solver : SolverBase {
             why = "n_y too large for the LDS budget";
             return false;
         }
-        if (force && force->tly > 0 && tly != force->tly) { why = "y lines exceed the budget"; return false; }
+        if (force && force->tly > 0 && tly != force->tly) { why = "y lines: a feasible power of two"; return false; }
         // z pass: a tile of y columns (up to 128 bytes per row)
         if (g.dim == 3) {
             const long long zcols = (long long)g.nxh * g.ny * g.B;
@@ -484,7 +491,7 @@ struct Solver : SolverBase {
                 why = "n_z too large for the LDS budget";
                 return false;
             }
-            if (force && force->tlz > 0 && tlz != force->tlz) { why = "z tile exceeds the budget"; return false; }
+            if (force && force->tlz > 0 && tlz != force->tlz) { why = "z tile: a feasible power of two"; return false; }
         }
         return true;
     }
