@@ -147,6 +147,39 @@ __device__ __forceinline__ int line_len(const AxisPlan& pl) {
     else return pl.N;
 }
 
+// Global loads each thread keeps in flight in the gather loops of the passes.
+constexpr int kLd = 4;
+
+// Keeps the scheduler from sinking the loads above it to their uses below:
+// the loads of a round are all in flight before the first use waits.
+__device__ __forceinline__ void loads_issued() { __builtin_amdgcn_sched_barrier(0); }
+
+// The fixed-size FFTs read their twiddles from an LDS copy at the start of
+// the dynamic LDS (global twiddle loads inside the butterflies would each
+// wait on memory); the runtime plans read them from global memory.
+template <typename F>
+__device__ __forceinline__ constexpr int tw_lds_len() { return F::fast ? F::N : 0; }
+
+template <typename T, typename F>
+__device__ __forceinline__ void stage_twiddles(cplx<T>* twl, const cplx<T>* tw) {
+    if constexpr (F::fast) {
+        for (int i0 = threadIdx.x; i0 < F::N; i0 += kLd * blockDim.x) {
+            cplx<T> t[kLd];
+#pragma unroll
+            for (int u = 0; u < kLd; ++u) {
+                const int i = i0 + u * blockDim.x;
+                t[u] = tw[i < F::N ? i : 0];
+            }
+            loads_issued();
+#pragma unroll
+            for (int u = 0; u < kLd; ++u) {
+                const int i = i0 + u * blockDim.x;
+                if (i < F::N) twl[i] = t[u];
+            }
+        }
+    }
+}
+
 // Consecutive workgroups of a launch go to the eight XCDs in turn, and each
 // XCD has its own L2.  Renumbering the x index so that the workgroups one XCD
 // receives cover consecutive row groups lets neighbouring groups, which share
@@ -164,14 +197,19 @@ __device__ __forceinline__ int xcd_group(int bx, int n) {
 template <typename T, int S, int MODE, typename F>
 __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
     extern __shared__ unsigned char smem_raw[];
-    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* const twl = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* buf = twl + tw_lds_len<F>();
+    const cplx<T>* const twp = F::fast ? twl : a.tw;
     const Geom& g = a.g;
     const int b = blockIdx.y;
     const int k = a.iter;
     constexpr bool PCG = MODE == XF_PCG || MODE == XF_PCG0;
     constexpr bool CGM = MODE == XF_CG || MODE == XF_CG_T;
     if (CGM) {
-        if (a.cg[b].conv <= k) return;
+        // a solve that stopped in an earlier launch; conv == k (k > 0) is
+        // this launch's own stop, whose blocks still apply the last x update
+        const int cv = a.cg[b].conv;
+        if (k == 0 ? cv <= 0 : cv < k) return;
     } else if (PCG) {
         if (a.pcg[b].conv <= k) return;
     } else if (a.active && !a.active[b]) {
@@ -192,24 +230,29 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
     const uint16_t* mid = a.mat_id + so;
     const T* phi = a.phi + so;
 
-    // CG: beta = rr_k / rr_{k-1} and the stopping test, from the r.r
-    // partials of the previous x-inverse pass.  PCG: alpha = rz_k / p.q.
-    T beta = T(0), alpha = T(0);
-    bool first = false;
+    // CG: the update x += alpha_{k-1} p_{k-1} of the previous iteration
+    // (alpha from the p.Ap partials of the previous x-forward pass, the same
+    // bits the x-inverse pass used for r), then beta = rr_k / rr_{k-1} and the
+    // stopping test from the r.r partials of the previous x-inverse pass.
+    // PCG: alpha = rz_k / p.q.
+    T beta = T(0), alpha = T(0), alpha_x = T(0);
+    bool first = false, stop_now = false;
     if (CGM) {
         const CgDev& cg = a.cg[b];
         if (cg.max_it < 0) {
-            beta = T(0.5);                       // timing run
+            beta = T(0.5);                       // timing run: alpha_x = 0
         } else if (k == 0) {
             first = true;
         } else {
-            double rr[1];
+            double rr[1], pap[1];
             block_sum_all<1>(a.rr_part + (long long)b * a.nblocks, 0, a.nblocks, rr);
+            block_sum_all<1>(a.pap_prev + (long long)b * a.nblocks, 0, a.nblocks, pap);
+            const double prev = cg.rr_hist[(k - 1) & 1];
+            alpha_x = T(prev / pap[0]);
             int stop = 0;
             if (!isfinite(rr[0])) stop = 2;
             else if (rr[0] <= cg.tol2 * cg.bn2) stop = 1;
             else if (k >= cg.max_it) stop = 3;
-            const double prev = cg.rr_hist[(k - 1) & 1];
             if (threadIdx.x == 0) {
                 CgDev* w = const_cast<CgDev*>(a.cg) + b;
                 w->rr_hist[k & 1] = rr[0];
@@ -219,7 +262,7 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
                     w->conv = k;
                 }
             }
-            if (stop) return;
+            stop_now = stop != 0;
             beta = T(rr[0] / prev);
         }
     } else if (MODE == XF_PCG) {
@@ -234,81 +277,159 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
         }
         alpha = T(a.pcg[b].rz_hist[k & 1] / pq[0]);
     }
-    double part = 0.0;
-    for (int v = threadIdx.x; v < RB * nx; v += blockDim.x) {
-        const int rl = v / nx, x = v - rl * nx;
-        const int row = r0 + rl;
-        T sig[S];
-        if (row < nrows && PCG) {
-            // damage PCG: x += alpha p, r -= alpha q; transform sc * r
-            const long long o = so + (long long)row * nx + x;
-            T rv = a.r[o];
-            if (MODE == XF_PCG) {
-                a.x[o] += alpha * a.pd[o];
-                rv -= alpha * a.q[o];
-                a.r[o] = rv;
-            }
-            part += double(rv) * double(rv);
-            sig[0] = a.sc[o] * rv;
-        } else if (row < nrows) {
-            const long long idx = (long long)row * nx + x;
-            const MatEntry<T>& m = mat[mid[idx]];
-            const T gg = degr(phi[idx], T(g.k_res));
-            T e[S];
-            if (CGM) {
+    if constexpr (CGM) {
+        if (stop_now) {      // the solve ends here: only the last x update
+            for (int v = threadIdx.x; v < RB * nx; v += blockDim.x) {
+                const int row = r0 + v / nx;
+                if (row >= nrows) continue;
+                const long long idx = (long long)row * nx + (v - (v / nx) * nx);
 #pragma unroll
                 for (int c = 0; c < S; ++c) {
                     const long long o = fo + c * N + idx;
-                    const T rv = a.r[o];
-                    const T pv = first ? rv : rv + beta * a.p[o];
-                    a.p[o] = pv;
-                    e[c] = pv;
+                    a.x[o] += alpha_x * a.p[o];
+                }
+            }
+            return;
+        }
+    }
+    // U voxels per thread and round, in three phases: (1) every global load
+    // of the round, unconditional at clamped addresses so that none waits
+    // for another; (2) the Krylov updates and their stores; (3) the
+    // constitutive law, whose material-table loads then meet no global store
+    // (a store may alias a load as far as the compiler knows) and can all be
+    // issued together, and the LDS tile.
+    constexpr int U = S == 6 ? 2 : 4;
+    const int tot = RB * nx;
+    stage_twiddles<T, F>(twl, a.tw);     // ordered by the barrier before the FFT
+    double part = 0.0;
+    for (int v0 = threadIdx.x; v0 < tot; v0 += U * blockDim.x) {
+        T in0[U][S], in1[U][S], in2[U][S], in3[U], in4[U], ph[U];
+        int mv[U];
+        long long ix[U];
+        bool ok[U];
+        // ---- (1) loads
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int v = v0 + u * blockDim.x;
+            const int rl = v / nx, x = v - rl * nx;
+            const int row = r0 + rl;
+            ok[u] = v < tot && row < nrows;
+            const long long idx = (long long)(ok[u] ? row : 0) * nx + x;
+            ix[u] = idx;
+            if constexpr (PCG) {
+                const long long o = so + idx;
+                in0[u][0] = a.r[o];
+                in4[u] = a.sc[o];
+                if constexpr (MODE == XF_PCG) {
+                    in1[u][0] = a.x[o];
+                    in2[u][0] = a.pd[o];
+                    in3[u] = a.q[o];
+                }
+            } else {
+                mv[u] = mid[idx];
+                ph[u] = phi[idx];
+#pragma unroll
+                for (int c = 0; c < S; ++c) {
+                    const long long o = fo + c * N + idx;
+                    if constexpr (CGM) {
+                        in0[u][c] = a.r[o];
+                        if (!first) {
+                            in1[u][c] = a.p[o];
+                            in2[u][c] = a.x[o];
+                        }
+                    } else {
+                        in0[u][c] = a.eps ? a.eps[o] : T(0);
+                    }
+                }
+                if constexpr (MODE == XF_CG_T) in3[u] = T(a.tmask[so + idx]);
+            }
+        }
+        loads_issued();
+        // ---- (2) Krylov updates; in0 becomes the strain the law acts on
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (!ok[u]) continue;
+            const long long idx = ix[u];
+            if constexpr (PCG) {
+                // damage PCG: x += alpha p, r -= alpha q; transform sc * r
+                if constexpr (MODE == XF_PCG) {
+                    const long long o = so + idx;
+                    a.x[o] = in1[u][0] + alpha * in2[u][0];
+                    in0[u][0] -= alpha * in3[u];
+                    a.r[o] = in0[u][0];
+                }
+            } else if constexpr (CGM) {
+#pragma unroll
+                for (int c = 0; c < S; ++c) {
+                    const long long o = fo + c * N + idx;
+                    if (!first) {
+                        a.x[o] = in2[u][c] + alpha_x * in1[u][c];
+                        in0[u][c] = in0[u][c] + beta * in1[u][c];
+                    }
+                    a.p[o] = in0[u][c];
                 }
             } else {
 #pragma unroll
-                for (int c = 0; c < S; ++c)
-                    e[c] = (a.eps ? a.eps[fo + c * N + idx] : T(0)) + a.fcoef * a.f[c];
-            }
-            T o[S];
-            mat_apply<T, S>(m, e, o);
-#pragma unroll
-            for (int c = 0; c < S; ++c) sig[c] = gg * o[c];
-            if constexpr (MODE == XF_SPLIT || MODE == XF_CG_T) {
-                // sigma = g (C:e - K tr e I) + w K tr e I with w = g where the
-                // (Newton-point) trace is tensile, 1 where it is not: the split
-                // law itself for XF_SPLIT, its tangent for XF_CG_T
-                constexpr int NI = S == 3 ? 2 : 3;
-                T tr = T(0);
-#pragma unroll
-                for (int c = 0; c < NI; ++c) tr += e[c];
-                bool ten;
+                for (int c = 0; c < S; ++c) in0[u][c] = in0[u][c] + a.fcoef * a.f[c];
                 if constexpr (MODE == XF_SPLIT) {
-                    ten = tr > T(0);
-                    a.tmask[so + idx] = ten ? 1 : 0;
-                } else {
-                    ten = a.tmask[so + idx] != 0;
+                    constexpr int NI = S == 3 ? 2 : 3;
+                    T tr = T(0);
+#pragma unroll
+                    for (int c = 0; c < NI; ++c) tr += in0[u][c];
+                    in3[u] = tr > T(0) ? T(1) : T(0);
+                    a.tmask[so + idx] = tr > T(0) ? 1 : 0;
                 }
-                const T add = ((ten ? gg : T(1)) - gg) * m.K * tr;
-#pragma unroll
-                for (int c = 0; c < NI; ++c) sig[c] += add;
             }
-            if constexpr (CGM) {
-#pragma unroll
-                for (int c = 0; c < S; ++c) part += double(e[c]) * double(sig[c]);
-            }
-        } else {
-#pragma unroll
-            for (int c = 0; c < S; ++c) sig[c] = T(0);
         }
+        // ---- (3) constitutive law and the LDS tile
 #pragma unroll
-        for (int c = 0; c < S; ++c) {
-            cplx<T>& dst = buf[(c * npairs + (rl >> 1)) * LS + lp(x)];
-            if (rl & 1) dst.y = sig[c];
-            else dst.x = sig[c];
+        for (int u = 0; u < U; ++u) {
+            const int v = v0 + u * blockDim.x;
+            if (v >= tot) break;
+            const int rl = v / nx, x = v - rl * nx;
+            T sig[S];
+            if (ok[u] && PCG) {
+                part += double(in0[u][0]) * double(in0[u][0]);
+                sig[0] = in4[u] * in0[u][0];
+            } else if (ok[u]) {
+                const MatEntry<T>& m = mat[mv[u]];
+                const T gg = degr(ph[u], T(g.k_res));
+                const T (&e)[S] = in0[u];
+                T o[S];
+                mat_apply<T, S>(m, e, o);
+#pragma unroll
+                for (int c = 0; c < S; ++c) sig[c] = gg * o[c];
+                if constexpr (MODE == XF_SPLIT || MODE == XF_CG_T) {
+                    // sigma = g (C:e - K tr e I) + w K tr e I with w = g where
+                    // the (Newton-point) trace is tensile, 1 where it is not:
+                    // the split law itself for XF_SPLIT, its tangent for XF_CG_T
+                    constexpr int NI = S == 3 ? 2 : 3;
+                    T tr = T(0);
+#pragma unroll
+                    for (int c = 0; c < NI; ++c) tr += e[c];
+                    const bool ten = in3[u] != T(0);
+                    const T add = ((ten ? gg : T(1)) - gg) * m.K * tr;
+#pragma unroll
+                    for (int c = 0; c < NI; ++c) sig[c] += add;
+                }
+                if constexpr (CGM) {
+#pragma unroll
+                    for (int c = 0; c < S; ++c) part += double(e[c]) * double(sig[c]);
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < S; ++c) sig[c] = T(0);
+            }
+#pragma unroll
+            for (int c = 0; c < S; ++c) {
+                cplx<T>& dst = buf[(c * npairs + (rl >> 1)) * LS + lp(x)];
+                if (rl & 1) dst.y = sig[c];
+                else dst.x = sig[c];
+            }
         }
     }
     __syncthreads();
-    line_fft<T, F>(buf, S * npairs, LS, a.pl, a.tw, false);
+    line_fft<T, F>(buf, S * npairs, LS, a.pl, twp, false);
 
     // split the packed lines into the half spectra of their two rows and
     // store them transposed: consecutive threads write consecutive y
@@ -343,7 +464,9 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
 template <typename T, int S, int MODE, typename F>
 __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
     extern __shared__ unsigned char smem_raw[];
-    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* const twl = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* buf = twl + tw_lds_len<F>();
+    const cplx<T>* const twp = F::fast ? twl : a.tw;
     const Geom& g = a.g;
     const int b = blockIdx.z;
     if (a.cg && a.cg[b].conv <= a.iter) return;
@@ -355,21 +478,37 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
     const int ny = g.ny, nz = g.nz;
     cplx<T>* sp = a.spec + (long long)b * S * g.Nspec;
     const bool inv_only = MODE == AX_INV;
+    stage_twiddles<T, F>(twl, a.tw);     // ordered by the barrier before the FFT
 
     const int LS = lds_line(Na);
     if (a.contiguous) {
         // lines L = kx * nz + z, element y; LDS line (c, tl)
         const long long nlines = (long long)g.nxh * nz;
         const long long L0 = (long long)blockIdx.x * TL;
-        for (int e = threadIdx.x; e < S * TL * Na; e += blockDim.x) {
-            const int q = e / Na, j = e - q * Na, tl = q & (TL - 1), c = q >> lgt;
-            const long long L = L0 + tl;
-            cplx<T> v = {T(0), T(0)};
-            if (L < nlines) v = sp[(long long)c * g.Nspec + L * ny + j];
-            buf[(c * TL + tl) * LS + lp(j)] = v;
+        const int tot = S * TL * Na;
+        // kLd loads per thread in flight before their LDS writes
+        for (int e0 = threadIdx.x; e0 < tot; e0 += kLd * blockDim.x) {
+            cplx<T> t[kLd];
+            bool in[kLd];
+#pragma unroll
+            for (int u = 0; u < kLd; ++u) {     // unconditional loads at clamped addresses
+                const int e = e0 + u * blockDim.x;
+                const int q = e / Na, j = e - q * Na, tl = q & (TL - 1), c = q >> lgt;
+                const long long L = L0 + tl;
+                in[u] = e < tot && L < nlines;
+                t[u] = sp[in[u] ? (long long)c * g.Nspec + L * ny + j : 0];
+            }
+            loads_issued();
+#pragma unroll
+            for (int u = 0; u < kLd; ++u) {
+                const int e = e0 + u * blockDim.x;
+                const int q = e / Na, j = e - q * Na, tl = q & (TL - 1), c = q >> lgt;
+                if (e < tot)
+                    buf[(c * TL + tl) * LS + lp(j)] = {in[u] ? t[u].x : T(0), in[u] ? t[u].y : T(0)};
+            }
         }
         __syncthreads();
-        line_fft<T, F>(buf, S * TL, LS, a.pl, a.tw, inv_only);
+        line_fft<T, F>(buf, S * TL, LS, a.pl, twp, inv_only);
         if constexpr (MODE == AX_FWD_M_INV) {
             const double abar = a.pcg[b].abar, bbar = a.pcg[b].bbar;
             for (int e = threadIdx.x; e < S * TL * Na; e += blockDim.x) {
@@ -382,7 +521,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
                 v.y *= m;
             }
             __syncthreads();
-            line_fft<T, F>(buf, S * TL, LS, a.pl, a.tw, true);
+            line_fft<T, F>(buf, S * TL, LS, a.pl, twp, true);
         }
         if constexpr (MODE == AX_FWD_P_INV) {
             for (int e = threadIdx.x; e < TL * Na; e += blockDim.x) {
@@ -401,7 +540,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
                 for (int c = 0; c < S; ++c) buf[(c * TL + tl) * LS + lp(j)] = v[c];
             }
             __syncthreads();
-            line_fft<T, F>(buf, S * TL, LS, a.pl, a.tw, true);
+            line_fft<T, F>(buf, S * TL, LS, a.pl, twp, true);
         }
         for (int e = threadIdx.x; e < S * TL * Na; e += blockDim.x) {
             const int q = e / Na, j = e - q * Na, tl = q & (TL - 1), c = q >> lgt;
@@ -416,14 +555,28 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
         const int y0 = (tile % nyt) * TL;
         const int W = S * TL;
         const long long base = (long long)kx * nz * ny + y0;
-        for (int e = threadIdx.x; e < W * Na; e += blockDim.x) {
-            const int tl = e & (TL - 1), q = e >> lgt, j = q / S, c = q - j * S;
-            cplx<T> v = {T(0), T(0)};
-            if (y0 + tl < ny) v = sp[(long long)c * g.Nspec + base + (long long)j * ny + tl];
-            buf[(c * TL + tl) * LS + lp(j)] = v;
+        const int tot = W * Na;
+        for (int e0 = threadIdx.x; e0 < tot; e0 += kLd * blockDim.x) {
+            cplx<T> t[kLd];
+            bool in[kLd];
+#pragma unroll
+            for (int u = 0; u < kLd; ++u) {     // unconditional loads at clamped addresses
+                const int e = e0 + u * blockDim.x;
+                const int tl = e & (TL - 1), q = e >> lgt, j = q / S, c = q - j * S;
+                in[u] = e < tot && y0 + tl < ny;
+                t[u] = sp[in[u] ? (long long)c * g.Nspec + base + (long long)j * ny + tl : 0];
+            }
+            loads_issued();
+#pragma unroll
+            for (int u = 0; u < kLd; ++u) {
+                const int e = e0 + u * blockDim.x;
+                const int tl = e & (TL - 1), q = e >> lgt, j = q / S, c = q - j * S;
+                if (e < tot)
+                    buf[(c * TL + tl) * LS + lp(j)] = {in[u] ? t[u].x : T(0), in[u] ? t[u].y : T(0)};
+            }
         }
         __syncthreads();
-        line_fft<T, F>(buf, W, LS, a.pl, a.tw, inv_only);
+        line_fft<T, F>(buf, W, LS, a.pl, twp, inv_only);
         if constexpr (MODE == AX_FWD_M_INV) {
             const double abar = a.pcg[b].abar, bbar = a.pcg[b].bbar;
             for (int e = threadIdx.x; e < W * Na; e += blockDim.x) {
@@ -435,7 +588,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
                 v.y *= m;
             }
             __syncthreads();
-            line_fft<T, F>(buf, W, LS, a.pl, a.tw, true);
+            line_fft<T, F>(buf, W, LS, a.pl, twp, true);
         }
         if constexpr (MODE == AX_FWD_P_INV) {
             for (int e = threadIdx.x; e < TL * Na; e += blockDim.x) {
@@ -452,7 +605,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
                 for (int c = 0; c < S; ++c) buf[(c * TL + tl) * LS + lp(j)] = v[c];
             }
             __syncthreads();
-            line_fft<T, F>(buf, W, LS, a.pl, a.tw, true);
+            line_fft<T, F>(buf, W, LS, a.pl, twp, true);
         }
         for (int e = threadIdx.x; e < W * Na; e += blockDim.x) {
             const int tl = e & (TL - 1), q = e >> lgt, j = q / S, c = q - j * S;
@@ -469,7 +622,9 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
 template <typename T, int S, int MODE, typename F>
 __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
     extern __shared__ unsigned char smem_raw[];
-    cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* const twl = reinterpret_cast<cplx<T>*>(smem_raw);
+    cplx<T>* buf = twl + tw_lds_len<F>();
+    const cplx<T>* const twp = F::fast ? twl : a.tw;
     const Geom& g = a.g;
     const int b = blockIdx.y;
     if (MODE == XI_CG) {
@@ -503,50 +658,94 @@ __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
     const int LS = lds_line(nx);
     const cplx<T>* sp = a.spec + (long long)b * S * g.Nspec;
 
-    // gather Z = A + iB from the transposed half spectra of the row pair
-    for (int e = threadIdx.x; e < S * npairs * nx; e += blockDim.x) {
-        const int pr = e & (npairs - 1);
-        const int q = e >> lgp;               // q = c * nx + k
-        const int c = q / nx;
-        const int k = q - c * nx;
-        const int rowA = r0 + 2 * pr;
-        const bool lo = k < nxh;
-        const int kk = lo ? k : nx - k;
-        const cplx<T>* spc = sp + (long long)c * g.Nspec + (long long)kk * nz * ny;
-        cplx<T> A = {T(0), T(0)}, B = {T(0), T(0)};
-        if (rowA < nrows) A = spc[rowA];
-        if (rowA + 1 < nrows) B = spc[rowA + 1];
-        if (!lo) { A.y = -A.y; B.y = -B.y; }
-        buf[(c * npairs + pr) * LS + lp(k)] = {A.x - B.y, A.y + B.x};
+    stage_twiddles<T, F>(twl, a.tw);     // ordered by the barrier before the FFT
+    // gather Z = A + iB from the transposed half spectra of the row pair,
+    // kLd elements per thread in flight before their LDS writes
+    const int gtot = S * npairs * nx;
+    for (int e0 = threadIdx.x; e0 < gtot; e0 += kLd * blockDim.x) {
+        cplx<T> A[kLd], B[kLd];
+        bool ina[kLd], inb[kLd];
+#pragma unroll
+        for (int u = 0; u < kLd; ++u) {     // unconditional loads at clamped addresses
+            const int e = e0 + u * blockDim.x;
+            const int pr = e & (npairs - 1);
+            const int q = e >> lgp;               // q = c * nx + k
+            const int c = q / nx;
+            const int k = q - c * nx;
+            const int rowA = r0 + 2 * pr;
+            const int kk = k < nxh ? k : nx - k;
+            const long long o = (long long)c * g.Nspec + (long long)kk * nz * ny + rowA;
+            ina[u] = e < gtot && rowA < nrows;
+            inb[u] = e < gtot && rowA + 1 < nrows;
+            A[u] = sp[ina[u] ? o : 0];
+            B[u] = sp[inb[u] ? o + 1 : 0];
+        }
+        loads_issued();
+#pragma unroll
+        for (int u = 0; u < kLd; ++u) {
+            const int e = e0 + u * blockDim.x;
+            if (e >= gtot) break;
+            const int pr = e & (npairs - 1);
+            const int q = e >> lgp;
+            const int c = q / nx;
+            const int k = q - c * nx;
+            const T ax = ina[u] ? A[u].x : T(0), bx = inb[u] ? B[u].x : T(0);
+            T ay = ina[u] ? A[u].y : T(0), by = inb[u] ? B[u].y : T(0);
+            if (k >= nxh) { ay = -ay; by = -by; }
+            buf[(c * npairs + pr) * LS + lp(k)] = {ax - by, ay + bx};
+        }
     }
     __syncthreads();
-    line_fft<T, F>(buf, S * npairs, LS, a.pl, a.tw, true);
+    line_fft<T, F>(buf, S * npairs, LS, a.pl, twp, true);
 
     const T scale = T(g.inv_N) * a.scale;
     const long long fo = (long long)b * S * g.N;
+    // loads of U voxels per thread ahead of their stores, as in k_xfwd
+    constexpr int U = S == 6 ? 2 : 4;
+    const int tot = RB * nx;
     double part = 0.0;
-    for (int v = threadIdx.x; v < RB * nx; v += blockDim.x) {
-        const int rl = v / nx, x = v - rl * nx;
-        const int row = r0 + rl;
-        if (row >= nrows) continue;
-        const long long idx = (long long)row * nx + x;
+    for (int v0 = threadIdx.x; v0 < tot; v0 += U * blockDim.x) {
+        T l0[U][S], l1[U][S];
+        if constexpr (MODE != XI_STORE) {
 #pragma unroll
-        for (int c = 0; c < S; ++c) {
-            const cplx<T> z = buf[(c * npairs + (rl >> 1)) * LS + lp(x)];
-            const T q = ((rl & 1) ? z.y : z.x) * scale;
-            const long long o = fo + c * g.N + idx;
-            if (MODE == XI_STORE) {
-                if (a.out) a.out[o] = q;
-                part += double(q) * double(q);
-            } else if (MODE == XI_PCG) {   // z = sc F^-1[...]; r.z
-                const T z = a.sc[o] * q;
-                a.out[o] = z;
-                part += double(a.r[o]) * double(z);
-            } else {  // XI_CG
-                a.x[o] += alpha * a.p[o];
-                const T rn = a.r[o] - alpha * q;
-                a.r[o] = rn;
-                part += double(rn) * double(rn);
+            for (int u = 0; u < U; ++u) {       // unconditional, clamped addresses
+                const int v = v0 + u * blockDim.x;
+                const int rl = v / nx, x = v - rl * nx;
+                const int row = r0 + rl;
+                const long long idx = (long long)(v < tot && row < nrows ? row : 0) * nx + x;
+#pragma unroll
+                for (int c = 0; c < S; ++c) {
+                    const long long o = fo + c * g.N + idx;
+                    l0[u][c] = a.r[o];
+                    if constexpr (MODE == XI_PCG) l1[u][c] = a.sc[o];
+                }
+            }
+            loads_issued();
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int v = v0 + u * blockDim.x;
+            const int rl = v / nx, x = v - rl * nx;
+            const int row = r0 + rl;
+            if (v >= tot || row >= nrows) continue;
+            const long long idx = (long long)row * nx + x;
+#pragma unroll
+            for (int c = 0; c < S; ++c) {
+                const cplx<T> z = buf[(c * npairs + (rl >> 1)) * LS + lp(x)];
+                const T q = ((rl & 1) ? z.y : z.x) * scale;
+                const long long o = fo + c * g.N + idx;
+                if constexpr (MODE == XI_STORE) {
+                    if (a.out) a.out[o] = q;
+                    part += double(q) * double(q);
+                } else if constexpr (MODE == XI_PCG) {   // z = sc F^-1[...]; r.z
+                    const T zz = l1[u][c] * q;
+                    a.out[o] = zz;
+                    part += double(l0[u][c]) * double(zz);
+                } else {  // XI_CG (x takes alpha p in the next x-forward pass)
+                    const T rn = l0[u][c] - alpha * q;
+                    a.r[o] = rn;
+                    part += double(rn) * double(rn);
+                }
             }
         }
     }

@@ -74,7 +74,7 @@ struct XfwdArgs {
     T f[6];
     T* r;                // XF_CG: residual; XF_PCG*: damage residual (updated in place)
     T* p;                // XF_CG: direction (updated in place)
-    T* x;                // XF_PCG: damage iterate (updated in place)
+    T* x;                // XF_PCG: damage iterate; XF_CG: solution (both updated in place)
     const T* pd;         // XF_PCG: damage direction
     const T* q;          // XF_PCG: A pd
     const T* sc;         // XF_PCG*: diagonal scaling of the preconditioner
@@ -82,6 +82,7 @@ struct XfwdArgs {
     PcgDev* pcg;         // XF_PCG*
     uint8_t* tmask;      // XF_SPLIT: written; XF_CG_T: read (1 where tr eps > 0)
     const double* rr_part;   // XF_CG: r.r partials of the previous x-inverse ([B][nblocks])
+    const double* pap_prev;  // XF_CG: p.Ap partials of the previous x-forward ([B][nblocks])
     const double* pq_part;   // XF_PCG: p.q partials, RVE b at pq_part + b * pq_stride
     long long pq_stride;
     int pq_n;
@@ -117,8 +118,6 @@ struct XinvArgs {
     const cplx<T>* spec;
     T scale;             // multiplies the (normalised) inverse
     T* out;              // XI_STORE (may be null: norm only); XI_PCG: z
-    T* x;                // XI_CG
-    const T* p;          // XI_CG
     T* r;                // XI_CG (updated); XI_PCG: read for r.z
     const T* sc;         // XI_PCG: diagonal scaling
     CgDev* cg;           // XI_CG

@@ -286,7 +286,7 @@ struct Solver : SolverBase {
     cplx<T>* tw;
     uint16_t* mat_id;
     MatEntry<T>* mat;
-    double *partials, *cgpA, *cgpB, *ppA, *ppB, *sums, *dE, *dgamma;
+    double *partials, *cgpA, *cgpB, *cgpC, *ppA, *ppB, *sums, *dE, *dgamma;
     int *dmask[6], *dorder, *dm1, *count;
     uint8_t* tmask = nullptr;       // split: tension flags of the Newton point
     T* dxs = nullptr;               // split: Newton correction (s fields)
@@ -342,6 +342,7 @@ struct Solver : SolverBase {
         const long long maxblk = std::max<long long>(nbx, (g.ny * (long long)g.nz + 1) / 2);
         const size_t ocgA = L.off(sizeof(double) * maxblk * B);
         const size_t ocgB = L.off(sizeof(double) * maxblk * B);
+        const size_t ocgC = L.off(sizeof(double) * maxblk * B);
         const size_t oppA = L.off(sizeof(double) * maxblk * B);
         const size_t oppB = L.off(sizeof(double) * maxblk * B);
         const size_t osums = L.off(sizeof(double) * kMaxVals * B);
@@ -373,6 +374,7 @@ struct Solver : SolverBase {
             s->partials = (double*)(base + opart);
             s->cgpA = (double*)(base + ocgA);
             s->cgpB = (double*)(base + ocgB);
+            s->cgpC = (double*)(base + ocgC);
             s->ppA = (double*)(base + oppA);
             s->ppB = (double*)(base + oppB);
             s->sums = (double*)(base + osums);
@@ -432,11 +434,13 @@ struct Solver : SolverBase {
         const bool fixed = force && force->rb > 0;
         if (fixed) RB = force->rb;
         if (RB < 2 || (RB & (RB - 1))) { why = "rows per block must be a power of two >= 2"; return false; }
+        // the fixed-size FFTs keep an LDS copy of their N twiddles
+        const size_t twx = fast_len(g.nx) ? (size_t)g.nx * ce : 0;
         if (fast_len(g.nx)) {
-            while (!fixed && RB > 2 && ((size_t)g.s * (RB / 2) * lx > kLdsCap ||
+            while (!fixed && RB > 2 && ((size_t)g.s * (RB / 2) * lx + twx > kLdsCap ||
                                         g.s * (RB / 2) * split_max(g.nx) > 256))
                 RB /= 2;
-            if ((size_t)g.s * (RB / 2) * lx <= kLdsCap && g.s * (RB / 2) * split_max(g.nx) <= 256)
+            if ((size_t)g.s * (RB / 2) * lx + twx <= kLdsCap && g.s * (RB / 2) * split_max(g.nx) <= 256)
                 px.fastN = g.nx;
         }
         auto xmb = [&](int rb) {
@@ -445,7 +449,7 @@ struct Solver : SolverBase {
         if (fixed && fast_len(g.nx) && !px.fastN) { why = "shape exceeds the block budget"; return false; }
         if (!px.fastN)
             while (!fixed && RB > 2 && ((size_t)g.s * (RB / 2) * lx > kLdsCap || xmb(RB) < 0)) RB /= 2;
-        lds_x = (size_t)g.s * (RB / 2) * lx;
+        lds_x = (size_t)g.s * (RB / 2) * lx + (px.fastN ? twx : 0);
         maxb_x = px.fastN ? 1 : xmb(RB);
         if (lds_x > kLdsCap || maxb_x < 0) { why = "n_x too large for the LDS budget"; return false; }
         thr_x = px.fastN ? threads_for(g.s * (RB / 2) * split_max(g.nx)) : 256;
@@ -457,8 +461,9 @@ struct Solver : SolverBase {
             for (int t = pow2_floor(std::max(1, want)); t >= 1; t /= 2) {
                 const size_t l = (size_t)g.s * t * lds_line(pl.N) * ce;
                 if (fast) {
-                    if (l <= kLdsCap && g.s * t * split_max(pl.N) <= 256) {
-                        tl = t; mb = 1; lds = l; pl.fastN = pl.N;
+                    const size_t lt = l + (size_t)pl.N * ce;     // + LDS twiddles
+                    if (lt <= kLdsCap && g.s * t * split_max(pl.N) <= 256) {
+                        tl = t; mb = 1; lds = lt; pl.fastN = pl.N;
                         thr = threads_for(g.s * t * split_max(pl.N));
                         return true;
                     }
@@ -640,11 +645,13 @@ struct Solver : SolverBase {
     }
 
     // ---- Green operator passes --------------------------------------------
-    // Mechanics CG partials: the x-forward pass writes p.Ap into cgpA, the
-    // x-inverse pass r.r into cgpB; each pass of iteration k reads what the
-    // other left.
+    // Mechanics CG partials: the x-forward pass of iteration k writes p.Ap
+    // into pap_slot(k) (read by the x-inverse pass of k, for r, and by the
+    // x-forward pass of k + 1, for x); the x-inverse pass writes r.r into
+    // cgpB, read by the next x-forward pass.
+    double* pap_slot(int k) const { return (k & 1) ? cgpC : cgpA; }
     int fwd_x(int mode, const T* phi, const T* eps, double fcoef, double* part, const int* mask,
-              int iter = 0) {
+              int iter = 0, T* xsol = nullptr) {
         XfwdArgs<T> a;
         std::memset(&a, 0, sizeof(a));
         a.g = g;
@@ -658,13 +665,18 @@ struct Solver : SolverBase {
         for (int c = 0; c < 6; ++c) a.f[c] = T(c < g.s ? cfg.f[c] : 0.0);
         a.r = r;
         a.p = p;
-        a.cg = (mode == XF_CG || mode == XF_CG_T) ? cg : nullptr;
         a.tmask = tmask;
-        a.rr_part = cgpB;
         a.iter = iter;
         a.active = mask;
         a.spec = spec;
         a.partials = part;
+        if (mode == XF_CG || mode == XF_CG_T) {
+            a.cg = cg;
+            a.x = xsol ? xsol : x;
+            a.rr_part = cgpB;
+            a.partials = pap_slot(iter);
+            a.pap_prev = pap_slot(iter + 1);
+        }
         a.rows_per_block = RB;
         a.nblocks = nbx;
         a.threads = thr_x;
@@ -703,8 +715,7 @@ struct Solver : SolverBase {
         }
         return RVE_OK;
     }
-    int inv_x(int mode, T* out, double scale, double* part, const int* mask, int iter = 0,
-              T* xsol = nullptr) {
+    int inv_x(int mode, T* out, double scale, double* part, const int* mask, int iter = 0) {
         XinvArgs<T> a;
         std::memset(&a, 0, sizeof(a));
         a.g = g;
@@ -713,11 +724,9 @@ struct Solver : SolverBase {
         a.spec = spec;
         a.scale = T(scale);
         a.out = out;
-        a.x = xsol ? xsol : x;
-        a.p = p;
         a.r = r;
         a.cg = mode == XI_CG ? cg : nullptr;
-        a.pAp_part = cgpA;
+        a.pAp_part = pap_slot(iter);
         a.iter = iter;
         a.active = mask;
         a.partials = part;
@@ -868,9 +877,9 @@ struct Solver : SolverBase {
         for (;;) {
             if (cfg.graphs && st) chunk = (chunk + kGraphChunk - 1) / kGraphChunk * kGraphChunk;
             CHK(run_iterations(key, k, chunk, [&](int kk) -> int {
-                CHK(fwd_x(mode, phi, nullptr, 0.0, cgpA, nullptr, kk));
+                CHK(fwd_x(mode, phi, nullptr, 0.0, nullptr, nullptr, kk, xsol));
                 CHK(axes(cg, nullptr, kk));
-                CHK(inv_x(XI_CG, nullptr, 1.0, cgpB, nullptr, kk, xsol));
+                CHK(inv_x(XI_CG, nullptr, 1.0, cgpB, nullptr, kk));
                 return RVE_OK;
             }));
             k += chunk;
@@ -1824,8 +1833,8 @@ struct Solver : SolverBase {
     // Launch one kind of pass `repeat` times on every ready RVE of the batch
     // (for timing against its algorithmic bytes).  0: x-forward (constitutive),
     // 1: the projection axis pass, 2: x-inverse (store), 3: x-forward with the
-    // CG direction update, 4: x-inverse with the CG update (alpha = 0, so the
-    // iterate is unchanged).
+    // CG updates of x and p, 4: x-inverse with the CG update of r (alpha = 0,
+    // so the iterate is unchanged).
     int profile_pass(int pass, int repeat, double* bytes) override {
         std::vector<int> rd(B, 0);
         int nready = 0;
@@ -1860,7 +1869,7 @@ struct Solver : SolverBase {
                 case 1: HIPCHK(launch_axis<T>(a, AX_FWD_P_INV, three ? maxb_z : maxb_y, grid,
                                               three ? lds_z : lds_y, st)); break;
                 case 2: CHK(inv_x(XI_STORE, p, 1.0, cgpB, dmask[0])); break;
-                case 3: CHK(fwd_x(XF_CG, phi_c, nullptr, 0.0, cgpA, nullptr, 1)); break;
+                case 3: CHK(fwd_x(XF_CG, phi_c, nullptr, 0.0, nullptr, nullptr, 1)); break;
                 case 4: CHK(inv_x(XI_CG, nullptr, 1.0, cgpB, nullptr, 1)); break;
                 case 5: {   // the forward y pass of a 3D operator (2D: as pass 1)
                     AxisArgs<T> y = a;
@@ -1883,8 +1892,8 @@ struct Solver : SolverBase {
             case 0: bb = N * ((S + 1) * w + 2) + N * sp * S * w; break;
             case 1: bb = 2.0 * N * sp * S * w; break;
             case 2: bb = N * sp * S * w + N * S * w; break;
-            case 3: bb = N * (3 * S * w + w + 2) + N * sp * S * w; break;
-            case 4: bb = N * sp * S * w + N * 5 * S * w; break;
+            case 3: bb = N * (5 * S * w + w + 2) + N * sp * S * w; break;
+            case 4: bb = N * sp * S * w + N * 2 * S * w; break;
             case 5: bb = 2.0 * N * sp * S * w; break;
         }
         if (bytes) *bytes = bb;
