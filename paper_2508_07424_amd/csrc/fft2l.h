@@ -110,7 +110,9 @@ __host__ __device__ constexpr int split_max(int N) {
 }
 
 // In-place DFT of nlines lines (element e of line l at buf[l * LS + lp(e)]),
-// natural order in and out.  tw = exp(-2 pi i m / N), m < N.
+// natural order in and out.  tw holds the phase-A twiddles in LDS as an
+// N1 x N2 table, tw[k1 * N2 + t] = exp(-2 pi i t k1 / N), so that the
+// threads of a column group read consecutive entries (no bank conflicts).
 template <typename T, int N>
 __device__ __forceinline__ void fft_lines(cplx<T>* buf, int nlines, int LS,
                                           const cplx<T>* __restrict__ tw, bool inv) {
@@ -127,7 +129,7 @@ __device__ __forceinline__ void fft_lines(cplx<T>* buf, int nlines, int LS,
             RegDFT<T, N1>::run(v, inv);
 #pragma unroll
             for (int k1 = 1; k1 < N1; ++k1) {
-                cplx<T> w = tw[t * k1];
+                cplx<T> w = tw[k1 * N2 + t];
                 if (inv) w.y = -w.y;
                 v[k1] = cmul(v[k1], w);
             }

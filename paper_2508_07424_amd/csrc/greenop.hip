@@ -45,9 +45,13 @@ __device__ inline T degr(T phi, T k) {
 }
 
 // Compatible-strain projection P(n) (Eq. 26, symmetric reading) on one
-// Mandel vector of complex spectra, n real and unit (or zero).
+// Mandel vector of complex spectra.  The direction is passed as the
+// frequency x and y = x / |x|^2 (both zero at the zero frequency): with
+// n = x / |x| and the symmetric tensor t of the Mandel vector,
+// P_ij = n_i u_j + u_i n_j - (n.u) n_i n_j, u = t n, equals
+// y_i U_j + U_i y_j - (x.U) y_i y_j with U = t x, which needs no square root.
 template <typename T>
-__device__ __forceinline__ void project2(cplx<T> (&v)[3], T n1, T n2) {
+__device__ __forceinline__ void project2(cplx<T> (&v)[3], const T (&x)[3], const T (&y)[3]) {
     const T is2 = T(0.70710678118654752440084436210485);
     const T s2 = T(1.4142135623730950488016887242097);
 #pragma unroll
@@ -55,21 +59,20 @@ __device__ __forceinline__ void project2(cplx<T> (&v)[3], T n1, T n2) {
         const T a = part ? v[0].y : v[0].x;
         const T b = part ? v[1].y : v[1].x;
         const T c = (part ? v[2].y : v[2].x) * is2;
-        const T u1 = a * n1 + c * n2, u2 = c * n1 + b * n2;
-        const T w = n1 * u1 + n2 * u2;
-        const T p0 = T(2) * n1 * u1 - w * n1 * n1;
-        const T p1 = T(2) * n2 * u2 - w * n2 * n2;
-        const T p2 = s2 * (n1 * u2 + n2 * u1 - w * n1 * n2);
+        const T U1 = a * x[0] + c * x[1], U2 = c * x[0] + b * x[1];
+        const T W = x[0] * U1 + x[1] * U2;
+        const T p0 = T(2) * y[0] * U1 - W * y[0] * y[0];
+        const T p1 = T(2) * y[1] * U2 - W * y[1] * y[1];
+        const T p2 = s2 * (y[0] * U2 + y[1] * U1 - W * y[0] * y[1]);
         if (part) { v[0].y = p0; v[1].y = p1; v[2].y = p2; }
         else { v[0].x = p0; v[1].x = p1; v[2].x = p2; }
     }
 }
 
 template <typename T>
-__device__ __forceinline__ void project3(cplx<T> (&v)[6], T n1, T n2, T n3) {
+__device__ __forceinline__ void project3(cplx<T> (&v)[6], const T (&x)[3], const T (&y)[3]) {
     const T is2 = T(0.70710678118654752440084436210485);
     const T s2 = T(1.4142135623730950488016887242097);
-    const T n[3] = {n1, n2, n3};
 #pragma unroll
     for (int part = 0; part < 2; ++part) {
         T q[6];
@@ -78,11 +81,11 @@ __device__ __forceinline__ void project3(cplx<T> (&v)[6], T n1, T n2, T n3) {
         const T t[3][3] = {{q[0], q[5] * is2, q[4] * is2},
                            {q[5] * is2, q[1], q[3] * is2},
                            {q[4] * is2, q[3] * is2, q[2]}};
-        T u[3];
+        T U[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) u[i] = t[i][0] * n[0] + t[i][1] * n[1] + t[i][2] * n[2];
-        const T w = n[0] * u[0] + n[1] * u[1] + n[2] * u[2];
-        auto P = [&](int i, int j) { return n[i] * u[j] + u[i] * n[j] - w * n[i] * n[j]; };
+        for (int i = 0; i < 3; ++i) U[i] = t[i][0] * x[0] + t[i][1] * x[1] + t[i][2] * x[2];
+        const T W = x[0] * U[0] + x[1] * U[1] + x[2] * U[2];
+        auto P = [&](int i, int j) { return y[i] * U[j] + U[i] * y[j] - W * y[i] * y[j]; };
         const T o[6] = {P(0, 0), P(1, 1), P(2, 2), s2 * P(1, 2), s2 * P(0, 2), s2 * P(0, 1)};
 #pragma unroll
         for (int a = 0; a < 6; ++a) {
@@ -94,10 +97,13 @@ __device__ __forceinline__ void project3(cplx<T> (&v)[6], T n1, T n2, T n3) {
 
 __device__ __forceinline__ int signed_k(int k, int N) { return (2 * k < N) ? k : k - N; }
 
-// Frequency direction with the Nyquist rule: on an even axis the index
-// k = -N/2 keeps its frequency only if every other index is zero.
+// Frequency with the Nyquist rule: on an even axis the index k = -N/2
+// keeps its frequency only if every other index is zero.  Same h on every
+// axis, so x_j = k_j / N_j up to a common factor (rN_j = 1 / N_j); returns
+// x and y = x / |x|^2, both zero at the zero frequency.
 template <typename T>
-__device__ __forceinline__ void freq_dir(const Geom& g, int kx, int ky, int kz, T& n1, T& n2, T& n3) {
+__device__ __forceinline__ void freq_xy(const Geom& g, int kx, int ky, int kz, const T (&rN)[3],
+                                        T (&x)[3], T (&y)[3]) {
     int sx = (g.nx % 2 == 0 && 2 * kx == g.nx) ? -g.nx / 2 : kx;
     int sy = signed_k(ky, g.ny);
     int sz = g.dim == 3 ? signed_k(kz, g.nz) : 0;
@@ -110,13 +116,13 @@ __device__ __forceinline__ void freq_dir(const Geom& g, int kx, int ky, int kz, 
     if (nyx && (oy != 0 || oz != 0)) sx = 0;
     if (nyy && (ox != 0 || oz != 0)) sy = 0;
     if (nyz && (ox != 0 || oy != 0)) sz = 0;
-    // same h on every axis: xi_j is proportional to k_j / N_j
-    const double x1 = double(sx) / g.nx, x2 = double(sy) / g.ny, x3 = double(sz) / g.nz;
-    const double nr = sqrt(x1 * x1 + x2 * x2 + x3 * x3);
-    if (nr == 0.0) { n1 = n2 = n3 = T(0); return; }
-    n1 = T(x1 / nr);
-    n2 = T(x2 / nr);
-    n3 = T(x3 / nr);
+    x[0] = T(sx) * rN[0];
+    x[1] = T(sy) * rN[1];
+    x[2] = T(sz) * rN[2];
+    const T n2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+    const T inv = n2 > T(0) ? T(1) / n2 : T(0);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) y[i] = x[i] * inv;
 }
 
 // Symbol of the damage preconditioner at frequency (kx, ky, kz):
@@ -154,21 +160,25 @@ constexpr int kLd = 4;
 // the loads of a round are all in flight before the first use waits.
 __device__ __forceinline__ void loads_issued() { __builtin_amdgcn_sched_barrier(0); }
 
-// The fixed-size FFTs read their twiddles from an LDS copy at the start of
+// The fixed-size FFTs read their twiddles from an LDS table at the start of
 // the dynamic LDS (global twiddle loads inside the butterflies would each
-// wait on memory); the runtime plans read them from global memory.
+// wait on memory): entry k1 * N2 + t holds exp(-2 pi i t k1 / N), the
+// twiddle of column t and output k1 of the first phase (t k1 < N).  The
+// runtime plans read theirs from global memory.
 template <typename F>
 __device__ __forceinline__ constexpr int tw_lds_len() { return F::fast ? F::N : 0; }
 
 template <typename T, typename F>
 __device__ __forceinline__ void stage_twiddles(cplx<T>* twl, const cplx<T>* tw) {
     if constexpr (F::fast) {
+        constexpr int N2 = Split<F::N>::N2;
         for (int i0 = threadIdx.x; i0 < F::N; i0 += kLd * blockDim.x) {
             cplx<T> t[kLd];
 #pragma unroll
             for (int u = 0; u < kLd; ++u) {
                 const int i = i0 + u * blockDim.x;
-                t[u] = tw[i < F::N ? i : 0];
+                const int k1 = i / N2, c = i - k1 * N2;
+                t[u] = tw[i < F::N ? c * k1 : 0];
             }
             loads_issued();
 #pragma unroll
@@ -478,6 +488,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
     const int ny = g.ny, nz = g.nz;
     cplx<T>* sp = a.spec + (long long)b * S * g.Nspec;
     const bool inv_only = MODE == AX_INV;
+    const T rN[3] = {T(1) / T(g.nx), T(1) / T(g.ny), T(1) / T(g.nz)};
     stage_twiddles<T, F>(twl, a.tw);     // ordered by the barrier before the FFT
 
     const int LS = lds_line(Na);
@@ -529,13 +540,13 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
                 const long long L = L0 + tl;
                 if (L >= nlines) continue;
                 const int kx = (int)(L / nz), kz = (int)(L % nz);
-                T n1, n2, n3;
-                freq_dir<T>(g, kx, j, kz, n1, n2, n3);
+                T fx[3], fy[3];
+                freq_xy<T>(g, kx, j, kz, rN, fx, fy);
                 cplx<T> v[S];
 #pragma unroll
                 for (int c = 0; c < S; ++c) v[c] = buf[(c * TL + tl) * LS + lp(j)];
-                if constexpr (S == 3) project2<T>(v, n1, n2);
-                else if constexpr (S == 6) project3<T>(v, n1, n2, n3);
+                if constexpr (S == 3) project2<T>(v, fx, fy);
+                else if constexpr (S == 6) project3<T>(v, fx, fy);
 #pragma unroll
                 for (int c = 0; c < S; ++c) buf[(c * TL + tl) * LS + lp(j)] = v[c];
             }
@@ -594,13 +605,13 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
             for (int e = threadIdx.x; e < TL * Na; e += blockDim.x) {
                 const int tl = e & (TL - 1), j = e >> lgt;
                 if (y0 + tl >= ny) continue;
-                T n1, n2, n3;
-                freq_dir<T>(g, kx, y0 + tl, j, n1, n2, n3);
+                T fx[3], fy[3];
+                freq_xy<T>(g, kx, y0 + tl, j, rN, fx, fy);
                 cplx<T> v[S];
 #pragma unroll
                 for (int c = 0; c < S; ++c) v[c] = buf[(c * TL + tl) * LS + lp(j)];
-                if constexpr (S == 3) project2<T>(v, n1, n2);
-                else if constexpr (S == 6) project3<T>(v, n1, n2, n3);
+                if constexpr (S == 3) project2<T>(v, fx, fy);
+                else if constexpr (S == 6) project3<T>(v, fx, fy);
 #pragma unroll
                 for (int c = 0; c < S; ++c) buf[(c * TL + tl) * LS + lp(j)] = v[c];
             }
