@@ -40,19 +40,32 @@ struct Nb {
     long long xm, xp, ym, yp, zm, zp;
 };
 
+// q = u / d and u - q d in 32-bit arithmetic (a shift and a mask for a
+// power-of-two d, uniform across the wave).
+__device__ __forceinline__ unsigned divmod_u32(unsigned u, unsigned d, unsigned& r) {
+    if ((d & (d - 1)) == 0) {
+        r = u & (d - 1);
+        return u >> __builtin_ctz(d);
+    }
+    const unsigned q = u / d;
+    r = u - q * d;
+    return q;
+}
+
+// Periodic neighbour indices of voxel idx of one RVE (N <= 2^30: every
+// axis has at most 1024 voxels).
 __device__ inline Nb neighbours(const Geom& g, long long idx) {
-    const int x = (int)(idx % g.nx);
-    const long long t = idx / g.nx;
-    const int y = (int)(t % g.ny);
-    const int z = (int)(t / g.ny);
+    unsigned x, y;
+    const unsigned t = divmod_u32((unsigned)idx, (unsigned)g.nx, x);
+    const unsigned z = divmod_u32(t, (unsigned)g.ny, y);
     const long long sy = g.nx, sz = (long long)g.nx * g.ny;
     Nb n;
     n.xm = idx + (x == 0 ? g.nx - 1 : -1);
-    n.xp = idx + (x == g.nx - 1 ? -(g.nx - 1) : 1);
+    n.xp = idx + (x == (unsigned)g.nx - 1 ? -(g.nx - 1) : 1);
     n.ym = idx + (y == 0 ? (g.ny - 1) * sy : -sy);
-    n.yp = idx + (y == g.ny - 1 ? -(g.ny - 1) * sy : sy);
+    n.yp = idx + (y == (unsigned)g.ny - 1 ? -(g.ny - 1) * sy : sy);
     n.zm = idx + (z == 0 ? (g.nz - 1) * sz : -sz);
-    n.zp = idx + (z == g.nz - 1 ? -(g.nz - 1) * sz : sz);
+    n.zp = idx + (z == (unsigned)g.nz - 1 ? -(g.nz - 1) * sz : sz);
     return n;
 }
 

@@ -271,6 +271,9 @@ struct Solver : SolverBase {
     int RB1 = 2, nbx1 = 1, tly1 = 1, tlz1 = 1;
     int thr_x = 256, thr_y = 256, thr_z = 256;
     size_t lds_x = 0, lds_y = 0, lds_z = 0;
+    // launch shape of the one-component passes (damage preconditioner)
+    int thr_x1 = 256, thr_y1 = 256, thr_z1 = 256;
+    size_t lds_x1 = 0, lds_y1 = 0, lds_z1 = 0;
     int nred = 1;
     hipStream_t st;
     int load_axis = 1;
@@ -509,12 +512,7 @@ struct Solver : SolverBase {
         Layout L;
         layout(c, g, nbx, L, this);
         nred = (int)std::min<long long>((g.N + 255) / 256, kRedBlocks);
-        // one-component passes keep the rows / lines per block of the s-component
-        // ones: the grid stays as large, and the LDS and threads fit a fortiori
-        RB1 = RB;
-        nbx1 = (int)((g.ny * (long long)g.nz + RB1 - 1) / RB1);
-        tly1 = tly;
-        tlz1 = tlz;
+        one_comp_shape();
         int ax = 0;
         double best = -1;
         for (int a = 0; a < g.dim; ++a)
@@ -761,8 +759,8 @@ struct Solver : SolverBase {
         a.partials = ppA;
         a.rows_per_block = RB1;
         a.nblocks = nbx1;
-        a.threads = thr_x;
-        HIPCHK(launch_xfwd<T>(a, xmode, maxb_x, lds_x, st));
+        a.threads = thr_x1;
+        HIPCHK(launch_xfwd<T>(a, xmode, maxb_x, lds_x1, st));
         AxisArgs<T> y;
         std::memset(&y, 0, sizeof(y));
         y.g = g;
@@ -773,19 +771,19 @@ struct Solver : SolverBase {
         y.tw = tw + ply.tw_off;
         y.contiguous = 1;
         y.lines = tly1;
-        y.threads = thr_y;
+        y.threads = thr_y1;
         if (g.dim == 2) {
-            HIPCHK(launch_axis<T>(y, AX_FWD_M_INV, maxb_y, grid_y(tly1), lds_y, st));
+            HIPCHK(launch_axis<T>(y, AX_FWD_M_INV, maxb_y, grid_y(tly1), lds_y1, st));
         } else {
-            HIPCHK(launch_axis<T>(y, AX_FWD, maxb_y, grid_y(tly1), lds_y, st));
+            HIPCHK(launch_axis<T>(y, AX_FWD, maxb_y, grid_y(tly1), lds_y1, st));
             AxisArgs<T> z = y;
             z.pl = plz;
             z.tw = tw + plz.tw_off;
             z.contiguous = 0;
             z.lines = tlz1;
-            z.threads = thr_z;
-            HIPCHK(launch_axis<T>(z, AX_FWD_M_INV, maxb_z, grid_z(tlz1), lds_z, st));
-            HIPCHK(launch_axis<T>(y, AX_INV, maxb_y, grid_y(tly1), lds_y, st));
+            z.threads = thr_z1;
+            HIPCHK(launch_axis<T>(z, AX_FWD_M_INV, maxb_z, grid_z(tlz1), lds_z1, st));
+            HIPCHK(launch_axis<T>(y, AX_INV, maxb_y, grid_y(tly1), lds_y1, st));
         }
         XinvArgs<T> v;
         std::memset(&v, 0, sizeof(v));
@@ -802,8 +800,8 @@ struct Solver : SolverBase {
         v.partials = ppB;
         v.rows_per_block = RB1;
         v.nblocks = nbx1;
-        v.threads = thr_x;
-        HIPCHK(launch_xinv<T>(v, XI_PCG, maxb_x, lds_x, st));
+        v.threads = thr_x1;
+        HIPCHK(launch_xinv<T>(v, XI_PCG, maxb_x, lds_x1, st));
         return RVE_OK;
     }
 
@@ -1715,6 +1713,44 @@ struct Solver : SolverBase {
     }
 
     // ---- launch shape -----------------------------------------------------------
+    // One-component passes (the damage preconditioner): the x passes keep the
+    // rows per block of the s-component ones (the grid stays as large); the
+    // axis passes take s times the lines (columns) per block, rounded down to
+    // a power of two (at least 4 lines for the fixed-size FFTs, so that a
+    // wave's lanes all carry butterflies).  LDS and threads are sized for one
+    // component, which raises the blocks per CU.
+    void one_comp_shape() {
+        const size_t ce = sizeof(cplx<T>);
+        RB1 = RB;
+        nbx1 = (int)((g.ny * (long long)g.nz + RB1 - 1) / RB1);
+        if (plx.fastN) {
+            thr_x1 = threads_for((RB1 / 2) * split_max(g.nx));
+            lds_x1 = (size_t)(RB1 / 2) * lds_line(g.nx) * ce + (size_t)g.nx * ce;
+        } else {
+            thr_x1 = thr_x;
+            lds_x1 = lds_x;
+        }
+        auto lines1 = [&](const AxisPlan& pl, int tl_s, int cap, size_t lds_s, int thr_s, int& tl1,
+                          size_t& lds1, int& thr1) {
+            tl1 = pow2_floor(std::max(1, g.s * tl_s));
+            if (!pl.fastN) {               // within the s-component shape
+                lds1 = lds_s;
+                thr1 = thr_s;
+                return;
+            }
+            tl1 = std::max(tl1, 4);
+            auto fits = [&](int t) {
+                return t <= cap && t * split_max(pl.N) <= 256 &&
+                       (size_t)t * lds_line(pl.N) * ce + (size_t)pl.N * ce <= kLdsCap;
+            };
+            while (tl1 > 1 && !fits(tl1)) tl1 /= 2;
+            lds1 = (size_t)tl1 * lds_line(pl.N) * ce + (size_t)pl.N * ce;
+            thr1 = threads_for(tl1 * split_max(pl.N));
+        };
+        lines1(ply, tly, 1 << 20, lds_y, thr_y, tly1, lds_y1, thr_y1);
+        if (g.dim == 3) lines1(plz, tlz, g.ny, lds_z, thr_z, tlz1, lds_z1, thr_z1);
+    }
+
     int set_shape(const Shape& sh) {
         Geom g2;
         AxisPlan a = plx, b = ply, d = plz;
@@ -1732,10 +1768,7 @@ struct Solver : SolverBase {
         tly = ty; maxb_y = my; lds_y = ly;
         tlz = tz; maxb_z = mz; lds_z = lz;
         thr_x = t1; thr_y = t2; thr_z = t3;
-        RB1 = RB;
-        nbx1 = (int)((g.ny * (long long)g.nz + RB1 - 1) / RB1);
-        tly1 = tly;
-        tlz1 = tlz;
+        one_comp_shape();
         clear_graphs();            // captured launches carry the old shape
         return RVE_OK;
     }
