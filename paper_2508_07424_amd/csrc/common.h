@@ -10,6 +10,10 @@ constexpr int kMaxStages = 12;     // radix stages per axis (N <= 1024)
 constexpr int kMaxMat = 65536;     // material table entries
 constexpr int kRedBlocks = 1024;   // max blocks of a reduction kernel
 
+// Keeps the scheduler from sinking the loads above it to their uses below:
+// the loads of a round are all in flight before the first use waits.
+__device__ __forceinline__ void loads_issued() { __builtin_amdgcn_sched_barrier(0); }
+
 template <typename T>
 struct cplx {
     T x, y;

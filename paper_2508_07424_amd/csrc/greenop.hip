@@ -156,9 +156,6 @@ __device__ __forceinline__ int line_len(const AxisPlan& pl) {
 // Global loads each thread keeps in flight in the gather loops of the passes.
 constexpr int kLd = 4;
 
-// Keeps the scheduler from sinking the loads above it to their uses below:
-// the loads of a round are all in flight before the first use waits.
-__device__ __forceinline__ void loads_issued() { __builtin_amdgcn_sched_barrier(0); }
 
 // The fixed-size FFTs read their twiddles from an LDS table at the start of
 // the dynamic LDS (global twiddle loads inside the butterflies would each

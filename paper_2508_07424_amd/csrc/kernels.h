@@ -212,19 +212,21 @@ hipError_t launch_pcg_start(const Geom& g, const T* b, const T* Ax, const T* din
 // test, beta = rz_k / rz_{k-1}; then the direction p_new = z + beta p_old
 // evaluated at the voxel and its stencil neighbours (z = dinv r for Jacobi,
 // the stored field zf for the FFT preconditioner), q = A p_new, partials p.q
-// (value 0).
+// (value 0) from nblk blocks per RVE (nblk <= kRedBlocks).
 template <typename T>
 hipError_t launch_pcg_matvec_dir(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
                                  const T* H, int mode, double c, int pre, const T* r,
                                  const T* dinv, const T* zf, const T* p_old, T* p_new, T* q,
                                  const double* rz_part, long long rz_stride, int rz_n,
                                  const double* rr_part, long long rr_stride, int rr_n,
-                                 double* partials, int nred, PcgDev* d, int iter, hipStream_t st);
-// Iteration k, step 2 (Jacobi): alpha = rz_k / p.q, x += alpha p,
-// r -= alpha q, partials r.(dinv r) (value 1) and r.r (value 2).
+                                 double* partials, int nblk, PcgDev* d, int iter, hipStream_t st);
+// Iteration k, step 2 (Jacobi): alpha = rz_k / p.q (n_pq partials),
+// x += alpha p, r -= alpha q, partials r.(dinv r) (value 1) and r.r
+// (value 2) from nred blocks.
 template <typename T>
 hipError_t launch_pcg_update(const Geom& g, PcgDev* d, T* x, T* r, const T* p, const T* q,
-                             const T* dinv, double* partials, int nred, int iter, hipStream_t st);
+                             const T* dinv, double* partials, int n_pq, int nred, int iter,
+                             hipStream_t st);
 
 // D(phi) (value 0) and Gamma(phi) (value 1) partials without the h^d factor.
 template <typename T>

@@ -495,6 +495,89 @@ __device__ __forceinline__ T zval(const T* r, const T* dinv, const T* zf, long l
     else return zf[j];
 }
 
+// U voxels per thread and round of the direction update + operator below, in
+// three phases: (1) the independent loads (phase ids, history, z and the old
+// direction at the voxel and its 2 d neighbours), at clamped addresses so
+// that none waits for another; (2) the Gc of the phase ids; (3) arithmetic
+// and stores.  Returns the thread's p.q partial.
+template <typename T, int PRE, int DIM, int U>
+__device__ __forceinline__ double matvec_dir_rounds(const Geom& g, const uint16_t* mid,
+                                                    const MatEntry<T>* mt, const T* Hb, int mode,
+                                                    T c, const T* r, const T* dinv, const T* zf,
+                                                    const T* po, T beta, bool first, T* pn, T* q) {
+    constexpr int NP = 1 + 2 * DIM;       // the voxel, then xm, xp, ym, yp (zm, zp)
+    constexpr int NW = 1 + DIM;           // Gc at the voxel and at xm, ym (zm)
+    const T ell = T(g.ell);
+    const T ih2 = T(1.0 / (g.h * g.h));
+    const long long N = g.N;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    double part = 0.0;
+    for (long long i0 = blockIdx.x * (long long)blockDim.x + threadIdx.x; i0 < N; i0 += U * stride) {
+        T zz[U][NP], pp[U][NP], hh[U], gcw[U][NW];
+        int id[U][NW];
+        long long iv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const long long i = i0 + u * stride;
+            iv[u] = i;
+            const Nb n = neighbours(g, i < N ? i : 0);
+            const long long j[7] = {i < N ? i : 0, n.xm, n.xp, n.ym, n.yp, n.zm, n.zp};
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                if constexpr (PRE == PRE_JACOBI) zz[u][k] = dinv[j[k]] * r[j[k]];
+                else zz[u][k] = zf[j[k]];
+                pp[u][k] = first ? T(0) : po[j[k]];
+            }
+            hh[u] = Hb ? Hb[j[0]] : T(0);
+            if (mode == 0) {
+                id[u][0] = mid[j[0]];
+#pragma unroll
+                for (int k = 1; k < NW; ++k) id[u][k] = mid[j[2 * k - 1]];
+            }
+        }
+        loads_issued();
+        if (mode == 0) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int k = 0; k < NW; ++k) gcw[u][k] = mt[id[u][k]].Gc;
+            loads_issued();
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (iv[u] >= N) break;
+            T a, w, wm[NW];
+            if (mode == 0) {
+                a = gcw[u][0] / ell + (Hb ? T(2) * hh[u] : T(0));
+                w = gcw[u][0] * ell;
+#pragma unroll
+                for (int k = 1; k < NW; ++k) wm[k] = gcw[u][k] * ell;
+            } else {
+                a = T(1);
+                w = c;
+#pragma unroll
+                for (int k = 1; k < NW; ++k) wm[k] = c;
+            }
+            T pd[NP];
+#pragma unroll
+            for (int k = 0; k < NP; ++k) pd[k] = first ? zz[u][k] : zz[u][k] + beta * pp[u][k];
+            const T pc = pd[0];
+            T acc = T(0);
+#pragma unroll
+            for (int d = 0; d < DIM; ++d)
+                acc += wm[d + 1] * (pc - pd[1 + 2 * d]) - w * (pd[2 + 2 * d] - pc);
+            const T v = a * pc + acc * ih2;
+            pn[iv[u]] = pc;
+            q[iv[u]] = v;
+            part += double(pc) * double(v);
+        }
+    }
+    return part;
+}
+
+// One PCG step: r.z and r.r of the residual left by the previous step and
+// the stopping test; then p = z + beta p_old (p = z at k = 0, where p_old is
+// not read: it may hold anything), q = A p and the p.q partials.
 template <typename T, int PRE>
 __global__ void __launch_bounds__(TPB) k_pcg_matvec_dir(
     Geom g, const uint16_t* mat_id, const MatEntry<T>* mat, const T* H, int mode, T c,
@@ -503,7 +586,6 @@ __global__ void __launch_bounds__(TPB) k_pcg_matvec_dir(
     long long rr_stride, int rr_n, double* partials, PcgDev* d, int k) {
     const int b = blockIdx.y;
     if (d[b].conv <= k) return;
-    // r.z and r.r of the residual left by the previous step; stopping test
     double rz[1], rr[1];
     block_sum_all<1>(rz_part + (long long)b * rz_stride, 0, rz_n, rz);
     block_sum_all<1>(rr_part + (long long)b * rr_stride, 0, rr_n, rr);
@@ -524,34 +606,15 @@ __global__ void __launch_bounds__(TPB) k_pcg_matvec_dir(
     if (stop) return;
     const T beta = k > 0 ? T(rz[0] / prev) : T(0);
     RVE_OFFSETS
-    const T* r = r_a + so;
-    const T* dinv = dinv_a + so;
-    const T* zf = zf_a ? zf_a + so : nullptr;
-    const T* po = po_a + so;
     const T* Hb = H ? H + so : nullptr;
-    const T ell = T(g.ell);
-    const T ih2 = T(1.0 / (g.h * g.h));
-    // the first direction is z itself (p_old is not read: it may hold anything)
-    auto pdir = [&](long long j) {
-        const T z = zval<T, PRE>(r, dinv, zf, j);
-        return k > 0 ? z + beta * po[j] : z;
-    };
-    double part = 0.0;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.N;
-         i += (long long)gridDim.x * blockDim.x) {
-        T a, w;
-        coeffs(g, mt, mid, Hb, mode, c, i, a, w);
-        const Nb n = neighbours(g, i);
-        const T pc = pdir(i);
-        T acc = wcoef(mt, mid, mode, ell, c, n.xm) * (pc - pdir(n.xm)) - w * (pdir(n.xp) - pc);
-        acc += wcoef(mt, mid, mode, ell, c, n.ym) * (pc - pdir(n.ym)) - w * (pdir(n.yp) - pc);
-        if (g.dim == 3)
-            acc += wcoef(mt, mid, mode, ell, c, n.zm) * (pc - pdir(n.zm)) - w * (pdir(n.zp) - pc);
-        const T v = a * pc + acc * ih2;
-        pn_a[so + i] = pc;
-        q_a[so + i] = v;
-        part += double(pc) * double(v);
-    }
+    const T* zf = zf_a ? zf_a + so : nullptr;
+    double part;
+    if (g.dim == 2)
+        part = matvec_dir_rounds<T, PRE, 2, 4>(g, mid, mt, Hb, mode, c, r_a + so, dinv_a + so, zf,
+                                               po_a + so, beta, k == 0, pn_a + so, q_a + so);
+    else
+        part = matvec_dir_rounds<T, PRE, 3, 2>(g, mid, mt, Hb, mode, c, r_a + so, dinv_a + so, zf,
+                                               po_a + so, beta, k == 0, pn_a + so, q_a + so);
     double pv[1] = {part};
     block_sum_store<1>(pv, pslot(partials, b, 0), kRedBlocks, blockIdx.x);
 }
@@ -562,13 +625,13 @@ hipError_t launch_pcg_matvec_dir(const Geom& g, const uint16_t* mat_id, const Ma
                                  const T* dinv, const T* zf, const T* p_old, T* p_new, T* q,
                                  const double* rz_part, long long rz_stride, int rz_n,
                                  const double* rr_part, long long rr_stride, int rr_n,
-                                 double* partials, int nred, PcgDev* d, int iter, hipStream_t st) {
+                                 double* partials, int nblk, PcgDev* d, int iter, hipStream_t st) {
     if (pre == PRE_JACOBI)
-        hipLaunchKernelGGL((k_pcg_matvec_dir<T, PRE_JACOBI>), dim3(nred, g.B), dim3(TPB), 0, st, g,
+        hipLaunchKernelGGL((k_pcg_matvec_dir<T, PRE_JACOBI>), dim3(nblk, g.B), dim3(TPB), 0, st, g,
                            mat_id, mat, H, mode, T(c), r, dinv, zf, p_old, p_new, q, rz_part,
                            rz_stride, rz_n, rr_part, rr_stride, rr_n, partials, d, iter);
     else
-        hipLaunchKernelGGL((k_pcg_matvec_dir<T, PRE_FFT>), dim3(nred, g.B), dim3(TPB), 0, st, g,
+        hipLaunchKernelGGL((k_pcg_matvec_dir<T, PRE_FFT>), dim3(nblk, g.B), dim3(TPB), 0, st, g,
                            mat_id, mat, H, mode, T(c), r, dinv, zf, p_old, p_new, q, rz_part,
                            rz_stride, rz_n, rr_part, rr_stride, rr_n, partials, d, iter);
     return hipGetLastError();
@@ -577,11 +640,11 @@ hipError_t launch_pcg_matvec_dir(const Geom& g, const uint16_t* mat_id, const Ma
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_pcg_update(long long N, PcgDev* d, T* x, T* r,
                                                     const T* p, const T* q, const T* dinv,
-                                                    double* partials, int k) {
+                                                    double* partials, int n_pq, int k) {
     const int b = blockIdx.y;
     if (d[b].conv <= k) return;
     double pq[1];
-    block_sum_all<1>(pslot(partials, b, 0), 0, gridDim.x, pq);
+    block_sum_all<1>(pslot(partials, b, 0), 0, n_pq, pq);
     if (!(pq[0] > 0.0) || !isfinite(pq[0])) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             d[b].status = 2;
@@ -607,9 +670,10 @@ __global__ void __launch_bounds__(TPB) k_pcg_update(long long N, PcgDev* d, T* x
 
 template <typename T>
 hipError_t launch_pcg_update(const Geom& g, PcgDev* d, T* x, T* r, const T* p, const T* q,
-                             const T* dinv, double* partials, int nred, int iter, hipStream_t st) {
+                             const T* dinv, double* partials, int n_pq, int nred, int iter,
+                             hipStream_t st) {
     hipLaunchKernelGGL((k_pcg_update<T>), dim3(nred, g.B), dim3(TPB), 0, st, g.N, d, x, r, p, q,
-                       dinv, partials, iter);
+                       dinv, partials, n_pq, iter);
     return hipGetLastError();
 }
 
@@ -1022,7 +1086,7 @@ hipError_t launch_zero_int(int* p, int n, hipStream_t st) {
     template hipError_t launch_pcg_start<T>(const Geom&, const T*, const T*, const T*, T*,         \
                                             double*, int, const int*, hipStream_t);                \
     template hipError_t launch_pcg_update<T>(const Geom&, PcgDev*, T*, T*, const T*, const T*,     \
-                                             const T*, double*, int, int, hipStream_t);            \
+                                             const T*, double*, int, int, int, hipStream_t);       \
     template hipError_t launch_pcg_matvec_dir<T>(const Geom&, const uint16_t*, const MatEntry<T>*, \
                                                  const T*, int, double, int, const T*, const T*,   \
                                                  const T*, const T*, T*, T*, const double*,        \

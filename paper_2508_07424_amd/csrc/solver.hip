@@ -275,6 +275,7 @@ struct Solver : SolverBase {
     int thr_x1 = 256, thr_y1 = 256, thr_z1 = 256;
     size_t lds_x1 = 0, lds_y1 = 0, lds_z1 = 0;
     int nred = 1;
+    int nmv = 1;                     // blocks per RVE of the damage direction + operator step
     hipStream_t st;
     int load_axis = 1;
     void* ws = nullptr;
@@ -512,6 +513,9 @@ struct Solver : SolverBase {
         Layout L;
         layout(c, g, nbx, L, this);
         nred = (int)std::min<long long>((g.N + 255) / 256, kRedBlocks);
+        // about eight voxels per thread: the per-block reduction of the
+        // previous step's partials is amortised over more voxels
+        nmv = (int)std::max<long long>(1, std::min<long long>(nred, (g.N + 2047) / 2048));
         one_comp_shape();
         int ax = 0;
         double best = -1;
@@ -753,7 +757,7 @@ struct Solver : SolverBase {
         a.pcg = pcg;
         a.pq_part = partials;
         a.pq_stride = (long long)kMaxVals * kRedBlocks;
-        a.pq_n = nred;
+        a.pq_n = nmv;
         a.iter = k;
         a.spec = spec;
         a.partials = ppA;
@@ -1020,9 +1024,10 @@ struct Solver : SolverBase {
                 T* pn = (kk & 1) ? pp : pp2;
                 HIPCHK(launch_pcg_matvec_dir<T>(g, mat_id, mat, Hc, mode, c, fft ? PRE_FFT : PRE_JACOBI,
                                                 pr, pdinv, pz, pcur, pn, pq, rzp, rzs, rzn, rrp, rrs,
-                                                rrn, partials, nred, pcg, kk, st));
+                                                rrn, partials, nmv, pcg, kk, st));
                 if (fft) CHK(precond_fft(XF_PCG, kk, u, pn));
-                else HIPCHK(launch_pcg_update<T>(g, pcg, u, pr, pn, pq, pdinv, partials, nred, kk, st));
+                else HIPCHK(launch_pcg_update<T>(g, pcg, u, pr, pn, pq, pdinv, partials, nmv, nred,
+                                                 kk, st));
                 return RVE_OK;
             }));
             k += chunk;
