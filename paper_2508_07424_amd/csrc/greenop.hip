@@ -126,22 +126,13 @@ __device__ __forceinline__ void freq_xy(const Geom& g, int kx, int ky, int kz, c
 }
 
 // Symbol of the damage preconditioner at frequency (kx, ky, kz):
-// 1 / (abar + bbar |d|^2), |d_j|^2 = 4 sin^2(pi k_j / N_j) / h^2 for the
-// forward differences of the damage operator (Sec. 4.1, Eq. 24 R2).
+// 1 / (abar + bbar |d|^2), |d|^2 the sum over the axes of the tabulated
+// |d_j(k_j)|^2 = 4 sin^2(pi k_j / N_j) / h^2 of the forward differences of the
+// damage operator (Sec. 4.1, Eq. 24 R2).
 template <typename T>
-__device__ __forceinline__ T sinpi_t(T v);
-template <>
-__device__ __forceinline__ double sinpi_t<double>(double v) { return sinpi(v); }
-template <>
-__device__ __forceinline__ float sinpi_t<float>(float v) { return sinpif(v); }
-
-template <typename T>
-__device__ __forceinline__ T precond_symbol(const Geom& g, int kx, int ky, int kz, double abar,
-                                            double bbar) {
-    const T sx = sinpi_t<T>(T(kx) / T(g.nx));
-    const T sy = sinpi_t<T>(T(ky) / T(g.ny));
-    const T sz = g.dim == 3 ? sinpi_t<T>(T(kz) / T(g.nz)) : T(0);
-    const T d2 = T(4.0 / (g.h * g.h)) * (sx * sx + sy * sy + sz * sz);
+__device__ __forceinline__ T precond_symbol(const Geom& g, const T* dsq, int kx, int ky, int kz,
+                                            double abar, double bbar) {
+    const T d2 = dsq[kx] + dsq[g.nx + ky] + (g.dim == 3 ? dsq[g.nx + g.ny + kz] : T(0));
     return T(1) / (T(abar) + T(bbar) * d2);
 }
 
@@ -523,7 +514,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
                 const int q = e / Na, j = e - q * Na, tl = q & (TL - 1), c = q >> lgt;
                 const long long L = L0 + tl;
                 if (L >= nlines) continue;
-                const T m = precond_symbol<T>(g, (int)(L / nz), j, (int)(L % nz), abar, bbar);
+                const T m = precond_symbol<T>(g, a.dsq, (int)(L / nz), j, (int)(L % nz), abar, bbar);
                 cplx<T>& v = buf[(c * TL + tl) * LS + lp(j)];
                 v.x *= m;
                 v.y *= m;
@@ -590,7 +581,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
             for (int e = threadIdx.x; e < W * Na; e += blockDim.x) {
                 const int tl = e & (TL - 1), q = e >> lgt, j = q / S, c = q - j * S;
                 if (y0 + tl >= ny) continue;
-                const T m = precond_symbol<T>(g, kx, y0 + tl, j, abar, bbar);
+                const T m = precond_symbol<T>(g, a.dsq, kx, y0 + tl, j, abar, bbar);
                 cplx<T>& v = buf[(c * TL + tl) * LS + lp(j)];
                 v.x *= m;
                 v.y *= m;

@@ -103,6 +103,7 @@ struct AxisArgs {
     cplx<T>* spec;
     const CgDev* cg;     // skip RVE b when cg[b].conv <= iter
     const PcgDev* pcg;   // or pcg[b].conv <= iter; AX_FWD_M_INV takes abar, bbar here
+    const T* dsq;        // AX_FWD_M_INV: |d_j(k)|^2 of x, y, z at offsets 0, n_x, n_x + n_y
     int iter;
     const int* active;   // or when active && !active[b]
     int contiguous;      // 1: y lines (stride 1); 0: z lines (stride n_y)

@@ -288,6 +288,7 @@ struct Solver : SolverBase {
     T *aF, *aG;                     // Anderson ring buffers: kHist slots of B*N
     cplx<T>* spec;
     cplx<T>* tw;
+    T* dsq;                         // |d_j(k)|^2 per axis (damage preconditioner symbol)
     uint16_t* mat_id;
     MatEntry<T>* mat;
     double *partials, *cgpA, *cgpB, *cgpC, *ppA, *ppB, *sums, *dE, *dgamma;
@@ -338,6 +339,7 @@ struct Solver : SolverBase {
         const size_t ox = L.off(sN), oxc = L.off(sN), orr = L.off(sN), op = L.off(sN);
         const size_t ospec = L.off(sizeof(cplx<T>) * g.s * g.Nspec * B);
         const size_t otw = L.off(sizeof(cplx<T>) * (g.nx + g.ny + g.nz));
+        const size_t odsq = L.off(sizeof(T) * (g.nx + g.ny + g.nz));
         const size_t omid = L.off(sizeof(uint16_t) * g.N * B);
         const size_t omat = L.off(sizeof(MatEntry<T>) * (size_t)g.mstride * B);
         const size_t opart = L.off(sizeof(double) * kMaxVals * kRedBlocks * B);
@@ -373,6 +375,7 @@ struct Solver : SolverBase {
             s->p = (T*)(base + op);
             s->spec = (cplx<T>*)(base + ospec);
             s->tw = (cplx<T>*)(base + otw);
+            s->dsq = (T*)(base + odsq);
             s->mat_id = (uint16_t*)(base + omid);
             s->mat = (MatEntry<T>*)(base + omat);
             s->partials = (double*)(base + opart);
@@ -576,6 +579,16 @@ struct Solver : SolverBase {
         ply.tw_off = g.nx;
         plz.tw_off = g.nx + g.ny;
         HIPCHK(hipMemcpyAsync(tw, t.data(), t.size() * sizeof(cplx<T>), hipMemcpyHostToDevice, st));
+        // squared symbols of the forward differences, |d(k)|^2 = 4 sin^2(pi k / N) / h^2,
+        // per axis at the same offsets
+        std::vector<T> d2;
+        for (int N : {g.nx, g.ny, g.nz}) {
+            for (int k = 0; k < N; ++k) {
+                const long double sn = std::sin(3.141592653589793238462643383279502884L * k / N);
+                d2.push_back(T(4.0L * sn * sn / ((long double)g.h * g.h)));
+            }
+        }
+        HIPCHK(hipMemcpyAsync(dsq, d2.data(), d2.size() * sizeof(T), hipMemcpyHostToDevice, st));
         // every slot starts with a valid (zero) material index and table
         HIPCHK(hipMemsetAsync(mat_id, 0, sizeof(uint16_t) * g.N * B, st));
         HIPCHK(hipMemsetAsync(mat, 0, sizeof(MatEntry<T>) * (size_t)g.mstride * B, st));
@@ -773,6 +786,7 @@ struct Solver : SolverBase {
         y.iter = k;
         y.pl = ply;
         y.tw = tw + ply.tw_off;
+        y.dsq = dsq;
         y.contiguous = 1;
         y.lines = tly1;
         y.threads = thr_y1;
