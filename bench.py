@@ -324,7 +324,8 @@ def main():
                    "rve_steps_per_s": round(args.batch * args.steps / sec, 3),
                    "greenops_per_rve_step": round(greenops / (args.batch * args.steps) / rve.N, 1),
                    "launch_shape": {"x_rows_per_block": shape[0], "y_lines_per_block": shape[1],
-                                    "z_columns_per_tile": shape[2]},
+                                    "z_columns_per_tile": shape[2],
+                                    "krylov_vectors_nontemporal": shape[3]},
                    "operator_voxel_iter_per_s": round(rve.N * args.batch / op_s, 1)},
         "roofline": roof,
     }

@@ -257,13 +257,16 @@ int rve_profile_pass(rve_handle h, int pass, int repeat, double* bytes_per_launc
 
 /* Autotuner of the launch shapes of the Green operator's passes (rows per
  * block of the x passes, lines per block of the y pass, y columns per tile
- * of the 3D z pass): times every feasible shape's CG-mode passes `repeat`
- * times on the handle's own slots (at least one slot must be set) and keeps
- * the fastest for the handle.  The choice is cached for the process per
- * (grid, batch, precision): later handles of the same kind take it without
- * timing.  shape_out (may be NULL) receives the three values.  Results of
- * the solver do not depend on the shape beyond the summation order of the
- * per-block partial sums. */
+ * of the 3D z pass) and of the streaming policy of the Krylov x passes
+ * (non-temporal loads and stores of r, p, x, which leave the last-level
+ * cache to the spectrum when the batch's vectors do not fit it): times every
+ * feasible choice's CG-mode passes `repeat` times on the handle's own slots
+ * (at least one slot must be set) and keeps the fastest for the handle.  The
+ * choice is cached for the process per (grid, batch, precision): later
+ * handles of the same kind take it without timing.  shape_out (may be NULL)
+ * receives four values: rows, lines, columns, and 1 if the vectors are
+ * streamed non-temporally (else 0).  Results of the solver do not depend on
+ * the choice beyond the summation order of the per-block partial sums. */
 int rve_autotune(rve_handle h, int repeat, int* shape_out);
 
 /* Message of the last error of h (or of the calling thread when h is NULL,

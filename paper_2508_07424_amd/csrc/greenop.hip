@@ -147,6 +147,20 @@ __device__ __forceinline__ int line_len(const AxisPlan& pl) {
 // Global loads each thread keeps in flight in the gather loops of the passes.
 constexpr int kLd = 4;
 
+// Loads and stores of the voxel vectors that a pass streams once: with NT,
+// non-temporal (the lines are not kept in the caches, which leaves the
+// last-level cache to the transposed spectrum that the next pass reads).
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_s(const T* p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_s(T* p, T v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 
 // The fixed-size FFTs read their twiddles from an LDS table at the start of
 // the dynamic LDS (global twiddle loads inside the butterflies would each
@@ -192,7 +206,7 @@ __device__ __forceinline__ int xcd_group(int bx, int n) {
 // x-forward pass
 // ---------------------------------------------------------------------------
 
-template <typename T, int S, int MODE, typename F>
+template <typename T, int S, int MODE, typename F, bool NT>
 __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* const twl = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -316,24 +330,24 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
             ix[u] = idx;
             if constexpr (PCG) {
                 const long long o = so + idx;
-                in0[u][0] = a.r[o];
+                in0[u][0] = ld_s<NT>(a.r + o);
                 in4[u] = a.sc[o];
                 if constexpr (MODE == XF_PCG) {
-                    in1[u][0] = a.x[o];
-                    in2[u][0] = a.pd[o];
-                    in3[u] = a.q[o];
+                    in1[u][0] = ld_s<NT>(a.x + o);
+                    in2[u][0] = ld_s<NT>(a.pd + o);
+                    in3[u] = ld_s<NT>(a.q + o);
                 }
             } else {
                 mv[u] = mid[idx];
-                ph[u] = phi[idx];
+                ph[u] = ld_s<NT>(phi + idx);
 #pragma unroll
                 for (int c = 0; c < S; ++c) {
                     const long long o = fo + c * N + idx;
                     if constexpr (CGM) {
-                        in0[u][c] = a.r[o];
+                        in0[u][c] = ld_s<NT>(a.r + o);
                         if (!first) {
-                            in1[u][c] = a.p[o];
-                            in2[u][c] = a.x[o];
+                            in1[u][c] = ld_s<NT>(a.p + o);
+                            in2[u][c] = ld_s<NT>(a.x + o);
                         }
                     } else {
                         in0[u][c] = a.eps ? a.eps[o] : T(0);
@@ -352,19 +366,19 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
                 // damage PCG: x += alpha p, r -= alpha q; transform sc * r
                 if constexpr (MODE == XF_PCG) {
                     const long long o = so + idx;
-                    a.x[o] = in1[u][0] + alpha * in2[u][0];
+                    st_s<NT>(a.x + o, in1[u][0] + alpha * in2[u][0]);
                     in0[u][0] -= alpha * in3[u];
-                    a.r[o] = in0[u][0];
+                    st_s<NT>(a.r + o, in0[u][0]);
                 }
             } else if constexpr (CGM) {
 #pragma unroll
                 for (int c = 0; c < S; ++c) {
                     const long long o = fo + c * N + idx;
                     if (!first) {
-                        a.x[o] = in2[u][c] + alpha_x * in1[u][c];
+                        st_s<NT>(a.x + o, in2[u][c] + alpha_x * in1[u][c]);
                         in0[u][c] = in0[u][c] + beta * in1[u][c];
                     }
-                    a.p[o] = in0[u][c];
+                    st_s<NT>(a.p + o, in0[u][c]);
                 }
             } else {
 #pragma unroll
@@ -459,7 +473,8 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
 // axis pass: forward, [projection], inverse along y (contiguous lines) or z
 // ---------------------------------------------------------------------------
 
-template <typename T, int S, int MODE, typename F>
+// (NT is unused: the axis passes touch only the spectrum.)
+template <typename T, int S, int MODE, typename F, bool NT>
 __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* const twl = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -618,7 +633,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
 // x-inverse pass
 // ---------------------------------------------------------------------------
 
-template <typename T, int S, int MODE, typename F>
+template <typename T, int S, int MODE, typename F, bool NT>
 __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* const twl = reinterpret_cast<cplx<T>*>(smem_raw);
@@ -715,7 +730,7 @@ __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
 #pragma unroll
                 for (int c = 0; c < S; ++c) {
                     const long long o = fo + c * g.N + idx;
-                    l0[u][c] = a.r[o];
+                    l0[u][c] = ld_s<NT>(a.r + o);
                     if constexpr (MODE == XI_PCG) l1[u][c] = a.sc[o];
                 }
             }
@@ -742,7 +757,7 @@ __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
                     part += double(l0[u][c]) * double(zz);
                 } else {  // XI_CG (x takes alpha p in the next x-forward pass)
                     const T rn = l0[u][c] - alpha * q;
-                    a.r[o] = rn;
+                    st_s<NT>(a.r + o, rn);
                     part += double(rn) * double(rn);
                 }
             }
@@ -762,52 +777,59 @@ static hipError_t launch_k(K kern, dim3 grid, size_t lds, hipStream_t st, const 
     return hipGetLastError();
 }
 
-// Instantiate kernel template KT<T, S, MODE, F> for the FFT policy of the
-// plan: fixed power-of-two length, else the runtime plan with maxb.
-#define MIRVE_DISPATCH(KT, T, S, MODE, pl, maxb, grid, lds, st, a)                         \
-    do {                                                                                    \
-        switch ((pl).fastN) {                                                               \
-            case 16: return launch_k(KT<T, S, MODE, FastFFT<16>>, grid, lds, st, a);        \
-            case 32: return launch_k(KT<T, S, MODE, FastFFT<32>>, grid, lds, st, a);        \
-            case 64: return launch_k(KT<T, S, MODE, FastFFT<64>>, grid, lds, st, a);        \
-            case 128: return launch_k(KT<T, S, MODE, FastFFT<128>>, grid, lds, st, a);      \
-            case 256: return launch_k(KT<T, S, MODE, FastFFT<256>>, grid, lds, st, a);      \
-            case 512: return launch_k(KT<T, S, MODE, FastFFT<512>>, grid, lds, st, a);      \
-            case 1024: return launch_k(KT<T, S, MODE, FastFFT<1024>>, grid, lds, st, a);    \
-            default: break;                                                                 \
-        }                                                                                   \
-        switch (maxb) {                                                                     \
-            case 1: return launch_k(KT<T, S, MODE, GenericFFT<1>>, grid, lds, st, a);       \
-            case 2: return launch_k(KT<T, S, MODE, GenericFFT<2>>, grid, lds, st, a);       \
-            case 4: return launch_k(KT<T, S, MODE, GenericFFT<4>>, grid, lds, st, a);       \
-            default: return launch_k(KT<T, S, MODE, GenericFFT<8>>, grid, lds, st, a);      \
-        }                                                                                   \
+// Instantiate kernel template KT<T, S, MODE, F, NTV> for the FFT policy of
+// the plan: fixed power-of-two length, else the runtime plan with maxb.
+#define MIRVE_DISPATCH(KT, T, S, MODE, NTV, pl, maxb, grid, lds, st, a)                         \
+    do {                                                                                         \
+        switch ((pl).fastN) {                                                                    \
+            case 16: return launch_k(KT<T, S, MODE, FastFFT<16>, NTV>, grid, lds, st, a);        \
+            case 32: return launch_k(KT<T, S, MODE, FastFFT<32>, NTV>, grid, lds, st, a);        \
+            case 64: return launch_k(KT<T, S, MODE, FastFFT<64>, NTV>, grid, lds, st, a);        \
+            case 128: return launch_k(KT<T, S, MODE, FastFFT<128>, NTV>, grid, lds, st, a);      \
+            case 256: return launch_k(KT<T, S, MODE, FastFFT<256>, NTV>, grid, lds, st, a);      \
+            case 512: return launch_k(KT<T, S, MODE, FastFFT<512>, NTV>, grid, lds, st, a);      \
+            case 1024: return launch_k(KT<T, S, MODE, FastFFT<1024>, NTV>, grid, lds, st, a);    \
+            default: break;                                                                      \
+        }                                                                                        \
+        switch (maxb) {                                                                          \
+            case 1: return launch_k(KT<T, S, MODE, GenericFFT<1>, NTV>, grid, lds, st, a);       \
+            case 2: return launch_k(KT<T, S, MODE, GenericFFT<2>, NTV>, grid, lds, st, a);       \
+            case 4: return launch_k(KT<T, S, MODE, GenericFFT<4>, NTV>, grid, lds, st, a);       \
+            default: return launch_k(KT<T, S, MODE, GenericFFT<8>, NTV>, grid, lds, st, a);      \
+        }                                                                                        \
     } while (0)
 
-template <typename T, int S, int MODE>
+template <typename T, int S, int MODE, bool NT = false>
 static hipError_t launch_xfwd_s(const XfwdArgs<T>& a, int maxb, size_t lds, hipStream_t st) {
     const dim3 grid(a.nblocks, a.g.B);
-    MIRVE_DISPATCH(k_xfwd, T, S, MODE, a.pl, maxb, grid, lds, st, a);
+    MIRVE_DISPATCH(k_xfwd, T, S, MODE, NT, a.pl, maxb, grid, lds, st, a);
+}
+
+// Krylov modes with a.nt set stream their voxel vectors non-temporally.
+template <typename T, int S, int MODE>
+static hipError_t launch_xfwd_k(const XfwdArgs<T>& a, int maxb, size_t lds, hipStream_t st) {
+    return a.nt ? launch_xfwd_s<T, S, MODE, true>(a, maxb, lds, st)
+                : launch_xfwd_s<T, S, MODE, false>(a, maxb, lds, st);
 }
 
 template <typename T>
 hipError_t launch_xfwd(const XfwdArgs<T>& a, int mode, int maxb, size_t lds, hipStream_t st) {
-    if (mode == XF_PCG) return launch_xfwd_s<T, 1, XF_PCG>(a, maxb, lds, st);
-    if (mode == XF_PCG0) return launch_xfwd_s<T, 1, XF_PCG0>(a, maxb, lds, st);
+    if (mode == XF_PCG) return launch_xfwd_k<T, 1, XF_PCG>(a, maxb, lds, st);
+    if (mode == XF_PCG0) return launch_xfwd_k<T, 1, XF_PCG0>(a, maxb, lds, st);
     if (a.g.s == 3) {
         switch (mode) {
             case XF_GREEN: return launch_xfwd_s<T, 3, XF_GREEN>(a, maxb, lds, st);
-            case XF_CG: return launch_xfwd_s<T, 3, XF_CG>(a, maxb, lds, st);
+            case XF_CG: return launch_xfwd_k<T, 3, XF_CG>(a, maxb, lds, st);
             case XF_SPLIT: return launch_xfwd_s<T, 3, XF_SPLIT>(a, maxb, lds, st);
-            case XF_CG_T: return launch_xfwd_s<T, 3, XF_CG_T>(a, maxb, lds, st);
+            case XF_CG_T: return launch_xfwd_k<T, 3, XF_CG_T>(a, maxb, lds, st);
             default: return hipErrorInvalidValue;
         }
     }
     switch (mode) {
         case XF_GREEN: return launch_xfwd_s<T, 6, XF_GREEN>(a, maxb, lds, st);
-        case XF_CG: return launch_xfwd_s<T, 6, XF_CG>(a, maxb, lds, st);
+        case XF_CG: return launch_xfwd_k<T, 6, XF_CG>(a, maxb, lds, st);
         case XF_SPLIT: return launch_xfwd_s<T, 6, XF_SPLIT>(a, maxb, lds, st);
-        case XF_CG_T: return launch_xfwd_s<T, 6, XF_CG_T>(a, maxb, lds, st);
+        case XF_CG_T: return launch_xfwd_k<T, 6, XF_CG_T>(a, maxb, lds, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -815,7 +837,7 @@ hipError_t launch_xfwd(const XfwdArgs<T>& a, int mode, int maxb, size_t lds, hip
 template <typename T, int S, int MODE>
 static hipError_t launch_axis_s(const AxisArgs<T>& a, int maxb, dim3 grid, size_t lds,
                                 hipStream_t st) {
-    MIRVE_DISPATCH(k_axis, T, S, MODE, a.pl, maxb, grid, lds, st, a);
+    MIRVE_DISPATCH(k_axis, T, S, MODE, false, a.pl, maxb, grid, lds, st, a);
 }
 
 // The damage preconditioner (a.pcg set) transforms one scalar field.
@@ -846,19 +868,25 @@ hipError_t launch_axis(const AxisArgs<T>& a, int mode, int maxb, dim3 grid, size
     }
 }
 
-template <typename T, int S, int MODE>
+template <typename T, int S, int MODE, bool NT = false>
 static hipError_t launch_xinv_s(const XinvArgs<T>& a, int maxb, size_t lds, hipStream_t st) {
     const dim3 grid(a.nblocks, a.g.B);
-    MIRVE_DISPATCH(k_xinv, T, S, MODE, a.pl, maxb, grid, lds, st, a);
+    MIRVE_DISPATCH(k_xinv, T, S, MODE, NT, a.pl, maxb, grid, lds, st, a);
+}
+
+template <typename T, int S, int MODE>
+static hipError_t launch_xinv_k(const XinvArgs<T>& a, int maxb, size_t lds, hipStream_t st) {
+    return a.nt ? launch_xinv_s<T, S, MODE, true>(a, maxb, lds, st)
+                : launch_xinv_s<T, S, MODE, false>(a, maxb, lds, st);
 }
 
 template <typename T>
 hipError_t launch_xinv(const XinvArgs<T>& a, int mode, int maxb, size_t lds, hipStream_t st) {
-    if (mode == XI_PCG) return launch_xinv_s<T, 1, XI_PCG>(a, maxb, lds, st);
+    if (mode == XI_PCG) return launch_xinv_k<T, 1, XI_PCG>(a, maxb, lds, st);
     if (a.g.s == 3)
-        return mode == XI_CG ? launch_xinv_s<T, 3, XI_CG>(a, maxb, lds, st)
+        return mode == XI_CG ? launch_xinv_k<T, 3, XI_CG>(a, maxb, lds, st)
                              : launch_xinv_s<T, 3, XI_STORE>(a, maxb, lds, st);
-    return mode == XI_CG ? launch_xinv_s<T, 6, XI_CG>(a, maxb, lds, st)
+    return mode == XI_CG ? launch_xinv_k<T, 6, XI_CG>(a, maxb, lds, st)
                          : launch_xinv_s<T, 6, XI_STORE>(a, maxb, lds, st);
 }
 

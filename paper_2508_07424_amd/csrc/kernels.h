@@ -93,6 +93,7 @@ struct XfwdArgs {
     int rows_per_block;
     int nblocks;
     int threads;         // block size (multiple of 64, <= 256)
+    int nt;              // Krylov modes: stream the voxel vectors with non-temporal loads / stores
 };
 
 template <typename T>
@@ -130,6 +131,7 @@ struct XinvArgs {
     int rows_per_block;
     int nblocks;
     int threads;         // block size (multiple of 64, <= 256)
+    int nt;              // Krylov modes: stream the voxel vectors with non-temporal loads / stores
 };
 
 template <typename T>

@@ -275,6 +275,7 @@ struct Solver : SolverBase {
     int thr_x1 = 256, thr_y1 = 256, thr_z1 = 256;
     size_t lds_x1 = 0, lds_y1 = 0, lds_z1 = 0;
     int nred = 1;
+    int stream_nt = 0;               // Krylov passes stream r, p, x non-temporally
     int nmv = 1;                     // blocks per RVE of the damage direction + operator step
     hipStream_t st;
     int load_axis = 1;
@@ -406,6 +407,7 @@ struct Solver : SolverBase {
     // pass, y columns per tile of the z pass (0: the default heuristic).
     struct Shape {
         int rb = 0, tly = 0, tlz = 0;
+        int nt = -1;                 // streaming policy of the Krylov passes (-1: keep)
     };
 
     static bool make_geom(const rve_config& c, Geom& g, AxisPlan& px, AxisPlan& py, AxisPlan& pz,
@@ -519,6 +521,10 @@ struct Solver : SolverBase {
         // about eight voxels per thread: the per-block reduction of the
         // previous step's partials is amortised over more voxels
         nmv = (int)std::max<long long>(1, std::min<long long>(nred, (g.N + 2047) / 2048));
+        // stream the Krylov vectors past the caches when r, p and x alone
+        // exceed about three quarters of the 256 MB last-level cache (the
+        // autotuner times both policies)
+        stream_nt = 3.0 * g.s * (double)g.N * g.B * sizeof(T) > 192.0 * (1 << 20) ? 1 : 0;
         one_comp_shape();
         int ax = 0;
         double best = -1;
@@ -686,6 +692,7 @@ struct Solver : SolverBase {
         a.spec = spec;
         a.partials = part;
         if (mode == XF_CG || mode == XF_CG_T) {
+            a.nt = stream_nt;
             a.cg = cg;
             a.x = xsol ? xsol : x;
             a.rr_part = cgpB;
@@ -741,6 +748,7 @@ struct Solver : SolverBase {
         a.out = out;
         a.r = r;
         a.cg = mode == XI_CG ? cg : nullptr;
+        a.nt = mode == XI_CG ? stream_nt : 0;
         a.pAp_part = pap_slot(iter);
         a.iter = iter;
         a.active = mask;
@@ -777,6 +785,7 @@ struct Solver : SolverBase {
         a.rows_per_block = RB1;
         a.nblocks = nbx1;
         a.threads = thr_x1;
+        a.nt = stream_nt;
         HIPCHK(launch_xfwd<T>(a, xmode, maxb_x, lds_x1, st));
         AxisArgs<T> y;
         std::memset(&y, 0, sizeof(y));
@@ -819,6 +828,7 @@ struct Solver : SolverBase {
         v.rows_per_block = RB1;
         v.nblocks = nbx1;
         v.threads = thr_x1;
+        v.nt = stream_nt;
         HIPCHK(launch_xinv<T>(v, XI_PCG, maxb_x, lds_x1, st));
         return RVE_OK;
     }
@@ -1787,6 +1797,7 @@ struct Solver : SolverBase {
         tly = ty; maxb_y = my; lds_y = ly;
         tlz = tz; maxb_z = mz; lds_z = lz;
         thr_x = t1; thr_y = t2; thr_z = t3;
+        if (sh.nt >= 0) stream_nt = sh.nt ? 1 : 0;
         one_comp_shape();
         clear_graphs();            // captured launches carry the old shape
         return RVE_OK;
@@ -1809,7 +1820,7 @@ struct Solver : SolverBase {
             auto it = tune_cache().find(key);
             if (it != tune_cache().end()) {
                 CHK(set_shape(it->second));
-                if (out) { out[0] = RB; out[1] = tly; out[2] = tlz; }
+                if (out) { out[0] = RB; out[1] = tly; out[2] = tlz; out[3] = stream_nt; }
                 return RVE_OK;
             }
         }
@@ -1831,6 +1842,7 @@ struct Solver : SolverBase {
         best.rb = RB;
         best.tly = tly;
         best.tlz = g.dim == 3 ? tlz : 0;
+        best.nt = stream_nt;
         double tb = INFINITY;
         for (int rb : {2, 4, 8, 16, 32}) {
             Shape sh = best;
@@ -1863,6 +1875,17 @@ struct Solver : SolverBase {
                 if (a < tb) { tb = a; best.tlz = t; }
             }
         }
+        // streaming policy of the Krylov x passes at the chosen shape
+        tb = INFINITY;
+        for (int nt : {0, 1}) {
+            Shape sh = best;
+            sh.nt = nt;
+            if (set_shape(sh) != RVE_OK) continue;
+            double a = 0, c = 0;
+            CHK(timed(3, a));
+            CHK(timed(4, c));
+            if (a + c < tb) { tb = a + c; best.nt = nt; }
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         CHK(set_shape(best));
@@ -1870,7 +1893,7 @@ struct Solver : SolverBase {
             std::lock_guard<std::mutex> lk(tune_mutex());
             tune_cache()[key] = best;
         }
-        if (out) { out[0] = RB; out[1] = tly; out[2] = tlz; }
+        if (out) { out[0] = RB; out[1] = tly; out[2] = tlz; out[3] = stream_nt; }
         return RVE_OK;
     }
     static std::map<std::string, Shape>& tune_cache() {

@@ -319,8 +319,9 @@ class Rve:
 
     def rve_autotune(self, repeat=20):
         """Pick the fastest launch shapes for this handle; returns
-        (rows per x block, y lines per block, z columns per tile)."""
-        out = (C.c_int * 3)()
+        (rows per x block, y lines per block, z columns per tile,
+        1 if the Krylov vectors are streamed non-temporally)."""
+        out = (C.c_int * 4)()
         self._chk(lib.rve_autotune(self.h, int(repeat), out))
         return tuple(out)
 
