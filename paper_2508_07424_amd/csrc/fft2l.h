@@ -110,12 +110,12 @@ __host__ __device__ constexpr int split_max(int N) {
 }
 
 // In-place DFT of nlines lines (element e of line l at buf[l * LS + lp(e)]),
-// natural order in and out.  tw holds the phase-A twiddles in LDS as an
-// N1 x N2 table, tw[k1 * N2 + t] = exp(-2 pi i t k1 / N), so that the
-// threads of a column group read consecutive entries (no bank conflicts).
-template <typename T, int N>
-__device__ __forceinline__ void fft_lines(cplx<T>* buf, int nlines, int LS,
-                                          const cplx<T>* __restrict__ tw, bool inv) {
+// natural order in and out.  tw(k1, t) = exp(-2 pi i t k1 / N) is the
+// twiddle of column t and output k1 of the first phase: an LDS table
+// (LdsTw) or the calling thread's own values in registers (RegTw).
+template <typename T, int N, typename TW>
+__device__ __forceinline__ void fft_lines_tw(cplx<T>* buf, int nlines, int LS, const TW& tw,
+                                             bool inv) {
     constexpr int N1 = Split<N>::N1, N2 = Split<N>::N2;
     const int tid = threadIdx.x;
     {   // phase A: columns t < N2
@@ -129,7 +129,7 @@ __device__ __forceinline__ void fft_lines(cplx<T>* buf, int nlines, int LS,
             RegDFT<T, N1>::run(v, inv);
 #pragma unroll
             for (int k1 = 1; k1 < N1; ++k1) {
-                cplx<T> w = tw[k1 * N2 + t];
+                cplx<T> w = tw(k1, t);
                 if (inv) w.y = -w.y;
                 v[k1] = cmul(v[k1], w);
             }
@@ -160,6 +160,41 @@ __device__ __forceinline__ void fft_lines(cplx<T>* buf, int nlines, int LS,
     }
 }
 
+// Phase-A twiddles from an LDS table laid out as N1 x N2,
+// tw[k1 * N2 + t], so that the threads of a column group read consecutive
+// entries (no bank conflicts).
+template <typename T, int N>
+struct LdsTw {
+    const cplx<T>* tw;
+    __device__ __forceinline__ cplx<T> operator()(int k1, int t) const {
+        return tw[k1 * Split<N>::N2 + t];
+    }
+};
+
+// Phase-A twiddles of the calling thread (column t = threadIdx.x mod N2)
+// held in registers: w[k1] = exp(-2 pi i t k1 / N).
+template <typename T, int N>
+struct RegTw {
+    const cplx<T> (&w)[Split<N>::N1];
+    __device__ __forceinline__ cplx<T> operator()(int k1, int) const { return w[k1]; }
+};
+
+// Loads the calling thread's phase-A twiddles from the global table
+// tw[m] = exp(-2 pi i m / N).
+template <typename T, int N>
+__device__ __forceinline__ void load_reg_twiddles(const cplx<T>* tw, cplx<T> (&w)[Split<N>::N1]) {
+    const int t = threadIdx.x % Split<N>::N2;
+    w[0] = {T(1), T(0)};
+#pragma unroll
+    for (int k1 = 1; k1 < Split<N>::N1; ++k1) w[k1] = tw[t * k1];
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void fft_lines(cplx<T>* buf, int nlines, int LS,
+                                          const cplx<T>* __restrict__ tw, bool inv) {
+    fft_lines_tw<T, N>(buf, nlines, LS, LdsTw<T, N>{tw}, inv);
+}
+
 // Line-FFT policies of the kernels: a fixed power-of-two length, or the
 // runtime mixed-radix plan with MAXB butterflies per thread.
 template <int N_>
@@ -179,6 +214,27 @@ template <typename T, typename F>
 __device__ __forceinline__ void line_fft(cplx<T>* buf, int nlines, int LS, const AxisPlan& pl,
                                          const cplx<T>* __restrict__ tw, bool inv) {
     if constexpr (F::fast) fft_lines<T, F::N>(buf, nlines, LS, tw, inv);
+    else lds_fft<T, F::MAXB>(buf, nlines, LS, pl, tw, inv);
+}
+
+// Number of phase-A twiddles a thread holds in registers (1 for the runtime
+// plans, which read theirs from global memory).
+template <typename F, bool = F::fast>
+struct RegTwCount {
+    static constexpr int n = 1;
+};
+template <typename F>
+struct RegTwCount<F, true> {
+    static constexpr int n = Split<F::N>::N1;
+};
+
+// Line FFT with the fixed-size plans' twiddles in the calling thread's
+// registers (wr, from load_reg_twiddles); the runtime plans use tw.
+template <typename T, typename F>
+__device__ __forceinline__ void line_fft_rt(cplx<T>* buf, int nlines, int LS, const AxisPlan& pl,
+                                            const cplx<T> (&wr)[RegTwCount<F>::n],
+                                            const cplx<T>* __restrict__ tw, bool inv) {
+    if constexpr (F::fast) fft_lines_tw<T, F::N>(buf, nlines, LS, RegTw<T, F::N>{wr}, inv);
     else lds_fft<T, F::MAXB>(buf, nlines, LS, pl, tw, inv);
 }
 

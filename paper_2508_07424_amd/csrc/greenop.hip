@@ -170,6 +170,13 @@ __device__ __forceinline__ void st_s(T* p, T v) {
 template <typename F>
 __device__ __forceinline__ constexpr int tw_lds_len() { return F::fast ? F::N : 0; }
 
+// Axis passes of a fixed-size FFT in FP64 hold the phase-A twiddles in
+// registers instead of the LDS table (the host sizes their LDS to match).
+template <typename T, typename F>
+__device__ __forceinline__ constexpr bool axis_reg_twiddles() {
+    return F::fast && sizeof(T) == 8;
+}
+
 template <typename T, typename F>
 __device__ __forceinline__ void stage_twiddles(cplx<T>* twl, const cplx<T>* tw) {
     if constexpr (F::fast) {
@@ -473,13 +480,16 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
 // axis pass: forward, [projection], inverse along y (contiguous lines) or z
 // ---------------------------------------------------------------------------
 
-// (NT is unused: the axis passes touch only the spectrum.)
+// (NT is unused: the axis passes touch only the spectrum.)  The fixed-size
+// FFTs take their phase-A twiddles from registers in FP64, where LDS limits
+// the blocks per CU, and from the LDS table in FP32, where registers do.
 template <typename T, int S, int MODE, typename F, bool NT>
 __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
+    constexpr bool RT = axis_reg_twiddles<T, F>();
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* const twl = reinterpret_cast<cplx<T>*>(smem_raw);
-    cplx<T>* buf = twl + tw_lds_len<F>();
-    const cplx<T>* const twp = F::fast ? twl : a.tw;
+    cplx<T>* buf = twl + (RT ? 0 : tw_lds_len<F>());
+    const cplx<T>* const twp = (F::fast && !RT) ? twl : a.tw;
     const Geom& g = a.g;
     const int b = blockIdx.z;
     if (a.cg && a.cg[b].conv <= a.iter) return;
@@ -492,9 +502,15 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
     cplx<T>* sp = a.spec + (long long)b * S * g.Nspec;
     const bool inv_only = MODE == AX_INV;
     const T rN[3] = {T(1) / T(g.nx), T(1) / T(g.ny), T(1) / T(g.nz)};
-    stage_twiddles<T, F>(twl, a.tw);     // ordered by the barrier before the FFT
+    cplx<T> wr[RegTwCount<F>::n];
+    if constexpr (RT) load_reg_twiddles<T, F::N>(a.tw, wr);
+    else stage_twiddles<T, F>(twl, a.tw);     // ordered by the barrier before the FFT
 
     const int LS = lds_line(Na);
+    auto fft = [&](int nl, bool inv) {
+        if constexpr (RT) line_fft_rt<T, F>(buf, nl, LS, a.pl, wr, twp, inv);
+        else line_fft<T, F>(buf, nl, LS, a.pl, twp, inv);
+    };
     if (a.contiguous) {
         // lines L = kx * nz + z, element y; LDS line (c, tl)
         const long long nlines = (long long)g.nxh * nz;
@@ -522,7 +538,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
             }
         }
         __syncthreads();
-        line_fft<T, F>(buf, S * TL, LS, a.pl, twp, inv_only);
+        fft(S * TL, inv_only);
         if constexpr (MODE == AX_FWD_M_INV) {
             const double abar = a.pcg[b].abar, bbar = a.pcg[b].bbar;
             for (int e = threadIdx.x; e < S * TL * Na; e += blockDim.x) {
@@ -535,7 +551,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
                 v.y *= m;
             }
             __syncthreads();
-            line_fft<T, F>(buf, S * TL, LS, a.pl, twp, true);
+            fft(S * TL, true);
         }
         if constexpr (MODE == AX_FWD_P_INV) {
             for (int e = threadIdx.x; e < TL * Na; e += blockDim.x) {
@@ -554,7 +570,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
                 for (int c = 0; c < S; ++c) buf[(c * TL + tl) * LS + lp(j)] = v[c];
             }
             __syncthreads();
-            line_fft<T, F>(buf, S * TL, LS, a.pl, twp, true);
+            fft(S * TL, true);
         }
         for (int e = threadIdx.x; e < S * TL * Na; e += blockDim.x) {
             const int q = e / Na, j = e - q * Na, tl = q & (TL - 1), c = q >> lgt;
@@ -590,7 +606,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
             }
         }
         __syncthreads();
-        line_fft<T, F>(buf, W, LS, a.pl, twp, inv_only);
+        fft(W, inv_only);
         if constexpr (MODE == AX_FWD_M_INV) {
             const double abar = a.pcg[b].abar, bbar = a.pcg[b].bbar;
             for (int e = threadIdx.x; e < W * Na; e += blockDim.x) {
@@ -602,7 +618,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
                 v.y *= m;
             }
             __syncthreads();
-            line_fft<T, F>(buf, W, LS, a.pl, twp, true);
+            fft(W, true);
         }
         if constexpr (MODE == AX_FWD_P_INV) {
             for (int e = threadIdx.x; e < TL * Na; e += blockDim.x) {
@@ -619,7 +635,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
                 for (int c = 0; c < S; ++c) buf[(c * TL + tl) * LS + lp(j)] = v[c];
             }
             __syncthreads();
-            line_fft<T, F>(buf, W, LS, a.pl, twp, true);
+            fft(W, true);
         }
         for (int e = threadIdx.x; e < W * Na; e += blockDim.x) {
             const int tl = e & (TL - 1), q = e >> lgt, j = q / S, c = q - j * S;

@@ -499,7 +499,9 @@ __device__ __forceinline__ T zval(const T* r, const T* dinv, const T* zf, long l
 // three phases: (1) the independent loads (phase ids, history, z and the old
 // direction at the voxel and its 2 d neighbours), at clamped addresses so
 // that none waits for another; (2) the Gc of the phase ids; (3) arithmetic
-// and stores.  Returns the thread's p.q partial.
+// and stores.  U = 2: a larger U holds more values in flight per thread but
+// costs more in occupancy (measured slower at U = 4).  Returns the thread's
+// p.q partial.
 template <typename T, int PRE, int DIM, int U>
 __device__ __forceinline__ double matvec_dir_rounds(const Geom& g, const uint16_t* mid,
                                                     const MatEntry<T>* mt, const T* Hb, int mode,
@@ -610,7 +612,7 @@ __global__ void __launch_bounds__(TPB) k_pcg_matvec_dir(
     const T* zf = zf_a ? zf_a + so : nullptr;
     double part;
     if (g.dim == 2)
-        part = matvec_dir_rounds<T, PRE, 2, 4>(g, mid, mt, Hb, mode, c, r_a + so, dinv_a + so, zf,
+        part = matvec_dir_rounds<T, PRE, 2, 2>(g, mid, mt, Hb, mode, c, r_a + so, dinv_a + so, zf,
                                                po_a + so, beta, k == 0, pn_a + so, q_a + so);
     else
         part = matvec_dir_rounds<T, PRE, 3, 2>(g, mid, mt, Hb, mode, c, r_a + so, dinv_a + so, zf,

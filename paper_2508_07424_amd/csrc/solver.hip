@@ -402,6 +402,9 @@ struct Solver : SolverBase {
 
     // geometry and launch shapes from a configuration; false if unsupported
     static int threads_for(int n) { return std::min(256, ((n + 63) / 64) * 64); }
+    // LDS twiddle table of a fixed-size axis pass: FP32 only (FP64 axis
+    // passes hold their twiddles in registers)
+    static size_t axis_tw_bytes(int N) { return sizeof(T) == 8 ? 0 : (size_t)N * sizeof(cplx<T>); }
 
     // Launch shape: rows per block of the x passes, lines per block of the y
     // pass, y columns per tile of the z pass (0: the default heuristic).
@@ -470,7 +473,7 @@ struct Solver : SolverBase {
             for (int t = pow2_floor(std::max(1, want)); t >= 1; t /= 2) {
                 const size_t l = (size_t)g.s * t * lds_line(pl.N) * ce;
                 if (fast) {
-                    const size_t lt = l + (size_t)pl.N * ce;     // + LDS twiddles
+                    const size_t lt = l + axis_tw_bytes(pl.N);
                     if (lt <= kLdsCap && g.s * t * split_max(pl.N) <= 256) {
                         tl = t; mb = 1; lds = lt; pl.fastN = pl.N;
                         thr = threads_for(g.s * t * split_max(pl.N));
@@ -1770,10 +1773,10 @@ struct Solver : SolverBase {
             tl1 = std::max(tl1, 4);
             auto fits = [&](int t) {
                 return t <= cap && t * split_max(pl.N) <= 256 &&
-                       (size_t)t * lds_line(pl.N) * ce + (size_t)pl.N * ce <= kLdsCap;
+                       (size_t)t * lds_line(pl.N) * ce + axis_tw_bytes(pl.N) <= kLdsCap;
             };
             while (tl1 > 1 && !fits(tl1)) tl1 /= 2;
-            lds1 = (size_t)tl1 * lds_line(pl.N) * ce + (size_t)pl.N * ce;
+            lds1 = (size_t)tl1 * lds_line(pl.N) * ce + axis_tw_bytes(pl.N);
             thr1 = threads_for(tl1 * split_max(pl.N));
         };
         lines1(ply, tly, 1 << 20, lds_y, thr_y, tly1, lds_y1, thr_y1);
