@@ -170,10 +170,11 @@ __device__ __forceinline__ void st_s(T* p, T v) {
 template <typename F>
 __device__ __forceinline__ constexpr int tw_lds_len() { return F::fast ? F::N : 0; }
 
-// Axis passes of a fixed-size FFT in FP64 hold the phase-A twiddles in
-// registers instead of the LDS table (the host sizes their LDS to match).
+// Axis and x-inverse passes of a fixed-size FFT in FP64 hold the phase-A
+// twiddles in registers instead of the LDS table (the host sizes their LDS
+// to match).
 template <typename T, typename F>
-__device__ __forceinline__ constexpr bool axis_reg_twiddles() {
+__device__ __forceinline__ constexpr bool reg_twiddles() {
     return F::fast && sizeof(T) == 8;
 }
 
@@ -485,7 +486,7 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
 // the blocks per CU, and from the LDS table in FP32, where registers do.
 template <typename T, int S, int MODE, typename F, bool NT>
 __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
-    constexpr bool RT = axis_reg_twiddles<T, F>();
+    constexpr bool RT = reg_twiddles<T, F>();
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* const twl = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* buf = twl + (RT ? 0 : tw_lds_len<F>());
@@ -651,10 +652,11 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
 
 template <typename T, int S, int MODE, typename F, bool NT>
 __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
+    constexpr bool RT = reg_twiddles<T, F>();
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* const twl = reinterpret_cast<cplx<T>*>(smem_raw);
-    cplx<T>* buf = twl + tw_lds_len<F>();
-    const cplx<T>* const twp = F::fast ? twl : a.tw;
+    cplx<T>* buf = twl + (RT ? 0 : tw_lds_len<F>());
+    const cplx<T>* const twp = (F::fast && !RT) ? twl : a.tw;
     const Geom& g = a.g;
     const int b = blockIdx.y;
     if (MODE == XI_CG) {
@@ -688,7 +690,9 @@ __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
     const int LS = lds_line(nx);
     const cplx<T>* sp = a.spec + (long long)b * S * g.Nspec;
 
-    stage_twiddles<T, F>(twl, a.tw);     // ordered by the barrier before the FFT
+    cplx<T> wr[RegTwCount<F>::n];
+    if constexpr (RT) load_reg_twiddles<T, F::N>(a.tw, wr);
+    else stage_twiddles<T, F>(twl, a.tw);     // ordered by the barrier before the FFT
     // gather Z = A + iB from the transposed half spectra of the row pair,
     // kLd elements per thread in flight before their LDS writes
     const int gtot = S * npairs * nx;
@@ -726,7 +730,8 @@ __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
         }
     }
     __syncthreads();
-    line_fft<T, F>(buf, S * npairs, LS, a.pl, twp, true);
+    if constexpr (RT) line_fft_rt<T, F>(buf, S * npairs, LS, a.pl, wr, twp, true);
+    else line_fft<T, F>(buf, S * npairs, LS, a.pl, twp, true);
 
     const T scale = T(g.inv_N) * a.scale;
     const long long fo = (long long)b * S * g.N;

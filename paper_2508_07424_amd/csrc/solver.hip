@@ -405,6 +405,11 @@ struct Solver : SolverBase {
     // LDS twiddle table of a fixed-size axis pass: FP32 only (FP64 axis
     // passes hold their twiddles in registers)
     static size_t axis_tw_bytes(int N) { return sizeof(T) == 8 ? 0 : (size_t)N * sizeof(cplx<T>); }
+    // The x-inverse passes of a fixed-size FFT in FP64 hold their twiddles in
+    // registers too: the LDS table the x-forward passes need is not allocated.
+    size_t xinv_tw_saving() const {
+        return (sizeof(T) == 8 && plx.fastN) ? (size_t)g.nx * sizeof(cplx<T>) : 0;
+    }
 
     // Launch shape: rows per block of the x passes, lines per block of the y
     // pass, y columns per tile of the z pass (0: the default heuristic).
@@ -759,7 +764,7 @@ struct Solver : SolverBase {
         a.rows_per_block = RB;
         a.nblocks = nbx;
         a.threads = thr_x;
-        HIPCHK(launch_xinv<T>(a, mode, maxb_x, lds_x, st));
+        HIPCHK(launch_xinv<T>(a, mode, maxb_x, lds_x - xinv_tw_saving(), st));
         return RVE_OK;
     }
 
@@ -832,7 +837,7 @@ struct Solver : SolverBase {
         v.nblocks = nbx1;
         v.threads = thr_x1;
         v.nt = stream_nt;
-        HIPCHK(launch_xinv<T>(v, XI_PCG, maxb_x, lds_x1, st));
+        HIPCHK(launch_xinv<T>(v, XI_PCG, maxb_x, lds_x1 - xinv_tw_saving(), st));
         return RVE_OK;
     }
 
