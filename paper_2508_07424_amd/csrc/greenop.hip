@@ -170,9 +170,8 @@ __device__ __forceinline__ void st_s(T* p, T v) {
 template <typename F>
 __device__ __forceinline__ constexpr int tw_lds_len() { return F::fast ? F::N : 0; }
 
-// Axis and x-inverse passes of a fixed-size FFT in FP64 hold the phase-A
-// twiddles in registers instead of the LDS table (the host sizes their LDS
-// to match).
+// Passes of a fixed-size FFT in FP64 hold the phase-A twiddles in registers
+// instead of the LDS table (the host sizes their LDS to match).
 template <typename T, typename F>
 __device__ __forceinline__ constexpr bool reg_twiddles() {
     return F::fast && sizeof(T) == 8;
@@ -216,10 +215,11 @@ __device__ __forceinline__ int xcd_group(int bx, int n) {
 
 template <typename T, int S, int MODE, typename F, bool NT>
 __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
+    constexpr bool RT = reg_twiddles<T, F>();
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* const twl = reinterpret_cast<cplx<T>*>(smem_raw);
-    cplx<T>* buf = twl + tw_lds_len<F>();
-    const cplx<T>* const twp = F::fast ? twl : a.tw;
+    cplx<T>* buf = twl + (RT ? 0 : tw_lds_len<F>());
+    const cplx<T>* const twp = (F::fast && !RT) ? twl : a.tw;
     const Geom& g = a.g;
     const int b = blockIdx.y;
     const int k = a.iter;
@@ -320,7 +320,9 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
     // issued together, and the LDS tile.
     constexpr int U = S == 6 ? 2 : 4;
     const int tot = RB * nx;
-    stage_twiddles<T, F>(twl, a.tw);     // ordered by the barrier before the FFT
+    cplx<T> wr[RegTwCount<F>::n];
+    if constexpr (RT) load_reg_twiddles<T, F::N>(a.tw, wr);
+    else stage_twiddles<T, F>(twl, a.tw);     // ordered by the barrier before the FFT
     double part = 0.0;
     for (int v0 = threadIdx.x; v0 < tot; v0 += U * blockDim.x) {
         T in0[U][S], in1[U][S], in2[U][S], in3[U], in4[U], ph[U];
@@ -449,7 +451,8 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
         }
     }
     __syncthreads();
-    line_fft<T, F>(buf, S * npairs, LS, a.pl, twp, false);
+    if constexpr (RT) line_fft_rt<T, F>(buf, S * npairs, LS, a.pl, wr, twp, false);
+    else line_fft<T, F>(buf, S * npairs, LS, a.pl, twp, false);
 
     // split the packed lines into the half spectra of their two rows and
     // store them transposed: consecutive threads write consecutive y

@@ -402,14 +402,9 @@ struct Solver : SolverBase {
 
     // geometry and launch shapes from a configuration; false if unsupported
     static int threads_for(int n) { return std::min(256, ((n + 63) / 64) * 64); }
-    // LDS twiddle table of a fixed-size axis pass: FP32 only (FP64 axis
-    // passes hold their twiddles in registers)
+    // LDS twiddle table of a fixed-size pass: FP32 only (FP64 passes hold
+    // their twiddles in registers)
     static size_t axis_tw_bytes(int N) { return sizeof(T) == 8 ? 0 : (size_t)N * sizeof(cplx<T>); }
-    // The x-inverse passes of a fixed-size FFT in FP64 hold their twiddles in
-    // registers too: the LDS table the x-forward passes need is not allocated.
-    size_t xinv_tw_saving() const {
-        return (sizeof(T) == 8 && plx.fastN) ? (size_t)g.nx * sizeof(cplx<T>) : 0;
-    }
 
     // Launch shape: rows per block of the x passes, lines per block of the y
     // pass, y columns per tile of the z pass (0: the default heuristic).
@@ -451,8 +446,8 @@ struct Solver : SolverBase {
         const bool fixed = force && force->rb > 0;
         if (fixed) RB = force->rb;
         if (RB < 2 || (RB & (RB - 1))) { why = "rows per block must be a power of two >= 2"; return false; }
-        // the fixed-size FFTs keep an LDS copy of their N twiddles
-        const size_t twx = fast_len(g.nx) ? (size_t)g.nx * ce : 0;
+        // the fixed-size FFTs keep an LDS copy of their N twiddles (FP32)
+        const size_t twx = fast_len(g.nx) ? axis_tw_bytes(g.nx) : 0;
         if (fast_len(g.nx)) {
             while (!fixed && RB > 2 && ((size_t)g.s * (RB / 2) * lx + twx > kLdsCap ||
                                         g.s * (RB / 2) * split_max(g.nx) > 256))
@@ -764,7 +759,7 @@ struct Solver : SolverBase {
         a.rows_per_block = RB;
         a.nblocks = nbx;
         a.threads = thr_x;
-        HIPCHK(launch_xinv<T>(a, mode, maxb_x, lds_x - xinv_tw_saving(), st));
+        HIPCHK(launch_xinv<T>(a, mode, maxb_x, lds_x, st));
         return RVE_OK;
     }
 
@@ -837,7 +832,7 @@ struct Solver : SolverBase {
         v.nblocks = nbx1;
         v.threads = thr_x1;
         v.nt = stream_nt;
-        HIPCHK(launch_xinv<T>(v, XI_PCG, maxb_x, lds_x1 - xinv_tw_saving(), st));
+        HIPCHK(launch_xinv<T>(v, XI_PCG, maxb_x, lds_x1, st));
         return RVE_OK;
     }
 
@@ -1762,7 +1757,7 @@ struct Solver : SolverBase {
         nbx1 = (int)((g.ny * (long long)g.nz + RB1 - 1) / RB1);
         if (plx.fastN) {
             thr_x1 = threads_for((RB1 / 2) * split_max(g.nx));
-            lds_x1 = (size_t)(RB1 / 2) * lds_line(g.nx) * ce + (size_t)g.nx * ce;
+            lds_x1 = (size_t)(RB1 / 2) * lds_line(g.nx) * ce + axis_tw_bytes(g.nx);
         } else {
             thr_x1 = thr_x;
             lds_x1 = lds_x;
