@@ -177,6 +177,12 @@ __device__ __forceinline__ constexpr bool reg_twiddles() {
     return F::fast && sizeof(T) == 8;
 }
 
+// The x passes of a fixed-size FFT hold them in registers in both precisions.
+template <typename F>
+__device__ __forceinline__ constexpr bool x_reg_twiddles() {
+    return F::fast;
+}
+
 template <typename T, typename F>
 __device__ __forceinline__ void stage_twiddles(cplx<T>* twl, const cplx<T>* tw) {
     if constexpr (F::fast) {
@@ -215,7 +221,7 @@ __device__ __forceinline__ int xcd_group(int bx, int n) {
 
 template <typename T, int S, int MODE, typename F, bool NT>
 __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
-    constexpr bool RT = reg_twiddles<T, F>();
+    constexpr bool RT = x_reg_twiddles<F>();
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* const twl = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* buf = twl + (RT ? 0 : tw_lds_len<F>());
@@ -655,7 +661,7 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
 
 template <typename T, int S, int MODE, typename F, bool NT>
 __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
-    constexpr bool RT = reg_twiddles<T, F>();
+    constexpr bool RT = x_reg_twiddles<F>();
     extern __shared__ unsigned char smem_raw[];
     cplx<T>* const twl = reinterpret_cast<cplx<T>*>(smem_raw);
     cplx<T>* buf = twl + (RT ? 0 : tw_lds_len<F>());

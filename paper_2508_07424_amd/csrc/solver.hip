@@ -446,8 +446,9 @@ struct Solver : SolverBase {
         const bool fixed = force && force->rb > 0;
         if (fixed) RB = force->rb;
         if (RB < 2 || (RB & (RB - 1))) { why = "rows per block must be a power of two >= 2"; return false; }
-        // the fixed-size FFTs keep an LDS copy of their N twiddles (FP32)
-        const size_t twx = fast_len(g.nx) ? axis_tw_bytes(g.nx) : 0;
+        // the x passes' fixed-size FFTs hold their twiddles in registers (no
+        // LDS table)
+        const size_t twx = 0;
         if (fast_len(g.nx)) {
             while (!fixed && RB > 2 && ((size_t)g.s * (RB / 2) * lx + twx > kLdsCap ||
                                         g.s * (RB / 2) * split_max(g.nx) > 256))
@@ -1757,7 +1758,7 @@ struct Solver : SolverBase {
         nbx1 = (int)((g.ny * (long long)g.nz + RB1 - 1) / RB1);
         if (plx.fastN) {
             thr_x1 = threads_for((RB1 / 2) * split_max(g.nx));
-            lds_x1 = (size_t)(RB1 / 2) * lds_line(g.nx) * ce + axis_tw_bytes(g.nx);
+            lds_x1 = (size_t)(RB1 / 2) * lds_line(g.nx) * ce;
         } else {
             thr_x1 = thr_x;
             lds_x1 = lds_x;
