@@ -161,23 +161,25 @@ __device__ __forceinline__ void st_s(T* p, T v) {
     else *p = v;
 }
 
-
-// The fixed-size FFTs read their twiddles from an LDS table at the start of
-// the dynamic LDS (global twiddle loads inside the butterflies would each
-// wait on memory): entry k1 * N2 + t holds exp(-2 pi i t k1 / N), the
-// twiddle of column t and output k1 of the first phase (t k1 < N).  The
-// runtime plans read theirs from global memory.
+// Twiddles of the fixed-size FFTs, loaded once per block (global twiddle
+// loads inside the butterflies would each wait on memory).  Each thread
+// needs exp(-2 pi i t k1 / N) for its first-phase column t and k1 < N1.
+// The x passes, and the axis passes in FP64, whose blocks are limited by
+// LDS, keep these in registers (load_reg_twiddles).  The axis passes in
+// FP32, limited by registers, keep an LDS table at the start of the dynamic
+// LDS whose entry k1 * N2 + t holds that value (stage_twiddles; the host
+// sizes every pass's LDS to match).  The runtime plans read theirs from
+// global memory.
 template <typename F>
 __device__ __forceinline__ constexpr int tw_lds_len() { return F::fast ? F::N : 0; }
 
-// Passes of a fixed-size FFT in FP64 hold the phase-A twiddles in registers
-// instead of the LDS table (the host sizes their LDS to match).
+// Axis passes: registers in FP64, the LDS table in FP32.
 template <typename T, typename F>
 __device__ __forceinline__ constexpr bool reg_twiddles() {
     return F::fast && sizeof(T) == 8;
 }
 
-// The x passes of a fixed-size FFT hold them in registers in both precisions.
+// x passes: registers in both precisions.
 template <typename F>
 __device__ __forceinline__ constexpr bool x_reg_twiddles() {
     return F::fast;
