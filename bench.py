@@ -249,8 +249,8 @@ def main():
                     help="set up the batch and time the Green-operator passes only (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(RVEs shard across GPUs with no collective; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: there is no multi-GPU path here "
+              "(independent RVEs would shard across GPUs with no collective)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -10,8 +10,7 @@ toughness estimation by FFT based phase field fracture: application to
 composites and polycrystals", arXiv 2508.07424) in float64 with numpy /
 scipy primitives only (FFT, sparse direct solve).  Each function cites the
 section or equation it follows.  Where the paper is silent or its printed
-formula is inconsistent, the reading taken is stated in the docstring and
-listed in DESIGN.md.
+formula is inconsistent, the reading taken is stated in the docstring.
 
 Modules
 -------

@@ -4,7 +4,7 @@ Oracle; test infrastructure only.  Arrays are indexed [x, y(, z)]: array
 axis j is spatial direction j.  (The public input layout is the reverse,
 x fastest in memory; ``solver.Problem`` transposes once on entry.)
 
-Readings of the paper taken here (listed in the design doc):
+Readings of the paper taken here:
 
 * Degradation (Sec. 2.1).  The paper prints g = (1 - phi)^2 - k, which is
   negative at phi = 1; the residual stiffness is added:

@@ -24,7 +24,7 @@ The committed step stores phi, E, H^{n+1} = max(E^2 psi_o1 + psi_ini, H^n)
 (Eq. 38 with psi_o1 of a final (M) at the committed phi), the macroscopic
 stress Sigma = <sigma>:f and the running trapezoid T of Eq. 33.
 
-Readings of the paper taken here (listed in the design doc): the fracture point
+Readings of the paper taken here: the fracture point
 F (Sec. 4.2) is the first step at which every line of voxels along the
 loading axis holds a broken voxel (phi >= 0.95, or a notch voxel);
 A_g = h^(d-1) x (number of such lines without a notch voxel); V = N h^d;

@@ -10,7 +10,7 @@ exp(-2 pi i k.x / N) with inverse 1/N sum_k ...  Grids are periodic with
 voxel size h; index j of an axis of length N maps to the signed wavenumber
 k in [-N/2, N/2).
 
-Readings of the paper taken here (listed in the design doc):
+Readings of the paper taken here:
 
 * Projection.  Eq. 26 prints the projection for non-symmetric tensors; the
   unknowns are symmetric strains, so the symmetric projection onto
