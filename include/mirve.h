@@ -119,6 +119,10 @@ typedef struct {
     int    graphs;         /* 1 (default): run the Krylov iterations as replays of
                               captured HIP graphs (chunks of 8 iterations) when the
                               handle has a stream of its own; 0: launch them       */
+    int    streaming;      /* cache policy of the Krylov x passes' r, p, x: -1
+                              (default) chosen from the batch's footprint and by
+                              rve_autotune; 0 cached loads and stores; 1
+                              non-temporal ones (arithmetic is the same)          */
 } rve_config;
 
 typedef struct {
@@ -257,9 +261,10 @@ int rve_profile_pass(rve_handle h, int pass, int repeat, double* bytes_per_launc
 
 /* Autotuner of the launch shapes of the Green operator's passes (rows per
  * block of the x passes, lines per block of the y pass, y columns per tile
- * of the 3D z pass) and of the streaming policy of the Krylov x passes
- * (non-temporal loads and stores of r, p, x, which leave the last-level
- * cache to the spectrum when the batch's vectors do not fit it): times every
+ * of the 3D z pass) and, when the config's streaming is -1, of the streaming
+ * policy of the Krylov x passes (non-temporal loads and stores of r, p, x,
+ * which leave the last-level cache to the spectrum when the batch's vectors
+ * do not fit it): times every
  * feasible choice's CG-mode passes `repeat` times on the handle's own slots
  * (at least one slot must be set) and keeps the fastest for the handle.  The
  * choice is cached for the process per (grid, batch, precision): later

@@ -529,6 +529,7 @@ struct Solver : SolverBase {
         // exceed about three quarters of the 256 MB last-level cache (the
         // autotuner times both policies)
         stream_nt = 3.0 * g.s * (double)g.N * g.B * sizeof(T) > 192.0 * (1 << 20) ? 1 : 0;
+        if (c.streaming >= 0) stream_nt = c.streaming;
         one_comp_shape();
         int ax = 0;
         double best = -1;
@@ -1801,7 +1802,7 @@ struct Solver : SolverBase {
         tly = ty; maxb_y = my; lds_y = ly;
         tlz = tz; maxb_z = mz; lds_z = lz;
         thr_x = t1; thr_y = t2; thr_z = t3;
-        if (sh.nt >= 0) stream_nt = sh.nt ? 1 : 0;
+        if (sh.nt >= 0 && cfg.streaming < 0) stream_nt = sh.nt ? 1 : 0;   // a fixed policy wins
         one_comp_shape();
         clear_graphs();            // captured launches carry the old shape
         return RVE_OK;
@@ -1818,7 +1819,8 @@ struct Solver : SolverBase {
         if (!ready) return fail(RVE_ESTATE, "set_microstructure first");
         repeat = std::max(1, repeat);
         char key[128];
-        std::snprintf(key, sizeof(key), "%d:%dx%dx%d:B%d:w%d", g.dim, g.nx, g.ny, g.nz, B, (int)sizeof(T));
+        std::snprintf(key, sizeof(key), "%d:%dx%dx%d:B%d:w%d:s%d", g.dim, g.nx, g.ny, g.nz, B,
+                      (int)sizeof(T), cfg.streaming);
         {
             std::lock_guard<std::mutex> lk(tune_mutex());
             auto it = tune_cache().find(key);
@@ -1882,6 +1884,7 @@ struct Solver : SolverBase {
         // streaming policy of the Krylov x passes at the chosen shape
         tb = INFINITY;
         for (int nt : {0, 1}) {
+            if (cfg.streaming >= 0 && nt != cfg.streaming) continue;   // fixed by the config
             Shape sh = best;
             sh.nt = nt;
             if (set_shape(sh) != RVE_OK) continue;
@@ -2001,6 +2004,7 @@ static int validate(const rve_config* c, std::string& why) {
     if (c->max_materials < 1 || c->max_materials > kMaxMat) { why = "max_materials in [1, 65536]"; return RVE_EINVAL; }
     if (c->batch < 1 || c->batch > 1024) { why = "batch in [1, 1024]"; return RVE_EINVAL; }
     if (c->graphs != 0 && c->graphs != 1) { why = "graphs must be 0 or 1"; return RVE_EINVAL; }
+    if (c->streaming < -1 || c->streaming > 1) { why = "streaming must be -1, 0 or 1"; return RVE_EINVAL; }
     if (c->damage_precond != RVE_PRECOND_FFT && c->damage_precond != RVE_PRECOND_JACOBI) {
         why = "damage_precond must be RVE_PRECOND_FFT or RVE_PRECOND_JACOBI";
         return RVE_EINVAL;
@@ -2056,6 +2060,7 @@ int rve_default_config(rve_config* c) {
     c->batch = 1;
     c->damage_precond = RVE_PRECOND_FFT;
     c->graphs = 1;
+    c->streaming = -1;
     return RVE_OK;
 }
 

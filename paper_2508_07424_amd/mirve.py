@@ -55,7 +55,7 @@ class rve_config(C.Structure):
                 ("max_stagger", C.c_int), ("max_cg", C.c_int), ("max_pcg", C.c_int),
                 ("anderson_depth", C.c_int), ("frac_threshold", C.c_double), ("A_g", C.c_double),
                 ("max_materials", C.c_int), ("batch", C.c_int), ("damage_precond", C.c_int),
-                ("graphs", C.c_int)]
+                ("graphs", C.c_int), ("streaming", C.c_int)]
 
 
 class rve_phase(C.Structure):
