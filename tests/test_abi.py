@@ -79,6 +79,7 @@ def test_version_and_defaults(lib):
     assert so.rve_default_config(C.byref(cfg)) == lib.RVE_OK
     assert cfg.dim == 2 and tuple(cfg.n) == (64, 64, 1) and cfg.batch == 1
     assert cfg.k_res == 1e-6 and cfg.f[1] == 1.0 and cfg.split == lib.RVE_SPLIT_NONE
+    assert cfg.graphs == 1 and cfg.streaming == -1
     assert so.rve_default_config(None) == lib.RVE_EINVAL
 
 
@@ -108,6 +109,7 @@ def test_workspace_query(lib):
     {"dim": 4}, {"n": (1, 64)}, {"n": (64, 2048)}, {"h": 0.0}, {"ell": -1.0},
     {"tol_cg": 0.0}, {"max_cg": 0}, {"batch": 0}, {"batch": 5000}, {"anderson_depth": 9},
     {"f": (0, 0, 0)}, {"n": (97, 64)},   # 97 is prime: no FFT factorisation
+    {"streaming": 2}, {"streaming": -2}, {"graphs": 2},
 ])
 def test_invalid_configs_are_rejected(lib, bad):
     kw = {"n": (64, 64)}
