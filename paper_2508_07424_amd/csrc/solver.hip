@@ -1226,9 +1226,12 @@ struct Solver : SolverBase {
         CHK(upload_ints(dm1, m1));
         CHK(set_mask(3, mixing));
         const long long sstride = g.N * (long long)B;
-        HIPCHK(launch_anderson_gram<T>(g, aF, sstride, dorder, dm1, partials, nred, dmask[3], st));
+        // about 16 voxels per thread: the block reduction of the 30 Gram
+        // entries is amortised over more voxels
+        const int ngr = (int)std::max<long long>(1, std::min<long long>(nred, (g.N + 4095) / 4096));
+        HIPCHK(launch_anderson_gram<T>(g, aF, sstride, dorder, dm1, partials, ngr, dmask[3], st));
         const int nv = kAndersonMax * kAndersonMax + kAndersonMax;
-        HIPCHK(launch_sum_partials(partials, nred, nv, B, sums, dmask[3], st));
+        HIPCHK(launch_sum_partials(partials, ngr, nv, B, sums, dmask[3], st));
         CHK(read_sums(nv));
         std::vector<double> gam(kAndersonMax * B, 0.0);
         for (int b = 0; b < B; ++b) {
