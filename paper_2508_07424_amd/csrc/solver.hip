@@ -521,7 +521,9 @@ struct Solver : SolverBase {
         ws = wsp;
         Layout L;
         layout(c, g, nbx, L, this);
-        nred = (int)std::min<long long>((g.N + 255) / 256, kRedBlocks);
+        // reduction kernels: about eight voxels per thread, so that each
+        // block's partial-sum reduction is amortised
+        nred = (int)std::max<long long>(1, std::min<long long>((g.N + 2047) / 2048, kRedBlocks));
         // about eight voxels per thread: the per-block reduction of the
         // previous step's partials is amortised over more voxels
         nmv = (int)std::max<long long>(1, std::min<long long>(nred, (g.N + 2047) / 2048));
