@@ -15,7 +15,10 @@ value = sum over RVEs of (voxels x Green-operator applications) / seconds.
 
 The JSON line also carries the roofline of the dominant kernel (timed with
 HIP events on its stream, repeated launches of the same kernel on the same
-data) and the CPU oracle's rate on a bounded sample of the same workload.
+data), the same for the Green-operator path as a whole
+(roofline.operator_path: the passes' algorithmic bytes over their summed
+durations) and the CPU oracle's rate on a bounded sample of the same
+workload.
 """
 import argparse
 import json
@@ -112,7 +115,8 @@ def roofline(r, torch, repeat=50):
             "kernel": PASS_NAMES[dom], "kernel_symbol": PASS_SYMBOLS[dom],
             "avg_us": round(ms * 1e3, 2),
             "bytes_per_launch": nbytes,
-            "passes_us": {PASS_NAMES[k]: round(v[0] * 1e3, 2) for k, v in res.items()}}
+            "passes_us": {PASS_NAMES[k]: round(v[0] * 1e3, 2) for k, v in res.items()},
+            "passes_bytes": {PASS_NAMES[k]: v[1] for k, v in res.items()}}
 
 
 def copy_bandwidth(torch, mib=1024, repeat=10):
@@ -304,8 +308,16 @@ def main():
     # 3D: y forward, z with the projection, y inverse; the two y passes are
     # priced as the z pass)
     op_s = sum(v for v in roof["passes_us"].values()) * 1e-6
+    op_b = sum(roof["passes_bytes"].values())
     if len(wls[0].n) == 3:
         op_s += 2e-6 * roof["passes_us"][PASS_NAMES[1]]
+        op_b += 2 * roof["passes_bytes"][PASS_NAMES[1]]
+    # the fused Green-operator path as a whole: its passes' algorithmic bytes
+    # over their summed durations
+    gbs_path = op_b / op_s / 1e9
+    roof["operator_path"] = {"achieved": round(gbs_path, 1), "unit": "GB/s",
+                             "frac": round(gbs_path / HBM_PEAK_GBS, 4),
+                             "bytes_per_application": op_b, "us_per_application": round(op_s * 1e6, 2)}
     out = {
         "metric": "voxel-iter/s FFT Green-op solve",
         "value": round(value, 1),
