@@ -198,9 +198,25 @@ def test_homogeneous_rve_exact_uniform_stress():
     assert np.max(np.abs(x)) < 1e-14           # no fluctuation beyond rounding
     _, sig, _, S1 = solver.unit_response(prob, phi, x)
     C = mandel.c4_to_mandel(mandel.isotropic_c4(2.0, 0.3), 2)
-    ref = model.degradation(0.25, prob.k) * C @ w.f
+    # g(0.25) = (1 - 0.25)^2 + k written out as a number: k = 1e-6 enters
+    # with a plus sign (the printed "- k" would give 0.562499, a cubic
+    # degradation 0.421876)
+    assert prob.k == 1e-6
+    ref = 0.562501 * C @ w.f
     assert np.max(np.abs(sig - ref[:, None, None])) < 1e-14
     assert abs(S1 - ref @ w.f) < 1e-14
+
+
+@pytest.mark.parametrize("phi,g", [(0.0, 1.000001), (0.25, 0.562501), (0.5, 0.250001),
+                                   (0.9, 0.010001), (1.0, 0.000001)])
+def test_degradation_literal_values(phi, g):
+    """g(phi) = (1 - phi)^2 + k with k = 1e-6 (Sec. 2.1, Eq. 2 with the sign
+    of k read as +), as numbers worked out by hand; its derivative
+    -2 (1 - phi) (Eq. 6) by a central difference."""
+    assert abs(model.degradation(np.array(phi), 1e-6) - g) < 1e-15
+    d = 1e-6
+    num = (model.degradation(phi + d, 1e-6) - model.degradation(phi - d, 1e-6)) / (2 * d)
+    assert abs(num + 2.0 * (1.0 - phi)) < 1e-8
 
 
 # --------------------------------------------------------------------------
@@ -419,6 +435,98 @@ def test_energy_balance_without_history_converges():
     e2 = _energy_balance_error(0.0025)
     assert e1 < 2e-3
     assert e2 < e1 / 1.8
+
+
+def test_fracture_test_on_hand_built_fields():
+    """The fracture point (Sec. 4.2): every line of voxels along the load axis
+    holds a voxel with phi >= 0.95 or a notch voxel.  Fields built by hand."""
+    w = W.homogeneous_2d(nx=12, ny=8, ell=1.5, crack=4)
+    prob = oracle_problem(w)                  # load e_y (x) e_y: lines run along y
+    assert prob.load_axis == 1
+    notch_x = set(np.nonzero(prob.mat.void.any(axis=1))[0].tolist())
+    assert notch_x == {4, 5, 6, 7}
+    phi = np.zeros(prob.n)
+    assert not solver.fractured(prob, phi)
+    phi[:, 4] = 0.95                          # a band across the ligament at the notch row
+    assert solver.fractured(prob, phi)
+    phi[0, 4] = 0.949                         # one column just below the threshold
+    assert not solver.fractured(prob, phi)
+    phi[0, 1] = 0.97                          # that column broken at another height
+    assert solver.fractured(prob, phi)
+    band = np.zeros(prob.n)
+    band[:, 4] = 1.0
+    band[9, :] = 0.0                          # column x = 9 intact everywhere
+    assert not solver.fractured(prob, band)
+    band[9, 7] = 1.0
+    assert solver.fractured(prob, band)
+    # notch columns count as broken with phi = 0 there
+    only_lig = np.zeros(prob.n)
+    for x in range(12):
+        if x not in notch_x:
+            only_lig[x, 2] = 0.99
+    assert solver.fractured(prob, only_lig)
+    # a line along the load axis (a crack parallel to the load) does not split it
+    lengthwise = np.zeros(prob.n)
+    lengthwise[3, :] = 1.0
+    assert not solver.fractured(prob, lengthwise)
+
+
+def test_fracture_test_3d_lines_along_z():
+    n = (4, 3, 5)
+    w = W.Workload(n=n, h=1.0, ell=1.5, phases=[W.iso(1.0, 0.3, 1.0)],
+                   phase_id=np.zeros((5, 3, 4), np.uint16), f=W.load_zz(), dtau=1)
+    prob = oracle_problem(w)
+    assert prob.load_axis == 2
+    phi = np.zeros(n)
+    phi[:, :, 2] = 0.96                       # the plane z = 2 broken: every (x, y) line
+    assert solver.fractured(prob, phi)
+    phi[1, 2, 2] = 0.5
+    assert not solver.fractured(prob, phi)
+    phi[1, 2, 0] = 0.95
+    assert solver.fractured(prob, phi)
+
+
+def test_history_field_literal_values():
+    """H = max(E^2 psi_o1 + psi_ini, H^n) with history (Eq. 38, the max of
+    Eq. 11), E^2 psi_o1 + psi_ini without it; values worked out by hand."""
+    w = W.homogeneous_2d(nx=4, ny=4, ell=1.5, crack=2)
+    on, off = oracle_problem(w), oracle_problem(w, history=False)
+    psi1 = np.array([1.0, 2.0, 0.5, 0.0])
+    psi_ini = np.array([0.5, 0.5, 0.25, 0.0])
+    Hn = np.array([3.0, 1.0, 0.5, 0.125])
+    E = 1.5                                   # E^2 psi1 + psi_ini = [2.75, 5.0, 1.375, 0.0]
+    assert np.array_equal(solver.history_field(on, E, psi1, psi_ini, Hn), [3.0, 5.0, 1.375, 0.125])
+    assert np.array_equal(solver.history_field(off, E, psi1, psi_ini, Hn), [2.75, 5.0, 1.375, 0.0])
+
+
+def test_history_binds_after_the_load_drops():
+    """Along a homogeneous run to fracture the load E falls once the crack
+    runs (softening); there the stored history H^n exceeds the current
+    driving energy E^2 psi_o1 + psi_ini on part of the grid and the max of
+    Eq. 38 must keep it: H never decreases at any voxel (Eq. 11), and the
+    committed H equals H^n exactly where the max binds."""
+    w = W.homogeneous_2d(nx=24, ny=12, ell=1.5, crack=6)
+    prob = oracle_problem(w, tol=1e-9, tol_cg=1e-11, tol_al=1e-11)
+    st = solver.State(prob)
+    bound = 0
+    E_prev = 0.0
+    drops = 0
+    while not st.fractured and st.step < 300:
+        H_prev = st.H.copy()
+        solver.step(prob, st, w.dtau)
+        assert np.all(st.H >= H_prev)
+        x, _ = solver.mechanics(prob, st.phi, st.x)
+        _, _, psi1, _ = solver.unit_response(prob, st.phi, x)
+        drive = st.E ** 2 * psi1 + st.psi_ini
+        keep = H_prev > drive
+        assert np.array_equal(st.H[keep], H_prev[keep])
+        assert np.allclose(st.H[~keep], drive[~keep], rtol=1e-12, atol=0.0)
+        if st.E < E_prev:
+            drops += 1
+            bound += int(np.count_nonzero(keep & (H_prev > 1.001 * drive)))
+        E_prev = st.E
+    assert st.fractured
+    assert drops > 0 and bound > 0
 
 
 def test_broken_in_two_homogeneous():
