@@ -2,23 +2,22 @@
 """Benchmark of the FFT Green-operator solve of the phase-field-fracture
 toughness solver on one MI355X.
 
-A step is one dissipation-controlled step (Eq. 16 of the paper: mechanics CG
-with the fused Green operator, damage PCG, arc-length constraint, commit and
-fracture test) of every RVE of a batch of synthetic 256 x 256 fibre
-composites: elastic contrast {2, 5, 10} x toughness contrast {1, 2, 4}, seven
-random realizations of each (the paper's sample size for random fibres,
-Sec. 5.2.2), fibre radius U[5, 9] up to volume fraction 0.3, l = 2 voxels, a
-40-voxel notch.  The RVEs are loaded to an intermediate state by the warm-up
-steps, then K steps are timed.
+Default workload: a batch of 64 synthetic 2D elastic polycrystals of
+512 x 512 voxels (200 Voronoi grains, rotated cubic stiffness, orientation-
+dependent cleavage toughness, l = 2, a notch of 0.1 L_x), FP32 bulk with
+FP64 reductions and constraint, in one batched handle.  A step is one
+dissipation-controlled step (Eq. 16 of the paper: mechanics CG with the
+fused Green operator, damage PCG, arc-length constraint, commit and
+fracture test) of every RVE of the batch; each RVE goes at its own pace
+within the call.  W warm-up steps, then K timed steps, inputs resident in
+HBM.
 
 value = sum over RVEs of (voxels x Green-operator applications) / seconds.
 
-The JSON line also carries the roofline of the dominant kernel (timed with
-HIP events on its stream, repeated launches of the same kernel on the same
-data), the same for the Green-operator path as a whole
-(roofline.operator_path: the passes' algorithmic bytes over their summed
-durations) and the CPU oracle's rate on a bounded sample of the same
-workload.
+The JSON line also carries the roofline of the dominant kernel (HIP events
+on its stream) on the algorithmic bytes of a Green-operator application,
+the in-solve rate and a plain-operator microbenchmark against the same
+bytes, and the CPU oracle's rate on a bounded sample of the workload.
 """
 import argparse
 import json
@@ -90,11 +89,29 @@ WORKLOADS = {
 }
 
 
-def roofline(r, torch, repeat=50):
-    """Average duration of each CG-iteration pass (one launch covers every
-    RVE of the batch) by HIP events on the handle's stream; returns the
-    dominant one with its algorithmic bytes."""
+def alg_bytes(dim, w, m=2):
+    """Algorithmic bytes per voxel of one Green-operator application on the
+    minimal-pass schedule (the compulsory traffic of the hot path): in 2D
+    three passes, [x-R2C + constitutive: read s+1 fields and the material id,
+    write s] + [y forward, projection, y inverse: 2s] + [x-C2R: 2s], i.e.
+    (6s + 1) w + m; in 3D five passes, (10s + 1) w + m.  Returns the total
+    and each pass's share."""
+    s = 3 if dim == 2 else 6
+    share = {"x-forward": (s + 1) * w + m + s * w, "axis": 2 * s * w, "x-inverse": 2 * s * w}
+    total = (6 * s + 1) * w + m if dim == 2 else (10 * s + 1) * w + m
+    return total, share
+
+
+def roofline(r, torch, dim, w, repeat=50):
+    """Average duration of each pass of a mechanics CG iteration (one launch
+    covers every RVE of the batch), by HIP events on the handle's stream.
+    The dominant pass (the x-forward pass, which carries the constitutive
+    law and the CG direction update) is priced at its share of the
+    algorithmic bytes of a Green-operator application; the bytes it moves
+    for the Krylov vectors (r, p, x) are reported beside it."""
     stream = torch.cuda.current_stream() if r.stream is None else r.stream
+    B_alg, share = alg_bytes(dim, w)
+    shares = {3: share["x-forward"], 1: share["axis"], 4: share["x-inverse"]}
     res = {}
     for p in (3, 1, 4):
         r.rve_profile_pass(p, 3)
@@ -105,18 +122,53 @@ def roofline(r, torch, repeat=50):
         nbytes = r.rve_profile_pass(p, repeat)
         b.record(stream)
         torch.cuda.synchronize()
-        ms = a.elapsed_time(b) / repeat
-        res[p] = (ms, nbytes)
+        res[p] = (a.elapsed_time(b) / repeat, nbytes)
     dom = max(res, key=lambda k: res[k][0])
-    ms, nbytes = res[dom]
-    gbs = nbytes / (ms * 1e-3) / 1e9
+    ms, krylov_bytes = res[dom]
+    vox = r.N * r.B
+    alg = shares[dom] * vox
+    gbs = alg / (ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel": PASS_NAMES[dom], "kernel_symbol": PASS_SYMBOLS[dom],
             "avg_us": round(ms * 1e3, 2),
-            "bytes_per_launch": nbytes,
-            "passes_us": {PASS_NAMES[k]: round(v[0] * 1e3, 2) for k, v in res.items()},
-            "passes_bytes": {PASS_NAMES[k]: v[1] for k, v in res.items()}}
+            "algorithmic_bytes_per_launch": alg,
+            "algorithmic_bytes_per_voxel": shares[dom],
+            "krylov_inclusive_bytes_per_launch": krylov_bytes,
+            "krylov_inclusive_gbs": round(krylov_bytes / (ms * 1e-3) / 1e9, 1),
+            "passes_us": {PASS_NAMES[k]: round(v[0] * 1e3, 2) for k, v in res.items()}}
+
+
+def operator_bench(r, torch, dim, w, repeat=1000):
+    """The plain Green operator out = F^-1{P : F[g C : eps]} applied `repeat`
+    times to a fixed strain on the batch's current (mid-run) damage, every
+    RVE of the batch per application: voxel-iter/s and its fraction of the
+    HBM roofline on the algorithmic bytes."""
+    stream = torch.cuda.current_stream() if r.stream is None else r.stream
+    dt = torch.float64 if w == 8 else torch.float32
+    n = r.B * r.s * r.N
+    with torch.cuda.stream(stream):
+        g = torch.Generator(device="cuda")
+        g.manual_seed(3)
+        eps = torch.randn(n, dtype=dt, device="cuda", generator=g)
+        out = torch.empty_like(eps)
+    torch.cuda.synchronize()
+    r.rve_apply_green_op_device(eps, out, 5)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    r.rve_apply_green_op_device(eps, out, repeat)
+    b.record(stream)
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) * 1e-3
+    B_alg, _ = alg_bytes(dim, w)
+    rate = repeat * r.N * r.B / sec
+    return {"applications": repeat, "voxel_iter_per_s": round(rate, 1),
+            "us_per_application": round(1e6 * sec / repeat, 2),
+            "algorithmic_bytes_per_voxel": B_alg,
+            "achieved_gbs": round(rate * B_alg / 1e9, 1),
+            "frac": round(rate * B_alg / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def copy_bandwidth(torch, mib=1024, repeat=10):
@@ -209,6 +261,24 @@ def serving(n_requests, seed, rate):
     return out
 
 
+def host_cpu():
+    """Cores this process may use and the CPU model of the host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": usable, "cpu_count": os.cpu_count(), "model": model}
+
+
 def cpu_baseline(w, seconds):
     """The oracle's conjugate-gradient Green-operator solve on the host,
     bounded to about `seconds` of work: voxel-iterations per second."""
@@ -227,8 +297,9 @@ def cpu_baseline(w, seconds):
     x, it = solver.mechanics(prob, st.phi, st.x)
     t1 = time.perf_counter()
     N = int(np.prod(w.n))
+    host = host_cpu()
     return {"value": round(N * (it + 2) / (t1 - t0), 1), "unit": "voxel-iter/s", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "host_nproc": host["nproc"], "host_cpu": host["model"],
             "sample": "%d CG iterations (+2 set-up Green operators) of the oracle's mechanics solve on "
                       "one %s RVE at its enriched initial state, numpy FFT, 1 thread, %.1f s"
                       % (it, "x".join(map(str, w.n)), t1 - t0)}
@@ -237,16 +308,18 @@ def cpu_baseline(w, seconds):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="composite256")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="polycrystal512")
     ap.add_argument("--batch", type=int, default=None,
-                    help="RVEs (default: 63 = 9 contrast cases x 7 realizations for composite256)")
+                    help="RVEs (default: 64 polycrystals; 63 = 9 contrast cases x 7 realizations "
+                         "for composite256)")
     ap.add_argument("--size", type=int, default=None)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=8,
+    ap.add_argument("--operator-repeat", type=int, default=1000)
+    ap.add_argument("--serve-requests", type=int, default=0,
                     help="requests of the serving comparison (0: skip it)")
     ap.add_argument("--serve-rate", type=float, default=2.0, help="Poisson arrivals per second")
     ap.add_argument("--roofline-only", action="store_true",
@@ -264,60 +337,63 @@ def main():
     args.batch = args.batch or batch0
     args.precision = args.precision or prec0
     prec = mirve.RVE_PREC_FP64 if args.precision == "fp64" else mirve.RVE_PREC_MIXED
+    w_bytes = 8 if prec == mirve.RVE_PREC_FP64 else 4
     progress("generating %d %s inputs" % (args.batch, args.workload))
     wls = build(args.size, args.batch)
-    # one batched handle: every launch covers all RVEs of the batch
+    dim = len(wls[0].n)
+    # one batched handle; each RVE advances at its own pace within a call
     progress("setting up %d RVEs" % len(wls))
     rve = mirve.from_workloads(wls, precision=prec, stream=torch.cuda.Stream())
     dtaus = [w.dtau for w in wls]
     torch.cuda.synchronize()
     progress("set up")
     shape = rve.rve_autotune(10)
-    progress("autotuned launch shape (x rows, y lines, z columns) = %s" % (shape,))
+    progress("autotuned launch shape (x rows, y lines, z columns, non-temporal) = %s" % (shape,))
     if args.roofline_only:
-        shape = rve.rve_autotune(10)
-        roof = roofline(rve, torch)
+        roof = roofline(rve, torch, dim, w_bytes)
         roof["copy_gbs"] = copy_bandwidth(torch)
         print(json.dumps({"roofline": roof}), flush=True)
         return
 
-    for k in range(args.warmup):
-        _, st = rve.rve_step_dissipation_slots(dtaus)
-        assert all(v == 0 for v in st), st
-        progress("warm-up step %d" % (k + 1))
+    failed = {}
+
+    def run(nsteps, label):
+        t0 = time.perf_counter()
+        infos, st = rve.rve_run_slots([d if b not in failed else 0.0 for b, d in enumerate(dtaus)],
+                                      [nsteps] * len(dtaus))
+        for b, (i, s) in enumerate(zip(infos, st)):
+            if s != 0 and b not in failed:
+                failed[b] = {"slot": b, "status": s, "reason": mirve.WHY.get(i["reason"], "?"),
+                             "phase": label, "steps_done": i["n_steps"]}
+        done = sum(i["n_steps"] for i in infos)
+        progress("%s: %d RVE-steps in %.2f s, %d failed slots" % (label, done, time.perf_counter() - t0,
+                                                                  len(failed)))
+        return infos
+
+    if args.warmup > 0:
+        run(args.warmup, "warm-up (%d steps per RVE)" % args.warmup)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    greenops = 0
-    for _ in range(args.steps):
-        info, st = rve.rve_step_dissipation_slots(dtaus)
-        assert all(v == 0 for v in st), st
-        greenops += sum(rve.N * i["n_greenop"] for i in info)
-        progress("timed step")
+    infos = run(args.steps, "timed (%d steps per RVE)" % args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sec = t1 - t0
+    greenops = sum(rve.N * i["n_greenop"] for i in infos)
+    rve_steps = sum(i["n_steps"] for i in infos)
     value = greenops / sec
 
-    roof = roofline(rve, torch)
+    B_alg, _ = alg_bytes(dim, w_bytes)
+    roof = roofline(rve, torch, dim, w_bytes)
     roof["copy_gbs"] = copy_bandwidth(torch)
     roof["frac_of_copy"] = round(roof["achieved"] / roof["copy_gbs"], 4)
     tag = "f64" if prec == mirve.RVE_PREC_FP64 else "mixed"
     roof["traffic"] = stored_traffic("traffic_%s_%s_b%d_%s.txt" % (
-        roof["kernel_symbol"], "x".join([str(args.size)] * len(wls[0].n)), args.batch, tag))
-    # one Green operator: the x passes once each, the axis passes (2D: one;
-    # 3D: y forward, z with the projection, y inverse; the two y passes are
-    # priced as the z pass)
-    op_s = sum(v for v in roof["passes_us"].values()) * 1e-6
-    op_b = sum(roof["passes_bytes"].values())
-    if len(wls[0].n) == 3:
-        op_s += 2e-6 * roof["passes_us"][PASS_NAMES[1]]
-        op_b += 2 * roof["passes_bytes"][PASS_NAMES[1]]
-    # the fused Green-operator path as a whole: its passes' algorithmic bytes
-    # over their summed durations
-    gbs_path = op_b / op_s / 1e9
-    roof["operator_path"] = {"achieved": round(gbs_path, 1), "unit": "GB/s",
-                             "frac": round(gbs_path / HBM_PEAK_GBS, 4),
-                             "bytes_per_application": op_b, "us_per_application": round(op_s * 1e6, 2)}
+        roof["kernel_symbol"], "x".join([str(args.size)] * dim), args.batch, tag))
+    roof["in_solve"] = {"voxel_iter_per_s": round(value, 1), "algorithmic_bytes_per_voxel": B_alg,
+                        "achieved_gbs": round(value * B_alg / 1e9, 1),
+                        "frac": round(value * B_alg / 1e9 / HBM_PEAK_GBS, 4)}
+    progress("operator microbenchmark (%d applications)" % args.operator_repeat)
+    roof["operator"] = operator_bench(rve, torch, dim, w_bytes, args.operator_repeat)
     out = {
         "metric": "voxel-iter/s FFT Green-op solve",
         "value": round(value, 1),
@@ -333,12 +409,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc.format(n=args.size, r=(args.batch + 8) // 9, b=args.batch),
                    "batch": args.batch, "precision": args.precision,
-                   "rve_steps_per_s": round(args.batch * args.steps / sec, 3),
-                   "greenops_per_rve_step": round(greenops / (args.batch * args.steps) / rve.N, 1),
+                   "rve_steps": rve_steps,
+                   "rve_steps_per_s": round(rve_steps / sec, 3),
+                   "greenops_per_rve_step": round(greenops / max(rve_steps, 1) / rve.N, 1),
+                   "failed_slots": sorted(failed.values(), key=lambda d: d["slot"]),
                    "launch_shape": {"x_rows_per_block": shape[0], "y_lines_per_block": shape[1],
                                     "z_columns_per_tile": shape[2],
-                                    "krylov_vectors_nontemporal": shape[3]},
-                   "operator_voxel_iter_per_s": round(rve.N * args.batch / op_s, 1)},
+                                    "krylov_vectors_nontemporal": shape[3]}},
         "roofline": roof,
     }
     if args.serve_requests > 0:

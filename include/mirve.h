@@ -31,11 +31,17 @@
  *   - A handle is not thread-safe.  Distinct handles may run concurrently
  *     on distinct streams.
  *   - Steps are transactional: a step that fails leaves the committed state
- *     (phi, history, E, curve) unchanged.
- *   - A handle holds cfg.batch RVE slots of the same grid.  Every kernel
- *     launch covers all slots; slots advance in lockstep and each keeps its
- *     own microstructure, state and convergence.  The functions without a
- *     slot argument address slot 0 (rve_step_dissipation needs batch = 1).
+ *     (phi, history, E, curve) as it was when the step began.  A step whose
+ *     solve fails (any iteration limit, a stalled stagger or a breakdown) is
+ *     first redone as two steps of half the increment, recursively, down to
+ *     cfg.max_halvings levels; dissipation control allows any subdivision of
+ *     the increment (Sec. 4.1).
+ *   - A handle holds cfg.batch RVE slots of the same grid, each with its own
+ *     microstructure, state and convergence.  Kernel launches cover the
+ *     slots that are in the same phase of their step; a slot that finishes a
+ *     step goes on with its next one while others still iterate.  The
+ *     functions without a slot argument address slot 0
+ *     (rve_step_dissipation needs batch = 1).
  */
 #ifndef MIRVE_H
 #define MIRVE_H
@@ -56,6 +62,22 @@ extern "C" {
 #define RVE_ENUMERIC -5   /* NaN / Inf met in a reduction                 */
 #define RVE_ESTATE   -6   /* call out of order (e.g. step before set_microstructure) */
 #define RVE_ENOTDONE -7   /* no fracture point reached yet                */
+
+/* why a step failed (rve_step_info.reason) */
+#define RVE_WHY_NONE      0
+#define RVE_WHY_STAGGER   1  /* staggered fixed point: max_stagger reached, or stalled
+                                (its error not halved within stall_window iterations) */
+#define RVE_WHY_CG        2  /* mechanics CG reached max_cg                         */
+#define RVE_WHY_PCG       3  /* damage PCG reached max_pcg                          */
+#define RVE_WHY_ARCLENGTH 4  /* the dissipation constraint's root finder reached
+                                its iteration limit                                */
+#define RVE_WHY_SPLIT     5  /* the split law's Newton loop reached its limit       */
+#define RVE_WHY_BREAKDOWN 6  /* Krylov breakdown or a non-finite reduction          */
+#define RVE_WHY_ANDERSON  7  /* singular or non-finite Anderson system              */
+
+/* flags of rve_run_slots */
+#define RVE_RUN_STOP_AT_FRACTURE 1  /* a slot stops after the step that reaches its
+                                       fracture point (and takes none once there)   */
 
 /* precision modes */
 #define RVE_PREC_FP64  0  /* every field and transform in FP64                        */
@@ -99,12 +121,19 @@ typedef struct {
     int    split;          /* RVE_SPLIT_*                                            */
     int    history;        /* 1: H = max(psi_o + psi_ini, H^n) (Eq. 38); 0: no max   */
     int    precision;      /* RVE_PREC_*                                             */
+    /* tolerances; 0 takes the default of the precision mode:
+       FP64  tol 1e-8, tol_cg 1e-10, tol_pcg 1e-12, tol_al 1e-10;
+       MIXED tol 1e-5, tol_cg 1e-6,  tol_pcg 1e-7,  tol_al 1e-6                       */
     double tol;            /* stagger tolerance on the relative change of phi and E  */
     double tol_cg;         /* mechanics CG: ||r|| <= tol_cg ||b||                    */
     double tol_pcg;        /* damage PCG: ||r|| <= tol_pcg ||rhs||                   */
     double tol_al;         /* dissipation constraint: |D - tau| <= tol_al tau        */
-    int    max_stagger;    /* stagger iteration limit per step; a step that reaches
-                              it is redone as two half steps, down to dtau / 16     */
+    int    max_stagger;    /* stagger iteration limit per step attempt               */
+    int    max_halvings;   /* a failed step attempt is redone as two of half the
+                              increment, at most this many levels deep (0-12)       */
+    int    stall_window;   /* an attempt whose stagger error has not halved within
+                              this many iterations counts as failed (0, the
+                              default: off)                                       */
     int    max_cg;         /* CG iteration limit per mechanics solve                 */
     int    max_pcg;        /* PCG iteration limit per damage solve                   */
     int    anderson_depth; /* Anderson acceleration depth of the stagger (0 = off)   */
@@ -130,6 +159,11 @@ typedef struct {
     double E, nu;          /* isotropic constants              */
     double C11, C12, C44;  /* cubic constants (lattice axes)   */
     double Gc;             /* critical energy release rate     */
+    double beta;           /* cleavage anisotropy A_f = I + beta (I - n (x) n) of the
+                              crack-surface density (Sec. 2.2, Eq. 14-15); only the
+                              isotropic surface beta = 0 is supported: other values
+                              are rejected with RVE_EINVAL                        */
+    double n[3];           /* cleavage-plane normal (lattice axes) for beta != 0   */
 } rve_phase;
 
 typedef struct {
@@ -148,7 +182,13 @@ typedef struct {
     double res_R3;         /* |D - tau| / tau                                        */
     int    fractured;      /* 1 once every line along the load axis is broken        */
     int    step;           /* index of the committed step (1, 2, ...)                */
+    int    n_steps;        /* steps committed by the call                            */
+    int    n_substeps;     /* committed sub-steps (a step split by halving has > 1)  */
+    int    reason;         /* RVE_WHY_* of a failed step, else RVE_WHY_NONE          */
 } rve_step_info;
+/* E .. step describe the last step the call committed (the committed state
+ * when it committed none).  The counters n_stagger, n_cg, n_pcg, n_greenop
+ * sum all the work of the call, failed attempts included. */
 
 /* Fill cfg with defaults (tolerances, limits, FP64, no split, history on). */
 int rve_default_config(rve_config* cfg);
@@ -188,12 +228,23 @@ int rve_set_microstructure_slot(rve_handle h, int slot, const uint16_t* phase_id
  * commit and the fracture test.  out may be NULL.  Needs batch = 1. */
 int rve_step_dissipation(rve_handle h, double dtau, rve_step_info* out);
 
-/* One lockstep step of every slot b with dtau[b] > 0 (dtau[b] = 0: the slot
- * idles).  dtau, info (may be NULL) and status have `batch` entries; each
- * slot's step is transactional on its own.  Returns RVE_OK if every stepped
- * slot succeeded, else the first failure code. */
+/* One step of every slot b with dtau[b] > 0 (dtau[b] = 0: the slot idles).
+ * dtau, info (may be NULL) and status (may be NULL) have `batch` entries;
+ * each slot's step is transactional on its own.  Returns RVE_OK if every
+ * stepped slot succeeded, else the first failure code. */
 int rve_step_dissipation_slots(rve_handle h, const double* dtau, rve_step_info* info,
                                int* status);
+
+/* Up to max_steps[b] steps of dtau[b] for every slot b with max_steps[b] > 0
+ * and dtau[b] > 0, each slot at its own pace (Eq. 16; the batched form): a
+ * slot that commits a step starts its next one while other slots are still
+ * iterating theirs.  A slot stops at its first failed step (status[b] then
+ * holds its code and info[b].reason the cause; the steps before it stay
+ * committed) or, with RVE_RUN_STOP_AT_FRACTURE, after the step that reaches
+ * its fracture point.  info and status may be NULL.  Returns RVE_OK if no
+ * slot failed, else the first failure code. */
+int rve_run_slots(rve_handle h, const double* dtau, const int* max_steps, int flags,
+                  rve_step_info* info, int* status);
 
 /* Number of slots of the handle. */
 int rve_batch_size(rve_handle h);
@@ -219,6 +270,17 @@ int rve_get_field(rve_handle h, int which, double* host, size_t count);
 int rve_set_field(rve_handle h, int which, const double* host, size_t count);
 int rve_get_field_slot(rve_handle h, int slot, int which, double* host, size_t count);
 int rve_set_field_slot(rve_handle h, int slot, int which, const double* host, size_t count);
+
+/* Checkpoint of one slot's committed state (phi, history H^n, the committed
+ * strain fluctuation, the warm start of the arc-length tangent, and the
+ * scalars E, Sigma, T, tau, tau0, step, fractured) as an opaque host blob of
+ * rve_state_bytes() bytes.  rve_load_state needs a handle of the same grid
+ * and precision whose slot already holds the same microstructure
+ * (rve_set_microstructure_slot); stepping on from a loaded state gives the
+ * same results, bit for bit, as stepping on from the saved one. */
+int rve_state_bytes(rve_handle h, size_t* bytes);
+int rve_save_state(rve_handle h, int slot, void* host, size_t bytes);
+int rve_load_state(rve_handle h, int slot, const void* host, size_t bytes);
 
 /* Scalars of the committed state: out[0..5] = {E, Sigma, T, tau, tau0, step}.
  * The slot form also returns out[6] = fractured and out[7] = A_g (8 values). */

@@ -31,6 +31,7 @@ A_g = h^(d-1) x (number of such lines without a notch voxel); V = N h^d;
 tau^0 = D(phi_ini); the trapezoid of Eq. 33 is used (the text says Simpson,
 the printed formula is the trapezoid).
 """
+import copy
 import math
 import numpy as np
 
@@ -48,7 +49,8 @@ class Problem:
     def __init__(self, n, h, ell, phases, phase_id, f, *, theta=None, void=None,
                  phi_disc=None, phi_M=0.8, k=1e-6, split="none", history=True,
                  A_g=None, tol=1e-10, tol_cg=1e-12, tol_al=1e-12, max_stagger=100,
-                 max_cg=20000, frac_threshold=0.95, anderson_depth=5, max_halvings=4):
+                 max_cg=20000, frac_threshold=0.95, anderson_depth=5, max_halvings=4,
+                 stall_window=0):
         self.n = tuple(int(v) for v in n)
         self.d = len(self.n)
         self.s = mandel.nsym(self.d)
@@ -59,6 +61,7 @@ class Problem:
         self.frac_threshold = frac_threshold
         self.anderson_depth = int(anderson_depth)
         self.max_halvings = int(max_halvings)
+        self.stall_window = int(stall_window)
         tr = lambda a: None if a is None else np.ascontiguousarray(np.asarray(a).T)
         pid = tr(phase_id)
         void_x = tr(void) if void is not None else np.zeros(self.n, dtype=bool)
@@ -253,7 +256,7 @@ def arclength(prob, psi1, psi_ini, Hn, tau, E0):
         if not math.isinf(hi) and hi - lo <= 1e-15 * hi:
             return E, phi, nsolves
         E = En
-    raise RuntimeError("arc-length root finder did not converge")
+    raise ConstraintNotConverged("arc-length root finder did not converge")
 
 
 # --------------------------------------------------------------------------
@@ -284,28 +287,46 @@ def fractured(prob, phi):
     return bool(np.all(np.any(broken, axis=prob.load_axis)))
 
 
-class StaggerNotConverged(RuntimeError):
+class StepNotConverged(RuntimeError):
     pass
 
 
-def step(prob, st, dtau, _depth=0):
+class StaggerNotConverged(StepNotConverged):
+    pass
+
+
+class ConstraintNotConverged(StepNotConverged):
+    pass
+
+
+def step(prob, st, dtau):
     """One dissipation-controlled step tau^{n+1} = tau^n + dtau (Eq. 16).
 
     At an unstable crack advance the staggered map can stall (its fixed
-    point is approached no further, Sec. 4.1 has the paper relax its Newton
-    steps for the same reason); dissipation control allows any subdivision
-    of the increment, so a step whose stagger has not converged within
-    max_stagger iterations leaves the state unchanged and is redone as two
-    steps of dtau / 2, down to dtau / 2^max_halvings.  Returns the record of
-    the last (sub)step.
+    point is approached no further; Sec. 4.1 has the paper relax its Newton
+    steps for the same reason).  Dissipation control allows any subdivision
+    of the increment, so an attempt that fails leaves the state unchanged
+    and is replaced by two attempts of half its increment, recursively, at
+    most max_halvings levels deep.  If the deepest one fails as well, the
+    state returns to what it was when the step began and the failure is
+    raised.  Returns the record of the last (sub)step.
     """
+    saved = copy.deepcopy(st)
+    try:
+        return _step_split(prob, st, dtau, 0)
+    except StepNotConverged:
+        st.__dict__.update(saved.__dict__)
+        raise
+
+
+def _step_split(prob, st, dtau, depth):
     try:
         return _step_once(prob, st, dtau)
-    except StaggerNotConverged:
-        if _depth >= prob.max_halvings:
+    except StepNotConverged:
+        if depth >= prob.max_halvings:
             raise
-        step(prob, st, 0.5 * dtau, _depth + 1)
-        return step(prob, st, 0.5 * dtau, _depth + 1)
+        _step_split(prob, st, 0.5 * dtau, depth + 1)
+        return _step_split(prob, st, 0.5 * dtau, depth + 1)
 
 
 def _step_once(prob, st, dtau):
@@ -313,8 +334,10 @@ def _step_once(prob, st, dtau):
     (M) then one (A)) is iterated to its fixed point; the iterates are
     combined by Anderson mixing of depth prob.anderson_depth (least squares
     on the last residual differences), which leaves the fixed point
-    unchanged and only shortens the way there.  The state is changed only
-    once the stagger has converged.
+    unchanged and only shortens the way there.  The attempt fails after
+    max_stagger iterations, or once its error has not been halved for
+    stall_window iterations (a stall).  The state is changed only once the
+    stagger has converged.
     """
     tau = st.tau + dtau
     phi, E, x = st.phi.copy(), st.E, st.x.copy()
@@ -322,6 +345,7 @@ def _step_once(prob, st, dtau):
     err = math.inf
     hist_F, hist_G = [], []
     m = prob.anderson_depth
+    ref, ref_it = math.inf, 0
     for it in range(1, prob.max_stagger + 1):
         x, ncg = mechanics(prob, phi, x)
         n_cg += ncg
@@ -332,9 +356,13 @@ def _step_once(prob, st, dtau):
         dE = abs(E_new - E) / max(abs(E_new), 1e-300)
         err = max(dphi, dE)
         E = E_new
+        if err < 0.5 * ref:
+            ref, ref_it = err, it
         if err < prob.tol:
             phi = phi_new
             break
+        if prob.stall_window > 0 and it - ref_it >= prob.stall_window:
+            raise StaggerNotConverged("stagger stalled (err=%g)" % err)
         if m > 0:
             hist_F.append((phi_new - phi).ravel())
             hist_G.append(phi_new.ravel())

@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstring>
 #include <cstdlib>
+#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -237,7 +238,7 @@ struct SolverBase {
     virtual ~SolverBase() {}
     virtual int set_microstructure(int slot, const uint16_t*, const rve_phase*, int, const double*,
                                    const uint8_t*, const uint8_t*, double) = 0;
-    virtual int step(const double* dtau, rve_step_info* info, int* status) = 0;
+    virtual int run(const double* dtau, const int* todo, int flags, rve_step_info* info, int* status) = 0;
     virtual int get_field(int slot, int which, double* host, size_t count) = 0;
     virtual int set_field(int slot, int which, const double* host, size_t count) = 0;
     virtual int apply_green(int slot, const double* eps, double* out) = 0;
@@ -247,6 +248,9 @@ struct SolverBase {
     virtual int dissipation(int slot, double* D, double* G) = 0;
     virtual int profile_pass(int pass, int repeat, double* bytes_per_launch) = 0;
     virtual int autotune(int repeat, int* shape_out) = 0;
+    virtual size_t state_bytes() const = 0;
+    virtual int save_state(int slot, void* host, size_t bytes) = 0;
+    virtual int load_state(int slot, const void* host, size_t bytes) = 0;
     std::vector<SlotState> slots;
     int B = 1;
 };
@@ -309,12 +313,10 @@ struct Solver : SolverBase {
 
     int greenops = 0;
     std::vector<int> step_greens;    // Green-operator applications per slot in this step
-    std::vector<int> stag_fail;      // the slot's last step stopped on the stagger limit
     bool trace = false;              // MIRVE_TRACE set: stagger progress on stderr
     // captured Krylov chunks: key -> executable graph of kGraphChunk iterations
     std::map<std::string, hipGraphExec_t> graphs;
     static constexpr int kGraphChunk = 8;
-    static constexpr int kMaxHalvings = 4;
     static constexpr double kGammaMax = 10.0;
     static constexpr int kMaxNewton = 100;
     std::vector<int> slope_warm;     // tmp holds a usable tangent of this slot
@@ -559,6 +561,13 @@ struct Solver : SolverBase {
     int fail(int code, const std::string& m) {
         hd->err = m;
         return code;
+    }
+    // a per-slot failure: status code, reason (RVE_WHY_*) and the handle's message
+    std::vector<int> why_;
+    void slot_fail(std::vector<int>& rcs, int b, int code, int why, const char* msg) {
+        rcs[b] = code;
+        if ((int)why_.size() == B) why_[b] = why;
+        hd->err = std::string("slot ") + std::to_string(b) + ": " + msg;
     }
 
 #define HIPCHK(expr)                                                                      \
@@ -938,11 +947,9 @@ struct Solver : SolverBase {
             if (c.status == 1) continue;
             if (c.status == 2) {
                 if (std::isfinite(c.rr) && c.rr <= 1e4 * c.tol2 * c.bn2) continue;
-                rcs[b] = RVE_ENUMERIC;
-                hd->err = "mechanics CG breakdown or non-finite residual";
+                slot_fail(rcs, b, RVE_ENUMERIC, RVE_WHY_BREAKDOWN, "mechanics CG breakdown or non-finite residual");
             } else {
-                rcs[b] = RVE_ENOCONV;
-                hd->err = "mechanics CG did not converge";
+                slot_fail(rcs, b, RVE_ENOCONV, RVE_WHY_CG, "mechanics CG did not converge within max_cg");
             }
         }
         return RVE_OK;
@@ -1000,10 +1007,7 @@ struct Solver : SolverBase {
             }
         }
         for (int b = 0; b < B; ++b)
-            if (nw[b]) {
-                rcs[b] = RVE_ENOCONV;
-                hd->err = "split mechanics: Newton did not converge";
-            }
+            if (nw[b]) slot_fail(rcs, b, RVE_ENOCONV, RVE_WHY_SPLIT, "split mechanics: Newton did not converge");
         return RVE_OK;
     }
 
@@ -1091,11 +1095,9 @@ struct Solver : SolverBase {
             if (d.status == 1) continue;
             if (d.status == 2) {
                 if (std::isfinite(d.rr) && (d.rr <= 1e4 * d.tol2 * d.bn2 || d.bn2 == 0.0)) continue;
-                rcs[b] = RVE_ENUMERIC;
-                hd->err = "damage PCG breakdown or non-finite residual";
+                slot_fail(rcs, b, RVE_ENUMERIC, RVE_WHY_BREAKDOWN, "damage PCG breakdown or non-finite residual");
             } else {
-                rcs[b] = RVE_ENOCONV;
-                hd->err = "damage PCG did not converge";
+                slot_fail(rcs, b, RVE_ENOCONV, RVE_WHY_PCG, "damage PCG did not converge within max_pcg");
             }
         }
         return RVE_OK;
@@ -1208,10 +1210,8 @@ struct Solver : SolverBase {
             }
         }
         for (int b = 0; b < B; ++b)
-            if (al[b] && rcs[b] == RVE_OK) {
-                rcs[b] = RVE_ENOCONV;
-                hd->err = "dissipation constraint (arc-length) did not converge";
-            }
+            if (al[b] && rcs[b] == RVE_OK)
+                slot_fail(rcs, b, RVE_ENOCONV, RVE_WHY_ARCLENGTH, "dissipation constraint (arc-length) did not converge");
         return RVE_OK;
     }
 
@@ -1283,10 +1283,7 @@ struct Solver : SolverBase {
             // plain fixed-point step instead (gamma = 0 gives phi(E))
             if (ok && sizeof(T) != sizeof(double) && gsum > kGammaMax)
                 for (int k = 0; k < m; ++k) gb[k] = 0.0;
-            if (!ok) {
-                rcs[b] = RVE_ENUMERIC;
-                hd->err = "singular or non-finite Anderson system";
-            }
+            if (!ok) slot_fail(rcs, b, RVE_ENUMERIC, RVE_WHY_ANDERSON, "singular or non-finite Anderson system");
         }
         CHK(upload_doubles(dgamma, gam));
         HIPCHK(launch_anderson_mix<T>(g, aG, sstride, dorder, dm1, dgamma, out, dmask[3], st));
@@ -1300,26 +1297,30 @@ struct Solver : SolverBase {
         if (slot < 0 || slot >= B) return fail(RVE_EINVAL, "slot out of range");
         if (!pid || !phases || nph <= 0) return fail(RVE_EINVAL, "phase_id and phases required");
         if (!(phi_M > 0.0 && phi_M < 1.0)) return fail(RVE_EINVAL, "phi_M must be in (0, 1)");
-        slope_warm[slot] = 0;
         for (int i = 0; i < nph; ++i) {
             const rve_phase& ph = phases[i];
             if (!(ph.Gc > 0.0) || !std::isfinite(ph.Gc)) return fail(RVE_EINVAL, "Gc must be > 0");
+            if (ph.beta != 0.0)
+                return fail(RVE_EINVAL, "cleavage anisotropy (beta != 0) is not supported: beta must be 0");
+            for (int a = 0; a < 3; ++a)
+                if (!std::isfinite(ph.n[a])) return fail(RVE_EINVAL, "non-finite cleavage normal");
             if (ph.kind == RVE_PHASE_ISO) {
-                if (!(ph.E > 0.0) || !(ph.nu > -1.0 && ph.nu < 0.5))
+                if (!(ph.E > 0.0) || !std::isfinite(ph.E) || !(ph.nu > -1.0 && ph.nu < 0.5))
                     return fail(RVE_EINVAL, "isotropic phase needs E > 0, -1 < nu < 0.5");
             } else if (ph.kind == RVE_PHASE_CUBIC) {
-                if (!(ph.C11 > std::fabs(ph.C12)) || !(ph.C11 + 2 * ph.C12 > 0) || !(ph.C44 > 0))
+                if (!std::isfinite(ph.C11) || !std::isfinite(ph.C12) || !std::isfinite(ph.C44) ||
+                    !(ph.C11 > std::fabs(ph.C12)) || !(ph.C11 + 2 * ph.C12 > 0) || !(ph.C44 > 0))
                     return fail(RVE_EINVAL, "cubic phase is not positive definite");
             } else {
                 return fail(RVE_EINVAL, "unknown phase kind");
             }
         }
-        SlotState& S = slots[slot];
-        S.ready = false;
+        // every input is checked (and the material table built) before the
+        // slot is touched
         std::map<std::tuple<int, double, int>, int> keys;
         std::vector<uint16_t> ids(g.N);
         std::vector<MatEntry<T>> table;
-        S.min_gc = INFINITY;
+        double min_gc = INFINITY;
         for (long long i = 0; i < g.N; ++i) {
             const int ph = pid[i];
             if (ph >= nph) return fail(RVE_EINVAL, "phase_id out of range");
@@ -1352,8 +1353,12 @@ struct Solver : SolverBase {
                 id = it->second;
             }
             ids[i] = (uint16_t)id;
-            S.min_gc = std::min(S.min_gc, phases[ph].Gc);
+            min_gc = std::min(min_gc, phases[ph].Gc);
         }
+        slope_warm[slot] = 0;
+        SlotState& S = slots[slot];
+        S.ready = false;
+        S.min_gc = min_gc;
         CHK(drain());
         HIPCHK(hipMemcpy(mat_id + (long long)slot * g.N, ids.data(), sizeof(uint16_t) * g.N,
                          hipMemcpyHostToDevice));
@@ -1419,223 +1424,363 @@ struct Solver : SolverBase {
         return RVE_OK;
     }
 
-    // ---- one lockstep step of the RVEs with dtau[b] > 0 ---------------------------
-    int step(const double* dtau, rve_step_info* info, int* status) override {
-        std::vector<int> act(B, 0), rcs(B, RVE_OK);
-        for (int b = 0; b < B; ++b) {
-            if (dtau[b] == 0.0) continue;
-            if (!slots[b].ready) { rcs[b] = RVE_ESTATE; continue; }
-            if (!(dtau[b] > 0.0) || !std::isfinite(dtau[b])) { rcs[b] = RVE_EINVAL; continue; }
-            act[b] = 1;
+    // ---- dissipation-controlled steps, every slot at its own pace ---------------
+    // Progress of one slot during an rve_run_slots call.  A step of dtau is an
+    // attempt at the full increment; an attempt that fails (any solver limit
+    // or a breakdown) leaves the committed state unchanged and is replaced by
+    // two attempts of half the increment, recursively down to max_halvings
+    // (dissipation control allows any subdivision of the increment).  If the
+    // deepest attempt fails too, the slot returns to the state it had when
+    // the step began.
+    struct Progress {
+        int stage = 0;                 // 0 nothing to do, 1 stagger, 2 final equilibrium + commit
+        int todo = 0;                  // steps still to take
+        double dtau = 0.0;             // increment of a step
+        std::deque<std::pair<double, int>> pend;   // sub-steps of the step: (increment, depth)
+        double tau = 0.0, E = 0.0;     // target dissipation and load of the attempt
+        int it = 0, nhist = 0;         // stagger iterations and Anderson history of the attempt
+        double ref = INFINITY;         // stall detection: best error, halved at iteration ref_it
+        int ref_it = 0;
+        bool sub_done = false;         // a sub-step of the step has been committed
+        bool snap = false;             // s_* hold the state at the start of the step
+        std::vector<char> s_phi, s_H, s_x, s_tan;
+        SlotState s_state;
+        int s_warm = 0;
+        bool stop_frac = false;
+        int n_steps = 0, n_sub = 0, n_stag = 0, n_cg = 0, n_pcg = 0, n_green = 0;
+        int status = RVE_OK, reason = RVE_WHY_NONE;
+        bool has_last = false;
+        rve_step_info last;
+    };
+
+    void begin_step(Progress& q) {
+        q.pend.clear();
+        q.pend.push_back({q.dtau, 0});
+        q.sub_done = false;
+        q.snap = false;
+        q.s_phi.clear(); q.s_H.clear(); q.s_x.clear(); q.s_tan.clear();
+    }
+    void begin_attempt(int b, Progress& q, std::vector<int>& fresh) {
+        q.tau = slots[b].tau + q.pend.front().first;
+        q.E = slots[b].E;
+        q.it = 0;
+        q.nhist = 0;
+        q.ref = INFINITY;
+        q.ref_it = 0;
+        q.stage = 1;
+        fresh[b] = 1;                  // phi_w <- phi_c, x <- x_c before the next equilibrium
+    }
+
+    // host copies of the committed fields of one slot (raw bytes of the bulk type)
+    int save_fields(int b, std::vector<char>& sphi, std::vector<char>& sH, std::vector<char>& sx,
+                    std::vector<char>& stan) {
+        CHK(drain());
+        const size_t fN = sizeof(T) * g.N, sN = fN * g.s;
+        sphi.resize(fN); sH.resize(fN); sx.resize(sN); stan.resize(fN);
+        HIPCHK(hipMemcpy(sphi.data(), phi_c + (long long)b * g.N, fN, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(sH.data(), Hn + (long long)b * g.N, fN, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(sx.data(), x_c + (long long)b * g.s * g.N, sN, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(stan.data(), tmp + (long long)b * g.N, fN, hipMemcpyDeviceToHost));
+        return RVE_OK;
+    }
+    int load_fields(int b, const char* sphi, const char* sH, const char* sx, const char* stan) {
+        CHK(drain());
+        const size_t fN = sizeof(T) * g.N, sN = fN * g.s;
+        HIPCHK(hipMemcpy(phi_c + (long long)b * g.N, sphi, fN, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(Hn + (long long)b * g.N, sH, fN, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(x_c + (long long)b * g.s * g.N, sx, sN, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(x + (long long)b * g.s * g.N, sx, sN, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(tmp + (long long)b * g.N, stan, fN, hipMemcpyHostToDevice));
+        return RVE_OK;
+    }
+
+    // A failed attempt of slot b (its working strain is already reset).
+    int on_failure(int b, Progress& q, int code, int why, std::vector<int>& fresh) {
+        const auto cur = q.pend.front();
+        const bool retry = (code == RVE_ENOCONV || code == RVE_ENUMERIC) && cur.second < cfg.max_halvings;
+        if (retry) {
+            // the first failure of a step comes before any of its sub-steps has
+            // committed: the committed state is still the one the step began from
+            if (!q.snap) {
+                CHK(save_fields(b, q.s_phi, q.s_H, q.s_x, q.s_tan));
+                q.s_state = slots[b];
+                q.s_warm = slope_warm[b];
+                q.snap = true;
+            }
+            q.pend.pop_front();
+            q.pend.push_front({0.5 * cur.first, cur.second + 1});
+            q.pend.push_front({0.5 * cur.first, cur.second + 1});
+            begin_attempt(b, q, fresh);
+            return RVE_OK;
         }
-        int rc = RVE_OK;
-        step_greens.assign(B, 0);
-        std::vector<double> dt(dtau, dtau + B);
-        if (any(act)) rc = step_split(dt, act, rcs, info, 0);
-        int worst = rc;
+        if (q.sub_done) {              // transactional: back to the start of the step
+            CHK(load_fields(b, q.s_phi.data(), q.s_H.data(), q.s_x.data(), q.s_tan.data()));
+            slots[b] = q.s_state;
+            slope_warm[b] = q.s_warm;
+        }
+        q.status = code;
+        q.reason = why;
+        q.stage = 0;
+        q.todo = 0;
+        return RVE_OK;
+    }
+
+    // Slots b with todo[b] > 0 take up to todo[b] steps of dtau[b] each
+    // (Eq. 16), at their own pace: a slot that commits a step starts its next
+    // one in the following round, while other slots are still iterating.
+    // Every launch of a round covers the slots that are in that phase.
+    int run(const double* dtau, const int* todo, int flags, rve_step_info* info, int* status) override {
+        std::vector<Progress> P(B);
+        std::vector<int> fresh(B, 0);
         for (int b = 0; b < B; ++b) {
-            if (status) status[b] = rc != RVE_OK && act[b] ? rc : rcs[b];
-            if (worst == RVE_OK && rcs[b] != RVE_OK) worst = rcs[b];
+            Progress& q = P[b];
+            if (todo[b] <= 0 || dtau[b] == 0.0) continue;
+            if (!slots[b].ready) { q.status = RVE_ESTATE; hd->err = "set_microstructure first"; continue; }
+            if (!(dtau[b] > 0.0) || !std::isfinite(dtau[b])) {
+                q.status = RVE_EINVAL;
+                hd->err = "dtau must be finite and > 0";
+                continue;
+            }
+            q.stop_frac = (flags & RVE_RUN_STOP_AT_FRACTURE) != 0;
+            if (q.stop_frac && slots[b].fractured) continue;
+            q.todo = todo[b];
+            q.dtau = dtau[b];
+            begin_step(q);
+            begin_attempt(b, q, fresh);
+        }
+        for (;;) {
+            std::vector<int> M(B, 0);
+            for (int b = 0; b < B; ++b) M[b] = P[b].stage != 0;
+            if (!any(M)) break;
+            if (any(fresh)) {
+                CHK(set_mask(0, fresh));
+                HIPCHK(launch_copy<T>(phi_c, phi_w, g.N, B, dmask[0], st));
+                HIPCHK(launch_copy<T>(x_c, x, g.s * g.N, B, dmask[0], st));
+                fresh.assign(B, 0);
+            }
+            std::vector<int> rc(B, RVE_OK), ncg(B, 0), npcg(B, 0);
+            why_.assign(B, RVE_WHY_NONE);
+            step_greens.assign(B, 0);
+            // (M) equilibrium at the working damage of every slot of the round
+            CHK(set_mask(1, M));
+            CHK(mech_solve(phi_w, 1, M, ncg, rc));
+            std::vector<int> ok(B, 0), C(B, 0), S(B, 0);
+            for (int b = 0; b < B; ++b) ok[b] = M[b] && rc[b] == RVE_OK;
+            std::vector<double> S1(B, 0.0), s2(B, 0.0);
+            if (any(ok)) {
+                CHK(set_mask(1, ok));
+                CHK(unit_response(phi_w, 1));
+                for (int b = 0; b < B; ++b) {
+                    if (!ok[b]) continue;
+                    S1[b] = sum_of(b, 0) / double(g.N);
+                    s2[b] = sum_of(b, 1);
+                    (P[b].stage == 2 ? C : S)[b] = 1;
+                }
+            }
+            // (A), (U) one stagger iteration of the slots still iterating; the
+            // slots committing below start their next attempt in the next round
+            if (any(S)) CHK(stagger_iteration(S, P, rc, npcg));
+            if (any(C)) CHK(commit(C, S1, s2, P, fresh));
+            for (int b = 0; b < B; ++b) {
+                if (!M[b]) continue;
+                P[b].n_cg += ncg[b];
+                P[b].n_pcg += npcg[b];
+                P[b].n_green += step_greens[b];
+            }
+            std::vector<int> failed(B, 0);
+            for (int b = 0; b < B; ++b) failed[b] = M[b] && rc[b] != RVE_OK;
+            if (any(failed)) {
+                CHK(set_mask(1, failed));
+                HIPCHK(launch_copy<T>(x_c, x, g.s * g.N, B, dmask[1], st));
+                for (int b = 0; b < B; ++b)
+                    if (failed[b]) CHK(on_failure(b, P[b], rc[b], why_[b], fresh));
+            }
+        }
+        int worst = RVE_OK;
+        for (int b = 0; b < B; ++b) {
+            const Progress& q = P[b];
+            if (status) status[b] = q.status;
+            if (worst == RVE_OK && q.status != RVE_OK) worst = q.status;
+            if (!info) continue;
+            rve_step_info o;
+            std::memset(&o, 0, sizeof(o));
+            if (q.has_last) {
+                o = q.last;
+            } else {
+                const SlotState& S0 = slots[b];
+                o.E = S0.E; o.Sigma = S0.Sigma; o.tau = S0.tau; o.T = S0.T;
+                o.fractured = S0.fractured ? 1 : 0;
+                o.step = S0.step;
+            }
+            o.n_stagger = q.n_stag;
+            o.n_cg = q.n_cg;
+            o.n_pcg = q.n_pcg;
+            o.n_greenop = q.n_green;
+            o.n_steps = q.n_steps;
+            o.n_substeps = q.n_sub;
+            o.reason = q.reason;
+            info[b] = o;
         }
         return worst;
     }
 
-    // One step of dt[b] for the slots in act.  At an unstable crack advance
-    // the staggered map can stall; dissipation control allows any
-    // subdivision of the increment, so a slot whose stagger has not
-    // converged within max_stagger iterations (its state left unchanged) is
-    // redone as two steps of dt / 2, down to dt / 2^kMaxHalvings.
-    int step_split(const std::vector<double>& dt, const std::vector<int>& act,
-                   std::vector<int>& rcs, rve_step_info* info, int depth) {
-        std::vector<int> r(rcs);
+    // One stagger iteration for the slots in S after their equilibrium solve:
+    // (A) the load E with D(phi(E)) = tau, (U) the convergence test on the
+    // relative changes of phi and E, and the next working damage (Anderson
+    // mixing of the iterates, or the plain fixed-point step).
+    int stagger_iteration(const std::vector<int>& S, std::vector<Progress>& P, std::vector<int>& rc,
+                          std::vector<int>& npcg) {
+        std::vector<double> tau(B, 0.0), E(B, 0.0), En(B, 0.0);
         for (int b = 0; b < B; ++b)
-            if (act[b]) r[b] = RVE_OK;
-        stag_fail.assign(B, 0);
-        CHK(step_impl(dt.data(), act, r, info));
-        // transactional: a failed slot restarts its working strain from the committed one
-        std::vector<int> failed(B, 0);
-        for (int b = 0; b < B; ++b) failed[b] = act[b] && r[b] != RVE_OK;
-        if (any(failed)) {
-            CHK(set_mask(1, failed));
-            HIPCHK(launch_copy<T>(x_c, x, g.s * g.N, B, dmask[1], st));
-            CHK(drain());
-        }
-        std::vector<int> redo(B, 0);
-        std::vector<double> half(B, 0.0);
+            if (S[b]) { tau[b] = P[b].tau; E[b] = P[b].E; }
+        CHK(set_mask(1, S));
+        HIPCHK(launch_copy<T>(phi_w, px, g.N, B, dmask[1], st));
+        CHK(arclength(tau, E, px, S, En, npcg, rc));
+        HIPCHK(launch_diff_norms<T>(px, phi_w, g.N, B, partials, nred, dmask[1], st));
+        HIPCHK(launch_sum_partials(partials, nred, 2, B, sums, dmask[1], st));
+        CHK(read_sums(2));
+        std::vector<int> take(B, 0), mixing(B, 0);
         for (int b = 0; b < B; ++b) {
-            if (!act[b]) continue;
-            if (r[b] == RVE_ENOCONV && stag_fail[b] && depth < kMaxHalvings) {
-                redo[b] = 1;
-                half[b] = 0.5 * dt[b];
+            if (!S[b]) continue;
+            Progress& q = P[b];
+            q.it += 1;
+            q.n_stag += 1;
+            if (rc[b] != RVE_OK) continue;
+            const double dphi = std::sqrt(sum_of(b, 0)) / std::max(std::sqrt(sum_of(b, 1)), 1e-300);
+            const double dEr = std::fabs(En[b] - q.E) / std::max(std::fabs(En[b]), 1e-300);
+            const double err = std::max(dphi, dEr);
+            if (trace)
+                std::fprintf(stderr, "[mirve] slot %d step %d stagger %d dphi %.3e dE %.3e E %.9g\n",
+                             b, slots[b].step + 1, q.it, dphi, dEr, En[b]);
+            q.E = En[b];
+            if (err < 0.5 * q.ref) { q.ref = err; q.ref_it = q.it; }
+            if (!std::isfinite(err)) {
+                slot_fail(rc, b, RVE_ENUMERIC, RVE_WHY_BREAKDOWN, "non-finite stagger update");
+            } else if (err < cfg.tol) {
+                take[b] = 1;
+                q.stage = 2;
+            } else if (q.it >= cfg.max_stagger ||
+                       (cfg.stall_window > 0 && q.it - q.ref_it >= cfg.stall_window)) {
+                slot_fail(rc, b, RVE_ENOCONV, RVE_WHY_STAGGER,
+                          q.it >= cfg.max_stagger ? "stagger did not converge within max_stagger"
+                                                  : "stagger stalled (no halving of its error within stall_window)");
+            } else if (m1_max > 1) {
+                mixing[b] = 1;
             } else {
-                rcs[b] = r[b];
+                take[b] = 1;
             }
         }
-        if (!any(redo)) return RVE_OK;
-        std::vector<int> r2(rcs);
-        CHK(step_split(half, redo, r2, info, depth + 1));
-        std::vector<int> again(B, 0);
-        for (int b = 0; b < B; ++b) again[b] = redo[b] && r2[b] == RVE_OK;
-        if (any(again)) CHK(step_split(half, again, r2, info, depth + 1));
-        for (int b = 0; b < B; ++b)
-            if (redo[b]) rcs[b] = r2[b];
+        // converged, or no mixing: phi_w = phi(E)
+        if (any(take)) {
+            CHK(set_mask(2, take));
+            HIPCHK(launch_copy<T>(px, phi_w, g.N, B, dmask[2], st));
+        }
+        if (!any(mixing)) return RVE_OK;
+        // push F = phi(E) - phi_w and G = phi(E) into each slot's ring
+        for (int ring = 0; ring < m1_max; ++ring) {
+            std::vector<int> ms(B, 0);
+            bool a = false;
+            for (int b = 0; b < B; ++b)
+                if (mixing[b] && P[b].nhist % m1_max == ring) { ms[b] = 1; a = true; }
+            if (!a) continue;
+            CHK(set_mask(2, ms));
+            T* Fs = aF + (long long)ring * g.N * B;
+            T* Gs = aG + (long long)ring * g.N * B;
+            HIPCHK(launch_sub<T>(px, phi_w, Fs, g.N, B, dmask[2], st));
+            HIPCHK(launch_copy<T>(px, Gs, g.N, B, dmask[2], st));
+        }
+        std::vector<int> mix2(B, 0), first(B, 0), nh(B, 0);
+        for (int b = 0; b < B; ++b) {
+            if (!mixing[b]) continue;
+            P[b].nhist += 1;
+            nh[b] = P[b].nhist;
+            if (P[b].nhist >= 2) mix2[b] = 1;
+            else first[b] = 1;
+        }
+        if (any(first)) {
+            CHK(set_mask(2, first));
+            HIPCHK(launch_copy<T>(px, phi_w, g.N, B, dmask[2], st));
+        }
+        if (any(mix2)) CHK(anderson_mix(mix2, nh, phi_w, rc));
         return RVE_OK;
     }
 
-    int step_impl(const double* dtau, const std::vector<int>& act, std::vector<int>& rcs,
-                  rve_step_info* info) {
-        greenops = 0;
-        std::vector<double> tau(B, 0.0), E(B, 0.0), En(B, 0.0);
-        std::vector<int> ncg(B, 0), npcg(B, 0), nst(B, 0), nhist(B, 0), stag = act, conv(B, 0);
-        for (int b = 0; b < B; ++b) {
-            tau[b] = slots[b].tau + (act[b] ? dtau[b] : 0.0);
-            E[b] = slots[b].E;
-        }
-        CHK(set_mask(0, act));
-        HIPCHK(launch_copy<T>(phi_c, phi_w, g.N, B, dmask[0], st));
-        HIPCHK(launch_copy<T>(x_c, x, g.s * g.N, B, dmask[0], st));
-        for (int it = 1; it <= cfg.max_stagger && any(stag); ++it) {
-            CHK(set_mask(1, stag));
-            CHK(mech_solve(phi_w, 1, stag, ncg, rcs));
-            CHK(unit_response(phi_w, 1));
-            HIPCHK(launch_copy<T>(phi_w, px, g.N, B, dmask[1], st));
-            CHK(arclength(tau, E, px, stag, En, npcg, rcs));
-            HIPCHK(launch_diff_norms<T>(px, phi_w, g.N, B, partials, nred, dmask[1], st));
-            HIPCHK(launch_sum_partials(partials, nred, 2, B, sums, dmask[1], st));
-            CHK(read_sums(2));
-            std::vector<int> done(B, 0), mixing(B, 0), plain(B, 0);
-            for (int b = 0; b < B; ++b) {
-                if (!stag[b]) continue;
-                nst[b] = it;
-                if (rcs[b] != RVE_OK) { stag[b] = 0; continue; }
-                const double dphi = std::sqrt(sum_of(b, 0)) / std::max(std::sqrt(sum_of(b, 1)), 1e-300);
-                const double dEr = std::fabs(En[b] - E[b]) / std::max(std::fabs(En[b]), 1e-300);
-                const double err = std::max(dphi, dEr);
-                if (trace)
-                    std::fprintf(stderr, "[mirve] slot %d step %d stagger %d dphi %.3e dE %.3e E %.9g\n",
-                                 b, slots[b].step + 1, it, dphi, dEr, En[b]);
-                E[b] = En[b];
-                if (!std::isfinite(err)) {
-                    rcs[b] = RVE_ENUMERIC;
-                    hd->err = "non-finite stagger update";
-                    stag[b] = 0;
-                } else if (err < cfg.tol) {
-                    done[b] = 1;
-                    conv[b] = 1;
-                    stag[b] = 0;
-                } else if (m1_max > 1) {
-                    mixing[b] = 1;
-                } else {
-                    plain[b] = 1;
-                }
-            }
-            // converged: phi_w = phi(E); no mixing: phi_w = phi(E)
-            std::vector<int> take(B, 0);
-            for (int b = 0; b < B; ++b) take[b] = done[b] || plain[b];
-            if (any(take)) {
-                CHK(set_mask(2, take));
-                HIPCHK(launch_copy<T>(px, phi_w, g.N, B, dmask[2], st));
-            }
-            if (any(mixing)) {
-                // push F = phi(E) - phi_w and G = phi(E) into each RVE's ring slot
-                for (int slot = 0; slot < m1_max; ++slot) {
-                    std::vector<int> ms(B, 0);
-                    bool a = false;
-                    for (int b = 0; b < B; ++b)
-                        if (mixing[b] && nhist[b] % m1_max == slot) { ms[b] = 1; a = true; }
-                    if (!a) continue;
-                    CHK(set_mask(2, ms));
-                    T* Fs = aF + (long long)slot * g.N * B;
-                    T* Gs = aG + (long long)slot * g.N * B;
-                    HIPCHK(launch_sub<T>(px, phi_w, Fs, g.N, B, dmask[2], st));
-                    HIPCHK(launch_copy<T>(px, Gs, g.N, B, dmask[2], st));
-                }
-                std::vector<int> mix2(B, 0), first(B, 0);
-                for (int b = 0; b < B; ++b) {
-                    if (!mixing[b]) continue;
-                    nhist[b] += 1;
-                    if (nhist[b] >= 2) mix2[b] = 1;
-                    else first[b] = 1;
-                }
-                if (any(first)) {
-                    CHK(set_mask(2, first));
-                    HIPCHK(launch_copy<T>(px, phi_w, g.N, B, dmask[2], st));
-                }
-                if (any(mix2)) CHK(anderson_mix(mix2, nhist, phi_w, rcs));
-                for (int b = 0; b < B; ++b)
-                    if (mix2[b] && rcs[b] != RVE_OK) stag[b] = 0;
-            }
-        }
+    // Commit the slots in C after the final equilibrium at their converged
+    // damage (S1, s2: its unit-load stress sums): residuals of Eq. 24, history
+    // (Eq. 38), committed fields, dissipation, fracture test, the trapezoid of
+    // Eq. 33; then each slot's next sub-step or step.
+    int commit(const std::vector<int>& C, const std::vector<double>& S1, const std::vector<double>& s2,
+               std::vector<Progress>& P, std::vector<int>& fresh) {
+        std::vector<double> E(B, 0.0), R1(B, 0.0), R2(B, 0.0), D(B, 0.0), G(B, 0.0);
         for (int b = 0; b < B; ++b)
-            if (act[b] && rcs[b] == RVE_OK && !conv[b]) {
-                rcs[b] = RVE_ENOCONV;
-                stag_fail[b] = 1;
-                hd->err = "stagger did not converge";
-            }
-        std::vector<int> ok(B, 0);
-        for (int b = 0; b < B; ++b) ok[b] = act[b] && rcs[b] == RVE_OK;
-        if (!any(ok)) return RVE_OK;
-        // final equilibrium at the converged damage, then commit
-        CHK(set_mask(1, ok));
-        CHK(mech_solve(phi_w, 1, ok, ncg, rcs));
-        for (int b = 0; b < B; ++b) ok[b] = ok[b] && rcs[b] == RVE_OK;
-        CHK(set_mask(1, ok));
-        CHK(unit_response(phi_w, 1));
-        std::vector<double> S1(B, 0.0), s2(B, 0.0), R1(B, 0.0), R2(B, 0.0);
-        for (int b = 0; b < B; ++b)
-            if (ok[b]) { S1[b] = sum_of(b, 0) / double(g.N); s2[b] = sum_of(b, 1); }
+            if (C[b]) E[b] = P[b].E;
+        CHK(set_mask(1, C));
         // residuals of the committed state: R1 (equilibrium) and R2 (damage with
         // the H of the last damage solve)
         CHK(green(phi_w, x, 1.0, nullptr, 1.0, cgpB, dmask[1]));
         HIPCHK(launch_sum_rows(cgpB, nbx, B, sums, 0, st));
         CHK(read_sums(1));
         for (int b = 0; b < B; ++b)
-            if (ok[b]) R1[b] = std::sqrt(sum_of(b, 0)) / std::max(std::sqrt(s2[b]), 1e-300);
+            if (C[b]) R1[b] = std::sqrt(sum_of(b, 0)) / std::max(std::sqrt(s2[b]), 1e-300);
         HIPCHK(launch_damage_residual<T>(g, mat_id, mat, H, phi_w, partials, nred, dmask[1], st));
         HIPCHK(launch_sum_partials(partials, nred, 2, B, sums, dmask[1], st));
         CHK(read_sums(2));
         for (int b = 0; b < B; ++b)
-            if (ok[b]) R2[b] = std::sqrt(sum_of(b, 0)) / std::max(std::sqrt(sum_of(b, 1)), 1e-300);
+            if (C[b]) R2[b] = std::sqrt(sum_of(b, 0)) / std::max(std::sqrt(sum_of(b, 1)), 1e-300);
         CHK(upload_doubles(dE, E));
         HIPCHK(launch_commit_history<T>(g, psi1, psi_ini, dE, cfg.history, Hn, dmask[1], st));
         HIPCHK(launch_copy<T>(phi_w, phi_c, g.N, B, dmask[1], st));
         HIPCHK(launch_copy<T>(x, x_c, g.s * g.N, B, dmask[1], st));
         CHK(dissip(phi_c, 1));
-        std::vector<double> D(B, 0.0), G(B, 0.0);
         for (int b = 0; b < B; ++b)
-            if (ok[b]) { D[b] = sum_of(b, 0) * hd_(); G[b] = sum_of(b, 1) * hd_(); }
+            if (C[b]) { D[b] = sum_of(b, 0) * hd_(); G[b] = sum_of(b, 1) * hd_(); }
         HIPCHK(launch_zero_int(count, B, st));
         HIPCHK(launch_fracture_count<T>(g, mat_id, mat, phi_c, cfg.frac_threshold, load_axis, count,
                                         dmask[1], st));
         HIPCHK(hipMemcpyAsync(h_count, count, sizeof(int) * B, hipMemcpyDeviceToHost, st));
         CHK(drain());
         for (int b = 0; b < B; ++b) {
-            if (!ok[b]) continue;
-            SlotState& S = slots[b];
+            if (!C[b]) continue;
+            Progress& q = P[b];
+            SlotState& Ss = slots[b];
+            step_greens[b] += 1;       // the R1 check
             const double Sigma = E[b] * S1[b];
-            S.T += 0.5 * (Sigma + S.Sigma) * (E[b] - S.E);
-            S.E = E[b];
-            S.Sigma = Sigma;
-            S.tau = tau[b];
-            S.step += 1;
-            S.fractured = h_count[b] == 0;
-            if (info) {
-                rve_step_info& o = info[b];
-                o.E = E[b];
-                o.Sigma = Sigma;
-                o.D = D[b];
-                o.Gamma = G[b];
-                o.tau = tau[b];
-                o.T = S.T;
-                o.n_stagger = nst[b];
-                o.n_cg = ncg[b];
-                o.n_pcg = npcg[b];
-                o.n_greenop = step_greens[b] + 1;   // mechanics solves + the R1 check
-                o.res_R1 = R1[b];
-                o.res_R2 = R2[b];
-                o.res_R3 = std::fabs(D[b] - tau[b]) / tau[b];
-                o.fractured = S.fractured ? 1 : 0;
-                o.step = S.step;
+            Ss.T += 0.5 * (Sigma + Ss.Sigma) * (E[b] - Ss.E);
+            Ss.E = E[b];
+            Ss.Sigma = Sigma;
+            Ss.tau = q.tau;
+            Ss.step += 1;
+            Ss.fractured = h_count[b] == 0;
+            rve_step_info& o = q.last;
+            std::memset(&o, 0, sizeof(o));
+            o.E = E[b];
+            o.Sigma = Sigma;
+            o.D = D[b];
+            o.Gamma = G[b];
+            o.tau = q.tau;
+            o.T = Ss.T;
+            o.res_R1 = R1[b];
+            o.res_R2 = R2[b];
+            o.res_R3 = std::fabs(D[b] - q.tau) / q.tau;
+            o.fractured = Ss.fractured ? 1 : 0;
+            o.step = Ss.step;
+            q.has_last = true;
+            q.n_sub += 1;
+            q.sub_done = true;
+            q.pend.pop_front();
+            if (!q.pend.empty()) {     // the next sub-step of this step
+                begin_attempt(b, q, fresh);
+                continue;
+            }
+            q.n_steps += 1;
+            q.todo -= 1;
+            q.snap = false;
+            q.s_phi.clear(); q.s_H.clear(); q.s_x.clear(); q.s_tan.clear();
+            if (q.todo > 0 && !(q.stop_frac && Ss.fractured)) {
+                begin_step(q);
+                begin_attempt(b, q, fresh);
+            } else {
+                q.stage = 0;
             }
         }
         return RVE_OK;
@@ -1748,6 +1893,66 @@ struct Solver : SolverBase {
         CHK(dissip(phi_c, 0));
         if (D) *D = sum_of(slot, 0) * hd_();
         if (G) *G = sum_of(slot, 1) * hd_();
+        return RVE_OK;
+    }
+
+    // ---- checkpoints ------------------------------------------------------------
+    // Blob: a header (magic, precision, grid), the slot's scalars, then the raw
+    // committed fields phi, H^n, the strain fluctuation and the tangent warm
+    // start, in the bulk type.
+    struct StateHeader {
+        uint32_t magic, word;
+        int32_t dim, n[3];
+        double E, Sigma, Tc, tau, tau0;
+        int32_t step, fractured, warm, pad;
+    };
+    static constexpr uint32_t kStateMagic = 0x4d525653u;   // "MRVS"
+    size_t state_bytes() const override {
+        return sizeof(StateHeader) + sizeof(T) * (size_t)g.N * (3 + g.s);
+    }
+    int save_state(int slot, void* host, size_t bytes) override {
+        CHK(check_slot(slot));
+        if (!host || bytes < state_bytes()) return fail(RVE_EINVAL, "state buffer too small");
+        StateHeader hdr;
+        std::memset(&hdr, 0, sizeof(hdr));
+        hdr.magic = kStateMagic;
+        hdr.word = sizeof(T);
+        hdr.dim = g.dim; hdr.n[0] = g.nx; hdr.n[1] = g.ny; hdr.n[2] = g.nz;
+        const SlotState& S = slots[slot];
+        hdr.E = S.E; hdr.Sigma = S.Sigma; hdr.Tc = S.T; hdr.tau = S.tau; hdr.tau0 = S.tau0;
+        hdr.step = S.step; hdr.fractured = S.fractured ? 1 : 0; hdr.warm = slope_warm[slot];
+        std::vector<char> a, b, c, d;
+        CHK(save_fields(slot, a, b, c, d));
+        char* o = (char*)host;
+        std::memcpy(o, &hdr, sizeof(hdr)); o += sizeof(hdr);
+        for (auto* v : {&a, &b, &c, &d}) { std::memcpy(o, v->data(), v->size()); o += v->size(); }
+        return RVE_OK;
+    }
+    int load_state(int slot, const void* host, size_t bytes) override {
+        CHK(check_slot(slot));
+        if (!host || bytes < state_bytes()) return fail(RVE_EINVAL, "state buffer too small");
+        StateHeader hdr;
+        std::memcpy(&hdr, host, sizeof(hdr));
+        if (hdr.magic != kStateMagic || hdr.word != sizeof(T) || hdr.dim != g.dim || hdr.n[0] != g.nx ||
+            hdr.n[1] != g.ny || hdr.n[2] != g.nz)
+            return fail(RVE_EINVAL, "state blob of another grid or precision");
+        const double sc[5] = {hdr.E, hdr.Sigma, hdr.Tc, hdr.tau, hdr.tau0};
+        for (double v : sc)
+            if (!std::isfinite(v)) return fail(RVE_EINVAL, "non-finite scalar in state blob");
+        const size_t fN = sizeof(T) * g.N, sN = fN * g.s;
+        const char* p = (const char*)host + sizeof(hdr);
+        const T* fields = reinterpret_cast<const T*>(p);
+        const size_t cnt = (size_t)g.N * (3 + g.s);
+        for (size_t i = 0; i < cnt; ++i) {
+            T v;
+            std::memcpy(&v, (const char*)fields + i * sizeof(T), sizeof(T));
+            if (!std::isfinite((double)v)) return fail(RVE_EINVAL, "non-finite field value in state blob");
+        }
+        CHK(load_fields(slot, p, p + fN, p + 2 * fN, p + 2 * fN + sN));
+        SlotState& S = slots[slot];
+        S.E = hdr.E; S.Sigma = hdr.Sigma; S.T = hdr.Tc; S.tau = hdr.tau; S.tau0 = hdr.tau0;
+        S.step = hdr.step; S.fractured = hdr.fractured != 0;
+        slope_warm[slot] = hdr.warm ? 1 : 0;
         return RVE_OK;
     }
 
@@ -2003,8 +2208,13 @@ static int validate(const rve_config* c, std::string& why) {
     if (!(c->h > 0) || !(c->ell > 0) || !(c->k_res > 0)) { why = "h, ell, k_res must be > 0"; return RVE_EINVAL; }
     if (c->split != RVE_SPLIT_NONE && c->split != RVE_SPLIT_VOLDEV) { why = "bad split"; return RVE_EINVAL; }
     if (c->precision != RVE_PREC_FP64 && c->precision != RVE_PREC_MIXED) { why = "bad precision"; return RVE_EINVAL; }
-    if (!(c->tol > 0) || !(c->tol_cg > 0) || !(c->tol_pcg > 0) || !(c->tol_al > 0)) { why = "tolerances must be > 0"; return RVE_EINVAL; }
+    if (!(c->tol >= 0) || !(c->tol_cg >= 0) || !(c->tol_pcg >= 0) || !(c->tol_al >= 0)) {
+        why = "tolerances must be >= 0 (0: the precision's default)";
+        return RVE_EINVAL;
+    }
     if (c->max_stagger < 1 || c->max_cg < 1 || c->max_pcg < 1) { why = "iteration limits must be >= 1"; return RVE_EINVAL; }
+    if (c->max_halvings < 0 || c->max_halvings > 12) { why = "max_halvings in [0, 12]"; return RVE_EINVAL; }
+    if (c->stall_window < 0) { why = "stall_window must be >= 0"; return RVE_EINVAL; }
     if (c->anderson_depth < 0 || c->anderson_depth > kAndersonMax) { why = "anderson_depth in [0, 5]"; return RVE_EINVAL; }
     if (c->max_materials < 1 || c->max_materials > kMaxMat) { why = "max_materials in [1, 65536]"; return RVE_EINVAL; }
     if (c->batch < 1 || c->batch > 1024) { why = "batch in [1, 1024]"; return RVE_EINVAL; }
@@ -2036,6 +2246,17 @@ static int geom_check(const rve_config* c, Geom& g, int& nbx, std::string& why) 
 
 static thread_local std::string g_last_error;
 
+// A tolerance of 0 takes the default of the precision mode.  FP32 fields
+// resolve D(E) to about 1e-7, so in mixed precision the constraint is held
+// to 1e-6 and the damage solves that evaluate it to 1e-7.
+static void resolve_defaults(rve_config& c) {
+    const bool mixed = c.precision == RVE_PREC_MIXED;
+    if (c.tol == 0.0) c.tol = mixed ? 1e-5 : 1e-8;
+    if (c.tol_cg == 0.0) c.tol_cg = mixed ? 1e-6 : 1e-10;
+    if (c.tol_pcg == 0.0) c.tol_pcg = mixed ? 1e-7 : 1e-12;
+    if (c.tol_al == 0.0) c.tol_al = mixed ? 1e-6 : 1e-10;
+}
+
 extern "C" {
 
 int rve_default_config(rve_config* c) {
@@ -2051,11 +2272,13 @@ int rve_default_config(rve_config* c) {
     c->split = RVE_SPLIT_NONE;
     c->history = 1;
     c->precision = RVE_PREC_FP64;
-    c->tol = 1e-8;
-    c->tol_cg = 1e-10;
-    c->tol_pcg = 1e-12;
-    c->tol_al = 1e-10;
+    c->tol = 0.0;          // the precision's defaults (resolve_defaults)
+    c->tol_cg = 0.0;
+    c->tol_pcg = 0.0;
+    c->tol_al = 0.0;
     c->max_stagger = 100;
+    c->max_halvings = 4;
+    c->stall_window = 0;
     c->max_cg = 20000;
     c->max_pcg = 20000;
     c->anderson_depth = 5;
@@ -2098,14 +2321,16 @@ int rve_create(const rve_config* c, void* ws, size_t wsb, void* stream, rve_hand
     if (wsb < need) { g_last_error = "workspace too small"; return RVE_ENOSPC; }
     if ((reinterpret_cast<uintptr_t>(ws) & 255) != 0) { g_last_error = "workspace not 256-byte aligned"; return RVE_EINVAL; }
     auto* h = new rve_handle_s();
-    h->cfg = *c;
+    rve_config cr = *c;
+    resolve_defaults(cr);
+    h->cfg = cr;
     hipStream_t st = (hipStream_t)stream;
     if (c->precision == RVE_PREC_FP64) {
-        auto* s = new Solver<double>(h, *c, ws, st);
+        auto* s = new Solver<double>(h, cr, ws, st);
         h->impl.reset(s);
         rc = s->init_device();
     } else {
-        auto* s = new Solver<float>(h, *c, ws, st);
+        auto* s = new Solver<float>(h, cr, ws, st);
         h->impl.reset(s);
         rc = s->init_device();
     }
@@ -2140,17 +2365,25 @@ int rve_set_microstructure(rve_handle h, const uint16_t* phase_id, const rve_pha
                                        phi_M);
 }
 
+int rve_run_slots(rve_handle h, const double* dtau, const int* max_steps, int flags,
+                  rve_step_info* info, int* status) {
+    if (!h || !dtau || !max_steps) return RVE_EINVAL;
+    if (flags & ~RVE_RUN_STOP_AT_FRACTURE) { h->err = "unknown flags"; return RVE_EINVAL; }
+    return h->impl->run(dtau, max_steps, flags, info, status);
+}
+
 int rve_step_dissipation_slots(rve_handle h, const double* dtau, rve_step_info* info, int* status) {
     if (!h || !dtau) return RVE_EINVAL;
-    return h->impl->step(dtau, info, status);
+    std::vector<int> one(h->impl->B, 1);
+    return h->impl->run(dtau, one.data(), 0, info, status);
 }
 
 int rve_step_dissipation(rve_handle h, double dtau, rve_step_info* out) {
     if (!h) return RVE_EINVAL;
     if (h->impl->B != 1) { h->err = "batched handle: use rve_step_dissipation_slots"; return RVE_EINVAL; }
-    if (dtau == 0.0) { h->err = "dtau must be > 0"; return RVE_EINVAL; }
-    int status = RVE_OK;
-    int rc = h->impl->step(&dtau, out, &status);
+    if (!(dtau > 0.0) || !std::isfinite(dtau)) { h->err = "dtau must be finite and > 0"; return RVE_EINVAL; }
+    int status = RVE_OK, one = 1;
+    int rc = h->impl->run(&dtau, &one, 0, out, &status);
     return rc != RVE_OK ? rc : status;
 }
 
@@ -2196,6 +2429,20 @@ int rve_set_field_slot(rve_handle h, int slot, int which, const double* host, si
 }
 int rve_set_field(rve_handle h, int which, const double* host, size_t count) {
     return rve_set_field_slot(h, 0, which, host, count);
+}
+
+int rve_state_bytes(rve_handle h, size_t* bytes) {
+    if (!h || !bytes) return RVE_EINVAL;
+    *bytes = h->impl->state_bytes();
+    return RVE_OK;
+}
+int rve_save_state(rve_handle h, int slot, void* host, size_t bytes) {
+    if (!h || slot < 0 || slot >= h->impl->B) return RVE_EINVAL;
+    return h->impl->save_state(slot, host, bytes);
+}
+int rve_load_state(rve_handle h, int slot, const void* host, size_t bytes) {
+    if (!h || slot < 0 || slot >= h->impl->B) return RVE_EINVAL;
+    return h->impl->load_state(slot, host, bytes);
 }
 
 int rve_get_scalars_slot(rve_handle h, int slot, double* o) {

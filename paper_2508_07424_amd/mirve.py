@@ -32,6 +32,9 @@ RVE_PRECOND_FFT = 0
 RVE_PRECOND_JACOBI = 1
 RVE_PHASE_ISO = 0
 RVE_PHASE_CUBIC = 1
+RVE_RUN_STOP_AT_FRACTURE = 1
+WHY = {0: "none", 1: "stagger", 2: "cg", 3: "pcg", 4: "arclength", 5: "split", 6: "breakdown",
+       7: "anderson"}
 
 FIELDS = {"phi": 0, "hist": 1, "psi_ini": 2, "eps1": 3, "sig1": 4, "psi1": 5, "phi_ini": 6}
 
@@ -44,7 +47,8 @@ EXPORTS = ["rve_default_config", "rve_query_workspace", "rve_create", "rve_destr
            "rve_get_scalars", "rve_set_scalars", "rve_get_scalars_slot", "rve_set_scalars_slot",
            "rve_apply_green_op", "rve_apply_green_op_device", "rve_solve_mechanics",
            "rve_solve_damage", "rve_dissipation", "rve_profile_pass", "rve_autotune",
-           "rve_last_error", "rve_version"]
+           "rve_last_error", "rve_version", "rve_run_slots", "rve_state_bytes", "rve_save_state",
+           "rve_load_state"]
 
 
 class rve_config(C.Structure):
@@ -52,7 +56,8 @@ class rve_config(C.Structure):
                 ("k_res", C.c_double), ("f", C.c_double * 6), ("split", C.c_int),
                 ("history", C.c_int), ("precision", C.c_int), ("tol", C.c_double),
                 ("tol_cg", C.c_double), ("tol_pcg", C.c_double), ("tol_al", C.c_double),
-                ("max_stagger", C.c_int), ("max_cg", C.c_int), ("max_pcg", C.c_int),
+                ("max_stagger", C.c_int), ("max_halvings", C.c_int), ("stall_window", C.c_int),
+                ("max_cg", C.c_int), ("max_pcg", C.c_int),
                 ("anderson_depth", C.c_int), ("frac_threshold", C.c_double), ("A_g", C.c_double),
                 ("max_materials", C.c_int), ("batch", C.c_int), ("damage_precond", C.c_int),
                 ("graphs", C.c_int), ("streaming", C.c_int)]
@@ -60,7 +65,8 @@ class rve_config(C.Structure):
 
 class rve_phase(C.Structure):
     _fields_ = [("kind", C.c_int), ("E", C.c_double), ("nu", C.c_double), ("C11", C.c_double),
-                ("C12", C.c_double), ("C44", C.c_double), ("Gc", C.c_double)]
+                ("C12", C.c_double), ("C44", C.c_double), ("Gc", C.c_double), ("beta", C.c_double),
+                ("n", C.c_double * 3)]
 
 
 class rve_step_info(C.Structure):
@@ -68,7 +74,8 @@ class rve_step_info(C.Structure):
                 ("Gamma", C.c_double), ("tau", C.c_double), ("T", C.c_double),
                 ("n_stagger", C.c_int), ("n_cg", C.c_int), ("n_pcg", C.c_int),
                 ("n_greenop", C.c_int), ("res_R1", C.c_double), ("res_R2", C.c_double),
-                ("res_R3", C.c_double), ("fractured", C.c_int), ("step", C.c_int)]
+                ("res_R3", C.c_double), ("fractured", C.c_int), ("step", C.c_int),
+                ("n_steps", C.c_int), ("n_substeps", C.c_int), ("reason", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -91,6 +98,11 @@ def _load():
         "rve_set_microstructure": (I, [P, P, C.POINTER(rve_phase), I, P, P, P, D]),
         "rve_set_microstructure_slot": (I, [P, I, P, C.POINTER(rve_phase), I, P, P, P, D]),
         "rve_step_dissipation_slots": (I, [P, dp, C.POINTER(rve_step_info), C.POINTER(C.c_int)]),
+        "rve_run_slots": (I, [P, dp, C.POINTER(C.c_int), I, C.POINTER(rve_step_info),
+                              C.POINTER(C.c_int)]),
+        "rve_state_bytes": (I, [P, C.POINTER(C.c_size_t)]),
+        "rve_save_state": (I, [P, I, P, S]),
+        "rve_load_state": (I, [P, I, P, S]),
         "rve_batch_size": (I, [P]),
         "rve_release_slot": (I, [P, I]),
         "rve_effective_toughness_slot": (I, [P, I, dp]),
@@ -158,11 +170,7 @@ def make_config(n, h=1.0, ell=1.5, k=1e-6, f=None, precision=RVE_PREC_FP64, **kw
         ff[:s] = np.asarray(f, dtype=float)[:s]
     for i in range(6):
         c.f[i] = ff[i]
-    c.precision = precision
-    if precision == RVE_PREC_MIXED:
-        # FP32 fields resolve D(E) to about 1e-7: the constraint is held to
-        # 1e-6, the damage solves that evaluate it to 1e-7
-        c.tol, c.tol_cg, c.tol_pcg, c.tol_al = 1e-5, 1e-6, 1e-7, 1e-6
+    c.precision = precision          # tolerances left at 0 take the precision's defaults
     for key, v in kw.items():
         setattr(c, key, v)
     return c
@@ -180,9 +188,11 @@ def phases_array(phases):
     arr = (rve_phase * len(phases))()
     for i, ph in enumerate(phases):
         if ph["kind"] == "iso":
-            arr[i] = rve_phase(RVE_PHASE_ISO, ph["E"], ph["nu"], 0.0, 0.0, 0.0, ph["Gc"])
+            arr[i] = rve_phase(RVE_PHASE_ISO, ph["E"], ph["nu"], 0.0, 0.0, 0.0, ph["Gc"],
+                               ph.get("beta", 0.0))
         else:
-            arr[i] = rve_phase(RVE_PHASE_CUBIC, 0.0, 0.0, ph["C11"], ph["C12"], ph["C44"], ph["Gc"])
+            arr[i] = rve_phase(RVE_PHASE_CUBIC, 0.0, 0.0, ph["C11"], ph["C12"], ph["C44"], ph["Gc"],
+                               ph.get("beta", 0.0))
     return arr
 
 
@@ -250,6 +260,29 @@ class Rve:
         status = (C.c_int * self.B)()
         lib.rve_step_dissipation_slots(self.h, _dptr(dt), infos, status)
         return [infos[i].as_dict() for i in range(self.B)], [status[i] for i in range(self.B)]
+
+    def rve_run_slots(self, dtaus, max_steps, stop_at_fracture=False):
+        """Up to max_steps[b] steps of dtaus[b] per slot, each slot at its own
+        pace.  Returns (infos, status)."""
+        dt = np.ascontiguousarray(dtaus, dtype=np.float64)
+        ms = np.ascontiguousarray(max_steps, dtype=np.int32)
+        assert dt.size == self.B and ms.size == self.B
+        infos = (rve_step_info * self.B)()
+        status = (C.c_int * self.B)()
+        lib.rve_run_slots(self.h, _dptr(dt), ms.ctypes.data_as(C.POINTER(C.c_int)),
+                          RVE_RUN_STOP_AT_FRACTURE if stop_at_fracture else 0, infos, status)
+        return [infos[i].as_dict() for i in range(self.B)], [status[i] for i in range(self.B)]
+
+    def rve_save_state(self, slot=0):
+        n = C.c_size_t(0)
+        self._chk(lib.rve_state_bytes(self.h, C.byref(n)))
+        buf = np.zeros(n.value, dtype=np.uint8)
+        self._chk(lib.rve_save_state(self.h, int(slot), C.c_void_p(buf.ctypes.data), n.value))
+        return buf
+
+    def rve_load_state(self, blob, slot=0):
+        b = np.ascontiguousarray(blob, dtype=np.uint8)
+        self._chk(lib.rve_load_state(self.h, int(slot), C.c_void_p(b.ctypes.data), b.size))
 
     def rve_release_slot(self, slot):
         self._chk(lib.rve_release_slot(self.h, int(slot)))

@@ -9,9 +9,12 @@ its own HIP stream and its fields resident in HBM.  Every scheduler tick:
      of their class, or open a new pool if its workspace
      (rve_query_workspace for its slot count) fits the HBM budget beside
      the pools already open; otherwise they wait (an admission stall);
-  2. all pools with occupied slots advance those slots by one
-     dissipation-controlled step (Eq. 16), concurrently on their streams;
-     slots of one pool may be at different steps;
+  2. all pools with occupied slots advance those slots by up to
+     steps_per_tick dissipation-controlled steps (Eq. 16) in one
+     rve_run_slots call, concurrently on their streams; slots of one pool
+     are at different steps and within a call each goes at its own pace (a
+     step that fails is halved inside the library, and a step that still
+     fails leaves the slot's state as it was and ends the request);
   3. a slot whose RVE has reached the fracture point yields G_eff
      (Eq. 32-33), records its latency and is released for the next request;
      pools left empty are closed when memory is needed.
@@ -34,26 +37,6 @@ class Request:
     workload: object                  # workloads.Workload
     arrival: float = 0.0              # seconds after the start of the stream
     max_steps: int = 400
-    max_retries: int = 6              # step halvings allowed after RVE_ENOCONV
-
-
-class StepControl:
-    """Per-request step size: a step that does not converge leaves the
-    committed state unchanged (transactional steps), so it is retried with
-    half the dissipation increment, up to max_retries times."""
-
-    def __init__(self, req):
-        self.dtau = float(req.workload.dtau)
-        self.retries = 0
-        self.max_retries = req.max_retries
-
-    def failed(self, status):
-        """True if the step is to be retried (dtau halved)."""
-        if status == mirve.RVE_ENOCONV and self.retries < self.max_retries:
-            self.retries += 1
-            self.dtau *= 0.5
-            return True
-        return False
 
 
 @dataclasses.dataclass
@@ -91,7 +74,6 @@ class Pool:
         self.B = slots
         self.nbytes = self.rve.nbytes
         self.req: List[Optional[Request]] = [None] * slots
-        self.ctl: List[Optional[StepControl]] = [None] * slots
         self.admitted = [0.0] * slots
         self.steps = [0] * slots
         self.greens = [0] * slots
@@ -109,15 +91,16 @@ class Pool:
         i = self.free_slot()
         self.rve.set_workload(req.workload, slot=i)
         self.req[i] = req
-        self.ctl[i] = StepControl(req)
         self.admitted[i] = now
         self.steps[i] = 0
         self.greens[i] = 0
         return i
 
-    def step(self):
-        dt = [c.dtau if r is not None else 0.0 for r, c in zip(self.req, self.ctl)]
-        return self.rve.rve_step_dissipation_slots(dt)
+    def step(self, steps_per_tick):
+        dt = [float(r.workload.dtau) if r is not None else 0.0 for r in self.req]
+        todo = [min(steps_per_tick, r.max_steps - s) if r is not None else 0
+                for r, s in zip(self.req, self.steps)]
+        return self.rve.rve_run_slots(dt, todo, stop_at_fracture=True)
 
     def close(self):
         self.rve.close()
@@ -132,7 +115,8 @@ class Server:
     """
 
     def __init__(self, precision=mirve.RVE_PREC_MIXED, split=mirve.RVE_SPLIT_NONE,
-                 budget_bytes=None, slots_per_pool=16, tol=None, clock=time.perf_counter):
+                 budget_bytes=None, slots_per_pool=16, tol=None, clock=time.perf_counter,
+                 steps_per_tick=1):
         import torch
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info()
@@ -141,6 +125,7 @@ class Server:
         self.split = split
         self.budget = int(budget_bytes)
         self.slots_per_pool = int(slots_per_pool)
+        self.steps_per_tick = max(1, int(steps_per_tick))
         self.tol = dict(tol or {})
         self.pools: Dict[tuple, List[Pool]] = {}
         self.waiting: List[Request] = []
@@ -227,7 +212,7 @@ class Server:
         active = [p for p in self.all_pools() if p.occupied()]
         if not active:
             return []
-        outs = list(self._ex.map(lambda p: p.step(), active))
+        outs = list(self._ex.map(lambda p: p.step(self.steps_per_tick), active))
         self.ticks += 1
         done = []
         for p, (infos, status) in zip(active, outs):
@@ -235,9 +220,7 @@ class Server:
                 if req is None:
                     continue
                 st = status[i]
-                if st != 0 and p.ctl[i].failed(st):
-                    continue
-                p.steps[i] += 1
+                p.steps[i] += infos[i]["n_steps"]
                 p.greens[i] += infos[i]["n_greenop"] * int(np.prod(req.workload.n))
                 finished = st != 0 or infos[i]["fractured"] or p.steps[i] >= req.max_steps
                 if not finished:
@@ -252,7 +235,6 @@ class Server:
                 self.results[req.rid] = res
                 done.append(res)
                 p.req[i] = None
-                p.ctl[i] = None
                 p.rve.rve_release_slot(i)
         return done
 
@@ -309,23 +291,11 @@ def serve_sequential(requests, precision=mirve.RVE_PREC_FP64, split=mirve.RVE_SP
         start = clock() - t0
         w = req.workload
         r = mirve.from_workload(w, precision=precision, split=split, **dict(tol or {}))
-        steps = greens = 0
-        st = 0
-        fractured = False
-        ctl = StepControl(req)
-        while steps < req.max_steps:
-            try:
-                info = r.rve_step_dissipation(ctl.dtau)
-            except mirve.MirveError as e:
-                if ctl.failed(e.code):
-                    continue
-                st = e.code
-                break
-            steps += 1
-            greens += info["n_greenop"] * int(np.prod(w.n))
-            if info["fractured"]:
-                fractured = True
-                break
+        infos, status = r.rve_run_slots([w.dtau], [req.max_steps], stop_at_fracture=True)
+        st = status[0]
+        steps = infos[0]["n_steps"]
+        greens = infos[0]["n_greenop"] * int(np.prod(w.n))
+        fractured = bool(infos[0]["fractured"]) and st == 0
         G = r.rve_effective_toughness() if fractured else None
         if st == 0 and not fractured:
             st = mirve.RVE_ENOTDONE

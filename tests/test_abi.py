@@ -80,6 +80,9 @@ def test_version_and_defaults(lib):
     assert cfg.dim == 2 and tuple(cfg.n) == (64, 64, 1) and cfg.batch == 1
     assert cfg.k_res == 1e-6 and cfg.f[1] == 1.0 and cfg.split == lib.RVE_SPLIT_NONE
     assert cfg.graphs == 1 and cfg.streaming == -1
+    # tolerances 0: the library resolves them per precision at rve_create
+    assert cfg.tol == cfg.tol_cg == cfg.tol_pcg == cfg.tol_al == 0.0
+    assert cfg.max_halvings == 4 and cfg.stall_window == 0
     assert so.rve_default_config(None) == lib.RVE_EINVAL
 
 
@@ -107,7 +110,8 @@ def test_workspace_query(lib):
 
 @pytest.mark.parametrize("bad", [
     {"dim": 4}, {"n": (1, 64)}, {"n": (64, 2048)}, {"h": 0.0}, {"ell": -1.0},
-    {"tol_cg": 0.0}, {"max_cg": 0}, {"batch": 0}, {"batch": 5000}, {"anderson_depth": 9},
+    {"tol_cg": -1e-8}, {"tol": float("nan")}, {"max_cg": 0}, {"max_halvings": 13},
+    {"max_halvings": -1}, {"stall_window": -1}, {"batch": 0}, {"batch": 5000}, {"anderson_depth": 9},
     {"f": (0, 0, 0)}, {"n": (97, 64)},   # 97 is prime: no FFT factorisation
     {"streaming": 2}, {"streaming": -2}, {"graphs": 2},
 ])

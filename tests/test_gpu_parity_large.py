@@ -1,0 +1,108 @@
+"""GPU parity at the line lengths the benchmarks run: the fixed-size FFTs
+of 128 to 1024 points (and the z pass of a 3D grid), element by element
+against the CPU oracle.
+
+The cases go through a batched handle (three slots, a stream of its own,
+so that Krylov chunks run as captured graphs and the Krylov vectors are
+streamed non-temporally) and use a two-phase microstructure with a rotated
+cubic phase at 24 lattice angles and a notch with crack-tip enrichment, so
+g(phi) and the stiffness vary from voxel to voxel.
+
+Bars: FP64 Green operator (Eq. 24 R1, Eq. 26) within 1e-12 of max|ref|
+at every voxel and component; mixed precision within 1e-5; the FP64
+mechanics solve (Eq. 16a) within 1e-10.
+"""
+import numpy as np
+import pytest
+
+from oracle import model, solver, spectral
+from paper_2508_07424_amd import workloads as W
+from tests.helpers import oracle_problem, rel, to_oracle
+
+pytestmark = pytest.mark.gpu
+
+
+def _random_rve(n, seed):
+    """Two phases (isotropic matrix, rotated cubic inclusions at 24
+    angles), about 30 % inclusions, a notch along x at mid-height (2D) or a
+    square notch in the z mid-plane (3D)."""
+    rng = np.random.default_rng(seed)
+    shape = tuple(reversed(n))
+    pid = (rng.random(shape) < 0.3).astype(np.uint16)
+    angles = np.linspace(0.0, np.pi, 24, endpoint=False)
+    theta = angles[rng.integers(0, 24, size=shape)]
+    phases = [W.iso(1.0, 0.3, 1.0), W.cubic(3.0, 1.2, 0.9, 2.0)]
+    if len(n) == 2:
+        nx, ny = n
+        void, tips = W.notch_2d(n, 1.0, ny // 2, nx // 4, nx // 4 + max(2, nx // 8))
+        f = W.load_yy(2)
+    else:
+        nx, ny, nz = n
+        void, tips = W.notch_3d_square(n, 1.0, nz // 2, nx // 4, nx // 2, ny // 4, ny // 2)
+        f = W.load_zz()
+    pid[void.astype(bool)] = 0
+    return W.Workload(n=n, h=1.0, ell=1.5, phases=phases, phase_id=pid, f=f, dtau=1.0, theta=theta,
+                      void=void, phi_disc=tips, phi_M=0.8)
+
+
+CASES = [
+    ("FastFFT<256>x<256>", (256, 256)),
+    ("FastFFT<512>x<64>", (512, 64)),
+    ("FastFFT<1024>x<16>", (1024, 16)),
+    ("FastFFT<128>x<32>x<16>", (128, 32, 16)),
+    ("FastFFT<16>x<16>x<128>", (16, 16, 128)),
+]
+
+
+def _handle(m, w, prec, **kw):
+    import torch
+    ws = [w, _random_rve(w.n, 99), _random_rve(w.n, 98)]
+    return m.from_workloads(ws, precision=prec, stream=torch.cuda.Stream(), streaming=1, graphs=1,
+                            **kw)
+
+
+def _elementwise(gpu, ref):
+    return float(np.max(np.abs(gpu - ref)) / np.max(np.abs(ref)))
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "mixed"])
+@pytest.mark.parametrize("name,n", CASES, ids=[c[0] for c in CASES])
+def test_green_op_at_bench_line_lengths(name, n, prec):
+    from paper_2508_07424_amd import mirve as m
+    w = _random_rve(n, 5)
+    print("case", name, n, "precision", prec, flush=True)
+    r = _handle(m, w, prec)
+    prob = oracle_problem(w)
+    st = solver.State(prob)
+    eps = np.random.default_rng(13).standard_normal((prob.s,) + w.shape)
+    gpu = r.rve_apply_green_op(eps)
+    sig = model.stress(to_oracle(eps, prob.d), st.phi, prob.mat)
+    ref = prob.to_public(spectral.green_apply(sig, prob.P))
+    e_max, e_l2 = _elementwise(gpu, ref), rel(gpu, ref)
+    print("max|gpu - ref| / max|ref| = %.3e, L2 %.3e" % (e_max, e_l2), flush=True)
+    bar = 1e-12 if prec == 0 else 1e-5
+    assert e_max < bar and e_l2 < bar
+    if prec == 0:
+        phi_ini = r.rve_get_field("phi_ini")
+        assert _elementwise(phi_ini, prob.to_public(st.phi_ini)) < 1e-11
+
+
+@pytest.mark.parametrize("name,n", [CASES[0], CASES[1]], ids=[CASES[0][0], CASES[1][0]])
+def test_mechanics_fp64_at_bench_line_lengths(name, n):
+    """The mechanics CG (fused x-forward / axis / x-inverse passes with the
+    Krylov updates) at 256 and 512 points per line, against the oracle's CG
+    to the same tolerance."""
+    from paper_2508_07424_amd import mirve as m
+    w = _random_rve(n, 7)
+    print("case", name, n, flush=True)
+    r = _handle(m, w, 0, tol_cg=1e-13)
+    prob = oracle_problem(w, tol_cg=1e-13)
+    st = solver.State(prob)
+    it, S1 = r.rve_solve_mechanics()
+    x, it_o = solver.mechanics(prob, st.phi, st.x)
+    eps1_o, _, _, S1_o = solver.unit_response(prob, st.phi, x)
+    eps1 = r.rve_get_field("eps1")
+    e_max = _elementwise(eps1, prob.to_public(eps1_o))
+    print("cg iterations gpu", it, "oracle", it_o, "max-rel %.3e" % e_max, flush=True)
+    assert e_max < 1e-10
+    assert abs(S1 - S1_o) <= 1e-10 * abs(S1_o)
