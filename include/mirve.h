@@ -82,7 +82,12 @@ extern "C" {
 /* precision modes */
 #define RVE_PREC_FP64  0  /* every field and transform in FP64                        */
 #define RVE_PREC_MIXED 1  /* fields, FFTs, constitutive and Krylov updates in FP32;
-                             reductions, the arc-length solve and curve in FP64       */
+                             reductions, the arc-length solve and curve in FP64; the
+                             damage solution of the arc-length solve is held in FP64
+                             and refined to tol_pcg (FP64 residual, FP32 corrections);
+                             the stagger also ends when its error is within 10 tol and
+                             has not halved for 20 iterations (the noise floor that
+                             the FP32 mechanics solve leaves)                      */
 
 /* tension / compression split of the elastic energy */
 #define RVE_SPLIT_NONE   0 /* the paper's model: sigma = g C:eps, psi = 1/2 eps:C:eps  */
@@ -123,7 +128,7 @@ typedef struct {
     int    precision;      /* RVE_PREC_*                                             */
     /* tolerances; 0 takes the default of the precision mode:
        FP64  tol 1e-8, tol_cg 1e-10, tol_pcg 1e-12, tol_al 1e-10;
-       MIXED tol 1e-5, tol_cg 1e-6,  tol_pcg 1e-7,  tol_al 1e-6                       */
+       MIXED tol 1e-5, tol_cg 1e-6,  tol_pcg 1e-10, tol_al 1e-6                       */
     double tol;            /* stagger tolerance on the relative change of phi and E  */
     double tol_cg;         /* mechanics CG: ||r|| <= tol_cg ||b||                    */
     double tol_pcg;        /* damage PCG: ||r|| <= tol_pcg ||rhs||                   */
@@ -185,6 +190,11 @@ typedef struct {
     int    n_steps;        /* steps committed by the call                            */
     int    n_substeps;     /* committed sub-steps (a step split by halving has > 1)  */
     int    reason;         /* RVE_WHY_* of a failed step, else RVE_WHY_NONE          */
+    double G_inst;         /* instantaneous energy release rate of the step (Sec. 4.2,
+                              Eq. 34): V [(T - 1/2 Sigma E)^n - (T - 1/2 Sigma E)^(n-1)]
+                              / (Gamma^n - Gamma^(n-1)), the dissipated part of the
+                              curve over the growth of the crack surface; NaN when
+                              Gamma did not grow or no step was committed        */
 } rve_step_info;
 /* E .. step describe the last step the call committed (the committed state
  * when it committed none).  The counters n_stagger, n_cg, n_pcg, n_greenop
@@ -273,7 +283,7 @@ int rve_set_field_slot(rve_handle h, int slot, int which, const double* host, si
 
 /* Checkpoint of one slot's committed state (phi, history H^n, the committed
  * strain fluctuation, the warm start of the arc-length tangent, and the
- * scalars E, Sigma, T, tau, tau0, step, fractured) as an opaque host blob of
+ * scalars E, Sigma, T, tau, tau0, Gamma, step, fractured) as an opaque host blob of
  * rve_state_bytes() bytes.  rve_load_state needs a handle of the same grid
  * and precision whose slot already holds the same microstructure
  * (rve_set_microstructure_slot); stepping on from a loaded state gives the

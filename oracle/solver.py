@@ -392,8 +392,31 @@ def _step_once(prob, st, dtau):
                D=model.dissipation(phi, prob.mat.Gc, prob.ell, prob.h),
                Gamma=model.crack_surface(phi, prob.ell, prob.h), tau=tau,
                n_stagger=it, n_cg=n_cg, n_damage_solves=n_solves, fractured=st.fractured)
+    rec["G_inst"] = instantaneous_G(prob, st.curve[-1], rec)
     st.curve.append(rec)
     return rec
+
+
+def dissipated_by_curve(rec):
+    """Energy per unit volume dissipated up to a point of the curve: the
+    area under Sigma(E) minus the elastic energy still stored,
+    T - 1/2 Sigma E (Eq. 33 at that point)."""
+    return rec["T"] - 0.5 * rec["Sigma"] * rec["E"]
+
+
+def instantaneous_G(prob, prev, rec):
+    """Instantaneous energy release rate between two consecutive points of
+    the curve (Sec. 4.2, Eq. 34): the change of the dissipated energy over
+    the change of the crack surface Gamma (Eq. 4),
+    G = V [(T - 1/2 Sigma E)^n - (T - 1/2 Sigma E)^(n-1)] / (Gamma^n - Gamma^(n-1)).
+    Eq. 34 prints the difference of T alone; the text defines G as the
+    variation of the dissipation, and T also carries the change of the
+    stored elastic energy, so the dissipated part of the curve is used.
+    None when Gamma did not grow."""
+    dG = rec["Gamma"] - prev["Gamma"]
+    if not dG > 0.0:
+        return None
+    return prob.V * (dissipated_by_curve(rec) - dissipated_by_curve(prev)) / dG
 
 
 def effective_toughness(prob, st):

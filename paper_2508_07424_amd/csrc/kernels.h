@@ -257,6 +257,22 @@ hipError_t launch_dissipation_dir(const Geom& g, const uint16_t* mat_id, const M
                                   const int* active, hipStream_t st);
 
 // Field utilities over n elements per RVE (stride n).
+// iterative refinement of the damage balance (FP64 solution, bulk-type correction)
+template <typename T>
+hipError_t launch_ir_residual(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
+                              const T* psi1, const T* psi_ini, const T* Hn, const double* E,
+                              int history, const double* phi64, T* r, double* partials, int nred,
+                              const int* active, hipStream_t st);
+template <typename T>
+hipError_t launch_ir_update(double* phi64, const T* delta, T* phi, long long n, int B,
+                            const int* active, hipStream_t st);
+template <typename T>
+hipError_t launch_widen(const T* phi, double* phi64, long long n, int B, const int* active,
+                        hipStream_t st);
+template <typename T>
+hipError_t launch_dissipation64(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
+                                const double* phi64, double* partials, int nred, const int* active,
+                                hipStream_t st);
 template <typename T>
 hipError_t launch_copy(const T* src, T* dst, long long n, int B, const int* active, hipStream_t st);
 template <typename T>

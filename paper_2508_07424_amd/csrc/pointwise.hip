@@ -1069,7 +1069,155 @@ hipError_t launch_zero_int(int* p, int n, hipStream_t st) {
 // explicit instantiations
 // ---------------------------------------------------------------------------
 
+// ---------------------------------------------------------------------------
+// Iterative refinement of the damage balance (mixed precision).  The
+// solution phi64 is held in FP64; the residual of the system with the bulk
+// data (H, Gc in the bulk type) is formed in FP64 arithmetic, the correction
+// comes from the bulk-precision PCG, and the update is FP64.
+// ---------------------------------------------------------------------------
+
+// r = 2H - A phi64 (Eq. 16b, mode 0 of apply_op) in FP64, stored in the bulk
+// type for the correction solve; partials ||r||^2 and ||2H||^2.  The history
+// field of load E, H = max(E^2 psi1 + psi_ini, H^n) (Eq. 38; without the max
+// when history is off), is formed here in FP64 from the bulk-type fields, so
+// that D(phi(E)) is a smooth function of E and not one quantised by the
+// rounding of H to the bulk type.
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_ir_residual(Geom g, const uint16_t* mat_id,
+                                                     const MatEntry<T>* mat, const T* psi1,
+                                                     const T* psi_ini, const T* Hn,
+                                                     const double* E, int history,
+                                                     const double* phi64, T* r, double* partials,
+                                                     const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
+    RVE_OFFSETS
+    const double* p = phi64 + so;
+    const double ell = g.ell, ih2 = 1.0 / (g.h * g.h), E2 = E[b] * E[b];
+    double s0 = 0.0, s1 = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.N;
+         i += (long long)gridDim.x * blockDim.x) {
+        const Nb n = neighbours(g, i);
+        const double gc = double(mt[mid[i]].Gc);
+        const double ht = E2 * double(psi1[so + i]) + double(psi_ini[so + i]);
+        const double hn = double(Hn[so + i]);
+        const double hb = 2.0 * (history && hn > ht ? hn : ht);
+        const double a = gc / ell + hb, w = gc * ell, pc = p[i];
+        double acc = double(mt[mid[n.xm]].Gc) * ell * (pc - p[n.xm]) - w * (p[n.xp] - pc);
+        acc += double(mt[mid[n.ym]].Gc) * ell * (pc - p[n.ym]) - w * (p[n.yp] - pc);
+        if (g.dim == 3) acc += double(mt[mid[n.zm]].Gc) * ell * (pc - p[n.zm]) - w * (p[n.zp] - pc);
+        const double res = hb - (a * pc + acc * ih2);
+        r[so + i] = T(res);
+        s0 += res * res;
+        s1 += hb * hb;
+    }
+    double pv[2] = {s0, s1};
+    block_sum_store<2>(pv, pslot(partials, b, 0), kRedBlocks, blockIdx.x);
+}
+
+template <typename T>
+hipError_t launch_ir_residual(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
+                              const T* psi1, const T* psi_ini, const T* Hn, const double* E,
+                              int history, const double* phi64, T* r, double* partials, int nred,
+                              const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_ir_residual<T>), dim3(nred, g.B), dim3(TPB), 0, st, g, mat_id, mat, psi1,
+                       psi_ini, Hn, E, history, phi64, r, partials, active);
+    return hipGetLastError();
+}
+
+// phi64 += delta; phi = phi64 rounded to the bulk type (delta may be null:
+// rounding only)
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_ir_update(double* phi64, const T* delta, T* phi, long long n,
+                                                   const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
+    const long long o = (long long)b * n;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        double v = phi64[o + i];
+        if (delta) {
+            v += double(delta[o + i]);
+            phi64[o + i] = v;
+        }
+        if (phi) phi[o + i] = T(v);
+    }
+}
+
+template <typename T>
+hipError_t launch_ir_update(double* phi64, const T* delta, T* phi, long long n, int B,
+                            const int* active, hipStream_t st) {
+    hipLaunchKernelGGL((k_ir_update<T>), dim3(blocks_for(n), B), dim3(TPB), 0, st, phi64, delta,
+                       phi, n, active);
+    return hipGetLastError();
+}
+
+// phi64 = phi (widening copy)
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_widen(const T* phi, double* phi64, long long n,
+                                               const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
+    const long long o = (long long)b * n;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        phi64[o + i] = double(phi[o + i]);
+}
+
+template <typename T>
+hipError_t launch_widen(const T* phi, double* phi64, long long n, int B, const int* active,
+                        hipStream_t st) {
+    hipLaunchKernelGGL((k_widen<T>), dim3(blocks_for(n), B), dim3(TPB), 0, st, phi, phi64, n, active);
+    return hipGetLastError();
+}
+
+// D and Gamma (Eq. 3, 4) of an FP64 damage field with the bulk material table
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_dissipation64(Geom g, const uint16_t* mat_id,
+                                                       const MatEntry<T>* mat, const double* phi_all,
+                                                       double* partials, const int* active) {
+    const int b = blockIdx.y;
+    if (skip(active, b)) return;
+    RVE_OFFSETS
+    const double* phi = phi_all + so;
+    double sD = 0.0, sG = 0.0;
+    const double ell = g.ell, ih = 1.0 / g.h;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.N;
+         i += (long long)gridDim.x * blockDim.x) {
+        const Nb n = neighbours(g, i);
+        const double pc = phi[i];
+        const double gx = (phi[n.xp] - pc) * ih;
+        const double gy = (phi[n.yp] - pc) * ih;
+        const double gz = g.dim == 3 ? (phi[n.zp] - pc) * ih : 0.0;
+        const double dens = pc * pc / (2.0 * ell) + 0.5 * ell * (gx * gx + gy * gy + gz * gz);
+        sD += double(mt[mid[i]].Gc) * dens;
+        sG += dens;
+    }
+    double pv[2] = {sD, sG};
+    block_sum_store<2>(pv, pslot(partials, b, 0), kRedBlocks, blockIdx.x);
+}
+
+template <typename T>
+hipError_t launch_dissipation64(const Geom& g, const uint16_t* mat_id, const MatEntry<T>* mat,
+                                const double* phi64, double* partials, int nred, const int* active,
+                                hipStream_t st) {
+    hipLaunchKernelGGL((k_dissipation64<T>), dim3(nred, g.B), dim3(TPB), 0, st, g, mat_id, mat,
+                       phi64, partials, active);
+    return hipGetLastError();
+}
+
 #define INST(T)                                                                                    \
+    template hipError_t launch_ir_residual<T>(const Geom&, const uint16_t*, const MatEntry<T>*,    \
+                                              const T*, const T*, const T*, const double*, int,    \
+                                              const double*, T*, double*, int, const int*,         \
+                                              hipStream_t);                                        \
+    template hipError_t launch_ir_update<T>(double*, const T*, T*, long long, int, const int*,     \
+                                            hipStream_t);                                          \
+    template hipError_t launch_widen<T>(const T*, double*, long long, int, const int*,             \
+                                        hipStream_t);                                              \
+    template hipError_t launch_dissipation64<T>(const Geom&, const uint16_t*, const MatEntry<T>*,  \
+                                                const double*, double*, int, const int*,           \
+                                                hipStream_t);                                      \
     template hipError_t launch_unit_response<T>(const Geom&, const uint16_t*, const MatEntry<T>*,  \
                                                 const T*, const T*, const F6&, int, T*, T*, T*,    \
                                                 double*, int, const int*, hipStream_t);            \

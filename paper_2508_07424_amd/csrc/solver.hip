@@ -230,6 +230,7 @@ struct SlotState {
     bool ready = false;
     bool fractured = false;
     double E = 0, Sigma = 0, T = 0, tau = 0, tau0 = 0;
+    double Gamma = 0;               // crack surface Gamma of the committed damage (Eq. 4)
     double V = 0, A_g = 0, min_gc = 0;
     int step = 0;
 };
@@ -297,7 +298,10 @@ struct Solver : SolverBase {
     uint16_t* mat_id;
     MatEntry<T>* mat;
     double *partials, *cgpA, *cgpB, *cgpC, *ppA, *ppB, *sums, *dE, *dgamma;
-    int *dmask[6], *dorder, *dm1, *count;
+    int *dmask[7], *dorder, *dm1, *count;
+    // mixed precision: FP64 solution of the damage balance (iterative refinement)
+    double* phi64 = nullptr;
+    T* dlt = nullptr;                // its bulk-precision correction
     uint8_t* tmask = nullptr;       // split: tension flags of the Newton point
     T* dxs = nullptr;               // split: Newton correction (s fields)
     CgDev* cg;
@@ -318,11 +322,18 @@ struct Solver : SolverBase {
     std::map<std::string, hipGraphExec_t> graphs;
     static constexpr int kGraphChunk = 8;
     static constexpr double kGammaMax = 10.0;
+    static constexpr double kFloorFactor = 10.0;
+    static constexpr int kFloorWindow = 20;
     static constexpr int kMaxNewton = 100;
     std::vector<int> slope_warm;     // tmp holds a usable tangent of this slot
     static constexpr double kSlopeTol = 1e-8;
+    static constexpr double kSlopeTolBulk32 = 1e-7;   // what an FP32 PCG reaches
 
     // ------------------------------------------------------------------ layout
+    static long long pass_blocks_max(const Geom& g, int nbx) {
+        return std::max<long long>(nbx, (g.ny * (long long)g.nz + 1) / 2);
+    }
+    long long pass_blocks_max() const { return pass_blocks_max(g, nbx); }
     static size_t layout(const rve_config& c, const Geom& g, int nbx, Layout& L, Solver* s) {
         const long long B = g.B;
         const size_t fN = sizeof(T) * g.N * B;
@@ -348,7 +359,7 @@ struct Solver : SolverBase {
         const size_t opart = L.off(sizeof(double) * kMaxVals * kRedBlocks * B);
         // pass partials: one per block, sized for the smallest rows per block
         // (2), so that any launch shape the tuner picks fits
-        const long long maxblk = std::max<long long>(nbx, (g.ny * (long long)g.nz + 1) / 2);
+        const long long maxblk = pass_blocks_max(g, nbx);
         const size_t ocgA = L.off(sizeof(double) * maxblk * B);
         const size_t ocgB = L.off(sizeof(double) * maxblk * B);
         const size_t ocgC = L.off(sizeof(double) * maxblk * B);
@@ -357,8 +368,12 @@ struct Solver : SolverBase {
         const size_t osums = L.off(sizeof(double) * kMaxVals * B);
         const size_t oE = L.off(sizeof(double) * B);
         const size_t ogam = L.off(sizeof(double) * kAndersonMax * B);
-        size_t omask[6];
-        for (int i = 0; i < 6; ++i) omask[i] = L.off(sizeof(int) * B);
+        size_t omask[7];
+        for (int i = 0; i < 7; ++i) omask[i] = L.off(sizeof(int) * B);
+        // mixed precision: the FP64 damage solution and its correction
+        const bool ir = sizeof(T) < sizeof(double);
+        const size_t ophi64 = ir ? L.off(sizeof(double) * g.N * B) : 0;
+        const size_t odlt = ir ? L.off(fN) : 0;
         const bool split = c.split != RVE_SPLIT_NONE;
         const size_t otm = split ? L.off(sizeof(uint8_t) * g.N * B) : 0;
         const size_t odx = split ? L.off(sN) : 0;
@@ -390,7 +405,9 @@ struct Solver : SolverBase {
             s->sums = (double*)(base + osums);
             s->dE = (double*)(base + oE);
             s->dgamma = (double*)(base + ogam);
-            for (int i = 0; i < 6; ++i) s->dmask[i] = (int*)(base + omask[i]);
+            for (int i = 0; i < 7; ++i) s->dmask[i] = (int*)(base + omask[i]);
+            s->phi64 = ir ? (double*)(base + ophi64) : nullptr;
+            s->dlt = ir ? (T*)(base + odlt) : nullptr;
             s->tmask = split ? (uint8_t*)(base + otm) : nullptr;
             s->dxs = split ? (T*)(base + odx) : nullptr;
             s->dorder = (int*)(base + oord);
@@ -1115,8 +1132,72 @@ struct Solver : SolverBase {
                   std::vector<double>& D, std::vector<int>& npcg, std::vector<int>& rcs) {
         CHK(upload_doubles(dE, E));
         HIPCHK(launch_history<T>(g, psi1, psi_ini, Hn, dE, cfg.history, H, pb, dmask[mask_id], st));
+        if (phi64) return damage_refined(u, mask_id, act, D, npcg, rcs);
         CHK(pcg_solve(H, 0, 0.0, pb, u, cfg.tol_pcg, cfg.max_pcg, mask_id, act, npcg, rcs));
         CHK(dissip(u, mask_id));
+        for (int b = 0; b < B; ++b)
+            if (act[b]) D[b] = sum_of(b, 0) * hd_();
+        return RVE_OK;
+    }
+
+    // Mixed precision: the damage balance of the load in dE solved to tol_pcg
+    // by iterative refinement.  The solution phi64 is FP64 and starts from
+    // the warm start in phi64; each round forms the residual 2H - A phi64 in
+    // FP64 (H of Eq. 38 formed in FP64 too), solves A d = r in the bulk
+    // precision to kIrInner with the bulk-type H already in H, and adds d in
+    // FP64.  D(phi) comes from the FP64 field; u receives it rounded to the
+    // bulk type.  An FP32 solve alone stalls near 1e-7, and a D(E) that
+    // noisy keeps the constraint solve and the staggered fixed point from
+    // converging near unstable crack advance.
+    static constexpr int kIrMax = 12;
+    static constexpr double kIrInner = 1e-4;
+    int damage_refined(T* u, int mask_id, const std::vector<int>& act, std::vector<double>& D,
+                       std::vector<int>& npcg, std::vector<int>& rcs) {
+        std::vector<int> todo(B, 0);
+        for (int b = 0; b < B; ++b) todo[b] = act[b] && rcs[b] == RVE_OK;
+        for (int k = 0; any(todo); ++k) {
+            CHK(set_mask(6, todo));
+            HIPCHK(launch_ir_residual<T>(g, mat_id, mat, psi1, psi_ini, Hn, dE, cfg.history, phi64, pb,
+                                         partials, nred, dmask[6], st));
+            HIPCHK(launch_sum_partials(partials, nred, 2, B, sums, dmask[6], st));
+            CHK(read_sums(2));
+            std::vector<int> zero(B, 0), more(B, 0);
+            for (int b = 0; b < B; ++b) {
+                if (!todo[b]) continue;
+                const double rr = sum_of(b, 0), bb = sum_of(b, 1);
+                if (!std::isfinite(rr)) {
+                    slot_fail(rcs, b, RVE_ENUMERIC, RVE_WHY_BREAKDOWN, "non-finite damage residual");
+                    todo[b] = 0;
+                } else if (bb == 0.0) {
+                    zero[b] = 1;            // the solution of a zero right-hand side is 0
+                    todo[b] = 0;
+                } else if (rr <= cfg.tol_pcg * cfg.tol_pcg * bb) {
+                    todo[b] = 0;
+                } else if (k >= kIrMax) {
+                    slot_fail(rcs, b, RVE_ENOCONV, RVE_WHY_PCG, "damage refinement did not converge");
+                    todo[b] = 0;
+                } else {
+                    more[b] = 1;
+                }
+            }
+            if (any(zero)) {
+                CHK(set_mask(6, zero));
+                HIPCHK(launch_fill<double>(phi64, 0.0, g.N, B, dmask[6], st));
+            }
+            if (!any(more)) break;
+            CHK(set_mask(6, more));
+            HIPCHK(launch_fill<T>(dlt, T(0), g.N, B, dmask[6], st));
+            CHK(pcg_solve(H, 0, 0.0, pb, dlt, kIrInner, cfg.max_pcg, 6, more, npcg, rcs));
+            for (int b = 0; b < B; ++b)
+                if (more[b] && rcs[b] != RVE_OK) { more[b] = 0; todo[b] = 0; }
+            CHK(set_mask(6, more));
+            HIPCHK(launch_ir_update<T>(phi64, dlt, (T*)nullptr, g.N, B, dmask[6], st));
+        }
+        const int* mk = dmask[mask_id];
+        HIPCHK(launch_ir_update<T>(phi64, (const T*)nullptr, u, g.N, B, mk, st));
+        HIPCHK(launch_dissipation64<T>(g, mat_id, mat, phi64, partials, nred, mk, st));
+        HIPCHK(launch_sum_partials(partials, nred, 2, B, sums, mk, st));
+        CHK(read_sums(2));
         for (int b = 0; b < B; ++b)
             if (act[b]) D[b] = sum_of(b, 0) * hd_();
         return RVE_OK;
@@ -1138,7 +1219,8 @@ struct Solver : SolverBase {
         }
         // the tangent only steers Newton on E (the constraint is tested on D
         // itself), so it is solved to a looser tolerance
-        const double tol = std::max(cfg.tol_pcg, kSlopeTol);
+        const double tol = std::max(sizeof(T) < sizeof(double) ? kSlopeTolBulk32 : cfg.tol_pcg,
+                                    kSlopeTol);
         CHK(pcg_solve(H, 0, 0.0, pb, tmp, tol, cfg.max_pcg, mask_id, act, npcg, rcs));
         for (int b = 0; b < B; ++b)
             if (act[b]) slope_warm[b] = rcs[b] == RVE_OK ? 1 : 0;
@@ -1416,6 +1498,7 @@ struct Solver : SolverBase {
         HIPCHK(launch_fill<T>(psi1, T(0), g.N, B, mk, st));
         CHK(dissip(phi_c, 0));
         S.tau = S.tau0 = sum_of(slot, 0) * hd_();
+        S.Gamma = sum_of(slot, 1) * hd_();
         if (!std::isfinite(S.tau)) return fail(RVE_ENUMERIC, "non-finite initial dissipation");
         S.E = S.Sigma = S.T = 0.0;
         S.step = 0;
@@ -1611,6 +1694,7 @@ struct Solver : SolverBase {
                 o.E = S0.E; o.Sigma = S0.Sigma; o.tau = S0.tau; o.T = S0.T;
                 o.fractured = S0.fractured ? 1 : 0;
                 o.step = S0.step;
+                o.G_inst = NAN;
             }
             o.n_stagger = q.n_stag;
             o.n_cg = q.n_cg;
@@ -1635,6 +1719,7 @@ struct Solver : SolverBase {
             if (S[b]) { tau[b] = P[b].tau; E[b] = P[b].E; }
         CHK(set_mask(1, S));
         HIPCHK(launch_copy<T>(phi_w, px, g.N, B, dmask[1], st));
+        if (phi64) HIPCHK(launch_widen<T>(phi_w, phi64, g.N, B, dmask[1], st));
         CHK(arclength(tau, E, px, S, En, npcg, rc));
         HIPCHK(launch_diff_norms<T>(px, phi_w, g.N, B, partials, nred, dmask[1], st));
         HIPCHK(launch_sum_partials(partials, nred, 2, B, sums, dmask[1], st));
@@ -1656,7 +1741,13 @@ struct Solver : SolverBase {
             if (err < 0.5 * q.ref) { q.ref = err; q.ref_it = q.it; }
             if (!std::isfinite(err)) {
                 slot_fail(rc, b, RVE_ENUMERIC, RVE_WHY_BREAKDOWN, "non-finite stagger update");
-            } else if (err < cfg.tol) {
+            } else if (err < cfg.tol ||
+                       (sizeof(T) < sizeof(double) && err < kFloorFactor * cfg.tol &&
+                        q.it - q.ref_it >= kFloorWindow)) {
+                // converged; in mixed precision also when the error has come
+                // within kFloorFactor of tol and has not halved for
+                // kFloorWindow iterations: the FP32 mechanics solve gives the
+                // staggered map a noise floor of that order
                 take[b] = 1;
                 q.stage = 2;
             } else if (q.it >= cfg.max_stagger ||
@@ -1745,6 +1836,8 @@ struct Solver : SolverBase {
             SlotState& Ss = slots[b];
             step_greens[b] += 1;       // the R1 check
             const double Sigma = E[b] * S1[b];
+            // dissipated energy per volume on the curve, T - 1/2 Sigma E, before the step
+            const double dext_prev = Ss.T - 0.5 * Ss.Sigma * Ss.E;
             Ss.T += 0.5 * (Sigma + Ss.Sigma) * (E[b] - Ss.E);
             Ss.E = E[b];
             Ss.Sigma = Sigma;
@@ -1764,6 +1857,11 @@ struct Solver : SolverBase {
             o.res_R3 = std::fabs(D[b] - q.tau) / q.tau;
             o.fractured = Ss.fractured ? 1 : 0;
             o.step = Ss.step;
+            // instantaneous energy release rate (Eq. 34) on the dissipated part
+            // of the curve; NaN when the crack surface did not grow
+            const double dGam = G[b] - Ss.Gamma;
+            o.G_inst = dGam > 0.0 ? Ss.V * ((Ss.T - 0.5 * Sigma * E[b]) - dext_prev) / dGam : NAN;
+            Ss.Gamma = G[b];
             q.has_last = true;
             q.n_sub += 1;
             q.sub_done = true;
@@ -1831,7 +1929,13 @@ struct Solver : SolverBase {
             if (!std::isfinite(hostp[i])) return fail(RVE_EINVAL, "non-finite field value");
         CHK(drain());
         switch (which) {
-            case RVE_FIELD_PHI: return upload(phi_c + so, hostp, N);
+            case RVE_FIELD_PHI: {          // the committed crack surface follows phi
+                CHK(upload(phi_c + so, hostp, N));
+                CHK(set_mask(0, only(slot)));
+                CHK(dissip(phi_c, 0));
+                slots[slot].Gamma = sum_of(slot, 1) * hd_();
+                return RVE_OK;
+            }
             case RVE_FIELD_HIST: return upload(Hn + so, hostp, N);
             case RVE_FIELD_PSI1: return upload(psi1 + so, hostp, N);
             default: return fail(RVE_EINVAL, "field is read-only");
@@ -1849,14 +1953,25 @@ struct Solver : SolverBase {
         return download(outp, p + fo, sN);
     }
 
+    // mask `which` = the slots that hold a microstructure, written straight
+    // into the pinned staging ring (no host container)
+    int set_mask_ready(int which) {
+        const size_t n = sizeof(int) * B, need = (n + 255) & ~size_t(255);
+        if (stage_off + need > stage_bytes) CHK(drain());
+        int* slot = reinterpret_cast<int*>((char*)h_stage + stage_off);
+        for (int b = 0; b < B; ++b) slot[b] = slots[b].ready ? 1 : 0;
+        HIPCHK(hipMemcpyAsync(dmask[which], slot, n, hipMemcpyHostToDevice, st));
+        stage_off += need;
+        return RVE_OK;
+    }
+
     int apply_green_device(const void* eps, void* outp, int repeat) override {
-        std::vector<int> rd(B, 0);
-        for (int b = 0; b < B; ++b) rd[b] = slots[b].ready ? 1 : 0;
-        CHK(set_mask(0, rd));
+        CHK(set_mask_ready(0));
         for (int i = 0; i < repeat; ++i)
             CHK(green(phi_c, (const T*)eps, 0.0, (T*)outp, 1.0, cgpB, dmask[0]));
         return RVE_OK;
     }
+
 
     int solve_mechanics(int slot, int* it, double* Sigma1) override {
         CHK(check_slot(slot));
@@ -1879,6 +1994,7 @@ struct Solver : SolverBase {
         Ev[slot] = E;
         CHK(set_mask(2, one));
         HIPCHK(launch_copy<T>(phi_c, px, g.N, B, dmask[2], st));
+        if (phi64) HIPCHK(launch_widen<T>(phi_c, phi64, g.N, B, dmask[2], st));
         CHK(damage_at(Ev, px, 2, one, Dv, its, rcs));
         if (rcs[slot] != RVE_OK) return rcs[slot];
         if (D) *D = Dv[slot];
@@ -1903,10 +2019,10 @@ struct Solver : SolverBase {
     struct StateHeader {
         uint32_t magic, word;
         int32_t dim, n[3];
-        double E, Sigma, Tc, tau, tau0;
+        double E, Sigma, Tc, tau, tau0, Gamma;
         int32_t step, fractured, warm, pad;
     };
-    static constexpr uint32_t kStateMagic = 0x4d525653u;   // "MRVS"
+    static constexpr uint32_t kStateMagic = 0x3256524du;   // "MRV2"
     size_t state_bytes() const override {
         return sizeof(StateHeader) + sizeof(T) * (size_t)g.N * (3 + g.s);
     }
@@ -1920,6 +2036,7 @@ struct Solver : SolverBase {
         hdr.dim = g.dim; hdr.n[0] = g.nx; hdr.n[1] = g.ny; hdr.n[2] = g.nz;
         const SlotState& S = slots[slot];
         hdr.E = S.E; hdr.Sigma = S.Sigma; hdr.Tc = S.T; hdr.tau = S.tau; hdr.tau0 = S.tau0;
+        hdr.Gamma = S.Gamma;
         hdr.step = S.step; hdr.fractured = S.fractured ? 1 : 0; hdr.warm = slope_warm[slot];
         std::vector<char> a, b, c, d;
         CHK(save_fields(slot, a, b, c, d));
@@ -1936,7 +2053,7 @@ struct Solver : SolverBase {
         if (hdr.magic != kStateMagic || hdr.word != sizeof(T) || hdr.dim != g.dim || hdr.n[0] != g.nx ||
             hdr.n[1] != g.ny || hdr.n[2] != g.nz)
             return fail(RVE_EINVAL, "state blob of another grid or precision");
-        const double sc[5] = {hdr.E, hdr.Sigma, hdr.Tc, hdr.tau, hdr.tau0};
+        const double sc[6] = {hdr.E, hdr.Sigma, hdr.Tc, hdr.tau, hdr.tau0, hdr.Gamma};
         for (double v : sc)
             if (!std::isfinite(v)) return fail(RVE_EINVAL, "non-finite scalar in state blob");
         const size_t fN = sizeof(T) * g.N, sN = fN * g.s;
@@ -1951,6 +2068,7 @@ struct Solver : SolverBase {
         CHK(load_fields(slot, p, p + fN, p + 2 * fN, p + 2 * fN + sN));
         SlotState& S = slots[slot];
         S.E = hdr.E; S.Sigma = hdr.Sigma; S.T = hdr.Tc; S.tau = hdr.tau; S.tau0 = hdr.tau0;
+        S.Gamma = hdr.Gamma;
         S.step = hdr.step; S.fractured = hdr.fractured != 0;
         slope_warm[slot] = hdr.warm ? 1 : 0;
         return RVE_OK;
@@ -2246,6 +2364,7 @@ static int geom_check(const rve_config* c, Geom& g, int& nbx, std::string& why) 
 
 static thread_local std::string g_last_error;
 
+
 // A tolerance of 0 takes the default of the precision mode.  FP32 fields
 // resolve D(E) to about 1e-7, so in mixed precision the constraint is held
 // to 1e-6 and the damage solves that evaluate it to 1e-7.
@@ -2253,7 +2372,7 @@ static void resolve_defaults(rve_config& c) {
     const bool mixed = c.precision == RVE_PREC_MIXED;
     if (c.tol == 0.0) c.tol = mixed ? 1e-5 : 1e-8;
     if (c.tol_cg == 0.0) c.tol_cg = mixed ? 1e-6 : 1e-10;
-    if (c.tol_pcg == 0.0) c.tol_pcg = mixed ? 1e-7 : 1e-12;
+    if (c.tol_pcg == 0.0) c.tol_pcg = mixed ? 1e-10 : 1e-12;
     if (c.tol_al == 0.0) c.tol_al = mixed ? 1e-6 : 1e-10;
 }
 
@@ -2276,7 +2395,7 @@ int rve_default_config(rve_config* c) {
     c->tol_cg = 0.0;
     c->tol_pcg = 0.0;
     c->tol_al = 0.0;
-    c->max_stagger = 100;
+    c->max_stagger = 300;
     c->max_halvings = 4;
     c->stall_window = 0;
     c->max_cg = 20000;

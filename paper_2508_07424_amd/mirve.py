@@ -75,7 +75,8 @@ class rve_step_info(C.Structure):
                 ("n_stagger", C.c_int), ("n_cg", C.c_int), ("n_pcg", C.c_int),
                 ("n_greenop", C.c_int), ("res_R1", C.c_double), ("res_R2", C.c_double),
                 ("res_R3", C.c_double), ("fractured", C.c_int), ("step", C.c_int),
-                ("n_steps", C.c_int), ("n_substeps", C.c_int), ("reason", C.c_int)]
+                ("n_steps", C.c_int), ("n_substeps", C.c_int), ("reason", C.c_int),
+                ("G_inst", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

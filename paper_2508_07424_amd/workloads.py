@@ -237,6 +237,60 @@ def laminate_2d(nx=64, ny=32, widths=(0.5, 0.5), Gcs=(1.0, 3.0), Es=(1.0, 1.0), 
                     k=1e-6, meta={"name": "laminate_2d", "edges": edges.tolist()})
 
 
+def inclusion_2d(n=24, radius=4.0, centre=(18.0, 12.0), E_ratio=3.0, Gc_ratio=2.0, ell=1.5,
+                 crack=6):
+    """n x n matrix (E = 1, nu = 0.3, Gc = 1) with one disk inclusion
+    (E_ratio, nu = 0.25, Gc_ratio) at `centre` (voxel units) and a centred
+    notch row of `crack` voxels at mid-height: a small case whose crack
+    meets, grazes or misses the inclusion depending on where it starts."""
+    nn = (n, n)
+    h = 1.0
+    X, Y = _centres(nn, h)
+    d2 = _periodic_delta(X, centre[0] * h, n * h) ** 2 + _periodic_delta(Y, centre[1] * h, n * h) ** 2
+    pid = (d2 <= (radius * h) ** 2).astype(np.uint16)
+    row = n // 2
+    x0 = n // 2 - crack // 2
+    void, tips = notch_2d(nn, h, row, x0, x0 + crack)
+    pid[void.astype(bool)] = 0
+    return Workload(n=nn, h=h, ell=ell, phases=[iso(1.0, 0.3, 1.0), iso(E_ratio, 0.25, Gc_ratio)],
+                    phase_id=pid, f=load_yy(2), dtau=0.01 * n * h, void=void, phi_disc=tips,
+                    phi_M=0.8, k=1e-6, meta={"name": "inclusion_2d_%d" % n})
+
+
+def _load_axis(w):
+    """Index (0 x, 1 y, 2 z) of the largest normal component of the load."""
+    d = len(w.n)
+    return int(np.argmax(np.abs(np.asarray(w.f, dtype=float)[:d])))
+
+
+def crack_position_samples(w, count):
+    """The same RVE with the initial crack at `count` positions along the
+    load axis (Sec. 3: the toughness estimate is the minimum over crack
+    positions).  The RVE is periodic, so the microstructure (phase ids and
+    orientations) is shifted cyclically by k L / count voxels along the load
+    axis while the notch and its enrichment points stay where they are;
+    notch voxels keep the phase they have in the unshifted RVE.  Returns
+    [(shift, Workload)]."""
+    a = _load_axis(w)
+    d = len(w.n)
+    axis = d - 1 - a                      # array axis of the load direction
+    L = int(w.n[a])
+    out = []
+    for k in range(count):
+        sh = int(round(k * L / count))
+        pid = np.roll(w.phase_id, sh, axis=axis)
+        th = None if w.theta is None else np.roll(w.theta, sh, axis=axis)
+        if w.void is not None:
+            pid = pid.copy()
+            pid[w.void.astype(bool)] = w.phase_id[w.void.astype(bool)]
+        meta = dict(w.meta)
+        meta["crack_shift"] = sh
+        out.append((sh, Workload(n=w.n, h=w.h, ell=w.ell, phases=w.phases, phase_id=pid, f=w.f,
+                                 dtau=w.dtau, theta=th, void=w.void, phi_disc=w.phi_disc,
+                                 phi_M=w.phi_M, k=w.k, meta=meta)))
+    return out
+
+
 def _voronoi_ids(X, Y, seeds, L):
     """Index of the nearest seed (periodic distance) of every voxel centre;
     ties go to the lower index."""

@@ -14,6 +14,7 @@ Krylov and constraint 1e-12) of every step, so a run is held to a looser
 bound than one step (1e-9) or one operator (1e-12).
 """
 import json
+import math
 import os
 
 import pytest
@@ -37,6 +38,14 @@ def _compare(infos, gold):
         for key in ("E", "Sigma", "D", "T"):
             d = abs(info[key] - ref[key]) / max(abs(ref[key]), 1e-300)
             worst[key] = max(worst.get(key, 0.0), d)
+        # instantaneous energy release rate (Eq. 34): None / NaN where the
+        # crack surface did not grow
+        g, gr = info["G_inst"], ref["G_inst"]
+        if gr is None:
+            assert math.isnan(g), (info["step"], g)
+        else:
+            d = abs(g - gr) / max(abs(gr), 1e-300)
+            worst["G_inst"] = max(worst.get("G_inst", 0.0), d)
     print("worst relative deviation per quantity", worst, flush=True)
     for key, d in worst.items():
         assert d < CURVE_TOL, (key, d)
@@ -86,3 +95,21 @@ def test_composite_60_steps_fp64():
     r = mirve.from_workload(w, **_fp64_tol(gold))
     infos = [r.rve_step_dissipation(w.dtau) for _ in gold["steps"]]
     _compare(infos, gold)
+
+
+def test_crack_position_sampling_fp64():
+    """Toughness as the minimum over initial-crack positions (Sec. 3): four
+    positions of the 24 x 24 plate with one inclusion run as the slots of
+    one batched handle, each at its own pace, against the oracle's runs of
+    the same positions (tests/golden/sampling24_fp64.json)."""
+    from paper_2508_07424_amd import sampling
+    with open(os.path.join(HERE, "golden", "sampling24_fp64.json")) as fh:
+        gold = json.load(fh)
+    w = W.inclusion_2d()
+    res = sampling.min_toughness_over_crack_positions(w, 4, **_fp64_tol(gold))
+    print("G_eff per shift", list(zip(res["shifts"], res["G_eff"])), flush=True)
+    for ref, G, n in zip(gold["runs"], res["G_eff"], res["steps"]):
+        assert n == ref["steps"]
+        assert abs(G - ref["G_eff"]) <= CURVE_TOL * abs(ref["G_eff"]), (ref["shift"], G, ref["G_eff"])
+    assert res["shift_min"] == gold["shift_min"]
+    assert abs(res["G_min"] - gold["G_min"]) <= CURVE_TOL * gold["G_min"]

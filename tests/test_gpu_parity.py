@@ -1,7 +1,8 @@
 """GPU parity: the HIP path through the C ABI against the CPU oracle.
 
-FP64 mode must agree with the oracle to 1e-10 relative (operators to
-1e-12); mixed mode to 1e-5 on the stress field.
+FP64 mode must agree with the oracle to 1e-10 relative (steps: E, Sigma,
+D, T, phi and the history field; operators to 1e-12); mixed mode to 1e-5
+on the stress field.
 """
 import numpy as np
 import pytest
@@ -117,7 +118,11 @@ def test_steps_fp64(name, make, nsteps, pre):
         rec = solver.step(prob, st, w.dtau)
         print("step", k + 1, {q: info[q] for q in ("E", "Sigma", "D", "n_stagger", "n_cg", "n_pcg",
                                                    "res_R1", "res_R2", "res_R3")}, flush=True)
-        for key in ("E", "Sigma", "D", "T"):
-            assert abs(info[key] - rec[key]) <= 1e-9 * abs(rec[key]), (key, info[key], rec[key])
-    assert rel(r.rve_get_field("phi"), prob.to_public(st.phi)) < 1e-9
-    assert rel(r.rve_get_field("hist"), prob.to_public(st.H)) < 1e-9
+        dev = {key: abs(info[key] - rec[key]) / abs(rec[key]) for key in ("E", "Sigma", "D", "T")}
+        print("  relative deviation from the oracle", dev, flush=True)
+        for key, d in dev.items():
+            assert d <= 1e-10, (key, info[key], rec[key])
+    e_phi = rel(r.rve_get_field("phi"), prob.to_public(st.phi))
+    e_H = rel(r.rve_get_field("hist"), prob.to_public(st.H))
+    print("  phi %.3e  history %.3e" % (e_phi, e_H), flush=True)
+    assert e_phi < 1e-10 and e_H < 1e-10

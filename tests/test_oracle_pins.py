@@ -437,6 +437,39 @@ def test_energy_balance_without_history_converges():
     assert e2 < e1 / 1.8
 
 
+def test_instantaneous_energy_release_rate_recovers_gc():
+    """Eq. 34 on a homogeneous plate without history: there D = Gc Gamma
+    (Eq. 3, 4) and the curve's dissipated energy V (T - 1/2 Sigma E) equals
+    D - D^0 up to the trapezoid error (the energy balance above), so while
+    the crack grows each step's G_inst = V d(T - 1/2 Sigma E) / dGamma is
+    Gc.  The first step carries no dissipation on the curve (it starts from
+    E = 0) and the early steps form the process zone, so the propagation
+    phase is judged: the second half of the run.  The difference of T
+    alone (as Eq. 34 is printed) also carries the change of the stored
+    energy and misses Gc by far: snap-back makes it negative."""
+    Gc = 2.5
+    w = W.homogeneous_2d(nx=24, ny=32, ell=1.5, crack=6, Gc=Gc)
+    prob = oracle_problem(w, tol=1e-9, tol_cg=1e-11, tol_al=1e-11, history=False)
+    st = solver.State(prob)
+    g_inst, g_T = [], []
+    while not st.fractured and st.step < 300:
+        prev = st.curve[-1]
+        rec = solver.step(prob, st, w.dtau)
+        g_inst.append(rec["G_inst"])
+        g_T.append(prob.V * (rec["T"] - prev["T"]) / (rec["Gamma"] - prev["Gamma"]))
+    assert st.fractured and g_inst[0] == 0.0
+    late = np.array(g_inst[len(g_inst) // 2:]) / Gc
+    late_T = np.array(g_T[len(g_T) // 2:]) / Gc
+    print("G_inst / Gc over the second half:", np.round(late, 4))
+    assert np.median(np.abs(late - 1.0)) < 0.01
+    assert np.max(np.abs(late - 1.0)) < 0.05
+    assert np.median(np.abs(late_T - 1.0)) > 0.5
+    # the increments add up to the effective toughness of Eq. 32-33
+    dG = np.diff([r["Gamma"] for r in st.curve])
+    total = sum(g * d for g, d in zip(g_inst, dG) if g is not None)
+    assert abs(total - solver.effective_toughness(prob, st) * prob.A_g) < 1e-9 * total
+
+
 def test_fracture_test_on_hand_built_fields():
     """The fracture point (Sec. 4.2): every line of voxels along the load axis
     holds a voxel with phi >= 0.95 or a notch voxel.  Fields built by hand."""
