@@ -309,6 +309,30 @@ int rve_apply_green_op(rve_handle h, const double* eps_host, double* out_host);
  * with a microstructure are enqueued on the handle's stream. */
 int rve_apply_green_op_device(rve_handle h, const void* eps_dev, void* out_dev, int repeat);
 
+/* Size of the static device array behind rve_apply_green_op_device_noalloc
+ * (one array per device the library runs on, held until the process ends). */
+#define RVE_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* Allocation-free form of rve_apply_green_op_device, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same operation, arguments, layout and
+ * result as rve_apply_green_op_device; the intermediate spectrum and the
+ * per-block partial sums of its passes live in the library's static device
+ * array of RVE_NOALLOC_SCRATCH_BYTES bytes instead of the handle's
+ * workspace.  The call allocates nothing (no hipMalloc, hipFree or other
+ * allocating routine) and enqueues its work on the handle's stream.
+ *   Limit: the handle needs 16 (FP64) or 8 (MIXED) bytes x s x (n_x/2+1) x
+ *   n_y x n_z x batch of spectrum plus 8 bytes per x-pass block and slot;
+ *   a larger handle is refused with RVE_ENOSPC before any work.
+ *   Sharing: every call on one device uses the same array and leaves its
+ *   contents behind (nothing in it needs to start cleared).  Calls ordered
+ *   on one stream are safe; calls that overlap in time on one device (other
+ *   streams, other host threads) race on the array and give wrong results.
+ *   Errors: RVE_EINVAL for a null handle or pointer or repeat < 0;
+ *   RVE_EDEVICE if the array's address could not be obtained when the
+ *   handle was created. */
+int rve_apply_green_op_device_noalloc(rve_handle h, const void* eps_dev, void* out_dev, int repeat);
+
 /* Equilibrium for the unit load at the committed phi (Eq. 16a): updates
  * EPS1/SIG1/PSI1 and returns the CG iteration count and Sigma_1. */
 int rve_solve_mechanics(rve_handle h, int* iterations, double* Sigma1);

@@ -244,6 +244,8 @@ struct SolverBase {
     virtual int set_field(int slot, int which, const double* host, size_t count) = 0;
     virtual int apply_green(int slot, const double* eps, double* out) = 0;
     virtual int apply_green_device(const void* eps, void* out, int repeat) = 0;
+    virtual int apply_green_device_scratch(void* scr, size_t cap, const void* eps, void* out,
+                                           int repeat) = 0;
     virtual int solve_mechanics(int slot, int* it, double* Sigma1) = 0;
     virtual int solve_damage(int slot, double E, double* D, int* it, int commit) = 0;
     virtual int dissipation(int slot, double* D, double* G) = 0;
@@ -260,6 +262,7 @@ struct rve_handle_s {
     rve_config cfg;
     std::unique_ptr<SolverBase> impl;
     std::string err;
+    void* scratch = nullptr;   // device address of the static scratch array on the handle's device
 };
 
 namespace mirve {
@@ -1972,6 +1975,26 @@ struct Solver : SolverBase {
         return RVE_OK;
     }
 
+    // The same with the spectrum and the pass partials in the caller's
+    // scratch `scr` of `cap` bytes instead of the workspace (the handle's own
+    // buffers are put back afterwards).
+    int apply_green_device_scratch(void* scr, size_t cap, const void* eps, void* outp,
+                                   int repeat) override {
+        const size_t spec_b = (sizeof(cplx<T>) * g.s * (size_t)g.Nspec * B + 255) & ~size_t(255);
+        const size_t part_b = sizeof(double) * (size_t)pass_blocks_max() * B;
+        if (spec_b + part_b > cap)
+            return fail(RVE_ENOSPC, "the handle needs " + std::to_string(spec_b + part_b) +
+                                        " bytes of static scratch; the array holds " +
+                                        std::to_string(cap));
+        cplx<T>* const own_spec = spec;
+        double* const own_part = cgpB;
+        spec = reinterpret_cast<cplx<T>*>(scr);
+        cgpB = reinterpret_cast<double*>((char*)scr + spec_b);
+        const int rc = apply_green_device(eps, outp, repeat);
+        spec = own_spec;
+        cgpB = own_part;
+        return rc;
+    }
 
     int solve_mechanics(int slot, int* it, double* Sigma1) override {
         CHK(check_slot(slot));
@@ -2364,6 +2387,37 @@ static int geom_check(const rve_config* c, Geom& g, int& nbx, std::string& why) 
 
 static thread_local std::string g_last_error;
 
+// Static device scratch of rve_apply_green_op_device_noalloc.  Host code never
+// uses its name as an address: each device's copy is found once, at the
+// set-up of the first handle on that device, with that device current.
+static __device__ __align__(256) unsigned char scratch[RVE_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mutex;
+static void* g_scratch_ptr[256];
+static bool g_scratch_tried[256];
+
+// Address of the current device's scratch array (nullptr if the runtime
+// could not give it; the error text goes to why).
+static void* scratch_address(std::string& why) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 256) {
+        why = "no current HIP device";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_tried[dev]) {
+        g_scratch_tried[dev] = true;
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            why = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    if (!g_scratch_ptr[dev]) why = "the static scratch array has no address on this device";
+    return g_scratch_ptr[dev];
+}
 
 // A tolerance of 0 takes the default of the precision mode.  FP32 fields
 // resolve D(E) to about 1e-7, so in mixed precision the constraint is held
@@ -2458,6 +2512,9 @@ int rve_create(const rve_config* c, void* ws, size_t wsb, void* stream, rve_hand
         delete h;
         return rc;
     }
+    // the allocation-free entry point reports a missing address itself
+    std::string why;
+    h->scratch = scratch_address(why);
     *out = h;
     return RVE_OK;
 }
@@ -2613,6 +2670,13 @@ int rve_apply_green_op(rve_handle h, const double* eps, double* out) {
 int rve_apply_green_op_device(rve_handle h, const void* eps, void* out, int repeat) {
     if (!h || !eps || !out || repeat < 0) return RVE_EINVAL;
     return h->impl->apply_green_device(eps, out, repeat);
+}
+
+int rve_apply_green_op_device_noalloc(rve_handle h, const void* eps, void* out, int repeat) {
+    if (!h) return RVE_EINVAL;
+    if (!eps || !out || repeat < 0) { h->err = "null device pointer or repeat < 0"; return RVE_EINVAL; }
+    if (!h->scratch) { h->err = "static scratch array unavailable on this device"; return RVE_EDEVICE; }
+    return h->impl->apply_green_device_scratch(h->scratch, RVE_NOALLOC_SCRATCH_BYTES, eps, out, repeat);
 }
 
 int rve_solve_mechanics(rve_handle h, int* it, double* Sigma1) {

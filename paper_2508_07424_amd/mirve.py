@@ -21,6 +21,7 @@ RVE_ENOCONV = -4
 RVE_ENUMERIC = -5
 RVE_ESTATE = -6
 RVE_ENOTDONE = -7
+RVE_NOALLOC_SCRATCH_BYTES = 64 << 20   # static device array of rve_apply_green_op_device_noalloc
 _NAMES = {0: "RVE_OK", -1: "RVE_EINVAL", -2: "RVE_ENOSPC", -3: "RVE_EDEVICE", -4: "RVE_ENOCONV",
           -5: "RVE_ENUMERIC", -6: "RVE_ESTATE", -7: "RVE_ENOTDONE"}
 
@@ -48,7 +49,7 @@ EXPORTS = ["rve_default_config", "rve_query_workspace", "rve_create", "rve_destr
            "rve_apply_green_op", "rve_apply_green_op_device", "rve_solve_mechanics",
            "rve_solve_damage", "rve_dissipation", "rve_profile_pass", "rve_autotune",
            "rve_last_error", "rve_version", "rve_run_slots", "rve_state_bytes", "rve_save_state",
-           "rve_load_state"]
+           "rve_load_state", "rve_apply_green_op_device_noalloc"]
 
 
 class rve_config(C.Structure):
@@ -121,6 +122,7 @@ def _load():
         "rve_set_scalars": (I, [P, dp]),
         "rve_apply_green_op": (I, [P, dp, dp]),
         "rve_apply_green_op_device": (I, [P, P, P, I]),
+        "rve_apply_green_op_device_noalloc": (I, [P, P, P, I]),
         "rve_solve_mechanics": (I, [P, C.POINTER(C.c_int), dp]),
         "rve_solve_damage": (I, [P, D, dp, C.POINTER(C.c_int), I]),
         "rve_dissipation": (I, [P, dp, dp]),
@@ -331,6 +333,12 @@ class Rve:
     def rve_apply_green_op_device(self, eps_dev, out_dev, repeat=1):
         self._chk(lib.rve_apply_green_op_device(self.h, C.c_void_p(eps_dev.data_ptr()),
                                                 C.c_void_p(out_dev.data_ptr()), int(repeat)))
+
+    def rve_apply_green_op_device_noalloc(self, eps_dev, out_dev, repeat=1):
+        """rve_apply_green_op_device with the spectrum and partial sums in the
+        library's static device array (allocates nothing)."""
+        self._chk(lib.rve_apply_green_op_device_noalloc(self.h, C.c_void_p(eps_dev.data_ptr()),
+                                                        C.c_void_p(out_dev.data_ptr()), int(repeat)))
 
     def rve_solve_mechanics(self):
         it = C.c_int(0)
