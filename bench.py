@@ -218,18 +218,30 @@ def stored_traffic(kernel_file):
         return None
 
 
-def serving(n_requests, seed, rate):
+SERVE_SIZES = {
+    # name: (2D sides, 3D sides), drawn log-uniform and rounded to the nearest listed side
+    "small": ((32, 48, 64), (16, 24)),
+    "full": ((64, 128, 256, 512), (64, 128)),
+}
+
+
+def serving(n_requests, seed, rate, sizes="small", max_steps=300):
     """The serving form against the plain form on one seeded request stream
-    (2D 32^2-64^2 composites and polycrystals, 3D 16^3-24^3 composites,
-    Poisson arrivals): continuous batching in mixed precision versus one RVE
-    at a time in FP64, same arrivals.  Reports solves/s, p50/p99 latency and
-    the largest relative G_eff difference between the two."""
+    (2D fibre composites and polycrystals, 3D sphere composites, elastic
+    contrast U[1, 10], toughness contrast U[1, 4], Poisson arrivals; sizes
+    "small": 32^2-64^2 and 16^3-24^3, "full": 64^2-512^2 and 64^3-128^3):
+    continuous batching in mixed precision versus one RVE at a time in
+    FP64, same arrivals.  Reports solves/s, p50/p99 latency and the largest
+    relative G_eff difference between the two."""
     import torch
     from paper_2508_07424_amd import mirve, serve
     from paper_2508_07424_amd import workloads as W
-    stream = W.serving_stream(n_requests, seed=seed, sizes_2d=(32, 48, 64), sizes_3d=(16, 24),
+    s2, s3 = SERVE_SIZES[sizes]
+    stream = W.serving_stream(n_requests, seed=seed, sizes_2d=s2, sizes_3d=s3,
                               frac_3d=0.25, rate=rate, dtau_frac=0.02)
-    reqs = [serve.Request(i, w, arrival=a, max_steps=300) for i, (a, w) in enumerate(stream)]
+    reqs = [serve.Request(i, w, arrival=a, max_steps=max_steps) for i, (a, w) in enumerate(stream)]
+    progress("stream: " + ", ".join("%d:%s" % (i, "x".join(map(str, w.n)))
+                                    for i, (a, w) in enumerate(stream)))
     torch.cuda.synchronize()
     progress("serving %d requests, mixed precision, continuous batching" % n_requests)
     t0 = time.perf_counter()
@@ -249,7 +261,12 @@ def serving(n_requests, seed, rate):
     wall_p = time.perf_counter() - t0
     both = [(a, b) for a, b in zip(res_s, res_p) if a.G_eff is not None and b.G_eff is not None]
     dev = max((abs(a.G_eff - b.G_eff) / abs(b.G_eff) for a, b in both), default=None)
-    out = {"requests": n_requests, "arrival_rate_per_s": rate,
+    out = {"requests": n_requests, "arrival_rate_per_s": rate, "sizes": sizes,
+           "grids": ["x".join(map(str, r.workload.n)) for r in reqs],
+           "per_request": [{"rid": a.rid, "G_eff_mixed_batched": a.G_eff, "G_eff_plain_fp64": b.G_eff,
+                            "steps": [a.steps, b.steps], "latency_s": [round(a.latency, 2),
+                                                                       round(b.latency, 2)]}
+                           for a, b in zip(res_s, res_p)],
            "served_mixed_batched": serve.summarize(res_s, wall_s),
            "plain_fp64_one_at_a_time": serve.summarize(res_p, wall_p),
            "max_rel_G_eff_diff": None if dev is None else float("%.3g" % dev),
@@ -322,6 +339,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=0,
                     help="requests of the serving comparison (0: skip it)")
     ap.add_argument("--serve-rate", type=float, default=2.0, help="Poisson arrivals per second")
+    ap.add_argument("--serve-sizes", choices=sorted(SERVE_SIZES), default="small")
+    ap.add_argument("--serve-seed", type=int, default=5)
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only the serving comparison (one JSON line with its field)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="set up the batch and time the Green-operator passes only (for counter runs)")
     args = ap.parse_args()
@@ -332,6 +353,11 @@ def main():
 
     import torch
     from paper_2508_07424_amd import mirve
+    if args.serve_only:
+        out = {"serving": serving(max(1, args.serve_requests), seed=args.serve_seed,
+                                  rate=args.serve_rate, sizes=args.serve_sizes)}
+        print(json.dumps(out), flush=True)
+        return
     build, size0, batch0, prec0, desc = WORKLOADS[args.workload]
     args.size = args.size or size0
     args.batch = args.batch or batch0
@@ -421,7 +447,8 @@ def main():
     if args.serve_requests > 0:
         del rve
         torch.cuda.empty_cache()
-        out["serving"] = serving(args.serve_requests, seed=5, rate=args.serve_rate)
+        out["serving"] = serving(args.serve_requests, seed=args.serve_seed, rate=args.serve_rate,
+                                 sizes=args.serve_sizes)
     if not args.no_cpu_baseline:
         progress("oracle on the host")
         out["cpu_baseline"] = cpu_baseline(wls[0], args.cpu_seconds)

@@ -165,10 +165,14 @@ typedef struct {
     double C11, C12, C44;  /* cubic constants (lattice axes)   */
     double Gc;             /* critical energy release rate     */
     double beta;           /* cleavage anisotropy A_f = I + beta (I - n (x) n) of the
-                              crack-surface density (Sec. 2.2, Eq. 14-15); only the
-                              isotropic surface beta = 0 is supported: other values
-                              are rejected with RVE_EINVAL                        */
-    double n[3];           /* cleavage-plane normal (lattice axes) for beta != 0   */
+                              crack-surface density (Sec. 2.2, Eq. 14-17, 36-37b):
+                              the damage gradient term becomes Gc l/2 grad phi . A
+                              grad phi in D, the damage operator and the enrichment;
+                              0 = isotropic; must be finite and > -1               */
+    double n[3];           /* weak-plane normal in lattice axes (beta != 0), rotated
+                              with the voxel's theta about z; in 2D its projection on
+                              the plane is used, normalised (along z: A = (1+beta) I);
+                              in 3D it must be non-zero                            */
 } rve_phase;
 
 typedef struct {

@@ -13,7 +13,13 @@ Readings of the paper taken here:
   no elastic driving force (psi_0 = 0) and its phase's G_c.
 * Discrete damage derivatives.  Forward differences with periodic wrap;
   the operator L(phi) = -div(G_c l A grad phi) of Eq. 10b / 17 is
-  D^T diag(G_c l) D with D the forward difference (A = I, beta = 0).
+  sum_jk D_j^T diag(G_c l A_jk) D_k with D the forward difference, A the
+  voxel's cleavage tensor (Eq. 15) applied to the forward-difference
+  gradient at the voxel (A = I when beta = 0).
+* Cleavage tensor (Sec. 2.2, Eq. 15).  A = I + beta (I - n n) with n the
+  phase's weak-plane normal (lattice axes) rotated by the voxel's angle
+  about z; in 2D, n is its projection on the plane, normalised (A = (1 +
+  beta) I when the normal is along z).
 * Crack-tip enrichment (Eq. 35).  The smoothing solves
   phi_o + l^2 D^T D phi_o = phi_disc (the printed l in front of the
   Laplacian is taken as l^2 for consistent units).
@@ -43,8 +49,26 @@ def phase_stiffness(phase, d, theta=0.0):
     return mandel.c4_to_mandel(C4r, d), mandel.bulk_modulus_c4(C4r)
 
 
+def cleavage_tensor(phase, d, theta=0.0):
+    """A_f = I + beta (I - n n) of one phase (Eq. 15), n rotated about z by
+    theta and, in 2D, projected on the plane and normalised."""
+    beta = float(phase.get("beta", 0.0))
+    I = np.eye(d)
+    if beta == 0.0:
+        return I
+    n = mandel.rotation_z(theta) @ np.asarray(phase.get("n", (0.0, 0.0, 1.0)), dtype=float)
+    n = n[:d]
+    norm = np.linalg.norm(n)
+    if norm == 0.0:
+        return (1.0 + beta) * I
+    n = n / norm
+    return I + beta * (I - np.outer(n, n))
+
+
 class MaterialField:
-    """Per-voxel stiffness C[*n, s, s], bulk modulus K, G_c and void flag."""
+    """Per-voxel stiffness C[*n, s, s], bulk modulus K, G_c, void flag and,
+    when some phase has beta != 0, the cleavage tensor A[*n, d, d] (else
+    A is None: the isotropic functionals)."""
 
     def __init__(self, n, phases, phase_id, theta=None, void=None, k=1e-6):
         n = tuple(n)
@@ -55,6 +79,8 @@ class MaterialField:
         self.K = np.zeros(n)
         self.Gc = np.zeros(n)
         self.void = np.zeros(n, dtype=bool) if void is None else void.astype(bool)
+        aniso = any(float(ph.get("beta", 0.0)) != 0.0 for ph in phases)
+        self.A = np.zeros(n + (d, d)) if aniso else None
         cache = {}
         for idx in np.ndindex(*n):
             p = int(phase_id[idx])
@@ -67,6 +93,8 @@ class MaterialField:
             self.C[idx] = scale * C
             self.K[idx] = scale * K
             self.Gc[idx] = phases[p]["Gc"]
+            if aniso:
+                self.A[idx] = cleavage_tensor(phases[p], d, th)
 
 
 def degradation(phi, k):
@@ -137,25 +165,35 @@ def backward_difference_adjoint(v, axis, h):
     return (np.roll(v, 1, axis=axis) - v) / h
 
 
-def dissipation(phi, Gc, ell, h):
-    """D(phi) = int G_c (phi^2 / 2l + l/2 grad phi . grad phi) (Eq. 3)."""
+def _grad_A_grad(phi, h, A):
+    """grad phi . A grad phi per voxel, forward-difference gradient."""
     d = phi.ndim
-    dens = phi ** 2 / (2.0 * ell)
-    for j in range(d):
-        dens = dens + 0.5 * ell * forward_difference(phi, j, h) ** 2
+    g = [forward_difference(phi, j, h) for j in range(d)]
+    if A is None:
+        return sum(gj * gj for gj in g)
+    return sum(A[..., j, k] * g[j] * g[k] for j in range(d) for k in range(d))
+
+
+def dissipation(phi, Gc, ell, h, A=None):
+    """D(phi) = int G_c (phi^2 / 2l + l/2 A : grad phi grad phi) (Eq. 3, 14)."""
+    d = phi.ndim
+    dens = phi ** 2 / (2.0 * ell) + 0.5 * ell * _grad_A_grad(phi, h, A)
     return float(np.sum(Gc * dens) * h ** d)
 
 
-def crack_surface(phi, ell, h):
-    """Gamma(phi) = int (phi^2 / 2l + l/2 grad phi . grad phi) (Eq. 4)."""
-    return dissipation(phi, np.ones_like(phi), ell, h)
+def crack_surface(phi, ell, h, A=None):
+    """Gamma(phi) = int (phi^2 / 2l + l/2 A : grad phi grad phi) (Eq. 4)."""
+    return dissipation(phi, np.ones_like(phi), ell, h, A)
 
 
-def damage_operator(phi, Gc, ell, h):
-    """L(phi) = -div(G_c l grad phi) = sum_j D_j^T (G_c l D_j phi)."""
+def damage_operator(phi, Gc, ell, h, A=None):
+    """L(phi) = -div(G_c l A grad phi) = sum_jk D_j^T (G_c l A_jk D_k phi) (Eq. 17)."""
+    d = phi.ndim
+    g = [forward_difference(phi, k, h) for k in range(d)]
     out = np.zeros_like(phi)
-    for j in range(phi.ndim):
-        out += backward_difference_adjoint(Gc * ell * forward_difference(phi, j, h), j, h)
+    for j in range(d):
+        flux = g[j] if A is None else sum(A[..., j, k] * g[k] for k in range(d))
+        out += backward_difference_adjoint(Gc * ell * flux, j, h)
     return out
 
 
@@ -166,9 +204,9 @@ def damage_operator_fft(phi, Gc, ell, dsym):
     return -spectral.divergence(Gc * ell * grad, dsym)
 
 
-def gamma_prime(phi, Gc, ell, h):
-    """gamma_f'(phi) = G_c phi / l - div(G_c l grad phi) (Eq. 17, A = I)."""
-    return Gc * phi / ell + damage_operator(phi, Gc, ell, h)
+def gamma_prime(phi, Gc, ell, h, A=None):
+    """gamma_f'(phi) = G_c phi / l - div(G_c l A grad phi) (Eq. 17)."""
+    return Gc * phi / ell + damage_operator(phi, Gc, ell, h, A)
 
 
 def _difference_matrix_1d(N, h):
@@ -188,44 +226,59 @@ def difference_matrices(n, h):
     return mats
 
 
-def damage_matrix(H, Gc, ell, Dmats):
-    """Matrix of the damage system (G_c/l + 2H) phi + L phi = 2H (Eq. 10b with
-    H in place of psi_o, Eq. 11)."""
+def gradient_matrix(coef, Dmats, A=None):
+    """sum_jk D_j^T diag(coef A_jk) D_k (A = I when None)."""
+    d = len(Dmats)
+    M = None
+    for j in range(d):
+        for k in range(d):
+            if A is None and j != k:
+                continue
+            c = coef if A is None else coef * A[..., j, k]
+            term = Dmats[j].T @ sp.diags(np.ravel(c)) @ Dmats[k]
+            M = term if M is None else M + term
+    return M
+
+
+def damage_matrix(H, Gc, ell, Dmats, A=None):
+    """Matrix of the damage system (G_c/l + 2H) phi + L phi = 2H (Eq. 10b / 16b
+    with H in place of psi_o, Eq. 11, 17)."""
     diag = (Gc / ell + 2.0 * H).ravel()
-    A = sp.diags(diag)
-    w = sp.diags((Gc * ell).ravel())
-    for D in Dmats:
-        A = A + D.T @ w @ D
-    return A.tocsc()
+    return (sp.diags(diag) + gradient_matrix(Gc * ell, Dmats, A)).tocsc()
 
 
-def factor_damage(H, Gc, ell, Dmats):
+def factor_damage(H, Gc, ell, Dmats, A=None):
     """Sparse LU factors of the damage matrix; .solve(b) applies its inverse."""
-    return spla.splu(damage_matrix(H, Gc, ell, Dmats))
+    return spla.splu(damage_matrix(H, Gc, ell, Dmats, A))
 
 
-def solve_damage(H, Gc, ell, Dmats, rhs=None):
+def solve_damage(H, Gc, ell, Dmats, rhs=None, A=None):
     """phi solving (G_c/l + 2H) phi + L phi = 2H (or the given rhs), direct."""
-    A = damage_matrix(H, Gc, ell, Dmats)
+    M = damage_matrix(H, Gc, ell, Dmats, A)
     b = (2.0 * H if rhs is None else rhs).ravel()
-    return spla.spsolve(A, b).reshape(H.shape)
+    return spla.spsolve(M, b).reshape(H.shape)
 
 
 # --------------------------------------------------------------------------
 # crack-tip enrichment (Sec. 4.3, Eq. 35, 37a, 38)
 # --------------------------------------------------------------------------
 
-def cte_initial_damage(phi_disc, ell, h, phi_M):
-    """phi_o + l^2 D^T D phi_o = phi_disc; phi_ini = phi_M phi_o / max phi_o (Eq. 35)."""
+def cte_initial_damage(phi_disc, ell, h, phi_M, A=None, Dmats=None):
+    """phi_o + l^2 D^T A D phi_o = phi_disc; phi_ini = phi_M phi_o / max phi_o
+    (Eq. 35; Eq. 36 with the cleavage tensor A, solved directly then)."""
     n = phi_disc.shape
     if not np.any(phi_disc > 0):
         return np.zeros(n)
-    dsym = spectral.difference_symbols(n, h)
-    lap = np.sum(np.abs(dsym) ** 2, axis=0)
-    phio = np.fft.ifftn(np.fft.fftn(phi_disc) / (1.0 + ell ** 2 * lap)).real
+    if A is None:
+        dsym = spectral.difference_symbols(n, h)
+        lap = np.sum(np.abs(dsym) ** 2, axis=0)
+        phio = np.fft.ifftn(np.fft.fftn(phi_disc) / (1.0 + ell ** 2 * lap)).real
+    else:
+        M = sp.identity(int(np.prod(n))) + gradient_matrix(np.full(n, ell * ell), Dmats, A)
+        phio = spla.spsolve(M.tocsc(), np.ravel(phi_disc).astype(float)).reshape(n)
     return phi_M * phio / np.max(phio)
 
 
-def cte_initial_energy(phi_ini, Gc, ell, h):
-    """psi_ini = max(0, gamma_f'(phi_ini) / (2 (1 - phi_ini))) (Eq. 37a, sign read)."""
-    return np.maximum(gamma_prime(phi_ini, Gc, ell, h) / (2.0 * (1.0 - phi_ini)), 0.0)
+def cte_initial_energy(phi_ini, Gc, ell, h, A=None):
+    """psi_ini = max(0, gamma_f'(phi_ini) / (2 (1 - phi_ini))) (Eq. 37a / 37b, sign read)."""
+    return np.maximum(gamma_prime(phi_ini, Gc, ell, h, A) / (2.0 * (1.0 - phi_ini)), 0.0)

@@ -220,20 +220,26 @@ def arclength(prob, psi1, psi_ini, Hn, tau, E0):
     def evaluate(E):
         nonlocal nsolves
         H = history_field(prob, E, psi1, psi_ini, Hn)
-        lu = model.factor_damage(H, Gc, ell, prob.Dmats)
+        lu = model.factor_damage(H, Gc, ell, prob.Dmats, prob.mat.A)
         phi = lu.solve((2.0 * H).ravel()).reshape(prob.n)
         nsolves += 1
-        return model.dissipation(phi, Gc, ell, h), phi, H, lu
+        return model.dissipation(phi, Gc, ell, h, prob.mat.A), phi, H, lu
 
     def derivative(E, phi, lu):
         Ht = E * E * psi1 + psi_ini
         active = (Ht > Hn) if prob.history else np.ones(prob.n, dtype=bool)
         dH = np.where(active, 2.0 * E * psi1, 0.0)
         dphi = lu.solve((2.0 * (1.0 - phi) * dH).ravel()).reshape(prob.n)
+        # dD/dE = int G_c (phi phi' / l + l grad phi . A grad phi')
+        A = prob.mat.A
         dens = Gc * phi * dphi / ell
         for j in range(prob.d):
-            dens = dens + Gc * ell * model.forward_difference(phi, j, h) * \
-                model.forward_difference(dphi, j, h)
+            for k in range(prob.d):
+                if A is None and j != k:
+                    continue
+                a = 1.0 if A is None else A[..., j, k]
+                dens = dens + Gc * ell * a * model.forward_difference(phi, j, h) * \
+                    model.forward_difference(dphi, k, h)
         return float(np.sum(dens) * h ** prob.d)
 
     lo, hi = 0.0, math.inf
@@ -266,20 +272,22 @@ def arclength(prob, psi1, psi_ini, Hn, tau, E0):
 class State:
     def __init__(self, prob):
         Gc = prob.mat.Gc
-        self.phi_ini = model.cte_initial_damage(prob.phi_disc, prob.ell, prob.h, prob.phi_M)
-        self.psi_ini = model.cte_initial_energy(self.phi_ini, Gc, prob.ell, prob.h)
+        A = prob.mat.A
+        self.phi_ini = model.cte_initial_damage(prob.phi_disc, prob.ell, prob.h, prob.phi_M, A,
+                                                prob.Dmats)
+        self.psi_ini = model.cte_initial_energy(self.phi_ini, Gc, prob.ell, prob.h, A)
         self.phi = self.phi_ini.copy()
         self.H = self.psi_ini.copy()
         self.x = np.zeros((prob.s,) + prob.n)
         self.E = 0.0
         self.Sigma = 0.0
         self.T = 0.0
-        self.tau = model.dissipation(self.phi, Gc, prob.ell, prob.h)
+        self.tau = model.dissipation(self.phi, Gc, prob.ell, prob.h, A)
         self.tau0 = self.tau
         self.step = 0
         self.fractured = False
         self.curve = [dict(step=0, E=0.0, Sigma=0.0, T=0.0, D=self.tau,
-                           Gamma=model.crack_surface(self.phi, prob.ell, prob.h), tau=self.tau)]
+                           Gamma=model.crack_surface(self.phi, prob.ell, prob.h, A), tau=self.tau)]
 
 
 def fractured(prob, phi):
@@ -389,8 +397,8 @@ def _step_once(prob, st, dtau):
     st.step += 1
     st.fractured = fractured(prob, phi)
     rec = dict(step=st.step, E=E, Sigma=Sigma, T=st.T,
-               D=model.dissipation(phi, prob.mat.Gc, prob.ell, prob.h),
-               Gamma=model.crack_surface(phi, prob.ell, prob.h), tau=tau,
+               D=model.dissipation(phi, prob.mat.Gc, prob.ell, prob.h, prob.mat.A),
+               Gamma=model.crack_surface(phi, prob.ell, prob.h, prob.mat.A), tau=tau,
                n_stagger=it, n_cg=n_cg, n_damage_solves=n_solves, fractured=st.fractured)
     rec["G_inst"] = instantaneous_G(prob, st.curve[-1], rec)
     st.curve.append(rec)

@@ -53,6 +53,8 @@ struct MatEntry {
     T Gc;            // critical energy release rate
     T drive;         // 1, or 0 on notch voxels (no elastic driving force)
     T pad;
+    T A[6];          // cleavage tensor A_f = I + beta (I - n n) (Eq. 15) in the
+                     // order xx, yy, zz, yz, xz, xy (2D: xx, yy, xy used)
 };
 
 // Geometry shared by all kernels of a handle.
@@ -66,6 +68,7 @@ struct Geom {
     double inv_N;             // 1 / N (inverse DFT normalisation)
     int B;                    // RVEs in the batch
     int mstride;              // material-table entries per RVE
+    int aniso;                // 1 when some phase has a cleavage tensor A != I
 };
 
 }  // namespace mirve

@@ -70,6 +70,83 @@ __device__ inline Nb neighbours(const Geom& g, long long idx) {
 }
 
 // ---------------------------------------------------------------------------
+// cleavage anisotropy (Sec. 2.2, Eq. 14-17): the damage operator
+// sum_jk D_j^T (w A_jk D_k p), A per voxel, forward differences D
+// ---------------------------------------------------------------------------
+
+// A_jk of a material entry (A stored as xx, yy, zz, yz, xz, xy)
+template <typename T>
+__device__ __forceinline__ T acoef(const MatEntry<T>& m, int j, int k) {
+    if (j == k) return m.A[j];
+    const int t = j + k;                       // (x, y) 1, (x, z) 2, (y, z) 3
+    return m.A[t == 1 ? 5 : t == 2 ? 4 : 3];
+}
+
+// voxel idx shifted by (dx, dy, dz) voxels, periodic (|d| <= 1)
+__device__ inline long long shifted(const Geom& g, long long idx, int dx, int dy, int dz) {
+    unsigned xu, yu;
+    const unsigned t = divmod_u32((unsigned)idx, (unsigned)g.nx, xu);
+    const unsigned zu = divmod_u32(t, (unsigned)g.ny, yu);
+    int x = (int)xu + dx, y = (int)yu + dy, z = (int)zu + dz;
+    x += x < 0 ? g.nx : (x >= g.nx ? -g.nx : 0);
+    y += y < 0 ? g.ny : (y >= g.ny ? -g.ny : 0);
+    z += z < 0 ? g.nz : (z >= g.nz ? -g.nz : 0);
+    return ((long long)z * g.ny + y) * g.nx + x;
+}
+
+__device__ __forceinline__ long long step_axis(const Geom& g, long long idx, int axis, int d) {
+    return shifted(g, idx, axis == 0 ? d : 0, axis == 1 ? d : 0, axis == 2 ? d : 0);
+}
+
+// sum_j [w_j(i - e_j) - w_j(i)] h^-2 with w_j(k) = coef(k) sum_m A_jm(k)
+// (p(k + e_m) - p(k)): the anisotropic part of the operator at voxel i.
+// coef(k) is Gc(k) l (mode 0) or c (mode 1); pv(k) returns p at voxel k.
+template <typename R, typename T, typename PV>
+__device__ inline R aniso_div(const Geom& g, const uint16_t* mid, const MatEntry<T>* mt, int mode,
+                              R c, long long i, PV pv) {
+    const R ell = R(g.ell);
+    const int d = g.dim;
+    const R pi = pv(i);
+    R acc = R(0);
+    const MatEntry<T>& mi = mt[mid[i]];
+    const R ci = mode == 0 ? R(mi.Gc) * ell : c;
+    for (int j = 0; j < d; ++j) {
+        // w_j at the voxel itself
+        R wi = R(0);
+        for (int m = 0; m < d; ++m) wi += R(acoef(mi, j, m)) * (pv(step_axis(g, i, m, 1)) - pi);
+        // w_j at i - e_j, whose forward neighbour along j is i
+        const long long k = step_axis(g, i, j, -1);
+        const MatEntry<T>& mk = mt[mid[k]];
+        const R ck = mode == 0 ? R(mk.Gc) * ell : c;
+        const R pk = pv(k);
+        R wk = R(0);
+        for (int m = 0; m < d; ++m) {
+            const long long km = m == j ? i : step_axis(g, k, m, 1);
+            wk += R(acoef(mk, j, m)) * (pv(km) - pk);
+        }
+        acc += ck * wk - ci * wi;
+    }
+    return acc * R(1.0 / (g.h * g.h));
+}
+
+// grad a . A grad b at voxel i (forward differences, A of the voxel's entry)
+template <typename R, typename T, typename PA, typename PB>
+__device__ inline R aniso_grad_dot(const Geom& g, const MatEntry<T>& m, long long i, PA pa, PB pb) {
+    const int d = g.dim;
+    R ga[3], gb[3];
+    const R a0 = pa(i), b0 = pb(i);
+    for (int j = 0; j < d; ++j) {
+        const long long nb = step_axis(g, i, j, 1);
+        ga[j] = pa(nb) - a0;
+        gb[j] = pb(nb) - b0;
+    }
+    R s = R(0);
+    for (int j = 0; j < d; ++j)
+        for (int k = 0; k < d; ++k) s += R(acoef(m, j, k)) * ga[j] * gb[k];
+    return s * R(1.0 / (g.h * g.h));
+}
+
+// ---------------------------------------------------------------------------
 // finalize kernels: one block of 256 threads per RVE (blockIdx.x = b)
 // ---------------------------------------------------------------------------
 
@@ -373,6 +450,8 @@ __device__ inline T apply_op(const Geom& g, const uint16_t* mid, const MatEntry<
                              const T* H, int mode, T c, const T* p, long long i) {
     T a, w;
     coeffs(g, mat, mid, H, mode, c, i, a, w);
+    if (g.aniso)
+        return a * p[i] + aniso_div<T>(g, mid, mat, mode, c, i, [&](long long k) { return p[k]; });
     const Nb n = neighbours(g, i);
     const T ell = T(g.ell);
     const T ih2 = T(1.0 / (g.h * g.h));
@@ -438,8 +517,20 @@ __global__ void __launch_bounds__(TPB) k_damage_diag(Geom g, const uint16_t* mat
         T a, w;
         coeffs(g, mt, mid, Hb, mode, c, i, a, w);
         const Nb n = neighbours(g, i);
-        T s = T(2) * w + wcoef(mt, mid, mode, ell, c, n.xm) + wcoef(mt, mid, mode, ell, c, n.ym);
-        if (g.dim == 3) s += w + wcoef(mt, mid, mode, ell, c, n.zm);
+        T s;
+        if (g.aniso) {
+            // sum_j [coef(i - e_j) A_jj(i - e_j) + coef(i) sum_m A_jm(i)]
+            s = T(0);
+            const MatEntry<T>& mi = mt[mid[i]];
+            for (int j = 0; j < g.dim; ++j) {
+                const long long k = step_axis(g, i, j, -1);
+                s += wcoef(mt, mid, mode, ell, c, k) * acoef(mt[mid[k]], j, j);
+                for (int m = 0; m < g.dim; ++m) s += w * acoef(mi, j, m);
+            }
+        } else {
+            s = T(2) * w + wcoef(mt, mid, mode, ell, c, n.xm) + wcoef(mt, mid, mode, ell, c, n.ym);
+            if (g.dim == 3) s += w + wcoef(mt, mid, mode, ell, c, n.zm);
+        }
         const T di = T(1) / (a + s * T(1.0 / (g.h * g.h)));
         dinv[so + i] = sqrt_out ? sqrt(di) : di;
         sa += double(a);
@@ -611,7 +702,30 @@ __global__ void __launch_bounds__(TPB) k_pcg_matvec_dir(
     const T* Hb = H ? H + so : nullptr;
     const T* zf = zf_a ? zf_a + so : nullptr;
     double part;
-    if (g.dim == 2)
+    if (g.aniso) {
+        // the direction p = z + beta p_old formed at every voxel the
+        // anisotropic stencil reads (the voxel, its axis and diagonal
+        // neighbours), then q = A p
+        const T* r = r_a + so;
+        const T* dv = dinv_a + so;
+        const T* po = po_a + so;
+        const bool first = k == 0;
+        auto pv = [&](long long j) {
+            const T z = zval<T, PRE>(r, dv, zf, j);
+            return first ? z : z + beta * po[j];
+        };
+        part = 0.0;
+        for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.N;
+             i += (long long)gridDim.x * blockDim.x) {
+            T a, w;
+            coeffs(g, mt, mid, Hb, mode, c, i, a, w);
+            const T pc = pv(i);
+            const T v = a * pc + aniso_div<T>(g, mid, mt, mode, c, i, pv);
+            pn_a[so + i] = pc;
+            q_a[so + i] = v;
+            part += double(pc) * double(v);
+        }
+    } else if (g.dim == 2)
         part = matvec_dir_rounds<T, PRE, 2, 2>(g, mid, mt, Hb, mode, c, r_a + so, dinv_a + so, zf,
                                                po_a + so, beta, k == 0, pn_a + so, q_a + so);
     else
@@ -697,10 +811,17 @@ __global__ void __launch_bounds__(TPB) k_dissipation(Geom g, const uint16_t* mat
          i += (long long)gridDim.x * blockDim.x) {
         const Nb n = neighbours(g, i);
         const double pc = phi[i];
-        const double gx = (double(phi[n.xp]) - pc) * ih;
-        const double gy = (double(phi[n.yp]) - pc) * ih;
-        const double gz = g.dim == 3 ? (double(phi[n.zp]) - pc) * ih : 0.0;
-        const double dens = pc * pc / (2.0 * ell) + 0.5 * ell * (gx * gx + gy * gy + gz * gz);
+        double gag;
+        if (g.aniso) {
+            auto pv = [&](long long k) { return double(phi[k]); };
+            gag = aniso_grad_dot<double>(g, mt[mid[i]], i, pv, pv);
+        } else {
+            const double gx = (double(phi[n.xp]) - pc) * ih;
+            const double gy = (double(phi[n.yp]) - pc) * ih;
+            const double gz = g.dim == 3 ? (double(phi[n.zp]) - pc) * ih : 0.0;
+            gag = gx * gx + gy * gy + gz * gz;
+        }
+        const double dens = pc * pc / (2.0 * ell) + 0.5 * ell * gag;
         sD += double(mt[mid[i]].Gc) * dens;
         sG += dens;
     }
@@ -811,9 +932,15 @@ __global__ void __launch_bounds__(TPB) k_dissipation_dir(Geom g, const uint16_t*
          i += (long long)gridDim.x * blockDim.x) {
         const Nb n = neighbours(g, i);
         const double pc = phi[i], dc = dphi[i];
-        double gg = (double(phi[n.xp]) - pc) * (double(dphi[n.xp]) - dc);
-        gg += (double(phi[n.yp]) - pc) * (double(dphi[n.yp]) - dc);
-        if (g.dim == 3) gg += (double(phi[n.zp]) - pc) * (double(dphi[n.zp]) - dc);
+        double gg;
+        if (g.aniso) {
+            gg = aniso_grad_dot<double>(g, mt[mid[i]], i, [&](long long k) { return double(phi[k]); },
+                                        [&](long long k) { return double(dphi[k]); }) / (ih * ih);
+        } else {
+            gg = (double(phi[n.xp]) - pc) * (double(dphi[n.xp]) - dc);
+            gg += (double(phi[n.yp]) - pc) * (double(dphi[n.yp]) - dc);
+            if (g.dim == 3) gg += (double(phi[n.zp]) - pc) * (double(dphi[n.zp]) - dc);
+        }
         s += double(mt[mid[i]].Gc) * (pc * dc / ell + ell * gg * ih * ih);
     }
     double pv[1] = {s};
@@ -1103,10 +1230,16 @@ __global__ void __launch_bounds__(TPB) k_ir_residual(Geom g, const uint16_t* mat
         const double hn = double(Hn[so + i]);
         const double hb = 2.0 * (history && hn > ht ? hn : ht);
         const double a = gc / ell + hb, w = gc * ell, pc = p[i];
-        double acc = double(mt[mid[n.xm]].Gc) * ell * (pc - p[n.xm]) - w * (p[n.xp] - pc);
-        acc += double(mt[mid[n.ym]].Gc) * ell * (pc - p[n.ym]) - w * (p[n.yp] - pc);
-        if (g.dim == 3) acc += double(mt[mid[n.zm]].Gc) * ell * (pc - p[n.zm]) - w * (p[n.zp] - pc);
-        const double res = hb - (a * pc + acc * ih2);
+        double op;
+        if (g.aniso) {
+            op = a * pc + aniso_div<double>(g, mid, mt, 0, 0.0, i, [&](long long k) { return p[k]; });
+        } else {
+            double acc = double(mt[mid[n.xm]].Gc) * ell * (pc - p[n.xm]) - w * (p[n.xp] - pc);
+            acc += double(mt[mid[n.ym]].Gc) * ell * (pc - p[n.ym]) - w * (p[n.yp] - pc);
+            if (g.dim == 3) acc += double(mt[mid[n.zm]].Gc) * ell * (pc - p[n.zm]) - w * (p[n.zp] - pc);
+            op = a * pc + acc * ih2;
+        }
+        const double res = hb - op;
         r[so + i] = T(res);
         s0 += res * res;
         s1 += hb * hb;
@@ -1186,10 +1319,17 @@ __global__ void __launch_bounds__(TPB) k_dissipation64(Geom g, const uint16_t* m
          i += (long long)gridDim.x * blockDim.x) {
         const Nb n = neighbours(g, i);
         const double pc = phi[i];
-        const double gx = (phi[n.xp] - pc) * ih;
-        const double gy = (phi[n.yp] - pc) * ih;
-        const double gz = g.dim == 3 ? (phi[n.zp] - pc) * ih : 0.0;
-        const double dens = pc * pc / (2.0 * ell) + 0.5 * ell * (gx * gx + gy * gy + gz * gz);
+        double gag;
+        if (g.aniso) {
+            auto pv = [&](long long k) { return phi[k]; };
+            gag = aniso_grad_dot<double>(g, mt[mid[i]], i, pv, pv);
+        } else {
+            const double gx = (phi[n.xp] - pc) * ih;
+            const double gy = (phi[n.yp] - pc) * ih;
+            const double gz = g.dim == 3 ? (phi[n.zp] - pc) * ih : 0.0;
+            gag = gx * gx + gy * gy + gz * gz;
+        }
+        const double dens = pc * pc / (2.0 * ell) + 0.5 * ell * gag;
         sD += double(mt[mid[i]].Gc) * dens;
         sG += dens;
     }

@@ -88,10 +88,33 @@ static void mandel_rotation(double theta, double Q[6][6]) {
 struct HostMat {
     double C[6][6];
     double K, Gc, drive;
+    double A[6];        // cleavage tensor, order xx, yy, zz, yz, xz, xy
 };
 
-static HostMat phase_entry(const rve_phase& ph, double theta, bool notch, double k_res) {
+// Cleavage tensor A_f = I + beta (I - n n) of a phase (Sec. 2.2, Eq. 15):
+// the lattice normal n rotated about z by theta; in 2D its projection on the
+// plane, normalised (all in-plane directions alike, A = (1 + beta) I, when
+// the normal is along z).
+static void cleavage_tensor(const rve_phase& ph, double theta, int dim, double A[6]) {
+    const double c = std::cos(theta), s = std::sin(theta);
+    double n[3] = {c * ph.n[0] - s * ph.n[1], s * ph.n[0] + c * ph.n[1], ph.n[2]};
+    if (dim == 2) n[2] = 0.0;
+    const double nn = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    const double b = ph.beta;
+    if (nn > 0.0)
+        for (double& v : n) v /= nn;
+    // I + beta (I - n n); with no normal, I + beta I in the plane
+    A[0] = 1.0 + b * (1.0 - n[0] * n[0]);
+    A[1] = 1.0 + b * (1.0 - n[1] * n[1]);
+    A[2] = 1.0 + b * (1.0 - n[2] * n[2]);
+    A[3] = -b * n[1] * n[2];
+    A[4] = -b * n[0] * n[2];
+    A[5] = -b * n[0] * n[1];
+}
+
+static HostMat phase_entry(const rve_phase& ph, double theta, bool notch, double k_res, int dim) {
     HostMat m;
+    cleavage_tensor(ph, theta, dim, m.A);
     double C[6][6] = {{0}};
     if (ph.kind == RVE_PHASE_ISO) {
         const double lam = ph.E * ph.nu / ((1.0 + ph.nu) * (1.0 - 2.0 * ph.nu));
@@ -453,6 +476,7 @@ struct Solver : SolverBase {
         g.inv_N = 1.0 / double(g.N);
         g.B = std::max(1, c.batch);
         g.mstride = std::max(1, c.max_materials);
+        g.aniso = 0;
         if (!factorize(g.nx, px) || !factorize(g.ny, py) || !factorize(g.nz, pz)) {
             why = "grid sizes must be products of 2, 3, 5, 7 (<= 1024)";
             return false;
@@ -1385,10 +1409,12 @@ struct Solver : SolverBase {
         for (int i = 0; i < nph; ++i) {
             const rve_phase& ph = phases[i];
             if (!(ph.Gc > 0.0) || !std::isfinite(ph.Gc)) return fail(RVE_EINVAL, "Gc must be > 0");
-            if (ph.beta != 0.0)
-                return fail(RVE_EINVAL, "cleavage anisotropy (beta != 0) is not supported: beta must be 0");
+            if (!std::isfinite(ph.beta) || !(ph.beta > -1.0))
+                return fail(RVE_EINVAL, "cleavage weight beta must be finite and > -1");
             for (int a = 0; a < 3; ++a)
                 if (!std::isfinite(ph.n[a])) return fail(RVE_EINVAL, "non-finite cleavage normal");
+            if (ph.beta != 0.0 && g.dim == 3 && ph.n[0] == 0.0 && ph.n[1] == 0.0 && ph.n[2] == 0.0)
+                return fail(RVE_EINVAL, "a phase with beta != 0 needs a cleavage normal n");
             if (ph.kind == RVE_PHASE_ISO) {
                 if (!(ph.E > 0.0) || !std::isfinite(ph.E) || !(ph.nu > -1.0 && ph.nu < 0.5))
                     return fail(RVE_EINVAL, "isotropic phase needs E > 0, -1 < nu < 0.5");
@@ -1412,7 +1438,9 @@ struct Solver : SolverBase {
             const double th = theta ? theta[i] : 0.0;
             if (!std::isfinite(th)) return fail(RVE_EINVAL, "non-finite theta");
             const int nt = vmask ? (vmask[i] ? 1 : 0) : 0;
-            auto key = std::make_tuple(ph, phases[ph].kind == RVE_PHASE_ISO ? 0.0 : th, nt);
+            // the angle matters for rotated stiffness and for cleavage tensors
+            const bool by_angle = phases[ph].kind != RVE_PHASE_ISO || phases[ph].beta != 0.0;
+            auto key = std::make_tuple(ph, by_angle ? th : 0.0, nt);
             auto it = keys.find(key);
             int id;
             if (it == keys.end()) {
@@ -1420,7 +1448,7 @@ struct Solver : SolverBase {
                 if (id >= g.mstride || id >= kMaxMat)
                     return fail(RVE_EINVAL, "more distinct materials than max_materials");
                 keys[key] = id;
-                HostMat hm = phase_entry(phases[ph], std::get<1>(key), nt != 0, cfg.k_res);
+                HostMat hm = phase_entry(phases[ph], std::get<1>(key), nt != 0, cfg.k_res, g.dim);
                 MatEntry<T> me;
                 std::memset(&me, 0, sizeof(me));
                 static const int in2d[3] = {0, 1, 5};
@@ -1433,6 +1461,7 @@ struct Solver : SolverBase {
                 me.K = T(hm.K);
                 me.Gc = T(hm.Gc);
                 me.drive = T(hm.drive);
+                for (int a = 0; a < 6; ++a) me.A[a] = T(hm.A[a]);
                 table.push_back(me);
             } else {
                 id = it->second;
@@ -1441,6 +1470,15 @@ struct Solver : SolverBase {
             min_gc = std::min(min_gc, phases[ph].Gc);
         }
         slope_warm[slot] = 0;
+        // a handle whose slots have a cleavage tensor switches its damage
+        // kernels to the anisotropic stencil (graphs captured before hold the
+        // isotropic one)
+        bool aniso = false;
+        for (int i = 0; i < nph; ++i) aniso = aniso || phases[i].beta != 0.0;
+        if (aniso && !g.aniso) {
+            g.aniso = 1;
+            clear_graphs();
+        }
         SlotState& S = slots[slot];
         S.ready = false;
         S.min_gc = min_gc;

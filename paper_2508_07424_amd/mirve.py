@@ -190,12 +190,13 @@ def rve_query_workspace(cfg):
 def phases_array(phases):
     arr = (rve_phase * len(phases))()
     for i, ph in enumerate(phases):
+        nrm = (C.c_double * 3)(*[float(v) for v in ph.get("n", (0.0, 0.0, 1.0))])
         if ph["kind"] == "iso":
             arr[i] = rve_phase(RVE_PHASE_ISO, ph["E"], ph["nu"], 0.0, 0.0, 0.0, ph["Gc"],
-                               ph.get("beta", 0.0))
+                               ph.get("beta", 0.0), nrm)
         else:
             arr[i] = rve_phase(RVE_PHASE_CUBIC, 0.0, 0.0, ph["C11"], ph["C12"], ph["C44"], ph["Gc"],
-                               ph.get("beta", 0.0))
+                               ph.get("beta", 0.0), nrm)
     return arr
 
 

@@ -316,12 +316,33 @@ def _voronoi_ids(X, Y, seeds, L):
     return gid
 
 
+def _laguerre_ids(X, Y, seeds, weights, L):
+    """Index of the seed of least power distance |x - s|^2 - w (periodic) of
+    every voxel centre: a weighted (Laguerre) Voronoi tessellation; ties go
+    to the lower index."""
+    best = np.full(X.shape, np.inf)
+    gid = np.zeros(X.shape, dtype=np.uint16)
+    for g in range(len(seeds)):
+        d2 = (_periodic_delta(X, seeds[g, 0], L) ** 2 + _periodic_delta(Y, seeds[g, 1], L) ** 2
+              - weights[g])
+        closer = d2 < best
+        best[closer] = d2[closer]
+        gid[closer] = g
+    return gid
+
+
 def polycrystal_2d(n=512, grains=200, seed=1000, zener=2.0, a_cleave=1.0, ell=2.0,
-                   crack_frac=0.1):
+                   crack_frac=0.1, beta=0.0, size_sigma=0.0):
     """Periodic Voronoi polycrystal with uniform in-plane orientations.
 
     Cubic C11 = 1, C12 = 0.5, C44 = z/4 (so 2 C44 / (C11 - C12) = z);
     per-grain Gc = 1 + a cos^2(4 theta).  Each grain is its own phase.
+    beta > 0 gives every grain a cleavage plane (Sec. 5.3): the cubic [100]
+    plane, weak-plane normal (1, 0, 0) in lattice axes, rotated with the
+    grain.  size_sigma > 0 draws the grains as a weighted (Laguerre)
+    tessellation whose seed radii are log-normal with that standard
+    deviation of log r (Sec. 5.3 uses a weighted Voronoi with log-normal
+    grain sizes); 0 gives the plain Voronoi tessellation.
     """
     nn = (n, n)
     h = 1.0
@@ -329,9 +350,16 @@ def polycrystal_2d(n=512, grains=200, seed=1000, zener=2.0, a_cleave=1.0, ell=2.
     seeds = rng.uniform(0.0, n * h, size=(grains, 2))
     theta_g = rng.uniform(0.0, 2.0 * np.pi, size=grains)
     X, Y = _centres(nn, h)
-    gid = _voronoi_ids(X, Y, seeds, n * h)
+    if size_sigma > 0.0:
+        r_mean = n * h / math.sqrt(math.pi * grains)
+        radii = r_mean * np.exp(size_sigma * rng.standard_normal(grains) - 0.5 * size_sigma ** 2)
+        gid = _laguerre_ids(X, Y, seeds, radii ** 2, n * h)
+    else:
+        gid = _voronoi_ids(X, Y, seeds, n * h)
     C44 = zener / 4.0
     phases = [cubic(1.0, 0.5, C44, 1.0 + a_cleave * math.cos(4.0 * t) ** 2) for t in theta_g]
+    if beta != 0.0:
+        phases = [dict(p, beta=float(beta), n=(1.0, 0.0, 0.0)) for p in phases]
     theta = theta_g[gid]
     row = n // 2
     a = max(2, int(round(crack_frac * n)))
@@ -340,7 +368,8 @@ def polycrystal_2d(n=512, grains=200, seed=1000, zener=2.0, a_cleave=1.0, ell=2.
     return Workload(n=nn, h=h, ell=ell, phases=phases, phase_id=gid, f=load_yy(2),
                     dtau=0.01 * n * h, theta=theta, void=void, phi_disc=tips, phi_M=0.8,
                     k=1e-6, meta={"name": "polycrystal_2d_%d" % n, "grains": grains,
-                                  "seed": seed, "zener": zener, "a": a_cleave})
+                                  "seed": seed, "zener": zener, "a": a_cleave, "beta": beta,
+                                  "size_sigma": size_sigma})
 
 
 def composite_3d(n=128, seed=1, spheres=40, vf=0.2, E_ratio=5.0, Gc_ratio=3.0, ell=2.0):

@@ -120,11 +120,12 @@ def test_non_finite_inputs_are_rejected():
         with pytest.raises(m.MirveError) as e:
             r.rve_set_microstructure(w.phase_id, ph, void=w.void, phi_disc=w.phi_disc)
         assert e.value.code == m.RVE_EINVAL
-    ph = [dict(p) for p in w.phases]
-    ph[1]["beta"] = 2.0                      # cleavage anisotropy is not supported
-    with pytest.raises(m.MirveError) as e:
-        r.rve_set_microstructure(w.phase_id, ph, void=w.void, phi_disc=w.phi_disc)
-    assert e.value.code == m.RVE_EINVAL
+    for beta in (float("nan"), -1.5):        # A_f = I + beta (I - n n) must stay positive
+        ph = [dict(p) for p in w.phases]
+        ph[1]["beta"] = beta
+        with pytest.raises(m.MirveError) as e:
+            r.rve_set_microstructure(w.phase_id, ph, void=w.void, phi_disc=w.phi_disc)
+        assert e.value.code == m.RVE_EINVAL
     sc = dict(before[2])
     sc["E"] = float("nan")
     with pytest.raises(m.MirveError) as e:

@@ -359,6 +359,116 @@ def test_crack_energy_per_length_tends_to_gc():
 
 
 # --------------------------------------------------------------------------
+# cleavage anisotropy (Sec. 2.2, Eq. 14-17)
+# --------------------------------------------------------------------------
+
+def test_cleavage_tensor_literal_values():
+    """A = I + beta (I - n n), n rotated about z by theta, projected and
+    normalised in 2D (Eq. 15)."""
+    ph = dict(kind="iso", E=1.0, nu=0.3, Gc=1.0, beta=2.0, n=(1.0, 0.0, 0.0))
+    assert np.allclose(model.cleavage_tensor(ph, 2), [[1.0, 0.0], [0.0, 3.0]], atol=1e-15)
+    assert np.allclose(model.cleavage_tensor(ph, 2, np.pi / 2), [[3.0, 0.0], [0.0, 1.0]], atol=1e-15)
+    # 45 degrees: n = (1, 1)/sqrt2, I - n n = [[1/2, -1/2], [-1/2, 1/2]]
+    assert np.allclose(model.cleavage_tensor(ph, 2, np.pi / 4), [[2.0, -1.0], [-1.0, 2.0]], atol=1e-15)
+    # a normal out of the plane projects to zero: every in-plane direction is weakened alike
+    ph_z = dict(ph, n=(0.0, 0.0, 1.0))
+    assert np.allclose(model.cleavage_tensor(ph_z, 2, 0.3), 3.0 * np.eye(2), atol=1e-15)
+    assert np.allclose(model.cleavage_tensor(ph_z, 3), np.diag([3.0, 3.0, 1.0]), atol=1e-15)
+    assert np.allclose(model.cleavage_tensor(dict(ph, beta=0.0), 2, 0.7), np.eye(2))
+
+
+def _line_crack_aniso(ell, beta, normal, ny=128, nx=2):
+    """Penalised broken row (crack along x, gradient along y) in a phase of
+    cleavage weight beta and weak-plane normal `normal`."""
+    n = (nx, ny)
+    H = np.zeros(n)
+    H[:, ny // 2] = 1e12
+    ph = dict(kind="iso", E=1.0, nu=0.3, Gc=1.0, beta=beta, n=normal)
+    mat = model.MaterialField(n, [ph], np.zeros(n, dtype=int))
+    Dm = model.difference_matrices(n, 1.0)
+    phi = model.solve_damage(H, np.ones(n), ell, Dm, A=mat.A)
+    return phi, mat.A
+
+
+@pytest.mark.parametrize("beta", [0.5, 1.0, 3.0])
+def test_cleavage_crack_energy_scales_with_sqrt_one_plus_beta(beta):
+    """With the crack plane the weak plane (normal e_y) the profile and
+    energy are the isotropic ones; with the weak-plane normal along the
+    crack (e_x), the gradient across the crack sees A_yy = 1 + beta, and the
+    discrete functional equals sqrt(1 + beta) times the isotropic one at
+    length l sqrt(1 + beta): the crack costs sqrt(1 + beta) G_c per length
+    in the continuum (Eq. 14)."""
+    ell = 1.7
+    phi_iso, _ = _line_crack(ell, 128, nx=2)
+    g_iso = model.crack_surface(phi_iso, ell, 1.0)
+    phi_w, A_w = _line_crack_aniso(ell, beta, (0.0, 1.0, 0.0))
+    assert np.max(np.abs(phi_w - phi_iso)) < 1e-12
+    assert abs(model.crack_surface(phi_w, ell, 1.0, A_w) - g_iso) < 1e-12 * g_iso
+    a = math.sqrt(1.0 + beta)
+    phi_s, A_s = _line_crack_aniso(ell, beta, (1.0, 0.0, 0.0))
+    phi_ref, _ = _line_crack(ell * a, 128, nx=2)
+    assert np.max(np.abs(phi_s - phi_ref)) < 1e-10
+    g = model.crack_surface(phi_s, ell, 1.0, A_s)
+    assert abs(g - a * model.crack_surface(phi_ref, ell * a, 1.0)) < 1e-10 * g
+    # and its continuum limit per unit length (two rows): sqrt(1 + beta) times
+    # the discrete factor 1 + (h / l_eff)^2 / 8 of l_eff = l sqrt(1 + beta)
+    assert 0.11 < (g / 2.0 / a - 1.0) * (ell * a) ** 2 < 0.13
+
+
+def test_cleavage_operator_forms_agree():
+    """The anisotropic damage operator: stencil form, sparse-matrix form and,
+    for a uniform tensor, the Fourier form with the symbol
+    sum_jk conj(d_j) A_jk d_k (off-diagonal coupling included); symmetric;
+    and the gradient of D (Eq. 14, 17) for a heterogeneous A."""
+    rng = np.random.default_rng(5)
+    n = (8, 6)
+    phi = rng.random(n)
+    ph = dict(kind="iso", E=1.0, nu=0.3, Gc=1.0, beta=2.0, n=(1.0, 0.0, 0.0))
+    A_u = np.broadcast_to(model.cleavage_tensor(ph, 2, 0.5), n + (2, 2)).copy()
+    Gc = np.full(n, 1.3)
+    L1 = model.damage_operator(phi, Gc, 1.4, 1.0, A_u)
+    dsym = spectral.difference_symbols(n, 1.0)
+    sym = sum(np.conj(dsym[j]) * A_u[0, 0, j, k] * dsym[k] for j in range(2) for k in range(2))
+    L2 = np.fft.ifftn(1.3 * 1.4 * sym * np.fft.fftn(phi)).real
+    assert np.max(np.abs(L1 - L2)) < 1e-12
+    # heterogeneous: per-voxel angles and weights
+    theta = rng.uniform(0, np.pi, size=n)
+    pid = (rng.random(n) < 0.5).astype(int)
+    phases = [dict(ph, beta=0.7), dict(ph, beta=3.0, n=(0.6, 0.8, 0.0))]
+    mat = model.MaterialField(n, phases, pid, theta=theta)
+    Gc = rng.uniform(1, 2, size=n)
+    Dm = model.difference_matrices(n, 1.0)
+    M = model.damage_matrix(np.zeros(n), Gc, 1.4, Dm, mat.A)
+    L3 = model.damage_operator(phi, Gc, 1.4, 1.0, mat.A) + Gc * phi / 1.4
+    assert np.max(np.abs(M @ phi.ravel() - L3.ravel())) < 1e-12
+    assert abs(M - M.T).max() < 1e-13
+    e = rng.standard_normal(n)
+    eps = 1e-6
+    fd = (model.dissipation(phi + eps * e, Gc, 1.4, 1.0, mat.A)
+          - model.dissipation(phi - eps * e, Gc, 1.4, 1.0, mat.A)) / (2 * eps)
+    assert abs(fd - np.sum(e * model.gamma_prime(phi, Gc, 1.4, 1.0, mat.A))) < 1e-7 * abs(fd)
+
+
+def test_cleavage_enrichment_is_the_zero_load_damage_state():
+    """Eq. 36-37b: phi_ini from (I + l^2 D^T A D) phi_o = phi_disc and
+    psi_ini from gamma_f' with A make phi_ini the damage solution at zero
+    load, with the same cleavage tensor."""
+    w = W.homogeneous_2d(nx=24, ny=16, ell=1.5, crack=6, phi_M=0.8)
+    w.phases = [dict(w.phases[0], beta=2.0, n=(0.6, 0.8, 0.0))]
+    prob = oracle_problem(w)
+    assert prob.mat.A is not None
+    st = solver.State(prob)
+    tips = prob.phi_disc > 0
+    assert abs(st.phi_ini.max() - 0.8) < 1e-15
+    assert np.max(np.abs(st.psi_ini[~tips])) < 1e-12 * st.psi_ini.max()
+    phi0 = model.solve_damage(st.psi_ini, prob.mat.Gc, prob.ell, prob.Dmats, A=prob.mat.A)
+    assert np.max(np.abs(phi0 - st.phi_ini)) < 1e-12
+    # the isotropic enrichment differs
+    iso = model.cte_initial_damage(prob.phi_disc, prob.ell, prob.h, prob.phi_M)
+    assert np.max(np.abs(iso - st.phi_ini)) > 1e-2
+
+
+# --------------------------------------------------------------------------
 # crack-tip enrichment (Eq. 35, 37a, 38)
 # --------------------------------------------------------------------------
 

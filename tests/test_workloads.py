@@ -89,3 +89,26 @@ def test_composite_3d_small():
     # crack front: the boundary ring of the square notch
     assert w.phi_disc.sum() == 4 * 16 - 4
     assert list(w.f) == [0, 0, 1, 0, 0, 0]
+
+
+def test_weighted_voronoi_is_a_power_diagram():
+    """size_sigma > 0: every voxel belongs to the seed of least power
+    distance |x - s|^2 - r^2 (periodic), and the grain sizes spread more
+    than in the plain tessellation of the same seeds."""
+    n, grains = 48, 12
+    w0 = W.polycrystal_2d(n=n, grains=grains, seed=3)
+    w1 = W.polycrystal_2d(n=n, grains=grains, seed=3, size_sigma=0.4)
+    rng = np.random.default_rng(3)
+    seeds = rng.uniform(0.0, n, size=(grains, 2))
+    rng.uniform(0.0, 2.0 * np.pi, size=grains)
+    r_mean = n / np.sqrt(np.pi * grains)
+    radii = r_mean * np.exp(0.4 * rng.standard_normal(grains) - 0.5 * 0.4 ** 2)
+    for (y, x) in [(0, 0), (5, 17), (23, 40), (47, 47), (30, 2)]:
+        cx, cy = x + 0.5, y + 0.5
+        dx = (cx - seeds[:, 0] + n / 2) % n - n / 2
+        dy = (cy - seeds[:, 1] + n / 2) % n - n / 2
+        assert w1.phase_id[y, x] == int(np.argmin(dx ** 2 + dy ** 2 - radii ** 2))
+    def spread(w):
+        c = np.bincount(w.phase_id.ravel().astype(int), minlength=grains)
+        return np.std(np.log(c[c > 0]))
+    assert spread(w1) > spread(w0)
