@@ -225,7 +225,7 @@ SERVE_SIZES = {
 }
 
 
-def serving(n_requests, seed, rate, sizes="small", max_steps=300):
+def serving(n_requests, seed, rate, sizes="small", max_steps=300, forms="both"):
     """The serving form against the plain form on one seeded request stream
     (2D fibre composites and polycrystals, 3D sphere composites, elastic
     contrast U[1, 10], toughness contrast U[1, 4], Poisson arrivals; sizes
@@ -243,22 +243,34 @@ def serving(n_requests, seed, rate, sizes="small", max_steps=300):
     progress("stream: " + ", ".join("%d:%s" % (i, "x".join(map(str, w.n)))
                                     for i, (a, w) in enumerate(stream)))
     torch.cuda.synchronize()
-    progress("serving %d requests, mixed precision, continuous batching" % n_requests)
-    t0 = time.perf_counter()
-    srv = serve.Server(precision=mirve.RVE_PREC_MIXED, slots_per_pool=16)
-    try:
-        res_s = srv.run(reqs, realtime=True,
-                        on_result=lambda r: progress("  served %d: G_eff %s after %d steps"
-                                                     % (r.rid, r.G_eff, r.steps)))
-    finally:
-        srv.close()
-    wall_s = time.perf_counter() - t0
-    progress("same requests, plain FP64, one at a time")
-    t0 = time.perf_counter()
-    res_p = serve.serve_sequential(reqs, precision=mirve.RVE_PREC_FP64,
-                                   on_result=lambda r: progress("  solved %d: G_eff %s after %d steps"
-                                                                % (r.rid, r.G_eff, r.steps)))
-    wall_p = time.perf_counter() - t0
+    res_s = res_p = None
+    if forms in ("both", "batched"):
+        progress("serving %d requests, mixed precision, continuous batching" % n_requests)
+        t0 = time.perf_counter()
+        srv = serve.Server(precision=mirve.RVE_PREC_MIXED, slots_per_pool=16)
+        try:
+            res_s = srv.run(reqs, realtime=True,
+                            on_result=lambda r: progress("  served %d: G_eff %s after %d steps"
+                                                         % (r.rid, r.G_eff, r.steps)))
+        finally:
+            srv.close()
+        wall_s = time.perf_counter() - t0
+    if forms in ("both", "plain"):
+        progress("same requests, plain FP64, one at a time")
+        t0 = time.perf_counter()
+        res_p = serve.serve_sequential(
+            reqs, precision=mirve.RVE_PREC_FP64,
+            on_result=lambda r: progress("  solved %d: G_eff %s after %d steps" % (r.rid, r.G_eff, r.steps)),
+            on_chunk=lambda rid, n: progress("    request %d: %d steps" % (rid, n)))
+        wall_p = time.perf_counter() - t0
+    if res_s is None or res_p is None:
+        one, wall, name = (res_s, wall_s, "served_mixed_batched") if res_p is None else \
+            (res_p, wall_p, "plain_fp64_one_at_a_time")
+        return {"requests": n_requests, "arrival_rate_per_s": rate, "sizes": sizes,
+                "grids": ["x".join(map(str, r.workload.n)) for r in reqs],
+                name: serve.summarize(one, wall),
+                "per_request": [{"rid": a.rid, "G_eff": a.G_eff, "steps": a.steps, "status": a.status,
+                                 "latency_s": round(a.latency, 2)} for a in one]}
     both = [(a, b) for a, b in zip(res_s, res_p) if a.G_eff is not None and b.G_eff is not None]
     dev = max((abs(a.G_eff - b.G_eff) / abs(b.G_eff) for a, b in both), default=None)
     out = {"requests": n_requests, "arrival_rate_per_s": rate, "sizes": sizes,
@@ -343,6 +355,8 @@ def main():
     ap.add_argument("--serve-seed", type=int, default=5)
     ap.add_argument("--serve-only", action="store_true",
                     help="only the serving comparison (one JSON line with its field)")
+    ap.add_argument("--serve-form", choices=["both", "batched", "plain"], default="both",
+                    help="run one form only (the stream and arrivals are the same)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="set up the batch and time the Green-operator passes only (for counter runs)")
     args = ap.parse_args()
@@ -355,7 +369,7 @@ def main():
     from paper_2508_07424_amd import mirve
     if args.serve_only:
         out = {"serving": serving(max(1, args.serve_requests), seed=args.serve_seed,
-                                  rate=args.serve_rate, sizes=args.serve_sizes)}
+                                  rate=args.serve_rate, sizes=args.serve_sizes, forms=args.serve_form)}
         print(json.dumps(out), flush=True)
         return
     build, size0, batch0, prec0, desc = WORKLOADS[args.workload]

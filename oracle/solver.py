@@ -48,8 +48,8 @@ class Problem:
 
     def __init__(self, n, h, ell, phases, phase_id, f, *, theta=None, void=None,
                  phi_disc=None, phi_M=0.8, k=1e-6, split="none", history=True,
-                 A_g=None, tol=1e-10, tol_cg=1e-12, tol_al=1e-12, max_stagger=100,
-                 max_cg=20000, frac_threshold=0.95, anderson_depth=5, max_halvings=4,
+                 A_g=None, tol=1e-10, tol_cg=1e-12, tol_al=1e-12, max_stagger=300,
+                 max_cg=20000, frac_threshold=0.95, anderson_depth=5, max_halvings=8,
                  stall_window=0):
         self.n = tuple(int(v) for v in n)
         self.d = len(self.n)

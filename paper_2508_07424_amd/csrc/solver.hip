@@ -2488,7 +2488,7 @@ int rve_default_config(rve_config* c) {
     c->tol_pcg = 0.0;
     c->tol_al = 0.0;
     c->max_stagger = 300;
-    c->max_halvings = 4;
+    c->max_halvings = 8;
     c->stall_window = 0;
     c->max_cg = 20000;
     c->max_pcg = 20000;

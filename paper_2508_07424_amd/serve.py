@@ -276,7 +276,7 @@ def summarize(results, wall):
 
 
 def serve_sequential(requests, precision=mirve.RVE_PREC_FP64, split=mirve.RVE_SPLIT_NONE,
-                     tol=None, clock=time.perf_counter, on_result=None):
+                     tol=None, clock=time.perf_counter, on_result=None, chunk=10, on_chunk=None):
     """The plain form: one RVE at a time, first come first served, each in a
     handle of its own (batch 1).  Latency includes the wait behind earlier
     requests; arrivals are honoured (the GPU idles until the next one)."""
@@ -291,11 +291,20 @@ def serve_sequential(requests, precision=mirve.RVE_PREC_FP64, split=mirve.RVE_SP
         start = clock() - t0
         w = req.workload
         r = mirve.from_workload(w, precision=precision, split=split, **dict(tol or {}))
-        infos, status = r.rve_run_slots([w.dtau], [req.max_steps], stop_at_fracture=True)
-        st = status[0]
-        steps = infos[0]["n_steps"]
-        greens = infos[0]["n_greenop"] * int(np.prod(w.n))
-        fractured = bool(infos[0]["fractured"]) and st == 0
+        # chunks of `chunk` steps (the same steps as one call; the caller can
+        # report progress between them)
+        steps = greens = 0
+        st, fractured = 0, False
+        while steps < req.max_steps and st == 0 and not fractured:
+            todo = min(chunk, req.max_steps - steps)
+            infos, status = r.rve_run_slots([w.dtau], [todo], stop_at_fracture=True)
+            st = status[0]
+            steps += infos[0]["n_steps"]
+            greens += infos[0]["n_greenop"] * int(np.prod(w.n))
+            fractured = bool(infos[0]["fractured"])
+            if on_chunk:
+                on_chunk(req.rid, steps)
+        fractured = fractured and st == 0
         G = r.rve_effective_toughness() if fractured else None
         if st == 0 and not fractured:
             st = mirve.RVE_ENOTDONE

@@ -82,7 +82,7 @@ def test_version_and_defaults(lib):
     assert cfg.graphs == 1 and cfg.streaming == -1
     # tolerances 0: the library resolves them per precision at rve_create
     assert cfg.tol == cfg.tol_cg == cfg.tol_pcg == cfg.tol_al == 0.0
-    assert cfg.max_halvings == 4 and cfg.stall_window == 0
+    assert cfg.max_halvings == 8 and cfg.stall_window == 0
     assert so.rve_default_config(None) == lib.RVE_EINVAL
 
 

@@ -700,3 +700,57 @@ def test_broken_in_two_homogeneous():
         print("l", ell, "G(F)", G, "G(F+1), G(F+2)", later, "c Gc", c * Gc)
         assert G < c * Gc < later[1]
         assert abs(G / (c * Gc) - 1.0) < 0.02, (ell, G, c)
+
+
+# --------------------------------------------------------------------------
+# the paper's monolithic Newton-Raphson step (Sec. 4.1, Eq. 22-31)
+# --------------------------------------------------------------------------
+
+def test_newton_jacobian_matches_finite_differences():
+    """J1-J3 of Eq. 25 are the derivative of R1-R3 of Eq. 24: central
+    differences along a compatible random direction at a loaded state of a
+    two-phase RVE with a notch, at a load above the committed one so that
+    the active set of the history is the same at q +- eps dq.  A J2 without
+    the history derivative, or with the wrong sign of g', fails."""
+    from oracle import newton
+    rng = np.random.default_rng(21)
+    n = (12, 10)
+    pid = (rng.random((10, 12)) < 0.4).astype(np.uint16)
+    void, tips = W.notch_2d(n, 1.0, 5, 3, 7)
+    pid[void.astype(bool)] = 0
+    w = W.Workload(n=n, h=1.0, ell=1.5, phases=[W.iso(1, 0.3, 1), W.iso(4, 0.25, 2)],
+                   phase_id=pid, f=W.load_yy(2), dtau=0.12, void=void, phi_disc=tips)
+    prob = oracle_problem(w, tol=1e-11, tol_cg=1e-13, tol_al=1e-13)
+    st = solver.State(prob)
+    solver.step(prob, st, w.dtau)
+    # 10% above the committed load: the loaded voxels are strictly above
+    # their history, off the kink of the max in Eq. 38
+    x, phi, E = 1.1 * st.E * st.x, st.phi, 1.1 * st.E
+    dx = spectral.green_apply(rng.standard_normal((prob.s,) + prob.n), prob.P)
+    dphi = rng.standard_normal(prob.n)
+    dE = 0.3
+    J1, J2, J3 = newton.jacobian_apply(prob, st, x, phi, E, dx, dphi, dE)
+    h = 1e-7
+    Rp = newton.residual(prob, st, x + h * dx, phi + h * dphi, E + h * dE, 1.0)
+    Rm = newton.residual(prob, st, x - h * dx, phi - h * dphi, E - h * dE, 1.0)
+    for J, a, b in zip((J1, J2, J3), Rp, Rm):
+        fd = (np.asarray(a) - np.asarray(b)) / (2 * h)
+        assert np.linalg.norm(np.ravel(fd - J)) < 1e-6 * np.linalg.norm(np.ravel(J))
+
+
+def test_newton_reaches_the_staggered_fixed_point():
+    """Monolithic Newton on (eps~, phi, E) and the staggered fixed point of
+    solver.step solve the same per-step system (R1 = R2 = R3 = 0 with the
+    history of Eq. 38): three steps of a notched plate agree to 1e-10."""
+    from oracle import newton
+    w = W.homogeneous_2d(nx=24, ny=16, crack=6)
+    prob = oracle_problem(w, tol=1e-11, tol_cg=1e-13, tol_al=1e-13)
+    a, b = solver.State(prob), solver.State(prob)
+    for _ in range(3):
+        ra = solver.step(prob, a, w.dtau)
+        rb = newton.step(prob, b, w.dtau, tol=1e-11)
+        for key in ("E", "Sigma", "D", "T"):
+            assert abs(ra[key] - rb[key]) <= 1e-10 * abs(ra[key]), key
+        assert rb["alpha"] == 1.0                # the load still rises: no relaxation
+    assert np.linalg.norm(a.phi - b.phi) <= 1e-10 * np.linalg.norm(a.phi)
+    assert np.linalg.norm(a.H - b.H) <= 1e-10 * np.linalg.norm(a.H)
