@@ -396,6 +396,7 @@ def main():
         return
 
     failed = {}
+    occupancy = {}
 
     def run(nsteps, label):
         t0 = time.perf_counter()
@@ -406,8 +407,10 @@ def main():
                 failed[b] = {"slot": b, "status": s, "reason": mirve.WHY.get(i["reason"], "?"),
                              "phase": label, "steps_done": i["n_steps"]}
         done = sum(i["n_steps"] for i in infos)
-        progress("%s: %d RVE-steps in %.2f s, %d failed slots" % (label, done, time.perf_counter() - t0,
-                                                                  len(failed)))
+        rounds, occ = rve.rve_run_stats()
+        progress("%s: %d RVE-steps in %.2f s, %d failed slots, %d rounds at %.3f mean slot occupancy"
+                 % (label, done, time.perf_counter() - t0, len(failed), rounds, occ))
+        occupancy[label] = {"rounds": rounds, "mean_active_slot_fraction": round(occ, 4)}
         return infos
 
     if args.warmup > 0:
@@ -453,6 +456,7 @@ def main():
                    "rve_steps_per_s": round(rve_steps / sec, 3),
                    "greenops_per_rve_step": round(greenops / max(rve_steps, 1) / rve.N, 1),
                    "failed_slots": sorted(failed.values(), key=lambda d: d["slot"]),
+                   "slot_occupancy": occupancy,
                    "launch_shape": {"x_rows_per_block": shape[0], "y_lines_per_block": shape[1],
                                     "z_columns_per_tile": shape[2],
                                     "krylov_vectors_nontemporal": shape[3]}},

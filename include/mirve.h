@@ -260,6 +260,14 @@ int rve_step_dissipation_slots(rve_handle h, const double* dtau, rve_step_info* 
 int rve_run_slots(rve_handle h, const double* dtau, const int* max_steps, int flags,
                   rve_step_info* info, int* status);
 
+/* Occupancy of the handle's last rve_run_slots call: out2[0] = rounds (each
+ * round is one launch sequence - a mechanics solve, then one stagger
+ * iteration or commit - over the slots that are in that phase of their
+ * step), out2[1] = the mean fraction of the batch's slots those rounds
+ * covered (1 when every slot was busy in every round; lower while slots
+ * that finished wait for others). */
+int rve_run_stats(rve_handle h, double* out2);
+
 /* Number of slots of the handle. */
 int rve_batch_size(rve_handle h);
 

@@ -279,6 +279,10 @@ struct SolverBase {
     virtual int load_state(int slot, const void* host, size_t bytes) = 0;
     std::vector<SlotState> slots;
     int B = 1;
+    // occupancy of the last rve_run_slots call: rounds (each a mechanics
+    // solve, a stagger iteration or commit, one launch sequence over the
+    // slots in that phase) and the slots those rounds covered in total
+    long long run_rounds = 0, run_active = 0;
 };
 
 struct rve_handle_s {
@@ -352,8 +356,10 @@ struct Solver : SolverBase {
     static constexpr int kFloorWindow = 20;
     static constexpr int kMaxNewton = 100;
     std::vector<int> slope_warm;     // tmp holds a usable tangent of this slot
-    static constexpr double kSlopeTol = 1e-8;
-    static constexpr double kSlopeTolBulk32 = 1e-7;   // what an FP32 PCG reaches
+    // the tangent only steers Newton on E (the constraint is tested on D
+    // itself): a relative error of 1e-6 in dD/dE costs nothing in the root
+    static constexpr double kSlopeTol = 1e-6;
+    static constexpr double kSlopeTolBulk32 = 1e-5;
 
     // ------------------------------------------------------------------ layout
     static long long pass_blocks_max(const Geom& g, int nbx) {
@@ -1672,10 +1678,13 @@ struct Solver : SolverBase {
             begin_step(q);
             begin_attempt(b, q, fresh);
         }
+        run_rounds = run_active = 0;
         for (;;) {
             std::vector<int> M(B, 0);
             for (int b = 0; b < B; ++b) M[b] = P[b].stage != 0;
             if (!any(M)) break;
+            run_rounds += 1;
+            for (int b = 0; b < B; ++b) run_active += M[b];
             if (any(fresh)) {
                 CHK(set_mask(0, fresh));
                 HIPCHK(launch_copy<T>(phi_c, phi_w, g.N, B, dmask[0], st));
@@ -2584,6 +2593,14 @@ int rve_run_slots(rve_handle h, const double* dtau, const int* max_steps, int fl
     if (!h || !dtau || !max_steps) return RVE_EINVAL;
     if (flags & ~RVE_RUN_STOP_AT_FRACTURE) { h->err = "unknown flags"; return RVE_EINVAL; }
     return h->impl->run(dtau, max_steps, flags, info, status);
+}
+
+int rve_run_stats(rve_handle h, double* out2) {
+    if (!h || !out2) return RVE_EINVAL;
+    const SolverBase& s = *h->impl;
+    out2[0] = double(s.run_rounds);
+    out2[1] = s.run_rounds > 0 ? double(s.run_active) / (double(s.run_rounds) * s.B) : 0.0;
+    return RVE_OK;
 }
 
 int rve_step_dissipation_slots(rve_handle h, const double* dtau, rve_step_info* info, int* status) {

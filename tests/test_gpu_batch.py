@@ -143,3 +143,21 @@ def test_run_slots_each_at_its_own_pace():
             assert b[key] == v, (i, key, b[key], v)
         assert np.array_equal(batch.rve_get_field("phi", slot=i), r.rve_get_field("phi"))
         assert np.array_equal(batch.rve_get_field("hist", slot=i), r.rve_get_field("hist"))
+
+
+def test_run_stats_report_slot_occupancy():
+    """rve_run_stats: the rounds of the last rve_run_slots call and the mean
+    fraction of the batch they covered.  With one of three slots idle every
+    round covers at most two thirds of the batch; a slot that finishes its
+    steps early lowers it further."""
+    from paper_2508_07424_amd import mirve as m
+    ws = [W.composite_2d_small(seed=s) for s in (1, 2, 3)]
+    r = m.from_workloads(ws)
+    infos, st = r.rve_run_slots([ws[0].dtau, ws[1].dtau, 0.0], [2, 1, 0])
+    assert st == [0, 0, 0]
+    rounds, occ = r.rve_run_stats()
+    print("rounds", rounds, "occupancy", occ, flush=True)
+    assert rounds > 0 and 0.0 < occ < 2.0 / 3.0
+    infos, st = r.rve_run_slots([w.dtau for w in ws], [1, 1, 1])
+    rounds1, occ1 = r.rve_run_stats()
+    assert rounds1 > 0 and occ < occ1 <= 1.0

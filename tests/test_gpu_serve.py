@@ -37,6 +37,27 @@ def test_alone_equals_in_the_mix_fp64():
         assert abs(a.G_eff - m.G_eff) <= 1e-9 * abs(a.G_eff)
 
 
+def test_alone_equals_in_the_mix_mixed_precision():
+    """The same in the precision form: each request's G_eff served as a slot
+    of a shared mixed-precision pool equals its G_eff alone in a mixed
+    handle of its own within the toughness bar of 1e-3 (the launch shape of
+    a pool may differ from a single slot's, which changes the summation
+    order of the partial sums)."""
+    from paper_2508_07424_amd import mirve
+    from paper_2508_07424_amd.serve import Server, serve_sequential
+    reqs = _requests()
+    alone = serve_sequential(reqs, precision=mirve.RVE_PREC_MIXED)
+    srv = Server(precision=mirve.RVE_PREC_MIXED, slots_per_pool=2)
+    try:
+        mixed = srv.run(reqs, realtime=False)
+    finally:
+        srv.close()
+    for a, m in zip(alone, mixed):
+        print(a.rid, reqs[a.rid].workload.n, a.steps, m.steps, a.G_eff, m.G_eff, flush=True)
+        assert a.status == 0 and m.status == 0
+        assert abs(a.G_eff - m.G_eff) <= 1e-3 * abs(a.G_eff)
+
+
 def test_admission_respects_the_budget():
     from paper_2508_07424_amd import mirve
     from paper_2508_07424_amd.serve import Server
