@@ -8,11 +8,17 @@ dependent cleavage toughness, l = 2, a notch of 0.1 L_x), FP32 bulk with
 FP64 reductions and constraint, in one batched handle.  A step is one
 dissipation-controlled step (Eq. 16 of the paper: mechanics CG with the
 fused Green operator, damage PCG, arc-length constraint, commit and
-fracture test) of every RVE of the batch; each RVE goes at its own pace
-within the call.  W warm-up steps, then K timed steps, inputs resident in
-HBM.
+fracture test) of every RVE of the batch.  W warm-up steps, then K timed
+steps, inputs resident in HBM: the batch of B RVEs commits W x B, then
+K x B RVE-steps in one call each, every RVE at its own pace (a fast RVE
+takes more steps than a slow one, so the launches keep covering the whole
+batch).  An RVE caught in the middle of a step when the total is reached
+returns to the start of that step, and the work of that step is not
+counted.  With --schedule fixed every RVE takes exactly W, then K steps,
+and a call ends with its slowest RVE.
 
-value = sum over RVEs of (voxels x Green-operator applications) / seconds.
+value = sum over RVEs of (voxels x Green-operator applications of their
+committed steps) / seconds.
 
 The JSON line also carries the roofline of the dominant kernel (HIP events
 on its stream) on the algorithmic bytes of a Green-operator application,
@@ -357,6 +363,9 @@ def main():
                     help="only the serving comparison (one JSON line with its field)")
     ap.add_argument("--serve-form", choices=["both", "batched", "plain"], default="both",
                     help="run one form only (the stream and arrivals are the same)")
+    ap.add_argument("--schedule", choices=["budget", "fixed"], default="budget",
+                    help="budget: the batch commits steps x B RVE-steps, each RVE at its own pace; "
+                         "fixed: every RVE takes exactly the steps (a call ends with its slowest RVE)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="set up the batch and time the Green-operator passes only (for counter runs)")
     args = ap.parse_args()
@@ -400,8 +409,11 @@ def main():
 
     def run(nsteps, label):
         t0 = time.perf_counter()
-        infos, st = rve.rve_run_slots([d if b not in failed else 0.0 for b, d in enumerate(dtaus)],
-                                      [nsteps] * len(dtaus))
+        live = [d if b not in failed else 0.0 for b, d in enumerate(dtaus)]
+        if args.schedule == "budget":
+            infos, st = rve.rve_run_budget(live, nsteps * sum(1 for d in live if d > 0.0))
+        else:
+            infos, st = rve.rve_run_slots(live, [nsteps] * len(live))
         for b, (i, s) in enumerate(zip(infos, st)):
             if s != 0 and b not in failed:
                 failed[b] = {"slot": b, "status": s, "reason": mirve.WHY.get(i["reason"], "?"),
@@ -410,14 +422,18 @@ def main():
         rounds, occ = rve.rve_run_stats()
         progress("%s: %d RVE-steps in %.2f s, %d failed slots, %d rounds at %.3f mean slot occupancy"
                  % (label, done, time.perf_counter() - t0, len(failed), rounds, occ))
-        occupancy[label] = {"rounds": rounds, "mean_active_slot_fraction": round(occ, 4)}
+        per = [i["n_steps"] for i in infos]
+        occupancy[label] = {"rounds": rounds, "mean_active_slot_fraction": round(occ, 4),
+                            "rve_steps": done, "steps_per_rve_min": min(per),
+                            "steps_per_rve_max": max(per)}
         return infos
 
+    per = " on average" if args.schedule == "budget" else ""
     if args.warmup > 0:
-        run(args.warmup, "warm-up (%d steps per RVE)" % args.warmup)
+        run(args.warmup, "warm-up (%d steps per RVE%s)" % (args.warmup, per))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = run(args.steps, "timed (%d steps per RVE)" % args.steps)
+    infos = run(args.steps, "timed (%d steps per RVE%s)" % (args.steps, per))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     sec = t1 - t0
@@ -451,7 +467,7 @@ def main():
         "dtype": "f64" if prec == mirve.RVE_PREC_FP64 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": desc.format(n=args.size, r=(args.batch + 8) // 9, b=args.batch),
-                   "batch": args.batch, "precision": args.precision,
+                   "batch": args.batch, "precision": args.precision, "schedule": args.schedule,
                    "rve_steps": rve_steps,
                    "rve_steps_per_s": round(rve_steps / sec, 3),
                    "greenops_per_rve_step": round(greenops / max(rve_steps, 1) / rve.N, 1),

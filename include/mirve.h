@@ -260,7 +260,21 @@ int rve_step_dissipation_slots(rve_handle h, const double* dtau, rve_step_info* 
 int rve_run_slots(rve_handle h, const double* dtau, const int* max_steps, int flags,
                   rve_step_info* info, int* status);
 
-/* Occupancy of the handle's last rve_run_slots call: out2[0] = rounds (each
+/* The batched form under a step budget (Eq. 16 per slot): every slot b with
+ * dtau[b] > 0 takes steps of dtau[b] at its own pace until the slots
+ * together have committed total_steps steps; the call then ends at the end
+ * of that round, and a slot in the middle of a step returns to the state the
+ * step began from (its step does not happen).  Slots that finish early keep
+ * the batch busy instead of waiting for the slowest one.  A slot stops at a
+ * failed step as in rve_run_slots, and with RVE_RUN_STOP_AT_FRACTURE at its
+ * fracture point.  info (n_steps per slot) and status as in rve_run_slots;
+ * its work counters cover the committed steps only (not the abandoned one).
+ * rve_run_stats reports the call's occupancy.  Returns RVE_EINVAL for
+ * total_steps < 0 or unknown flags. */
+int rve_run_budget(rve_handle h, const double* dtau, long long total_steps, int flags,
+                   rve_step_info* info, int* status);
+
+/* Occupancy of the handle's last rve_run_slots or rve_run_budget call: out2[0] = rounds (each
  * round is one launch sequence - a mechanics solve, then one stagger
  * iteration or commit - over the slots that are in that phase of their
  * step), out2[1] = the mean fraction of the batch's slots those rounds

@@ -30,6 +30,8 @@
 #include <tuple>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/mirve.h"
 #include "kernels.h"
 #include "fft2l.h"
@@ -249,6 +251,16 @@ struct Layout {
 using namespace mirve;
 
 // Committed host-side state of one RVE slot.
+// A roctx range over a host scope: the stages of a step show up as ranges in
+// a marker trace (rocprofv3 --marker-trace); without a tracer the calls do
+// nothing.
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
+
 struct SlotState {
     bool ready = false;
     bool fractured = false;
@@ -262,7 +274,8 @@ struct SolverBase {
     virtual ~SolverBase() {}
     virtual int set_microstructure(int slot, const uint16_t*, const rve_phase*, int, const double*,
                                    const uint8_t*, const uint8_t*, double) = 0;
-    virtual int run(const double* dtau, const int* todo, int flags, rve_step_info* info, int* status) = 0;
+    virtual int run(const double* dtau, const int* todo, int flags, rve_step_info* info, int* status,
+                    long long budget = -1) = 0;
     virtual int get_field(int slot, int which, double* host, size_t count) = 0;
     virtual int set_field(int slot, int which, const double* host, size_t count) = 0;
     virtual int apply_green(int slot, const double* eps, double* out) = 0;
@@ -1409,6 +1422,7 @@ struct Solver : SolverBase {
     int set_microstructure(int slot, const uint16_t* pid, const rve_phase* phases, int nph,
                            const double* theta, const uint8_t* vmask, const uint8_t* disc,
                            double phi_M) override {
+        Range rg("mirve: microstructure + enrichment (Eq. 35-38)");
         if (slot < 0 || slot >= B) return fail(RVE_EINVAL, "slot out of range");
         if (!pid || !phases || nph <= 0) return fail(RVE_EINVAL, "phase_id and phases required");
         if (!(phi_M > 0.0 && phi_M < 1.0)) return fail(RVE_EINVAL, "phi_M must be in (0, 1)");
@@ -1578,17 +1592,31 @@ struct Solver : SolverBase {
         int s_warm = 0;
         bool stop_frac = false;
         int n_steps = 0, n_sub = 0, n_stag = 0, n_cg = 0, n_pcg = 0, n_green = 0;
+        int sub_step = 0;              // sub-steps of the current step committed so far
         int status = RVE_OK, reason = RVE_WHY_NONE;
         bool has_last = false;
-        rve_step_info last;
+        rve_step_info last{};
+        bool pre_has_last = false;     // last / has_last as the current step began
+        rve_step_info pre_last{};
+        int pre_sub = 0, pre_stag = 0, pre_cg = 0, pre_pcg = 0, pre_green = 0;   // counters then
+        bool recount = false;          // take pre_* again once the round's work is counted
     };
 
     void begin_step(Progress& q) {
         q.pend.clear();
         q.pend.push_back({q.dtau, 0});
         q.sub_done = false;
+        q.sub_step = 0;
+        q.pre_has_last = q.has_last;
+        q.pre_last = q.last;
+        mark_counters(q);
         q.snap = false;
         q.s_phi.clear(); q.s_H.clear(); q.s_x.clear(); q.s_tan.clear();
+    }
+    static void mark_counters(Progress& q) {
+        q.pre_sub = q.n_sub; q.pre_stag = q.n_stag; q.pre_cg = q.n_cg;
+        q.pre_pcg = q.n_pcg; q.pre_green = q.n_green;
+        q.recount = false;
     }
     void begin_attempt(int b, Progress& q, std::vector<int>& fresh) {
         q.tau = slots[b].tau + q.pend.front().first;
@@ -1624,6 +1652,30 @@ struct Solver : SolverBase {
         return RVE_OK;
     }
 
+    // Slot b stops in the middle of a step (a step budget was reached): the
+    // step does not happen; sub-steps of it that had committed are undone,
+    // and the work counters drop the step's work.
+    int abandon_step(int b, Progress& q) {
+        if (q.stage == 0) return RVE_OK;
+        q.n_sub = q.pre_sub; q.n_stag = q.pre_stag; q.n_cg = q.pre_cg;
+        q.n_pcg = q.pre_pcg; q.n_green = q.pre_green;
+        if (q.sub_done) {
+            if (!q.snap) return fail(RVE_EDEVICE, "no snapshot of the step's start");
+            CHK(load_fields(b, q.s_phi.data(), q.s_H.data(), q.s_x.data(), q.s_tan.data()));
+            slots[b] = q.s_state;
+            slope_warm[b] = q.s_warm;
+            q.has_last = q.pre_has_last;
+            q.last = q.pre_last;
+        } else {
+            // the working fields are copies; only the strain warm start moved
+            const long long so = (long long)b * g.s * g.N;
+            HIPCHK(hipMemcpyAsync(x + so, x_c + so, sizeof(T) * g.s * g.N, hipMemcpyDeviceToDevice, st));
+        }
+        q.stage = 0;
+        q.todo = 0;
+        return RVE_OK;
+    }
+
     // A failed attempt of slot b (its working strain is already reset).
     int on_failure(int b, Progress& q, int code, int why, std::vector<int>& fresh) {
         const auto cur = q.pend.front();
@@ -1647,6 +1699,9 @@ struct Solver : SolverBase {
             CHK(load_fields(b, q.s_phi.data(), q.s_H.data(), q.s_x.data(), q.s_tan.data()));
             slots[b] = q.s_state;
             slope_warm[b] = q.s_warm;
+            q.has_last = q.pre_has_last;
+            q.last = q.pre_last;
+            q.n_sub -= q.sub_step;
         }
         q.status = code;
         q.reason = why;
@@ -1659,7 +1714,12 @@ struct Solver : SolverBase {
     // (Eq. 16), at their own pace: a slot that commits a step starts its next
     // one in the following round, while other slots are still iterating.
     // Every launch of a round covers the slots that are in that phase.
-    int run(const double* dtau, const int* todo, int flags, rve_step_info* info, int* status) override {
+    // budget >= 0: the call ends once the slots together have committed that
+    // many steps (at the end of the round in which it is reached); a slot
+    // then in the middle of a step returns to the state the step began from.
+    int run(const double* dtau, const int* todo, int flags, rve_step_info* info, int* status,
+            long long budget = -1) override {
+        Range rg("mirve: rve_run_slots");
         std::vector<Progress> P(B);
         std::vector<int> fresh(B, 0);
         for (int b = 0; b < B; ++b) {
@@ -1680,6 +1740,14 @@ struct Solver : SolverBase {
         }
         run_rounds = run_active = 0;
         for (;;) {
+            if (budget >= 0) {
+                long long done = 0;
+                for (int b = 0; b < B; ++b) done += P[b].n_steps;
+                if (done >= budget) {
+                    for (int b = 0; b < B; ++b) CHK(abandon_step(b, P[b]));
+                    break;
+                }
+            }
             std::vector<int> M(B, 0);
             for (int b = 0; b < B; ++b) M[b] = P[b].stage != 0;
             if (!any(M)) break;
@@ -1696,7 +1764,10 @@ struct Solver : SolverBase {
             step_greens.assign(B, 0);
             // (M) equilibrium at the working damage of every slot of the round
             CHK(set_mask(1, M));
-            CHK(mech_solve(phi_w, 1, M, ncg, rc));
+            {
+                Range rg("mirve: equilibrium (Eq. 16a)");
+                CHK(mech_solve(phi_w, 1, M, ncg, rc));
+            }
             std::vector<int> ok(B, 0), C(B, 0), S(B, 0);
             for (int b = 0; b < B; ++b) ok[b] = M[b] && rc[b] == RVE_OK;
             std::vector<double> S1(B, 0.0), s2(B, 0.0);
@@ -1712,13 +1783,21 @@ struct Solver : SolverBase {
             }
             // (A), (U) one stagger iteration of the slots still iterating; the
             // slots committing below start their next attempt in the next round
-            if (any(S)) CHK(stagger_iteration(S, P, rc, npcg));
-            if (any(C)) CHK(commit(C, S1, s2, P, fresh));
+            if (any(S)) {
+                Range rg("mirve: constraint + damage (Eq. 16b, 16c)");
+                CHK(stagger_iteration(S, P, rc, npcg));
+            }
+            if (any(C)) {
+                Range rg("mirve: commit (Eq. 33, 38)");
+                CHK(commit(C, S1, s2, P, fresh));
+            }
             for (int b = 0; b < B; ++b) {
                 if (!M[b]) continue;
                 P[b].n_cg += ncg[b];
                 P[b].n_pcg += npcg[b];
                 P[b].n_green += step_greens[b];
+                // a step begun by this round's commit starts from these counts
+                if (P[b].recount) mark_counters(P[b]);
             }
             std::vector<int> failed(B, 0);
             for (int b = 0; b < B; ++b) failed[b] = M[b] && rc[b] != RVE_OK;
@@ -1914,6 +1993,7 @@ struct Solver : SolverBase {
             Ss.Gamma = G[b];
             q.has_last = true;
             q.n_sub += 1;
+            q.sub_step += 1;
             q.sub_done = true;
             q.pend.pop_front();
             if (!q.pend.empty()) {     // the next sub-step of this step
@@ -1926,6 +2006,7 @@ struct Solver : SolverBase {
             q.s_phi.clear(); q.s_H.clear(); q.s_x.clear(); q.s_tan.clear();
             if (q.todo > 0 && !(q.stop_frac && Ss.fractured)) {
                 begin_step(q);
+                q.recount = true;      // the round's counts are added after this
                 begin_attempt(b, q, fresh);
             } else {
                 q.stage = 0;
@@ -2601,6 +2682,16 @@ int rve_run_stats(rve_handle h, double* out2) {
     out2[0] = double(s.run_rounds);
     out2[1] = s.run_rounds > 0 ? double(s.run_active) / (double(s.run_rounds) * s.B) : 0.0;
     return RVE_OK;
+}
+
+int rve_run_budget(rve_handle h, const double* dtau, long long total_steps, int flags,
+                   rve_step_info* info, int* status) {
+    if (!h || !dtau) return RVE_EINVAL;
+    if (flags & ~RVE_RUN_STOP_AT_FRACTURE) { h->err = "unknown flags"; return RVE_EINVAL; }
+    if (total_steps < 0) { h->err = "total_steps must be >= 0"; return RVE_EINVAL; }
+    const int B = h->impl->B;
+    std::vector<int> todo(B, 1 << 30);
+    return h->impl->run(dtau, todo.data(), flags, info, status, total_steps);
 }
 
 int rve_step_dissipation_slots(rve_handle h, const double* dtau, rve_step_info* info, int* status) {

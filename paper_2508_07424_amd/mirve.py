@@ -49,7 +49,7 @@ EXPORTS = ["rve_default_config", "rve_query_workspace", "rve_create", "rve_destr
            "rve_apply_green_op", "rve_apply_green_op_device", "rve_solve_mechanics",
            "rve_solve_damage", "rve_dissipation", "rve_profile_pass", "rve_autotune",
            "rve_last_error", "rve_version", "rve_run_slots", "rve_state_bytes", "rve_save_state",
-           "rve_load_state", "rve_apply_green_op_device_noalloc", "rve_run_stats"]
+           "rve_load_state", "rve_apply_green_op_device_noalloc", "rve_run_stats", "rve_run_budget"]
 
 
 class rve_config(C.Structure):
@@ -107,6 +107,7 @@ def _load():
         "rve_load_state": (I, [P, I, P, S]),
         "rve_batch_size": (I, [P]),
         "rve_run_stats": (I, [P, dp]),
+        "rve_run_budget": (I, [P, dp, C.c_longlong, I, C.POINTER(rve_step_info), C.POINTER(C.c_int)]),
         "rve_release_slot": (I, [P, I]),
         "rve_effective_toughness_slot": (I, [P, I, dp]),
         "rve_get_field_slot": (I, [P, I, I, dp, S]),
@@ -278,9 +279,20 @@ class Rve:
                           RVE_RUN_STOP_AT_FRACTURE if stop_at_fracture else 0, infos, status)
         return [infos[i].as_dict() for i in range(self.B)], [status[i] for i in range(self.B)]
 
+    def rve_run_budget(self, dtaus, total_steps, stop_at_fracture=False):
+        """Steps at each slot's own pace until the slots together committed
+        total_steps.  Returns (infos, status)."""
+        dt = np.ascontiguousarray(dtaus, dtype=np.float64)
+        assert dt.size == self.B
+        infos = (rve_step_info * self.B)()
+        status = (C.c_int * self.B)()
+        lib.rve_run_budget(self.h, _dptr(dt), int(total_steps),
+                           RVE_RUN_STOP_AT_FRACTURE if stop_at_fracture else 0, infos, status)
+        return [infos[i].as_dict() for i in range(self.B)], [status[i] for i in range(self.B)]
+
     def rve_run_stats(self):
         """(rounds, mean fraction of the slots each round covered) of the last
-        rve_run_slots call."""
+        rve_run_slots or rve_run_budget call."""
         out = np.zeros(2)
         self._chk(lib.rve_run_stats(self.h, _dptr(out)))
         return int(out[0]), float(out[1])

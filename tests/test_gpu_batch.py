@@ -161,3 +161,59 @@ def test_run_stats_report_slot_occupancy():
     infos, st = r.rve_run_slots([w.dtau for w in ws], [1, 1, 1])
     rounds1, occ1 = r.rve_run_stats()
     assert rounds1 > 0 and occ < occ1 <= 1.0
+
+
+@pytest.mark.parametrize("case", ["plain", "halving"])
+def test_run_budget_ends_on_committed_states(case):
+    """rve_run_budget: slots step at their own pace until the batch has
+    committed the budget; every round covers the whole batch, and each slot
+    ends bitwise where the same RVE stepped alone for the slot's committed
+    steps ends (a slot caught in the middle of a step, also after sub-steps
+    of it had committed, returns to the step's start and drops its work).
+    The slots then go on from there as the lone RVEs do.  "halving" takes
+    doubled steps under a small stagger limit so that steps split."""
+    from paper_2508_07424_amd import mirve
+    ws = _three()
+    kw = {}
+    for w in ws:
+        w.f = W.load_yy(2)
+        if case == "halving":
+            w.dtau = 2.0 * w.dtau
+    if case == "halving":
+        kw = dict(max_stagger=6)
+    batch = mirve.from_workloads(ws, **kw)
+    alone = [mirve.from_workload(w, max_materials=4096, **kw) for w in ws]
+    dt = [w.dtau for w in ws]
+    split = 0
+    for call, budget in enumerate((4, 1, 2)):
+        infos, st = batch.rve_run_budget(dt, budget)
+        assert st == [0, 0, 0], st
+        done = [i["n_steps"] for i in infos]
+        rounds, occ = batch.rve_run_stats()
+        print("call", call, "budget", budget, "steps", done, "substeps",
+              [i["n_substeps"] for i in infos], "rounds", rounds, "occupancy", occ, flush=True)
+        assert budget <= sum(done) < budget + len(ws)
+        assert rounds > 0 and occ == 1.0
+        for i, r in enumerate(alone):
+            tot = {"n_cg": 0, "n_pcg": 0, "n_stagger": 0, "n_greenop": 0, "n_substeps": 0}
+            one = None
+            for _ in range(done[i]):
+                one = r.rve_step_dissipation(dt[i])
+                for key in tot:
+                    tot[key] += one[key]
+            split += tot["n_substeps"] - done[i]
+            b = infos[i]
+            for key, v in tot.items():
+                assert b[key] == v, (call, i, key, b[key], v)
+            sb, sa = batch.rve_get_scalars(slot=i), r.rve_get_scalars()
+            for key in ("E", "Sigma", "T", "tau", "step"):
+                assert sb[key] == sa[key], (call, i, key, sb[key], sa[key])
+            if one is not None:
+                for key in ("E", "Sigma", "D", "T", "Gamma"):
+                    assert b[key] == one[key], (call, i, key)
+            assert np.array_equal(batch.rve_get_field("phi", slot=i), r.rve_get_field("phi"))
+            assert np.array_equal(batch.rve_get_field("hist", slot=i), r.rve_get_field("hist"))
+    if case == "halving":
+        assert split > 0, "no step split: the case does not reach the sub-step path"
+    with pytest.raises(RuntimeError):
+        batch._chk(mirve.lib.rve_run_budget(batch.h, mirve._dptr(np.array(dt)), -1, 0, None, None))
