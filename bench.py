@@ -197,10 +197,14 @@ def copy_bandwidth(torch, mib=1024, repeat=10):
     return round(2 * n * 8 / (ms * 1e-3) / 1e9, 1)
 
 
+# the files the Green-operator passes are compiled from
+GREENOP_SOURCES = ("common.h", "fft2l.h", "fft_device.h", "greenop.hip", "kernels.h", "reduce.h")
+
+
 def stored_traffic(kernel_file):
     """HBM bytes per launch of the dominant kernel from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if it was taken on the current
-    kernel sources (else None)."""
+    sources of that kernel (else None)."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", kernel_file)
@@ -213,10 +217,10 @@ def stored_traffic(kernel_file):
                 k, v = line.split(":", 1)
                 vals[k.strip()] = v.strip()
     h = hashlib.sha256()
-    for name in sorted(os.listdir(os.path.join(here, "paper_2508_07424_amd", "csrc"))):
+    for name in GREENOP_SOURCES:
         with open(os.path.join(here, "paper_2508_07424_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
-    if vals.get("csrc_sha256") != h.hexdigest():
+    if vals.get("kernel_sources_sha256") != h.hexdigest():
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])

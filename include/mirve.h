@@ -192,7 +192,9 @@ typedef struct {
     int    fractured;      /* 1 once every line along the load axis is broken        */
     int    step;           /* index of the committed step (1, 2, ...)                */
     int    n_steps;        /* steps committed by the call                            */
-    int    n_substeps;     /* committed sub-steps (a step split by halving has > 1)  */
+    int    n_substeps;     /* committed sub-steps (a step split by halving has > 1;
+                              those of a step that then failed count, though the
+                              failure rolled them back)                            */
     int    reason;         /* RVE_WHY_* of a failed step, else RVE_WHY_NONE          */
     double G_inst;         /* instantaneous energy release rate of the step (Sec. 4.2,
                               Eq. 34): V [(T - 1/2 Sigma E)^n - (T - 1/2 Sigma E)^(n-1)]

@@ -1592,7 +1592,6 @@ struct Solver : SolverBase {
         int s_warm = 0;
         bool stop_frac = false;
         int n_steps = 0, n_sub = 0, n_stag = 0, n_cg = 0, n_pcg = 0, n_green = 0;
-        int sub_step = 0;              // sub-steps of the current step committed so far
         int status = RVE_OK, reason = RVE_WHY_NONE;
         bool has_last = false;
         rve_step_info last{};
@@ -1606,7 +1605,6 @@ struct Solver : SolverBase {
         q.pend.clear();
         q.pend.push_back({q.dtau, 0});
         q.sub_done = false;
-        q.sub_step = 0;
         q.pre_has_last = q.has_last;
         q.pre_last = q.last;
         mark_counters(q);
@@ -1701,7 +1699,6 @@ struct Solver : SolverBase {
             slope_warm[b] = q.s_warm;
             q.has_last = q.pre_has_last;
             q.last = q.pre_last;
-            q.n_sub -= q.sub_step;
         }
         q.status = code;
         q.reason = why;
@@ -1993,7 +1990,6 @@ struct Solver : SolverBase {
             Ss.Gamma = G[b];
             q.has_last = true;
             q.n_sub += 1;
-            q.sub_step += 1;
             q.sub_done = true;
             q.pend.pop_front();
             if (!q.pend.empty()) {     // the next sub-step of this step
