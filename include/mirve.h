@@ -74,6 +74,8 @@ extern "C" {
 #define RVE_WHY_SPLIT     5  /* the split law's Newton loop reached its limit       */
 #define RVE_WHY_BREAKDOWN 6  /* Krylov breakdown or a non-finite reduction          */
 #define RVE_WHY_ANDERSON  7  /* singular or non-finite Anderson system              */
+#define RVE_WHY_GMRES     8  /* Newton step: GMRES reached max_cycles restarts      */
+#define RVE_WHY_NEWTON    9  /* Newton step: max_newton iterations without Eq. 30   */
 
 /* flags of rve_run_slots */
 #define RVE_RUN_STOP_AT_FRACTURE 1  /* a slot stops after the step that reaches its
@@ -360,6 +362,45 @@ int rve_apply_green_op_device(rve_handle h, const void* eps_dev, void* out_dev, 
  *   RVE_EDEVICE if the array's address could not be obtained when the
  *   handle was created. */
 int rve_apply_green_op_device_noalloc(rve_handle h, const void* eps_dev, void* out_dev, int repeat);
+
+/* ---- the paper's monolithic per-step solver (Sec. 4.1, Eq. 22-31) ----
+ * One dissipation-controlled step of slot `slot` by Newton-Raphson on
+ * q = (x, phi, E): the residual R = (R1, R2, R3) of Eq. 24 (equilibrium
+ * Gamma[g C (x + E f)], the damage balance with H = max(psi0 + psi_ini,
+ * H^n) of Eq. 38, and D(phi) - tau^(n+1)), the Jacobian J1-J3 of Eq. 25
+ * applied matrix-free (J1 through the Green operator, J2 through the damage
+ * stencil, J3 as a reduction), each Newton system J dq = -R solved by
+ * restarted GMRES, the relaxation of Eq. 31 and the convergence test of
+ * Eq. 30.  It reaches the fixed point of the staggered step (rve_step_*),
+ * which it can replace step for step on the same handle; the commit (Eq. 33,
+ * 38, fracture test, Eq. 34) is the same.
+ * FP64 handles without a split law only (RVE_EINVAL otherwise).
+ * Readings: the relaxation factor of Eq. 31 is
+ * alpha = max(theta, Sigma^n / max_(j<n) Sigma^j), 1 for the first two
+ * steps; dH/deps = sigma0 where psi0 + psi_ini >= H^n and psi0 > 0 (not on
+ * notch voxels); from the unloaded state (E = 0, where J is singular) Newton
+ * starts from the elastic unit-load solution scaled to
+ * E = sqrt(min G_c / (l max psi_o1)).  The paper names BiCGSTAB for the
+ * Newton systems; GMRES is used (BiCGSTAB diverged on them).
+ * workspace: caller-owned device memory of at least rve_newton_workspace
+ * bytes for opts->restart, not shared with a call in flight; opts may be
+ * NULL (defaults).  A failed step (RVE_ENOCONV, RVE_ENUMERIC) leaves the
+ * committed state unchanged and sets info->reason.  In info, n_stagger is
+ * the Newton iteration count, n_cg the GMRES iterations (all systems),
+ * n_greenop the Green-operator applications. */
+typedef struct rve_newton_opts {
+    double tol;          /* Eq. 30 tolerance; <= 0: the handle's tol               */
+    double krylov_tol;   /* relative residual of each GMRES solve (1e-12)           */
+    double theta;        /* lower bound of the relaxation factor (0.3)              */
+    int    restart;      /* GMRES restart length, 1..1000 (200)                     */
+    int    max_cycles;   /* GMRES restart cycles per Newton system (100)            */
+    int    max_newton;   /* Newton iterations (50)                                  */
+    int    relax;        /* 1: relaxation of Eq. 31; 0: full Newton steps (1)       */
+} rve_newton_opts;
+void rve_newton_default_opts(rve_newton_opts* opts);
+int rve_newton_workspace(rve_handle h, int restart, size_t* bytes);
+int rve_step_newton(rve_handle h, int slot, double dtau, const rve_newton_opts* opts,
+                    void* workspace, size_t workspace_bytes, rve_step_info* info);
 
 /* Equilibrium for the unit load at the committed phi (Eq. 16a): updates
  * EPS1/SIG1/PSI1 and returns the CG iteration count and Sigma_1. */

@@ -21,6 +21,7 @@ LIB = os.path.join(HERE, "libmirve.so")
 SOURCES = [("greenop.hip", "greenop_f64.o", ["-DMIRVE_REAL=double"]),
            ("greenop.hip", "greenop_f32.o", ["-DMIRVE_REAL=float"]),
            ("pointwise.hip", "pointwise.o", []),
+           ("newton.hip", "newton.o", []),
            ("solver.hip", "solver.o", [])]
 ARCH = "gfx950"
 

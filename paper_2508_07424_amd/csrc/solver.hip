@@ -28,12 +28,14 @@
 #include <string>
 #include <thread>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "../../include/mirve.h"
 #include "kernels.h"
+#include "newton.h"
 #include "fft2l.h"
 
 namespace mirve {
@@ -267,6 +269,7 @@ struct SlotState {
     double E = 0, Sigma = 0, T = 0, tau = 0, tau0 = 0;
     double Gamma = 0;               // crack surface Gamma of the committed damage (Eq. 4)
     double V = 0, A_g = 0, min_gc = 0;
+    double sig_max_prev = 0;        // max of Sigma over the committed steps before the last
     int step = 0;
 };
 
@@ -286,6 +289,9 @@ struct SolverBase {
     virtual int solve_damage(int slot, double E, double* D, int* it, int commit) = 0;
     virtual int dissipation(int slot, double* D, double* G) = 0;
     virtual int profile_pass(int pass, int repeat, double* bytes_per_launch) = 0;
+    virtual size_t newton_workspace(int restart) const = 0;
+    virtual int newton_step(int slot, double dtau, const rve_newton_opts& o, void* ws, size_t ws_bytes,
+                            rve_step_info* info) = 0;
     virtual int autotune(int repeat, int* shape_out) = 0;
     virtual size_t state_bytes() const = 0;
     virtual int save_state(int slot, void* host, size_t bytes) = 0;
@@ -1562,6 +1568,7 @@ struct Solver : SolverBase {
         S.Gamma = sum_of(slot, 1) * hd_();
         if (!std::isfinite(S.tau)) return fail(RVE_ENUMERIC, "non-finite initial dissipation");
         S.E = S.Sigma = S.T = 0.0;
+        S.sig_max_prev = 0.0;
         S.step = 0;
         S.fractured = false;
         S.ready = true;
@@ -1965,6 +1972,7 @@ struct Solver : SolverBase {
             // dissipated energy per volume on the curve, T - 1/2 Sigma E, before the step
             const double dext_prev = Ss.T - 0.5 * Ss.Sigma * Ss.E;
             Ss.T += 0.5 * (Sigma + Ss.Sigma) * (E[b] - Ss.E);
+            Ss.sig_max_prev = std::max(Ss.sig_max_prev, Ss.Sigma);
             Ss.E = E[b];
             Ss.Sigma = Sigma;
             Ss.tau = q.tau;
@@ -2009,6 +2017,292 @@ struct Solver : SolverBase {
             }
         }
         return RVE_OK;
+    }
+
+    // ---- monolithic Newton-Raphson step (Sec. 4.1, Eq. 22-31) -----------------------
+    // One slot, FP64, no split.  The Newton point lives in the working buffers
+    // (x: the fluctuation of the actual strain, phi_w: the damage, E on the
+    // host); the committed state is not touched until the commit.  Scratch
+    // fields of the slot: r (J1's input strain), p (Green-operator output),
+    // pp (dphi), pq (damage operator output), pb (g' dH), pz (zero damage),
+    // H (the history of the Newton point).  The Krylov vectors live in the
+    // caller's workspace.
+    static long long nr_ld(const Geom& g) {
+        const long long n = (long long)(g.s + 1) * g.N + 1;
+        return (n + 31) / 32 * 32;
+    }
+    size_t newton_workspace(int m) const override {
+        if (m < 1) return 0;
+        const size_t ld = (size_t)nr_ld(g);
+        return sizeof(double) * ((size_t)(m + 4) * ld + (size_t)(m + 5) * 64 + 3 * (size_t)(m + 2) + 8);
+    }
+
+    int newton_step(int slot, double dtau, const rve_newton_opts& op, void* wsp, size_t wsb,
+                    rve_step_info* info) override {
+        if constexpr (!std::is_same<T, double>::value) {
+            (void)slot; (void)dtau; (void)op; (void)wsp; (void)wsb; (void)info;
+            return fail(RVE_EINVAL, "the Newton step runs on FP64 handles only");
+        } else {
+            CHK(check_slot(slot));
+            if (cfg.split != RVE_SPLIT_NONE) return fail(RVE_EINVAL, "the Newton step takes the law without split");
+            if (!(dtau > 0.0) || !std::isfinite(dtau)) return fail(RVE_EINVAL, "dtau must be finite and > 0");
+            const int m = op.restart;
+            if (m < 1 || m > 1000 || op.max_cycles < 1 || op.max_newton < 1 || !(op.krylov_tol > 0.0) ||
+                !(op.theta > 0.0 && op.theta <= 1.0))
+                return fail(RVE_EINVAL, "invalid Newton options");
+            if (!wsp || wsb < newton_workspace(m)) return fail(RVE_EINVAL, "Newton workspace too small");
+            const double tol = op.tol > 0.0 ? op.tol : cfg.tol;
+            Range rg("mirve: rve_step_newton (Eq. 22-31)");
+            const int b = slot;
+            const long long N = g.N, sN = (long long)g.s * N, n = sN + N + 1, ld = nr_ld(g);
+            double* V = (double*)wsp;
+            double* bv = V + (long long)(m + 1) * ld;
+            double* dq = bv + ld;
+            double* tv = dq + ld;
+            double* part = tv + ld;
+            double* hA = part + (long long)(m + 5) * 64;
+            double* hB = hA + (m + 2);
+            double* cf = hB + (m + 2);
+            double* upd = cf + (m + 2);
+            double* xs = x + b * sN;
+            double* ph = phi_w + b * N;
+            double* Hb = H + b * N;
+            SlotState& S = slots[b];
+            const double tau = S.tau + dtau;
+            const double hd = hd_();
+            step_greens.assign(B, 0);
+            F6 f;
+            for (int c = 0; c < 6; ++c) f.v[c] = c < g.s ? cfg.f[c] : 0.0;
+            CHK(set_mask(0, only(b)));
+            HIPCHK(launch_copy<T>(phi_c, phi_w, N, B, dmask[0], st));
+            HIPCHK(launch_fill<T>(pz, T(0), N, B, dmask[0], st));
+            rve_step_info o;
+            std::memset(&o, 0, sizeof(o));
+            auto give_up = [&](int code, int why, const char* msg) {
+                if (info) {
+                    o.E = S.E; o.Sigma = S.Sigma; o.tau = S.tau; o.T = S.T; o.step = S.step;
+                    o.fractured = S.fractured ? 1 : 0;
+                    o.G_inst = NAN;
+                    o.n_greenop = step_greens[b];
+                    o.reason = why;
+                    *info = o;
+                }
+                return fail(code, msg);
+            };
+            // the starting point: E x_c, or from the unloaded state the elastic
+            // unit-load solution scaled to the first guess of E
+            double E = S.E;
+            if (E == 0.0) {
+                HIPCHK(launch_copy<T>(x_c, x, sN, B, dmask[0], st));
+                std::vector<int> its(B, 0), rcs(B, RVE_OK);
+                CHK(mech_solve(phi_w, 0, only(b), its, rcs));
+                o.n_cg += its[b];
+                if (rcs[b] != RVE_OK) return give_up(rcs[b], RVE_WHY_CG, "mechanics of the first guess failed");
+                CHK(unit_response(phi_w, 0));
+                HIPCHK(launch_max_field<T>(psi1, N, B, partials, nred, dmask[0], st));
+                HIPCHK(launch_max_partials(partials, nred, B, sums, dmask[0], st));
+                CHK(read_sums(1));
+                const double pm = sum_of(b, 0);
+                E = pm > 0.0 ? std::sqrt(S.min_gc / cfg.ell / pm) : 1.0;
+                HIPCHK(launch_axpby(sN, E, xs, 0.0, xs, st));
+            } else {
+                HIPCHK(launch_axpby(sN, E, x_c + b * sN, 0.0, xs, st));
+            }
+            // relaxation of Eq. 31 (1 for the first two steps)
+            double alpha = 1.0;
+            if (op.relax && S.step >= 2 && S.sig_max_prev > 0.0)
+                alpha = std::max(op.theta, std::min(1.0, S.Sigma / S.sig_max_prev));
+            NrArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.g = g;
+            a.mat_id = mat_id + b * N;
+            a.mat = mat + (long long)b * g.mstride;
+            a.f = f;
+            a.x = xs;
+            a.E = E;
+            a.phi = ph;
+            a.psi_ini = psi_ini + b * N;
+            a.Hn = Hn + b * N;
+            a.history = cfg.history;
+            const double inv_g0 = 1.0 / (1.0 + g.k_res);
+            auto read = [&](const double* dev, double* hostp, long long cnt) -> int {
+                HIPCHK(hipMemcpyAsync(hostp, dev, sizeof(double) * cnt, hipMemcpyDeviceToHost, st));
+                return drain();
+            };
+            // bv = -R(q) (Eq. 24); returns D(phi)
+            auto residual = [&](double& D) -> int {
+                a.E = E;
+                HIPCHK(launch_nr_history(a, Hb, st));
+                CHK(green(phi_w, x, E, p, 1.0, cgpB, dmask[0]));
+                step_greens[b] += 1;
+                HIPCHK(launch_pcg_matvec<T>(g, mat_id, mat, H, 0, 0.0, phi_w, pq, nullptr, nred, nullptr,
+                                            dmask[0], st));
+                CHK(dissip(phi_w, 0));
+                D = sum_of(b, 0) * hd;
+                HIPCHK(launch_nr_pack(sN, N, bv, p + b * sN, -1.0, pq + b * N, -1.0, Hb, 2.0, nullptr, 0.0,
+                                      tau - D, st));
+                return RVE_OK;
+            };
+            // out = J(q) v (Eq. 25)
+            auto jac = [&](const double* v, double* out) -> int {
+                HIPCHK(launch_nr_jac_point(a, v, inv_g0, r + b * sN, pp + b * N, pb + b * N, st));
+                CHK(green(pz, r, 0.0, p, 1.0, cgpB, dmask[0]));
+                step_greens[b] += 1;
+                HIPCHK(launch_pcg_matvec<T>(g, mat_id, mat, H, 0, 0.0, pp, pq, nullptr, nred, nullptr,
+                                            dmask[0], st));
+                HIPCHK(launch_dissipation_dir<T>(g, mat_id, mat, phi_w, pp, partials, nred, dmask[0], st));
+                HIPCHK(launch_sum_partials(partials, nred, 1, B, sums, dmask[0], st));
+                HIPCHK(launch_nr_pack(sN, N, out, p + b * sN, 1.0, pq + b * N, 1.0, pb + b * N, 1.0,
+                                      sums + (long long)b * kMaxVals, hd, 0.0, st));
+                return RVE_OK;
+            };
+            // restarted GMRES for J dq = bv from dq = 0, classical Gram-Schmidt
+            // with one reorthogonalization; Givens rotations on the host
+            std::vector<double> Hh((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m), hh(2 * (m + 2));
+            auto gmres = [&](int& iters, bool& ok) -> int {
+                ok = false;
+                HIPCHK(launch_axpby(n, 0.0, bv, 0.0, dq, st));
+                double bn2 = 0.0;
+                HIPCHK(launch_mdot(bv, ld, 1, bv, n, part, hA, st));
+                CHK(read(hA, &bn2, 1));
+                const double bn = std::sqrt(bn2);
+                if (!std::isfinite(bn)) return RVE_OK;
+                if (bn == 0.0) { ok = true; return RVE_OK; }
+                for (int cyc = 0; cyc < op.max_cycles; ++cyc) {
+                    if (cyc == 0) {
+                        HIPCHK(launch_axpby(n, 1.0, bv, 0.0, V, st));
+                    } else {
+                        CHK(jac(dq, tv));
+                        HIPCHK(launch_axpby(n, 1.0, bv, 0.0, V, st));
+                        HIPCHK(launch_axpby(n, -1.0, tv, 1.0, V, st));
+                    }
+                    double beta2 = 0.0;
+                    HIPCHK(launch_mdot(V, ld, 1, V, n, part, hA, st));
+                    CHK(read(hA, &beta2, 1));
+                    const double beta = std::sqrt(beta2);
+                    if (!std::isfinite(beta)) return RVE_OK;
+                    if (beta <= op.krylov_tol * bn) { ok = true; return RVE_OK; }
+                    HIPCHK(launch_unit_scale(V, n, hA, st));
+                    std::fill(gv.begin(), gv.end(), 0.0);
+                    gv[0] = beta;
+                    int k = 0;
+                    for (int j = 0; j < m; ++j) {
+                        double* vj1 = V + (long long)(j + 1) * ld;
+                        CHK(jac(V + (long long)j * ld, vj1));
+                        HIPCHK(launch_mdot(V, ld, j + 1, vj1, n, part, hA, st));
+                        HIPCHK(launch_maxpy(V, ld, j + 1, hA, -1.0, vj1, n, st));
+                        HIPCHK(launch_mdot(V, ld, j + 1, vj1, n, part, hB, st));
+                        HIPCHK(launch_maxpy(V, ld, j + 1, hB, -1.0, vj1, n, st));
+                        HIPCHK(launch_mdot(vj1, ld, 1, vj1, n, part, hB + j + 1, st));
+                        HIPCHK(launch_unit_scale(vj1, n, hB + j + 1, st));
+                        CHK(read(hA, hh.data(), (m + 2) + j + 2));
+                        iters += 1;
+                        double* col = &Hh[(size_t)j * (m + 1)];
+                        for (int i = 0; i <= j; ++i) col[i] = hh[i] + hh[m + 2 + i];
+                        const double hn2 = hh[m + 2 + j + 1];
+                        col[j + 1] = hn2 > 0.0 ? std::sqrt(hn2) : 0.0;
+                        for (int i = 0; i < j; ++i) {
+                            const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+                            col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+                            col[i] = t;
+                        }
+                        const double rr = std::hypot(col[j], col[j + 1]);
+                        if (!(rr > 0.0) || !std::isfinite(rr)) return RVE_OK;
+                        cs[j] = col[j] / rr;
+                        sn[j] = col[j + 1] / rr;
+                        col[j] = rr;
+                        col[j + 1] = 0.0;
+                        gv[j + 1] = -sn[j] * gv[j];
+                        gv[j] = cs[j] * gv[j];
+                        k = j + 1;
+                        if (std::fabs(gv[j + 1]) <= op.krylov_tol * bn || !(hn2 > 0.0)) break;
+                    }
+                    for (int i = k - 1; i >= 0; --i) {
+                        double sacc = gv[i];
+                        for (int l = i + 1; l < k; ++l) sacc -= Hh[(size_t)l * (m + 1) + i] * y[l];
+                        y[i] = sacc / Hh[(size_t)i * (m + 1) + i];
+                    }
+                    CHK(upload_bytes(cf, y.data(), sizeof(double) * k));
+                    HIPCHK(launch_maxpy(V, ld, k, cf, 1.0, dq, n, st));
+                }
+                // the last cycle's update is in dq; accept it if its true residual is small
+                CHK(jac(dq, tv));
+                HIPCHK(launch_axpby(n, 1.0, bv, 0.0, V, st));
+                HIPCHK(launch_axpby(n, -1.0, tv, 1.0, V, st));
+                double r2 = 0.0;
+                HIPCHK(launch_mdot(V, ld, 1, V, n, part, hA, st));
+                CHK(read(hA, &r2, 1));
+                ok = std::sqrt(r2) <= op.krylov_tol * bn;
+                return RVE_OK;
+            };
+            int it = 0, nkry = 0;
+            bool conv = false;
+            double D = 0.0;
+            for (it = 1; it <= op.max_newton; ++it) {
+                CHK(residual(D));
+                bool ok = false;
+                CHK(gmres(nkry, ok));
+                if (!ok) {
+                    o.n_stagger = it; o.n_cg += nkry;
+                    return give_up(RVE_ENOCONV, RVE_WHY_GMRES, "GMRES of a Newton system did not converge");
+                }
+                double dEh = 0.0;
+                CHK(read(dq + sN + N, &dEh, 1));
+                const double En = E + alpha * dEh;
+                double u4[4];
+                HIPCHK(launch_nr_update(g.s, N, dq, alpha, f, En, xs, ph, part, upd, st));
+                CHK(read(upd, u4, 4));
+                E = En;
+                CHK(dissip(phi_w, 0));
+                D = sum_of(b, 0) * hd;
+                const double err = std::max({std::sqrt(u4[0]) / std::max(std::sqrt(u4[1]), 1e-300),
+                                             std::sqrt(u4[2]) / std::max(std::sqrt(u4[3]), 1e-300),
+                                             std::fabs(D - tau) / tau});
+                if (!std::isfinite(err) || !std::isfinite(E)) {
+                    o.n_stagger = it; o.n_cg += nkry;
+                    return give_up(RVE_ENUMERIC, RVE_WHY_BREAKDOWN, "non-finite Newton iterate");
+                }
+                if (trace) std::fprintf(stderr, "newton it %d E %.17g D-tau %.3e err %.3e krylov %d\n", it, E,
+                                        D - tau, err, nkry);
+                if (err < tol) { conv = true; break; }
+            }
+            if (!conv) {
+                o.n_stagger = op.max_newton; o.n_cg += nkry;
+                return give_up(RVE_ENOCONV, RVE_WHY_NEWTON, "Newton did not converge");
+            }
+            if (!(E > 0.0)) return give_up(RVE_ENUMERIC, RVE_WHY_BREAKDOWN, "Newton reached E <= 0");
+            // commit (Eq. 33, 38): the history of the Newton point, then the unit
+            // fluctuation x / E and the unit response the commit prices Sigma with
+            a.E = E;
+            HIPCHK(launch_nr_history(a, Hb, st));
+            HIPCHK(launch_axpby(sN, 1.0 / E, xs, 0.0, xs, st));
+            CHK(unit_response(phi_w, 0));
+            std::vector<double> S1(B, 0.0), s2(B, 0.0);
+            S1[b] = sum_of(b, 0) / double(N);
+            s2[b] = sum_of(b, 1);
+            std::vector<Progress> P(B);
+            Progress& q = P[b];
+            q.E = E;
+            q.tau = tau;
+            q.dtau = dtau;
+            q.todo = 1;
+            begin_step(q);
+            q.stage = 2;
+            std::vector<int> C = only(b), fresh(B, 0);
+            CHK(commit(C, S1, s2, P, fresh));
+            slope_warm[b] = 0;
+            if (info) {
+                o = q.last;
+                o.n_stagger = it;
+                o.n_cg += nkry;
+                o.n_greenop = step_greens[b];
+                o.n_steps = 1;
+                o.n_substeps = 1;
+                o.reason = RVE_WHY_NONE;
+                *info = o;
+            }
+            return RVE_OK;
+        }
     }
 
     // ---- single-slot helpers --------------------------------------------------------
@@ -2166,10 +2460,10 @@ struct Solver : SolverBase {
     struct StateHeader {
         uint32_t magic, word;
         int32_t dim, n[3];
-        double E, Sigma, Tc, tau, tau0, Gamma;
+        double E, Sigma, Tc, tau, tau0, Gamma, sig_max_prev;
         int32_t step, fractured, warm, pad;
     };
-    static constexpr uint32_t kStateMagic = 0x3256524du;   // "MRV2"
+    static constexpr uint32_t kStateMagic = 0x3356524du;   // "MRV3"
     size_t state_bytes() const override {
         return sizeof(StateHeader) + sizeof(T) * (size_t)g.N * (3 + g.s);
     }
@@ -2184,6 +2478,7 @@ struct Solver : SolverBase {
         const SlotState& S = slots[slot];
         hdr.E = S.E; hdr.Sigma = S.Sigma; hdr.Tc = S.T; hdr.tau = S.tau; hdr.tau0 = S.tau0;
         hdr.Gamma = S.Gamma;
+        hdr.sig_max_prev = S.sig_max_prev;
         hdr.step = S.step; hdr.fractured = S.fractured ? 1 : 0; hdr.warm = slope_warm[slot];
         std::vector<char> a, b, c, d;
         CHK(save_fields(slot, a, b, c, d));
@@ -2200,7 +2495,7 @@ struct Solver : SolverBase {
         if (hdr.magic != kStateMagic || hdr.word != sizeof(T) || hdr.dim != g.dim || hdr.n[0] != g.nx ||
             hdr.n[1] != g.ny || hdr.n[2] != g.nz)
             return fail(RVE_EINVAL, "state blob of another grid or precision");
-        const double sc[6] = {hdr.E, hdr.Sigma, hdr.Tc, hdr.tau, hdr.tau0, hdr.Gamma};
+        const double sc[7] = {hdr.E, hdr.Sigma, hdr.Tc, hdr.tau, hdr.tau0, hdr.Gamma, hdr.sig_max_prev};
         for (double v : sc)
             if (!std::isfinite(v)) return fail(RVE_EINVAL, "non-finite scalar in state blob");
         const size_t fN = sizeof(T) * g.N, sN = fN * g.s;
@@ -2216,6 +2511,7 @@ struct Solver : SolverBase {
         SlotState& S = slots[slot];
         S.E = hdr.E; S.Sigma = hdr.Sigma; S.T = hdr.Tc; S.tau = hdr.tau; S.tau0 = hdr.tau0;
         S.Gamma = hdr.Gamma;
+        S.sig_max_prev = hdr.sig_max_prev;
         S.step = hdr.step; S.fractured = hdr.fractured != 0;
         slope_warm[slot] = hdr.warm ? 1 : 0;
         return RVE_OK;
@@ -2703,6 +2999,34 @@ int rve_step_dissipation(rve_handle h, double dtau, rve_step_info* out) {
     int status = RVE_OK, one = 1;
     int rc = h->impl->run(&dtau, &one, 0, out, &status);
     return rc != RVE_OK ? rc : status;
+}
+
+void rve_newton_default_opts(rve_newton_opts* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->tol = 0.0;
+    o->krylov_tol = 1e-12;
+    o->theta = 0.3;
+    o->restart = 200;
+    o->max_cycles = 100;
+    o->max_newton = 50;
+    o->relax = 1;
+}
+
+int rve_newton_workspace(rve_handle h, int restart, size_t* bytes) {
+    if (!h || !bytes) return RVE_EINVAL;
+    if (restart < 1 || restart > 1000) { h->err = "restart must be in 1..1000"; return RVE_EINVAL; }
+    *bytes = h->impl->newton_workspace(restart);
+    return RVE_OK;
+}
+
+int rve_step_newton(rve_handle h, int slot, double dtau, const rve_newton_opts* opts, void* workspace,
+                    size_t workspace_bytes, rve_step_info* info) {
+    if (!h) return RVE_EINVAL;
+    rve_newton_opts o;
+    rve_newton_default_opts(&o);
+    if (opts) o = *opts;
+    return h->impl->newton_step(slot, dtau, o, workspace, workspace_bytes, info);
 }
 
 int rve_step_dissipation_batch(rve_handle* hs, int count, const double* dtau,

@@ -49,7 +49,8 @@ EXPORTS = ["rve_default_config", "rve_query_workspace", "rve_create", "rve_destr
            "rve_apply_green_op", "rve_apply_green_op_device", "rve_solve_mechanics",
            "rve_solve_damage", "rve_dissipation", "rve_profile_pass", "rve_autotune",
            "rve_last_error", "rve_version", "rve_run_slots", "rve_state_bytes", "rve_save_state",
-           "rve_load_state", "rve_apply_green_op_device_noalloc", "rve_run_stats", "rve_run_budget"]
+           "rve_load_state", "rve_apply_green_op_device_noalloc", "rve_run_stats", "rve_run_budget",
+           "rve_newton_default_opts", "rve_newton_workspace", "rve_step_newton"]
 
 
 class rve_config(C.Structure):
@@ -83,6 +84,12 @@ class rve_step_info(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class rve_newton_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("krylov_tol", C.c_double), ("theta", C.c_double),
+                ("restart", C.c_int), ("max_cycles", C.c_int), ("max_newton", C.c_int),
+                ("relax", C.c_int)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libmirve.so is not built; run `python -m paper_2508_07424_amd.build`")
@@ -108,6 +115,9 @@ def _load():
         "rve_batch_size": (I, [P]),
         "rve_run_stats": (I, [P, dp]),
         "rve_run_budget": (I, [P, dp, C.c_longlong, I, C.POINTER(rve_step_info), C.POINTER(C.c_int)]),
+        "rve_newton_default_opts": (None, [C.POINTER(rve_newton_opts)]),
+        "rve_newton_workspace": (I, [P, I, C.POINTER(C.c_size_t)]),
+        "rve_step_newton": (I, [P, I, D, C.POINTER(rve_newton_opts), P, S, C.POINTER(rve_step_info)]),
         "rve_release_slot": (I, [P, I]),
         "rve_effective_toughness_slot": (I, [P, I, dp]),
         "rve_get_field_slot": (I, [P, I, I, dp, S]),
@@ -289,6 +299,25 @@ class Rve:
         lib.rve_run_budget(self.h, _dptr(dt), int(total_steps),
                            RVE_RUN_STOP_AT_FRACTURE if stop_at_fracture else 0, infos, status)
         return [infos[i].as_dict() for i in range(self.B)], [status[i] for i in range(self.B)]
+
+    def rve_step_newton(self, dtau, slot=0, **opts):
+        """One step by the monolithic Newton-Raphson solver; opts override the
+        fields of rve_newton_opts.  The Krylov workspace is a device buffer
+        kept per restart length."""
+        import torch
+        o = rve_newton_opts()
+        lib.rve_newton_default_opts(C.byref(o))
+        for key, v in opts.items():
+            setattr(o, key, v)
+        nb = C.c_size_t(0)
+        self._chk(lib.rve_newton_workspace(self.h, o.restart, C.byref(nb)))
+        ws = getattr(self, "_newton_ws", None)
+        if ws is None or ws.numel() < nb.value:
+            ws = self._newton_ws = torch.empty(nb.value, dtype=torch.uint8, device=self.workspace.device)
+        info = rve_step_info()
+        self._chk(lib.rve_step_newton(self.h, int(slot), float(dtau), C.byref(o), C.c_void_p(ws.data_ptr()),
+                                      C.c_size_t(nb.value), C.byref(info)))
+        return info.as_dict()
 
     def rve_run_stats(self):
         """(rounds, mean fraction of the slots each round covered) of the last

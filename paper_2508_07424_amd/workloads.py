@@ -203,6 +203,19 @@ def composite_2d(n=256, seed=1, E_ratio=5.0, Gc_ratio=2.0, vf=0.3, ell=2.0, crac
                           "vf": float(mask.mean()), "seed": seed})
 
 
+def two_phase_plate_2d(seed=21, n=(12, 10), dtau=0.12):
+    """Small two-phase plate: each voxel stiff (E = 4, Gc = 2) with
+    probability 0.4, else soft (E = 1, Gc = 1); a notch of voxels x = 3..6
+    in row 5; l = 1.5, tension along y.  Small enough for Newton systems
+    solved without a preconditioner."""
+    rng = np.random.default_rng(seed)
+    pid = (rng.random((n[1], n[0])) < 0.4).astype(np.uint16)
+    void, tips = notch_2d(n, 1.0, 5, 3, 7)
+    pid[void.astype(bool)] = 0
+    return Workload(n=n, h=1.0, ell=1.5, phases=[iso(1, 0.3, 1), iso(4, 0.25, 2)], phase_id=pid,
+                    f=load_yy(2), dtau=dtau, void=void, phi_disc=tips)
+
+
 def homogeneous_2d(nx=32, ny=32, ell=1.5, crack=8, E=1.0, nu=0.3, Gc=1.0, phi_M=0.8,
                    dtau_frac=0.01):
     """Homogeneous plate with a centred notch (the 'broken in two' check)."""

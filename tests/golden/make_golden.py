@@ -7,6 +7,8 @@ fracture point; per step E, Sigma, D, T and G_eff (Eq. 32-33).
 composite64_fp64.json: the first 60 steps of the 64 x 64 composite.
 sampling24_fp64.json: the toughness of a 24 x 24 plate with one inclusion
 at four initial-crack positions and their minimum (Sec. 3).
+newton_plate12_fp64.json: 22 steps of the monolithic Newton-Raphson solver
+(Sec. 4.1) on a 12 x 10 two-phase plate, past the peak load.
 Both with tight tolerances (stagger 1e-10, Krylov and constraint 1e-12).
 """
 import json
@@ -90,8 +92,29 @@ def sampling24(count=4):
             "seconds": round(time.time() - t0, 1)}
 
 
+def newton_plate12(nsteps=22):
+    """The paper's monolithic Newton-Raphson step (Sec. 4.1, Eq. 22-31) on
+    the 12 x 10 two-phase plate: nsteps steps, the last ones past the peak
+    load, where the relaxation of Eq. 31 takes alpha < 1.  Newton tolerance
+    1e-11, GMRES relative residual 1e-12."""
+    from oracle import newton
+    w = W.two_phase_plate_2d()
+    prob = _problem(w)
+    st = solver.State(prob)
+    t0 = time.time()
+    curve = []
+    for k in range(nsteps):
+        rec = newton.step(prob, st, w.dtau, tol=1e-11)
+        curve.append(_record(rec))
+        print("newton step", k + 1, "E %.6g alpha %.6g newton %d" % (rec["E"], rec["alpha"], rec["n_newton"]),
+              flush=True)
+    return {"workload": "two_phase_plate_2d()", "tolerances": TOL, "newton_tol": 1e-11,
+            "krylov_tol": 1e-12, "dtau": w.dtau, "tau0": float(st.tau0), "steps": curve,
+            "phi": st.phi.T.ravel().tolist(), "seconds": round(time.time() - t0, 1)}
+
+
 if __name__ == "__main__":
-    which = sys.argv[1:] or ["homogeneous32", "composite64", "sampling24"]
+    which = sys.argv[1:] or ["homogeneous32", "composite64", "sampling24", "newton_plate12"]
     for name in which:
         out = globals()[name]()
         path = os.path.join(ROOT, "tests", "golden", name + "_fp64.json")
