@@ -318,6 +318,62 @@ def host_cpu():
     return {"nproc": usable, "cpu_count": os.cpu_count(), "model": model}
 
 
+def newton_compare(torch, size=32, steps=3, oracle=True):
+    """The monolithic Newton-Raphson step (Sec. 4.1) against the staggered
+    step on one FP64 RVE (homogeneous size x size plate, notch size / 4):
+    after one untimed step each, `steps` steps timed per solver on the GPU,
+    and one Newton step of the oracle on the host from the same state."""
+    from paper_2508_07424_amd import mirve
+    from paper_2508_07424_amd import workloads as W
+    w = W.homogeneous_2d(nx=size, ny=size, crack=size // 4)
+    tight = dict(tol=1e-10, tol_cg=1e-12, tol_pcg=1e-14, tol_al=1e-12)
+    stream = torch.cuda.Stream()
+    a = mirve.from_workload(w, stream=stream, **tight)
+    b = mirve.from_workload(w, stream=stream, **tight)
+    a.rve_step_dissipation(w.dtau)
+    b.rve_step_newton(w.dtau, tol=1e-10)
+    out = {"workload": "homogeneous %dx%d plate, notch %d, FP64, %d steps after the first"
+           % (size, size, size // 4, steps)}
+    for name, r, fn in (("staggered", a, lambda: a.rve_step_dissipation(w.dtau)),
+                        ("newton", b, lambda: b.rve_step_newton(w.dtau, tol=1e-10))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tot = {"n_greenop": 0, "n_stagger": 0, "n_cg": 0, "n_pcg": 0}
+        for _ in range(steps):
+            info = fn()
+            for key in tot:
+                tot[key] += info[key]
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        out[name] = {"ms_per_step": round(1e3 * sec / steps, 2),
+                     "greenops_per_step": round(tot["n_greenop"] / steps, 1),
+                     "voxel_iter_per_s": round(tot["n_greenop"] * r.N / sec, 1),
+                     "E": info["E"]}
+        if name == "newton":
+            out[name]["newton_iterations_per_step"] = round(tot["n_stagger"] / steps, 2)
+            out[name]["gmres_iterations_per_step"] = round(tot["n_cg"] / steps, 1)
+        else:
+            out[name]["stagger_iterations_per_step"] = round(tot["n_stagger"] / steps, 2)
+        progress("newton comparison: %s %.1f ms per step" % (name, out[name]["ms_per_step"]))
+    out["rel_E_diff"] = abs(out["newton"]["E"] - out["staggered"]["E"]) / abs(out["staggered"]["E"])
+    out["newton_over_staggered_time"] = round(out["newton"]["ms_per_step"] / out["staggered"]["ms_per_step"], 2)
+    if oracle:
+        from oracle import newton, solver
+        prob = solver.Problem(w.n, w.h, w.ell, w.phases, w.phase_id, w.f, theta=w.theta, void=w.void,
+                              phi_disc=w.phi_disc, phi_M=w.phi_M, k=w.k, tol=1e-10, tol_cg=1e-12,
+                              tol_al=1e-12)
+        st = solver.State(prob)
+        newton.step(prob, st, w.dtau, tol=1e-10)
+        t0 = time.perf_counter()
+        rec = newton.step(prob, st, w.dtau, tol=1e-10)
+        sec = time.perf_counter() - t0
+        out["oracle_newton"] = {"ms_per_step": round(1e3 * sec, 1), "kind": "oracle", "cores": 1,
+                                "newton_iterations": rec["n_newton"], "krylov_iterations": rec["n_krylov"],
+                                "sample": "the second step, after an untimed first"}
+        progress("newton comparison: oracle %.1f ms per step" % out["oracle_newton"]["ms_per_step"])
+    return out
+
+
 def cpu_baseline(w, seconds):
     """The oracle's conjugate-gradient Green-operator solve on the host,
     bounded to about `seconds` of work: voxel-iterations per second."""
@@ -370,6 +426,11 @@ def main():
     ap.add_argument("--schedule", choices=["budget", "fixed"], default="budget",
                     help="budget: the batch commits steps x B RVE-steps, each RVE at its own pace; "
                          "fixed: every RVE takes exactly the steps (a call ends with its slowest RVE)")
+    ap.add_argument("--newton-size", type=int, default=32,
+                    help="grid side of the Newton-against-staggered comparison (0: skip it)")
+    ap.add_argument("--newton-steps", type=int, default=3)
+    ap.add_argument("--newton-only", action="store_true",
+                    help="only the Newton-against-staggered comparison (one JSON line)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="set up the batch and time the Green-operator passes only (for counter runs)")
     args = ap.parse_args()
@@ -383,6 +444,11 @@ def main():
     if args.serve_only:
         out = {"serving": serving(max(1, args.serve_requests), seed=args.serve_seed,
                                   rate=args.serve_rate, sizes=args.serve_sizes, forms=args.serve_form)}
+        print(json.dumps(out), flush=True)
+        return
+    if args.newton_only:
+        out = {"newton": newton_compare(torch, args.newton_size, args.newton_steps,
+                                        oracle=not args.no_cpu_baseline)}
         print(json.dumps(out), flush=True)
         return
     build, size0, batch0, prec0, desc = WORKLOADS[args.workload]
@@ -483,10 +549,15 @@ def main():
         "roofline": roof,
     }
     if args.serve_requests > 0:
-        del rve
+        rve = None
         torch.cuda.empty_cache()
         out["serving"] = serving(args.serve_requests, seed=args.serve_seed, rate=args.serve_rate,
                                  sizes=args.serve_sizes)
+    if args.newton_size > 0:
+        rve = None
+        torch.cuda.empty_cache()
+        out["newton"] = newton_compare(torch, args.newton_size, args.newton_steps,
+                                       oracle=not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         progress("oracle on the host")
         out["cpu_baseline"] = cpu_baseline(wls[0], args.cpu_seconds)
