@@ -35,6 +35,15 @@ hipError_t launch_mdot(const double* V, long long ldv, int k, const double* w, l
 // w += alpha sum_{j<k} c[j] V_j (c on the device)
 hipError_t launch_maxpy(const double* V, long long ldv, int k, const double* c, double alpha,
                         double* w, long long n, hipStream_t st);
+// GMRES least-squares part on the device (one thread each): gv = sqrt(nrm2[0]) e_1;
+// column j of the Hessenberg matrix (hA + hB, norm sqrt(hB[j + 1])) into R
+// (column stride ldr) with its Givens rotation, est[j] = |residual| (NaN at
+// a breakdown); y = R^-1 gv over k columns
+hipError_t launch_gmres_start(double* gv, int m, const double* nrm2, hipStream_t st);
+hipError_t launch_gmres_col(int j, int ldr, const double* hA, const double* hB, double* R, double* cs,
+                            double* sn, double* gv, double* est, hipStream_t st);
+hipError_t launch_gmres_solve(int k, int ldr, const double* R, const double* gv, double* y,
+                              hipStream_t st);
 // w /= sqrt(nrm2[0])
 hipError_t launch_unit_scale(double* w, long long n, const double* nrm2, hipStream_t st);
 // y = a x + b y

@@ -131,6 +131,16 @@ __global__ void __launch_bounds__(TPB) k_mdot(const double* V, long long ldv, co
     block_sum_store<1>(pv, partials + (long long)j * gridDim.x, 1, blockIdx.x);
 }
 
+// out[j] = V_j . w by one block per j (short vectors: no second launch)
+__global__ void __launch_bounds__(TPB) k_mdot1(const double* V, long long ldv, const double* w,
+                                              long long n, double* out) {
+    const double* v = V + (long long)blockIdx.x * ldv;
+    double s = 0.0;
+    for (long long i = threadIdx.x; i < n; i += blockDim.x) s += v[i] * w[i];
+    double pv[1] = {s};
+    block_sum_store<1>(pv, out, 1, blockIdx.x);
+}
+
 // out[j] = sum of partials[j * nblk + 0 .. nblk) in a fixed order (one block per j)
 __global__ void __launch_bounds__(TPB) k_mdot_fin(const double* partials, int nblk, double* out) {
     const int j = blockIdx.x;
@@ -139,15 +149,102 @@ __global__ void __launch_bounds__(TPB) k_mdot_fin(const double* partials, int nb
     if (threadIdx.x == 0) out[j] = s[0];
 }
 
-// w += alpha * sum_{j < k} c[j] V_j
-__global__ void __launch_bounds__(TPB) k_maxpy(const double* V, long long ldv, int k,
-                                              const double* c, double alpha, double* w,
-                                              long long n) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
+// w += alpha * sum_{j < k} c[j] V_j.  A block covers 32 consecutive entries
+// with 8 groups of 32 lanes; group q adds the vectors j = q, q + 8, ...;
+// the 8 group sums are then added in order.
+constexpr int kAxpyLanes = 32, kAxpyGroups = TPB / kAxpyLanes;
+
+__global__ void __launch_bounds__(TPB) k_maxpy(const double* V, long long ldv, int k, const double* c,
+                                              double alpha, double* w, long long n) {
+    __shared__ double part[kAxpyGroups][kAxpyLanes];
+    const int lane = threadIdx.x % kAxpyLanes, q = threadIdx.x / kAxpyLanes;
+    for (long long base = (long long)blockIdx.x * kAxpyLanes; base < n;
+         base += (long long)gridDim.x * kAxpyLanes) {
+        const long long i = base + lane;
         double acc = 0.0;
-        for (int j = 0; j < k; ++j) acc += c[j] * V[(long long)j * ldv + i];
-        w[i] += alpha * acc;
+        if (i < n)
+            for (int j = q; j < k; j += kAxpyGroups) acc += c[j] * V[(long long)j * ldv + i];
+        part[q][lane] = acc;
+        __syncthreads();
+        if (q == 0 && i < n) {
+            double sum = 0.0;
+            for (int r = 0; r < kAxpyGroups; ++r) sum += part[r][lane];
+            w[i] += alpha * sum;
+        }
+        __syncthreads();
+    }
+}
+
+// Givens rotations of the Arnoldi process.  gv = beta e_1.
+__global__ void k_gmres_start(double* gv, int m, const double* nrm2) {
+    for (int i = threadIdx.x; i <= m; i += blockDim.x) gv[i] = i == 0 ? sqrt(fmax(nrm2[0], 0.0)) : 0.0;
+}
+
+constexpr int kMaxRestart = 1000;
+
+// Column j of the Hessenberg matrix (first and second Gram-Schmidt passes,
+// the new vector's norm^2 at hB[j + 1]) rotated by the previous rotations;
+// a new rotation zeroes its subdiagonal.  est[j] = |residual| after column
+// j, NaN at a breakdown.  The block stages the column and the rotations in
+// LDS; one thread applies the rotation chain.
+__global__ void __launch_bounds__(TPB) k_gmres_col(int j, int ldr, const double* hA, const double* hB,
+                                                  double* R, double* cs, double* sn, double* gv,
+                                                  double* est) {
+    __shared__ double c_col[kMaxRestart + 1], c_cs[kMaxRestart], c_sn[kMaxRestart];
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+        c_col[i] = hA[i] + hB[i];
+        if (i < j) { c_cs[i] = cs[i]; c_sn[i] = sn[i]; }
+    }
+    __syncthreads();
+    double* col = R + (long long)j * ldr;
+    if (threadIdx.x == 0) {
+        const double hn2 = hB[j + 1];
+        double lo = hn2 > 0.0 ? sqrt(hn2) : 0.0;
+        // rotation i mixes entries i and i + 1; entry i + 1 is carried to the next
+        double carry = c_col[0];
+        for (int i = 0; i < j; ++i) {
+            const double nxt = c_col[i + 1];
+            c_col[i] = c_cs[i] * carry + c_sn[i] * nxt;
+            carry = -c_sn[i] * carry + c_cs[i] * nxt;
+        }
+        const double rr = hypot(carry, lo);
+        if (!(rr > 0.0) || !isfinite(rr)) {
+            est[j] = __builtin_nan("");
+            c_col[j] = carry;
+        } else {
+            const double cj = carry / rr, sj = lo / rr;
+            cs[j] = cj;
+            sn[j] = sj;
+            c_col[j] = rr;
+            const double g = gv[j];
+            gv[j + 1] = -sj * g;
+            gv[j] = cj * g;
+            est[j] = fabs(sj * g);
+        }
+        col[j + 1] = 0.0;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = c_col[i];
+}
+
+// y = R^-1 gv over the first k columns: column-oriented back substitution,
+// the right-hand side in LDS, one barrier per column
+__global__ void __launch_bounds__(TPB) k_gmres_solve(int k, int ldr, const double* R, const double* gv,
+                                                    double* y) {
+    __shared__ double rhs[kMaxRestart];
+    __shared__ double yi;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) rhs[i] = gv[i];
+    __syncthreads();
+    for (int i = k - 1; i >= 0; --i) {
+        const double* ci = R + (long long)i * ldr;
+        if (threadIdx.x == 0) {
+            yi = rhs[i] / ci[i];
+            y[i] = yi;
+        }
+        __syncthreads();
+        const double v = yi;
+        for (int l = threadIdx.x; l < i; l += blockDim.x) rhs[l] -= ci[l] * v;
+        __syncthreads();
     }
 }
 
@@ -227,8 +324,15 @@ hipError_t launch_nr_pack(long long sN, long long N, double* out, const double* 
 
 int nr_dot_blocks(long long n) { return grid_for(n, 64); }
 
+// vectors up to this length take one block per dot product
+constexpr long long kMdotOneBlock = 1 << 16;
+
 hipError_t launch_mdot(const double* V, long long ldv, int k, const double* w, long long n,
                        double* partials, double* out, hipStream_t st) {
+    if (n <= kMdotOneBlock) {
+        hipLaunchKernelGGL(k_mdot1, dim3(k), dim3(TPB), 0, st, V, ldv, w, n, out);
+        return hipGetLastError();
+    }
     const int nblk = nr_dot_blocks(n);
     hipLaunchKernelGGL(k_mdot, dim3(nblk, k), dim3(TPB), 0, st, V, ldv, w, n, partials);
     hipLaunchKernelGGL(k_mdot_fin, dim3(k), dim3(TPB), 0, st, partials, nblk, out);
@@ -237,7 +341,28 @@ hipError_t launch_mdot(const double* V, long long ldv, int k, const double* w, l
 
 hipError_t launch_maxpy(const double* V, long long ldv, int k, const double* c, double alpha,
                         double* w, long long n, hipStream_t st) {
-    hipLaunchKernelGGL(k_maxpy, dim3(grid_for(n, 2048)), dim3(TPB), 0, st, V, ldv, k, c, alpha, w, n);
+    long long nb = (n + kAxpyLanes - 1) / kAxpyLanes;
+    if (nb > 8192) nb = 8192;
+    hipLaunchKernelGGL(k_maxpy, dim3((unsigned)nb), dim3(TPB), 0, st, V, ldv, k, c, alpha, w, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_gmres_start(double* gv, int m, const double* nrm2, hipStream_t st) {
+    hipLaunchKernelGGL(k_gmres_start, dim3(1), dim3(TPB), 0, st, gv, m, nrm2);
+    return hipGetLastError();
+}
+
+hipError_t launch_gmres_col(int j, int ldr, const double* hA, const double* hB, double* R, double* cs,
+                            double* sn, double* gv, double* est, hipStream_t st) {
+    if (j < 0 || j >= kMaxRestart) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gmres_col, dim3(1), dim3(TPB), 0, st, j, ldr, hA, hB, R, cs, sn, gv, est);
+    return hipGetLastError();
+}
+
+hipError_t launch_gmres_solve(int k, int ldr, const double* R, const double* gv, double* y,
+                              hipStream_t st) {
+    if (k < 0 || k > kMaxRestart) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_gmres_solve, dim3(1), dim3(TPB), 0, st, k, ldr, R, gv, y);
     return hipGetLastError();
 }
 

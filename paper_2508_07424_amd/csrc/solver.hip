@@ -2031,10 +2031,17 @@ struct Solver : SolverBase {
         const long long n = (long long)(g.s + 1) * g.N + 1;
         return (n + 31) / 32 * 32;
     }
+    // workspace: V (m + 1 vectors), b, dq, J dq, the dot-product partials, the Gram-Schmidt coefficients (two passes), the
+    // least-squares solution, the update norms, then the rotated Hessenberg
+    // columns, the rotations, the rotated right-hand side and the residual
+    // estimates
+    static size_t nr_doubles(long long ld, int m) {
+        return (size_t)(m + 4) * ld + (size_t)(m + 5) * 64 + 3 * (size_t)(m + 2) + 8 +
+               (size_t)(m + 1) * m + 2 * (size_t)m + (size_t)(m + 1) + (size_t)m;
+    }
     size_t newton_workspace(int m) const override {
         if (m < 1) return 0;
-        const size_t ld = (size_t)nr_ld(g);
-        return sizeof(double) * ((size_t)(m + 4) * ld + (size_t)(m + 5) * 64 + 3 * (size_t)(m + 2) + 8);
+        return sizeof(double) * nr_doubles(nr_ld(g), m);
     }
 
     int newton_step(int slot, double dtau, const rve_newton_opts& op, void* wsp, size_t wsb,
@@ -2064,6 +2071,11 @@ struct Solver : SolverBase {
             double* hB = hA + (m + 2);
             double* cf = hB + (m + 2);
             double* upd = cf + (m + 2);
+            double* Rm = upd + 8;
+            double* csd = Rm + (long long)(m + 1) * m;
+            double* snd = csd + m;
+            double* gvd = snd + m;
+            double* est = gvd + (m + 1);
             double* xs = x + b * sN;
             double* ph = phi_w + b * N;
             double* Hb = H + b * N;
@@ -2156,9 +2168,11 @@ struct Solver : SolverBase {
                                       sums + (long long)b * kMaxVals, hd, 0.0, st));
                 return RVE_OK;
             };
-            // restarted GMRES for J dq = bv from dq = 0, classical Gram-Schmidt
-            // with one reorthogonalization; Givens rotations on the host
-            std::vector<double> Hh((size_t)(m + 1) * m), cs(m), sn(m), gv(m + 1), y(m), hh(2 * (m + 2));
+            // restarted GMRES for J dq = bv from dq = 0: classical Gram-Schmidt
+            // with one reorthogonalization, the Givens rotations on the device;
+            // the host reads the residual estimates every kChunk iterations
+            constexpr int kChunk = 8;
+            std::vector<double> estv(kChunk);
             auto gmres = [&](int& iters, bool& ok) -> int {
                 ok = false;
                 HIPCHK(launch_axpby(n, 0.0, bv, 0.0, dq, st));
@@ -2168,7 +2182,8 @@ struct Solver : SolverBase {
                 const double bn = std::sqrt(bn2);
                 if (!std::isfinite(bn)) return RVE_OK;
                 if (bn == 0.0) { ok = true; return RVE_OK; }
-                for (int cyc = 0; cyc < op.max_cycles; ++cyc) {
+                for (int cyc = 0; cyc <= op.max_cycles; ++cyc) {
+                    // V_0 = bv - J dq (the true residual of the current dq)
                     if (cyc == 0) {
                         HIPCHK(launch_axpby(n, 1.0, bv, 0.0, V, st));
                     } else {
@@ -2182,57 +2197,36 @@ struct Solver : SolverBase {
                     const double beta = std::sqrt(beta2);
                     if (!std::isfinite(beta)) return RVE_OK;
                     if (beta <= op.krylov_tol * bn) { ok = true; return RVE_OK; }
+                    if (cyc == op.max_cycles) return RVE_OK;
+                    HIPCHK(launch_gmres_start(gvd, m, hA, st));
                     HIPCHK(launch_unit_scale(V, n, hA, st));
-                    std::fill(gv.begin(), gv.end(), 0.0);
-                    gv[0] = beta;
                     int k = 0;
-                    for (int j = 0; j < m; ++j) {
-                        double* vj1 = V + (long long)(j + 1) * ld;
-                        CHK(jac(V + (long long)j * ld, vj1));
-                        HIPCHK(launch_mdot(V, ld, j + 1, vj1, n, part, hA, st));
-                        HIPCHK(launch_maxpy(V, ld, j + 1, hA, -1.0, vj1, n, st));
-                        HIPCHK(launch_mdot(V, ld, j + 1, vj1, n, part, hB, st));
-                        HIPCHK(launch_maxpy(V, ld, j + 1, hB, -1.0, vj1, n, st));
-                        HIPCHK(launch_mdot(vj1, ld, 1, vj1, n, part, hB + j + 1, st));
-                        HIPCHK(launch_unit_scale(vj1, n, hB + j + 1, st));
-                        CHK(read(hA, hh.data(), (m + 2) + j + 2));
-                        iters += 1;
-                        double* col = &Hh[(size_t)j * (m + 1)];
-                        for (int i = 0; i <= j; ++i) col[i] = hh[i] + hh[m + 2 + i];
-                        const double hn2 = hh[m + 2 + j + 1];
-                        col[j + 1] = hn2 > 0.0 ? std::sqrt(hn2) : 0.0;
-                        for (int i = 0; i < j; ++i) {
-                            const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-                            col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
-                            col[i] = t;
+                    bool done = false;
+                    for (int j0 = 0; j0 < m && !done; j0 += kChunk) {
+                        const int j1 = std::min(m, j0 + kChunk);
+                        for (int j = j0; j < j1; ++j) {
+                            double* vj1 = V + (long long)(j + 1) * ld;
+                            CHK(jac(V + (long long)j * ld, vj1));
+                            HIPCHK(launch_mdot(V, ld, j + 1, vj1, n, part, hA, st));
+                            HIPCHK(launch_maxpy(V, ld, j + 1, hA, -1.0, vj1, n, st));
+                            HIPCHK(launch_mdot(V, ld, j + 1, vj1, n, part, hB, st));
+                            HIPCHK(launch_maxpy(V, ld, j + 1, hB, -1.0, vj1, n, st));
+                            HIPCHK(launch_mdot(vj1, ld, 1, vj1, n, part, hB + j + 1, st));
+                            HIPCHK(launch_unit_scale(vj1, n, hB + j + 1, st));
+                            HIPCHK(launch_gmres_col(j, m + 1, hA, hB, Rm, csd, snd, gvd, est, st));
+                            iters += 1;
                         }
-                        const double rr = std::hypot(col[j], col[j + 1]);
-                        if (!(rr > 0.0) || !std::isfinite(rr)) return RVE_OK;
-                        cs[j] = col[j] / rr;
-                        sn[j] = col[j + 1] / rr;
-                        col[j] = rr;
-                        col[j + 1] = 0.0;
-                        gv[j + 1] = -sn[j] * gv[j];
-                        gv[j] = cs[j] * gv[j];
-                        k = j + 1;
-                        if (std::fabs(gv[j + 1]) <= op.krylov_tol * bn || !(hn2 > 0.0)) break;
+                        CHK(read(est + j0, estv.data(), j1 - j0));
+                        k = j1;
+                        for (int j = j0; j < j1; ++j) {
+                            if (!std::isfinite(estv[j - j0])) { k = j; done = true; break; }
+                            if (estv[j - j0] <= op.krylov_tol * bn) { k = j + 1; done = true; break; }
+                        }
                     }
-                    for (int i = k - 1; i >= 0; --i) {
-                        double sacc = gv[i];
-                        for (int l = i + 1; l < k; ++l) sacc -= Hh[(size_t)l * (m + 1) + i] * y[l];
-                        y[i] = sacc / Hh[(size_t)i * (m + 1) + i];
-                    }
-                    CHK(upload_bytes(cf, y.data(), sizeof(double) * k));
+                    if (k == 0) return RVE_OK;          // breakdown at the first column
+                    HIPCHK(launch_gmres_solve(k, m + 1, Rm, gvd, cf, st));
                     HIPCHK(launch_maxpy(V, ld, k, cf, 1.0, dq, n, st));
                 }
-                // the last cycle's update is in dq; accept it if its true residual is small
-                CHK(jac(dq, tv));
-                HIPCHK(launch_axpby(n, 1.0, bv, 0.0, V, st));
-                HIPCHK(launch_axpby(n, -1.0, tv, 1.0, V, st));
-                double r2 = 0.0;
-                HIPCHK(launch_mdot(V, ld, 1, V, n, part, hA, st));
-                CHK(read(hA, &r2, 1));
-                ok = std::sqrt(r2) <= op.krylov_tol * bn;
                 return RVE_OK;
             };
             int it = 0, nkry = 0;
