@@ -241,6 +241,22 @@ int rve_set_microstructure_slot(rve_handle h, int slot, const uint16_t* phase_id
                                 const rve_phase* phases, int nphases, const double* theta,
                                 const uint8_t* void_mask, const uint8_t* phi_disc, double phi_M);
 
+/* Same with three Euler angles per voxel in place of theta (Sec. 5.3: grain
+ * orientations drawn in three dimensions, stiffness and cleavage normal
+ * rotated accordingly): euler[3 i + 0..2] = (a1, a2, a3) of voxel i, the
+ * lattice-to-sample rotation R = R_z(a1) R_x(a2) R_z(a3) (z-x-z), so that
+ * (a1, 0, 0) is the in-plane angle a1 of rve_set_microstructure.  A
+ * one-voxel plate of the paper is the 3D grid with n_z = 2 and a
+ * microstructure that does not vary along z: the solution is then
+ * z-independent and, per unit thickness, the plate's; its damage gradients
+ * lie in the plane, so the cleavage tensor acts through its in-plane block
+ * (the projection of the rotated normal on the cross section).  Errors as
+ * rve_set_microstructure; RVE_EINVAL for a null euler or a non-finite
+ * angle. */
+int rve_set_microstructure_euler(rve_handle h, int slot, const uint16_t* phase_id,
+                                 const rve_phase* phases, int nphases, const double* euler,
+                                 const uint8_t* void_mask, const uint8_t* phi_disc, double phi_M);
+
 /* One dissipation-controlled step tau^{n+1} = tau^n + dtau (Eq. 16): the
  * staggered fixed point of equilibrium, damage and the constraint, then
  * commit and the fracture test.  out may be NULL.  Needs batch = 1. */

@@ -93,6 +93,19 @@ def rotation_z(theta):
     return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
 
 
+def rotation_x(angle):
+    c, s = np.cos(angle), np.sin(angle)
+    return np.array([[1.0, 0.0, 0.0], [0.0, c, -s], [0.0, s, c]])
+
+
+def rotation_euler(phi1, Phi, phi2):
+    """Lattice-to-sample rotation of the Euler angles (phi1, Phi, phi2) in the
+    z-x-z convention: R = R_z(phi1) R_x(Phi) R_z(phi2) (Sec. 5.3 draws grain
+    orientations as three Euler angles; (phi1, 0, 0) is the in-plane angle
+    phi1)."""
+    return rotation_z(phi1) @ rotation_x(Phi) @ rotation_z(phi2)
+
+
 def rotate_c4(C4, R):
     """Eq. 13: C^r_ijkl = R_im R_jn R_kp R_lq C_mnpq."""
     return np.einsum("im,jn,kp,lq,mnpq->ijkl", R, R, R, R, C4)

@@ -37,40 +37,46 @@ from . import mandel, spectral
 # materials
 # --------------------------------------------------------------------------
 
-def phase_stiffness(phase, d, theta=0.0):
-    """Mandel stiffness of one phase, rotated about z by theta (Eq. 12-13)."""
+def phase_stiffness(phase, d, theta=0.0, R=None):
+    """Mandel stiffness of one phase, rotated by R (Eq. 12-13); without R,
+    about z by theta."""
     if phase["kind"] == "iso":
         C4 = mandel.isotropic_c4(phase["E"], phase["nu"])
     elif phase["kind"] == "cubic":
         C4 = mandel.cubic_c4(phase["C11"], phase["C12"], phase["C44"])
     else:
         raise ValueError("unknown phase kind")
-    C4r = mandel.rotate_c4(C4, mandel.rotation_z(theta))
+    C4r = mandel.rotate_c4(C4, mandel.rotation_z(theta) if R is None else R)
     return mandel.c4_to_mandel(C4r, d), mandel.bulk_modulus_c4(C4r)
 
 
-def cleavage_tensor(phase, d, theta=0.0):
-    """A_f = I + beta (I - n n) of one phase (Eq. 15), n rotated about z by
-    theta and, in 2D, projected on the plane and normalised."""
+def cleavage_tensor(phase, d, theta=0.0, R=None):
+    """A_f = I + beta (I - n n) of one phase (Eq. 15) with n the unit lattice
+    normal rotated by R (without R, about z by theta); in 2D its in-plane
+    block, which is what the projection of the rotated normal on the cross
+    section gives (Sec. 5.3): a normal along z weakens every in-plane
+    direction alike, A = (1 + beta) I."""
     beta = float(phase.get("beta", 0.0))
     I = np.eye(d)
     if beta == 0.0:
         return I
-    n = mandel.rotation_z(theta) @ np.asarray(phase.get("n", (0.0, 0.0, 1.0)), dtype=float)
-    n = n[:d]
+    n = np.asarray(phase.get("n", (0.0, 0.0, 1.0)), dtype=float)
     norm = np.linalg.norm(n)
     if norm == 0.0:
         return (1.0 + beta) * I
-    n = n / norm
-    return I + beta * (I - np.outer(n, n))
+    Rm = mandel.rotation_z(theta) if R is None else R
+    n = Rm @ (n / norm)
+    A = np.eye(3) + beta * (np.eye(3) - np.outer(n, n))
+    return A[:d, :d]
 
 
 class MaterialField:
     """Per-voxel stiffness C[*n, s, s], bulk modulus K, G_c, void flag and,
     when some phase has beta != 0, the cleavage tensor A[*n, d, d] (else
-    A is None: the isotropic functionals)."""
+    A is None: the isotropic functionals).  Orientations: theta[*n] (about
+    z) or euler[*n, 3] (z-x-z Euler angles, Sec. 5.3)."""
 
-    def __init__(self, n, phases, phase_id, theta=None, void=None, k=1e-6):
+    def __init__(self, n, phases, phase_id, theta=None, void=None, k=1e-6, euler=None):
         n = tuple(n)
         d = len(n)
         s = mandel.nsym(d)
@@ -82,19 +88,24 @@ class MaterialField:
         aniso = any(float(ph.get("beta", 0.0)) != 0.0 for ph in phases)
         self.A = np.zeros(n + (d, d)) if aniso else None
         cache = {}
+        assert theta is None or euler is None
         for idx in np.ndindex(*n):
             p = int(phase_id[idx])
-            th = 0.0 if theta is None else float(theta[idx])
-            key = (p, th)
+            if euler is not None:
+                ang = tuple(float(v) for v in euler[idx])
+            else:
+                ang = (0.0 if theta is None else float(theta[idx]), 0.0, 0.0)
+            R = mandel.rotation_euler(*ang)
+            key = (p, ang)
             if key not in cache:
-                cache[key] = phase_stiffness(phases[p], d, th)
+                cache[key] = phase_stiffness(phases[p], d, R=R)
             C, K = cache[key]
             scale = k if self.void[idx] else 1.0
             self.C[idx] = scale * C
             self.K[idx] = scale * K
             self.Gc[idx] = phases[p]["Gc"]
             if aniso:
-                self.A[idx] = cleavage_tensor(phases[p], d, th)
+                self.A[idx] = cleavage_tensor(phases[p], d, R=R)
 
 
 def degradation(phi, k):

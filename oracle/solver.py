@@ -50,7 +50,7 @@ class Problem:
                  phi_disc=None, phi_M=0.8, k=1e-6, split="none", history=True,
                  A_g=None, tol=1e-10, tol_cg=1e-12, tol_al=1e-12, max_stagger=300,
                  max_cg=20000, frac_threshold=0.95, anderson_depth=5, max_halvings=8,
-                 stall_window=0):
+                 stall_window=0, euler=None):
         self.n = tuple(int(v) for v in n)
         self.d = len(self.n)
         self.s = mandel.nsym(self.d)
@@ -65,7 +65,10 @@ class Problem:
         tr = lambda a: None if a is None else np.ascontiguousarray(np.asarray(a).T)
         pid = tr(phase_id)
         void_x = tr(void) if void is not None else np.zeros(self.n, dtype=bool)
-        self.mat = model.MaterialField(self.n, phases, pid, theta=tr(theta), void=void_x, k=k)
+        eu = None if euler is None else np.ascontiguousarray(
+            np.moveaxis(np.asarray(euler, dtype=float), -1, 0).T)
+        self.mat = model.MaterialField(self.n, phases, pid, theta=tr(theta), void=void_x, k=k,
+                                       euler=eu)
         self.f = np.asarray(f, dtype=float)
         assert self.f.shape == (self.s,)
         self.load_axis = int(np.argmax(np.abs(self.f[: self.d])))

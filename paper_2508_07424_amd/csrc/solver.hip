@@ -67,10 +67,31 @@ static void tensor_of_mandel(const double v[6], double t[3][3]) {
     }
 }
 
+// Lattice-to-sample rotation of the z-x-z Euler angles (a1, a2, a3):
+// R = R_z(a1) R_x(a2) R_z(a3); (a1, 0, 0) is the in-plane angle a1.
+static void euler_rotation(double a1, double a2, double a3, double R[3][3]) {
+    const double c1 = std::cos(a1), s1 = std::sin(a1), c2 = std::cos(a2), s2 = std::sin(a2);
+    const double c3 = std::cos(a3), s3 = std::sin(a3);
+    const double Z1[3][3] = {{c1, -s1, 0.0}, {s1, c1, 0.0}, {0.0, 0.0, 1.0}};
+    const double X2[3][3] = {{1.0, 0.0, 0.0}, {0.0, c2, -s2}, {0.0, s2, c2}};
+    const double Z3[3][3] = {{c3, -s3, 0.0}, {s3, c3, 0.0}, {0.0, 0.0, 1.0}};
+    double T[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; ++k) acc += Z1[i][k] * X2[k][j];
+            T[i][j] = acc;
+        }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; ++k) acc += T[i][k] * Z3[k][j];
+            R[i][j] = acc;
+        }
+}
+
 // Q with mandel(R t R^T) = Q mandel(t); orthogonal.  C' = Q C Q^T.
-static void mandel_rotation(double theta, double Q[6][6]) {
-    const double c = std::cos(theta), s = std::sin(theta);
-    const double R[3][3] = {{c, -s, 0.0}, {s, c, 0.0}, {0.0, 0.0, 1.0}};
+static void mandel_rotation(const double R[3][3], double Q[6][6]) {
     for (int b = 0; b < 6; ++b) {
         double e[6] = {0, 0, 0, 0, 0, 0};
         e[b] = 1.0;
@@ -95,19 +116,18 @@ struct HostMat {
     double A[6];        // cleavage tensor, order xx, yy, zz, yz, xz, xy
 };
 
-// Cleavage tensor A_f = I + beta (I - n n) of a phase (Sec. 2.2, Eq. 15):
-// the lattice normal n rotated about z by theta; in 2D its projection on the
-// plane, normalised (all in-plane directions alike, A = (1 + beta) I, when
-// the normal is along z).
-static void cleavage_tensor(const rve_phase& ph, double theta, int dim, double A[6]) {
-    const double c = std::cos(theta), s = std::sin(theta);
-    double n[3] = {c * ph.n[0] - s * ph.n[1], s * ph.n[0] + c * ph.n[1], ph.n[2]};
-    if (dim == 2) n[2] = 0.0;
-    const double nn = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+// Cleavage tensor A_f = I + beta (I - n n) of a phase (Sec. 2.2, Eq. 15),
+// n the unit lattice normal rotated by R.  2D takes its in-plane block,
+// which is what projecting the rotated normal on the cross section gives
+// (Sec. 5.3): a normal along z weakens every in-plane direction alike,
+// A = (1 + beta) I.  With no normal (2D only), A = (1 + beta) I.
+static void cleavage_tensor(const rve_phase& ph, const double R[3][3], double A[6]) {
+    const double nl = std::sqrt(ph.n[0] * ph.n[0] + ph.n[1] * ph.n[1] + ph.n[2] * ph.n[2]);
+    double n[3] = {0.0, 0.0, 0.0};
+    if (nl > 0.0)
+        for (int i = 0; i < 3; ++i)
+            n[i] = (R[i][0] * ph.n[0] + R[i][1] * ph.n[1] + R[i][2] * ph.n[2]) / nl;
     const double b = ph.beta;
-    if (nn > 0.0)
-        for (double& v : n) v /= nn;
-    // I + beta (I - n n); with no normal, I + beta I in the plane
     A[0] = 1.0 + b * (1.0 - n[0] * n[0]);
     A[1] = 1.0 + b * (1.0 - n[1] * n[1]);
     A[2] = 1.0 + b * (1.0 - n[2] * n[2]);
@@ -116,9 +136,9 @@ static void cleavage_tensor(const rve_phase& ph, double theta, int dim, double A
     A[5] = -b * n[0] * n[1];
 }
 
-static HostMat phase_entry(const rve_phase& ph, double theta, bool notch, double k_res, int dim) {
+static HostMat phase_entry(const rve_phase& ph, const double R[3][3], bool notch, double k_res) {
     HostMat m;
-    cleavage_tensor(ph, theta, dim, m.A);
+    cleavage_tensor(ph, R, m.A);
     double C[6][6] = {{0}};
     if (ph.kind == RVE_PHASE_ISO) {
         const double lam = ph.E * ph.nu / ((1.0 + ph.nu) * (1.0 - 2.0 * ph.nu));
@@ -132,7 +152,7 @@ static HostMat phase_entry(const rve_phase& ph, double theta, bool notch, double
         for (int a = 3; a < 6; ++a) C[a][a] = 2.0 * ph.C44;
     }
     double Q[6][6];
-    mandel_rotation(theta, Q);
+    mandel_rotation(R, Q);
     double QC[6][6];
     for (int a = 0; a < 6; ++a)
         for (int b = 0; b < 6; ++b) {
@@ -276,6 +296,7 @@ struct SlotState {
 struct SolverBase {
     virtual ~SolverBase() {}
     virtual int set_microstructure(int slot, const uint16_t*, const rve_phase*, int, const double*,
+                                   const double* euler,
                                    const uint8_t*, const uint8_t*, double) = 0;
     virtual int run(const double* dtau, const int* todo, int flags, rve_step_info* info, int* status,
                     long long budget = -1) = 0;
@@ -1425,9 +1446,10 @@ struct Solver : SolverBase {
     }
 
     // ---- microstructure of one slot ---------------------------------------------
+    // Orientations: theta[N] (about z), or euler[3 N] (z-x-z angles per voxel).
     int set_microstructure(int slot, const uint16_t* pid, const rve_phase* phases, int nph,
-                           const double* theta, const uint8_t* vmask, const uint8_t* disc,
-                           double phi_M) override {
+                           const double* theta, const double* euler, const uint8_t* vmask,
+                           const uint8_t* disc, double phi_M) override {
         Range rg("mirve: microstructure + enrichment (Eq. 35-38)");
         if (slot < 0 || slot >= B) return fail(RVE_EINVAL, "slot out of range");
         if (!pid || !phases || nph <= 0) return fail(RVE_EINVAL, "phase_id and phases required");
@@ -1454,19 +1476,24 @@ struct Solver : SolverBase {
         }
         // every input is checked (and the material table built) before the
         // slot is touched
-        std::map<std::tuple<int, double, int>, int> keys;
+        if (theta && euler) return fail(RVE_EINVAL, "theta and euler are exclusive");
+        std::map<std::tuple<int, double, double, double, int>, int> keys;
         std::vector<uint16_t> ids(g.N);
         std::vector<MatEntry<T>> table;
         double min_gc = INFINITY;
         for (long long i = 0; i < g.N; ++i) {
             const int ph = pid[i];
             if (ph >= nph) return fail(RVE_EINVAL, "phase_id out of range");
-            const double th = theta ? theta[i] : 0.0;
-            if (!std::isfinite(th)) return fail(RVE_EINVAL, "non-finite theta");
+            double ang[3] = {theta ? theta[i] : 0.0, 0.0, 0.0};
+            if (euler)
+                for (int a = 0; a < 3; ++a) ang[a] = euler[3 * i + a];
+            if (!std::isfinite(ang[0]) || !std::isfinite(ang[1]) || !std::isfinite(ang[2]))
+                return fail(RVE_EINVAL, "non-finite orientation angle");
             const int nt = vmask ? (vmask[i] ? 1 : 0) : 0;
-            // the angle matters for rotated stiffness and for cleavage tensors
+            // the angles matter for rotated stiffness and for cleavage tensors
             const bool by_angle = phases[ph].kind != RVE_PHASE_ISO || phases[ph].beta != 0.0;
-            auto key = std::make_tuple(ph, by_angle ? th : 0.0, nt);
+            if (!by_angle) ang[0] = ang[1] = ang[2] = 0.0;
+            auto key = std::make_tuple(ph, ang[0], ang[1], ang[2], nt);
             auto it = keys.find(key);
             int id;
             if (it == keys.end()) {
@@ -1474,7 +1501,9 @@ struct Solver : SolverBase {
                 if (id >= g.mstride || id >= kMaxMat)
                     return fail(RVE_EINVAL, "more distinct materials than max_materials");
                 keys[key] = id;
-                HostMat hm = phase_entry(phases[ph], std::get<1>(key), nt != 0, cfg.k_res, g.dim);
+                double R[3][3];
+                euler_rotation(ang[0], ang[1], ang[2], R);
+                HostMat hm = phase_entry(phases[ph], R, nt != 0, cfg.k_res);
                 MatEntry<T> me;
                 std::memset(&me, 0, sizeof(me));
                 static const int in2d[3] = {0, 1, 5};
@@ -2944,8 +2973,16 @@ int rve_set_microstructure_slot(rve_handle h, int slot, const uint16_t* phase_id
                                 const rve_phase* phases, int nphases, const double* theta,
                                 const uint8_t* void_mask, const uint8_t* phi_disc, double phi_M) {
     if (!h) return RVE_EINVAL;
-    return h->impl->set_microstructure(slot, phase_id, phases, nphases, theta, void_mask, phi_disc,
-                                       phi_M);
+    return h->impl->set_microstructure(slot, phase_id, phases, nphases, theta, nullptr, void_mask,
+                                       phi_disc, phi_M);
+}
+
+int rve_set_microstructure_euler(rve_handle h, int slot, const uint16_t* phase_id,
+                                 const rve_phase* phases, int nphases, const double* euler,
+                                 const uint8_t* void_mask, const uint8_t* phi_disc, double phi_M) {
+    if (!h || !euler) return RVE_EINVAL;
+    return h->impl->set_microstructure(slot, phase_id, phases, nphases, nullptr, euler, void_mask,
+                                       phi_disc, phi_M);
 }
 
 int rve_set_microstructure(rve_handle h, const uint16_t* phase_id, const rve_phase* phases,

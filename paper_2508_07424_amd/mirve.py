@@ -50,7 +50,8 @@ EXPORTS = ["rve_default_config", "rve_query_workspace", "rve_create", "rve_destr
            "rve_solve_damage", "rve_dissipation", "rve_profile_pass", "rve_autotune",
            "rve_last_error", "rve_version", "rve_run_slots", "rve_state_bytes", "rve_save_state",
            "rve_load_state", "rve_apply_green_op_device_noalloc", "rve_run_stats", "rve_run_budget",
-           "rve_newton_default_opts", "rve_newton_workspace", "rve_step_newton"]
+           "rve_newton_default_opts", "rve_newton_workspace", "rve_step_newton",
+           "rve_set_microstructure_euler"]
 
 
 class rve_config(C.Structure):
@@ -116,6 +117,7 @@ def _load():
         "rve_run_stats": (I, [P, dp]),
         "rve_run_budget": (I, [P, dp, C.c_longlong, I, C.POINTER(rve_step_info), C.POINTER(C.c_int)]),
         "rve_newton_default_opts": (None, [C.POINTER(rve_newton_opts)]),
+        "rve_set_microstructure_euler": (I, [P, I, P, C.POINTER(rve_phase), I, P, P, P, D]),
         "rve_newton_workspace": (I, [P, I, C.POINTER(C.c_size_t)]),
         "rve_step_newton": (I, [P, I, D, C.POINTER(rve_newton_opts), P, S, C.POINTER(rve_step_info)]),
         "rve_release_slot": (I, [P, I]),
@@ -264,7 +266,24 @@ class Rve:
         self._chk(lib.rve_set_microstructure_slot(self.h, int(slot), vp(pid), arr, len(phases),
                                                   vp(th), vp(vm), vp(pd), float(phi_M)))
 
+    def rve_set_microstructure_euler(self, phase_id, phases, euler, void=None, phi_disc=None, phi_M=0.8,
+                                     slot=0):
+        pid = np.ascontiguousarray(phase_id, dtype=np.uint16).reshape(-1)
+        assert pid.size == self.N
+        eu = np.ascontiguousarray(euler, dtype=np.float64).reshape(-1)
+        assert eu.size == 3 * self.N
+        vm = None if void is None else np.ascontiguousarray(void, dtype=np.uint8).reshape(-1)
+        pd = None if phi_disc is None else np.ascontiguousarray(phi_disc, dtype=np.uint8).reshape(-1)
+        arr = phases_array(phases)
+        vp = lambda a: None if a is None else C.c_void_p(a.ctypes.data)
+        self._chk(lib.rve_set_microstructure_euler(self.h, int(slot), vp(pid), arr, len(phases), vp(eu),
+                                                   vp(vm), vp(pd), float(phi_M)))
+
     def set_workload(self, w, slot=0):
+        if getattr(w, "euler", None) is not None:
+            self.rve_set_microstructure_euler(w.phase_id, w.phases, w.euler, void=w.void,
+                                              phi_disc=w.phi_disc, phi_M=w.phi_M, slot=slot)
+            return
         self.rve_set_microstructure(w.phase_id, w.phases, theta=w.theta, void=w.void,
                                     phi_disc=w.phi_disc, phi_M=w.phi_M, slot=slot)
 

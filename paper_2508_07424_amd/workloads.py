@@ -39,6 +39,7 @@ class Workload:
     phi_M: float = 0.8
     k: float = 1e-6
     meta: dict = field(default_factory=dict)
+    euler: Optional[np.ndarray] = None     # per-voxel z-x-z Euler angles, shape reversed(n) + (3,)
 
     @property
     def dim(self):
@@ -383,6 +384,48 @@ def polycrystal_2d(n=512, grains=200, seed=1000, zener=2.0, a_cleave=1.0, ell=2.
                     k=1e-6, meta={"name": "polycrystal_2d_%d" % n, "grains": grains,
                                   "seed": seed, "zener": zener, "a": a_cleave, "beta": beta,
                                   "size_sigma": size_sigma})
+
+
+def polycrystal_plate(n=64, layers=2, grains=30, seed=2000, zener=2.0, beta=1.0, ell=2.0,
+                      crack_frac=0.1, size_sigma=0.0):
+    """Polycrystal plate of Sec. 5.3: grains with orientations drawn in three
+    dimensions (z-x-z Euler angles, uniform on the rotations: a1, a3 ~
+    U[0, 2 pi), cos a2 ~ U[-1, 1]), cubic C11 = 1, C12 = 0.5, C44 = z/4,
+    Gc = 1, cleavage on the cubic [100] plane with weight beta (on the
+    cross section, the in-plane block of the rotated cleavage tensor: the
+    projection of the rotated normal).  The paper's one-voxel plate is
+    represented by `layers` identical layers along z (periodic, so the
+    solution does not vary along z); the tessellation, notch (0.1 L_x at
+    mid-height, through the thickness) and load e_y (x) e_y are those of
+    polycrystal_2d.  dtau = 0.01 Gc L_x L_z."""
+    h = 1.0
+    rng = np.random.default_rng(seed)
+    seeds = rng.uniform(0.0, n * h, size=(grains, 2))
+    a1 = rng.uniform(0.0, 2.0 * np.pi, size=grains)
+    a2 = np.arccos(rng.uniform(-1.0, 1.0, size=grains))
+    a3 = rng.uniform(0.0, 2.0 * np.pi, size=grains)
+    X, Y = _centres((n, n), h)
+    if size_sigma > 0.0:
+        r_mean = n * h / math.sqrt(math.pi * grains)
+        radii = r_mean * np.exp(size_sigma * rng.standard_normal(grains) - 0.5 * size_sigma ** 2)
+        gid2 = _laguerre_ids(X, Y, seeds, radii ** 2, n * h)
+    else:
+        gid2 = _voronoi_ids(X, Y, seeds, n * h)
+    phases = [dict(cubic(1.0, 0.5, zener / 4.0, 1.0), beta=float(beta), n=(1.0, 0.0, 0.0))
+              for _ in range(grains)]
+    euler2 = np.stack([a1[gid2], a2[gid2], a3[gid2]], axis=-1)
+    a = max(2, int(round(crack_frac * n)))
+    x0 = n // 2 - a // 2
+    void2, tips2 = notch_2d((n, n), h, n // 2, x0, x0 + a)
+    nn = (n, n, layers)
+    rep = lambda arr: np.ascontiguousarray(np.broadcast_to(arr, (layers,) + arr.shape))
+    f = np.zeros(6)
+    f[1] = 1.0
+    return Workload(n=nn, h=h, ell=ell, phases=phases, phase_id=rep(gid2), f=f,
+                    dtau=0.01 * n * h * layers * h, void=rep(void2), phi_disc=rep(tips2), phi_M=0.8,
+                    k=1e-6, euler=rep(euler2),
+                    meta={"name": "polycrystal_plate_%d" % n, "grains": grains, "seed": seed,
+                          "zener": zener, "beta": beta, "layers": layers})
 
 
 def composite_3d(n=128, seed=1, spheres=40, vf=0.2, E_ratio=5.0, Gc_ratio=3.0, ell=2.0):

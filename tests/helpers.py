@@ -6,7 +6,8 @@ from oracle import solver
 
 def oracle_problem(w, **kw):
     return solver.Problem(w.n, w.h, w.ell, w.phases, w.phase_id, w.f, theta=w.theta,
-                          void=w.void, phi_disc=w.phi_disc, phi_M=w.phi_M, k=w.k, **kw)
+                          void=w.void, phi_disc=w.phi_disc, phi_M=w.phi_M, k=w.k,
+                          euler=getattr(w, "euler", None), **kw)
 
 
 def to_oracle(a, d):

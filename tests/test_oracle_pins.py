@@ -754,3 +754,95 @@ def test_newton_reaches_the_staggered_fixed_point():
         assert rb["alpha"] == 1.0                # the load still rises: no relaxation
     assert np.linalg.norm(a.phi - b.phi) <= 1e-10 * np.linalg.norm(a.phi)
     assert np.linalg.norm(a.H - b.H) <= 1e-10 * np.linalg.norm(a.H)
+
+
+# --------------------------------------------------------------------------
+# orientations in three dimensions (Sec. 5.3): z-x-z Euler angles
+# --------------------------------------------------------------------------
+
+def test_euler_rotation_convention_by_hand():
+    """R = R_z(a1) R_x(a2) R_z(a3) is a rotation; (a1, 0, 0) is the in-plane
+    angle; and for (0, pi/2, pi/2) the lattice x axis goes to the sample z
+    axis (R_z(pi/2) takes e_x to e_y, R_x(pi/2) takes e_y to e_z), which the
+    reversed product would send to e_y instead."""
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        R = mandel.rotation_euler(*rng.uniform(0, 2 * np.pi, 3))
+        assert np.allclose(R @ R.T, np.eye(3), atol=1e-15) and abs(np.linalg.det(R) - 1) < 1e-14
+    a = 0.7
+    assert np.array_equal(mandel.rotation_euler(a, 0.0, 0.0), mandel.rotation_z(a))
+    R = mandel.rotation_euler(0.0, np.pi / 2, np.pi / 2)
+    assert np.allclose(R @ np.array([1.0, 0.0, 0.0]), [0.0, 0.0, 1.0], atol=1e-15)
+    # the cleavage normal follows: along z it weakens every in-plane
+    # direction alike; tilted by 45 degrees out of the plane (a2 = pi/4 takes
+    # e_y to (0, 1, 1)/sqrt2), the in-plane block is diag(1 + b, 1 + b/2)
+    ph = dict(W.cubic(1.0, 0.5, 0.5, 1.0), beta=2.0, n=(1.0, 0.0, 0.0))
+    assert np.allclose(model.cleavage_tensor(ph, 3, R=R), np.diag([3.0, 3.0, 1.0]), atol=1e-15)
+    assert np.allclose(model.cleavage_tensor(ph, 2, R=R), 3.0 * np.eye(2), atol=1e-15)
+    R45 = mandel.rotation_euler(0.0, np.pi / 4, np.pi / 2)
+    assert np.allclose(model.cleavage_tensor(ph, 2, R=R45), np.diag([3.0, 2.0]), atol=1e-15)
+    assert np.allclose(model.cleavage_tensor(ph, 3, R=R45),
+                       [[3.0, 0.0, 0.0], [0.0, 2.0, -1.0], [0.0, -1.0, 2.0]], atol=1e-15)
+
+
+def test_cubic_stiffness_under_rotations():
+    """A cubic stiffness is unchanged by the lattice's own quarter turns
+    (Euler (pi/2, 0, 0), (0, pi/2, 0), (pi/2, pi/2, pi/2)); any rotation
+    keeps its Mandel eigenvalues and bulk modulus; an isotropic stiffness
+    does not change at all."""
+    ph = W.cubic(1.0, 0.5, 0.8, 1.0)
+    C0, K0 = model.phase_stiffness(ph, 3, R=np.eye(3))
+    for ang in ((np.pi / 2, 0, 0), (0, np.pi / 2, 0), (np.pi / 2, np.pi / 2, np.pi / 2)):
+        C, K = model.phase_stiffness(ph, 3, R=mandel.rotation_euler(*ang))
+        assert np.allclose(C, C0, atol=1e-14) and abs(K - K0) < 1e-14
+    R = mandel.rotation_euler(0.3, 1.1, 2.0)
+    C, K = model.phase_stiffness(ph, 3, R=R)
+    assert not np.allclose(C, C0, atol=1e-3)
+    assert np.allclose(np.linalg.eigvalsh(C), np.linalg.eigvalsh(C0), atol=1e-13)
+    assert abs(K - K0) < 1e-14
+    iso = W.iso(2.0, 0.3, 1.0)
+    assert np.allclose(model.phase_stiffness(iso, 3, R=R)[0], model.phase_stiffness(iso, 3)[0], atol=1e-14)
+
+
+def _plate_pair(layers):
+    """A 16 x 12 two-grain plate (cubic grains turned about z only, cleavage
+    normals in the plane) as a 2D problem and as a 3D grid of `layers`
+    identical layers."""
+    n2 = (16, 12)
+    rng = np.random.default_rng(8)
+    gid = (rng.random((12, 16)) < 0.5).astype(np.uint16)
+    ang = np.where(gid == 0, 0.3, 1.2)
+    void, tips = W.notch_2d(n2, 1.0, 6, 6, 10)
+    gid[void.astype(bool)] = 0
+    phases = [dict(W.cubic(1.0, 0.5, 0.6, 1.0), beta=1.5, n=(1.0, 0.0, 0.0)),
+              dict(W.cubic(1.0, 0.5, 0.3, 1.5), beta=0.5, n=(1.0, 0.0, 0.0))]
+    w2 = W.Workload(n=n2, h=1.0, ell=1.5, phases=phases, phase_id=gid, f=W.load_yy(2), dtau=0.16,
+                    theta=ang, void=void, phi_disc=tips)
+    rep = lambda a: np.ascontiguousarray(np.broadcast_to(a, (layers,) + a.shape))
+    eu = np.stack([ang, np.zeros_like(ang), np.zeros_like(ang)], axis=-1)
+    w3 = W.Workload(n=n2 + (layers,), h=1.0, ell=1.5, phases=phases, phase_id=rep(gid), f=W.load_yy(3),
+                    dtau=0.16 * layers, void=rep(void), phi_disc=rep(tips), euler=rep(eu))
+    return w2, w3
+
+
+@pytest.mark.parametrize("layers", [1, 2])
+def test_plate_equals_plane_strain(layers):
+    """Sec. 5.3 runs its polycrystals as 3D plates one voxel thick.  With
+    orientations about z only (in-plane and anti-plane parts decouple) the
+    3D plate is the 2D plane-strain problem: E and Sigma per step agree, D
+    and T scale with the thickness; two identical layers give the same as
+    one (the solution does not vary along z)."""
+    w2, w3 = _plate_pair(layers)
+    p2 = oracle_problem(w2, tol=1e-11, tol_cg=1e-13, tol_al=1e-13)
+    p3 = oracle_problem(w3, tol=1e-11, tol_cg=1e-13, tol_al=1e-13)
+    s2, s3 = solver.State(p2), solver.State(p3)
+    assert abs(s3.tau - layers * s2.tau) <= 1e-12 * s3.tau
+    for _ in range(2):
+        r2 = solver.step(p2, s2, w2.dtau)
+        r3 = solver.step(p3, s3, w3.dtau)
+        for key in ("E", "Sigma"):
+            assert abs(r3[key] - r2[key]) <= 1e-9 * abs(r2[key]), key
+        for key in ("D", "T"):
+            scale = layers if key == "D" else 1.0
+            assert abs(r3[key] - scale * r2[key]) <= 1e-9 * abs(scale * r2[key]), key
+    assert np.allclose(s3.phi[..., 0], s2.phi, atol=1e-9)

@@ -112,3 +112,20 @@ def test_weighted_voronoi_is_a_power_diagram():
         c = np.bincount(w.phase_id.ravel().astype(int), minlength=grains)
         return np.std(np.log(c[c > 0]))
     assert spread(w1) > spread(w0)
+
+
+def test_polycrystal_plate_is_z_invariant_with_3d_orientations():
+    """The plate of Sec. 5.3: identical layers along z (phase ids, Euler
+    angles, notch, enrichment points), angles in range with cos a2 spread
+    over [-1, 1], dtau per unit of the cross-section area."""
+    w = W.polycrystal_plate(n=32, layers=2, grains=40, seed=3)
+    assert w.n == (32, 32, 2) and w.euler.shape == (2, 32, 32, 3)
+    for arr in (w.phase_id, w.euler, w.void, w.phi_disc):
+        assert np.array_equal(arr[0], arr[1])
+    a1, a2, a3 = (w.euler[..., i] for i in range(3))
+    assert a1.min() >= 0 and a1.max() < 2 * np.pi and a3.min() >= 0 and a3.max() < 2 * np.pi
+    assert a2.min() >= 0 and a2.max() <= np.pi
+    c = np.cos(np.array([w.euler[0][w.phase_id[0] == g][0, 1] for g in np.unique(w.phase_id[0])]))
+    assert c.min() < -0.3 and c.max() > 0.3
+    assert w.dtau == 0.01 * 32 * 2
+    assert all(p["beta"] == 1.0 and p["n"] == (1.0, 0.0, 0.0) for p in w.phases)
