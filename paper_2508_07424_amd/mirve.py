@@ -35,7 +35,7 @@ RVE_PHASE_ISO = 0
 RVE_PHASE_CUBIC = 1
 RVE_RUN_STOP_AT_FRACTURE = 1
 WHY = {0: "none", 1: "stagger", 2: "cg", 3: "pcg", 4: "arclength", 5: "split", 6: "breakdown",
-       7: "anderson"}
+       7: "anderson", 8: "gmres", 9: "newton"}
 
 FIELDS = {"phi": 0, "hist": 1, "psi_ini": 2, "eps1": 3, "sig1": 4, "psi1": 5, "phi_ini": 6}
 
