@@ -77,9 +77,10 @@ extern "C" {
 #define RVE_WHY_GMRES     8  /* Newton step: GMRES reached max_cycles restarts      */
 #define RVE_WHY_NEWTON    9  /* Newton step: max_newton iterations without Eq. 30   */
 
-/* flags of rve_run_slots */
+/* flags of rve_run_slots and rve_run_budget */
 #define RVE_RUN_STOP_AT_FRACTURE 1  /* a slot stops after the step that reaches its
                                        fracture point (and takes none once there)   */
+#define RVE_RUN_KEEP             2  /* rve_run_budget only: see there                 */
 
 /* precision modes */
 #define RVE_PREC_FP64  0  /* every field and transform in FP64                        */
@@ -281,18 +282,30 @@ int rve_run_slots(rve_handle h, const double* dtau, const int* max_steps, int fl
                   rve_step_info* info, int* status);
 
 /* The batched form under a step budget (Eq. 16 per slot): every slot b with
- * dtau[b] > 0 takes steps of dtau[b] at its own pace until the slots
- * together have committed total_steps steps; the call then ends at the end
- * of that round, and a slot in the middle of a step returns to the state the
- * step began from (its step does not happen).  Slots that finish early keep
- * the batch busy instead of waiting for the slowest one.  A slot stops at a
- * failed step as in rve_run_slots, and with RVE_RUN_STOP_AT_FRACTURE at its
- * fracture point.  info (n_steps per slot) and status as in rve_run_slots;
- * its work counters cover the committed steps only (not the abandoned one).
- * rve_run_stats reports the call's occupancy.  Returns RVE_EINVAL for
- * total_steps < 0 or unknown flags. */
-int rve_run_budget(rve_handle h, const double* dtau, long long total_steps, int flags,
-                   rve_step_info* info, int* status);
+ * dtau[b] > 0 takes steps of dtau[b] at its own pace, at most max_steps[b]
+ * (max_steps may be NULL: no limit), until the slots together have
+ * committed total_steps steps; the call then ends at the end of that round.
+ * Slots that finish early keep the batch busy instead of waiting for the
+ * slowest one.  A slot in the middle of a step at the end:
+ *   - without RVE_RUN_KEEP returns to the state the step began from (its
+ *     step does not happen) and its work counters drop that step's work;
+ *   - with RVE_RUN_KEEP keeps the step in flight on the handle (its working
+ *     fields stay on the device; the committed state and the scalars are
+ *     those before the step).  The next rve_run_budget call with
+ *     RVE_RUN_KEEP, max_steps[b] > 0 and the same dtau[b] resumes it where it
+ *     stopped, bit for bit as if the calls had been one; the counters of each
+ *     call cover the work that call did.  Any other call that reads or
+ *     changes the slot (rve_get_*, rve_set_*, checkpoints, the stage-level
+ *     forms, rve_step_*, rve_run_slots, a budget run without the flag or
+ *     with another dtau, rve_release_slot, rve_effective_toughness*,
+ *     rve_profile_pass, rve_autotune) first returns it to the step's start,
+ *     as without the flag.
+ * A slot stops at a failed step as in rve_run_slots, and with
+ * RVE_RUN_STOP_AT_FRACTURE at its fracture point.  info (n_steps per slot)
+ * and status as in rve_run_slots.  rve_run_stats reports the call's
+ * occupancy.  Returns RVE_EINVAL for total_steps < 0 or unknown flags. */
+int rve_run_budget(rve_handle h, const double* dtau, const int* max_steps, long long total_steps,
+                   int flags, rve_step_info* info, int* status);
 
 /* Occupancy of the handle's last rve_run_slots or rve_run_budget call: out2[0] = rounds (each
  * round is one launch sequence - a mechanics solve, then one stagger

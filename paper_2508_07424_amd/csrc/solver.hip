@@ -311,6 +311,9 @@ struct SolverBase {
     virtual int dissipation(int slot, double* D, double* G) = 0;
     virtual int profile_pass(int pass, int repeat, double* bytes_per_launch) = 0;
     virtual size_t newton_workspace(int restart) const = 0;
+    // a step kept in flight by a budget run (RVE_RUN_KEEP) returns to the
+    // state it began from; slot < 0: every slot
+    virtual int drop_kept(int slot) = 0;
     virtual int newton_step(int slot, double dtau, const rve_newton_opts& o, void* ws, size_t ws_bytes,
                             rve_step_info* info) = 0;
     virtual int autotune(int repeat, int* shape_out) = 0;
@@ -1452,6 +1455,7 @@ struct Solver : SolverBase {
                            const uint8_t* disc, double phi_M) override {
         Range rg("mirve: microstructure + enrichment (Eq. 35-38)");
         if (slot < 0 || slot >= B) return fail(RVE_EINVAL, "slot out of range");
+        CHK(drop_kept(slot));
         if (!pid || !phases || nph <= 0) return fail(RVE_EINVAL, "phase_id and phases required");
         if (!(phi_M > 0.0 && phi_M < 1.0)) return fail(RVE_EINVAL, "phi_M must be in (0, 1)");
         for (int i = 0; i < nph; ++i) {
@@ -1710,6 +1714,21 @@ struct Solver : SolverBase {
         return RVE_OK;
     }
 
+    // Steps kept in flight between budget runs (RVE_RUN_KEEP): the slot's
+    // progress, with its working damage, strain and Anderson history left on
+    // the device.  Every other call that reads or changes a slot drops its
+    // kept step first.
+    std::vector<Progress> kept;
+    int drop_kept(int slot) override {
+        if (kept.empty()) return RVE_OK;
+        for (int b = 0; b < B; ++b) {
+            if ((slot >= 0 && b != slot) || kept[b].stage == 0) continue;
+            CHK(abandon_step(b, kept[b]));
+            kept[b] = Progress();
+        }
+        return RVE_OK;
+    }
+
     // A failed attempt of slot b (its working strain is already reset).
     int on_failure(int b, Progress& q, int code, int why, std::vector<int>& fresh) {
         const auto cur = q.pend.front();
@@ -1755,8 +1774,34 @@ struct Solver : SolverBase {
         Range rg("mirve: rve_run_slots");
         std::vector<Progress> P(B);
         std::vector<int> fresh(B, 0);
+        const bool keep = (flags & RVE_RUN_KEEP) && budget >= 0;
+        if (kept.empty()) kept.resize(B);
+        std::vector<int> resume(B, 0);
+        for (int b = 0; b < B; ++b) {
+            if (kept[b].stage == 0) continue;
+            const bool sf = (flags & RVE_RUN_STOP_AT_FRACTURE) != 0;
+            resume[b] = keep && todo[b] > 0 && dtau[b] == kept[b].dtau && slots[b].ready &&
+                        !(sf && slots[b].fractured);
+            if (!resume[b]) CHK(drop_kept(b));
+        }
         for (int b = 0; b < B; ++b) {
             Progress& q = P[b];
+            if (resume[b]) {
+                // the kept step goes on from where the last call left it; this
+                // call's counters start at zero.  An attempt that had not run
+                // a round yet still takes its fresh working fields.
+                q = std::move(kept[b]);
+                kept[b] = Progress();
+                if (q.stage == 1 && q.it == 0) fresh[b] = 1;
+                q.todo = todo[b];
+                q.stop_frac = (flags & RVE_RUN_STOP_AT_FRACTURE) != 0;
+                q.n_steps = q.n_sub = q.n_stag = q.n_cg = q.n_pcg = q.n_green = 0;
+                mark_counters(q);
+                q.has_last = q.pre_has_last = false;
+                q.status = RVE_OK;
+                q.reason = RVE_WHY_NONE;
+                continue;
+            }
             if (todo[b] <= 0 || dtau[b] == 0.0) continue;
             if (!slots[b].ready) { q.status = RVE_ESTATE; hd->err = "set_microstructure first"; continue; }
             if (!(dtau[b] > 0.0) || !std::isfinite(dtau[b])) {
@@ -1777,7 +1822,10 @@ struct Solver : SolverBase {
                 long long done = 0;
                 for (int b = 0; b < B; ++b) done += P[b].n_steps;
                 if (done >= budget) {
-                    for (int b = 0; b < B; ++b) CHK(abandon_step(b, P[b]));
+                    for (int b = 0; b < B; ++b) {
+                        if (keep && P[b].stage != 0) kept[b] = P[b];
+                        else CHK(abandon_step(b, P[b]));
+                    }
                     break;
                 }
             }
@@ -2080,6 +2128,7 @@ struct Solver : SolverBase {
             return fail(RVE_EINVAL, "the Newton step runs on FP64 handles only");
         } else {
             CHK(check_slot(slot));
+            CHK(drop_kept(slot));
             if (cfg.split != RVE_SPLIT_NONE) return fail(RVE_EINVAL, "the Newton step takes the law without split");
             if (!(dtau > 0.0) || !std::isfinite(dtau)) return fail(RVE_EINVAL, "dtau must be finite and > 0");
             const int m = op.restart;
@@ -2342,6 +2391,7 @@ struct Solver : SolverBase {
 
     int get_field(int slot, int which, double* hostp, size_t cnt) override {
         CHK(check_slot(slot));
+        CHK(drop_kept(slot));
         const size_t N = (size_t)g.N, sN = (size_t)g.s * g.N;
         const long long so = (long long)slot * g.N;
         switch (which) {
@@ -2366,6 +2416,7 @@ struct Solver : SolverBase {
 
     int set_field(int slot, int which, const double* hostp, size_t cnt) override {
         CHK(check_slot(slot));
+        CHK(drop_kept(slot));
         const size_t N = (size_t)g.N;
         const long long so = (long long)slot * g.N;
         if (cnt != N) return fail(RVE_EINVAL, "field size mismatch");
@@ -2388,6 +2439,7 @@ struct Solver : SolverBase {
 
     int apply_green(int slot, const double* eps, double* outp) override {
         CHK(check_slot(slot));
+        CHK(drop_kept(slot));
         const size_t sN = (size_t)g.s * g.N;
         const long long fo = (long long)slot * g.s * g.N;
         CHK(drain());
@@ -2439,6 +2491,7 @@ struct Solver : SolverBase {
 
     int solve_mechanics(int slot, int* it, double* Sigma1) override {
         CHK(check_slot(slot));
+        CHK(drop_kept(slot));
         std::vector<int> one = only(slot), its(B, 0), rcs(B, RVE_OK);
         CHK(set_mask(0, one));
         HIPCHK(launch_copy<T>(x_c, x, g.s * g.N, B, dmask[0], st));
@@ -2453,6 +2506,7 @@ struct Solver : SolverBase {
 
     int solve_damage(int slot, double E, double* D, int* it, int commit) override {
         CHK(check_slot(slot));
+        CHK(drop_kept(slot));
         std::vector<int> one = only(slot), its(B, 0), rcs(B, RVE_OK);
         std::vector<double> Ev(B, 0.0), Dv(B, 0.0);
         Ev[slot] = E;
@@ -2469,6 +2523,7 @@ struct Solver : SolverBase {
 
     int dissipation(int slot, double* D, double* G) override {
         CHK(check_slot(slot));
+        CHK(drop_kept(slot));
         CHK(set_mask(0, only(slot)));
         CHK(dissip(phi_c, 0));
         if (D) *D = sum_of(slot, 0) * hd_();
@@ -2492,6 +2547,7 @@ struct Solver : SolverBase {
     }
     int save_state(int slot, void* host, size_t bytes) override {
         CHK(check_slot(slot));
+        CHK(drop_kept(slot));
         if (!host || bytes < state_bytes()) return fail(RVE_EINVAL, "state buffer too small");
         StateHeader hdr;
         std::memset(&hdr, 0, sizeof(hdr));
@@ -2512,6 +2568,7 @@ struct Solver : SolverBase {
     }
     int load_state(int slot, const void* host, size_t bytes) override {
         CHK(check_slot(slot));
+        CHK(drop_kept(slot));
         if (!host || bytes < state_bytes()) return fail(RVE_EINVAL, "state buffer too small");
         StateHeader hdr;
         std::memcpy(&hdr, host, sizeof(hdr));
@@ -2608,6 +2665,7 @@ struct Solver : SolverBase {
     // lines per block of the y pass, y columns per tile of the z pass.  The
     // choice is cached per (grid, batch, precision) for the process.
     int autotune(int repeat, int* out) override {
+        CHK(drop_kept(-1));
         bool ready = false;
         for (int b = 0; b < B; ++b) ready = ready || slots[b].ready;
         if (!ready) return fail(RVE_ESTATE, "set_microstructure first");
@@ -2712,6 +2770,7 @@ struct Solver : SolverBase {
     // CG updates of x and p, 4: x-inverse with the CG update of r (alpha = 0,
     // so the iterate is unchanged).
     int profile_pass(int pass, int repeat, double* bytes) override {
+        CHK(drop_kept(-1));
         std::vector<int> rd(B, 0);
         int nready = 0;
         for (int b = 0; b < B; ++b) { rd[b] = slots[b].ready ? 1 : 0; nready += rd[b]; }
@@ -3007,13 +3066,15 @@ int rve_run_stats(rve_handle h, double* out2) {
     return RVE_OK;
 }
 
-int rve_run_budget(rve_handle h, const double* dtau, long long total_steps, int flags,
+int rve_run_budget(rve_handle h, const double* dtau, const int* max_steps, long long total_steps, int flags,
                    rve_step_info* info, int* status) {
     if (!h || !dtau) return RVE_EINVAL;
-    if (flags & ~RVE_RUN_STOP_AT_FRACTURE) { h->err = "unknown flags"; return RVE_EINVAL; }
+    if (flags & ~(RVE_RUN_STOP_AT_FRACTURE | RVE_RUN_KEEP)) { h->err = "unknown flags"; return RVE_EINVAL; }
     if (total_steps < 0) { h->err = "total_steps must be >= 0"; return RVE_EINVAL; }
     const int B = h->impl->B;
     std::vector<int> todo(B, 1 << 30);
+    if (max_steps)
+        for (int b = 0; b < B; ++b) todo[b] = max_steps[b];
     return h->impl->run(dtau, todo.data(), flags, info, status, total_steps);
 }
 
@@ -3080,6 +3141,7 @@ int rve_step_dissipation_batch(rve_handle* hs, int count, const double* dtau,
 
 int rve_effective_toughness_slot(rve_handle h, int slot, double* G) {
     if (!h || !G || slot < 0 || slot >= h->impl->B) return RVE_EINVAL;
+    if (int rc = h->impl->drop_kept(slot)) return rc;
     const SlotState& s = h->impl->slots[slot];
     if (!s.ready) { h->err = "set_microstructure first"; return RVE_ESTATE; }
     if (!s.fractured) { h->err = "fracture point not reached"; return RVE_ENOTDONE; }
@@ -3120,6 +3182,7 @@ int rve_load_state(rve_handle h, int slot, const void* host, size_t bytes) {
 
 int rve_get_scalars_slot(rve_handle h, int slot, double* o) {
     if (!h || !o || slot < 0 || slot >= h->impl->B) return RVE_EINVAL;
+    if (int rc = h->impl->drop_kept(slot)) return rc;
     const SlotState& s = h->impl->slots[slot];
     o[0] = s.E;
     o[1] = s.Sigma;
@@ -3142,6 +3205,7 @@ int rve_set_scalars_slot(rve_handle h, int slot, const double* in) {
     if (!h || !in || slot < 0 || slot >= h->impl->B) return RVE_EINVAL;
     for (int i = 0; i < 6; ++i)
         if (!std::isfinite(in[i])) return RVE_EINVAL;
+    if (int rc = h->impl->drop_kept(slot)) return rc;
     SlotState& s = h->impl->slots[slot];
     s.E = in[0];
     s.Sigma = in[1];
@@ -3155,6 +3219,7 @@ int rve_set_scalars(rve_handle h, const double* in) { return rve_set_scalars_slo
 
 int rve_release_slot(rve_handle h, int slot) {
     if (!h || slot < 0 || slot >= h->impl->B) return RVE_EINVAL;
+    if (int rc = h->impl->drop_kept(slot)) return rc;
     h->impl->slots[slot] = SlotState();
     return RVE_OK;
 }

@@ -34,6 +34,7 @@ RVE_PRECOND_JACOBI = 1
 RVE_PHASE_ISO = 0
 RVE_PHASE_CUBIC = 1
 RVE_RUN_STOP_AT_FRACTURE = 1
+RVE_RUN_KEEP = 2
 WHY = {0: "none", 1: "stagger", 2: "cg", 3: "pcg", 4: "arclength", 5: "split", 6: "breakdown",
        7: "anderson", 8: "gmres", 9: "newton"}
 
@@ -115,7 +116,8 @@ def _load():
         "rve_load_state": (I, [P, I, P, S]),
         "rve_batch_size": (I, [P]),
         "rve_run_stats": (I, [P, dp]),
-        "rve_run_budget": (I, [P, dp, C.c_longlong, I, C.POINTER(rve_step_info), C.POINTER(C.c_int)]),
+        "rve_run_budget": (I, [P, dp, C.POINTER(C.c_int), C.c_longlong, I, C.POINTER(rve_step_info),
+                               C.POINTER(C.c_int)]),
         "rve_newton_default_opts": (None, [C.POINTER(rve_newton_opts)]),
         "rve_set_microstructure_euler": (I, [P, I, P, C.POINTER(rve_phase), I, P, P, P, D]),
         "rve_newton_workspace": (I, [P, I, C.POINTER(C.c_size_t)]),
@@ -308,15 +310,21 @@ class Rve:
                           RVE_RUN_STOP_AT_FRACTURE if stop_at_fracture else 0, infos, status)
         return [infos[i].as_dict() for i in range(self.B)], [status[i] for i in range(self.B)]
 
-    def rve_run_budget(self, dtaus, total_steps, stop_at_fracture=False):
+    def rve_run_budget(self, dtaus, total_steps, stop_at_fracture=False, keep=False, max_steps=None):
         """Steps at each slot's own pace until the slots together committed
-        total_steps.  Returns (infos, status)."""
+        total_steps (keep: steps in flight at the end stay for the next
+        keep call).  Returns (infos, status)."""
         dt = np.ascontiguousarray(dtaus, dtype=np.float64)
         assert dt.size == self.B
+        ms = None
+        if max_steps is not None:
+            ms = np.ascontiguousarray(max_steps, dtype=np.int32)
+            assert ms.size == self.B
         infos = (rve_step_info * self.B)()
         status = (C.c_int * self.B)()
-        lib.rve_run_budget(self.h, _dptr(dt), int(total_steps),
-                           RVE_RUN_STOP_AT_FRACTURE if stop_at_fracture else 0, infos, status)
+        flags = (RVE_RUN_STOP_AT_FRACTURE if stop_at_fracture else 0) | (RVE_RUN_KEEP if keep else 0)
+        lib.rve_run_budget(self.h, _dptr(dt), None if ms is None else ms.ctypes.data_as(C.POINTER(C.c_int)),
+                           int(total_steps), flags, infos, status)
         return [infos[i].as_dict() for i in range(self.B)], [status[i] for i in range(self.B)]
 
     def rve_step_newton(self, dtau, slot=0, **opts):

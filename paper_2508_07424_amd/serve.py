@@ -9,12 +9,15 @@ its own HIP stream and its fields resident in HBM.  Every scheduler tick:
      of their class, or open a new pool if its workspace
      (rve_query_workspace for its slot count) fits the HBM budget beside
      the pools already open; otherwise they wait (an admission stall);
-  2. all pools with occupied slots advance those slots by up to
-     steps_per_tick dissipation-controlled steps (Eq. 16) in one
-     rve_run_slots call, concurrently on their streams; slots of one pool
-     are at different steps and within a call each goes at its own pace (a
-     step that fails is halved inside the library, and a step that still
-     fails leaves the slot's state as it was and ends the request);
+  2. all pools with occupied slots advance them in one rve_run_budget call
+     each, concurrently on their streams: the pool's slots take
+     dissipation-controlled steps (Eq. 16) at their own pace until they
+     have committed steps_per_tick steps per occupied slot together (a fast
+     request takes more steps than a slow one), and a step still in flight
+     at the end of the call stays on the device for the next tick
+     (RVE_RUN_KEEP); a step that fails is halved inside the library, and a
+     step that still fails leaves the slot's state as it was and ends the
+     request;
   3. a slot whose RVE has reached the fracture point yields G_eff
      (Eq. 32-33), records its latency and is released for the next request;
      pools left empty are closed when memory is needed.
@@ -98,9 +101,9 @@ class Pool:
 
     def step(self, steps_per_tick):
         dt = [float(r.workload.dtau) if r is not None else 0.0 for r in self.req]
-        todo = [min(steps_per_tick, r.max_steps - s) if r is not None else 0
-                for r, s in zip(self.req, self.steps)]
-        return self.rve.rve_run_slots(dt, todo, stop_at_fracture=True)
+        caps = [r.max_steps - s if r is not None else 0 for r, s in zip(self.req, self.steps)]
+        return self.rve.rve_run_budget(dt, steps_per_tick * self.occupied(), stop_at_fracture=True,
+                                       keep=True, max_steps=caps)
 
     def close(self):
         self.rve.close()

@@ -216,4 +216,79 @@ def test_run_budget_ends_on_committed_states(case):
     if case == "halving":
         assert split > 0, "no step split: the case does not reach the sub-step path"
     with pytest.raises(RuntimeError):
-        batch._chk(mirve.lib.rve_run_budget(batch.h, mirve._dptr(np.array(dt)), -1, 0, None, None))
+        batch._chk(mirve.lib.rve_run_budget(batch.h, mirve._dptr(np.array(dt)), None, -1, 0, None, None))
+
+
+@pytest.mark.parametrize("case", ["plain", "halving"])
+def test_run_budget_keep_resumes_steps_in_flight(case):
+    """RVE_RUN_KEEP: budget calls of one step each leave the slots' steps in
+    flight on the handle, and the next keep call resumes them.  A last keep
+    call with max_steps = 1 lets every slot finish the step it is in.  Each
+    slot then holds bitwise the state of the same RVE stepped alone as many
+    times, and the work counters summed over the calls equal the lone RVE's
+    (nothing counted twice, nothing dropped).  A read of the scalars in
+    between returns the slots to their steps' starts; the next keep call
+    begins those steps again."""
+    from paper_2508_07424_amd import mirve
+    ws = _three()
+    kw = {}
+    for w in ws:
+        w.f = W.load_yy(2)
+        if case == "halving":
+            w.dtau = 2.0 * w.dtau
+    if case == "halving":
+        kw = dict(max_stagger=6)
+    dt = [w.dtau for w in ws]
+    keys = ("n_cg", "n_pcg", "n_stagger", "n_greenop", "n_substeps", "n_steps")
+    batch = mirve.from_workloads(ws, **kw)
+    tot = [dict.fromkeys(keys, 0) for _ in ws]
+
+    def add(infos):
+        for i, info in enumerate(infos):
+            for key in keys:
+                tot[i][key] += info[key]
+
+    for call in range(6 if case == "plain" else 3):
+        infos, st = batch.rve_run_budget(dt, 1, keep=True)
+        assert st == [0, 0, 0], st
+        add(infos)
+        print("keep call", call, "steps", [i["n_steps"] for i in infos], flush=True)
+    infos, last = batch.rve_run_budget(dt, 100, keep=True, max_steps=[1, 1, 1])
+    add(infos)
+    for i, w in enumerate(ws):
+        # the lone RVE takes the same steps; a step that fails for good (the
+        # halving case can exhaust its halvings) fails there too, with the
+        # same work and the same state left behind
+        r = mirve.from_workload(w, max_materials=4096, **kw)
+        ref = dict.fromkeys(keys, 0)
+        for k in range(tot[i]["n_steps"] + (0 if last[i] == 0 else 1)):
+            one, s1 = r.rve_run_slots([w.dtau], [1])
+            for key in keys:
+                ref[key] += one[0][key]
+        assert s1[0] == last[i], (i, s1, last)
+        print("rve", i, "status", last[i], "batch", tot[i], "alone", ref, flush=True)
+        assert tot[i] == ref, (i, tot[i], ref)
+        sb, sa = batch.rve_get_scalars(slot=i), r.rve_get_scalars()
+        for key in ("E", "Sigma", "T", "tau", "step"):
+            assert sb[key] == sa[key], (i, key)
+        assert np.array_equal(batch.rve_get_field("phi", slot=i), r.rve_get_field("phi"))
+        assert np.array_equal(batch.rve_get_field("hist", slot=i), r.rve_get_field("hist"))
+    if case != "plain":
+        return
+    # a read between keep calls drops the steps in flight: the slots restart
+    # them, and stay on the lone RVEs' path
+    nsteps = [t["n_steps"] for t in tot]
+    for _ in range(3):
+        batch.rve_get_scalars(slot=_)
+    infos, _st = batch.rve_run_budget(dt, 1, keep=True)
+    nsteps = [n + i["n_steps"] for n, i in zip(nsteps, infos)]
+    for i in range(3):
+        batch.rve_get_scalars(slot=i)
+    infos, st = batch.rve_run_budget(dt, 100, keep=True, max_steps=[1, 1, 1])
+    nsteps = [n + i["n_steps"] for n, i in zip(nsteps, infos)]
+    for i, w in enumerate(ws):
+        r = mirve.from_workload(w, max_materials=4096, **kw)
+        for _ in range(nsteps[i]):
+            r.rve_step_dissipation(w.dtau)
+        assert batch.rve_get_scalars(slot=i)["step"] == r.rve_get_scalars()["step"]
+        assert np.array_equal(batch.rve_get_field("phi", slot=i), r.rve_get_field("phi"))
