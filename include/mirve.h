@@ -419,7 +419,10 @@ int rve_apply_green_op_device_noalloc(rve_handle h, const void* eps_dev, void* o
  * n_greenop the Green-operator applications. */
 typedef struct rve_newton_opts {
     double tol;          /* Eq. 30 tolerance; <= 0: the handle's tol               */
-    double krylov_tol;   /* relative residual of each GMRES solve (1e-12)           */
+    double krylov_tol;   /* relative residual of each GMRES solve (1e-12); a restart
+                            cycle that no longer halves the residual ends the solve
+                            once it is below sqrt(krylov_tol) (rounding floor near
+                            Newton's solution)                                    */
     double theta;        /* lower bound of the relaxation factor (0.3)              */
     int    restart;      /* GMRES restart length, 1..1000 (200)                     */
     int    max_cycles;   /* GMRES restart cycles per Newton system (100)            */

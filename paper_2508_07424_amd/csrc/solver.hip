@@ -780,6 +780,11 @@ struct Solver : SolverBase {
     // x-forward pass of k + 1, for x); the x-inverse pass writes r.r into
     // cgpB, read by the next x-forward pass.
     double* pap_slot(int k) const { return (k & 1) ? cgpC : cgpA; }
+    // material override of the x-forward pass: ov_mat[ov_mid[i]] for every
+    // slot (the Newton step's projection P = Gamma0[I:], with a table whose
+    // one entry is the identity)
+    const uint16_t* ov_mid = nullptr;
+    const MatEntry<T>* ov_mat = nullptr;
     int fwd_x(int mode, const T* phi, const T* eps, double fcoef, double* part, const int* mask,
               int iter = 0, T* xsol = nullptr) {
         XfwdArgs<T> a;
@@ -789,6 +794,11 @@ struct Solver : SolverBase {
         a.tw = tw + plx.tw_off;
         a.mat_id = mat_id;
         a.mat = mat;
+        if (ov_mat) {               // one material for every voxel (the projection)
+            a.mat_id = ov_mid;
+            a.mat = ov_mat;
+            a.g.mstride = 0;
+        }
         a.phi = phi;
         a.eps = eps;
         a.fcoef = T(fcoef);
@@ -2108,13 +2118,15 @@ struct Solver : SolverBase {
         const long long n = (long long)(g.s + 1) * g.N + 1;
         return (n + 31) / 32 * 32;
     }
-    // workspace: V (m + 1 vectors), b, dq, J dq, the dot-product partials, the Gram-Schmidt coefficients (two passes), the
+    // workspace: V (m + 1 vectors), b, dq, J dq, the projected argument of J,
+    // the dot-product partials, the Gram-Schmidt coefficients (two passes), the
     // least-squares solution, the update norms, then the rotated Hessenberg
     // columns, the rotations, the rotated right-hand side and the residual
     // estimates
-    static size_t nr_doubles(long long ld, int m) {
-        return (size_t)(m + 4) * ld + (size_t)(m + 5) * 64 + 3 * (size_t)(m + 2) + 8 +
-               (size_t)(m + 1) * m + 2 * (size_t)m + (size_t)(m + 1) + (size_t)m;
+    size_t nr_doubles(long long ld, int m) const {
+        return (size_t)(m + 5) * ld + (size_t)(m + 5) * 64 + 3 * (size_t)(m + 2) + 8 +
+               (size_t)(m + 1) * m + 2 * (size_t)m + (size_t)(m + 1) + (size_t)m +
+               (sizeof(MatEntry<double>) + 7) / 8 + ((size_t)B * g.N * sizeof(uint16_t) + 7) / 8;
     }
     size_t newton_workspace(int m) const override {
         if (m < 1) return 0;
@@ -2154,6 +2166,9 @@ struct Solver : SolverBase {
             double* snd = csd + m;
             double* gvd = snd + m;
             double* est = gvd + (m + 1);
+            double* pv = est + m;                  // [P v_x, v_phi, v_E] (ld doubles)
+            MatEntry<T>* idm = reinterpret_cast<MatEntry<T>*>(pv + ld);
+            uint16_t* zid = reinterpret_cast<uint16_t*>(pv + ld + (sizeof(MatEntry<double>) + 7) / 8);
             double* xs = x + b * sN;
             double* ph = phi_w + b * N;
             double* Hb = H + b * N;
@@ -2166,6 +2181,16 @@ struct Solver : SolverBase {
             CHK(set_mask(0, only(b)));
             HIPCHK(launch_copy<T>(phi_c, phi_w, N, B, dmask[0], st));
             HIPCHK(launch_fill<T>(pz, T(0), N, B, dmask[0], st));
+            {   // the identity material (reference medium of P) for every voxel
+                MatEntry<T> me;
+                std::memset(&me, 0, sizeof(me));
+                for (int a = 0; a < g.s; ++a) me.C[a * g.s + a] = T(1);
+                me.K = T(1.0 / 3.0);
+                me.Gc = T(1);
+                me.drive = T(1);
+                CHK(upload_bytes(idm, &me, sizeof(me)));
+                HIPCHK(launch_zero_int(reinterpret_cast<int*>(zid), (int)(((long long)B * N * 2 + 3) / 4), st));
+            }
             rve_step_info o;
             std::memset(&o, 0, sizeof(o));
             auto give_up = [&](int code, int why, const char* msg) {
@@ -2233,6 +2258,20 @@ struct Solver : SolverBase {
                                       tau - D, st));
                 return RVE_OK;
             };
+            // outx = P vx, the projection on compatible strains: the Green
+            // operator of the identity material at phi = 0, divided by g(0)
+            auto project = [&](const double* vx, double* outx) -> int {
+                HIPCHK(launch_axpby(sN, 1.0, vx, 0.0, r + b * sN, st));
+                ov_mid = zid;
+                ov_mat = idm;
+                const int rc = green(pz, r, 0.0, p, inv_g0, cgpB, dmask[0]);
+                ov_mid = nullptr;
+                ov_mat = nullptr;
+                CHK(rc);
+                step_greens[b] += 1;
+                HIPCHK(launch_axpby(sN, 1.0, p + b * sN, 0.0, outx, st));
+                return RVE_OK;
+            };
             // out = J(q) v (Eq. 25)
             auto jac = [&](const double* v, double* out) -> int {
                 HIPCHK(launch_nr_jac_point(a, v, inv_g0, r + b * sN, pp + b * N, pb + b * N, st));
@@ -2246,9 +2285,26 @@ struct Solver : SolverBase {
                                       sums + (long long)b * kMaxVals, hd, 0.0, st));
                 return RVE_OK;
             };
+            // the operator of the Newton systems: J on the compatible part of
+            // the strain, the identity on the rest (J alone is singular on the
+            // full strain space: J1 sees only the compatible part)
+            auto jac_full = [&](const double* v, double* out) -> int {
+                CHK(project(v, pv));
+                HIPCHK(launch_axpby(N + 1, 1.0, v + sN, 0.0, pv + sN, st));
+                CHK(jac(pv, out));
+                HIPCHK(launch_axpby(sN, 1.0, v, 1.0, out, st));
+                HIPCHK(launch_axpby(sN, -1.0, pv, 1.0, out, st));
+                return RVE_OK;
+            };
             // restarted GMRES for J dq = bv from dq = 0: classical Gram-Schmidt
             // with one reorthogonalization, the Givens rotations on the device;
-            // the host reads the residual estimates every kChunk iterations
+            // the host reads the residual estimates every kChunk iterations.
+            // Converged at a true residual <= krylov_tol |bv|; near Newton's
+            // solution |bv| is so small that the rounding of the Jacobian
+            // products sets a floor above that, so a restart cycle that no
+            // longer halves the true residual ends the solve too, if the
+            // residual is below sqrt(krylov_tol) |bv| (the Newton test of
+            // Eq. 30 still decides convergence).
             constexpr int kChunk = 8;
             std::vector<double> estv(kChunk);
             auto gmres = [&](int& iters, bool& ok) -> int {
@@ -2260,12 +2316,13 @@ struct Solver : SolverBase {
                 const double bn = std::sqrt(bn2);
                 if (!std::isfinite(bn)) return RVE_OK;
                 if (bn == 0.0) { ok = true; return RVE_OK; }
+                double prev = INFINITY;
                 for (int cyc = 0; cyc <= op.max_cycles; ++cyc) {
                     // V_0 = bv - J dq (the true residual of the current dq)
                     if (cyc == 0) {
                         HIPCHK(launch_axpby(n, 1.0, bv, 0.0, V, st));
                     } else {
-                        CHK(jac(dq, tv));
+                        CHK(jac_full(dq, tv));
                         HIPCHK(launch_axpby(n, 1.0, bv, 0.0, V, st));
                         HIPCHK(launch_axpby(n, -1.0, tv, 1.0, V, st));
                     }
@@ -2273,8 +2330,11 @@ struct Solver : SolverBase {
                     HIPCHK(launch_mdot(V, ld, 1, V, n, part, hA, st));
                     CHK(read(hA, &beta2, 1));
                     const double beta = std::sqrt(beta2);
+                    if (trace) std::fprintf(stderr, "gmres cycle %d residual %.3e\n", cyc, beta / bn);
                     if (!std::isfinite(beta)) return RVE_OK;
                     if (beta <= op.krylov_tol * bn) { ok = true; return RVE_OK; }
+                    if (beta > 0.5 * prev && beta <= std::sqrt(op.krylov_tol) * bn) { ok = true; return RVE_OK; }
+                    prev = beta;
                     if (cyc == op.max_cycles) return RVE_OK;
                     HIPCHK(launch_gmres_start(gvd, m, hA, st));
                     HIPCHK(launch_unit_scale(V, n, hA, st));
@@ -2284,7 +2344,7 @@ struct Solver : SolverBase {
                         const int j1 = std::min(m, j0 + kChunk);
                         for (int j = j0; j < j1; ++j) {
                             double* vj1 = V + (long long)(j + 1) * ld;
-                            CHK(jac(V + (long long)j * ld, vj1));
+                            CHK(jac_full(V + (long long)j * ld, vj1));
                             HIPCHK(launch_mdot(V, ld, j + 1, vj1, n, part, hA, st));
                             HIPCHK(launch_maxpy(V, ld, j + 1, hA, -1.0, vj1, n, st));
                             HIPCHK(launch_mdot(V, ld, j + 1, vj1, n, part, hB, st));
@@ -2318,6 +2378,7 @@ struct Solver : SolverBase {
                     o.n_stagger = it; o.n_cg += nkry;
                     return give_up(RVE_ENOCONV, RVE_WHY_GMRES, "GMRES of a Newton system did not converge");
                 }
+                CHK(project(dq, dq));      // the strain update is compatible
                 double dEh = 0.0;
                 CHK(read(dq + sN + N, &dEh, 1));
                 const double En = E + alpha * dEh;
