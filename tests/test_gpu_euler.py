@@ -93,3 +93,28 @@ def test_euler_input_is_checked():
         r.rve_set_microstructure_euler(w.phase_id, w.phases, bad, void=w.void, phi_disc=w.phi_disc)
     assert e.value.code == m.RVE_EINVAL
     assert r.rve_get_scalars()["step"] == 0
+
+
+def test_euler_on_a_2d_grid():
+    """A 2D (plane-strain) grid takes the in-plane block of the stiffness and
+    of the cleavage tensor rotated by general Euler angles: the Green
+    operator, the initial state and two steps against the oracle."""
+    from paper_2508_07424_amd import mirve as m
+    w = W.polycrystal_2d(n=32, grains=8, seed=6, zener=3.0, a_cleave=1.0, beta=2.0)
+    rng = np.random.default_rng(2)
+    ang = np.stack([rng.uniform(0, 2 * np.pi, 8), np.arccos(rng.uniform(-1, 1, 8)),
+                    rng.uniform(0, 2 * np.pi, 8)], axis=-1)
+    w.euler = ang[w.phase_id]
+    w.theta = None
+    r = m.from_workload(w, **TIGHT)
+    prob = oracle_problem(w, **OTIGHT)
+    st = solver.State(prob)
+    eps = np.random.default_rng(5).standard_normal((3,) + w.shape)
+    sig = model.stress(to_oracle(eps, 2), st.phi, prob.mat)
+    assert rel(r.rve_apply_green_op(eps), prob.to_public(spectral.green_apply(sig, prob.P))) < 1e-12
+    assert rel(r.rve_get_field("phi_ini"), prob.to_public(st.phi_ini)) < 1e-11
+    for k in range(2):
+        info = r.rve_step_dissipation(w.dtau)
+        rec = solver.step(prob, st, w.dtau)
+        for key in ("E", "Sigma", "D", "T"):
+            assert abs(info[key] - rec[key]) <= 1e-10 * abs(rec[key]), (k, key)
