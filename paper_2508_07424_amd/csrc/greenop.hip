@@ -658,6 +658,152 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
+// one-wave axis pass: forward, per-frequency operator, inverse along y
+// ---------------------------------------------------------------------------
+//
+// For contiguous lines of N = 64 R points (R = 4: 256, R = 8: 512) one wave
+// owns one line position for all S components, so the block needs no
+// barrier.  Each line is a radix-R Stockham FFT of P = log_R N passes with
+// one butterfly per lane: in the pass of span p, butterfly i = lane (with
+// k = i mod p) reads x[i + 64 t], t < R, multiplies element t by
+// w_{pR}^{t k}, takes an R-point DFT and writes y[(i - k) R + k + t p].  The
+// first pass reads x[lane + 64 t] straight from HBM (coalesced); between
+// passes the line goes through the wave's own LDS region; after the last
+// pass (p = 64) output t of a lane is X[lane + 64 t], so the lane holds the
+// same frequencies of every component and the projection (or the damage
+// preconditioner) is applied in registers.  The inverse runs the same
+// passes with conjugate twiddles starting from that layout and ends in the
+// load layout, so the store is coalesced too.
+
+// Orders the LDS accesses of the lanes of one wave (no block barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int N>
+struct WaveRadix;
+template <> struct WaveRadix<256> { static constexpr int R = 4, P = 4; };
+template <> struct WaveRadix<512> { static constexpr int R = 8, P = 3; };
+
+template <typename T, int N>
+__device__ __forceinline__ void wave_dft_r(cplx<T> (&v)[WaveRadix<N>::R], bool inv) {
+    if constexpr (WaveRadix<N>::R == 8) dft8(v, inv);
+    else dft4(v[0], v[1], v[2], v[3], inv);
+}
+
+// In-place line FFT of the calling wave: v[t] = x[lane + 64 t] in and
+// X[lane + 64 t] out; wtw[s - 1][t - 1] = w_{p R}^{t k} of pass s >= 1
+// (forward sign); lds = the wave's region of lds_line(N) entries.
+template <typename T, int N>
+__device__ __forceinline__ void wave_line_fft(cplx<T> (&v)[WaveRadix<N>::R],
+                                              const cplx<T> (&wtw)[WaveRadix<N>::P - 1][WaveRadix<N>::R - 1],
+                                              cplx<T>* lds, int lane, bool inv) {
+    constexpr int R = WaveRadix<N>::R, P = WaveRadix<N>::P;
+    int p = 1;
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+        if (s > 0) {
+#pragma unroll
+            for (int t = 1; t < R; ++t) {
+                const cplx<T> w = wtw[s - 1][t - 1], u = v[t];
+                v[t] = inv ? cplx<T>{u.x * w.x + u.y * w.y, u.y * w.x - u.x * w.y}   // u conj(w)
+                           : cplx<T>{u.x * w.x - u.y * w.y, u.y * w.x + u.x * w.y};
+            }
+        }
+        wave_dft_r<T, N>(v, inv);
+        if (s < P - 1) {
+            const int k = lane & (p - 1);
+            const int base = (lane - k) * R + k;
+            wave_lds_sync();                      // earlier reads of the region are done
+#pragma unroll
+            for (int t = 0; t < R; ++t) lds[lp(base + t * p)] = v[t];
+            wave_lds_sync();
+#pragma unroll
+            for (int t = 0; t < R; ++t) v[t] = lds[lp(lane + 64 * t)];
+        }
+        p *= R;
+    }
+}
+
+// MODE: AX_FWD_P_INV (S = 3 or 6, projection) or AX_FWD_M_INV (S = 1,
+// damage preconditioner).  Four waves per block, one line position each.
+template <typename T, int S, int MODE, int N>
+__global__ void __launch_bounds__(256) k_axis_wave(AxisArgs<T> a) {
+    constexpr int R = WaveRadix<N>::R, P = WaveRadix<N>::P;
+    extern __shared__ unsigned char smem_raw[];
+    const Geom& g = a.g;
+    const int b = blockIdx.z;
+    if (a.cg && a.cg[b].conv <= a.iter) return;
+    if (a.pcg && a.pcg[b].conv <= a.iter) return;
+    if (a.active && !a.active[b]) return;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const long long L = (long long)blockIdx.x * (blockDim.x >> 6) + wv;   // L = kx * nz + z
+    const long long nlines = (long long)g.nxh * g.nz;
+    if (L >= nlines) return;                      // whole waves only: no barrier follows
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw) + wv * lds_line(N);
+    cplx<T>* sp = a.spec + (long long)b * S * g.Nspec + L * N;   // n_y == N
+
+    cplx<T> v[S][R];
+#pragma unroll
+    for (int c = 0; c < S; ++c)
+#pragma unroll
+        for (int t = 0; t < R; ++t) v[c][t] = sp[(long long)c * g.Nspec + lane + 64 * t];
+
+    // twiddles of passes 1 .. P-1: span p = R^s, k = lane mod p,
+    // w_{pR}^{t k} = tw[t k N / (p R)] with tw[m] = exp(-2 pi i m / N)
+    cplx<T> wtw[P - 1][R - 1];
+    {
+        int p = R;
+#pragma unroll
+        for (int s = 1; s < P; ++s) {
+            const int k = lane & (p - 1);
+            const int stride = N / (p * R);
+#pragma unroll
+            for (int t = 1; t < R; ++t) wtw[s - 1][t - 1] = a.tw[t * k * stride];
+            p *= R;
+        }
+    }
+
+#pragma unroll
+    for (int c = 0; c < S; ++c) wave_line_fft<T, N>(v[c], wtw, lds, lane, false);
+
+    const int kx = (int)(L / g.nz), kz = (int)(L - (long long)kx * g.nz);
+    if constexpr (MODE == AX_FWD_P_INV) {
+        const T rN[3] = {T(1) / T(g.nx), T(1) / T(g.ny), T(1) / T(g.nz)};
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            T fx[3], fy[3];
+            freq_xy<T>(g, kx, lane + 64 * t, kz, rN, fx, fy);
+            cplx<T> u[S];
+#pragma unroll
+            for (int c = 0; c < S; ++c) u[c] = v[c][t];
+            if constexpr (S == 3) project2<T>(u, fx, fy);
+            else project3<T>(u, fx, fy);
+#pragma unroll
+            for (int c = 0; c < S; ++c) v[c][t] = u[c];
+        }
+    } else {
+        const double abar = a.pcg[b].abar, bbar = a.pcg[b].bbar;
+#pragma unroll
+        for (int t = 0; t < R; ++t) {
+            const T m = precond_symbol<T>(g, a.dsq, kx, lane + 64 * t, kz, abar, bbar);
+            v[0][t].x *= m;
+            v[0][t].y *= m;
+        }
+    }
+
+#pragma unroll
+    for (int c = 0; c < S; ++c) wave_line_fft<T, N>(v[c], wtw, lds, lane, true);
+#pragma unroll
+    for (int c = 0; c < S; ++c)
+#pragma unroll
+        for (int t = 0; t < R; ++t) sp[(long long)c * g.Nspec + lane + 64 * t] = v[c][t];
+}
+
+// ---------------------------------------------------------------------------
 // x-inverse pass
 // ---------------------------------------------------------------------------
 
@@ -872,10 +1018,28 @@ static hipError_t launch_axis_s(const AxisArgs<T>& a, int maxb, dim3 grid, size_
     MIRVE_DISPATCH(k_axis, T, S, MODE, false, a.pl, maxb, grid, lds, st, a);
 }
 
+// Contiguous lines of 256 or 512 points with a per-frequency operator go
+// to the one-wave pass (grid, block and LDS of its own).
+template <typename T, int S, int MODE>
+static hipError_t launch_axis_wave(const AxisArgs<T>& a, hipStream_t st) {
+    constexpr int W = 4;                       // waves per block
+    const long long nlines = (long long)a.g.nxh * a.g.nz;
+    const dim3 grid((unsigned)((nlines + W - 1) / W), 1, a.g.B);
+    const int N = a.g.ny;
+    const size_t lds = (size_t)W * lds_line(N) * sizeof(cplx<T>);
+    if (N == 512) hipLaunchKernelGGL((k_axis_wave<T, S, MODE, 512>), grid, dim3(64 * W), lds, st, a);
+    else hipLaunchKernelGGL((k_axis_wave<T, S, MODE, 256>), grid, dim3(64 * W), lds, st, a);
+    return hipGetLastError();
+}
+
 // The damage preconditioner (a.pcg set) transforms one scalar field.
 template <typename T>
 hipError_t launch_axis(const AxisArgs<T>& a, int mode, int maxb, dim3 grid, size_t lds,
                        hipStream_t st) {
+    if (a.contiguous && (a.g.ny == 256 || a.g.ny == 512) && a.pl.N == a.g.ny) {
+        if (a.pcg && mode == AX_FWD_M_INV) return launch_axis_wave<T, 1, AX_FWD_M_INV>(a, st);
+        if (!a.pcg && a.g.s == 3 && mode == AX_FWD_P_INV) return launch_axis_wave<T, 3, AX_FWD_P_INV>(a, st);
+    }
     if (a.pcg) {
         switch (mode) {
             case AX_FWD: return launch_axis_s<T, 1, AX_FWD>(a, maxb, grid, lds, st);

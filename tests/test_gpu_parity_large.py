@@ -48,6 +48,7 @@ def _random_rve(n, seed):
 CASES = [
     ("FastFFT<256>x<256>", (256, 256)),
     ("FastFFT<512>x<64>", (512, 64)),
+    ("FastFFT<64>x<512>", (64, 512)),
     ("FastFFT<1024>x<16>", (1024, 16)),
     ("FastFFT<128>x<32>x<16>", (128, 32, 16)),
     ("FastFFT<16>x<16>x<128>", (16, 16, 128)),
@@ -87,7 +88,10 @@ def test_green_op_at_bench_line_lengths(name, n, prec):
         assert _elementwise(phi_ini, prob.to_public(st.phi_ini)) < 1e-11
 
 
-@pytest.mark.parametrize("name,n", [CASES[0], CASES[1]], ids=[CASES[0][0], CASES[1][0]])
+MECH = [CASES[0], CASES[1], CASES[2]]
+
+
+@pytest.mark.parametrize("name,n", MECH, ids=[c[0] for c in MECH])
 def test_mechanics_fp64_at_bench_line_lengths(name, n):
     """The mechanics CG (fused x-forward / axis / x-inverse passes with the
     Krylov updates) at 256 and 512 points per line, against the oracle's CG
@@ -106,3 +110,32 @@ def test_mechanics_fp64_at_bench_line_lengths(name, n):
     print("cg iterations gpu", it, "oracle", it_o, "max-rel %.3e" % e_max, flush=True)
     assert e_max < 1e-10
     assert abs(S1 - S1_o) <= 1e-10 * abs(S1_o)
+
+
+DAMAGE = [CASES[0], CASES[2]]
+
+
+@pytest.mark.parametrize("name,n", DAMAGE, ids=[c[0] for c in DAMAGE])
+def test_damage_fp64_at_bench_line_lengths(name, n):
+    """The damage PCG with the FFT preconditioner (Sec. 4.1, Eq. 24 R2; the
+    y pass applies the preconditioner symbol between its two FFTs) at 256
+    and 512 points per y line, against the oracle's sparse direct solve at
+    the same driving force."""
+    from paper_2508_07424_amd import mirve as m
+    w = _random_rve(n, 11)
+    print("case", name, n, flush=True)
+    r = _handle(m, w, 0, tol_cg=1e-13, tol_pcg=1e-13, damage_precond=0)
+    prob = oracle_problem(w, tol_cg=1e-13)
+    st = solver.State(prob)
+    x, _ = solver.mechanics(prob, st.phi, st.x)
+    _, _, psi1_o, _ = solver.unit_response(prob, st.phi, x)
+    r.rve_set_field("psi1", prob.to_public(psi1_o))
+    E = 1.5 * np.sqrt(1.0 / prob.ell / max(psi1_o.max(), 1e-300))
+    D, npcg = r.rve_solve_damage(E, commit=True)
+    H = solver.history_field(prob, E, psi1_o, st.psi_ini, st.H)
+    phi_o = model.solve_damage(H, prob.mat.Gc, prob.ell, prob.Dmats)
+    D_o = model.dissipation(phi_o, prob.mat.Gc, prob.ell, prob.h)
+    e_max = _elementwise(r.rve_get_field("phi"), prob.to_public(phi_o))
+    print("pcg iterations", npcg, "max-rel %.3e" % e_max, flush=True)
+    assert abs(D - D_o) <= 1e-10 * D_o
+    assert e_max < 1e-10
