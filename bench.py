@@ -544,6 +544,7 @@ def main():
                    "failed_slots": sorted(failed.values(), key=lambda d: d["slot"]),
                    "slot_occupancy": occupancy,
                    "launch_shape": {"x_rows_per_block": shape[0], "y_lines_per_block": shape[1],
+                                    "y_pass": "one wave per line" if shape[1] == 0 else "block",
                                     "z_columns_per_tile": shape[2],
                                     "krylov_vectors_nontemporal": shape[3]}},
         "roofline": roof,

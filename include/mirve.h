@@ -457,8 +457,10 @@ int rve_dissipation(rve_handle h, double* D, double* Gamma);
 int rve_profile_pass(rve_handle h, int pass, int repeat, double* bytes_per_launch);
 
 /* Autotuner of the launch shapes of the Green operator's passes (rows per
- * block of the x passes, lines per block of the y pass, y columns per tile
- * of the 3D z pass) and, when the config's streaming is -1, of the streaming
+ * block of the x passes, lines per block of the y pass or, for 2D grids
+ * with 256- or 512-point y lines, the one-wave y pass (one line position
+ * per wave, every component; no block barrier), y columns per tile of the
+ * 3D z pass) and, when the config's streaming is -1, of the streaming
  * policy of the Krylov x passes (non-temporal loads and stores of r, p, x,
  * which leave the last-level cache to the spectrum when the batch's vectors
  * do not fit it): times every
@@ -466,8 +468,8 @@ int rve_profile_pass(rve_handle h, int pass, int repeat, double* bytes_per_launc
  * (at least one slot must be set) and keeps the fastest for the handle.  The
  * choice is cached for the process per (grid, batch, precision): later
  * handles of the same kind take it without timing.  shape_out (may be NULL)
- * receives four values: rows, lines, columns, and 1 if the vectors are
- * streamed non-temporally (else 0).  Results of the solver do not depend on
+ * receives four values: rows, lines (0 for the one-wave y pass), columns,
+ * and 1 if the vectors are streamed non-temporally (else 0).  Results of the solver do not depend on
  * the choice beyond the summation order of the per-block partial sums. */
 int rve_autotune(rve_handle h, int repeat, int* shape_out);
 

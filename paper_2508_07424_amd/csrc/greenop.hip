@@ -1036,7 +1036,7 @@ static hipError_t launch_axis_wave(const AxisArgs<T>& a, hipStream_t st) {
 template <typename T>
 hipError_t launch_axis(const AxisArgs<T>& a, int mode, int maxb, dim3 grid, size_t lds,
                        hipStream_t st) {
-    if (a.contiguous && (a.g.ny == 256 || a.g.ny == 512) && a.pl.N == a.g.ny) {
+    if (!a.block_only && a.contiguous && (a.g.ny == 256 || a.g.ny == 512) && a.pl.N == a.g.ny) {
         if (a.pcg && mode == AX_FWD_M_INV) return launch_axis_wave<T, 1, AX_FWD_M_INV>(a, st);
         if (!a.pcg && a.g.s == 3 && mode == AX_FWD_P_INV) return launch_axis_wave<T, 3, AX_FWD_P_INV>(a, st);
     }

@@ -110,6 +110,7 @@ struct AxisArgs {
     int contiguous;      // 1: y lines (stride 1); 0: z lines (stride n_y)
     int lines;           // lines per block (y pass) / y columns per block (z pass)
     int threads;         // block size (multiple of 64, <= 256)
+    int block_only;      // 1: the block pass even where the one-wave y pass applies
 };
 
 template <typename T>

@@ -345,6 +345,9 @@ struct Solver : SolverBase {
     AxisPlan plx, ply, plz;
     int RB = 2, nbx = 1, maxb_x = 1;
     int tly = 1, maxb_y = 1, tlz = 1, maxb_z = 1;
+    // 1: the y pass of the mechanics operator stays a block pass where the
+    // one-wave pass (2D, 256- or 512-point lines) applies
+    int y_block = 0;
     // launch shape of the one-component passes of the damage preconditioner
     int RB1 = 2, nbx1 = 1, tly1 = 1, tlz1 = 1;
     int thr_x = 256, thr_y = 256, thr_z = 256;
@@ -505,6 +508,7 @@ struct Solver : SolverBase {
     struct Shape {
         int rb = 0, tly = 0, tlz = 0;
         int nt = -1;                 // streaming policy of the Krylov passes (-1: keep)
+        int yblock = -1;             // 1: block y pass, 0: one-wave y pass where it applies (-1: keep)
     };
 
     static bool make_geom(const rve_config& c, Geom& g, AxisPlan& px, AxisPlan& py, AxisPlan& pz,
@@ -841,6 +845,7 @@ struct Solver : SolverBase {
         a.contiguous = 1;
         a.lines = tly;
         a.threads = thr_y;
+        a.block_only = y_block;
         if (g.dim == 2) {
             HIPCHK(launch_axis<T>(a, AX_FWD_P_INV, maxb_y, grid_y(tly), lds_y, st));
         } else {
@@ -2715,6 +2720,7 @@ struct Solver : SolverBase {
         tlz = tz; maxb_z = mz; lds_z = lz;
         thr_x = t1; thr_y = t2; thr_z = t3;
         if (sh.nt >= 0 && cfg.streaming < 0) stream_nt = sh.nt ? 1 : 0;   // a fixed policy wins
+        if (sh.yblock >= 0) y_block = sh.yblock;
         one_comp_shape();
         clear_graphs();            // captured launches carry the old shape
         return RVE_OK;
@@ -2739,7 +2745,7 @@ struct Solver : SolverBase {
             auto it = tune_cache().find(key);
             if (it != tune_cache().end()) {
                 CHK(set_shape(it->second));
-                if (out) { out[0] = RB; out[1] = tly; out[2] = tlz; out[3] = stream_nt; }
+                if (out) { out[0] = RB; out[1] = y_lines_out(); out[2] = tlz; out[3] = stream_nt; }
                 return RVE_OK;
             }
         }
@@ -2762,6 +2768,7 @@ struct Solver : SolverBase {
         best.tly = tly;
         best.tlz = g.dim == 3 ? tlz : 0;
         best.nt = stream_nt;
+        best.yblock = y_block;
         double tb = INFINITY;
         for (int rb : {2, 4, 8, 16, 32}) {
             Shape sh = best;
@@ -2777,10 +2784,20 @@ struct Solver : SolverBase {
         for (int t : {1, 2, 4, 8, 16}) {
             Shape sh = best;
             sh.tly = t;
+            sh.yblock = 1;
             if (set_shape(sh) != RVE_OK) continue;
             double a = 0;
             CHK(timed(g.dim == 3 ? 5 : 1, a));
-            if (a < tb) { tb = a; best.tly = t; }
+            if (a < tb) { tb = a; best.tly = t; best.yblock = 1; }
+        }
+        if (wave_y()) {   // the one-wave y pass against the best block shape
+            Shape sh = best;
+            sh.yblock = 0;
+            double a = 0;
+            if (set_shape(sh) == RVE_OK) {
+                CHK(timed(1, a));
+                if (a < tb) { tb = a; best.yblock = 0; }
+            }
         }
         if (g.dim == 3) {
             CHK(set_shape(best));
@@ -2813,9 +2830,13 @@ struct Solver : SolverBase {
             std::lock_guard<std::mutex> lk(tune_mutex());
             tune_cache()[key] = best;
         }
-        if (out) { out[0] = RB; out[1] = tly; out[2] = tlz; out[3] = stream_nt; }
+        if (out) { out[0] = RB; out[1] = y_lines_out(); out[2] = tlz; out[3] = stream_nt; }
         return RVE_OK;
     }
+    // The one-wave y pass applies to 2D operators with 256- or 512-point y lines.
+    bool wave_y() const { return g.dim == 2 && g.s == 3 && (g.ny == 256 || g.ny == 512) && ply.N == g.ny; }
+    // lines per block of the y pass as reported: 0 for the one-wave pass
+    int y_lines_out() const { return wave_y() && !y_block ? 0 : tly; }
     static std::map<std::string, Shape>& tune_cache() {
         static std::map<std::string, Shape> m;
         return m;
@@ -2857,6 +2878,7 @@ struct Solver : SolverBase {
         a.contiguous = three ? 0 : 1;
         a.lines = three ? tlz : tly;
         a.threads = three ? thr_z : thr_y;
+        a.block_only = y_block;
         const dim3 grid = three ? dim3((unsigned)(g.nxh * ((g.ny + tlz - 1) / tlz)), 1, B)
                                 : dim3((unsigned)((g.nxh * (long long)g.nz + tly - 1) / tly), 1, B);
         for (int i = 0; i < repeat; ++i) {
