@@ -161,6 +161,29 @@ __device__ __forceinline__ void st_s(T* p, T v) {
     else *p = v;
 }
 
+// Two adjacent complex values (the same frequency of rows 2i and 2i+1 of the
+// transposed spectrum) at a 16-byte-aligned address: one access in FP32.
+template <typename T>
+__device__ __forceinline__ void ld_pair(const cplx<T>* p, cplx<T>& a, cplx<T>& b) {
+    if constexpr (sizeof(T) == 4) {
+        const float4 v = *reinterpret_cast<const float4*>(p);
+        a = {T(v.x), T(v.y)};
+        b = {T(v.z), T(v.w)};
+    } else {
+        a = p[0];
+        b = p[1];
+    }
+}
+template <typename T>
+__device__ __forceinline__ void st_pair(cplx<T>* p, cplx<T> a, cplx<T> b) {
+    if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4*>(p) = make_float4(float(a.x), float(a.y), float(b.x), float(b.y));
+    } else {
+        p[0] = a;
+        p[1] = b;
+    }
+}
+
 // Twiddles of the fixed-size FFTs, loaded once per block (global twiddle
 // loads inside the butterflies would each wait on memory).  Each thread
 // needs exp(-2 pi i t k1 / N) for its first-phase column t and k1 < N1.
@@ -479,8 +502,12 @@ __global__ void __launch_bounds__(256) k_xfwd(XfwdArgs<T> a) {
         const cplx<T> Bv = {T(0.5) * (z.y + zm.y), T(-0.5) * (z.x - zm.x)};
         const int rowA = r0 + 2 * pr;
         cplx<T>* spc = sp + (long long)c * g.Nspec + (long long)k * nz * ny;
-        if (rowA < nrows) spc[rowA] = A;            // rowA = z * ny + y
-        if (rowA + 1 < nrows) spc[rowA + 1] = Bv;
+        if (sizeof(T) == 4 && (nrows & 1) == 0) {   // rows 2i, 2i+1 adjacent and 16-byte aligned
+            if (rowA < nrows) st_pair(spc + rowA, A, Bv);
+        } else {
+            if (rowA < nrows) spc[rowA] = A;        // rowA = z * ny + y
+            if (rowA + 1 < nrows) spc[rowA + 1] = Bv;
+        }
     }
     if (MODE != XF_GREEN && MODE != XF_SPLIT) {
         double pv[1] = {part};
@@ -851,8 +878,13 @@ __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
     if constexpr (RT) load_reg_twiddles<T, F::N>(a.tw, wr);
     else stage_twiddles<T, F>(twl, a.tw);     // ordered by the barrier before the FFT
     // gather Z = A + iB from the transposed half spectra of the row pair,
-    // kLd elements per thread in flight before their LDS writes
-    const int gtot = S * npairs * nx;
+    // kLd elements per thread in flight before their LDS writes.  Each
+    // half-spectrum value k is read once and gives Z_k = A_k + i B_k and,
+    // for 0 < k < n_x/2, Z_{n_x-k} = conj(A_k) + i conj(B_k).  With an even
+    // row count, rows 2i and 2i+1 of a frequency are adjacent and 16-byte
+    // aligned, so in FP32 the pair is one load.
+    const int gtot = S * npairs * nxh;
+    const bool pair16 = sizeof(T) == 4 && (nrows & 1) == 0;
     for (int e0 = threadIdx.x; e0 < gtot; e0 += kLd * blockDim.x) {
         cplx<T> A[kLd], B[kLd];
         bool ina[kLd], inb[kLd];
@@ -860,16 +892,18 @@ __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
         for (int u = 0; u < kLd; ++u) {     // unconditional loads at clamped addresses
             const int e = e0 + u * blockDim.x;
             const int pr = e & (npairs - 1);
-            const int q = e >> lgp;               // q = c * nx + k
-            const int c = q / nx;
-            const int k = q - c * nx;
+            const int q = e >> lgp;               // q = c * nxh + k
+            const int c = q / nxh;
+            const int k = q - c * nxh;
             const int rowA = r0 + 2 * pr;
-            const int kk = k < nxh ? k : nx - k;
-            const long long o = (long long)c * g.Nspec + (long long)kk * nz * ny + rowA;
+            const long long o = (long long)c * g.Nspec + (long long)k * nz * ny + rowA;
             ina[u] = e < gtot && rowA < nrows;
             inb[u] = e < gtot && rowA + 1 < nrows;
-            A[u] = sp[ina[u] ? o : 0];
-            B[u] = sp[inb[u] ? o + 1 : 0];
+            if (pair16) ld_pair(sp + (ina[u] ? o : 0), A[u], B[u]);
+            else {
+                A[u] = sp[ina[u] ? o : 0];
+                B[u] = sp[inb[u] ? o + 1 : 0];
+            }
         }
         loads_issued();
 #pragma unroll
@@ -878,12 +912,13 @@ __global__ void __launch_bounds__(256) k_xinv(XinvArgs<T> a) {
             if (e >= gtot) break;
             const int pr = e & (npairs - 1);
             const int q = e >> lgp;
-            const int c = q / nx;
-            const int k = q - c * nx;
+            const int c = q / nxh;
+            const int k = q - c * nxh;
             const T ax = ina[u] ? A[u].x : T(0), bx = inb[u] ? B[u].x : T(0);
-            T ay = ina[u] ? A[u].y : T(0), by = inb[u] ? B[u].y : T(0);
-            if (k >= nxh) { ay = -ay; by = -by; }
-            buf[(c * npairs + pr) * LS + lp(k)] = {ax - by, ay + bx};
+            const T ay = ina[u] ? A[u].y : T(0), by = inb[u] ? B[u].y : T(0);
+            cplx<T>* L = buf + (c * npairs + pr) * LS;
+            L[lp(k)] = {ax - by, ay + bx};
+            if (k > 0 && 2 * k < nx) L[lp(nx - k)] = {ax + by, bx - ay};
         }
     }
     __syncthreads();
