@@ -685,22 +685,25 @@ __global__ void __launch_bounds__(256) k_axis(AxisArgs<T> a) {
 }
 
 // ---------------------------------------------------------------------------
-// one-wave axis pass: forward, per-frequency operator, inverse along y
+// one-wave axis pass: whole y lines in the registers of one wave
 // ---------------------------------------------------------------------------
 //
-// For contiguous lines of N = 64 R points (R = 4: 256, R = 8: 512) one wave
-// owns one line position for all S components, so the block needs no
-// barrier.  Each line is a radix-R Stockham FFT of P = log_R N passes with
-// one butterfly per lane: in the pass of span p, butterfly i = lane (with
-// k = i mod p) reads x[i + 64 t], t < R, multiplies element t by
-// w_{pR}^{t k}, takes an R-point DFT and writes y[(i - k) R + k + t p].  The
-// first pass reads x[lane + 64 t] straight from HBM (coalesced); between
-// passes the line goes through the wave's own LDS region; after the last
-// pass (p = 64) output t of a lane is X[lane + 64 t], so the lane holds the
-// same frequencies of every component and the projection (or the damage
-// preconditioner) is applied in registers.  The inverse runs the same
-// passes with conjugate twiddles starting from that layout and ends in the
-// load layout, so the store is coalesced too.
+// For contiguous lines of N = 128, 256 or 512 points, LN lanes of a wave
+// (64, or 32 for N = 128, so that a wave carries two lines) own one line
+// position for all S components, and no LDS or barrier is shared with the
+// other waves of the block.  Lane l of a line holds x[l + LN m], m < V
+// (V = N / LN values).  Each line is a Stockham FFT of P passes (512 = 8^3,
+// 256 = 4^4, 128 = 4^3 2) with V / R butterflies of radix R per lane: in the
+// pass of span p, butterfly i reads x[i + t N/R], t < R, multiplies element
+// t by w_{pR}^{t k} (k = i mod p), takes an R-point DFT and writes
+// y[(i - k) R + k + t p].  Butterfly i = l + LN j reads exactly the lane's
+// values m = j + t V/R, so the first pass reads the line straight from HBM
+// (coalesced runs); between passes the line goes through the wave's own LDS
+// region; after the last pass (p = N/R) the lane again holds X[l + LN m].
+// So the lane holds the same frequencies of every component, and the
+// projection (or the damage preconditioner) is applied in registers.  The
+// inverse runs the same passes with conjugate twiddles from that layout and
+// ends in it, so every load and store is a coalesced run.
 
 // Orders the LDS accesses of the lanes of one wave (no block barrier).
 __device__ __forceinline__ void wave_lds_sync() {
@@ -710,124 +713,163 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 template <int N>
-struct WaveRadix;
-template <> struct WaveRadix<256> { static constexpr int R = 4, P = 4; };
-template <> struct WaveRadix<512> { static constexpr int R = 8, P = 3; };
+struct WavePlan {
+    static constexpr int LN = N >= 256 ? 64 : 32;          // lanes per line
+    static constexpr int V = N / LN;                      // values per lane
+    static constexpr int P = N == 512 ? 3 : 4;            // passes
+    static constexpr int radix(int s) { return (N == 128 && s == 3) ? 2 : V; }
+    static constexpr int span(int s) {
+        int p = 1;
+        for (int u = 0; u < s; ++u) p *= radix(u);
+        return p;
+    }
+    // offset of pass s's twiddles (passes 1 .. P-1) in the lane's table
+    static constexpr int tw_off(int s) {
+        int o = 0;
+        for (int u = 1; u < s; ++u) o += (V / radix(u)) * (radix(u) - 1);
+        return o;
+    }
+    static constexpr int NTW = tw_off(P);
+};
 
-template <typename T, int N>
-__device__ __forceinline__ void wave_dft_r(cplx<T> (&v)[WaveRadix<N>::R], bool inv) {
-    if constexpr (WaveRadix<N>::R == 8) dft8(v, inv);
-    else dft4(v[0], v[1], v[2], v[3], inv);
-}
-
-// In-place line FFT of the calling wave: v[t] = x[lane + 64 t] in and
-// X[lane + 64 t] out; wtw[s - 1][t - 1] = w_{p R}^{t k} of pass s >= 1
-// (forward sign); lds = the wave's region of lds_line(N) entries.
-template <typename T, int N>
-__device__ __forceinline__ void wave_line_fft(cplx<T> (&v)[WaveRadix<N>::R],
-                                              const cplx<T> (&wtw)[WaveRadix<N>::P - 1][WaveRadix<N>::R - 1],
-                                              cplx<T>* lds, int lane, bool inv) {
-    constexpr int R = WaveRadix<N>::R, P = WaveRadix<N>::P;
-    int p = 1;
-#pragma unroll
-    for (int s = 0; s < P; ++s) {
-        if (s > 0) {
-#pragma unroll
-            for (int t = 1; t < R; ++t) {
-                const cplx<T> w = wtw[s - 1][t - 1], u = v[t];
-                v[t] = inv ? cplx<T>{u.x * w.x + u.y * w.y, u.y * w.x - u.x * w.y}   // u conj(w)
-                           : cplx<T>{u.x * w.x - u.y * w.y, u.y * w.x + u.x * w.y};
-            }
-        }
-        wave_dft_r<T, N>(v, inv);
-        if (s < P - 1) {
-            const int k = lane & (p - 1);
-            const int base = (lane - k) * R + k;
-            wave_lds_sync();                      // earlier reads of the region are done
-#pragma unroll
-            for (int t = 0; t < R; ++t) lds[lp(base + t * p)] = v[t];
-            wave_lds_sync();
-#pragma unroll
-            for (int t = 0; t < R; ++t) v[t] = lds[lp(lane + 64 * t)];
-        }
-        p *= R;
+template <typename T, int R>
+__device__ __forceinline__ void wave_dft(cplx<T> (&u)[R], bool inv) {
+    if constexpr (R == 8) dft8(u, inv);
+    else if constexpr (R == 4) dft4(u[0], u[1], u[2], u[3], inv);
+    else {
+        const cplx<T> a = u[0], b = u[1];
+        u[0] = cadd(a, b);
+        u[1] = csub(a, b);
     }
 }
 
-// MODE: AX_FWD_P_INV (S = 3 or 6, projection) or AX_FWD_M_INV (S = 1,
-// damage preconditioner).  Four waves per block, one line position each.
+// Pass s of the line FFT of the calling lane (l = lane within its line).
+template <typename T, int N, int s>
+__device__ __forceinline__ void wave_pass(cplx<T> (&v)[WavePlan<N>::V],
+                                          const cplx<T> (&wtw)[WavePlan<N>::NTW], cplx<T>* lds,
+                                          int l, bool inv) {
+    using WP = WavePlan<N>;
+    constexpr int R = WP::radix(s), p = WP::span(s), NB = WP::V / R;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        cplx<T> u[R];
+#pragma unroll
+        for (int t = 0; t < R; ++t) u[t] = v[j + t * NB];
+        if constexpr (s > 0) {
+#pragma unroll
+            for (int t = 1; t < R; ++t) {
+                const cplx<T> w = wtw[WP::tw_off(s) + j * (R - 1) + t - 1], x = u[t];
+                u[t] = inv ? cplx<T>{x.x * w.x + x.y * w.y, x.y * w.x - x.x * w.y}   // x conj(w)
+                           : cplx<T>{x.x * w.x - x.y * w.y, x.y * w.x + x.x * w.y};
+            }
+        }
+        wave_dft<T, R>(u, inv);
+#pragma unroll
+        for (int t = 0; t < R; ++t) v[j + t * NB] = u[t];
+    }
+    if constexpr (s < WP::P - 1) {
+        wave_lds_sync();                          // earlier reads of the region are done
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int i = l + WP::LN * j, k = i & (p - 1);
+            const int base = (i - k) * R + k;
+#pragma unroll
+            for (int t = 0; t < R; ++t) lds[lp(base + t * p)] = v[j + t * NB];
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int m = 0; m < WP::V; ++m) v[m] = lds[lp(l + WP::LN * m)];
+    }
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void wave_line_fft(cplx<T> (&v)[WavePlan<N>::V],
+                                              const cplx<T> (&wtw)[WavePlan<N>::NTW], cplx<T>* lds,
+                                              int l, bool inv) {
+    wave_pass<T, N, 0>(v, wtw, lds, l, inv);
+    wave_pass<T, N, 1>(v, wtw, lds, l, inv);
+    wave_pass<T, N, 2>(v, wtw, lds, l, inv);
+    if constexpr (WavePlan<N>::P > 3) wave_pass<T, N, 3>(v, wtw, lds, l, inv);
+}
+
+// MODE: AX_FWD or AX_INV (one direction, any S), AX_FWD_P_INV (S = 3,
+// projection) or AX_FWD_M_INV (S = 1, damage preconditioner).  Four waves
+// per block.
 template <typename T, int S, int MODE, int N>
 __global__ void __launch_bounds__(256) k_axis_wave(AxisArgs<T> a) {
-    constexpr int R = WaveRadix<N>::R, P = WaveRadix<N>::P;
+    using WP = WavePlan<N>;
+    constexpr int V = WP::V, LN = WP::LN, LPW = 64 / LN;
     extern __shared__ unsigned char smem_raw[];
     const Geom& g = a.g;
     const int b = blockIdx.z;
     if (a.cg && a.cg[b].conv <= a.iter) return;
     if (a.pcg && a.pcg[b].conv <= a.iter) return;
     if (a.active && !a.active[b]) return;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, l = lane & (LN - 1), gl = lane / LN;
     const int wv = threadIdx.x >> 6;
-    const long long L = (long long)blockIdx.x * (blockDim.x >> 6) + wv;   // L = kx * nz + z
+    const long long L = ((long long)blockIdx.x * (blockDim.x >> 6) + wv) * LPW + gl;   // kx * nz + z
     const long long nlines = (long long)g.nxh * g.nz;
-    if (L >= nlines) return;                      // whole waves only: no barrier follows
-    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw) + wv * lds_line(N);
+    if (L >= nlines) return;                      // no barrier follows
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw) + (wv * LPW + gl) * lds_line(N);
     cplx<T>* sp = a.spec + (long long)b * S * g.Nspec + L * N;   // n_y == N
 
-    cplx<T> v[S][R];
+    cplx<T> v[S][V];
 #pragma unroll
     for (int c = 0; c < S; ++c)
 #pragma unroll
-        for (int t = 0; t < R; ++t) v[c][t] = sp[(long long)c * g.Nspec + lane + 64 * t];
+        for (int m = 0; m < V; ++m) v[c][m] = sp[(long long)c * g.Nspec + l + LN * m];
 
-    // twiddles of passes 1 .. P-1: span p = R^s, k = lane mod p,
-    // w_{pR}^{t k} = tw[t k N / (p R)] with tw[m] = exp(-2 pi i m / N)
-    cplx<T> wtw[P - 1][R - 1];
-    {
-        int p = R;
+    // twiddles of passes 1 .. P-1: w_{pR}^{t k} = tw[t k N / (p R)],
+    // tw[m] = exp(-2 pi i m / N)
+    cplx<T> wtw[WP::NTW > 0 ? WP::NTW : 1];
 #pragma unroll
-        for (int s = 1; s < P; ++s) {
-            const int k = lane & (p - 1);
-            const int stride = N / (p * R);
+    for (int s = 1; s < WP::P; ++s) {
+        const int R = WP::radix(s), p = WP::span(s), NB = V / R, stride = N / (p * R);
 #pragma unroll
-            for (int t = 1; t < R; ++t) wtw[s - 1][t - 1] = a.tw[t * k * stride];
-            p *= R;
+        for (int j = 0; j < NB; ++j) {
+            const int k = (l + LN * j) & (p - 1);
+#pragma unroll
+            for (int t = 1; t < R; ++t) wtw[WP::tw_off(s) + j * (R - 1) + t - 1] = a.tw[t * k * stride];
         }
     }
 
+    constexpr bool FWD = MODE != AX_INV;
+    if constexpr (FWD) {
 #pragma unroll
-    for (int c = 0; c < S; ++c) wave_line_fft<T, N>(v[c], wtw, lds, lane, false);
-
+        for (int c = 0; c < S; ++c) wave_line_fft<T, N>(v[c], wtw, lds, l, false);
+    }
     const int kx = (int)(L / g.nz), kz = (int)(L - (long long)kx * g.nz);
     if constexpr (MODE == AX_FWD_P_INV) {
         const T rN[3] = {T(1) / T(g.nx), T(1) / T(g.ny), T(1) / T(g.nz)};
 #pragma unroll
-        for (int t = 0; t < R; ++t) {
+        for (int m = 0; m < V; ++m) {
             T fx[3], fy[3];
-            freq_xy<T>(g, kx, lane + 64 * t, kz, rN, fx, fy);
+            freq_xy<T>(g, kx, l + LN * m, kz, rN, fx, fy);
             cplx<T> u[S];
 #pragma unroll
-            for (int c = 0; c < S; ++c) u[c] = v[c][t];
+            for (int c = 0; c < S; ++c) u[c] = v[c][m];
             if constexpr (S == 3) project2<T>(u, fx, fy);
             else project3<T>(u, fx, fy);
 #pragma unroll
-            for (int c = 0; c < S; ++c) v[c][t] = u[c];
+            for (int c = 0; c < S; ++c) v[c][m] = u[c];
         }
-    } else {
+    } else if constexpr (MODE == AX_FWD_M_INV) {
         const double abar = a.pcg[b].abar, bbar = a.pcg[b].bbar;
 #pragma unroll
-        for (int t = 0; t < R; ++t) {
-            const T m = precond_symbol<T>(g, a.dsq, kx, lane + 64 * t, kz, abar, bbar);
-            v[0][t].x *= m;
-            v[0][t].y *= m;
+        for (int m = 0; m < V; ++m) {
+            const T mul = precond_symbol<T>(g, a.dsq, kx, l + LN * m, kz, abar, bbar);
+            v[0][m].x *= mul;
+            v[0][m].y *= mul;
         }
     }
-
+    if constexpr (MODE != AX_FWD) {
 #pragma unroll
-    for (int c = 0; c < S; ++c) wave_line_fft<T, N>(v[c], wtw, lds, lane, true);
+        for (int c = 0; c < S; ++c) wave_line_fft<T, N>(v[c], wtw, lds, l, true);
+    }
 #pragma unroll
     for (int c = 0; c < S; ++c)
 #pragma unroll
-        for (int t = 0; t < R; ++t) sp[(long long)c * g.Nspec + lane + 64 * t] = v[c][t];
+        for (int m = 0; m < V; ++m) sp[(long long)c * g.Nspec + l + LN * m] = v[c][m];
 }
 
 // ---------------------------------------------------------------------------
@@ -1053,27 +1095,47 @@ static hipError_t launch_axis_s(const AxisArgs<T>& a, int maxb, dim3 grid, size_
     MIRVE_DISPATCH(k_axis, T, S, MODE, false, a.pl, maxb, grid, lds, st, a);
 }
 
-// Contiguous lines of 256 or 512 points with a per-frequency operator go
-// to the one-wave pass (grid, block and LDS of its own).
+// Contiguous lines of 128, 256 or 512 points go to the one-wave pass (grid,
+// block and LDS of its own) unless the handle keeps the block pass.
 template <typename T, int S, int MODE>
 static hipError_t launch_axis_wave(const AxisArgs<T>& a, hipStream_t st) {
     constexpr int W = 4;                       // waves per block
-    const long long nlines = (long long)a.g.nxh * a.g.nz;
-    const dim3 grid((unsigned)((nlines + W - 1) / W), 1, a.g.B);
     const int N = a.g.ny;
-    const size_t lds = (size_t)W * lds_line(N) * sizeof(cplx<T>);
+    const int lpw = N >= 256 ? 1 : 2;          // lines per wave
+    const long long nlines = (long long)a.g.nxh * a.g.nz;
+    const long long waves = (nlines + lpw - 1) / lpw;
+    const dim3 grid((unsigned)((waves + W - 1) / W), 1, a.g.B);
+    const size_t lds = (size_t)W * lpw * lds_line(N) * sizeof(cplx<T>);
     if (N == 512) hipLaunchKernelGGL((k_axis_wave<T, S, MODE, 512>), grid, dim3(64 * W), lds, st, a);
-    else hipLaunchKernelGGL((k_axis_wave<T, S, MODE, 256>), grid, dim3(64 * W), lds, st, a);
+    else if (N == 256) hipLaunchKernelGGL((k_axis_wave<T, S, MODE, 256>), grid, dim3(64 * W), lds, st, a);
+    else hipLaunchKernelGGL((k_axis_wave<T, S, MODE, 128>), grid, dim3(64 * W), lds, st, a);
     return hipGetLastError();
+}
+
+template <typename T>
+static bool wave_axis_applies(const AxisArgs<T>& a) {
+    return !a.block_only && a.contiguous && a.pl.N == a.g.ny &&
+           (a.g.ny == 128 || a.g.ny == 256 || a.g.ny == 512);
 }
 
 // The damage preconditioner (a.pcg set) transforms one scalar field.
 template <typename T>
 hipError_t launch_axis(const AxisArgs<T>& a, int mode, int maxb, dim3 grid, size_t lds,
                        hipStream_t st) {
-    if (!a.block_only && a.contiguous && (a.g.ny == 256 || a.g.ny == 512) && a.pl.N == a.g.ny) {
-        if (a.pcg && mode == AX_FWD_M_INV) return launch_axis_wave<T, 1, AX_FWD_M_INV>(a, st);
-        if (!a.pcg && a.g.s == 3 && mode == AX_FWD_P_INV) return launch_axis_wave<T, 3, AX_FWD_P_INV>(a, st);
+    if (wave_axis_applies(a)) {
+        if (a.pcg) {
+            switch (mode) {
+                case AX_FWD: return launch_axis_wave<T, 1, AX_FWD>(a, st);
+                case AX_INV: return launch_axis_wave<T, 1, AX_INV>(a, st);
+                case AX_FWD_M_INV: return launch_axis_wave<T, 1, AX_FWD_M_INV>(a, st);
+                default: break;
+            }
+        } else if (a.g.s == 3 && mode == AX_FWD_P_INV) {
+            return launch_axis_wave<T, 3, AX_FWD_P_INV>(a, st);
+        } else if (a.g.s == 6 && (mode == AX_FWD || mode == AX_INV)) {
+            return mode == AX_FWD ? launch_axis_wave<T, 6, AX_FWD>(a, st)
+                                  : launch_axis_wave<T, 6, AX_INV>(a, st);
+        }
     }
     if (a.pcg) {
         switch (mode) {

@@ -345,8 +345,8 @@ struct Solver : SolverBase {
     AxisPlan plx, ply, plz;
     int RB = 2, nbx = 1, maxb_x = 1;
     int tly = 1, maxb_y = 1, tlz = 1, maxb_z = 1;
-    // 1: the y pass of the mechanics operator stays a block pass where the
-    // one-wave pass (2D, 256- or 512-point lines) applies
+    // 1: the y passes of the mechanics operator stay block passes where the
+    // one-wave pass (128-, 256- or 512-point y lines) applies
     int y_block = 0;
     // launch shape of the one-component passes of the damage preconditioner
     int RB1 = 2, nbx1 = 1, tly1 = 1, tlz1 = 1;
@@ -2795,7 +2795,7 @@ struct Solver : SolverBase {
             sh.yblock = 0;
             double a = 0;
             if (set_shape(sh) == RVE_OK) {
-                CHK(timed(1, a));
+                CHK(timed(g.dim == 3 ? 5 : 1, a));
                 if (a < tb) { tb = a; best.yblock = 0; }
             }
         }
@@ -2833,8 +2833,8 @@ struct Solver : SolverBase {
         if (out) { out[0] = RB; out[1] = y_lines_out(); out[2] = tlz; out[3] = stream_nt; }
         return RVE_OK;
     }
-    // The one-wave y pass applies to 2D operators with 256- or 512-point y lines.
-    bool wave_y() const { return g.dim == 2 && g.s == 3 && (g.ny == 256 || g.ny == 512) && ply.N == g.ny; }
+    // The one-wave y pass applies to 128-, 256- and 512-point y lines.
+    bool wave_y() const { return (g.ny == 128 || g.ny == 256 || g.ny == 512) && ply.N == g.ny; }
     // lines per block of the y pass as reported: 0 for the one-wave pass
     int y_lines_out() const { return wave_y() && !y_block ? 0 : tly; }
     static std::map<std::string, Shape>& tune_cache() {

@@ -1,5 +1,6 @@
 """GPU parity at the line lengths the benchmarks run: the fixed-size FFTs
-of 128 to 1024 points (and the z pass of a 3D grid), element by element
+of 128 to 1024 points (the block passes, the one-wave y passes of 128-,
+256- and 512-point lines, and the z pass of a 3D grid), element by element
 against the CPU oracle.
 
 The cases go through a batched handle (three slots, a stream of its own,
@@ -49,6 +50,9 @@ CASES = [
     ("FastFFT<256>x<256>", (256, 256)),
     ("FastFFT<512>x<64>", (512, 64)),
     ("FastFFT<64>x<512>", (64, 512)),
+    ("FastFFT<32>x<128>", (32, 128)),
+    ("FastFFT<16>x<128>x<16>", (16, 128, 16)),
+    ("FastFFT<8>x<256>x<4>", (8, 256, 4)),
     ("FastFFT<1024>x<16>", (1024, 16)),
     ("FastFFT<128>x<32>x<16>", (128, 32, 16)),
     ("FastFFT<16>x<16>x<128>", (16, 16, 128)),
@@ -88,13 +92,13 @@ def test_green_op_at_bench_line_lengths(name, n, prec):
         assert _elementwise(phi_ini, prob.to_public(st.phi_ini)) < 1e-11
 
 
-MECH = [CASES[0], CASES[1], CASES[2]]
+MECH = CASES[:6]
 
 
 @pytest.mark.parametrize("name,n", MECH, ids=[c[0] for c in MECH])
 def test_mechanics_fp64_at_bench_line_lengths(name, n):
     """The mechanics CG (fused x-forward / axis / x-inverse passes with the
-    Krylov updates) at 256 and 512 points per line, against the oracle's CG
+    Krylov updates) at 128 to 512 points per line, against the oracle's CG
     to the same tolerance."""
     from paper_2508_07424_amd import mirve as m
     w = _random_rve(n, 7)
@@ -112,15 +116,15 @@ def test_mechanics_fp64_at_bench_line_lengths(name, n):
     assert abs(S1 - S1_o) <= 1e-10 * abs(S1_o)
 
 
-DAMAGE = [CASES[0], CASES[2]]
+DAMAGE = [CASES[0], CASES[2], CASES[3], CASES[4]]
 
 
 @pytest.mark.parametrize("name,n", DAMAGE, ids=[c[0] for c in DAMAGE])
 def test_damage_fp64_at_bench_line_lengths(name, n):
-    """The damage PCG with the FFT preconditioner (Sec. 4.1, Eq. 24 R2; the
-    y pass applies the preconditioner symbol between its two FFTs) at 256
-    and 512 points per y line, against the oracle's sparse direct solve at
-    the same driving force."""
+    """The damage PCG with the FFT preconditioner (Sec. 4.1, Eq. 24 R2; in
+    2D the y pass applies the preconditioner symbol between its two FFTs)
+    at 128 to 512 points per y line, against the oracle's sparse direct
+    solve at the same driving force."""
     from paper_2508_07424_amd import mirve as m
     w = _random_rve(n, 11)
     print("case", name, n, flush=True)
