@@ -2931,7 +2931,11 @@ static int validate(const rve_config* c, std::string& why) {
     for (int i = 0; i < c->dim; ++i)
         if (c->n[i] < 2 || c->n[i] > 1024) { why = "n out of range [2, 1024]"; return RVE_EINVAL; }
     if (c->dim == 2 && c->n[2] != 1) { why = "n[2] must be 1 in 2D"; return RVE_EINVAL; }
-    if (!(c->h > 0) || !(c->ell > 0) || !(c->k_res > 0)) { why = "h, ell, k_res must be > 0"; return RVE_EINVAL; }
+    if (!(c->h > 0) || !(c->ell > 0) || !(c->k_res > 0) || !std::isfinite(c->h) ||
+        !std::isfinite(c->ell) || !std::isfinite(c->k_res)) {
+        why = "h, ell, k_res must be finite and > 0";
+        return RVE_EINVAL;
+    }
     if (c->split != RVE_SPLIT_NONE && c->split != RVE_SPLIT_VOLDEV) { why = "bad split"; return RVE_EINVAL; }
     if (c->precision != RVE_PREC_FP64 && c->precision != RVE_PREC_MIXED) { why = "bad precision"; return RVE_EINVAL; }
     if (!(c->tol >= 0) || !(c->tol_cg >= 0) || !(c->tol_pcg >= 0) || !(c->tol_al >= 0)) {

@@ -113,7 +113,8 @@ def test_workspace_query(lib):
     {"tol_cg": -1e-8}, {"tol": float("nan")}, {"max_cg": 0}, {"max_halvings": 13},
     {"max_halvings": -1}, {"stall_window": -1}, {"batch": 0}, {"batch": 5000}, {"anderson_depth": 9},
     {"f": (0, 0, 0)}, {"n": (97, 64)},   # 97 is prime: no FFT factorisation
-    {"streaming": 2}, {"streaming": -2}, {"graphs": 2},
+    {"streaming": 2}, {"streaming": -2}, {"graphs": 2}, {"ell": float("nan")}, {"k": float("inf")},
+    {"h": float("inf")},
 ])
 def test_invalid_configs_are_rejected(lib, bad):
     kw = {"n": (64, 64)}
