@@ -2672,7 +2672,22 @@ struct Solver : SolverBase {
     // component, which raises the blocks per CU.
     void one_comp_shape() {
         const size_t ce = sizeof(cplx<T>);
+        // The one-component x passes take more rows per block than the
+        // s-component ones where the batch still gives about 1024 blocks or
+        // more: the same LDS holds s times fewer lines, the blocks carry more
+        // waves, and the transposed spectrum is read and written in longer
+        // runs (16 rows: 128 B in FP32).  The partial-sum buffers are sized
+        // for two rows per block, so any larger count fits them.
         RB1 = RB;
+        if (plx.fastN) {
+            const long long rows = (long long)g.ny * g.nz;
+            auto fits = [&](int rb) {
+                return rb <= 16 && rb <= rows && (rb / 2) * split_max(g.nx) <= 256 &&
+                       (size_t)(rb / 2) * lds_line(g.nx) * ce <= kLdsCap &&
+                       rows * B / rb >= 1024;
+            };
+            while (fits(2 * RB1)) RB1 *= 2;
+        }
         nbx1 = (int)((g.ny * (long long)g.nz + RB1 - 1) / RB1);
         if (plx.fastN) {
             thr_x1 = threads_for((RB1 / 2) * split_max(g.nx));
