@@ -17,6 +17,14 @@ def to_oracle(a, d):
     return np.ascontiguousarray(a.transpose((0,) + tuple(range(a.ndim - 1, 0, -1))))
 
 
+def relmax(a, b):
+    """Element-wise deviation: max |a - b| over max |b|."""
+    a = np.asarray(a, dtype=float)
+    b = np.asarray(b, dtype=float)
+    den = np.max(np.abs(b)) if b.size else 0.0
+    return float(np.max(np.abs(a - b)) / (den if den > 0 else 1.0)) if b.size else 0.0
+
+
 def rel(a, b):
     a = np.asarray(a, dtype=float)
     b = np.asarray(b, dtype=float)
