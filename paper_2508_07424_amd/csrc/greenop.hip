@@ -792,6 +792,24 @@ __device__ __forceinline__ void wave_line_fft(cplx<T> (&v)[WavePlan<N>::V],
     if constexpr (WavePlan<N>::P > 3) wave_pass<T, N, 3>(v, wtw, lds, l, inv);
 }
 
+// Twiddles of passes 1 .. P-1 of the calling lane (l = lane within its
+// line): w_{pR}^{t k} = tw[t k N / (p R)], tw[m] = exp(-2 pi i m / N).
+template <typename T, int N>
+__device__ __forceinline__ void wave_twiddles(const cplx<T>* __restrict__ tw, int l,
+                                              cplx<T> (&wtw)[WavePlan<N>::NTW]) {
+    using WP = WavePlan<N>;
+#pragma unroll
+    for (int s = 1; s < WP::P; ++s) {
+        const int R = WP::radix(s), p = WP::span(s), NB = WP::V / R, stride = N / (p * R);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int k = (l + WP::LN * j) & (p - 1);
+#pragma unroll
+            for (int t = 1; t < R; ++t) wtw[WP::tw_off(s) + j * (R - 1) + t - 1] = tw[t * k * stride];
+        }
+    }
+}
+
 // MODE: AX_FWD or AX_INV (one direction, any S), AX_FWD_P_INV (S = 3,
 // projection) or AX_FWD_M_INV (S = 1, damage preconditioner).  Four waves
 // per block.
@@ -819,19 +837,8 @@ __global__ void __launch_bounds__(256) k_axis_wave(AxisArgs<T> a) {
 #pragma unroll
         for (int m = 0; m < V; ++m) v[c][m] = sp[(long long)c * g.Nspec + l + LN * m];
 
-    // twiddles of passes 1 .. P-1: w_{pR}^{t k} = tw[t k N / (p R)],
-    // tw[m] = exp(-2 pi i m / N)
-    cplx<T> wtw[WP::NTW > 0 ? WP::NTW : 1];
-#pragma unroll
-    for (int s = 1; s < WP::P; ++s) {
-        const int R = WP::radix(s), p = WP::span(s), NB = V / R, stride = N / (p * R);
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const int k = (l + LN * j) & (p - 1);
-#pragma unroll
-            for (int t = 1; t < R; ++t) wtw[WP::tw_off(s) + j * (R - 1) + t - 1] = a.tw[t * k * stride];
-        }
-    }
+    cplx<T> wtw[WP::NTW];
+    wave_twiddles<T, N>(a.tw, l, wtw);
 
     constexpr bool FWD = MODE != AX_INV;
     if constexpr (FWD) {
@@ -870,6 +877,64 @@ __global__ void __launch_bounds__(256) k_axis_wave(AxisArgs<T> a) {
     for (int c = 0; c < S; ++c)
 #pragma unroll
         for (int m = 0; m < V; ++m) sp[(long long)c * g.Nspec + l + LN * m] = v[c][m];
+}
+
+// ||out||^2 of out = scale F^-1{P : F[sigma]} without the inverse
+// transforms (2D, S = 3): by Parseval the sum over the voxels of |out|^2 is
+// scale^2 / N times the sum over all frequencies of |P : sigma^|^2, and the
+// half spectrum (k_x in [0, n_x/2]) stands for k_x and n_x - k_x at once:
+// weight 1 at k_x = 0 and, for even n_x, at k_x = n_x/2, else 2.  The
+// forward y FFT and the projection are those of k_axis_wave; the spectrum is
+// not written back.  Exactly nparts blocks per slot (the partial-sum layout
+// of the x-inverse pass this replaces), each taking line positions in a
+// grid-stride loop, so the sums are in a fixed order.
+template <typename T, int N>
+__global__ void __launch_bounds__(256) k_axis_wave_norm(AxisArgs<T> a) {
+    using WP = WavePlan<N>;
+    constexpr int S = 3, V = WP::V, LN = WP::LN, LPW = 64 / LN;
+    extern __shared__ unsigned char smem_raw[];
+    const Geom& g = a.g;
+    const int b = blockIdx.z;
+    if (a.active && !a.active[b]) return;
+    const int lane = threadIdx.x & 63, l = lane & (LN - 1), gl = lane / LN;
+    const int wv = threadIdx.x >> 6, W = blockDim.x >> 6;
+    cplx<T>* lds = reinterpret_cast<cplx<T>*>(smem_raw) + (wv * LPW + gl) * lds_line(N);
+    const cplx<T>* spb = a.spec + (long long)b * S * g.Nspec;
+    const long long nlines = (long long)g.nxh * g.nz;
+    cplx<T> wtw[WP::NTW];
+    wave_twiddles<T, N>(a.tw, l, wtw);
+    const T rN[3] = {T(1) / T(g.nx), T(1) / T(g.ny), T(1) / T(g.nz)};
+    double acc = 0.0;
+    for (long long base = ((long long)blockIdx.x * W + wv) * LPW; base < nlines;
+         base += (long long)gridDim.x * W * LPW) {
+        const long long L = base + gl;                // kx * nz + z
+        if (L >= nlines) continue;                    // no barrier inside the loop
+        const cplx<T>* sp = spb + L * N;
+        cplx<T> v[S][V];
+#pragma unroll
+        for (int c = 0; c < S; ++c)
+#pragma unroll
+            for (int m = 0; m < V; ++m) v[c][m] = sp[(long long)c * g.Nspec + l + LN * m];
+#pragma unroll
+        for (int c = 0; c < S; ++c) wave_line_fft<T, N>(v[c], wtw, lds, l, false);
+        const int kx = (int)(L / g.nz), kz = (int)(L - (long long)kx * g.nz);
+        const double wgt = (kx == 0 || 2 * kx == g.nx) ? 1.0 : 2.0;
+        double line = 0.0;
+#pragma unroll
+        for (int m = 0; m < V; ++m) {
+            T fx[3], fy[3];
+            freq_xy<T>(g, kx, l + LN * m, kz, rN, fx, fy);
+            cplx<T> u[S];
+#pragma unroll
+            for (int c = 0; c < S; ++c) u[c] = v[c][m];
+            project2<T>(u, fx, fy);
+#pragma unroll
+            for (int c = 0; c < S; ++c) line += double(u[c].x) * double(u[c].x) + double(u[c].y) * double(u[c].y);
+        }
+        acc += wgt * line;
+    }
+    double pv[1] = {acc * a.nscale};
+    block_sum_store<1>(pv, a.partials + (long long)b * a.nparts, 0, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1112,6 +1177,23 @@ static hipError_t launch_axis_wave(const AxisArgs<T>& a, hipStream_t st) {
     return hipGetLastError();
 }
 
+// The norm pass: nparts blocks per slot (see k_axis_wave_norm).
+template <typename T>
+hipError_t launch_axis_norm(const AxisArgs<T>& a, hipStream_t st) {
+    constexpr int W = 4;
+    const int N = a.g.ny;
+    if (a.contiguous == 0 || a.g.s != 3 || a.pl.N != N || a.nparts < 1 ||
+        !(N == 128 || N == 256 || N == 512))
+        return hipErrorInvalidValue;
+    const int lpw = N >= 256 ? 1 : 2;
+    const dim3 grid((unsigned)a.nparts, 1, a.g.B);
+    const size_t lds = (size_t)W * lpw * lds_line(N) * sizeof(cplx<T>);
+    if (N == 512) hipLaunchKernelGGL((k_axis_wave_norm<T, 512>), grid, dim3(64 * W), lds, st, a);
+    else if (N == 256) hipLaunchKernelGGL((k_axis_wave_norm<T, 256>), grid, dim3(64 * W), lds, st, a);
+    else hipLaunchKernelGGL((k_axis_wave_norm<T, 128>), grid, dim3(64 * W), lds, st, a);
+    return hipGetLastError();
+}
+
 template <typename T>
 static bool wave_axis_applies(const AxisArgs<T>& a) {
     return !a.block_only && a.contiguous && a.pl.N == a.g.ny &&
@@ -1188,5 +1270,6 @@ template hipError_t launch_xfwd<MIRVE_REAL>(const XfwdArgs<MIRVE_REAL>&, int, in
 template hipError_t launch_axis<MIRVE_REAL>(const AxisArgs<MIRVE_REAL>&, int, int, dim3, size_t,
                                             hipStream_t);
 template hipError_t launch_xinv<MIRVE_REAL>(const XinvArgs<MIRVE_REAL>&, int, int, size_t, hipStream_t);
+template hipError_t launch_axis_norm<MIRVE_REAL>(const AxisArgs<MIRVE_REAL>&, hipStream_t);
 
 }  // namespace mirve

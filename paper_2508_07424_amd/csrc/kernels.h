@@ -111,6 +111,9 @@ struct AxisArgs {
     int lines;           // lines per block (y pass) / y columns per block (z pass)
     int threads;         // block size (multiple of 64, <= 256)
     int block_only;      // 1: the block pass even where the one-wave y pass applies
+    double* partials;    // norm pass: [B][nparts] partial sums of ||out||^2
+    int nparts;          // norm pass: blocks per slot (the x-inverse pass's count)
+    double nscale;       // norm pass: scale^2 / N of out = scale F^-1{P : F[sigma]}
 };
 
 template <typename T>
@@ -142,6 +145,10 @@ hipError_t launch_axis(const AxisArgs<T>& a, int mode, int maxb, dim3 grid, size
                        hipStream_t st);
 template <typename T>
 hipError_t launch_xinv(const XinvArgs<T>& a, int mode, int maxb, size_t lds, hipStream_t st);
+// ||scale F^-1{P : F[sigma]}||^2 partials from the x-forward spectrum alone
+// (2D, 128-, 256- or 512-point y lines): a.partials, a.nparts per slot
+template <typename T>
+hipError_t launch_axis_norm(const AxisArgs<T>& a, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // finalize kernels (one block per RVE, fixed-order sums)

@@ -963,10 +963,32 @@ struct Solver : SolverBase {
     int green(const T* phi, const T* eps, double fcoef, T* out, double scale, double* part,
               const int* mask) {
         CHK(fwd_x(cfg.split == RVE_SPLIT_NONE ? XF_GREEN : XF_SPLIT, phi, eps, fcoef, part, mask));
-        CHK(axes(nullptr, mask));
-        CHK(inv_x(XI_STORE, out, scale, part, mask));
+        if (out == nullptr && norm_by_parseval()) {
+            // only ||out||^2 is wanted: summed over the projected spectrum of
+            // the forward y pass (Parseval), without the inverse transforms
+            AxisArgs<T> a;
+            std::memset(&a, 0, sizeof(a));
+            a.g = g;
+            a.pl = ply;
+            a.tw = tw + ply.tw_off;
+            a.spec = spec;
+            a.active = mask;
+            a.contiguous = 1;
+            a.partials = part;
+            a.nparts = nbx;
+            a.nscale = scale * scale * g.inv_N;
+            HIPCHK(launch_axis_norm<T>(a, st));
+        } else {
+            CHK(axes(nullptr, mask));
+            CHK(inv_x(XI_STORE, out, scale, part, mask));
+        }
         ++greenops;
         return RVE_OK;
+    }
+    // 2D operators with 128-, 256- or 512-point y lines take the norm of a
+    // Green-operator application from its spectrum
+    bool norm_by_parseval() const {
+        return g.dim == 2 && g.s == 3 && (g.ny == 128 || g.ny == 256 || g.ny == 512) && ply.N == g.ny;
     }
 
     // masks: device int[B] built from a host vector

@@ -143,3 +143,27 @@ def test_damage_fp64_at_bench_line_lengths(name, n):
     print("pcg iterations", npcg, "max-rel %.3e" % e_max, flush=True)
     assert abs(D - D_o) <= 1e-10 * D_o
     assert e_max < 1e-10
+
+
+STOP = [CASES[0], CASES[2], CASES[3]]
+
+
+@pytest.mark.parametrize("name,n", STOP, ids=[c[0] for c in STOP])
+def test_mechanics_stopping_reference_at_bench_line_lengths(name, n):
+    """The CG stops at ||r|| <= tol_cg ||b|| with ||b|| = ||P : (g C : f)||
+    (Eq. 24 R1).  On 2D grids with 128- to 512-point y lines that norm is
+    summed over the projected spectrum (Parseval) instead of the inverse
+    transform; a wrong frequency weight moves the threshold and with it the
+    iteration at which a loose solve stops.  Same iteration counts as the
+    oracle's CG (real-space norm) at several loose tolerances."""
+    from paper_2508_07424_amd import mirve as m
+    w = _random_rve(n, 17)
+    print("case", name, n, flush=True)
+    for tol in (1e-2, 1e-4, 1e-6):
+        r = _handle(m, w, 0, tol_cg=tol)
+        prob = oracle_problem(w, tol_cg=tol)
+        st = solver.State(prob)
+        it, _ = r.rve_solve_mechanics()
+        _, it_o = solver.mechanics(prob, st.phi, st.x)
+        print("tol_cg %.0e: cg iterations gpu %d oracle %d" % (tol, it, it_o), flush=True)
+        assert it == it_o
