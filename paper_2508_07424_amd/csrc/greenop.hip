@@ -10,7 +10,11 @@
 //  axis pass : per block, whole lines of all s components along y (stored
 //              contiguously) or a tile of y columns along z (strided by
 //              n_y, read in 128-byte rows).  Forward, projection P(n) applied
-//              per frequency, inverse, in one visit on the last axis.
+//              per frequency, inverse, in one visit on the last axis.  y
+//              lines of 128, 256 or 512 points can instead go one line
+//              position per wave (k_axis_wave), and a Green operator of
+//              which only the norm is wanted stops after the projection
+//              (k_axis_wave_norm, Parseval).
 //  x-inverse : the reverse of the x-forward pass; the epilogue stores the
 //              result or applies the conjugate-gradient update in place.
 //
