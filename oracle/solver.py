@@ -30,6 +30,12 @@ loading axis holds a broken voxel (phi >= 0.95, or a notch voxel);
 A_g = h^(d-1) x (number of such lines without a notch voxel); V = N h^d;
 tau^0 = D(phi_ini); the trapezoid of Eq. 33 is used (the text says Simpson,
 the printed formula is the trapezoid).
+
+Parity unpinned: the absolute effective toughness of a heterogeneous
+composite or polycrystal.  It has no closed form and the paper's ensembles
+are not given; the homogeneous, laminate and energy-balance cases pin the
+steps it is made of, but the value itself is checked only against the HIP
+path.
 """
 import copy
 import math
